@@ -1,0 +1,186 @@
+"""FP64 CPU oracle for the kd-GeRaF build and query (arXiv 1603.09596).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark call it; the product library never does.  It shares no code
+with the GPU library.  ``oracle.c`` holds the method (Alg. 1-3, Sec. 2.3);
+this module compiles it with gcc and marshals numpy arrays through ctypes.
+``bruteforce.py`` holds the exact k-NN definition used to pin it.
+
+Parity status of each function (what pins it is in tests/test_oracle_*.py):
+  splitmix64 / draw     pinned: published splitmix64 outputs for state 0
+  variance / top dims   pinned: numpy.var(ddof=1), hand-made columns
+  build                 pinned: partition / median / leaf-size invariants,
+                        the closed form for t = 1 (contiguous rank blocks)
+  search (eff key)      pinned: static leaf ranking (every leaf's key by an
+                        independent traversal), the 1-D closed form for
+                        m = t = 1, nesting in c, exhaustive budget = brute force
+  search (literal key)  diagnostic only; parity unpinned beyond sharing the
+                        same exhaustive-budget and home-leaf behaviour
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (-O2, no fast-math) into liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                               "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i32, i64, u64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    lib.orc_splitmix64.argtypes = [u64]
+    lib.orc_splitmix64.restype = u64
+    lib.orc_draw.argtypes = [u64, u64, u64, u64]
+    lib.orc_draw.restype = u64
+    lib.orc_variance.argtypes = [P, i64, i32, P]
+    lib.orc_variance.restype = ctypes.c_int
+    lib.orc_top_dims.argtypes = [P, i32, i32, P]
+    lib.orc_top_dims.restype = ctypes.c_int
+    lib.orc_depth.argtypes = [i64, i32]
+    lib.orc_depth.restype = i32
+    lib.orc_budget.argtypes = [i64, f64, i64]
+    lib.orc_budget.restype = i64
+    lib.orc_build.argtypes = [P, i64, i32, i32, i32, i32, u64, i32, P, P, P, P, P]
+    lib.orc_build.restype = ctypes.c_int
+    lib.orc_search.argtypes = [P, i64, i32, i32, i32, P, P, P, P, P, i64, i32, i64, f64,
+                               i32, i32, P, P, P, P, P, P, i64]
+    lib.orc_search.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def splitmix64(x: int) -> int:
+    return int(_load().orc_splitmix64(x & 0xFFFFFFFFFFFFFFFF))
+
+
+def draw(seed: int, stream: int, tree: int, idx: int) -> int:
+    return int(_load().orc_draw(seed, stream, tree, idx))
+
+
+def variance(X: np.ndarray) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    V = np.empty(X.shape[1], dtype=np.float64)
+    st = _load().orc_variance(_ptr(X), X.shape[0], X.shape[1], _ptr(V))
+    if st != 0:
+        raise ValueError(f"orc_variance failed: {st}")
+    return V
+
+
+def top_dims(V: np.ndarray, t: int) -> np.ndarray:
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    D = np.empty(t, dtype=np.int32)
+    st = _load().orc_top_dims(_ptr(V), V.shape[0], t, _ptr(D))
+    if st != 0:
+        raise ValueError(f"orc_top_dims failed: {st}")
+    return D
+
+
+def depth(n: int, p: int) -> int:
+    return int(_load().orc_depth(n, p))
+
+
+def budget(c: int, eps: float, total_leaves: int) -> int:
+    return int(_load().orc_budget(c, eps, total_leaves))
+
+
+def build_forest(X: np.ndarray, m: int, t: int, p: int, seed: int, nthreads: int = 0) -> dict:
+    """Alg. 1.  Returns the forest arrays (see oracle.c, orc_build)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, d = X.shape
+    H = depth(n, p)
+    n_int = (1 << H) - 1
+    D = np.empty(t, dtype=np.int32)
+    split_dim = np.zeros((m, max(n_int, 1)), dtype=np.int32)
+    split_val = np.zeros((m, max(n_int, 1)), dtype=np.float32)
+    perm = np.empty((m, n), dtype=np.uint32)
+    leaf_off = np.empty((1 << H) + 1, dtype=np.uint32)
+    if nthreads <= 0:
+        nthreads = os.cpu_count() or 1
+    st = _load().orc_build(_ptr(X), n, d, m, t, p, seed & 0xFFFFFFFFFFFFFFFF, nthreads, _ptr(D),
+                           _ptr(split_dim), _ptr(split_val), _ptr(perm), _ptr(leaf_off))
+    if st != 0:
+        raise ValueError(f"orc_build failed: {st}")
+    return dict(n=n, d=d, m=m, t=t, p=p, seed=seed, H=H, D=D,
+                split_dim=split_dim[:, :n_int], split_val=split_val[:, :n_int],
+                perm=perm, leaf_off=leaf_off)
+
+
+def search(forest: dict, X: np.ndarray, Q: np.ndarray, k: int, c: int, eps: float = 0.0,
+           literal: bool = False, nthreads: int = 0, trace: bool = True,
+           candidates: bool = False) -> dict:
+    """Alg. 2 for every row of Q.  Returns ids [nq,k], dists [nq,k] (FP64,
+    squared), and with trace=True the opened (tree<<24|leaf) codes and keys in
+    pop order; with candidates=True the checked point ids per query."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Q = np.ascontiguousarray(Q, dtype=np.float32)
+    n, d = X.shape
+    nq = Q.shape[0]
+    m, H = forest["m"], forest["H"]
+    B = budget(c, eps, m << H)
+    n_int = (1 << H) - 1
+    sd = np.zeros((m, max(n_int, 1)), dtype=np.int32)
+    sv = np.zeros((m, max(n_int, 1)), dtype=np.float32)
+    sd[:, :n_int] = forest["split_dim"]
+    sv[:, :n_int] = forest["split_val"]
+    ids = np.empty((nq, k), dtype=np.int32)
+    dists = np.empty((nq, k), dtype=np.float64)
+    opened = np.empty((nq, B), dtype=np.uint32) if trace else None
+    okey = np.empty((nq, B), dtype=np.float64) if trace else None
+    ncand = np.empty(nq, dtype=np.int64) if candidates else None
+    lo = forest["leaf_off"].astype(np.int64)
+    pmax = int((lo[1:] - lo[:-1]).max()) if lo.size > 1 else 0
+    cap = min(n, B * pmax) if candidates else 0
+    cand = np.empty((nq, max(cap, 1)), dtype=np.uint32) if candidates else None
+    if nthreads <= 0:
+        nthreads = os.cpu_count() or 1
+    st = _load().orc_search(_ptr(X), n, d, m, H, _ptr(sd), _ptr(sv),
+                            _ptr(np.ascontiguousarray(forest["perm"])),
+                            _ptr(np.ascontiguousarray(forest["leaf_off"])),
+                            _ptr(Q), nq, k, c, float(eps), int(bool(literal)), nthreads,
+                            _ptr(ids), _ptr(dists), _ptr(opened), _ptr(okey), _ptr(ncand),
+                            _ptr(cand), cap)
+    if st != 0:
+        raise ValueError(f"orc_search failed: {st}")
+    out = dict(ids=ids, dists=dists, B=B)
+    if trace:
+        out["opened"] = opened
+        out["opened_key"] = okey
+    if candidates:
+        out["ncand"] = ncand
+        out["cand"] = [cand[i, :ncand[i]].copy() for i in range(nq)]
+    return out
+
+
+def leaf_code(tree, leaf):
+    return (np.asarray(tree, dtype=np.uint32) << np.uint32(24)) | np.asarray(leaf, dtype=np.uint32)
+
+
+__all__ = ["build", "splitmix64", "draw", "variance", "top_dims", "depth", "budget",
+           "build_forest", "search", "leaf_code"]

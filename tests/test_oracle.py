@@ -1,0 +1,400 @@
+"""CPU pins for the FP64 oracle (no GPU).
+
+Each test checks the oracle against something other than itself: published
+RNG outputs, a hand-worked example, numpy's textbook routines, closed forms of
+the split and search rules, brute force, and structural invariants.  A
+plausible mistake in the oracle (a dropped term, a flipped comparison, a wrong
+child index or key) fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bruteforce as bf
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+M64 = (1 << 64) - 1
+GAMMA = 0x9E3779B97F4A7C15
+
+
+def py_mix(z):
+    """splitmix64's mixing function, as published (used as a helper below;
+    the published outputs in golden/splitmix64.json pin it)."""
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def py_draw(seed, stream, tree, idx):
+    h = py_mix((seed + GAMMA) & M64)
+    h = py_mix(((h ^ stream) + GAMMA) & M64)
+    h = py_mix(((h ^ tree) + GAMMA) & M64)
+    return py_mix(((h ^ idx) + GAMMA) & M64)
+
+
+# --------------------------------------------------------------------- RNG
+
+def test_splitmix64_published_outputs():
+    g = json.load(open(os.path.join(GOLD, "splitmix64.json")))
+    for i, hx in enumerate(g["state0_outputs_hex"]):
+        assert oracle.splitmix64((i * GAMMA) & M64) == int(hx, 16)
+        assert py_mix(((i + 1) * GAMMA) & M64) == int(hx, 16)
+
+
+def test_draw_is_keyed_composition():
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        s, a, b, c = (int(x) for x in rng.integers(0, 2**63, 4))
+        assert oracle.draw(s, a % 5, b % 300, c) == py_draw(s, a % 5, b % 300, c)
+
+
+# --------------------------------------------------- variance and top dims
+
+def test_variance_matches_numpy():
+    rng = np.random.default_rng(1)
+    X = (rng.standard_normal((777, 19)) * rng.uniform(0.1, 5, 19) + 3.0).astype(np.float32)
+    V = oracle.variance(X)
+    ref = np.var(X.astype(np.float64), axis=0, ddof=1)
+    assert np.allclose(V, ref, rtol=1e-12, atol=0)
+
+
+def test_variance_fewer_than_two_points_is_zero():
+    assert np.all(oracle.variance(np.ones((1, 4), np.float32) * 3) == 0)
+
+
+def test_top_dims_ties_go_to_lower_index_and_sorted():
+    V = np.array([1.0, 5.0, 3.0, 5.0, 2.0, 3.0])
+    assert oracle.top_dims(V, 1).tolist() == [1]
+    assert oracle.top_dims(V, 2).tolist() == [1, 3]
+    assert oracle.top_dims(V, 3).tolist() == [1, 2, 3]
+    assert oracle.top_dims(V, 4).tolist() == [1, 2, 3, 5]
+    assert oracle.top_dims(V, 6).tolist() == [0, 1, 2, 3, 4, 5]
+
+
+# ------------------------------------------------------------------ depth
+
+@pytest.mark.parametrize("n,p,H", [(10_000, 8, 11), (100_000, 16, 13), (1_000_000, 32, 15),
+                                   (200_000, 16, 14), (5, 5, 0), (5, 9, 0), (6, 5, 1),
+                                   (1, 1, 0), (2, 1, 1), (9, 2, 3), (8, 2, 2), (17, 4, 3)])
+def test_depth_closed_form(n, p, H):
+    assert oracle.depth(n, p) == H
+    assert math.ceil(n / 2**H) <= p and (H == 0 or math.ceil(n / 2**(H - 1)) > p)
+
+
+# ------------------------------------------------------------------- build
+
+def node_sizes(n, H):
+    """Point count of every node, level by level (left floor, right ceil)."""
+    sizes = [n]
+    for _ in range(H):
+        sizes = [s for z in sizes for s in (z // 2, z - z // 2)]
+    return sizes
+
+
+def subtree_points(F, tree, v):
+    """Point ids in the subtree of node v (from the leaf ranges)."""
+    H = F["H"]
+    lo, hi = v, v
+    while lo < (1 << H) - 1:
+        lo, hi = 2 * lo + 1, 2 * hi + 2
+    L0, L1 = lo - ((1 << H) - 1), hi - ((1 << H) - 1)
+    off = F["leaf_off"]
+    return F["perm"][tree, off[L0]:off[L1 + 1]]
+
+
+def check_build_invariants(F, X):
+    n, d = X.shape
+    m, t, H = F["m"], F["t"], F["H"]
+    D = F["D"]
+    # D = the t largest sample variances (numpy), as a set
+    V = np.var(X.astype(np.float64), axis=0, ddof=1)
+    order = sorted(range(d), key=lambda j: (-V[j], j))
+    assert sorted(order[:t]) == D.tolist()
+    # leaf offsets follow the floor/ceil size recursion; every leaf <= p
+    sizes = node_sizes(n, H)
+    assert F["leaf_off"].tolist() == [0] + np.cumsum(sizes).tolist()
+    assert max(sizes) <= F["p"]
+    keys = None
+    for tr in range(m):
+        perm = F["perm"][tr]
+        assert np.array_equal(np.sort(perm), np.arange(n))
+        for j in range(1 << H):
+            seg = perm[F["leaf_off"][j]:F["leaf_off"][j + 1]]
+            assert np.all(np.diff(seg.astype(np.int64)) > 0)       # ascending ids
+        keys = np.array([py_draw(F["seed"], 2, tr, i) for i in range(n)], dtype=np.uint64)
+        for v in range((1 << H) - 1):
+            s = int(F["split_dim"][tr, v])
+            assert s == int(D[py_draw(F["seed"], 1, tr, v) % t])
+            pts = subtree_points(F, tr, v)
+            left = subtree_points(F, tr, 2 * v + 1)
+            right = subtree_points(F, tr, 2 * v + 2)
+            assert len(left) == len(pts) // 2
+            # closed form of the median split: the left child holds the
+            # floor(|P|/2) smallest points under (x_s, tie key, id)
+            srt = sorted(pts.tolist(), key=lambda i: (float(X[i, s]), int(keys[i]), i))
+            assert set(srt[:len(pts) // 2]) == set(left.tolist())
+            val = F["split_val"][tr, v]
+            assert val == X[srt[len(pts) // 2], s]
+            if len(left):
+                assert X[left, s].max() <= val
+            assert X[right, s].min() == val
+
+
+@pytest.mark.parametrize("n,d,m,t,p,seed", [(300, 7, 3, 3, 5, 11), (257, 12, 2, 5, 4, 3),
+                                            (64, 4, 2, 4, 1, 0)])
+def test_build_invariants_continuous(n, d, m, t, p, seed):
+    X = np.random.default_rng(seed).standard_normal((n, d)).astype(np.float32)
+    X[:, 1] *= 3
+    F = oracle.build_forest(X, m, t, p, seed)
+    check_build_invariants(F, X)
+
+
+def test_build_invariants_quantised_ties():
+    # SIFT-like byte values: many equal coordinates, so the tie key decides
+    rng = np.random.default_rng(5)
+    X = rng.integers(0, 4, (200, 6)).astype(np.float32)
+    X[:, 2] *= 3
+    F = oracle.build_forest(X, 3, 3, 3, 99)
+    check_build_invariants(F, X)
+    # shuffling: different trees split the tied values differently
+    assert not np.array_equal(F["perm"][0], F["perm"][1])
+
+
+def test_build_t1_contiguous_rank_blocks():
+    # t = 1: every split is on D[0], so each tree's leaves are contiguous
+    # blocks of the order by (x_D0, tie key, id), block sizes from leaf_off
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((500, 5)).astype(np.float32)
+    X[:, 3] *= 4
+    X[::7, 3] = 0.5                                   # plus ties
+    F = oracle.build_forest(X, 3, 1, 6, 21)
+    assert F["D"].tolist() == [3]
+    for tr in range(3):
+        keys = [py_draw(21, 2, tr, i) for i in range(500)]
+        srt = sorted(range(500), key=lambda i: (float(X[i, 3]), keys[i], i))
+        off = F["leaf_off"]
+        for j in range(len(off) - 1):
+            assert sorted(srt[off[j]:off[j + 1]]) == F["perm"][tr, off[j]:off[j + 1]].tolist()
+
+
+def test_build_hand_worked_example():
+    g = json.load(open(os.path.join(GOLD, "tiny_2d.json")))
+    X = np.array(g["X"], dtype=np.float32)
+    F = oracle.build_forest(X, g["m"], g["t"], g["p"], g["seed"])
+    tr = g["tree"]
+    assert F["H"] == tr["H"]
+    assert F["D"].tolist() == tr["D"]
+    assert F["split_dim"][0].tolist() == tr["split_dim"]
+    assert F["split_val"][0].tolist() == tr["split_val"]
+    assert F["leaf_off"].tolist() == tr["leaf_off"]
+    assert F["perm"][0].tolist() == tr["perm"]
+
+
+# ------------------------------------------------------------------ search
+
+def search_hand_example(literal):
+    g = json.load(open(os.path.join(GOLD, "tiny_2d.json")))
+    X = np.array(g["X"], dtype=np.float32)
+    q = np.array([g["q"]], dtype=np.float32)
+    F = oracle.build_forest(X, g["m"], g["t"], g["p"], g["seed"])
+    for c in range(1, 5):
+        r = oracle.search(F, X, q, 3, c, literal=literal)
+        assert (r["opened"][0] & 0xFFFFFF).tolist() == g["pops"]["leaves"][:c]
+        assert r["opened_key"][0].tolist() == g["pops"]["keys"][:c]
+        exp = g["k3_by_c"][str(c)]
+        assert r["ids"][0].tolist() == exp["ids"]
+        assert r["dists"][0].tolist() == [float(x) for x in exp["dists"]]
+
+
+def test_search_hand_worked_example():
+    search_hand_example(False)
+
+
+def test_search_hand_worked_example_literal_key():
+    search_hand_example(True)
+
+
+def static_leaf_order(F, q):
+    """Every leaf's (eff, tree, entry) by an independent top-down traversal:
+    the near child inherits the parent's eff and entry, the far child gets
+    max(eff, |gap|) and becomes its own entry (gap = float32 q_s - v).
+    Returns the leaf codes sorted by that key, and the keys."""
+    H, m = F["H"], F["m"]
+    nint = (1 << H) - 1
+    items = []
+    for tr in range(m):
+        stack = [(0, np.float32(0), 0)]
+        while stack:
+            v, eff, entry = stack.pop()
+            if v >= nint:
+                items.append((float(eff), tr, entry, (tr << 24) | (v - nint)))
+                continue
+            s = F["split_dim"][tr, v]
+            g = np.float32(q[s]) - np.float32(F["split_val"][tr, v])
+            near, far = (2 * v + 1, 2 * v + 2) if g < 0 else (2 * v + 2, 2 * v + 1)
+            stack.append((near, eff, entry))
+            stack.append((far, max(eff, np.float32(abs(g))), far))
+    items.sort()
+    return [it[3] for it in items], [it[0] for it in items]
+
+
+@pytest.mark.parametrize("n,d,m,t,p,c,seed", [(2000, 24, 4, 5, 8, 100, 0),
+                                              (1000, 16, 3, 2, 3, 333, 1),
+                                              (333, 8, 5, 8, 2, 50, 2)])
+def test_search_pop_order_equals_static_leaf_ranking(n, d, m, t, p, c, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Q = (X[rng.integers(0, n, 12)] + 0.1 * rng.standard_normal((12, d))).astype(np.float32)
+    F = oracle.build_forest(X, m, t, p, seed)
+    r = oracle.search(F, X, Q, 3, c)
+    for i in range(len(Q)):
+        codes, keys = static_leaf_order(F, Q[i])
+        assert r["opened"][i].tolist() == codes[:r["B"]]
+        assert r["opened_key"][i].tolist() == keys[:r["B"]]
+
+
+def test_search_1d_closed_form_nearest_cells():
+    # m = t = 1: leaves are intervals of x_s; a leaf's key is the 1-D distance
+    # from q_s to its cell [lower split, upper split), so the opened leaves
+    # are the B cells nearest to q_s, in that order.
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((600, 3)).astype(np.float32)
+    X[:, 0] *= 5
+    F = oracle.build_forest(X, 1, 1, 4, 8)
+    s = int(F["D"][0])
+    perm, off = F["perm"][0], F["leaf_off"]
+    L = len(off) - 1
+    keys = [py_draw(8, 2, 0, i) for i in range(600)]
+    srt = sorted(range(600), key=lambda i: (float(X[i, s]), keys[i], i))
+    lower = [None] + [X[srt[off[j]], s] for j in range(1, L)]          # cell boundaries
+    Q = (X[rng.integers(0, 600, 20)] + 0.3 * rng.standard_normal((20, 3))).astype(np.float32)
+    B = 37
+    r = oracle.search(F, X, Q, 1, B)
+    for i in range(len(Q)):
+        qs = Q[i, s]
+        dist = []
+        for j in range(L):
+            lo = lower[j]
+            hi = lower[j + 1] if j + 1 < L else None
+            if lo is not None and qs < lo:
+                dist.append((float(np.float32(lo) - qs), j))
+            elif hi is not None and qs >= hi:
+                dist.append((float(qs - np.float32(hi)), j))
+            else:
+                dist.append((0.0, j))
+        dist.sort()
+        got = sorted((r["opened"][i] & 0xFFFFFF).tolist())
+        exp_keys = sorted(k for k, _ in dist)
+        assert r["opened_key"][i].tolist() == exp_keys[:B]
+        assert set(got) == {j for _, j in dist[:B]} or exp_keys[B - 1] == exp_keys[B]
+
+
+def test_search_nesting_and_count():
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((3000, 32)).astype(np.float32)
+    Q = (X[:10] + 0.05).astype(np.float32)
+    F = oracle.build_forest(X, 4, 5, 8, 2)
+    total = 4 << F["H"]
+    prev = None
+    for c in [1, 7, 64, 300, total, total + 50]:
+        r = oracle.search(F, X, Q, 2, c)
+        assert r["B"] == min(c, total)
+        assert r["opened"].shape[1] == min(c, total)
+        for i in range(10):
+            assert len(set(r["opened"][i].tolist())) == r["B"]        # distinct leaves
+        if prev is not None:
+            assert np.array_equal(r["opened"][:, :prev.shape[1]], prev)   # nested in c
+        prev = r["opened"]
+
+
+def test_search_budget_with_eps():
+    assert oracle.budget(100, 0.0, 10**6) == 100
+    assert oracle.budget(100, 0.5, 10**6) == 67          # ceil(100 / 1.5)
+    assert oracle.budget(100, 1.0, 10**6) == 50
+    assert oracle.budget(101, 1.0, 10**6) == 51
+    assert oracle.budget(100, 0.0, 40) == 40
+
+
+def test_search_candidates_union_and_topk_over_them():
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((4000, 40)).astype(np.float32)
+    Q = (X[rng.integers(0, 4000, 15)] + 0.05 * rng.standard_normal((15, 40))).astype(np.float32)
+    F = oracle.build_forest(X, 4, 5, 8, 3)
+    r = oracle.search(F, X, Q, 7, 90, candidates=True)
+    for i in range(15):
+        union = set()
+        for code in r["opened"][i].tolist():
+            tr, leaf = code >> 24, code & 0xFFFFFF
+            union |= set(F["perm"][tr, F["leaf_off"][leaf]:F["leaf_off"][leaf + 1]].tolist())
+        assert sorted(union) == r["cand"][i].tolist()
+    ei, ed = bf.knn_exact(X, Q, 7, subset=r["cand"])
+    assert np.array_equal(r["ids"], ei)
+    assert np.allclose(r["dists"], ed, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("literal", [False, True])
+def test_search_exhaustive_budget_is_exact_knn(literal):
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((1500, 20)).astype(np.float32)
+    Q = rng.standard_normal((25, 20)).astype(np.float32)
+    F = oracle.build_forest(X, 3, 4, 6, 6)
+    r = oracle.search(F, X, Q, 10, 3 << F["H"], literal=literal, candidates=True)
+    assert all(len(cq) == 1500 for cq in r["cand"])
+    ei, ed = bf.knn_exact(X, Q, 10)
+    assert np.array_equal(r["ids"], ei)
+    assert np.allclose(r["dists"], ed, rtol=1e-13, atol=0)
+
+
+def test_search_single_leaf_tree_is_exact_knn():
+    # p >= n: H = 0, each tree is one leaf holding every point
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((50, 6)).astype(np.float32)
+    Q = rng.standard_normal((5, 6)).astype(np.float32)
+    F = oracle.build_forest(X, 2, 2, 64, 1)
+    assert F["H"] == 0
+    r = oracle.search(F, X, Q, 4, 1)
+    ei, ed = bf.knn_exact(X, Q, 4)
+    assert np.array_equal(r["ids"], ei) and np.allclose(r["dists"], ed, rtol=1e-13)
+
+
+def test_search_pads_when_fewer_than_k_candidates():
+    rng = np.random.default_rng(10)
+    X = rng.standard_normal((100, 4)).astype(np.float32)
+    F = oracle.build_forest(X, 1, 2, 3, 1)
+    r = oracle.search(F, X, X[:3], 8, 1, candidates=True)
+    for i in range(3):
+        nc = int(r["ncand"][i])
+        assert nc <= 3
+        assert r["ids"][i, nc:].tolist() == [-1] * (8 - nc)
+        assert np.all(np.isinf(r["dists"][i, nc:]))
+        assert r["ids"][i, 0] == i and r["dists"][i, 0] == 0.0
+
+
+def test_search_home_leaves_first():
+    # the first m pops are the m home leaves (key 0), in tree order
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((800, 10)).astype(np.float32)
+    Q = rng.standard_normal((6, 10)).astype(np.float32)
+    F = oracle.build_forest(X, 5, 3, 4, 4)
+    for literal in (False, True):
+        r = oracle.search(F, X, Q, 1, 40, literal=literal)
+        assert np.all(r["opened_key"][:, :5] == 0)
+        assert ((r["opened"][:, :5] >> 24) == np.arange(5)).all()
+
+
+def test_search_threads_do_not_change_results():
+    w_rng = np.random.default_rng(12)
+    X = w_rng.standard_normal((2500, 30)).astype(np.float32)
+    Q = w_rng.standard_normal((40, 30)).astype(np.float32)
+    F1 = oracle.build_forest(X, 4, 5, 8, 5, nthreads=1)
+    F4 = oracle.build_forest(X, 4, 5, 8, 5, nthreads=4)
+    for key in ("split_dim", "split_val", "perm", "leaf_off", "D"):
+        assert np.array_equal(F1[key], F4[key])
+    r1 = oracle.search(F1, X, Q, 5, 77, nthreads=1)
+    r4 = oracle.search(F1, X, Q, 5, 77, nthreads=4)
+    for key in ("ids", "dists", "opened", "opened_key"):
+        assert np.array_equal(r1[key], r4[key])
