@@ -1,0 +1,155 @@
+/*
+ * geraf.h -- C ABI of the kd-GeRaF query-path library for MI355X (gfx950).
+ *
+ * Method: Avrithis, Emiris, Samaras, "High-dimensional approximate nearest
+ * neighbor: k-d Generalized Randomized Forests" (arXiv 1603.09596).
+ *   - gf_build_forest follows Alg. 1 (Sec. 2.2) with the storage of Sec. 3
+ *     ("Tree structure": perfect trees stored in arrays, points stored once)
+ *     and the variance of Alg. 3.
+ *   - gf_query follows Alg. 2 and Sec. 2.3 (one priority queue shared by all
+ *     trees, keyed by the gap of Eq. 1, no backtracking, stop after
+ *     ceil(c/(1+eps)) leaves, a visited array so no distance is computed
+ *     twice, the k best by squared distance), plus the squared-norm
+ *     expansion of Sec. 3 ("Distance computation") for the reduced-precision
+ *     forms.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns a gf_status; nothing throws across the ABI.  On
+ *     error no output has been written and gf_last_error() (thread-local)
+ *     describes the failure.  Arguments are validated before any HIP call.
+ *   - Matrices are row-major float32: X is [n][d], Q is [nq][d].
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Query entry points enqueue their kernels on it and return once the
+ *     results are in the caller's buffers (they synchronise the stream).
+ *   - Pointers marked host-or-device may point to either; the library checks
+ *     with hipPointerGetAttributes and stages host buffers itself.
+ *   - Distances are SQUARED Euclidean distances.  Result rows are sorted by
+ *     (distance, id) ascending; missing slots (fewer than k candidates) hold
+ *     id -1 and distance +inf.
+ *   - Limits: 1 <= m <= 255 trees, perfect-tree depth H <= 23, n < 2^31,
+ *     1 <= t <= min(d, 64), 1 <= k <= 64.
+ */
+#ifndef GERAF_H
+#define GERAF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gf_forest gf_forest;   /* opaque; owned by the library */
+
+typedef enum {
+    GF_OK = 0,
+    GF_EINVAL = -1,          /* invalid argument (nothing was launched) */
+    GF_ENOMEM = -2,          /* host or device allocation failed */
+    GF_EHIP = -3,            /* a HIP runtime call failed */
+    GF_EUNSUPPORTED = -4,    /* valid request outside this build's limits */
+    GF_EINTERNAL = -5        /* an internal consistency check failed */
+} gf_status;
+
+/* Distance forms.  FP32: direct sum of (q_j - x_j)^2 over FP32 rows.
+ * BF16 / FP8 (e4m3, per-row scale): ||x||^2 - 2 q.x + ||q||^2 on the
+ * reduced-precision copies with FP32 accumulation, used only to select the
+ * `rerank` best candidates, which are then measured again in FP32 (direct,
+ * compensated) on the FP32 rows.  In every form the distances that decide
+ * the k-th place within 1e-5 relative are measured once more in FP64. */
+typedef enum { GF_FORM_FP32 = 0, GF_FORM_BF16 = 1, GF_FORM_FP8 = 2 } gf_form;
+
+/* Bits of gf_build_forest's `forms` argument: which reduced-precision copies
+ * of X to keep on the device (FP32 rows are always kept). */
+#define GF_KEEP_BF16 (1u << 1)
+#define GF_KEEP_FP8  (1u << 2)
+
+/* Build a forest of m randomized k-d trees over X (Alg. 1).
+ *   X      [n][d] float32, host-or-device; read during the call only (the
+ *          library keeps its own device copies).  Must be finite.
+ *   m      number of trees; t size of the top-variance dimension set D;
+ *   leaf   maximum points per leaf (the paper's p); every tree is perfect of
+ *          depth H = min{h : ceil(n / 2^h) <= leaf};
+ *   seed   key of the counter-based RNG (splitmix64 keyed by seed, stream,
+ *          tree and node or point) that draws each node's split dimension
+ *          from D and each tree's tie-break key per point ("shuffling").
+ *   forms  GF_KEEP_* bits.
+ *   out    receives the new forest; release it with gf_free_forest.
+ * The build runs on the host (threads over trees, Sec. 3 "Parallelization");
+ * the arrays, the FP32 rows and the requested reduced-precision copies are
+ * then uploaded on `stream`. */
+gf_status gf_build_forest(const float *X, int64_t n, int32_t d, int32_t m, int32_t t,
+                          int32_t leaf, uint64_t seed, uint32_t forms, void *stream,
+                          gf_forest **out);
+
+/* Release a forest and all its device memory.  NULL is accepted. */
+gf_status gf_free_forest(gf_forest *F);
+
+/* Shape of a built forest (any output pointer may be NULL). */
+gf_status gf_forest_info(const gf_forest *F, int64_t *n, int32_t *d, int32_t *m,
+                         int32_t *t, int32_t *leaf, int32_t *H);
+
+/* Copy the host-side tree arrays out (host buffers, caller-allocated):
+ *   D[t]                         the top-variance dimensions, ascending;
+ *   split_dim[m][2^H - 1]        split column of each internal node;
+ *   split_val[m][2^H - 1]        split value of each internal node;
+ *   perm[m][n]                   per tree, point ids leaf by leaf, each leaf
+ *                                ascending;
+ *   leaf_off[2^H + 1]            leaf j = perm[tree][leaf_off[j] .. leaf_off[j+1]).
+ * Node v has children 2v+1 (left, coordinate < value) and 2v+2 (right).
+ * Any pointer may be NULL to skip that array. */
+gf_status gf_export_tree(const gf_forest *F, int32_t *D, int32_t *split_dim,
+                         float *split_val, uint32_t *perm, uint32_t *leaf_off);
+
+/* Search every row of Q (Alg. 2): the leaves opened per query are the first
+ * B = min(ceil(checks/(1+eps)), m * 2^H) of the shared queue's pop order;
+ * the candidates are the distinct points of those leaves; the result is the
+ * k best candidates.
+ *   Q                 [nq][d] float32, host-or-device, finite.
+ *   k                 neighbours per query (1..64).
+ *   checks            the paper's c: leaves to check per query (>= 1).
+ *   checks_per_query  NULL, or nq int32 budgets (host-or-device) that
+ *                     replace `checks` per query.
+ *   eps               >= 0; the budget becomes ceil(c / (1 + eps)).
+ *   form              gf_form; BF16/FP8 need the copy kept at build time.
+ *   rerank            reduced-precision forms: candidates re-measured in FP32
+ *                     (k <= rerank <= 64; 0 selects 4k, capped at 64).
+ *                     Ignored by GF_FORM_FP32.
+ *   ids, dists        [nq][k] int32 / float32 outputs, host-or-device. */
+gf_status gf_query(const gf_forest *F, const float *Q, int64_t nq, int32_t k,
+                   int32_t checks, const int32_t *checks_per_query, double eps,
+                   int32_t form, int32_t rerank, int32_t *ids, float *dists,
+                   void *stream);
+
+/* The query path's intermediate sets, for parity checks:
+ *   leaf_bits  [nq][m][W] uint32, W = max(1, 2^H / 32): bit (j % 32) of word
+ *              j / 32 of tree i is set iff leaf j of tree i was opened;
+ *   cand_bits  [nq][ceil(n/32)] uint32: bit i set iff point i was a
+ *              candidate (the visited array after all opened leaves);
+ *   ncand      [nq] int64: number of candidates.
+ * All three are host-or-device; any may be NULL.  Same budget rules as
+ * gf_query.  Runs the same selection and expansion kernels as gf_query. */
+gf_status gf_query_trace(const gf_forest *F, const float *Q, int64_t nq, int32_t checks,
+                         const int32_t *checks_per_query, double eps, uint32_t *leaf_bits,
+                         uint32_t *cand_bits, int64_t *ncand, void *stream);
+
+/* Diagnostics of the FP8 e4m3 storage format (used by the tests):
+ *   hw_decode[256]   every byte decoded by the gfx950 conversion instruction
+ *                    that the FP8 distance kernels use;
+ *   def_decode[256]  every byte decoded from the OCP E4M3 definition (bias 7,
+ *                    3 mantissa bits, subnormal step 2^-9, 0x7F/0xFF NaN);
+ *   enc_in[n_enc] -> enc_out[n_enc]  the library's float -> e4m3 rounding
+ *                    (nearest-even, saturating at 448).
+ * Host buffers. */
+gf_status gf_fp8_tables(float *hw_decode, float *def_decode, const float *enc_in,
+                        int32_t n_enc, uint8_t *enc_out);
+
+/* Human-readable description of the last error on the calling thread. */
+const char *gf_last_error(void);
+
+/* Library version string. */
+const char *gf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GERAF_H */

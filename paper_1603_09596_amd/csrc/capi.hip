@@ -1,0 +1,509 @@
+// capi.hip -- the C ABI (include/geraf.h): validation, device memory, and
+// the order of the query-path launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "forest.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gf_status fail(gf_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define GF_HIP(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(GF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+bool is_device_ptr(const void* p) {
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
+           attr.isManaged;
+}
+
+bool all_finite_host(const float* X, int64_t count) {
+    const unsigned nw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<char> ok(nw, 1);
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nw; ++w)
+        th.emplace_back([&, w] {
+            int64_t a = count * w / nw, b = count * (w + 1) / nw;
+            for (int64_t i = a; i < b; ++i)
+                if (!std::isfinite(X[i])) { ok[w] = 0; return; }
+        });
+    for (auto& t : th) t.join();
+    for (char c : ok)
+        if (!c) return false;
+    return true;
+}
+
+void free_forest_device(gf_forest* F) {
+    void* ptrs[] = {F->X32, F->X16, F->norm16, F->X8, F->scale8, F->norm8,
+                    F->nodes, F->perm, F->leaf_off, F->D, F->ws};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    F->X32 = nullptr; F->X16 = nullptr; F->norm16 = nullptr; F->X8 = nullptr;
+    F->scale8 = nullptr; F->norm8 = nullptr; F->nodes = nullptr; F->perm = nullptr;
+    F->leaf_off = nullptr; F->D = nullptr; F->ws = nullptr; F->ws_bytes = 0;
+}
+
+// Bump allocator over the forest's grow-only workspace.
+struct Carve {
+    size_t off = 0;
+    template <class T>
+    size_t take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        size_t at = off;
+        off += count * sizeof(T);
+        return at;
+    }
+};
+
+struct Workspace {
+    float* Qp; uint16_t* Q16; uint8_t* Q8; float* qscale; float* qnorm; int32_t* cpq;
+    gf::SelState* state; uint32_t* hist; uint32_t* ncollect; uint64_t* ckey; uint32_t* ccode;
+    uint32_t* leafbits; uint32_t* flags; int32_t* ids; float* dists;
+};
+
+gf_status get_workspace(gf_forest* F, int nb, int k, int form, Workspace& w) {
+    const int64_t W = std::max<int64_t>(1, (int64_t{1} << F->host.H) / 32);
+    Carve c;
+    size_t oQp = c.take<float>(size_t(nb) * F->ld32);
+    size_t oQ16 = form == gf::kFormBF16 ? c.take<uint16_t>(size_t(nb) * F->ld16) : 0;
+    size_t oQ8 = form == gf::kFormFP8 ? c.take<uint8_t>(size_t(nb) * F->ld8) : 0;
+    size_t oqs = c.take<float>(nb);
+    size_t oqn = c.take<float>(nb);
+    size_t ocpq = c.take<int32_t>(nb);
+    size_t ost = c.take<gf::SelState>(nb);
+    size_t ohist = c.take<uint32_t>(size_t(nb) * 128);
+    size_t onc = c.take<uint32_t>(nb);
+    size_t ock = c.take<uint64_t>(size_t(nb) * gf::kCollectCap);
+    size_t occ = c.take<uint32_t>(size_t(nb) * gf::kCollectCap);
+    size_t olb = c.take<uint32_t>(size_t(nb) * F->host.m * W);
+    size_t ofl = c.take<uint32_t>(8);
+    size_t oids = c.take<int32_t>(size_t(nb) * k);
+    size_t odst = c.take<float>(size_t(nb) * k);
+    size_t need = c.off + 256;
+    if (need > F->ws_bytes) {
+        if (F->ws) (void)hipFree(F->ws);
+        F->ws = nullptr;
+        F->ws_bytes = 0;
+        if (hipMalloc(&F->ws, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GF_ENOMEM, "device workspace allocation of " + std::to_string(need) +
+                                       " bytes failed");
+        }
+        F->ws_bytes = need;
+    }
+    char* b = static_cast<char*>(F->ws);
+    w.Qp = reinterpret_cast<float*>(b + oQp);
+    w.Q16 = form == gf::kFormBF16 ? reinterpret_cast<uint16_t*>(b + oQ16) : nullptr;
+    w.Q8 = form == gf::kFormFP8 ? reinterpret_cast<uint8_t*>(b + oQ8) : nullptr;
+    w.qscale = reinterpret_cast<float*>(b + oqs);
+    w.qnorm = reinterpret_cast<float*>(b + oqn);
+    w.cpq = reinterpret_cast<int32_t*>(b + ocpq);
+    w.state = reinterpret_cast<gf::SelState*>(b + ost);
+    w.hist = reinterpret_cast<uint32_t*>(b + ohist);
+    w.ncollect = reinterpret_cast<uint32_t*>(b + onc);
+    w.ckey = reinterpret_cast<uint64_t*>(b + ock);
+    w.ccode = reinterpret_cast<uint32_t*>(b + occ);
+    w.leafbits = reinterpret_cast<uint32_t*>(b + olb);
+    w.flags = reinterpret_cast<uint32_t*>(b + ofl);
+    w.ids = reinterpret_cast<int32_t*>(b + oids);
+    w.dists = reinterpret_cast<float*>(b + odst);
+    return GF_OK;
+}
+
+constexpr int kMaxBatch = 16384;
+
+struct QueryJob {
+    const float* Q;            // caller's rows (host or device)
+    bool q_dev;
+    const int32_t* cpq;        // caller's budgets (host or device) or null
+    bool cpq_dev;
+    int64_t nq;
+    int32_t k, checks;
+    double eps;
+    int form, kk;
+    // outputs (host or device), any may be null
+    int32_t* ids; float* dists; bool out_dev;
+    uint32_t* leaf_bits; uint32_t* cand_bits; int64_t* ncand; bool trace_dev;
+};
+
+// Runs the whole query path for queries [q0, q0 + nb).
+gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStream_t st) {
+    const gf::HostForest& h = F->host;
+    Workspace w;
+    gf_status s = get_workspace(F, nb, J.k, J.form, w);
+    if (s != GF_OK) return s;
+    const int64_t W = std::max<int64_t>(1, (int64_t{1} << h.H) / 32);
+
+    // a1: query prep -- padded FP32 rows, finiteness, reduced copies
+    GF_HIP(hipMemsetAsync(w.Qp, 0, size_t(nb) * F->ld32 * 4, st));
+    GF_HIP(hipMemcpy2DAsync(w.Qp, size_t(F->ld32) * 4, J.Q + q0 * h.d, size_t(h.d) * 4,
+                            size_t(h.d) * 4, nb,
+                            J.q_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    GF_HIP(hipMemsetAsync(w.flags, 0, 8 * 4, st));
+    {
+        const int64_t tot = int64_t(nb) * h.d;
+        hipLaunchKernelGGL(gf::k_check_finite, dim3((tot + 255) / 256), dim3(256), 0, st,
+                           w.Qp, int64_t(nb), h.d, int64_t(F->ld32), w.flags);
+        GF_HIP(hipGetLastError());
+    }
+    if (J.form == gf::kFormBF16) {
+        hipLaunchKernelGGL(gf::k_to_bf16, dim3((nb + 3) / 4), dim3(256), 0, st, w.Qp, int64_t(nb),
+                           h.d, int64_t(F->ld32), w.Q16, int64_t(F->ld16), w.qnorm);
+        GF_HIP(hipGetLastError());
+    } else if (J.form == gf::kFormFP8) {
+        hipLaunchKernelGGL(gf::k_to_fp8, dim3((nb + 3) / 4), dim3(256), 0, st, w.Qp, int64_t(nb),
+                           h.d, int64_t(F->ld32), w.Q8, int64_t(F->ld8), w.qscale, w.qnorm);
+        GF_HIP(hipGetLastError());
+    }
+    const int32_t* cpq = nullptr;
+    if (J.cpq) {
+        GF_HIP(hipMemcpyAsync(w.cpq, J.cpq + q0, size_t(nb) * 4,
+                              J.cpq_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+        cpq = w.cpq;
+    }
+    uint32_t bad = 0;
+    GF_HIP(hipMemcpyAsync(&bad, w.flags, 4, hipMemcpyDeviceToHost, st));
+    GF_HIP(hipStreamSynchronize(st));
+    if (bad) return fail(GF_EINVAL, "Q contains a non-finite value");
+
+    // a2: leaf selection
+    gf::SelectArgs sa{};
+    sa.Q = w.Qp; sa.ldq = F->ld32; sa.nq = nb; sa.m = h.m; sa.H = h.H; sa.t = h.t;
+    sa.n_internal = (int64_t{1} << h.H) - 1; sa.W = int(W); sa.nodes = F->nodes; sa.D = F->D;
+    sa.state = w.state; sa.hist = w.hist; sa.ncollect = w.ncollect; sa.ckey = w.ckey;
+    sa.ccode = w.ccode; sa.leafbits = w.leafbits;
+    hipLaunchKernelGGL(gf::k_select_init, dim3((nb + 255) / 256), dim3(256), 0, st, sa,
+                       J.checks, cpq, J.eps);
+    GF_HIP(hipGetLastError());
+    for (int pass = 0; pass < gf::kMaxPasses; ++pass) {
+        GF_HIP(hipMemsetAsync(w.flags + 1, 0, 4, st));
+        GF_HIP(gf::launch_select_walk(sa, pass, false, st));
+        hipLaunchKernelGGL(gf::k_select_pick, dim3((nb + 255) / 256), dim3(256), 0, st, sa, pass,
+                           w.flags + 1);
+        GF_HIP(hipGetLastError());
+        uint32_t more = 0;
+        GF_HIP(hipMemcpyAsync(&more, w.flags + 1, 4, hipMemcpyDeviceToHost, st));
+        GF_HIP(hipStreamSynchronize(st));
+        if (!more) break;
+    }
+    GF_HIP(gf::launch_select_walk(sa, 0, true, st));
+    hipLaunchKernelGGL(gf::k_select_finish, dim3(nb), dim3(256), 0, st, sa);
+    GF_HIP(hipGetLastError());
+
+    // a3-a6: candidates, distances, best k, re-rank, ties
+    const int64_t nbmw = (h.n + 31) / 32;
+    gf::ScanArgs ca{};
+    ca.nq = nb; ca.k = J.k; ca.kk = J.kk; ca.n = h.n; ca.d = h.d; ca.m = h.m; ca.W = int(W);
+    ca.leafbits = w.leafbits; ca.perm = F->perm; ca.leaf_off = F->leaf_off;
+    ca.Q = w.Qp; ca.ldq = F->ld32; ca.X32 = F->X32; ca.ld32 = F->ld32;
+    ca.X16 = F->X16; ca.ld16 = F->ld16; ca.norm16 = F->norm16;
+    ca.X8 = F->X8; ca.ld8 = F->ld8; ca.scale8 = F->scale8; ca.norm8 = F->norm8;
+    ca.Q16 = w.Q16; ca.Q8 = w.Q8; ca.qscale8 = w.qscale; ca.qnorm = w.qnorm;
+    ca.ids = J.out_dev && J.ids ? J.ids + q0 * J.k : w.ids;
+    ca.dists = J.out_dev && J.dists ? J.dists + q0 * J.k : w.dists;
+    ca.cand_bits = (J.cand_bits && J.trace_dev) ? J.cand_bits + q0 * nbmw : nullptr;
+    ca.ncand = (J.ncand && J.trace_dev) ? J.ncand + q0 : nullptr;
+    std::unique_ptr<uint32_t, decltype(&hipFree)> tmp_bits(nullptr, &hipFree);
+    std::unique_ptr<int64_t, decltype(&hipFree)> tmp_nc(nullptr, &hipFree);
+    if (J.cand_bits && !J.trace_dev) {
+        uint32_t* p = nullptr;
+        GF_HIP(hipMalloc(&p, size_t(nb) * nbmw * 4));
+        tmp_bits.reset(p);
+        ca.cand_bits = p;
+    }
+    if (J.ncand && !J.trace_dev) {
+        int64_t* p = nullptr;
+        GF_HIP(hipMalloc(&p, size_t(nb) * 8));
+        tmp_nc.reset(p);
+        ca.ncand = p;
+    }
+    GF_HIP(gf::launch_scan(ca, J.form, st));
+
+    // outputs
+    if (J.ids && !J.out_dev)
+        GF_HIP(hipMemcpyAsync(J.ids + q0 * J.k, w.ids, size_t(nb) * J.k * 4, hipMemcpyDeviceToHost, st));
+    if (J.dists && !J.out_dev)
+        GF_HIP(hipMemcpyAsync(J.dists + q0 * J.k, w.dists, size_t(nb) * J.k * 4, hipMemcpyDeviceToHost, st));
+    if (J.cand_bits && !J.trace_dev)
+        GF_HIP(hipMemcpyAsync(J.cand_bits + q0 * nbmw, ca.cand_bits, size_t(nb) * nbmw * 4,
+                              hipMemcpyDeviceToHost, st));
+    if (J.ncand && !J.trace_dev)
+        GF_HIP(hipMemcpyAsync(J.ncand + q0, ca.ncand, size_t(nb) * 8, hipMemcpyDeviceToHost, st));
+    if (J.leaf_bits) {
+        const int64_t words = int64_t(h.m) * W;
+        uint32_t* dst = J.leaf_bits + q0 * words;
+        std::unique_ptr<uint32_t, decltype(&hipFree)> tmp(nullptr, &hipFree);
+        if (!J.trace_dev) {
+            uint32_t* p = nullptr;
+            GF_HIP(hipMalloc(&p, size_t(nb) * words * 4));
+            tmp.reset(p);
+            dst = p;
+        }
+        const int64_t tot = words * nb;
+        hipLaunchKernelGGL(gf::k_leafbits_to_query_major, dim3((tot + 255) / 256), dim3(256), 0, st,
+                           w.leafbits, nb, words, dst);
+        GF_HIP(hipGetLastError());
+        if (!J.trace_dev) {
+            GF_HIP(hipMemcpyAsync(J.leaf_bits + q0 * words, dst, size_t(tot) * 4,
+                                  hipMemcpyDeviceToHost, st));
+            GF_HIP(hipStreamSynchronize(st));
+        }
+    }
+    GF_HIP(hipStreamSynchronize(st));
+    return GF_OK;
+}
+
+gf_status run_query(gf_forest* F, QueryJob& J, hipStream_t st) {
+    GF_HIP(hipSetDevice(F->device));
+    std::lock_guard<std::mutex> lock(F->ws_mutex);
+    for (int64_t q0 = 0; q0 < J.nq; q0 += kMaxBatch) {
+        const int nb = int(std::min<int64_t>(kMaxBatch, J.nq - q0));
+        gf_status s = run_batch(F, J, q0, nb, st);
+        if (s != GF_OK) return s;
+    }
+    return GF_OK;
+}
+
+gf_status validate_query_common(const gf_forest* F, const float* Q, int64_t nq, int32_t checks,
+                                const int32_t* cpq, double eps) {
+    if (!F) return fail(GF_EINVAL, "forest is NULL");
+    if (nq < 0) return fail(GF_EINVAL, "nq < 0");
+    if (nq > 0 && !Q) return fail(GF_EINVAL, "Q is NULL");
+    if (!cpq && checks < 1) return fail(GF_EINVAL, "checks < 1");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(GF_EINVAL, "eps must be finite and >= 0");
+    return GF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gf_last_error(void) { return g_last_error.c_str(); }
+
+const char* gf_version(void) { return "geraf-gfx950 0.1"; }
+
+gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32_t t, int32_t leaf,
+                          uint64_t seed, uint32_t forms, void* stream, gf_forest** out) {
+    if (!out) return fail(GF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!X) return fail(GF_EINVAL, "X is NULL");
+    if (n < 1 || n >= (int64_t{1} << 31)) return fail(GF_EINVAL, "n must be in [1, 2^31)");
+    if (d < 1) return fail(GF_EINVAL, "d < 1");
+    if (m < 1 || m > 255) return fail(GF_EINVAL, "m must be in [1, 255]");
+    if (t < 1 || t > d) return fail(GF_EINVAL, "t must be in [1, d]");
+    if (t > gf::kMaxT) return fail(GF_EUNSUPPORTED, "t above 64");
+    if (leaf < 1) return fail(GF_EINVAL, "leaf < 1");
+    if (forms & ~(GF_KEEP_BF16 | GF_KEEP_FP8)) return fail(GF_EINVAL, "unknown bits in forms");
+    if (gf::perfect_depth(n, leaf) > 23) return fail(GF_EUNSUPPORTED, "tree depth above 23");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    std::vector<float> staged;
+    const float* Xh = X;
+    if (is_device_ptr(X)) {
+        staged.resize(size_t(n) * d);
+        GF_HIP(hipMemcpy(staged.data(), X, staged.size() * 4, hipMemcpyDeviceToHost));
+        Xh = staged.data();
+    }
+    if (!all_finite_host(Xh, n * int64_t(d))) return fail(GF_EINVAL, "X contains a non-finite value");
+
+    std::unique_ptr<gf_forest> F(new gf_forest());
+    std::string err = gf::build_host_forest(Xh, n, d, m, t, leaf, seed, F->host);
+    if (!err.empty()) return fail(GF_EINTERNAL, err);
+    GF_HIP(hipGetDevice(&F->device));
+    const gf::HostForest& h = F->host;
+    F->ld32 = int32_t(round_up(d, 4));
+    F->ld16 = int32_t(round_up(d, 8));
+    F->ld8 = int32_t(round_up(d, 16));
+    const int64_t nint = (int64_t{1} << h.H) - 1;
+    auto cleanup = [&](gf_status s) { free_forest_device(F.get()); return s; };
+
+#define GF_HIP_B(expr)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return cleanup(fail(GF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+    } while (0)
+
+    GF_HIP_B(hipMalloc(&F->X32, size_t(n) * F->ld32 * 4));
+    GF_HIP_B(hipMemsetAsync(F->X32, 0, size_t(n) * F->ld32 * 4, st));
+    GF_HIP_B(hipMemcpy2DAsync(F->X32, size_t(F->ld32) * 4, Xh, size_t(d) * 4, size_t(d) * 4, n,
+                              hipMemcpyHostToDevice, st));
+    std::vector<uint2> nodes(size_t(m) * std::max<int64_t>(nint, 1));
+    for (int64_t i = 0; i < int64_t(m) * nint; ++i) {
+        uint32_t bits;
+        std::memcpy(&bits, &h.split_val[i], 4);
+        nodes[i] = make_uint2(bits, h.split_slot[i]);
+    }
+    GF_HIP_B(hipMalloc(&F->nodes, nodes.size() * sizeof(uint2)));
+    GF_HIP_B(hipMemcpyAsync(F->nodes, nodes.data(), nodes.size() * sizeof(uint2), hipMemcpyHostToDevice, st));
+    GF_HIP_B(hipMalloc(&F->perm, h.perm.size() * 4));
+    GF_HIP_B(hipMemcpyAsync(F->perm, h.perm.data(), h.perm.size() * 4, hipMemcpyHostToDevice, st));
+    GF_HIP_B(hipMalloc(&F->leaf_off, h.leaf_off.size() * 4));
+    GF_HIP_B(hipMemcpyAsync(F->leaf_off, h.leaf_off.data(), h.leaf_off.size() * 4, hipMemcpyHostToDevice, st));
+    GF_HIP_B(hipMalloc(&F->D, size_t(t) * 4));
+    GF_HIP_B(hipMemcpyAsync(F->D, h.D.data(), size_t(t) * 4, hipMemcpyHostToDevice, st));
+    if (forms & GF_KEEP_BF16) {
+        GF_HIP_B(hipMalloc(&F->X16, size_t(n) * F->ld16 * 2));
+        GF_HIP_B(hipMalloc(&F->norm16, size_t(n) * 4));
+        hipLaunchKernelGGL(gf::k_to_bf16, dim3((n + 3) / 4), dim3(256), 0, st, F->X32, n, d,
+                           int64_t(F->ld32), F->X16, int64_t(F->ld16), F->norm16);
+        GF_HIP_B(hipGetLastError());
+    }
+    if (forms & GF_KEEP_FP8) {
+        GF_HIP_B(hipMalloc(&F->X8, size_t(n) * F->ld8));
+        GF_HIP_B(hipMalloc(&F->scale8, size_t(n) * 4));
+        GF_HIP_B(hipMalloc(&F->norm8, size_t(n) * 4));
+        hipLaunchKernelGGL(gf::k_to_fp8, dim3((n + 3) / 4), dim3(256), 0, st, F->X32, n, d,
+                           int64_t(F->ld32), F->X8, int64_t(F->ld8), F->scale8, F->norm8);
+        GF_HIP_B(hipGetLastError());
+    }
+    GF_HIP_B(hipStreamSynchronize(st));
+#undef GF_HIP_B
+    *out = F.release();
+    return GF_OK;
+}
+
+gf_status gf_free_forest(gf_forest* F) {
+    if (!F) return GF_OK;
+    (void)hipSetDevice(F->device);
+    free_forest_device(F);
+    delete F;
+    return GF_OK;
+}
+
+gf_status gf_forest_info(const gf_forest* F, int64_t* n, int32_t* d, int32_t* m, int32_t* t,
+                         int32_t* leaf, int32_t* H) {
+    if (!F) return fail(GF_EINVAL, "forest is NULL");
+    if (n) *n = F->host.n;
+    if (d) *d = F->host.d;
+    if (m) *m = F->host.m;
+    if (t) *t = F->host.t;
+    if (leaf) *leaf = F->host.p;
+    if (H) *H = F->host.H;
+    return GF_OK;
+}
+
+gf_status gf_export_tree(const gf_forest* F, int32_t* D, int32_t* split_dim, float* split_val,
+                         uint32_t* perm, uint32_t* leaf_off) {
+    if (!F) return fail(GF_EINVAL, "forest is NULL");
+    const gf::HostForest& h = F->host;
+    if (D) std::memcpy(D, h.D.data(), h.D.size() * 4);
+    if (split_dim) std::memcpy(split_dim, h.split_dim.data(), h.split_dim.size() * 4);
+    if (split_val) std::memcpy(split_val, h.split_val.data(), h.split_val.size() * 4);
+    if (perm) std::memcpy(perm, h.perm.data(), h.perm.size() * 4);
+    if (leaf_off) std::memcpy(leaf_off, h.leaf_off.data(), h.leaf_off.size() * 4);
+    return GF_OK;
+}
+
+gf_status gf_query(const gf_forest* Fc, const float* Q, int64_t nq, int32_t k, int32_t checks,
+                   const int32_t* checks_per_query, double eps, int32_t form, int32_t rerank,
+                   int32_t* ids, float* dists, void* stream) {
+    gf_status s = validate_query_common(Fc, Q, nq, checks, checks_per_query, eps);
+    if (s != GF_OK) return s;
+    if (k < 1 || k > gf::kMaxK) return fail(GF_EINVAL, "k must be in [1, 64]");
+    if (nq > 0 && (!ids || !dists)) return fail(GF_EINVAL, "ids or dists is NULL");
+    if (form != GF_FORM_FP32 && form != GF_FORM_BF16 && form != GF_FORM_FP8)
+        return fail(GF_EINVAL, "unknown form");
+    gf_forest* F = const_cast<gf_forest*>(Fc);
+    if (form == GF_FORM_BF16 && !F->X16) return fail(GF_EINVAL, "forest was built without GF_KEEP_BF16");
+    if (form == GF_FORM_FP8 && !F->X8) return fail(GF_EINVAL, "forest was built without GF_KEEP_FP8");
+    int kk;
+    if (form == GF_FORM_FP32) {
+        kk = std::min(gf::kMaxK, k + 8);
+    } else {
+        if (rerank == 0) rerank = std::min(gf::kMaxK, 4 * k);
+        if (rerank < k || rerank > gf::kMaxK) return fail(GF_EINVAL, "rerank must be in [k, 64]");
+        kk = rerank;
+    }
+    if (!gf::scan_supported(F->host.n, form, F->ld8))
+        return fail(GF_EUNSUPPORTED, "n (or d in FP8) too large for the LDS-resident scan");
+    if (nq == 0) return GF_OK;
+    QueryJob J{};
+    J.Q = Q; J.q_dev = is_device_ptr(Q);
+    J.cpq = checks_per_query; J.cpq_dev = checks_per_query && is_device_ptr(checks_per_query);
+    if (checks_per_query && !J.cpq_dev) {
+        for (int64_t i = 0; i < nq; ++i)
+            if (checks_per_query[i] < 1) return fail(GF_EINVAL, "checks_per_query has a value < 1");
+    }
+    J.nq = nq; J.k = k; J.checks = checks; J.eps = eps; J.form = form; J.kk = kk;
+    J.ids = ids; J.dists = dists; J.out_dev = is_device_ptr(ids);
+    if (J.out_dev != is_device_ptr(dists)) return fail(GF_EINVAL, "ids and dists must both be host or both device");
+    return run_query(F, J, static_cast<hipStream_t>(stream));
+}
+
+gf_status gf_query_trace(const gf_forest* Fc, const float* Q, int64_t nq, int32_t checks,
+                         const int32_t* checks_per_query, double eps, uint32_t* leaf_bits,
+                         uint32_t* cand_bits, int64_t* ncand, void* stream) {
+    gf_status s = validate_query_common(Fc, Q, nq, checks, checks_per_query, eps);
+    if (s != GF_OK) return s;
+    gf_forest* F = const_cast<gf_forest*>(Fc);
+    if (!gf::scan_supported(F->host.n, GF_FORM_FP32, F->ld8))
+        return fail(GF_EUNSUPPORTED, "n too large for the LDS visited bitmap");
+    if (nq == 0) return GF_OK;
+    QueryJob J{};
+    J.Q = Q; J.q_dev = is_device_ptr(Q);
+    J.cpq = checks_per_query; J.cpq_dev = checks_per_query && is_device_ptr(checks_per_query);
+    if (checks_per_query && !J.cpq_dev) {
+        for (int64_t i = 0; i < nq; ++i)
+            if (checks_per_query[i] < 1) return fail(GF_EINVAL, "checks_per_query has a value < 1");
+    }
+    J.nq = nq; J.k = 1; J.checks = checks; J.eps = eps; J.form = GF_FORM_FP32; J.kk = 1;
+    J.leaf_bits = leaf_bits; J.cand_bits = cand_bits; J.ncand = ncand;
+    const void* any = leaf_bits ? (const void*)leaf_bits : cand_bits ? (const void*)cand_bits : (const void*)ncand;
+    J.trace_dev = any && is_device_ptr(any);
+    return run_query(F, J, static_cast<hipStream_t>(stream));
+}
+
+gf_status gf_fp8_tables(float* hw_decode, float* def_decode, const float* enc_in, int32_t n_enc,
+                        uint8_t* enc_out) {
+    if (!hw_decode || !def_decode || n_enc < 0 || (n_enc > 0 && (!enc_in || !enc_out)))
+        return fail(GF_EINVAL, "bad arguments");
+    float *dh = nullptr, *ds = nullptr, *din = nullptr;
+    uint8_t* dout = nullptr;
+    GF_HIP(hipMalloc(&dh, 256 * 4));
+    GF_HIP(hipMalloc(&ds, 256 * 4));
+    hipLaunchKernelGGL(gf::k_e4m3_decode_both, dim3(1), dim3(256), 0, 0, dh, ds);
+    GF_HIP(hipGetLastError());
+    GF_HIP(hipMemcpy(hw_decode, dh, 256 * 4, hipMemcpyDeviceToHost));
+    GF_HIP(hipMemcpy(def_decode, ds, 256 * 4, hipMemcpyDeviceToHost));
+    (void)hipFree(dh);
+    (void)hipFree(ds);
+    if (n_enc > 0) {
+        GF_HIP(hipMalloc(&din, size_t(n_enc) * 4));
+        GF_HIP(hipMalloc(&dout, size_t(n_enc)));
+        GF_HIP(hipMemcpy(din, enc_in, size_t(n_enc) * 4, hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(gf::k_e4m3_encode, dim3((n_enc + 255) / 256), dim3(256), 0, 0, din, n_enc, dout);
+        GF_HIP(hipGetLastError());
+        GF_HIP(hipMemcpy(enc_out, dout, size_t(n_enc), hipMemcpyDeviceToHost));
+        (void)hipFree(din);
+        (void)hipFree(dout);
+    }
+    return GF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// forest.h -- internal types of the kd-GeRaF library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/geraf.h"
+
+namespace gf {
+
+// Maximum size of the top-variance set D (query-side staging of q_D).
+constexpr int kMaxT = 64;
+// Largest k and re-rank depth (one list slot per lane of a wavefront).
+constexpr int kMaxK = 64;
+
+// Host-side forest arrays produced by the build (Alg. 1).
+struct HostForest {
+    int64_t n = 0;
+    int32_t d = 0, m = 0, t = 0, p = 0, H = 0;
+    uint64_t seed = 0;
+    std::vector<int32_t> D;           // [t] ascending
+    std::vector<int32_t> split_dim;   // [m][2^H - 1] column index
+    std::vector<uint8_t> split_slot;  // [m][2^H - 1] index into D
+    std::vector<float> split_val;     // [m][2^H - 1]
+    std::vector<uint32_t> perm;       // [m][n] leaf-ordered point ids
+    std::vector<uint32_t> leaf_off;   // [2^H + 1]
+};
+
+// Counter-based RNG (splitmix64 output function, keyed).
+uint64_t splitmix64(uint64_t x);
+uint64_t keyed_draw(uint64_t seed, uint64_t stream, uint64_t tree, uint64_t idx);
+
+int32_t perfect_depth(int64_t n, int32_t p);
+
+// Builds the host arrays; X is host memory [n][d].  Returns an empty string
+// on success, else the error text.
+std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, int32_t t,
+                              int32_t p, uint64_t seed, HostForest& out);
+
+}  // namespace gf
+
+// Device-resident forest (the opaque handle of the ABI).
+struct gf_forest {
+    gf::HostForest host;
+    int device = 0;
+    int32_t ld32 = 0;       // FP32 row stride (floats), multiple of 4
+    int32_t ld16 = 0;       // BF16 row stride (elements), multiple of 8
+    int32_t ld8 = 0;        // FP8 row stride (bytes), multiple of 16
+    float* X32 = nullptr;           // [n][ld32]
+    uint16_t* X16 = nullptr;        // [n][ld16] bfloat16 bits
+    float* norm16 = nullptr;        // [n] ||bf16(x)||^2
+    uint8_t* X8 = nullptr;          // [n][ld8] e4m3 bytes
+    float* scale8 = nullptr;        // [n] per-row scale
+    float* norm8 = nullptr;         // [n] ||dequant(x)||^2
+    uint2* nodes = nullptr;         // [m][2^H - 1] {float bits of value, slot in D}
+    uint32_t* perm = nullptr;       // [m][n]
+    uint32_t* leaf_off = nullptr;   // [2^H + 1]
+    int32_t* D = nullptr;           // [t]
+    // Grow-only scratch for queries.  Calls on one forest are serialised by
+    // this mutex (concurrent queries on one forest wait for each other).
+    std::mutex ws_mutex;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+};

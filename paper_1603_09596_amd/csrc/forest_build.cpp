@@ -1,0 +1,205 @@
+// forest_build.cpp -- host-side construction of the randomized k-d forest
+// (Alg. 1, Sec. 2.2; storage of Sec. 3 "Tree structure").
+//
+// Each tree is built level by level over one permutation array: at depth h
+// every node owns a contiguous segment of it, and splitting a node is a
+// selection (std::nth_element) of its floor(|P|/2) smallest points under the
+// order (coordinate in the split dimension, per-tree random key, id), which
+// is the paper's median split with its "shuffling" tie-break made
+// deterministic.  Trees are independent and are built by separate threads
+// (Sec. 3 "Parallelization").
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "forest.h"
+
+namespace gf {
+
+uint64_t splitmix64(uint64_t x) {
+    // splitmix64 output function (Steele, Lea, Flood 2014): advance by the
+    // golden-ratio increment, then two xor-shift-multiply rounds.
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+uint64_t keyed_draw(uint64_t seed, uint64_t stream, uint64_t tree, uint64_t idx) {
+    uint64_t h = splitmix64(seed);
+    h = splitmix64(h ^ stream);
+    h = splitmix64(h ^ tree);
+    return splitmix64(h ^ idx);
+}
+
+int32_t perfect_depth(int64_t n, int32_t p) {
+    int32_t H = 0;
+    while (((n + (int64_t{1} << H) - 1) >> H) > p) ++H;
+    return H;
+}
+
+namespace {
+
+constexpr uint64_t kStreamSplitDim = 1;
+constexpr uint64_t kStreamTieKey = 2;
+
+unsigned worker_count(int64_t jobs) {
+    unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    return static_cast<unsigned>(std::min<int64_t>(hw, std::max<int64_t>(1, jobs)));
+}
+
+// Per-dimension variance with Knuth's online update (Alg. 3), run over a
+// block of rows per thread; the per-block (count, mean, M2) triples are then
+// combined pairwise (Chan, Golub, LeVeque).
+void column_variance(const float* X, int64_t n, int32_t d, std::vector<double>& V) {
+    V.assign(d, 0.0);
+    if (n < 2) return;
+    const unsigned nw = worker_count(n / 4096 + 1);
+    std::vector<std::vector<double>> mean(nw, std::vector<double>(d, 0.0));
+    std::vector<std::vector<double>> m2(nw, std::vector<double>(d, 0.0));
+    std::vector<int64_t> cnt(nw, 0);
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nw; ++w) {
+        th.emplace_back([&, w] {
+            int64_t a = n * w / nw, b = n * (w + 1) / nw;
+            double* mu = mean[w].data();
+            double* v = m2[w].data();
+            for (int64_t i = a; i < b; ++i) {
+                const double alpha = 1.0 / double(i - a + 1);
+                const float* x = X + i * d;
+                for (int32_t j = 0; j < d; ++j) {
+                    double delta = double(x[j]) - mu[j];
+                    mu[j] += alpha * delta;
+                    v[j] += delta * (double(x[j]) - mu[j]);
+                }
+            }
+            cnt[w] = b - a;
+        });
+    }
+    for (auto& t : th) t.join();
+    std::vector<double> mu = mean[0], v = m2[0];
+    double na = double(cnt[0]);
+    for (unsigned w = 1; w < nw; ++w) {
+        double nb = double(cnt[w]);
+        if (nb == 0) continue;
+        double nt = na + nb;
+        for (int32_t j = 0; j < d; ++j) {
+            double delta = mean[w][j] - mu[j];
+            mu[j] += delta * nb / nt;
+            v[j] += m2[w][j] + delta * delta * na * nb / nt;
+        }
+        na = nt;
+    }
+    for (int32_t j = 0; j < d; ++j) V[j] = v[j] / double(n - 1);
+}
+
+struct Item {
+    float x;
+    uint64_t key;
+    uint32_t id;
+};
+
+inline bool item_less(const Item& a, const Item& b) {
+    if (a.x < b.x) return true;      // float order: -0 and +0 compare equal
+    if (b.x < a.x) return false;
+    if (a.key != b.key) return a.key < b.key;
+    return a.id < b.id;
+}
+
+void build_tree(const float* X, int64_t n, int32_t d, const HostForest& F, int32_t tree,
+                std::vector<int32_t>& split_dim, std::vector<uint8_t>& split_slot,
+                std::vector<float>& split_val, uint32_t* ids) {
+    const int32_t H = F.H;
+    const int64_t nint = (int64_t{1} << H) - 1;
+    std::vector<uint64_t> tie(n);
+    for (int64_t i = 0; i < n; ++i) tie[i] = keyed_draw(F.seed, kStreamTieKey, tree, uint64_t(i));
+    for (int64_t i = 0; i < n; ++i) ids[i] = uint32_t(i);
+    std::vector<Item> items;
+    // sizes/offsets of the nodes of the current level
+    std::vector<int64_t> size{n}, off{0};
+    for (int32_t h = 0; h < H; ++h) {
+        std::vector<int64_t> nsize, noff;
+        nsize.reserve(size.size() * 2);
+        noff.reserve(size.size() * 2);
+        for (size_t j = 0; j < size.size(); ++j) {
+            const int64_t v = (int64_t{1} << h) - 1 + int64_t(j);
+            const int64_t len = size[j], o = off[j];
+            const uint64_t r = keyed_draw(F.seed, kStreamSplitDim, tree, uint64_t(v));
+            const int32_t slot = int32_t(r % uint64_t(F.t));
+            const int32_t s = F.D[slot];
+            items.resize(len);
+            for (int64_t a = 0; a < len; ++a) {
+                uint32_t id = ids[o + a];
+                items[a] = Item{X[int64_t(id) * d + s], tie[id], id};
+            }
+            const int64_t nl = len / 2;
+            std::nth_element(items.begin(), items.begin() + nl, items.end(), item_less);
+            for (int64_t a = 0; a < len; ++a) ids[o + a] = items[a].id;
+            const int64_t slotpos = int64_t(tree) * nint + v;
+            split_dim[slotpos] = s;
+            split_slot[slotpos] = uint8_t(slot);
+            split_val[slotpos] = items[nl].x;   // smallest coordinate on the right
+            nsize.push_back(nl);
+            noff.push_back(o);
+            nsize.push_back(len - nl);
+            noff.push_back(o + nl);
+        }
+        size.swap(nsize);
+        off.swap(noff);
+    }
+    for (size_t j = 0; j < size.size(); ++j) std::sort(ids + off[j], ids + off[j] + size[j]);
+}
+
+}  // namespace
+
+std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, int32_t t,
+                              int32_t p, uint64_t seed, HostForest& F) {
+    F = HostForest{};
+    F.n = n; F.d = d; F.m = m; F.t = t; F.p = p; F.seed = seed;
+    F.H = perfect_depth(n, p);
+    if (F.H > 23) return "tree depth above 23 (n/leaf too large)";
+    const int64_t nint = (int64_t{1} << F.H) - 1;
+    const int64_t nleaf = int64_t{1} << F.H;
+
+    // V <- variances; D <- the t dimensions of largest variance (lower index
+    // first among equal variances), kept in ascending index order.
+    std::vector<double> V;
+    column_variance(X, n, d, V);
+    std::vector<int32_t> order(d);
+    for (int32_t j = 0; j < d; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return V[a] > V[b]; });
+    F.D.assign(order.begin(), order.begin() + t);
+    std::sort(F.D.begin(), F.D.end());
+
+    // Leaf offsets: node sizes split floor/ceil, so they depend on n only.
+    std::vector<int64_t> size{n};
+    for (int32_t h = 0; h < F.H; ++h) {
+        std::vector<int64_t> nx;
+        nx.reserve(size.size() * 2);
+        for (int64_t s : size) { nx.push_back(s / 2); nx.push_back(s - s / 2); }
+        size.swap(nx);
+    }
+    F.leaf_off.resize(nleaf + 1);
+    F.leaf_off[0] = 0;
+    for (int64_t j = 0; j < nleaf; ++j) F.leaf_off[j + 1] = uint32_t(F.leaf_off[j] + size[j]);
+
+    F.split_dim.assign(size_t(m) * nint, 0);
+    F.split_slot.assign(size_t(m) * nint, 0);
+    F.split_val.assign(size_t(m) * nint, 0.0f);
+    F.perm.resize(size_t(m) * n);
+    const unsigned nw = worker_count(m);
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nw; ++w) {
+        th.emplace_back([&, w] {
+            for (int32_t tree = int32_t(w); tree < m; tree += int32_t(nw))
+                build_tree(X, n, d, F, tree, F.split_dim, F.split_slot, F.split_val,
+                           F.perm.data() + size_t(tree) * n);
+        });
+    }
+    for (auto& x : th) x.join();
+    return {};
+}
+
+}  // namespace gf

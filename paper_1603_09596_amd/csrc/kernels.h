@@ -1,0 +1,98 @@
+// kernels.h -- argument blocks and launchers of the query-path kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gf {
+
+// ---------------------------------------------------------------- selection
+
+constexpr int kCollectCap = 4096;   // keys resolved by the final per-query sort
+constexpr int kMaxPasses = 9;       // 63 significant key bits / 7-bit digits
+
+enum : uint32_t { kSelSearching = 0, kSelReady = 1, kSelAll = 2, kSelDone = 3 };
+
+struct SelState {
+    uint64_t prefix;      // key digits fixed so far
+    uint32_t pass;        // number of digits fixed
+    uint32_t below;       // leaves whose key is below the current bin
+    uint32_t budget;      // B of this query
+    uint32_t status;
+    uint32_t bincount;    // leaves inside the current bin
+    uint32_t pad;
+};
+
+struct SelectArgs {
+    const float* Q;        // [nq][ldq] device
+    int64_t ldq;
+    int nq;
+    int m, H, t;
+    int64_t n_internal;    // 2^H - 1
+    int W;                 // leaf-bitmap words per tree
+    const uint2* nodes;    // [m][n_internal]
+    const int32_t* D;      // [t]
+    SelState* state;       // [nq]
+    uint32_t* hist;        // [nq][128]
+    uint32_t* ncollect;    // [nq]
+    uint64_t* ckey;        // [nq][kCollectCap]
+    uint32_t* ccode;       // [nq][kCollectCap]
+    uint32_t* leafbits;    // [m][W][nq]  (word-major, query fastest)
+};
+
+__global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps);
+__global__ void k_select_pick(SelectArgs a, int pass, uint32_t* any_searching);
+__global__ void k_select_finish(SelectArgs a);
+hipError_t launch_select_walk(const SelectArgs& a, int pass, bool collect, hipStream_t st);
+
+// --------------------------------------------------------------------- scan
+
+enum : int { kFormFP32 = 0, kFormBF16 = 1, kFormFP8 = 2 };
+
+struct ScanArgs {
+    int nq, k, kk;          // kk: list length kept per query (>= k)
+    int64_t n;
+    int d;
+    int m, W;
+    const uint32_t* leafbits;   // [m][W][nq]
+    const uint32_t* perm;       // [m][n]
+    const uint32_t* leaf_off;   // [2^H + 1]
+    const float* Q;             // [nq][ldq] FP32 queries (device)
+    int64_t ldq;
+    const float* X32;           // [n][ld32]
+    int64_t ld32;
+    // reduced-precision copies
+    const uint16_t* X16; int64_t ld16; const float* norm16;
+    const uint8_t* X8; int64_t ld8; const float* scale8; const float* norm8;
+    const uint16_t* Q16;        // [nq][ld16] bf16 queries
+    const uint8_t* Q8;          // [nq][ld8] e4m3 queries
+    const float* qscale8;       // [nq]
+    const float* qnorm;         // [nq] squared norm of the reduced query
+    // outputs
+    int32_t* ids;               // [nq][k]
+    float* dists;               // [nq][k]
+    uint32_t* cand_bits;        // [nq][ceil(n/32)] or null
+    int64_t* ncand;             // [nq] or null
+};
+
+// Scan kernel launch: one workgroup per query.  Returns hipErrorInvalidValue
+// when the (form, d) combination has no instantiation.
+hipError_t launch_scan(const ScanArgs& a, int form, hipStream_t st);
+size_t scan_lds_bytes(int64_t n, int form, int64_t ld8);
+bool scan_supported(int64_t n, int form, int64_t ld8);
+
+// --------------------------------------------------------- data conversion
+
+__global__ void k_to_bf16(const float* X, int64_t n, int d, int64_t ldx, uint16_t* Y,
+                          int64_t ldy, float* norm);
+__global__ void k_to_fp8(const float* X, int64_t n, int d, int64_t ldx, uint8_t* Y,
+                         int64_t ldy, float* scale, float* norm);
+__global__ void k_pad_rows(const float* X, int64_t n, int d, float* Y, int64_t ldy);
+__global__ void k_check_finite(const float* X, int64_t n, int d, int64_t ld, uint32_t* bad);
+__global__ void k_leafbits_to_query_major(const uint32_t* src, int nq, int64_t words,
+                                          uint32_t* dst);
+__global__ void k_e4m3_decode_both(float* hw, float* sw);
+__global__ void k_e4m3_encode(const float* x, int n, uint8_t* y);
+
+}  // namespace gf

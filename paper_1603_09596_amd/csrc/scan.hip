@@ -1,0 +1,553 @@
+// scan.hip -- candidates, distances and the k best of every query on gfx950
+// (Alg. 2 "descend at a leaf" and the visited array of Sec. 2.3; the
+// squared-norm expansion of Sec. 3 "Distance computation").
+//
+// One workgroup of 8 wavefronts per query:
+//   1. expansion: every opened leaf's point ids are OR-ed into a visited
+//      bitmap of n bits held in LDS, so each candidate appears once however
+//      many trees reach it;
+//   2. scan: the waves walk the bitmap in point-id order (16 words at a time
+//      per wave), gather the candidate rows with 16-byte loads and reduce each
+//      row's distance across the lanes that share it; walking ids in order
+//      keeps the row gathers monotone in address, so concurrent queries on
+//      the chip stream through the same region of X;
+//   3. each wave keeps its best `kk` (distance, id) pairs, one per lane,
+//      sorted; the eight lists are merged at the end;
+//   4. reduced-precision forms: the merged `kk` candidates are measured again
+//      on the FP32 rows with a compensated sum (two-sum / two-product), then
+//      ranked; every form: the distances within 1e-5 relative of the k-th
+//      are measured once more in FP64 and the tie group is re-ranked by
+//      (FP64 distance, id).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace gf {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kWaves = 8;
+constexpr int kThreads = kWave * kWaves;
+constexpr int kListWords = 16;                // bitmap words per wave step
+constexpr int kListCap = kListWords * 32;     // ids per wave step
+constexpr float kTieBand = 1e-5f;
+
+__device__ __forceinline__ bool entry_before(float da, int ia, float db, int ib) {
+    return da < db || (da == db && ia < ib);
+}
+
+// Sorted best-kk list spread over lanes 0..kk-1 of a wavefront.
+struct WaveList {
+    float d;
+    int id;
+    __device__ void init() { d = __builtin_inff(); id = 0x7FFFFFFF; }
+    __device__ float thr_d(int kk) const {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), kk - 1));
+    }
+    __device__ int thr_id(int kk) const { return __builtin_amdgcn_readlane(id, kk - 1); }
+    // Insert a wave-uniform (dc, ic) known to beat the current kk-th entry.
+    __device__ void insert(float dc, int ic, int kk) {
+        const int lane = threadIdx.x & (kWave - 1);
+        const bool before = lane < kk && entry_before(d, id, dc, ic);
+        const int pos = __popcll(__ballot(before));
+        const float pd = __shfl_up(d, 1);
+        const int pi = __shfl_up(id, 1);
+        if (lane < kk) {
+            if (lane > pos) { d = pd; id = pi; }
+            else if (lane == pos) { d = dc; id = ic; }
+        }
+    }
+    __device__ void offer(float dc, int ic, int kk) {
+        const float td = thr_d(kk);
+        const int ti = thr_id(kk);
+        if (entry_before(dc, ic, td, ti)) insert(dc, ic, kk);
+    }
+};
+
+template <int LPR>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+    for (int o = LPR / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ------------------------------------------------------------- row scoring
+
+template <int FORM>
+struct Chunk;   // one 16-byte slice of a row in the given storage form
+
+template <>
+struct Chunk<kFormFP32> {
+    using T = float4;
+    static constexpr int kElems = 4;
+    __device__ static float score(const float4& q, const float4& x) {
+        const float a = q.x - x.x, b = q.y - x.y, c = q.z - x.z, e = q.w - x.w;
+        return fmaf(a, a, fmaf(b, b, fmaf(c, c, e * e)));
+    }
+};
+
+template <>
+struct Chunk<kFormBF16> {
+    using T = uint4;
+    static constexpr int kElems = 8;
+    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+    __device__ static float dot2(uint32_t a, uint32_t b, float acc) {
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf2, a),
+                                               __builtin_bit_cast(bf2, b), acc, false);
+    }
+    __device__ static float score(const uint4& q, const uint4& x) {
+        float acc = dot2(q.x, x.x, 0.0f);
+        acc = dot2(q.y, x.y, acc);
+        acc = dot2(q.z, x.z, acc);
+        return dot2(q.w, x.w, acc);
+    }
+};
+
+template <>
+struct Chunk<kFormFP8> {
+    using T = uint4;
+    static constexpr int kElems = 16;
+    __device__ static float dot4(uint32_t a, uint32_t b, float acc) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const f2 a0 = __builtin_amdgcn_cvt_pk_f32_fp8(a, false);
+        const f2 a1 = __builtin_amdgcn_cvt_pk_f32_fp8(a, true);
+        const f2 b0 = __builtin_amdgcn_cvt_pk_f32_fp8(b, false);
+        const f2 b1 = __builtin_amdgcn_cvt_pk_f32_fp8(b, true);
+        acc = fmaf(a0.x, b0.x, acc);
+        acc = fmaf(a0.y, b0.y, acc);
+        acc = fmaf(a1.x, b1.x, acc);
+        return fmaf(a1.y, b1.y, acc);
+    }
+    __device__ static float score(const uint4& q, const uint4& x) {
+        float acc = dot4(q.x, x.x, 0.0f);
+        acc = dot4(q.y, x.y, acc);
+        acc = dot4(q.z, x.z, acc);
+        return dot4(q.w, x.w, acc);
+    }
+    // x (16 codes) against the decoded query held in LDS
+    __device__ static float score_lds(const float* q, const uint4& x) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+        const float4* q4 = reinterpret_cast<const float4*>(q);
+        float acc = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const f2 lo = __builtin_amdgcn_cvt_pk_f32_fp8(w[i], false);
+            const f2 hi = __builtin_amdgcn_cvt_pk_f32_fp8(w[i], true);
+            const float4 qq = q4[i];
+            acc = fmaf(lo.x, qq.x, acc);
+            acc = fmaf(lo.y, qq.y, acc);
+            acc = fmaf(hi.x, qq.z, acc);
+            acc = fmaf(hi.y, qq.w, acc);
+        }
+        return acc;
+    }
+};
+
+// Compensated FP32 squared distance of one row, computed by a whole wave:
+// (q - x) split exactly into s + e (two-sum), s^2 split exactly into p + r
+// (two-product with FMA), the p's summed with two-sum and every rounding
+// error collected in a second accumulator (Ogita, Rump, Oishi 2005).
+__device__ float row_dist_fp32_comp(const float* q, const float* x, int d) {
+    const int lane = threadIdx.x & (kWave - 1);
+    float sum = 0.0f, err = 0.0f;
+    for (int j = lane; j < d; j += kWave) {
+        const float a = q[j], b = -x[j];
+        const float s = a + b;
+        const float bb = s - a;
+        const float e = (a - (s - bb)) + (b - bb);
+        const float p = s * s;
+        const float r = fmaf(s, s, -p);
+        const float t = sum + p;
+        const float tp = t - sum;
+        err += ((sum - (t - tp)) + (p - tp)) + r + fmaf(2.0f * s, e, e * e);
+        sum = t;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+        const float os = __shfl_xor(sum, o);
+        const float oe = __shfl_xor(err, o);
+        const float t = sum + os;
+        const float tp = t - sum;
+        err = err + oe + ((sum - (t - tp)) + (os - tp));
+        sum = t;
+    }
+    return sum + err;
+}
+
+__device__ double row_dist_fp64(const float* q, const float* x, int d) {
+    const int lane = threadIdx.x & (kWave - 1);
+    double acc = 0.0;
+    for (int j = lane; j < d; j += kWave) {
+        const double diff = double(q[j]) - double(x[j]);
+        acc = fma(diff, diff, acc);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+    return acc;
+}
+
+// Re-rank the list by (FP64 distance, id) inside the band of the k-th place.
+__device__ void refine_ties(WaveList& L, int kk, int k, const float* q, const float* X32,
+                            int64_t ld32, int d) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const float dk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(L.d), k - 1));
+    double key = double(L.d);
+    if (dk < __builtin_inff()) {
+        const float lo = dk * (1.0f - kTieBand), hi = dk * (1.0f + kTieBand);
+        const bool inband = lane < kk && L.d >= lo && L.d <= hi && L.d < __builtin_inff();
+        uint64_t band = __ballot(inband);
+        while (band) {
+            const int b = __builtin_ctzll(band);
+            band &= band - 1;
+            const int id = __builtin_amdgcn_readlane(L.id, b);
+            const double d64 = row_dist_fp64(q, X32 + int64_t(id) * ld32, d);
+            if (lane == b) key = d64;
+        }
+    }
+    // bitonic sort of the 64 lanes by (key, id); lanes >= kk carry +inf
+    int id = L.id;
+    if (lane >= kk) { key = __builtin_inf(); id = 0x7FFFFFFF; }
+#pragma unroll
+    for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const double ok = __shfl_xor(key, stride);
+            const int oid = __shfl_xor(id, stride);
+            const bool up = (lane & size) == 0;
+            const bool lower = (lane & stride) == 0;
+            const bool other_first = ok < key || (ok == key && oid < id);
+            const bool take = (lower == up) ? other_first : !other_first;
+            if (take) { key = ok; id = oid; }
+        }
+    }
+    L.d = float(key);
+    L.id = id;
+}
+
+// ------------------------------------------------------------------ kernel
+
+template <int FORM, int LPR, int CPL>
+__global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
+    using C = Chunk<FORM>;
+    using T = typename C::T;
+    constexpr int G = kWave / LPR;     // rows per load instruction
+    // CPL == 0: rows wider than the register-resident tiles; each lane
+    // streams its chunks and reads the query from global memory (cached).
+    constexpr bool kStream = (CPL == 0);
+    constexpr int CPLR = kStream ? 1 : CPL;
+    constexpr int U = kStream ? 1 : ((FORM == kFormFP8 && CPL > 8) ? 1 : 2);
+    extern __shared__ uint32_t smem[];
+    const int q = blockIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int64_t nbmw = (a.n + 31) / 32;
+    const int64_t nbmw_pad = (nbmw + kListWords - 1) / kListWords * kListWords;
+    uint32_t* bm = smem;                                        // [nbmw_pad]
+    uint32_t* lists = bm + nbmw_pad;                            // [kWaves][kListCap]
+    float* mg_d = reinterpret_cast<float*>(lists + kWaves * kListCap);   // [kWaves][64]
+    int* mg_i = reinterpret_cast<int*>(mg_d + kWaves * kWave);           // [kWaves][64]
+    float* rr_d = reinterpret_cast<float*>(mg_i + kWaves * kWave);       // [64]
+    float* q8f = rr_d + kWave;                                           // [ld8] (FP8 form)
+
+    // 1. visited bitmap <- union of the opened leaves
+    for (int64_t i = threadIdx.x; i < nbmw_pad; i += kThreads) bm[i] = 0u;
+    __syncthreads();
+    const int64_t nwords = int64_t(a.m) * a.W;
+    for (int64_t f = threadIdx.x; f < nwords; f += kThreads) {
+        uint32_t bits = a.leafbits[f * a.nq + q];
+        if (!bits) continue;
+        const int tree = int(f / a.W);
+        const uint32_t wbase = uint32_t(f % a.W) * 32u;
+        const uint32_t* pts = a.perm + int64_t(tree) * a.n;
+        while (bits) {
+            const uint32_t leaf = wbase + uint32_t(__builtin_ctz(bits));
+            bits &= bits - 1;
+            const uint32_t lo = a.leaf_off[leaf], hi = a.leaf_off[leaf + 1];
+            uint32_t i = lo;
+            for (; i + 4 <= hi; i += 4) {
+                const uint32_t p0 = pts[i], p1 = pts[i + 1], p2 = pts[i + 2], p3 = pts[i + 3];
+                atomicOr(&bm[p0 >> 5], 1u << (p0 & 31u));
+                atomicOr(&bm[p1 >> 5], 1u << (p1 & 31u));
+                atomicOr(&bm[p2 >> 5], 1u << (p2 & 31u));
+                atomicOr(&bm[p3 >> 5], 1u << (p3 & 31u));
+            }
+            for (; i < hi; ++i) {
+                const uint32_t p0 = pts[i];
+                atomicOr(&bm[p0 >> 5], 1u << (p0 & 31u));
+            }
+        }
+    }
+    __syncthreads();
+    if (a.cand_bits) {
+        for (int64_t i = threadIdx.x; i < nbmw; i += kThreads)
+            a.cand_bits[int64_t(q) * nbmw + i] = bm[i];
+    }
+    if (a.ncand) {
+        uint32_t cnt = 0;
+        for (int64_t i = threadIdx.x; i < nbmw; i += kThreads) cnt += __popc(bm[i]);
+        for (int o = kWave / 2; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
+        if (lane == 0) mg_i[wave] = int(cnt);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t tot = 0;
+            for (int w = 0; w < kWaves; ++w) tot += mg_i[w];
+            a.ncand[q] = tot;
+        }
+        __syncthreads();
+    }
+
+    // 2./3. scan the candidates in id order, keep the best kk per wave
+    const int sub = lane % LPR;
+    const int grp = lane / LPR;
+    const int64_t nchunks_row = (FORM == kFormFP32) ? (a.ld32 / 4)
+                              : (FORM == kFormBF16) ? (a.ld16 / 8) : (a.ld8 / 16);
+    const T* Xb = (FORM == kFormFP32) ? reinterpret_cast<const T*>(a.X32)
+                : (FORM == kFormBF16) ? reinterpret_cast<const T*>(a.X16)
+                                      : reinterpret_cast<const T*>(a.X8);
+    const T* Qrow = (FORM == kFormFP32) ? reinterpret_cast<const T*>(a.Q + int64_t(q) * a.ldq)
+                  : (FORM == kFormBF16) ? reinterpret_cast<const T*>(a.Q16 + int64_t(q) * a.ld16)
+                                        : reinterpret_cast<const T*>(a.Q8 + int64_t(q) * a.ld8);
+    constexpr int QREG = (FORM == kFormFP8 || kStream) ? 1 : CPL;
+    T qv[QREG];
+    if constexpr (FORM == kFormFP8) {
+        // the e4m3 query, decoded once into LDS (same conversion as the rows)
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const uint32_t* q8w = reinterpret_cast<const uint32_t*>(a.Q8 + int64_t(q) * a.ld8);
+        for (int64_t i = threadIdx.x; i < a.ld8 / 4; i += kThreads) {
+            const uint32_t wv = q8w[i];
+            const f2 lo = __builtin_amdgcn_cvt_pk_f32_fp8(wv, false);
+            const f2 hi = __builtin_amdgcn_cvt_pk_f32_fp8(wv, true);
+            q8f[4 * i] = lo.x; q8f[4 * i + 1] = lo.y; q8f[4 * i + 2] = hi.x; q8f[4 * i + 3] = hi.y;
+        }
+        __syncthreads();
+        qv[0] = T{};
+    } else if constexpr (kStream) {
+        qv[0] = T{};
+    } else {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            const int64_t ci = sub + int64_t(j) * LPR;
+            qv[j] = (ci < nchunks_row) ? Qrow[ci] : T{};
+        }
+    }
+    float qn = 0.0f, qs = 0.0f;
+    if (FORM != kFormFP32) qn = a.qnorm[q];
+    if (FORM == kFormFP8) qs = a.qscale8[q];
+
+    WaveList L;
+    L.init();
+    const int kk = a.kk;
+    uint32_t* list = lists + wave * kListCap;
+    const int64_t nsteps = nbmw_pad / kListWords;
+    for (int64_t step = wave; step < nsteps; step += kWaves) {
+        uint32_t w = (lane < kListWords) ? bm[step * kListWords + lane] : 0u;
+        const int cnt = __popc(w);
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < kListWords; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        const int total = __shfl(incl, kListWords - 1);
+        if (total == 0) continue;
+        int pos = incl - cnt;
+        const uint32_t base = uint32_t(step * kListWords + lane) * 32u;
+        while (w) {
+            list[pos++] = base + uint32_t(__builtin_ctz(w));
+            w &= w - 1;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int r0 = 0; r0 < total; r0 += G * U) {
+            int rid[U];
+            T xv[U][CPLR];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int slot = r0 + u * G + grp;
+                rid[u] = (slot < total) ? int(list[slot]) : -1;
+                if constexpr (!kStream) {
+                    const T* xr = Xb + int64_t(rid[u] < 0 ? 0 : rid[u]) * nchunks_row;
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) {
+                        const int64_t ci = sub + int64_t(j) * LPR;
+                        xv[u][j] = (rid[u] >= 0 && ci < nchunks_row) ? xr[ci] : T{};
+                    }
+                }
+            }
+            float dist[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                float acc = 0.0f;
+                if constexpr (kStream) {
+                    if (rid[u] >= 0) {
+                        const T* xr = Xb + int64_t(rid[u]) * nchunks_row;
+                        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+                        int64_t ci = sub;
+                        for (; ci + 3 * LPR < nchunks_row; ci += 4 * LPR) {
+                            const T x0 = xr[ci], x1 = xr[ci + LPR], x2 = xr[ci + 2 * LPR],
+                                    x3 = xr[ci + 3 * LPR];
+                            if constexpr (FORM == kFormFP8) {
+                                a0 += C::score_lds(q8f + ci * 16, x0);
+                                a1 += C::score_lds(q8f + (ci + LPR) * 16, x1);
+                                a2 += C::score_lds(q8f + (ci + 2 * LPR) * 16, x2);
+                                a3 += C::score_lds(q8f + (ci + 3 * LPR) * 16, x3);
+                            } else {
+                                a0 += C::score(Qrow[ci], x0);
+                                a1 += C::score(Qrow[ci + LPR], x1);
+                                a2 += C::score(Qrow[ci + 2 * LPR], x2);
+                                a3 += C::score(Qrow[ci + 3 * LPR], x3);
+                            }
+                        }
+                        for (; ci < nchunks_row; ci += LPR) {
+                            if constexpr (FORM == kFormFP8) a0 += C::score_lds(q8f + ci * 16, xr[ci]);
+                            else a0 += C::score(Qrow[ci], xr[ci]);
+                        }
+                        acc = (a0 + a1) + (a2 + a3);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) {
+                        if constexpr (FORM == kFormFP8) {
+                            const int64_t ci = sub + int64_t(j) * LPR;
+                            if (ci < nchunks_row) acc += C::score_lds(q8f + ci * 16, xv[u][j]);
+                        } else {
+                            acc += C::score(qv[QREG > 1 ? j : 0], xv[u][j]);
+                        }
+                    }
+                }
+                acc = group_sum<LPR>(acc);
+                if (FORM == kFormBF16 && rid[u] >= 0)
+                    acc = a.norm16[rid[u]] - 2.0f * acc + qn;
+                if (FORM == kFormFP8 && rid[u] >= 0)
+                    acc = a.norm8[rid[u]] - 2.0f * (a.scale8[rid[u]] * qs) * acc + qn;
+                dist[u] = acc;
+            }
+            const float td = L.thr_d(kk);
+            const int ti = L.thr_id(kk);
+            bool any_q = false;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                any_q |= (sub == 0 && rid[u] >= 0 && entry_before(dist[u], rid[u], td, ti));
+            if (!__any(any_q)) continue;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int idc = __builtin_amdgcn_readlane(rid[u], g * LPR);
+                    if (idc < 0) continue;
+                    const float dc = __int_as_float(
+                        __builtin_amdgcn_readlane(__float_as_int(dist[u]), g * LPR));
+                    L.offer(dc, idc, kk);
+                }
+            }
+        }
+    }
+
+    // merge the per-wave lists into wave 0
+    if (lane < kk) {
+        mg_d[wave * kWave + lane] = L.d;
+        mg_i[wave * kWave + lane] = L.id;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 1; w < kWaves; ++w)
+            for (int e = 0; e < kk; ++e) {
+                const float dc = mg_d[w * kWave + e];
+                if (!(dc < __builtin_inff())) break;
+                L.offer(dc, mg_i[w * kWave + e], kk);
+            }
+        if (lane < kk) {
+            mg_d[lane] = L.d;
+            mg_i[lane] = L.id;
+        }
+    }
+    __syncthreads();
+
+    const float* qf = a.Q + int64_t(q) * a.ldq;
+    if (FORM != kFormFP32) {
+        // 4. re-measure the kk selected candidates on the FP32 rows
+        for (int e = wave; e < kk; e += kWaves) {
+            const int id = mg_i[e];
+            float dv = __builtin_inff();
+            if (mg_d[e] < __builtin_inff()) dv = row_dist_fp32_comp(qf, a.X32 + int64_t(id) * a.ld32, a.d);
+            if (lane == 0) rr_d[e] = dv;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            L.init();
+            for (int e = 0; e < kk; ++e) {
+                const float dc = rr_d[e];
+                if (!(dc < __builtin_inff())) continue;
+                L.offer(dc, mg_i[e], kk);
+            }
+        }
+    }
+    if (wave == 0) {
+        refine_ties(L, kk, a.k, qf, a.X32, a.ld32, a.d);
+        if (lane < a.k) {
+            const bool have = L.d < __builtin_inff();
+            a.ids[int64_t(q) * a.k + lane] = have ? L.id : -1;
+            a.dists[int64_t(q) * a.k + lane] = have ? L.d : __builtin_inff();
+        }
+    }
+}
+
+template <int FORM>
+hipError_t launch_form(const ScanArgs& a, hipStream_t st, size_t lds) {
+    const int64_t nchunks_row = (FORM == kFormFP32) ? (a.ld32 / 4)
+                              : (FORM == kFormBF16) ? (a.ld16 / 8) : (a.ld8 / 16);
+    dim3 grid(a.nq), block(kThreads);
+#define GF_TRY(LPRV, CPLV)                                                                   \
+    if (nchunks_row <= int64_t(LPRV) * CPLV) {                                               \
+        hipError_t e = hipFuncSetAttribute(                                                  \
+            reinterpret_cast<const void*>(&k_scan<FORM, LPRV, CPLV>),                        \
+            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));                           \
+        if (e != hipSuccess) return e;                                                       \
+        hipLaunchKernelGGL((k_scan<FORM, LPRV, CPLV>), grid, block, lds, st, a);             \
+        return hipGetLastError();                                                            \
+    }
+    GF_TRY(8, 4)
+    GF_TRY(16, 4)
+    GF_TRY(8, 16)
+    GF_TRY(16, 16)
+    GF_TRY(64, 8)
+    GF_TRY(64, 16)
+#undef GF_TRY
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan<FORM, 64, 0>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_scan<FORM, 64, 0>), grid, block, lds, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t scan_lds_bytes(int64_t n, int form, int64_t ld8) {
+    const int64_t nbmw = (n + 31) / 32;
+    const int64_t nbmw_pad = (nbmw + kListWords - 1) / kListWords * kListWords;
+    // bitmap + per-wave id lists + merge area + re-rank staging (+ FP8 query)
+    return size_t(nbmw_pad) * 4 + size_t(kWaves) * kListCap * 4 + size_t(kWaves) * kWave * 8 +
+           size_t(kWave) * 4 + (form == kFormFP8 ? size_t(ld8) * 4 : 0);
+}
+
+bool scan_supported(int64_t n, int form, int64_t ld8) {
+    return scan_lds_bytes(n, form, ld8) <= 160 * 1024;
+}
+
+hipError_t launch_scan(const ScanArgs& a, int form, hipStream_t st) {
+    const size_t lds = scan_lds_bytes(a.n, form, a.ld8);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    switch (form) {
+        case kFormFP32: return launch_form<kFormFP32>(a, st, lds);
+        case kFormBF16: return launch_form<kFormBF16>(a, st, lds);
+        case kFormFP8: return launch_form<kFormFP8>(a, st, lds);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gf

@@ -1,0 +1,85 @@
+"""CPU checks of the native library's boundary (no GPU compute).
+
+The library must load, export every function declared in include/geraf.h,
+and reject invalid arguments with GF_EINVAL before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1603_09596_amd import geraf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "geraf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gf_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(geraf.LIB_PATH):
+        from paper_1603_09596_amd import build
+        build.build()
+    return geraf.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("gf_build_forest", "gf_query", "gf_free_forest", "gf_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} declared in geraf.h but not exported"
+    assert set(geraf.EXPORTED) == set(declared_functions())
+
+
+def test_version_string(lib):
+    assert geraf.version().startswith("geraf-gfx950")
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_build_rejects_bad_arguments_before_hip(lib):
+    out = ctypes.c_void_p()
+    X = np.zeros((10, 4), np.float32)
+    p = X.ctypes.data_as(ctypes.c_void_p)
+    B = lib.gf_build_forest
+    assert B(None, 10, 4, 2, 2, 2, 0, 0, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(p, 0, 4, 2, 2, 2, 0, 0, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(p, 10, 0, 2, 2, 2, 0, 0, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(p, 10, 4, 0, 2, 2, 0, 0, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(p, 10, 4, 256, 2, 2, 0, 0, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(p, 10, 4, 2, 5, 2, 0, 0, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(p, 10, 4, 2, 0, 2, 0, 0, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(p, 10, 4, 2, 2, 0, 0, 0, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(p, 10, 4, 2, 2, 2, 0, 1 << 7, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(p, 10, 4, 2, 2, 2, 0, 0, None, None) == geraf.GF_EINVAL
+    assert b"out" in lib.gf_last_error()
+    Xw = np.zeros((100, 80), np.float32)
+    assert B(Xw.ctypes.data_as(ctypes.c_void_p), 100, 80, 2, 65, 2, 0, 0, None,
+             ctypes.byref(out)) == geraf.GF_EUNSUPPORTED
+    # depth above 23: n / leaf > 2^23
+    assert B(p, 1 << 25, 4, 2, 2, 1, 0, 0, None, ctypes.byref(out)) == geraf.GF_EUNSUPPORTED
+
+
+def test_query_rejects_bad_arguments_before_hip(lib):
+    Q = np.zeros((3, 4), np.float32)
+    ids = np.zeros((3, 2), np.int32)
+    dd = np.zeros((3, 2), np.float32)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    qf = lib.gf_query
+    assert qf(None, P(Q), 3, 2, 10, None, 0.0, 0, 0, P(ids), P(dd), None) == geraf.GF_EINVAL
+    assert lib.gf_query_trace(None, P(Q), 3, 10, None, 0.0, None, None, None, None) == geraf.GF_EINVAL
+    assert lib.gf_forest_info(None, None, None, None, None, None, None) == geraf.GF_EINVAL
+    assert lib.gf_export_tree(None, None, None, None, None, None) == geraf.GF_EINVAL
+    assert lib.gf_free_forest(None) == geraf.GF_OK
