@@ -1,0 +1,238 @@
+"""Benchmark of the kd-GeRaF query path on one MI355X.
+
+Workload desc-1m-960: 1,000,000 descriptor-like points in 960 dimensions,
+10,000 planted queries, a forest of 16 trees (t = 5, leaf <= 32), k = 10; the
+budget c is the smallest tested that reaches recall@10 >= 0.90 (see
+CHECKS_AT_090).  A step is one gf_query call over all queries: leaf
+selection, candidate expansion, gathers and distances, best-k, re-rank and
+tie re-check, with data and queries already in HBM.  The headline value is
+the BF16 form; the FP32 form is timed the same way beside it.
+
+Prints one JSON line.  Also reports:
+  roofline      the scan kernel (the dominant one): algorithmic bytes per
+                launch / its mean duration from HIP events recorded on the
+                query stream during the timed steps, against 8 TB/s;
+  cpu_baseline  the FP64 oracle, searching a bounded sample of the same
+                queries on the host's cores (its own forest build excluded).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "desc-1m-960"
+CHECKS_AT_090 = 114688         # smallest c on a 8192 grid with recall@10 >= 0.90 (oracle 200-query and GPU 500-query samples)
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_scan_desc-1m-960.txt")
+SCAN_SRC = os.path.join(ROOT, "paper_1603_09596_amd", "csrc", "scan.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def host_threads() -> int:
+    n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def recall_at(ids: np.ndarray, gt: np.ndarray) -> float:
+    k = gt.shape[1]
+    return float(np.mean([len(set(ids[i].tolist()) & set(gt[i].tolist())) / k
+                          for i in range(len(gt))]))
+
+
+def scan_bytes_per_launch(F, nq, ncand_total, form, k, kk, checks):
+    """Algorithmic HBM bytes of one scan launch over nq queries: candidate
+    rows (+ their norms), opened leaves' point ids, leaf-bitmap words, the
+    FP32 rows re-measured by the re-rank, the query rows, the outputs."""
+    ld32 = (F.d + 3) // 4 * 4
+    ld16 = (F.d + 7) // 8 * 8
+    if form == "bf16":
+        row = ld16 * 2 + 4
+        rerank = nq * kk * ld32 * 4
+        qrow = ld16 * 2 + ld32 * 4
+    else:
+        row = ld32 * 4
+        rerank = 0
+        qrow = ld32 * 4
+    leaf_pts = F.n / (1 << F.H)
+    perm = nq * checks * leaf_pts * 4
+    bits = nq * F.m * F.leaf_words * 4
+    return ncand_total * row + rerank + perm + bits + nq * qrow + nq * k * 8
+
+
+def pmc_traffic():
+    """HBM bytes per scan launch from the committed rocprofv3 --pmc summary,
+    or None when absent or taken on a different scan kernel source."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    vals = {}
+    for line in open(PMC_FILE):
+        if ":" in line:
+            key, v = line.split(":", 1)
+            vals[key.strip()] = v.strip()
+    cur = hashlib.sha256(open(SCAN_SRC, "rb").read()).hexdigest()
+    if vals.get("scan_source_sha256") != cur:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, idx_all, checks, seconds, threads):
+    import oracle
+    t0 = time.perf_counter()
+    F = oracle.build_forest(w.X, w.m, w.t, w.p, w.seed, nthreads=threads)
+    log(f"[bench] oracle build {time.perf_counter() - t0:.1f}s")
+    # calibrate on one query per thread, then size the sample to ~`seconds`
+    probe = idx_all[:threads]
+    t0 = time.perf_counter()
+    oracle.search(F, w.X, w.Q[probe], w.k, checks, nthreads=threads, trace=False)
+    dt = time.perf_counter() - t0
+    per_q = dt / len(probe)
+    nsample = int(max(threads, min(len(idx_all), seconds / max(per_q, 1e-9))))
+    nsample = (nsample + threads - 1) // threads * threads
+    sample = idx_all[:nsample]
+    t0 = time.perf_counter()
+    oracle.search(F, w.X, w.Q[sample], w.k, checks, nthreads=threads, trace=False)
+    dt = time.perf_counter() - t0
+    return dict(value=round(len(sample) / dt, 3), unit="queries/s", cores=threads, kind="oracle",
+                sample=f"first {len(sample)} of the {len(w.Q)} queries (evenly spaced), "
+                       f"c={checks}, k={w.k}; FP64 sequential queue per query, one query per "
+                       f"thread; forest build excluded")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--checks", type=int, default=CHECKS_AT_090)
+    ap.add_argument("--nq", type=int, default=10_000)
+    ap.add_argument("--recall-sample", type=int, default=500)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the query path is "
+              "measured on one MI355X and multi-GPU runs are not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from oracle import bruteforce as bf
+    from paper_1603_09596_amd import geraf, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    geraf.load()
+    t0 = time.perf_counter()
+    w = workloads.make(WORKLOAD, nq=args.nq)
+    log(f"[bench] workload {WORKLOAD}: X {w.X.shape} Q {w.Q.shape} in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    F = geraf.build_forest(w.X, w.m, w.t, w.p, w.seed, forms=("bf16",))
+    log(f"[bench] forest build + upload {time.perf_counter() - t0:.1f}s (H={F.H})")
+    Q = torch.from_numpy(w.Q).to(dev)
+    nq, k, c = len(w.Q), w.k, args.checks
+    kk = min(64, 4 * k)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    nc = torch.empty(nq, dtype=torch.int64, device=dev)
+    geraf.query_trace(F, Q, c, ncand=nc)
+    torch.cuda.synchronize()
+    ncand_total = int(nc.sum().item())
+    log(f"[bench] c={c}: mean candidates/query {ncand_total / nq:.0f}")
+
+    def timed(form, steps, warmup):
+        for _ in range(warmup):
+            geraf.query(F, Q, k, c, ids, dists, form=form)
+        torch.cuda.synchronize()
+        scan_ms, sel_ms = [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            geraf.query(F, Q, k, c, ids, dists, form=form)
+            tm = geraf.last_query_timing()
+            scan_ms.append(tm["scan_ms"] / max(1, tm["scan_launches"]))
+            sel_ms.append(tm["select_ms"])
+            log(f"[bench] {form} step: scan {tm['scan_ms']:.1f} ms select {tm['select_ms']:.1f} ms "
+                f"prep {tm['prep_ms']:.1f} ms")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, float(np.mean(scan_ms)), float(np.mean(sel_ms)), ids.cpu().numpy()
+
+    wall, scan_ms, sel_ms, ids_bf16 = timed("bf16", args.steps, args.warmup)
+    value = args.steps * nq / wall
+    fp32 = None
+    if not args.no_fp32:
+        wall32, scan32, sel32, ids_fp32 = timed("fp32", max(1, args.steps), 1)
+        fp32 = dict(value=round(args.steps * nq / wall32, 2), scan_ms=round(scan32, 2),
+                    ms_per_step=round(1000 * wall32 / max(1, args.steps), 2))
+
+    # recall@10 on a query sample against exact FP64 neighbours
+    idx = np.linspace(0, nq - 1, min(args.recall_sample, nq)).astype(np.int64)
+    t0 = time.perf_counter()
+    gt, _ = bf.knn_ground_truth(w.X, w.Q[idx], k)
+    log(f"[bench] ground truth for {len(idx)} queries {time.perf_counter() - t0:.1f}s")
+    rec_bf16 = recall_at(ids_bf16[idx], gt)
+    one_bf16 = float(np.mean([gt[i, 0] in set(ids_bf16[j].tolist()) for i, j in enumerate(idx)]))
+    if fp32 is not None:
+        fp32["recall@10"] = round(recall_at(ids_fp32[idx], gt), 4)
+
+    algo = scan_bytes_per_launch(F, nq, ncand_total, "bf16", k, kk, c)
+    achieved = algo / (scan_ms / 1000.0) / 1e9
+    traffic = pmc_traffic()
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel="k_scan (bf16)", bytes_per_launch=int(algo),
+                    ms_per_launch=round(scan_ms, 3))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, idx, c, args.cpu_seconds, host_threads())
+
+    out = {
+        "metric": "queries/s at recall@10>=0.90, 1Mx960, 16 trees; BF16 vs FP32 form",
+        "value": round(value, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000 * wall / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": int(F.n), "d": int(F.d), "m": int(F.m),
+                   "t": int(F.t), "leaf": int(F.leaf), "checks": c, "k": k, "nq": nq,
+                   "form": "bf16", "rerank": kk},
+        "recall@10": round(rec_bf16, 4),
+        "1-recall@10": round(one_bf16, 4),
+        "recall_sample": len(idx),
+        "mean_candidates": round(ncand_total / nq, 1),
+        "select_ms_per_step": round(sel_ms, 2),
+        "fp32_form": fp32,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    F.free()
+
+
+if __name__ == "__main__":
+    main()

@@ -142,6 +142,16 @@ gf_status gf_query_trace(const gf_forest *F, const float *Q, int64_t nq, int32_t
 gf_status gf_fp8_tables(float *hw_decode, float *def_decode, const float *enc_in,
                         int32_t n_enc, uint8_t *enc_out);
 
+/* Device time of the phases of the last successful gf_query or
+ * gf_query_trace on the calling thread, in milliseconds, from HIP events
+ * recorded on the query's stream: query preparation (copies, conversions),
+ * leaf selection (Alg. 2's queue, all passes), and the scan (candidate
+ * expansion, distances, best-k, re-rank, tie re-check; one kernel launch per
+ * batch of up to 16384 queries, counted in scan_launches).  Any pointer may
+ * be NULL. */
+gf_status gf_last_query_timing(double *prep_ms, double *select_ms, double *scan_ms,
+                               int64_t *scan_launches);
+
 /* Human-readable description of the last error on the calling thread. */
 const char *gf_last_error(void);
 

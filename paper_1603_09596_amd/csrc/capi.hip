@@ -16,6 +16,10 @@
 namespace {
 
 thread_local std::string g_last_error;
+// Phase times of the last gf_query / gf_query_trace call on this thread (ms):
+// query prep, leaf selection, scan (expansion + distances + top-k + re-rank).
+thread_local double g_phase_ms[3] = {0.0, 0.0, 0.0};
+thread_local int64_t g_scan_launches = 0;
 
 gf_status fail(gf_status s, const std::string& msg) {
     g_last_error = msg;
@@ -159,6 +163,10 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     if (s != GF_OK) return s;
     const int64_t W = std::max<int64_t>(1, (int64_t{1} << h.H) / 32);
 
+    hipEvent_t ev[4];
+    for (auto& e : ev) GF_HIP(hipEventCreate(&e));
+    struct EvGuard { hipEvent_t* e; ~EvGuard() { for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]); } } evg{ev};
+    GF_HIP(hipEventRecord(ev[0], st));
     // a1: query prep -- padded FP32 rows, finiteness, reduced copies
     GF_HIP(hipMemsetAsync(w.Qp, 0, size_t(nb) * F->ld32 * 4, st));
     GF_HIP(hipMemcpy2DAsync(w.Qp, size_t(F->ld32) * 4, J.Q + q0 * h.d, size_t(h.d) * 4,
@@ -192,6 +200,7 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     if (bad) return fail(GF_EINVAL, "Q contains a non-finite value");
 
     // a2: leaf selection
+    GF_HIP(hipEventRecord(ev[1], st));
     gf::SelectArgs sa{};
     sa.Q = w.Qp; sa.ldq = F->ld32; sa.nq = nb; sa.m = h.m; sa.H = h.H; sa.t = h.t;
     sa.n_internal = (int64_t{1} << h.H) - 1; sa.W = int(W); sa.nodes = F->nodes; sa.D = F->D;
@@ -242,7 +251,9 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
         tmp_nc.reset(p);
         ca.ncand = p;
     }
+    GF_HIP(hipEventRecord(ev[2], st));
     GF_HIP(gf::launch_scan(ca, J.form, st));
+    GF_HIP(hipEventRecord(ev[3], st));
 
     // outputs
     if (J.ids && !J.out_dev)
@@ -275,12 +286,20 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
         }
     }
     GF_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < 3; ++i) {
+        float ms = 0.0f;
+        GF_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+        g_phase_ms[i] += ms;
+    }
+    g_scan_launches += 1;
     return GF_OK;
 }
 
 gf_status run_query(gf_forest* F, QueryJob& J, hipStream_t st) {
     GF_HIP(hipSetDevice(F->device));
     std::lock_guard<std::mutex> lock(F->ws_mutex);
+    g_phase_ms[0] = g_phase_ms[1] = g_phase_ms[2] = 0.0;
+    g_scan_launches = 0;
     for (int64_t q0 = 0; q0 < J.nq; q0 += kMaxBatch) {
         const int nb = int(std::min<int64_t>(kMaxBatch, J.nq - q0));
         gf_status s = run_batch(F, J, q0, nb, st);
@@ -306,6 +325,15 @@ extern "C" {
 const char* gf_last_error(void) { return g_last_error.c_str(); }
 
 const char* gf_version(void) { return "geraf-gfx950 0.1"; }
+
+gf_status gf_last_query_timing(double* prep_ms, double* select_ms, double* scan_ms,
+                               int64_t* scan_launches) {
+    if (prep_ms) *prep_ms = g_phase_ms[0];
+    if (select_ms) *select_ms = g_phase_ms[1];
+    if (scan_ms) *scan_ms = g_phase_ms[2];
+    if (scan_launches) *scan_launches = g_scan_launches;
+    return GF_OK;
+}
 
 gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32_t t, int32_t leaf,
                           uint64_t seed, uint32_t forms, void* stream, gf_forest** out) {

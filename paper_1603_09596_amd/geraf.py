@@ -23,7 +23,8 @@ KEEP_BF16, KEEP_FP8 = 1 << 1, 1 << 2
 FORMS = {"fp32": FORM_FP32, "bf16": FORM_BF16, "fp8": FORM_FP8}
 
 EXPORTED = ["gf_build_forest", "gf_free_forest", "gf_forest_info", "gf_export_tree", "gf_query",
-            "gf_query_trace", "gf_fp8_tables", "gf_last_error", "gf_version"]
+            "gf_query_trace", "gf_fp8_tables", "gf_last_query_timing", "gf_last_error",
+            "gf_version"]
 
 _lib = None
 
@@ -52,6 +53,7 @@ def load():
     lib.gf_query.argtypes = [P, P, i64, i32, i32, P, f64, i32, i32, P, P, P]
     lib.gf_query_trace.argtypes = [P, P, i64, i32, P, f64, P, P, P, P]
     lib.gf_fp8_tables.argtypes = [P, P, P, i32, P]
+    lib.gf_last_query_timing.argtypes = [P, P, P, P]
     lib.gf_last_error.restype = ctypes.c_char_p
     lib.gf_version.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -168,6 +170,16 @@ def query_trace(F: Forest, Q, checks: int, leaf_bits=None, cand_bits=None, ncand
     st = stream if stream is not None else _stream_of(Q, leaf_bits, cand_bits, ncand)
     _check(load().gf_query_trace(F.handle, _ptr(Q), nq, checks, _ptr(checks_per_query),
                                  float(eps), _ptr(leaf_bits), _ptr(cand_bits), _ptr(ncand), st))
+
+
+def last_query_timing() -> dict:
+    """Phase times (ms, HIP events on the query stream) of the last query call
+    on this thread: prep, select, scan, and the number of scan launches."""
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    nl = ctypes.c_int64()
+    _check(load().gf_last_query_timing(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                       ctypes.byref(nl)))
+    return dict(prep_ms=a.value, select_ms=b.value, scan_ms=c.value, scan_launches=nl.value)
 
 
 def fp8_tables(enc_in: Optional[np.ndarray] = None):
