@@ -9,9 +9,12 @@ tie re-check, with data and queries already in HBM.  The headline value is
 the BF16 form; the FP32 form is timed the same way beside it.
 
 Prints one JSON line.  Also reports:
-  roofline      the scan kernel (the dominant one): algorithmic bytes per
-                launch / its mean duration from HIP events recorded on the
-                query stream during the timed steps, against 8 TB/s;
+  roofline      the dominant kernel of the path taken: on the tile path the
+                MFMA score kernel (2*nq*n*d flops per launch, against 2.5
+                PFLOP/s dense BF16), on the row path the scan kernel
+                (algorithmic bytes per launch, against 8 TB/s); its mean
+                duration comes from HIP events the library records on the
+                query stream during the timed steps;
   cpu_baseline  the FP64 oracle, searching a bounded sample of the same
                 queries on the host's cores (its own forest build excluded).
 """
@@ -32,8 +35,8 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "desc-1m-960"
 CHECKS_AT_090 = 114688         # smallest c on a 8192 grid with recall@10 >= 0.90 (oracle 200-query and GPU 500-query samples)
 HBM_PEAK_GBS = 8000.0
-PMC_FILE = os.path.join(ROOT, "profiles", "pmc_scan_desc-1m-960.txt")
-SCAN_SRC = os.path.join(ROOT, "paper_1603_09596_amd", "csrc", "scan.hip")
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_desc-1m-960.txt")
 
 
 def log(*a):
@@ -74,9 +77,10 @@ def scan_bytes_per_launch(F, nq, ncand_total, form, k, kk, checks):
     return ncand_total * row + rerank + perm + bits + nq * qrow + nq * k * 8
 
 
-def pmc_traffic():
-    """HBM bytes per scan launch from the committed rocprofv3 --pmc summary,
-    or None when absent or taken on a different scan kernel source."""
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary, or None when absent, for another kernel, or taken on a
+    different source of that kernel."""
     if not os.path.exists(PMC_FILE):
         return None
     vals = {}
@@ -84,8 +88,11 @@ def pmc_traffic():
         if ":" in line:
             key, v = line.split(":", 1)
             vals[key.strip()] = v.strip()
-    cur = hashlib.sha256(open(SCAN_SRC, "rb").read()).hexdigest()
-    if vals.get("scan_source_sha256") != cur:
+    src = vals.get("source_file")
+    if vals.get("kernel") != kernel or not src:
+        return None
+    cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+    if vals.get("source_sha256") != cur:
         return None
     try:
         return float(vals["hbm_bytes_per_dispatch"])
@@ -162,25 +169,29 @@ def main():
         for _ in range(warmup):
             geraf.query(F, Q, k, c, ids, dists, form=form)
         torch.cuda.synchronize()
-        scan_ms, sel_ms = [], []
+        phases = []
         t0 = time.perf_counter()
         for _ in range(steps):
             geraf.query(F, Q, k, c, ids, dists, form=form)
             tm = geraf.last_query_timing()
-            scan_ms.append(tm["scan_ms"] / max(1, tm["scan_launches"]))
-            sel_ms.append(tm["select_ms"])
-            log(f"[bench] {form} step: scan {tm['scan_ms']:.1f} ms select {tm['select_ms']:.1f} ms "
-                f"prep {tm['prep_ms']:.1f} ms")
+            phases.append(tm)
+            log(f"[bench] {form} step ({tm['path']} path): prep {tm['prep_ms']:.1f} ms, select "
+                f"{tm['select_ms']:.1f} ms, scan/expand {tm['scan_or_expand_ms']:.1f} ms, tile "
+                f"{tm['tile_ms']:.1f} ms, merge {tm['merge_ms']:.1f} ms")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        return wall, float(np.mean(scan_ms)), float(np.mean(sel_ms)), ids.cpu().numpy()
+        mean = {key: float(np.mean([p[key] for p in phases]))
+                for key in ("prep_ms", "select_ms", "scan_or_expand_ms", "tile_ms", "merge_ms")}
+        mean["path"] = phases[-1]["path"]
+        return wall, mean, ids.cpu().numpy()
 
-    wall, scan_ms, sel_ms, ids_bf16 = timed("bf16", args.steps, args.warmup)
+    wall, ph, ids_bf16 = timed("bf16", args.steps, args.warmup)
     value = args.steps * nq / wall
     fp32 = None
     if not args.no_fp32:
-        wall32, scan32, sel32, ids_fp32 = timed("fp32", max(1, args.steps), 1)
-        fp32 = dict(value=round(args.steps * nq / wall32, 2), scan_ms=round(scan32, 2),
+        wall32, ph32, ids_fp32 = timed("fp32", max(1, args.steps), 1)
+        fp32 = dict(value=round(args.steps * nq / wall32, 2), path=ph32["path"],
+                    scan_ms=round(ph32["scan_or_expand_ms"], 2),
                     ms_per_step=round(1000 * wall32 / max(1, args.steps), 2))
 
     # recall@10 on a query sample against exact FP64 neighbours
@@ -193,13 +204,21 @@ def main():
     if fp32 is not None:
         fp32["recall@10"] = round(recall_at(ids_fp32[idx], gt), 4)
 
-    algo = scan_bytes_per_launch(F, nq, ncand_total, "bf16", k, kk, c)
-    achieved = algo / (scan_ms / 1000.0) / 1e9
-    traffic = pmc_traffic()
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel="k_scan (bf16)", bytes_per_launch=int(algo),
-                    ms_per_launch=round(scan_ms, 3))
+    if ph["path"] == "tile":
+        # dominant kernel: the MFMA score kernel, 2*nq*n*d flops per launch
+        flops = 2.0 * nq * F.n * F.d
+        achieved = flops / (ph["tile_ms"] / 1000.0) / 1e12
+        roofline = dict(bound="mfma", achieved=round(achieved, 1), peak=MFMA_BF16_PEAK_TFLOPS,
+                        unit="TFLOP/s", frac=round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
+                        traffic=pmc_traffic("k_tile_bf16"), kernel="k_tile_bf16",
+                        flops_per_launch=int(flops), ms_per_launch=round(ph["tile_ms"], 3))
+    else:
+        algo = scan_bytes_per_launch(F, nq, ncand_total, "bf16", k, kk, c)
+        achieved = algo / (ph["scan_or_expand_ms"] / 1000.0) / 1e9
+        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=pmc_traffic("k_scan"),
+                        kernel="k_scan (bf16)", bytes_per_launch=int(algo),
+                        ms_per_launch=round(ph["scan_or_expand_ms"], 3))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -225,7 +244,8 @@ def main():
         "1-recall@10": round(one_bf16, 4),
         "recall_sample": len(idx),
         "mean_candidates": round(ncand_total / nq, 1),
-        "select_ms_per_step": round(sel_ms, 2),
+        "path": ph["path"],
+        "phases_ms": {key: round(v, 2) for key, v in ph.items() if key != "path"},
         "fp32_form": fp32,
         "roofline": roofline,
         "cpu_baseline": cpu,

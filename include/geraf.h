@@ -103,6 +103,12 @@ gf_status gf_export_tree(const gf_forest *F, int32_t *D, int32_t *split_dim,
  * B = min(ceil(checks/(1+eps)), m * 2^H) of the shared queue's pop order;
  * the candidates are the distinct points of those leaves; the result is the
  * k best candidates.
+ * Two execution paths give the same candidate sets: the row path gathers
+ * each query's candidate rows; the tile path (BF16 form, d <= 1024, batches
+ * of >= 128 queries whose candidates exceed ~1/256 of the points) computes
+ * BF16 scores of 128-query blocks against all points on MFMA and keeps only
+ * those of each query's candidates.  The environment variable GF_SCAN_PATH
+ * (= rows | tile) overrides the choice where the tile path is available.
  *   Q                 [nq][d] float32, host-or-device, finite.
  *   k                 neighbours per query (1..64).
  *   checks            the paper's c: leaves to check per query (>= 1).
@@ -144,13 +150,19 @@ gf_status gf_fp8_tables(float *hw_decode, float *def_decode, const float *enc_in
 
 /* Device time of the phases of the last successful gf_query or
  * gf_query_trace on the calling thread, in milliseconds, from HIP events
- * recorded on the query's stream: query preparation (copies, conversions),
- * leaf selection (Alg. 2's queue, all passes), and the scan (candidate
- * expansion, distances, best-k, re-rank, tie re-check; one kernel launch per
- * batch of up to 16384 queries, counted in scan_launches).  Any pointer may
- * be NULL. */
-gf_status gf_last_query_timing(double *prep_ms, double *select_ms, double *scan_ms,
-                               int64_t *scan_launches);
+ * recorded on the query's stream, summed over its batches (a call is split
+ * into batches of at most 16384 queries):
+ *   phase_ms[0]  query preparation (copies, conversions, finiteness check)
+ *   phase_ms[1]  leaf selection (Alg. 2's queue: every radix pass)
+ *   phase_ms[2]  row path: the whole scan kernel (candidate expansion,
+ *                gathers, distances, best-k, re-rank, tie re-check);
+ *                tile path: the candidate expansion kernel
+ *   phase_ms[3]  tile path: the MFMA score kernel (0 on the row path)
+ *   phase_ms[4]  tile path: merge, re-rank, tie re-check (0 on the row path)
+ * Up to nphase entries are written.  *path = 0 (row path) or 1 (tile path)
+ * for the last batch; *batches = number of batches.  Pointers may be NULL. */
+gf_status gf_last_query_timing(double *phase_ms, int32_t nphase, int32_t *path,
+                               int64_t *batches);
 
 /* Human-readable description of the last error on the calling thread. */
 const char *gf_last_error(void);

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -17,9 +18,13 @@ namespace {
 
 thread_local std::string g_last_error;
 // Phase times of the last gf_query / gf_query_trace call on this thread (ms):
-// query prep, leaf selection, scan (expansion + distances + top-k + re-rank).
-thread_local double g_phase_ms[3] = {0.0, 0.0, 0.0};
-thread_local int64_t g_scan_launches = 0;
+// query prep, leaf selection, then either the row scan (expansion +
+// distances + best-k + re-rank) or the tile path's expansion, MFMA tile
+// kernel and merge/re-rank; summed over the call's batches.
+constexpr int kPhases = 5;
+thread_local double g_phase_ms[kPhases] = {0.0, 0.0, 0.0, 0.0, 0.0};
+thread_local int32_t g_path = 0;
+thread_local int64_t g_batches = 0;
 
 gf_status fail(gf_status s, const std::string& msg) {
     g_last_error = msg;
@@ -86,11 +91,32 @@ struct Carve {
 
 struct Workspace {
     float* Qp; uint16_t* Q16; uint8_t* Q8; float* qscale; float* qnorm; int32_t* cpq;
-    gf::SelState* state; uint32_t* hist; uint32_t* ncollect; uint64_t* ckey; uint32_t* ccode;
+    gf::SelState* state; uint32_t* hist; uint32_t* coff; uint64_t* ckey; uint32_t* ccode;
     uint32_t* leafbits; uint32_t* flags; int32_t* ids; float* dists;
+    uint32_t* vis; float* part_s; int* part_i;   // tile path only
 };
 
-gf_status get_workspace(gf_forest* F, int nb, int k, int form, Workspace& w) {
+// Split of the points for the tile path: enough (query block, split)
+// workgroups to fill the chip several times over.
+struct TilePlan {
+    int nsplit = 0;
+    int64_t split_pts = 0, vw = 0;
+};
+
+TilePlan tile_plan(const gf_forest* F, int nb) {
+    TilePlan p;
+    const int64_t qblocks = (nb + 127) / 128;
+    int64_t ns = (2048 + qblocks - 1) / qblocks;
+    const int64_t tiles = (F->host.n + 63) / 64;
+    if (ns > tiles) ns = tiles;
+    if (ns < 1) ns = 1;
+    p.split_pts = ((tiles + ns - 1) / ns) * 64;
+    p.nsplit = int((F->host.n + p.split_pts - 1) / p.split_pts);
+    p.vw = round_up((F->host.n + 31) / 32, 2);
+    return p;
+}
+
+gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Workspace& w) {
     const int64_t W = std::max<int64_t>(1, (int64_t{1} << F->host.H) / 32);
     Carve c;
     size_t oQp = c.take<float>(size_t(nb) * F->ld32);
@@ -100,14 +126,22 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, Workspace& w) {
     size_t oqn = c.take<float>(nb);
     size_t ocpq = c.take<int32_t>(nb);
     size_t ost = c.take<gf::SelState>(nb);
-    size_t ohist = c.take<uint32_t>(size_t(nb) * 128);
-    size_t onc = c.take<uint32_t>(nb);
+    const int nslice = F->host.m * gf::select_slices_per_tree(F->host.H);
+    size_t ohist = c.take<uint32_t>(size_t(nb) * nslice * 128);
+    size_t onc = c.take<uint32_t>(size_t(nb) * nslice);
     size_t ock = c.take<uint64_t>(size_t(nb) * gf::kCollectCap);
     size_t occ = c.take<uint32_t>(size_t(nb) * gf::kCollectCap);
     size_t olb = c.take<uint32_t>(size_t(nb) * F->host.m * W);
     size_t ofl = c.take<uint32_t>(8);
     size_t oids = c.take<int32_t>(size_t(nb) * k);
     size_t odst = c.take<float>(size_t(nb) * k);
+    size_t ovis = 0, ops = 0, opi = 0;
+    if (tile) {
+        const TilePlan tp = tile_plan(F, nb);
+        ovis = c.take<uint32_t>(size_t(nb) * tp.vw);
+        ops = c.take<float>(size_t(nb) * tp.nsplit * gf::kTileList);
+        opi = c.take<int>(size_t(nb) * tp.nsplit * gf::kTileList);
+    }
     size_t need = c.off + 256;
     if (need > F->ws_bytes) {
         if (F->ws) (void)hipFree(F->ws);
@@ -129,13 +163,16 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, Workspace& w) {
     w.cpq = reinterpret_cast<int32_t*>(b + ocpq);
     w.state = reinterpret_cast<gf::SelState*>(b + ost);
     w.hist = reinterpret_cast<uint32_t*>(b + ohist);
-    w.ncollect = reinterpret_cast<uint32_t*>(b + onc);
+    w.coff = reinterpret_cast<uint32_t*>(b + onc);
     w.ckey = reinterpret_cast<uint64_t*>(b + ock);
     w.ccode = reinterpret_cast<uint32_t*>(b + occ);
     w.leafbits = reinterpret_cast<uint32_t*>(b + olb);
     w.flags = reinterpret_cast<uint32_t*>(b + ofl);
     w.ids = reinterpret_cast<int32_t*>(b + oids);
     w.dists = reinterpret_cast<float*>(b + odst);
+    w.vis = tile ? reinterpret_cast<uint32_t*>(b + ovis) : nullptr;
+    w.part_s = tile ? reinterpret_cast<float*>(b + ops) : nullptr;
+    w.part_i = tile ? reinterpret_cast<int*>(b + opi) : nullptr;
     return GF_OK;
 }
 
@@ -155,17 +192,38 @@ struct QueryJob {
     uint32_t* leaf_bits; uint32_t* cand_bits; int64_t* ncand; bool trace_dev;
 };
 
+// Whether a batch takes the tile path (BF16 scores of whole query blocks on
+// MFMA, masked by each query's candidate bitmap) instead of per-query row
+// gathers.  The tile path computes nb * n scores at MFMA rate; the gather
+// path reads every candidate's row from HBM.  It pays off once the batch
+// fills 128-query blocks and each query's candidates are more than ~1/256
+// of the points.  GF_SCAN_PATH=rows|tile forces a path.
+bool use_tile_path(const gf_forest* F, const QueryJob& J, int nb) {
+    if (J.form != gf::kFormBF16 || J.leaf_bits || J.cand_bits || J.ncand) return false;
+    if (F->ld16 > 1024) return false;
+    if (!gf::scan_supported(F->host.n, gf::kFormFP32, F->ld8)) return false;
+    if (gf::expand_lds_bytes(round_up((F->host.n + 31) / 32, 2)) > 160 * 1024) return false;
+    const char* env = std::getenv("GF_SCAN_PATH");
+    if (env && std::strcmp(env, "rows") == 0) return false;
+    if (env && std::strcmp(env, "tile") == 0) return true;
+    if (nb < 128) return false;
+    const double leaf_pts = double(F->host.n) / double(int64_t{1} << F->host.H);
+    const double cand_est = double(J.cpq ? J.checks : J.checks) * leaf_pts * 0.5;
+    return cand_est * 256.0 >= double(F->host.n);
+}
+
 // Runs the whole query path for queries [q0, q0 + nb).
 gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStream_t st) {
     const gf::HostForest& h = F->host;
     Workspace w;
-    gf_status s = get_workspace(F, nb, J.k, J.form, w);
+    const bool tile = use_tile_path(F, J, nb);
+    gf_status s = get_workspace(F, nb, J.k, J.form, tile, w);
     if (s != GF_OK) return s;
     const int64_t W = std::max<int64_t>(1, (int64_t{1} << h.H) / 32);
 
-    hipEvent_t ev[4];
+    hipEvent_t ev[6];
     for (auto& e : ev) GF_HIP(hipEventCreate(&e));
-    struct EvGuard { hipEvent_t* e; ~EvGuard() { for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]); } } evg{ev};
+    struct EvGuard { hipEvent_t* e; ~EvGuard() { for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]); } } evg{ev};
     GF_HIP(hipEventRecord(ev[0], st));
     // a1: query prep -- padded FP32 rows, finiteness, reduced copies
     GF_HIP(hipMemsetAsync(w.Qp, 0, size_t(nb) * F->ld32 * 4, st));
@@ -204,7 +262,8 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     gf::SelectArgs sa{};
     sa.Q = w.Qp; sa.ldq = F->ld32; sa.nq = nb; sa.m = h.m; sa.H = h.H; sa.t = h.t;
     sa.n_internal = (int64_t{1} << h.H) - 1; sa.W = int(W); sa.nodes = F->nodes; sa.D = F->D;
-    sa.state = w.state; sa.hist = w.hist; sa.ncollect = w.ncollect; sa.ckey = w.ckey;
+    sa.nslice = h.m * gf::select_slices_per_tree(h.H);
+    sa.state = w.state; sa.hist = w.hist; sa.coff = w.coff; sa.ckey = w.ckey;
     sa.ccode = w.ccode; sa.leafbits = w.leafbits;
     hipLaunchKernelGGL(gf::k_select_init, dim3((nb + 255) / 256), dim3(256), 0, st, sa,
                        J.checks, cpq, J.eps);
@@ -212,8 +271,7 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     for (int pass = 0; pass < gf::kMaxPasses; ++pass) {
         GF_HIP(hipMemsetAsync(w.flags + 1, 0, 4, st));
         GF_HIP(gf::launch_select_walk(sa, pass, false, st));
-        hipLaunchKernelGGL(gf::k_select_pick, dim3((nb + 255) / 256), dim3(256), 0, st, sa, pass,
-                           w.flags + 1);
+        hipLaunchKernelGGL(gf::k_select_pick, dim3(nb), dim3(128), 0, st, sa, pass, w.flags + 1);
         GF_HIP(hipGetLastError());
         uint32_t more = 0;
         GF_HIP(hipMemcpyAsync(&more, w.flags + 1, 4, hipMemcpyDeviceToHost, st));
@@ -252,8 +310,26 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
         ca.ncand = p;
     }
     GF_HIP(hipEventRecord(ev[2], st));
-    GF_HIP(gf::launch_scan(ca, J.form, st));
-    GF_HIP(hipEventRecord(ev[3], st));
+    if (tile) {
+        const TilePlan tp = tile_plan(F, nb);
+        gf::ExpandArgs ea{};
+        ea.nq = nb; ea.m = h.m; ea.W = int(W); ea.n = h.n; ea.vw = tp.vw;
+        ea.leafbits = w.leafbits; ea.perm = F->perm; ea.leaf_off = F->leaf_off; ea.vis = w.vis;
+        gf::TileArgs ta{};
+        ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.vw = tp.vw; ta.Q16 = w.Q16; ta.X16 = F->X16;
+        ta.norm16 = F->norm16; ta.vis = w.vis; ta.nsplit = tp.nsplit; ta.split_pts = tp.split_pts;
+        ta.part_s = w.part_s; ta.part_i = w.part_i;
+        gf::MergeArgs ma{};
+        ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = tp.nsplit;
+        ma.part_s = w.part_s; ma.part_i = w.part_i; ma.Q = w.Qp; ma.ldq = F->ld32;
+        ma.X32 = F->X32; ma.ld32 = F->ld32; ma.ids = ca.ids; ma.dists = ca.dists;
+        GF_HIP(gf::launch_tile_path(ea, ta, ma, st, ev + 3));
+    } else {
+        GF_HIP(gf::launch_scan(ca, J.form, st));
+        GF_HIP(hipEventRecord(ev[3], st));
+        GF_HIP(hipEventRecord(ev[4], st));
+    }
+    GF_HIP(hipEventRecord(ev[5], st));
 
     // outputs
     if (J.ids && !J.out_dev)
@@ -286,20 +362,21 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
         }
     }
     GF_HIP(hipStreamSynchronize(st));
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < kPhases; ++i) {
         float ms = 0.0f;
         GF_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
         g_phase_ms[i] += ms;
     }
-    g_scan_launches += 1;
+    g_path = tile ? 1 : 0;
+    g_batches += 1;
     return GF_OK;
 }
 
 gf_status run_query(gf_forest* F, QueryJob& J, hipStream_t st) {
     GF_HIP(hipSetDevice(F->device));
     std::lock_guard<std::mutex> lock(F->ws_mutex);
-    g_phase_ms[0] = g_phase_ms[1] = g_phase_ms[2] = 0.0;
-    g_scan_launches = 0;
+    for (double& x : g_phase_ms) x = 0.0;
+    g_batches = 0;
     for (int64_t q0 = 0; q0 < J.nq; q0 += kMaxBatch) {
         const int nb = int(std::min<int64_t>(kMaxBatch, J.nq - q0));
         gf_status s = run_batch(F, J, q0, nb, st);
@@ -326,12 +403,11 @@ const char* gf_last_error(void) { return g_last_error.c_str(); }
 
 const char* gf_version(void) { return "geraf-gfx950 0.1"; }
 
-gf_status gf_last_query_timing(double* prep_ms, double* select_ms, double* scan_ms,
-                               int64_t* scan_launches) {
-    if (prep_ms) *prep_ms = g_phase_ms[0];
-    if (select_ms) *select_ms = g_phase_ms[1];
-    if (scan_ms) *scan_ms = g_phase_ms[2];
-    if (scan_launches) *scan_launches = g_scan_launches;
+gf_status gf_last_query_timing(double* phase_ms, int32_t nphase, int32_t* path, int64_t* batches) {
+    if (nphase < 0 || (nphase > 0 && !phase_ms)) return fail(GF_EINVAL, "bad phase buffer");
+    for (int i = 0; i < nphase; ++i) phase_ms[i] = i < kPhases ? g_phase_ms[i] : 0.0;
+    if (path) *path = g_path;
+    if (batches) *batches = g_batches;
     return GF_OK;
 }
 
@@ -365,7 +441,7 @@ gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32
     GF_HIP(hipGetDevice(&F->device));
     const gf::HostForest& h = F->host;
     F->ld32 = int32_t(round_up(d, 4));
-    F->ld16 = int32_t(round_up(d, 8));
+    F->ld16 = int32_t(round_up(d, 32));   // multiple of one MFMA k step (32 bf16)
     F->ld8 = int32_t(round_up(d, 16));
     const int64_t nint = (int64_t{1} << h.H) - 1;
     auto cleanup = [&](gf_status s) { free_forest_device(F.get()); return s; };

@@ -9,7 +9,7 @@ namespace gf {
 
 // ---------------------------------------------------------------- selection
 
-constexpr int kCollectCap = 4096;   // keys resolved by the final per-query sort
+constexpr int kCollectCap = 32768;  // keys resolved by the final per-query radix select
 constexpr int kMaxPasses = 9;       // 63 significant key bits / 7-bit digits
 
 enum : uint32_t { kSelSearching = 0, kSelReady = 1, kSelAll = 2, kSelDone = 3 };
@@ -33,9 +33,10 @@ struct SelectArgs {
     int W;                 // leaf-bitmap words per tree
     const uint2* nodes;    // [m][n_internal]
     const int32_t* D;      // [t]
+    int nslice;            // m * (leaf ranges per tree)
     SelState* state;       // [nq]
-    uint32_t* hist;        // [nq][128]
-    uint32_t* ncollect;    // [nq]
+    uint32_t* hist;        // [nq][nslice][128]
+    uint32_t* coff;        // [nq][nslice] collect offsets
     uint64_t* ckey;        // [nq][kCollectCap]
     uint32_t* ccode;       // [nq][kCollectCap]
     uint32_t* leafbits;    // [m][W][nq]  (word-major, query fastest)
@@ -43,6 +44,7 @@ struct SelectArgs {
 
 __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps);
 __global__ void k_select_pick(SelectArgs a, int pass, uint32_t* any_searching);
+int select_slices_per_tree(int H);
 __global__ void k_select_finish(SelectArgs a);
 hipError_t launch_select_walk(const SelectArgs& a, int pass, bool collect, hipStream_t st);
 
@@ -81,6 +83,50 @@ struct ScanArgs {
 hipError_t launch_scan(const ScanArgs& a, int form, hipStream_t st);
 size_t scan_lds_bytes(int64_t n, int form, int64_t ld8);
 bool scan_supported(int64_t n, int form, int64_t ld8);
+
+// ------------------------------------------------------- tile (MFMA) path
+
+constexpr int kTileList = 48;   // best scores kept per (query, point split)
+
+struct ExpandArgs {
+    int nq, m, W;
+    int64_t n, vw;
+    const uint32_t* leafbits;   // [m][W][nq]
+    const uint32_t* perm;       // [m][n]
+    const uint32_t* leaf_off;   // [2^H + 1]
+    uint32_t* vis;              // [nq][vw] visited bitmaps
+};
+
+struct TileArgs {
+    int nq;
+    int64_t n, ld16, vw;
+    const uint16_t* Q16;        // [nq][ld16]
+    const uint16_t* X16;        // [n][ld16]
+    const float* norm16;        // [n]
+    const uint32_t* vis;        // [nq][vw]
+    int nsplit;
+    int64_t split_pts;          // points per split, multiple of 64
+    float* part_s;              // [nq][nsplit][kTileList]
+    int* part_i;
+};
+
+struct MergeArgs {
+    int nq, k, kk, d, nsplit;
+    const float* part_s;
+    const int* part_i;
+    const float* Q;             // [nq][ldq] FP32 queries
+    int64_t ldq;
+    const float* X32;
+    int64_t ld32;
+    int32_t* ids;
+    float* dists;
+};
+
+size_t expand_lds_bytes(int64_t vw);
+// Records ev[0] after the expansion and ev[1] after the tile kernel (ev may
+// be null).
+hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeArgs& m,
+                            hipStream_t st, hipEvent_t* ev);
 
 // --------------------------------------------------------- data conversion
 

@@ -23,49 +23,16 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "rank.h"
 
 namespace gf {
 
 namespace {
 
-constexpr int kWave = 64;
 constexpr int kWaves = 8;
 constexpr int kThreads = kWave * kWaves;
 constexpr int kListWords = 16;                // bitmap words per wave step
 constexpr int kListCap = kListWords * 32;     // ids per wave step
-constexpr float kTieBand = 1e-5f;
-
-__device__ __forceinline__ bool entry_before(float da, int ia, float db, int ib) {
-    return da < db || (da == db && ia < ib);
-}
-
-// Sorted best-kk list spread over lanes 0..kk-1 of a wavefront.
-struct WaveList {
-    float d;
-    int id;
-    __device__ void init() { d = __builtin_inff(); id = 0x7FFFFFFF; }
-    __device__ float thr_d(int kk) const {
-        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), kk - 1));
-    }
-    __device__ int thr_id(int kk) const { return __builtin_amdgcn_readlane(id, kk - 1); }
-    // Insert a wave-uniform (dc, ic) known to beat the current kk-th entry.
-    __device__ void insert(float dc, int ic, int kk) {
-        const int lane = threadIdx.x & (kWave - 1);
-        const bool before = lane < kk && entry_before(d, id, dc, ic);
-        const int pos = __popcll(__ballot(before));
-        const float pd = __shfl_up(d, 1);
-        const int pi = __shfl_up(id, 1);
-        if (lane < kk) {
-            if (lane > pos) { d = pd; id = pi; }
-            else if (lane == pos) { d = dc; id = ic; }
-        }
-    }
-    __device__ void offer(float dc, int ic, int kk) {
-        const float td = thr_d(kk);
-        const int ti = thr_id(kk);
-        if (entry_before(dc, ic, td, ti)) insert(dc, ic, kk);
-    }
-};
 
 template <int LPR>
 __device__ __forceinline__ float group_sum(float v) {
@@ -146,87 +113,6 @@ struct Chunk<kFormFP8> {
         return acc;
     }
 };
-
-// Compensated FP32 squared distance of one row, computed by a whole wave:
-// (q - x) split exactly into s + e (two-sum), s^2 split exactly into p + r
-// (two-product with FMA), the p's summed with two-sum and every rounding
-// error collected in a second accumulator (Ogita, Rump, Oishi 2005).
-__device__ float row_dist_fp32_comp(const float* q, const float* x, int d) {
-    const int lane = threadIdx.x & (kWave - 1);
-    float sum = 0.0f, err = 0.0f;
-    for (int j = lane; j < d; j += kWave) {
-        const float a = q[j], b = -x[j];
-        const float s = a + b;
-        const float bb = s - a;
-        const float e = (a - (s - bb)) + (b - bb);
-        const float p = s * s;
-        const float r = fmaf(s, s, -p);
-        const float t = sum + p;
-        const float tp = t - sum;
-        err += ((sum - (t - tp)) + (p - tp)) + r + fmaf(2.0f * s, e, e * e);
-        sum = t;
-    }
-#pragma unroll
-    for (int o = kWave / 2; o >= 1; o >>= 1) {
-        const float os = __shfl_xor(sum, o);
-        const float oe = __shfl_xor(err, o);
-        const float t = sum + os;
-        const float tp = t - sum;
-        err = err + oe + ((sum - (t - tp)) + (os - tp));
-        sum = t;
-    }
-    return sum + err;
-}
-
-__device__ double row_dist_fp64(const float* q, const float* x, int d) {
-    const int lane = threadIdx.x & (kWave - 1);
-    double acc = 0.0;
-    for (int j = lane; j < d; j += kWave) {
-        const double diff = double(q[j]) - double(x[j]);
-        acc = fma(diff, diff, acc);
-    }
-#pragma unroll
-    for (int o = kWave / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-    return acc;
-}
-
-// Re-rank the list by (FP64 distance, id) inside the band of the k-th place.
-__device__ void refine_ties(WaveList& L, int kk, int k, const float* q, const float* X32,
-                            int64_t ld32, int d) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const float dk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(L.d), k - 1));
-    double key = double(L.d);
-    if (dk < __builtin_inff()) {
-        const float lo = dk * (1.0f - kTieBand), hi = dk * (1.0f + kTieBand);
-        const bool inband = lane < kk && L.d >= lo && L.d <= hi && L.d < __builtin_inff();
-        uint64_t band = __ballot(inband);
-        while (band) {
-            const int b = __builtin_ctzll(band);
-            band &= band - 1;
-            const int id = __builtin_amdgcn_readlane(L.id, b);
-            const double d64 = row_dist_fp64(q, X32 + int64_t(id) * ld32, d);
-            if (lane == b) key = d64;
-        }
-    }
-    // bitonic sort of the 64 lanes by (key, id); lanes >= kk carry +inf
-    int id = L.id;
-    if (lane >= kk) { key = __builtin_inf(); id = 0x7FFFFFFF; }
-#pragma unroll
-    for (int size = 2; size <= kWave; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const double ok = __shfl_xor(key, stride);
-            const int oid = __shfl_xor(id, stride);
-            const bool up = (lane & size) == 0;
-            const bool lower = (lane & stride) == 0;
-            const bool other_first = ok < key || (ok == key && oid < id);
-            const bool take = (lower == up) ? other_first : !other_first;
-            if (take) { key = ok; id = oid; }
-        }
-    }
-    L.d = float(key);
-    L.id = id;
-}
 
 // ------------------------------------------------------------------ kernel
 
@@ -468,34 +354,13 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     }
     __syncthreads();
 
-    const float* qf = a.Q + int64_t(q) * a.ldq;
-    if (FORM != kFormFP32) {
-        // 4. re-measure the kk selected candidates on the FP32 rows
-        for (int e = wave; e < kk; e += kWaves) {
-            const int id = mg_i[e];
-            float dv = __builtin_inff();
-            if (mg_d[e] < __builtin_inff()) dv = row_dist_fp32_comp(qf, a.X32 + int64_t(id) * a.ld32, a.d);
-            if (lane == 0) rr_d[e] = dv;
-        }
-        __syncthreads();
-        if (wave == 0) {
-            L.init();
-            for (int e = 0; e < kk; ++e) {
-                const float dc = rr_d[e];
-                if (!(dc < __builtin_inff())) continue;
-                L.offer(dc, mg_i[e], kk);
-            }
-        }
-    }
-    if (wave == 0) {
-        refine_ties(L, kk, a.k, qf, a.X32, a.ld32, a.d);
-        if (lane < a.k) {
-            const bool have = L.d < __builtin_inff();
-            a.ids[int64_t(q) * a.k + lane] = have ? L.id : -1;
-            a.dists[int64_t(q) * a.k + lane] = have ? L.d : __builtin_inff();
-        }
-    }
+    finish_query(FORM != kFormFP32, kk, a.k, q, a.Q + int64_t(q) * a.ldq, a.X32, a.ld32, a.d,
+                 mg_d, mg_i, rr_d, L, a.ids, a.dists);
 }
+
+}  // namespace
+
+namespace {
 
 template <int FORM>
 hipError_t launch_form(const ScanArgs& a, hipStream_t st, size_t lds) {

@@ -16,10 +16,12 @@
 //     each lane keeps its own eff and entry, and the bottom five levels are
 //     expanded breadth-first in registers, 32 leaves at a time;
 //   * a radix select on the 64-bit key K (7-bit digits, per-lane histograms
-//     in LDS) that narrows each query's threshold to a bin of at most
-//     kCollectCap leaves;
+//     in LDS, written out per (query, tree slice) without atomics) that
+//     narrows each query's threshold to a bin of at most kCollectCap leaves;
 //   * a final walk that marks every leaf below the bin in the query's leaf
-//     bitmap and collects the bin, which a per-query sort resolves.
+//     bitmap and writes the bin's keys to per-slice offsets of the query's
+//     collect buffer (again without atomics); a per-query radix select over
+//     those keys (8-bit digits, LDS histogram) finds the exact B-th key.
 //
 // Key layout: bits 63..32 = eff as float bits (eff >= 0, so the bit pattern
 // orders like the value), 31..24 = tree, 23..0 = entry node (heap index).
@@ -156,11 +158,12 @@ __global__ __launch_bounds__(64) void k_select_hist(SelectArgs a, int pass) {
                       }
                   });
     if (!active) return;
-    uint32_t* gh = a.hist + int64_t(q) * kBins;
+    const int slice = int(tree) * int(gridDim.z) + int(blockIdx.z);
+    uint32_t* gh = a.hist + (int64_t(q) * a.nslice + slice) * kBins;
     for (int b = 0; b < kBins / 2; ++b) {
         const uint32_t w = hist[b * kWave + lane];
-        if (w & 0xFFFFu) atomicAdd(&gh[2 * b], w & 0xFFFFu);
-        if (w >> 16) atomicAdd(&gh[2 * b + 1], w >> 16);
+        gh[2 * b] = w & 0xFFFFu;
+        gh[2 * b + 1] = w >> 16;
     }
 }
 
@@ -185,7 +188,9 @@ __global__ __launch_bounds__(64) void k_select_collect(SelectArgs a) {
     const uint32_t cb = blockIdx.z * per;
     const uint32_t ce = min(nchunks, cb + per);
     const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
-    uint32_t* col_n = a.ncollect;
+    // this slice's share of the bin starts at coff[q][slice]
+    const int slice = int(tree) * int(gridDim.z) + int(blockIdx.z);
+    uint32_t pos = (q < a.nq && st.status == kSelReady) ? a.coff[int64_t(q) * a.nslice + slice] : 0u;
     walk_tree<CH>(nodes, a.H, cb, ce, qd, pe, pn,
                   [&](uint32_t c, const float* ef, const uint32_t* en) {
                       if (q >= a.nq) return;
@@ -196,12 +201,12 @@ __global__ __launch_bounds__(64) void k_select_collect(SelectArgs a) {
                           if (all || K < lo) {
                               bits |= 1u << x;
                           } else if (K < hi) {
-                              const uint32_t slot = atomicAdd(&col_n[q], 1u);
-                              if (slot < uint32_t(kCollectCap)) {
-                                  const int64_t o = int64_t(q) * kCollectCap + slot;
+                              if (pos < uint32_t(kCollectCap)) {
+                                  const int64_t o = int64_t(q) * kCollectCap + pos;
                                   a.ckey[o] = K;
                                   a.ccode[o] = (tree << 24) | ((c << CH) + uint32_t(x));
                               }
+                              ++pos;
                           }
                       }
                       a.leafbits[(int64_t(tree) * a.W + c) * a.nq + q] = bits;
@@ -224,76 +229,105 @@ __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, 
     s.budget = uint32_t(B);
     s.status = (B == total) ? kSelAll : (B == 0 ? kSelDone : kSelSearching);
     a.state[q] = s;
-    a.ncollect[q] = 0;
-    for (int b = 0; b < kBins; ++b) a.hist[int64_t(q) * kBins + b] = 0;
 }
 
-// After a histogram pass: fix the digit holding the B-th smallest key.
-__global__ void k_select_pick(SelectArgs a, int pass, uint32_t* any_searching) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.nq) return;
+// After a histogram pass: fix the digit holding the B-th smallest key (one
+// workgroup of 128 threads per query: thread b sums bin b over the slices),
+// and the offsets at which each slice will write its share of that bin.
+__global__ __launch_bounds__(kBins) void k_select_pick(SelectArgs a, int pass,
+                                                       uint32_t* any_searching) {
+    __shared__ uint32_t tot[kBins];
+    const int q = blockIdx.x;
     SelState s = a.state[q];
     if (s.status != kSelSearching) return;
-    uint32_t* h = a.hist + int64_t(q) * kBins;
+    const uint32_t* h = a.hist + int64_t(q) * a.nslice * kBins;
+    uint32_t sum = 0;
+    for (int sl = 0; sl < a.nslice; ++sl) sum += h[int64_t(sl) * kBins + threadIdx.x];
+    tot[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     uint32_t cum = s.below;
     int dgt = kBins - 1;
     for (int b = 0; b < kBins; ++b) {
-        if (cum + h[b] >= s.budget) { dgt = b; break; }
-        cum += h[b];
+        if (cum + tot[b] >= s.budget) { dgt = b; break; }
+        cum += tot[b];
     }
     s.below = cum;
-    s.bincount = h[dgt];
+    s.bincount = tot[dgt];
     s.prefix = (s.prefix << kDigitBits) | uint64_t(dgt);
     s.pass = uint32_t(pass + 1);
     if (s.bincount <= uint32_t(kCollectCap) || s.pass == uint32_t(kMaxPasses)) {
         s.status = kSelReady;
+        uint32_t off = 0;
+        for (int sl = 0; sl < a.nslice; ++sl) {
+            a.coff[int64_t(q) * a.nslice + sl] = off;
+            off += h[int64_t(sl) * kBins + dgt];
+        }
     } else {
         atomicOr(any_searching, 1u);
     }
-    for (int b = 0; b < kBins; ++b) h[b] = 0;
     a.state[q] = s;
 }
 
-// Resolve the bin: sort the collected keys, mark the first budget-below.
+// Resolve the bin: a radix select (8-bit digits, from the top) over the
+// collected keys finds the (B - below)-th smallest; every collected leaf with
+// a key up to it is marked.  Keys are distinct, so exactly B leaves end up
+// marked in total.
 __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
-    __shared__ uint64_t key[kCollectCap];
-    __shared__ uint32_t code[kCollectCap];
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t sh_prefix;
+    __shared__ uint32_t sh_need;
     const int q = blockIdx.x;
     const SelState s = a.state[q];
     if (s.status != kSelReady) return;
-    const uint32_t cnt = min(a.ncollect[q], uint32_t(kCollectCap));
-    const uint32_t take = s.budget - s.below;
-    uint32_t np2 = 1;
-    while (np2 < cnt) np2 <<= 1;
-    for (uint32_t i = threadIdx.x; i < np2; i += blockDim.x) {
-        if (i < cnt) {
-            key[i] = a.ckey[int64_t(q) * kCollectCap + i];
-            code[i] = a.ccode[int64_t(q) * kCollectCap + i];
-        } else {
-            key[i] = ~0ull;
-            code[i] = 0;
-        }
+    const uint32_t cnt = min(s.bincount, uint32_t(kCollectCap));
+    const uint64_t* keys = a.ckey + int64_t(q) * kCollectCap;
+    const uint32_t* codes = a.ccode + int64_t(q) * kCollectCap;
+    if (threadIdx.x == 0) {
+        sh_prefix = 0;
+        sh_need = s.budget - s.below;
     }
     __syncthreads();
-    for (uint32_t size = 2; size <= np2; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t i = threadIdx.x; i < np2; i += blockDim.x) {
-                const uint32_t j = i ^ stride;
-                if (j > i) {
-                    const bool up = (i & size) == 0;
-                    if ((key[i] > key[j]) == up) {
-                        const uint64_t tk = key[i]; key[i] = key[j]; key[j] = tk;
-                        const uint32_t tc = code[i]; code[i] = code[j]; code[j] = tc;
-                    }
+    uint64_t kstar = ~0ull;
+    if (sh_need < cnt) {
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 56 - 8 * pass;
+            hist[threadIdx.x] = 0;
+            __syncthreads();
+            const uint64_t prefix = sh_prefix;
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+                const uint64_t K = keys[i];
+                if (pass == 0 || (K >> (shift + 8)) == prefix)
+                    atomicAdd(&hist[(K >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t need = sh_need, d = 255;
+                for (uint32_t b = 0; b < 256; ++b) {
+                    if (hist[b] >= need) { d = b; break; }
+                    need -= hist[b];
                 }
+                sh_need = need;
+                sh_prefix = (prefix << 8) | d;
             }
             __syncthreads();
         }
+        kstar = sh_prefix;
     }
-    for (uint32_t i = threadIdx.x; i < take && i < cnt; i += blockDim.x) {
-        const uint32_t tree = code[i] >> 24, leaf = code[i] & 0xFFFFFFu;
-        atomicOr(&a.leafbits[(int64_t(tree) * a.W + (leaf >> 5)) * a.nq + q], 1u << (leaf & 31u));
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        if (keys[i] <= kstar) {
+            const uint32_t tree = codes[i] >> 24, leaf = codes[i] & 0xFFFFFFu;
+            atomicOr(&a.leafbits[(int64_t(tree) * a.W + (leaf >> 5)) * a.nq + q], 1u << (leaf & 31u));
+        }
     }
+}
+
+// Each tree is walked in ranges of at most 2^15 leaves (one workgroup per
+// range), so that the packed 16-bit histogram counters cannot overflow.
+int select_slices_per_tree(int H) {
+    int z = 1;
+    while ((int64_t{1} << H) / z > 32768) z <<= 1;
+    return z;
 }
 
 hipError_t launch_select_walk(const SelectArgs& a, int pass, bool collect, hipStream_t st) {
@@ -301,10 +335,8 @@ hipError_t launch_select_walk(const SelectArgs& a, int pass, bool collect, hipSt
     const int U = a.H - CH;
     const size_t lds = size_t(a.t) * kWave * 4 + size_t(U + 1) * kWave * 8 +
                        (collect ? 0 : size_t(kBins / 2) * kWave * 4);
-    // split each tree into ranges of at most 2^15 leaves (16-bit counters)
-    const uint32_t nchunks = 1u << U;
-    uint32_t zsplit = 1;
-    while ((uint64_t(nchunks) << CH) / zsplit > 32768u) zsplit <<= 1;
+    const int zsplit = select_slices_per_tree(a.H);
+    if (a.nslice != a.m * zsplit) return hipErrorInvalidValue;
     dim3 grid((a.nq + kWave - 1) / kWave, a.m, zsplit);
 #define GF_WALK(CHV)                                                                       \
     case CHV:                                                                              \

@@ -53,7 +53,7 @@ def load():
     lib.gf_query.argtypes = [P, P, i64, i32, i32, P, f64, i32, i32, P, P, P]
     lib.gf_query_trace.argtypes = [P, P, i64, i32, P, f64, P, P, P, P]
     lib.gf_fp8_tables.argtypes = [P, P, P, i32, P]
-    lib.gf_last_query_timing.argtypes = [P, P, P, P]
+    lib.gf_last_query_timing.argtypes = [P, i32, P, P]
     lib.gf_last_error.restype = ctypes.c_char_p
     lib.gf_version.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -174,12 +174,16 @@ def query_trace(F: Forest, Q, checks: int, leaf_bits=None, cand_bits=None, ncand
 
 def last_query_timing() -> dict:
     """Phase times (ms, HIP events on the query stream) of the last query call
-    on this thread: prep, select, scan, and the number of scan launches."""
-    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-    nl = ctypes.c_int64()
-    _check(load().gf_last_query_timing(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
-                                       ctypes.byref(nl)))
-    return dict(prep_ms=a.value, select_ms=b.value, scan_ms=c.value, scan_launches=nl.value)
+    on this thread, the path of its last batch and the number of batches."""
+    ph = (ctypes.c_double * 5)()
+    path = ctypes.c_int32()
+    nb = ctypes.c_int64()
+    _check(load().gf_last_query_timing(ph, 5, ctypes.byref(path), ctypes.byref(nb)))
+    names = ("prep_ms", "select_ms", "scan_or_expand_ms", "tile_ms", "merge_ms")
+    out = {n: ph[i] for i, n in enumerate(names)}
+    out["path"] = "tile" if path.value == 1 else "rows"
+    out["batches"] = nb.value
+    return out
 
 
 def fp8_tables(enc_in: Optional[np.ndarray] = None):

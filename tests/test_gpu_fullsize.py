@@ -1,0 +1,98 @@
+"""Parity at full workload sizes, in the launch configuration bench.py times.
+
+The whole query batch runs through the library exactly as the benchmark
+runs it; the oracle then computes a sample of the queries one by one, and
+the sampled outputs are compared: opened leaves and candidate sets bit for
+bit (through gf_query_trace on the same batch), neighbours by the acceptance
+rule (FP32 form) or by recall and exact distances (reduced-precision forms).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_09596_amd import geraf, workloads as W
+from parity import check_knn, ids_from_bits, leaf_set_from_bits
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+THREADS = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16"))))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    geraf.load()
+
+
+def run_case(w, c, form, sample, forms):
+    dev = torch.device("cuda:0")
+    Fg = geraf.build_forest(w.X, w.m, w.t, w.p, w.seed, forms=forms)
+    Fo = oracle.build_forest(w.X, w.m, w.t, w.p, w.seed, nthreads=THREADS)
+    T = Fg.export_tree()
+    for key in ("D", "split_dim", "split_val", "perm", "leaf_off"):
+        assert np.array_equal(T[key], Fo[key]), key
+    Q = torch.from_numpy(w.Q).to(dev)
+    nq, k = len(w.Q), w.k
+    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    dd = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    geraf.query(Fg, Q, k, c, ids, dd, form=form)
+    timing = geraf.last_query_timing()
+    ids, dd = ids.cpu().numpy(), dd.cpu().numpy()
+    idx = np.linspace(0, nq - 1, sample).astype(np.int64)
+    Qs = np.ascontiguousarray(w.Q[idx])
+    lb = np.zeros((len(idx), Fg.m, Fg.leaf_words), np.uint32)
+    nc = np.zeros(len(idx), np.int64)
+    cb = np.zeros((len(idx), (Fg.n + 31) // 32), np.uint32)
+    geraf.query_trace(Fg, Qs, c, leaf_bits=lb, cand_bits=cb, ncand=nc)
+    ref = oracle.search(Fo, w.X, Qs, k, c, nthreads=THREADS, candidates=True)
+    for j in range(len(idx)):
+        assert leaf_set_from_bits(lb[j]) == set(ref["opened"][j].tolist()), f"query {idx[j]}"
+        assert np.array_equal(ids_from_bits(cb[j], Fg.n), ref["cand"][j]), f"query {idx[j]}"
+    assert np.array_equal(nc, ref["ncand"])
+    Fg.free()
+    return ids[idx], dd[idx], ref, Qs, timing
+
+
+def check_reduced(w, ids, dd, ref, Qs, floor):
+    hits = 0
+    for j in range(len(Qs)):
+        got = ids[j][ids[j] >= 0]
+        for r, gid in enumerate(got.tolist()):
+            diff = w.X[gid].astype(np.float64) - Qs[j].astype(np.float64)
+            true_d = float(diff @ diff)
+            assert abs(dd[j][r] - true_d) <= 1e-5 * true_d
+        hits += len(set(got.tolist()) & set(ref["ids"][j].tolist()))
+    recall = hits / ref["ids"].size
+    print(f"recall vs FP64 oracle on {len(Qs)} sampled queries: {recall:.4f}")
+    assert recall >= floor
+
+
+def test_desc_1m_960_bench_configuration():
+    import bench
+    w = W.make("desc-1m-960")
+    ids, dd, ref, Qs, timing = run_case(w, bench.CHECKS_AT_090, "bf16", 12, ("bf16",))
+    assert timing["path"] == "tile"
+    check_reduced(w, ids, dd, ref, Qs, 0.97)
+
+
+def test_desc_1m_960_fp32_form():
+    w = W.make("desc-1m-960", nq=2000)
+    ids, dd, ref, Qs, _ = run_case(w, 16384, "fp32", 12, ())
+    check_knn(ids, dd, ref["ids"], ref["dists"], X=w.X, Q=Qs)
+
+
+def test_sphere_100k_1000_full():
+    w = W.make("sphere-100k-1000")
+    ids, dd, ref, Qs, _ = run_case(w, w.c, "fp32", 24, ())
+    check_knn(ids, dd, ref["ids"], ref["dists"], X=w.X, Q=Qs)
+
+
+def test_gauss_200k_10000_fp8_full():
+    w = W.make("gauss-200k-10000")
+    ids, dd, ref, Qs, _ = run_case(w, w.c, "fp8", 16, ("fp8",))
+    check_reduced(w, ids, dd, ref, Qs, 0.97)

@@ -265,3 +265,56 @@ def test_fp8_encoder_is_round_to_nearest_even_saturating():
         if xi < 0 or (xi == 0 and np.signbit(np.float32(xi))):
             exp_c |= 0x80
         assert ci == exp_c, (xi, ci, exp_c)
+
+
+@pytest.fixture
+def scan_path(monkeypatch):
+    def set_path(p):
+        monkeypatch.setenv("GF_SCAN_PATH", p)
+    return set_path
+
+
+@pytest.mark.parametrize("name,k,c,nq", [("desc-60k-960", 10, 4096, None),
+                                         ("gauss-10k-128", 10, 700, None),
+                                         ("sphere-20k-1000", 5, 1024, None),
+                                         ("ragged-3001-77", 7, 300, None),
+                                         ("desc-600q", 10, 2048, 600)])
+def test_tile_path_bf16(name, k, c, nq, scan_path):
+    """The MFMA tile path (scores of 128-query blocks, masked by each query's
+    visited bitmap) against the oracle and against the per-query BF16 path."""
+    if name == "desc-600q":
+        X, _, _ = W.descriptor(60_000, 960, 1, 0.02, 2)
+        rng = np.random.default_rng(11)
+        Q = (X[rng.integers(0, 60_000, nq)] + 0.02 * rng.standard_normal((nq, 960))).astype(np.float32)
+        key = ("desc-600q", ("bf16",))
+        if key not in _cache:
+            Fg = geraf.build_forest(dev(X), 16, 5, 32, 77, forms=("bf16",))
+            Fo = oracle.build_forest(X, 16, 5, 32, 77)
+            _cache[key] = (X, Q, Fg, Fo, 77)
+        X, Q, Fg, Fo, _ = _cache[key]
+    else:
+        X, Q, Fg, Fo, _ = forests(name, forms=("bf16",))
+    ref = oracle.search(Fo, X, Q, k, c, trace=False)
+    out = {}
+    for path in ("tile", "rows"):
+        scan_path(path)
+        ids = np.zeros((len(Q), k), np.int32)
+        dd = np.zeros((len(Q), k), np.float32)
+        geraf.query(Fg, Q, k, c, ids, dd, form="bf16")
+        out[path] = (ids, dd)
+    ids, dd = out["tile"]
+    hits, agree = 0, 0
+    for i in range(len(Q)):
+        got = ids[i][ids[i] >= 0]
+        for j, gid in enumerate(got.tolist()):
+            diff = X[gid].astype(np.float64) - Q[i].astype(np.float64)
+            true_d = float(diff @ diff)
+            assert abs(dd[i][j] - true_d) <= 1e-5 * true_d
+        assert np.all(np.diff(dd[i][ids[i] >= 0]) >= 0)
+        hits += len(set(got.tolist()) & set(ref["ids"][i][ref["ids"][i] >= 0].tolist()))
+        agree += len(set(got.tolist()) & set(out["rows"][0][i][out["rows"][0][i] >= 0].tolist()))
+    n_ref = max(1, int((ref["ids"] >= 0).sum()))
+    recall, agreement = hits / n_ref, agree / n_ref
+    print(f"{name} tile path: recall vs oracle {recall:.4f}, agreement with rows path {agreement:.4f}")
+    assert np.array_equal(ids >= 0, ref["ids"] >= 0)
+    assert recall >= 0.98 and agreement >= 0.99
