@@ -134,6 +134,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a plain copy "
+                         "kernel of known size that scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the query path is "
@@ -159,6 +162,13 @@ def main():
     kk = min(64, 4 * k)
     ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    if args.copy_probe_mb > 0:
+        src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mb} MiB device-to-device")
+        del src, dst
     nc = torch.empty(nq, dtype=torch.int64, device=dev)
     geraf.query_trace(F, Q, c, ncand=nc)
     torch.cuda.synchronize()

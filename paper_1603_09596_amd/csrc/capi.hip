@@ -69,12 +69,12 @@ bool all_finite_host(const float* X, int64_t count) {
 
 void free_forest_device(gf_forest* F) {
     void* ptrs[] = {F->X32, F->X16, F->norm16, F->X8, F->scale8, F->norm8,
-                    F->nodes, F->perm, F->leaf_off, F->D, F->ws};
+                    F->nodes, F->perm, F->leaf_off, F->permp, F->D, F->ws};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     F->X32 = nullptr; F->X16 = nullptr; F->norm16 = nullptr; F->X8 = nullptr;
     F->scale8 = nullptr; F->norm8 = nullptr; F->nodes = nullptr; F->perm = nullptr;
-    F->leaf_off = nullptr; F->D = nullptr; F->ws = nullptr; F->ws_bytes = 0;
+    F->leaf_off = nullptr; F->permp = nullptr; F->D = nullptr; F->ws = nullptr; F->ws_bytes = 0;
 }
 
 // Bump allocator over the forest's grow-only workspace.
@@ -285,8 +285,8 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     // a3-a6: candidates, distances, best k, re-rank, ties
     const int64_t nbmw = (h.n + 31) / 32;
     gf::ScanArgs ca{};
-    ca.nq = nb; ca.k = J.k; ca.kk = J.kk; ca.n = h.n; ca.d = h.d; ca.m = h.m; ca.W = int(W);
-    ca.leafbits = w.leafbits; ca.perm = F->perm; ca.leaf_off = F->leaf_off;
+    ca.nq = nb; ca.k = J.k; ca.kk = J.kk; ca.n = h.n; ca.d = h.d; ca.m = h.m; ca.W = int(W); ca.H = h.H;
+    ca.leafbits = w.leafbits; ca.permp = F->permp; ca.pp = F->pp;
     ca.Q = w.Qp; ca.ldq = F->ld32; ca.X32 = F->X32; ca.ld32 = F->ld32;
     ca.X16 = F->X16; ca.ld16 = F->ld16; ca.norm16 = F->norm16;
     ca.X8 = F->X8; ca.ld8 = F->ld8; ca.scale8 = F->scale8; ca.norm8 = F->norm8;
@@ -313,8 +313,8 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     if (tile) {
         const TilePlan tp = tile_plan(F, nb);
         gf::ExpandArgs ea{};
-        ea.nq = nb; ea.m = h.m; ea.W = int(W); ea.n = h.n; ea.vw = tp.vw;
-        ea.leafbits = w.leafbits; ea.perm = F->perm; ea.leaf_off = F->leaf_off; ea.vis = w.vis;
+        ea.nq = nb; ea.m = h.m; ea.W = int(W); ea.H = h.H; ea.n = h.n; ea.vw = tp.vw;
+        ea.leafbits = w.leafbits; ea.permp = F->permp; ea.pp = F->pp; ea.vis = w.vis;
         gf::TileArgs ta{};
         ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.vw = tp.vw; ta.Q16 = w.Q16; ta.X16 = F->X16;
         ta.norm16 = F->norm16; ta.vis = w.vis; ta.nsplit = tp.nsplit; ta.split_pts = tp.split_pts;
@@ -469,6 +469,22 @@ gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32
     GF_HIP_B(hipMemcpyAsync(F->perm, h.perm.data(), h.perm.size() * 4, hipMemcpyHostToDevice, st));
     GF_HIP_B(hipMalloc(&F->leaf_off, h.leaf_off.size() * 4));
     GF_HIP_B(hipMemcpyAsync(F->leaf_off, h.leaf_off.data(), h.leaf_off.size() * 4, hipMemcpyHostToDevice, st));
+    {
+        // leaf rows padded to pp ids (pow2 >= the largest leaf, >= 4)
+        const int64_t nleaf = int64_t{1} << h.H;
+        uint32_t maxleaf = 0;
+        for (int64_t j = 0; j < nleaf; ++j) maxleaf = std::max(maxleaf, h.leaf_off[j + 1] - h.leaf_off[j]);
+        int32_t pp = 4;
+        while (uint32_t(pp) < maxleaf) pp <<= 1;
+        F->pp = pp;
+        std::vector<uint32_t> padded(size_t(m) * nleaf * pp, 0xFFFFFFFFu);
+        for (int32_t tr = 0; tr < m; ++tr)
+            for (int64_t j = 0; j < nleaf; ++j)
+                for (uint32_t i = h.leaf_off[j]; i < h.leaf_off[j + 1]; ++i)
+                    padded[(size_t(tr) * nleaf + j) * pp + (i - h.leaf_off[j])] = h.perm[size_t(tr) * n + i];
+        GF_HIP_B(hipMalloc(&F->permp, padded.size() * 4));
+        GF_HIP_B(hipMemcpy(F->permp, padded.data(), padded.size() * 4, hipMemcpyHostToDevice));
+    }
     GF_HIP_B(hipMalloc(&F->D, size_t(t) * 4));
     GF_HIP_B(hipMemcpyAsync(F->D, h.D.data(), size_t(t) * 4, hipMemcpyHostToDevice, st));
     if (forms & GF_KEEP_BF16) {

@@ -59,6 +59,8 @@ struct gf_forest {
     uint2* nodes = nullptr;         // [m][2^H - 1] {float bits of value, slot in D}
     uint32_t* perm = nullptr;       // [m][n]
     uint32_t* leaf_off = nullptr;   // [2^H + 1]
+    uint32_t* permp = nullptr;      // [m][2^H][pp] leaf rows padded with 0xFFFFFFFF
+    int32_t pp = 0;                 // ids per padded leaf row: pow2 >= max leaf size, >= 4
     int32_t* D = nullptr;           // [t]
     // Grow-only scratch for queries.  Calls on one forest are serialised by
     // this mutex (concurrent queries on one forest wait for each other).

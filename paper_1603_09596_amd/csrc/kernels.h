@@ -56,10 +56,10 @@ struct ScanArgs {
     int nq, k, kk;          // kk: list length kept per query (>= k)
     int64_t n;
     int d;
-    int m, W;
+    int m, W, H;
     const uint32_t* leafbits;   // [m][W][nq]
-    const uint32_t* perm;       // [m][n]
-    const uint32_t* leaf_off;   // [2^H + 1]
+    const uint32_t* permp;      // [m][2^H][pp] padded leaf rows
+    int pp;
     const float* Q;             // [nq][ldq] FP32 queries (device)
     int64_t ldq;
     const float* X32;           // [n][ld32]
@@ -89,11 +89,11 @@ bool scan_supported(int64_t n, int form, int64_t ld8);
 constexpr int kTileList = 48;   // best scores kept per (query, point split)
 
 struct ExpandArgs {
-    int nq, m, W;
+    int nq, m, W, H;
     int64_t n, vw;
     const uint32_t* leafbits;   // [m][W][nq]
-    const uint32_t* perm;       // [m][n]
-    const uint32_t* leaf_off;   // [2^H + 1]
+    const uint32_t* permp;      // [m][2^H][pp] padded leaf rows
+    int pp;
     uint32_t* vis;              // [nq][vw] visited bitmaps
 };
 

@@ -164,4 +164,48 @@ __device__ __forceinline__ void finish_query(bool rerank, int kk, int k, int q, 
     }
 }
 
+// OR the point ids of every opened leaf of query q into the LDS bitmap bm.
+// Threads take whole words (32 leaves of one tree) of the query's leaf
+// bitmap, strided by `stride`; each opened leaf is one padded row of pp ids
+// (16-byte aligned, unused slots 0xFFFFFFFF), read as 16-byte vectors, two
+// leaves in flight at a time.  leafbits: [m][W][nq] words.
+__device__ __forceinline__ void expand_opened_leaves(uint32_t* bm, const uint32_t* leafbits, int q,
+                                                     int nq, int m, int W, int H,
+                                                     const uint32_t* permp, int pp, int first,
+                                                     int stride) {
+    const int64_t nwords = int64_t(m) * W;
+    const int64_t nleaf = int64_t(1) << H;      // leaves per tree (rows per tree in permp)
+    const int pp4 = pp / 4;
+    for (int64_t f = first; f < nwords; f += stride) {
+        uint32_t bits = leafbits[f * nq + q];
+        const int64_t tree = f / W;
+        const int64_t leaf0 = (f % W) * 32;
+        while (bits) {
+            const int ja = __builtin_ctz(bits);
+            bits &= bits - 1;
+            int jb = -1;
+            if (bits) { jb = __builtin_ctz(bits); bits &= bits - 1; }
+            const uint4* ra = reinterpret_cast<const uint4*>(permp + ((tree * nleaf) + leaf0 + ja) * pp);
+            const uint4* rb = reinterpret_cast<const uint4*>(permp + ((tree * nleaf) + leaf0 + (jb < 0 ? ja : jb)) * pp);
+            for (int c = 0; c < pp4; c += 8) {
+                uint4 va[8], vb[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const bool ok = c + i < pp4;
+                    va[i] = ok ? ra[c + i] : make_uint4(~0u, ~0u, ~0u, ~0u);
+                    vb[i] = (ok && jb >= 0) ? rb[c + i] : make_uint4(~0u, ~0u, ~0u, ~0u);
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t ids[8] = {va[i].x, va[i].y, va[i].z, va[i].w,
+                                             vb[i].x, vb[i].y, vb[i].z, vb[i].w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        if (ids[e] != 0xFFFFFFFFu) atomicOr(&bm[ids[e] >> 5], 1u << (ids[e] & 31u));
+                }
+            }
+        }
+    }
+}
+
 }  // namespace gf

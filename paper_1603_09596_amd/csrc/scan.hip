@@ -142,31 +142,8 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     // 1. visited bitmap <- union of the opened leaves
     for (int64_t i = threadIdx.x; i < nbmw_pad; i += kThreads) bm[i] = 0u;
     __syncthreads();
-    const int64_t nwords = int64_t(a.m) * a.W;
-    for (int64_t f = threadIdx.x; f < nwords; f += kThreads) {
-        uint32_t bits = a.leafbits[f * a.nq + q];
-        if (!bits) continue;
-        const int tree = int(f / a.W);
-        const uint32_t wbase = uint32_t(f % a.W) * 32u;
-        const uint32_t* pts = a.perm + int64_t(tree) * a.n;
-        while (bits) {
-            const uint32_t leaf = wbase + uint32_t(__builtin_ctz(bits));
-            bits &= bits - 1;
-            const uint32_t lo = a.leaf_off[leaf], hi = a.leaf_off[leaf + 1];
-            uint32_t i = lo;
-            for (; i + 4 <= hi; i += 4) {
-                const uint32_t p0 = pts[i], p1 = pts[i + 1], p2 = pts[i + 2], p3 = pts[i + 3];
-                atomicOr(&bm[p0 >> 5], 1u << (p0 & 31u));
-                atomicOr(&bm[p1 >> 5], 1u << (p1 & 31u));
-                atomicOr(&bm[p2 >> 5], 1u << (p2 & 31u));
-                atomicOr(&bm[p3 >> 5], 1u << (p3 & 31u));
-            }
-            for (; i < hi; ++i) {
-                const uint32_t p0 = pts[i];
-                atomicOr(&bm[p0 >> 5], 1u << (p0 & 31u));
-            }
-        }
-    }
+    expand_opened_leaves(bm, a.leafbits, q, a.nq, a.m, a.W, a.H, a.permp, a.pp, threadIdx.x,
+                         kThreads);
     __syncthreads();
     if (a.cand_bits) {
         for (int64_t i = threadIdx.x; i < nbmw; i += kThreads)

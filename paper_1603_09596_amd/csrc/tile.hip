@@ -114,6 +114,8 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     __shared__ __attribute__((aligned(16))) uint16_t xs[2][kTP * kRowPad];
     __shared__ float lst_s[kTWaves * 16 * kTileList];   // per wave: 16 queries x 48 entries
     __shared__ int lst_i[kTWaves * 16 * kTileList];
+    __shared__ uint32_t epi_vis[2 * kTQ];    // visited words of the tile: [query][half]
+    __shared__ float epi_norm[kTP];          // squared norms of the tile's points
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int quarter = lane >> 4, col = lane & 15;
@@ -150,46 +152,67 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
 
     const int64_t pb = int64_t(blockIdx.y) * a.split_pts;
     const int64_t pe = (pb + a.split_pts < a.n) ? pb + a.split_pts : a.n;
+    const int64_t ntile = (pe > pb) ? (pe - pb + kTP - 1) / kTP : 0;
     constexpr int kMaxChunks = (KSTEPS * 32 + kKC - 1) / kKC;
 
-    for (int64_t p0 = pb; p0 < pe; p0 += kTP) {
-        // stage chunk 0 of this tile: 64 rows x 512 B, 4 x 16 B per thread
-        auto load_chunk = [&](int c, uint4 (&r)[4]) {
+    // X tiles stream through two LDS buffers; stage s (tile s / nchunks,
+    // chunk s % nchunks) is computed from buffer s & 1 while stage s + 1 is
+    // being fetched, across tile boundaries too.
+    auto load_chunk = [&](int64_t p0, int c, uint4 (&r)[4]) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int e = threadIdx.x + kTThreads * j;   // 16-byte unit, 32 per row
-                const int row = e >> 5, c16 = e & 31;
-                const int64_t x = p0 + row;
-                const int64_t k = int64_t(c) * kKC + c16 * 8;
-                r[j] = (x < pe && k < a.ld16)
-                           ? *reinterpret_cast<const uint4*>(a.X16 + x * a.ld16 + k)
-                           : make_uint4(0, 0, 0, 0);
-            }
-        };
-        auto store_chunk = [&](int buf, const uint4 (&r)[4]) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int e = threadIdx.x + kTThreads * j;
-                const int row = e >> 5, c16 = e & 31;
-                *reinterpret_cast<uint4*>(&xs[buf][row * kRowPad + c16 * 8]) = r[j];
-            }
-        };
-        {
-            uint4 r[4];
-            load_chunk(0, r);
-            store_chunk(0, r);
+        for (int j = 0; j < 4; ++j) {
+            const int e = threadIdx.x + kTThreads * j;   // 16-byte unit, 32 per row
+            const int row = e >> 5, c16 = e & 31;
+            const int64_t x = p0 + row;
+            const int64_t k = int64_t(c) * kKC + c16 * 8;
+            r[j] = (x < pe && k < a.ld16)
+                       ? *reinterpret_cast<const uint4*>(a.X16 + x * a.ld16 + k)
+                       : make_uint4(0, 0, 0, 0);
         }
-        __syncthreads();
+    };
+    auto store_chunk = [&](int buf, const uint4 (&r)[4]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = threadIdx.x + kTThreads * j;
+            const int row = e >> 5, c16 = e & 31;
+            *reinterpret_cast<uint4*>(&xs[buf][row * kRowPad + c16 * 8]) = r[j];
+        }
+    };
+    if (ntile > 0) {
+        uint4 r[4];
+        load_chunk(pb, 0, r);
+        store_chunk(0, r);
+    }
+    __syncthreads();
+    int stage = 0;
+    for (int64_t t = 0; t < ntile; ++t) {
+        const int64_t p0 = pb + t * kTP;
+        // operands of this tile's epilogue, fetched ahead of the MFMA loop
+        // (one per thread): the visited words of the 128 queries for points
+        // p0..p0+31 and p0+32..p0+63, and the squared norms of the 64 points
+        uint32_t pre = 0;
+        {
+            const int tid = threadIdx.x;
+            if (tid < 2 * kTQ) {
+                const int qq = blockIdx.x * kTQ + (tid >> 1);
+                const int64_t x = p0 + 32 * (tid & 1);
+                pre = (qq < a.nq && x < pe) ? a.vis[int64_t(qq) * a.vw + (x >> 5)] : 0u;
+            } else if (tid < 2 * kTQ + kTP) {
+                const int64_t x = p0 + (tid - 2 * kTQ);
+                pre = (x < pe) ? __float_as_uint(a.norm16[x]) : 0u;
+            }
+        }
         f4 acc[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int c = 0; c < kMaxChunks; ++c) {
             if (c < nchunks) {
+                const bool last = (c + 1 == nchunks);
+                const bool more = !last || (t + 1 < ntile);
                 uint4 nxt[4];
-                const bool more = c + 1 < nchunks;
-                if (more) load_chunk(c + 1, nxt);
-                const uint16_t* xb = xs[c & 1];
+                if (more) load_chunk(last ? p0 + kTP : p0, last ? 0 : c + 1, nxt);
+                const uint16_t* xb = xs[stage & 1];
 #pragma unroll
                 for (int s = 0; s < kKC / 32; ++s) {
                     const int S = c * (kKC / 32) + s;
@@ -203,27 +226,29 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
                         }
                     }
                 }
-                if (more) store_chunk((c + 1) & 1, nxt);
+                if (more) store_chunk((stage + 1) & 1, nxt);
                 __syncthreads();
+                ++stage;
             }
         }
+        if (threadIdx.x < 2 * kTQ) epi_vis[threadIdx.x] = pre;
+        else if (threadIdx.x < 2 * kTQ + kTP) epi_norm[threadIdx.x - 2 * kTQ] = __uint_as_float(pre);
+        __syncthreads();
         // epilogue: C[row 4 quarter + i][col] of block b = q(row) . x(16 b + col)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int64_t x = p0 + 16 * b + col;
             const bool xin = x < pe;
-            const float nx = xin ? a.norm16[x] : 0.0f;
+            const float nxb = epi_norm[16 * b + col];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int q = q0 + 4 * quarter + i;
                 bool cand = false;
                 float sc = __builtin_inff();
-                if (xin && q < a.nq) {
-                    const uint32_t w = a.vis[int64_t(q) * a.vw + (x >> 5)];
-                    if ((w >> (x & 31)) & 1u) {
-                        sc = nx - 2.0f * acc[b][i];
-                        cand = entry_before(sc, int(x), ts[i], ti[i]);
-                    }
+                const uint32_t vword = epi_vis[2 * (wave * 16 + 4 * quarter + i) + (b >> 1)];
+                if (xin && q < a.nq && ((vword >> (x & 31)) & 1u)) {
+                    sc = nxb - 2.0f * acc[b][i];
+                    cand = entry_before(sc, int(x), ts[i], ti[i]);
                 }
                 const int rbase = (wave * 16 + 4 * quarter + i) * kTileList;
                 quarter_offer(cand, sc, int(x), lst_s + rbase, lst_i + rbase, ts[i], ti[i]);
@@ -252,52 +277,11 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
 __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
     extern __shared__ uint32_t smem[];
     uint32_t* bm = smem;                                   // [vw]
-    int* lstart = reinterpret_cast<int*>(bm + a.vw);       // [waves][32]
-    int* lpre = lstart + (kExpandThreads / kWave) * 32;    // [waves][32]
     const int q = blockIdx.x;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    const int nwaves = kExpandThreads / kWave;
     for (int64_t i = threadIdx.x; i < a.vw; i += kExpandThreads) bm[i] = 0u;
     __syncthreads();
-    const int64_t nwords = int64_t(a.m) * a.W;
-    int* my_start = lstart + wave * 32;
-    int* my_pre = lpre + wave * 32;
-    for (int64_t f = wave; f < nwords; f += nwaves) {
-        const uint32_t bits = a.leafbits[f * a.nq + q];
-        if (!bits) continue;
-        const int tree = int(f / a.W);
-        const uint32_t leaf = uint32_t(f % a.W) * 32u + uint32_t(lane);
-        const bool has = lane < 32 && ((bits >> lane) & 1u);
-        const int lo = has ? int(a.leaf_off[leaf]) : 0;
-        const int sz = has ? int(a.leaf_off[leaf + 1]) - lo : 0;
-        int incl = sz;
-#pragma unroll
-        for (int o = 1; o < 32; o <<= 1) {
-            const int t = __shfl_up(incl, o);
-            if (lane >= o) incl += t;
-        }
-        const int total = __shfl(incl, 31);
-        if (lane < 32) {
-            my_start[lane] = lo;
-            my_pre[lane] = incl;        // inclusive prefix of sizes
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint32_t* pts = a.perm + int64_t(tree) * a.n;
-        for (int o = lane; o < total; o += kWave) {
-            int lo_j = 0, hi_j = 31;                 // first leaf with prefix > o
-            while (lo_j < hi_j) {
-                const int mid = (lo_j + hi_j) >> 1;
-                if (my_pre[mid] > o) hi_j = mid; else lo_j = mid + 1;
-            }
-            const int before = lo_j ? my_pre[lo_j - 1] : 0;
-            const uint32_t id = pts[my_start[lo_j] + (o - before)];
-            atomicOr(&bm[id >> 5], 1u << (id & 31u));
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
+    expand_opened_leaves(bm, a.leafbits, q, a.nq, a.m, a.W, a.H, a.permp, a.pp, threadIdx.x,
+                         kExpandThreads);
     __syncthreads();
     for (int64_t i = threadIdx.x; i < a.vw; i += kExpandThreads) a.vis[int64_t(q) * a.vw + i] = bm[i];
 }
@@ -339,9 +323,7 @@ __global__ __launch_bounds__(512) void k_merge_rerank(MergeArgs a) {
                  a.ids, a.dists);
 }
 
-size_t expand_lds_bytes(int64_t vw) {
-    return size_t(vw) * 4 + size_t(kExpandThreads / kWave) * 32 * 8;
-}
+size_t expand_lds_bytes(int64_t vw) { return size_t(vw) * 4; }
 
 hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeArgs& m,
                             hipStream_t st, hipEvent_t* ev) {
