@@ -69,12 +69,13 @@ bool all_finite_host(const float* X, int64_t count) {
 
 void free_forest_device(gf_forest* F) {
     void* ptrs[] = {F->X32, F->X16, F->norm16, F->X8, F->scale8, F->norm8,
-                    F->nodes, F->perm, F->leaf_off, F->permp, F->D, F->ws};
+                    F->nodes, F->perm, F->leaf_off, F->permp, F->leafof, F->D, F->ws};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     F->X32 = nullptr; F->X16 = nullptr; F->norm16 = nullptr; F->X8 = nullptr;
     F->scale8 = nullptr; F->norm8 = nullptr; F->nodes = nullptr; F->perm = nullptr;
-    F->leaf_off = nullptr; F->permp = nullptr; F->D = nullptr; F->ws = nullptr; F->ws_bytes = 0;
+    F->leaf_off = nullptr; F->permp = nullptr; F->leafof = nullptr; F->D = nullptr; F->ws = nullptr;
+    F->ws_bytes = 0;
 }
 
 // Bump allocator over the forest's grow-only workspace.
@@ -93,14 +94,17 @@ struct Workspace {
     float* Qp; uint16_t* Q16; uint8_t* Q8; float* qscale; float* qnorm; int32_t* cpq;
     gf::SelState* state; uint32_t* hist; uint32_t* coff; uint64_t* ckey; uint32_t* ccode;
     uint32_t* leafbits; uint32_t* flags; int32_t* ids; float* dists;
-    uint32_t* vis; float* part_s; int* part_i;   // tile path only
+    uint32_t* openT; uint32_t* visT; uint32_t* gthr; float* part_s; int* part_i;   // tile path only
 };
 
 // Split of the points for the tile path: enough (query block, split)
-// workgroups to fill the chip several times over.
+// workgroups to fill the chip several times over, each split small enough
+// for 32-bit byte offsets into its rows; and the query chunking of the
+// point-major candidate sets.
 struct TilePlan {
     int nsplit = 0;
-    int64_t split_pts = 0, vw = 0;
+    int64_t split_pts = 0;
+    int cw = 0, nchunk = 0;
 };
 
 TilePlan tile_plan(const gf_forest* F, int nb) {
@@ -108,11 +112,16 @@ TilePlan tile_plan(const gf_forest* F, int nb) {
     const int64_t qblocks = (nb + 127) / 128;
     int64_t ns = (2048 + qblocks - 1) / qblocks;
     const int64_t tiles = (F->host.n + 63) / 64;
+    const int64_t max_tiles = ((int64_t{1} << 31) - 1) / (int64_t(F->ld16) * 2 * 64);
     if (ns > tiles) ns = tiles;
     if (ns < 1) ns = 1;
+    if ((tiles + ns - 1) / ns > max_tiles) ns = (tiles + max_tiles - 1) / max_tiles;
     p.split_pts = ((tiles + ns - 1) / ns) * 64;
     p.nsplit = int((F->host.n + p.split_pts - 1) / p.split_pts);
-    p.vw = round_up((F->host.n + 31) / 32, 2);
+    const int64_t nqw = (nb + 31) / 32;
+    p.cw = 4;
+    while (p.cw < 32 && p.cw < nqw) p.cw <<= 1;
+    p.nchunk = int((nqw + p.cw - 1) / p.cw);
     return p;
 }
 
@@ -135,10 +144,12 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Worksp
     size_t ofl = c.take<uint32_t>(8);
     size_t oids = c.take<int32_t>(size_t(nb) * k);
     size_t odst = c.take<float>(size_t(nb) * k);
-    size_t ovis = 0, ops = 0, opi = 0;
+    size_t oopen = 0, ovis = 0, othr = 0, ops = 0, opi = 0;
     if (tile) {
         const TilePlan tp = tile_plan(F, nb);
-        ovis = c.take<uint32_t>(size_t(nb) * tp.vw);
+        oopen = c.take<uint32_t>(size_t(tp.nchunk) * F->host.m * (size_t{1} << F->host.H) * tp.cw);
+        ovis = c.take<uint32_t>(size_t(tp.nchunk) * F->host.n * tp.cw);
+        othr = c.take<uint32_t>(nb);
         ops = c.take<float>(size_t(nb) * tp.nsplit * gf::kTileList);
         opi = c.take<int>(size_t(nb) * tp.nsplit * gf::kTileList);
     }
@@ -170,7 +181,9 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Worksp
     w.flags = reinterpret_cast<uint32_t*>(b + ofl);
     w.ids = reinterpret_cast<int32_t*>(b + oids);
     w.dists = reinterpret_cast<float*>(b + odst);
-    w.vis = tile ? reinterpret_cast<uint32_t*>(b + ovis) : nullptr;
+    w.openT = tile ? reinterpret_cast<uint32_t*>(b + oopen) : nullptr;
+    w.visT = tile ? reinterpret_cast<uint32_t*>(b + ovis) : nullptr;
+    w.gthr = tile ? reinterpret_cast<uint32_t*>(b + othr) : nullptr;
     w.part_s = tile ? reinterpret_cast<float*>(b + ops) : nullptr;
     w.part_i = tile ? reinterpret_cast<int*>(b + opi) : nullptr;
     return GF_OK;
@@ -200,9 +213,10 @@ struct QueryJob {
 // of the points.  GF_SCAN_PATH=rows|tile forces a path.
 bool use_tile_path(const gf_forest* F, const QueryJob& J, int nb) {
     if (J.form != gf::kFormBF16 || J.leaf_bits || J.cand_bits || J.ncand) return false;
+    if (J.kk > gf::kTileList) return false;   // each split keeps kTileList entries per query
     if (F->ld16 > 1024) return false;
     if (!gf::scan_supported(F->host.n, gf::kFormFP32, F->ld8)) return false;
-    if (gf::expand_lds_bytes(round_up((F->host.n + 31) / 32, 2)) > 160 * 1024) return false;
+    if (!F->leafof) return false;
     const char* env = std::getenv("GF_SCAN_PATH");
     if (env && std::strcmp(env, "rows") == 0) return false;
     if (env && std::strcmp(env, "tile") == 0) return true;
@@ -313,11 +327,13 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     if (tile) {
         const TilePlan tp = tile_plan(F, nb);
         gf::ExpandArgs ea{};
-        ea.nq = nb; ea.m = h.m; ea.W = int(W); ea.H = h.H; ea.n = h.n; ea.vw = tp.vw;
-        ea.leafbits = w.leafbits; ea.permp = F->permp; ea.pp = F->pp; ea.vis = w.vis;
+        ea.nq = nb; ea.m = h.m; ea.W = int(W); ea.H = h.H; ea.n = h.n;
+        ea.cw = tp.cw; ea.nchunk = tp.nchunk;
+        ea.leafbits = w.leafbits; ea.leafof = F->leafof; ea.openT = w.openT; ea.visT = w.visT;
+        ea.gthr = w.gthr;
         gf::TileArgs ta{};
-        ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.vw = tp.vw; ta.Q16 = w.Q16; ta.X16 = F->X16;
-        ta.norm16 = F->norm16; ta.vis = w.vis; ta.nsplit = tp.nsplit; ta.split_pts = tp.split_pts;
+        ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.cw = tp.cw; ta.Q16 = w.Q16; ta.X16 = F->X16;
+        ta.norm16 = F->norm16; ta.visT = w.visT; ta.gthr = w.gthr; ta.nsplit = tp.nsplit; ta.split_pts = tp.split_pts;
         ta.part_s = w.part_s; ta.part_i = w.part_i;
         gf::MergeArgs ma{};
         ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = tp.nsplit;
@@ -488,6 +504,15 @@ gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32
     GF_HIP_B(hipMalloc(&F->D, size_t(t) * 4));
     GF_HIP_B(hipMemcpyAsync(F->D, h.D.data(), size_t(t) * 4, hipMemcpyHostToDevice, st));
     if (forms & GF_KEEP_BF16) {
+        // leaf of every point in every tree, point-major (tile path)
+        const int64_t nleaf = int64_t{1} << h.H;
+        std::vector<uint32_t> lof(size_t(n) * m);
+        for (int32_t tr = 0; tr < m; ++tr)
+            for (int64_t j = 0; j < nleaf; ++j)
+                for (uint32_t i = h.leaf_off[j]; i < h.leaf_off[j + 1]; ++i)
+                    lof[size_t(h.perm[size_t(tr) * n + i]) * m + tr] = uint32_t(tr * nleaf + j);
+        GF_HIP_B(hipMalloc(&F->leafof, lof.size() * 4));
+        GF_HIP_B(hipMemcpy(F->leafof, lof.data(), lof.size() * 4, hipMemcpyHostToDevice));
         GF_HIP_B(hipMalloc(&F->X16, size_t(n) * F->ld16 * 2));
         GF_HIP_B(hipMalloc(&F->norm16, size_t(n) * 4));
         hipLaunchKernelGGL(gf::k_to_bf16, dim3((n + 3) / 4), dim3(256), 0, st, F->X32, n, d,

@@ -61,6 +61,7 @@ struct gf_forest {
     uint32_t* leaf_off = nullptr;   // [2^H + 1]
     uint32_t* permp = nullptr;      // [m][2^H][pp] leaf rows padded with 0xFFFFFFFF
     int32_t pp = 0;                 // ids per padded leaf row: pow2 >= max leaf size, >= 4
+    uint32_t* leafof = nullptr;     // [n][m] tree * 2^H + leaf of each point (BF16 form)
     int32_t* D = nullptr;           // [t]
     // Grow-only scratch for queries.  Calls on one forest are serialised by
     // this mutex (concurrent queries on one forest wait for each other).

@@ -88,24 +88,32 @@ bool scan_supported(int64_t n, int form, int64_t ld8);
 
 constexpr int kTileList = 48;   // best scores kept per (query, point split)
 
+// Candidate sets in point-major form for the tile path.  Queries are grouped
+// in chunks of 32 cw (cw words of query bits per row, cw a power of two in
+// [4, 32]); bit (q & 31) of word (q >> 5) % cw of a row belongs to query q.
 struct ExpandArgs {
     int nq, m, W, H;
-    int64_t n, vw;
-    const uint32_t* leafbits;   // [m][W][nq]
-    const uint32_t* permp;      // [m][2^H][pp] padded leaf rows
-    int pp;
-    uint32_t* vis;              // [nq][vw] visited bitmaps
+    int64_t n;
+    int cw, nchunk;
+    const uint32_t* leafbits;   // [m][W][nq] opened leaves, query fastest
+    const uint32_t* leafof;     // [n][m] tree * 2^H + leaf holding each point
+    uint32_t* openT;            // [nchunk][m 2^H][cw] queries that opened each leaf
+    uint32_t* visT;             // [nchunk][n][cw] queries having each point as candidate
+    uint32_t* gthr;             // [nq] set to the bits of +inf here
 };
 
 struct TileArgs {
     int nq;
-    int64_t n, ld16, vw;
+    int64_t n, ld16;
+    int cw;
     const uint16_t* Q16;        // [nq][ld16]
     const uint16_t* X16;        // [n][ld16]
     const float* norm16;        // [n]
-    const uint32_t* vis;        // [nq][vw]
+    const uint32_t* visT;       // [nchunk][n][cw]
+    uint32_t* gthr;             // [nq] order-preserving bits of an upper bound on
+                                // each query's kTileList-th best score
     int nsplit;
-    int64_t split_pts;          // points per split, multiple of 64
+    int64_t split_pts;          // points per split, multiple of 64, split_pts * ld16 * 2 < 2^31
     float* part_s;              // [nq][nsplit][kTileList]
     int* part_i;
 };
@@ -122,7 +130,6 @@ struct MergeArgs {
     float* dists;
 };
 
-size_t expand_lds_bytes(int64_t vw);
 // Records ev[0] after the expansion and ev[1] after the tile kernel (ev may
 // be null).
 hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeArgs& m,

@@ -12,17 +12,21 @@
 // set, Sec. 2.3).  The result is the reduced-precision selection of the
 // per-query path, followed by the same FP32 re-rank and FP64 tie re-check.
 //
-//   k_expand        one workgroup per query: opened leaves -> visited bitmap
-//                   (LDS), written out as [nq][vw] words.
-//   k_tile_bf16     grid (query blocks of 128, point splits): each wave keeps
-//                   its 16 queries' BF16 rows in registers as MFMA A operands;
-//                   64-point x 256-k tiles of X stream through LDS (double
-//                   buffered) as B operands; the epilogue masks by the visited
-//                   bits and keeps, per query and split, the 48 best (score,
-//                   id) pairs in registers of the 16 lanes that hold that
-//                   query's row of the MFMA result.
-//   k_merge_rerank  one workgroup per query: best `kk` over the splits, then
-//                   FP32 compensated re-rank and FP64 tie re-check.
+//   k_open_transpose  opened-leaf words (32 leaves of one query each) -> one
+//                    row per (tree, leaf) of the bits of the queries that
+//                    opened it, in chunks of up to 1024 queries.
+//   k_expand_points  one row per point: the OR of the rows of the m leaves
+//                    holding it = the queries having the point as candidate.
+//   k_tile_bf16      grid (query blocks of 128, point splits): each wave keeps
+//                    its 16 queries' BF16 rows in registers as MFMA A operands;
+//                    64-point x 128-k stages of X stream into four LDS buffers
+//                    with direct global->LDS loads (three stages in flight) as
+//                    B operands; the epilogue masks by the candidate bits and
+//                    keeps, per query and split, the 48 best (score, id) pairs
+//                    in LDS, shared by the 16 lanes that hold that query's row
+//                    of the MFMA result.
+//   k_merge_rerank   one workgroup per query: best `kk` over the splits, then
+//                    FP32 compensated re-rank and FP64 tie re-check.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -41,19 +45,24 @@ constexpr int kTWaves = 8;
 constexpr int kTThreads = kTWaves * kWave;
 constexpr int kTQ = kTWaves * 16;     // queries per workgroup
 constexpr int kTP = 64;               // points per tile
-constexpr int kKC = 256;              // k (bf16 elements) per LDS stage
-constexpr int kRowPad = kKC + 8;      // LDS row stride in elements (528 B)
 constexpr int kSlots = 3;             // list entries per lane and query (x 16 lanes)
 constexpr int kExpandThreads = 1024;
 
-// Lexicographic maximum of (s, i) over the 16 lanes of a quarter-wave.
+// One DPP step of a 16-lane reduction (a DPP row is a quarter-wave).
+template <int CTRL>
+__device__ __forceinline__ void quarter_max_step(float& s, int& i) {
+    const float os = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), CTRL, 0xF, 0xF, false));
+    const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+    if (entry_before(s, i, os, oi)) { s = os; i = oi; }
+}
+
+// Lexicographic maximum of (s, i) over the 16 lanes of a quarter-wave:
+// pairs, quads, halves of the row, whole row.
 __device__ __forceinline__ void quarter_max(float& s, int& i) {
-#pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) {
-        const float os = __shfl_xor(s, o);
-        const int oi = __shfl_xor(i, o);
-        if (entry_before(s, i, os, oi)) { s = os; i = oi; }
-    }
+    quarter_max_step<0xB1>(s, i);    // quad_perm [1, 0, 3, 2]
+    quarter_max_step<0x4E>(s, i);    // quad_perm [2, 3, 0, 1]
+    quarter_max_step<0x141>(s, i);   // row_half_mirror
+    quarter_max_step<0x140>(s, i);   // row_mirror
 }
 
 // Offer every lane's (sc, id) with cand set to the list of its quarter-wave.
@@ -109,19 +118,76 @@ __device__ __forceinline__ void quarter_offer(bool cand, float sc, int id, float
     }
 }
 
+// s_waitcnt immediates (gfx9 encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] at 15:14)
+constexpr int kWaitVm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
+
+constexpr int kKS = 128;                               // k (bf16 elements) per pipeline stage
+constexpr int kNBuf = 4;                               // LDS stages (prefetch distance kNBuf - 1)
+constexpr int kStageBytes = kTP * kKS * 2;             // 64 rows x 256 B = 16 KB
+constexpr int kDmaPerWave = kStageBytes / 1024 / kTWaves;   // 1 KB per wave instruction -> 2
+// epilogue operands per tile (dwords): 4 candidate words per point, the
+// points' norms, the block's 128 shared thresholds
+constexpr int kEpiVis = 0, kEpiNorm = 4 * kTP, kEpiThr = 5 * kTP;
+constexpr int kEpi = 5 * kTP + kTQ;
+
+// Order-preserving map of float scores to uint32 (a < b <=> key(a) < key(b)).
+__device__ __forceinline__ uint32_t score_key(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key_score(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+__device__ __forceinline__ uint32_t lds_offset(const void* p) {
+    return uint32_t(uintptr_t((const lds_u32*)p));   // generic -> LDS address space
+}
+
+__device__ __forceinline__ const void* uniform_ptr(const void* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    return reinterpret_cast<const void*>((uint64_t(hi) << 32) | lo);
+}
+
+// Direct global -> LDS loads (gfx950 global_load_lds_*): every lane of the
+// wave reads `size` bytes at its own global address and the wave writes them
+// contiguously at LDS address m0 + lane * size.  They are issued from inline
+// assembly so that the compiler does not wait for them before unrelated LDS
+// reads; the kernel waits for them itself (s_waitcnt vmcnt) before a barrier.
+// dma_16s addresses a uniform base plus a 32-bit per-lane byte offset.
+__device__ __forceinline__ void dma_16s(const void* base, uint32_t voff, uint32_t lds) {
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+                 :: "v"(voff), "s"(base), "{m0}"(__builtin_amdgcn_readfirstlane(lds)) : "memory");
+}
+__device__ __forceinline__ void dma_16(const void* g, uint32_t lds) {
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                 :: "v"(g), "{m0}"(__builtin_amdgcn_readfirstlane(lds)) : "memory");
+}
+__device__ __forceinline__ void dma_4(const void* g, uint32_t lds) {
+    asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off"
+                 :: "v"(g), "{m0}"(__builtin_amdgcn_readfirstlane(lds)) : "memory");
+}
+
+// KSTEPS k steps of 32 (the row length rounded up; steps past the row have
+// zero A operands), in KSTEPS / 4 rounded up stages of 128 per tile.
 template <int KSTEPS>
 __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t xs[2][kTP * kRowPad];
+    constexpr int NC = (KSTEPS + 3) / 4;
+    // X stages: row r of a stage holds its 16 k units (16 B each) at
+    // positions unit ^ (r & 15), so the contiguous 1 KB writes of the direct
+    // loads and the 16-row B-operand reads are both free of bank conflicts.
+    __shared__ __attribute__((aligned(1024))) uint16_t xs[kNBuf * kStageBytes / 2];
     __shared__ float lst_s[kTWaves * 16 * kTileList];   // per wave: 16 queries x 48 entries
     __shared__ int lst_i[kTWaves * 16 * kTileList];
-    __shared__ uint32_t epi_vis[2 * kTQ];    // visited words of the tile: [query][half]
-    __shared__ float epi_norm[kTP];          // squared norms of the tile's points
+    __shared__ __attribute__((aligned(1024))) uint32_t epi[kEpi];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int quarter = lane >> 4, col = lane & 15;
     const int q0 = blockIdx.x * kTQ + wave * 16;
     const int ks = int(a.ld16 / 32);
-    const int nchunks = int((a.ld16 + kKC - 1) / kKC);
 
     // A operands: query row q0 + col, elements k = 32 s + 8 quarter .. + 8
     bf16x8 qa[KSTEPS];
@@ -138,7 +204,9 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             }
         }
     }
-    // list of query row r of this wave: lst_*[(wave * 16 + r) * 48 ..]
+    // the A operands are complete before any direct load is issued, so the
+    // compiler has no pending load of its own to wait for inside the loop
+    __builtin_amdgcn_s_waitcnt(kWaitVm(0));
     float ts[4];
     int ti[4];
 #pragma unroll
@@ -151,110 +219,167 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     }
 
     const int64_t pb = int64_t(blockIdx.y) * a.split_pts;
-    const int64_t pe = (pb + a.split_pts < a.n) ? pb + a.split_pts : a.n;
-    const int64_t ntile = (pe > pb) ? (pe - pb + kTP - 1) / kTP : 0;
-    constexpr int kMaxChunks = (KSTEPS * 32 + kKC - 1) / kKC;
+    const int npts = int((pb + a.split_pts < a.n) ? a.split_pts : a.n - pb);
+    const int ntile = (npts + kTP - 1) / kTP;
+    const uint32_t xs0 = lds_offset(xs), epi0 = lds_offset(epi);
+    const void* xbase = uniform_ptr(a.X16 + pb * a.ld16);
+    const uint32_t rowbytes = uint32_t(a.ld16) * 2u;
+    // this block's 128 queries: words wo .. wo + 3 of query chunk qc
+    const int qc = (4 * int(blockIdx.x)) / a.cw, wo = (4 * int(blockIdx.x)) % a.cw;
+    const uint32_t* visb = a.visT + (int64_t(qc) * a.n + pb) * a.cw + wo;
 
-    // X tiles stream through two LDS buffers; stage s (tile s / nchunks,
-    // chunk s % nchunks) is computed from buffer s & 1 while stage s + 1 is
-    // being fetched, across tile boundaries too.
-    auto load_chunk = [&](int64_t p0, int c, uint4 (&r)[4]) {
+    // This wave's share of a stage: rows 4 inst .. 4 inst + 3 for inst =
+    // wave, wave + kTWaves; lane l loads k unit (l & 15) ^ (row & 15) of row
+    // 4 inst + l / 16.  Rows past the split and k past the row are clamped to
+    // valid addresses; that data is never used.
+    int drow[kDmaPerWave];
+    uint32_t dk[kDmaPerWave], trow[kDmaPerWave];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int e = threadIdx.x + kTThreads * j;   // 16-byte unit, 32 per row
-            const int row = e >> 5, c16 = e & 31;
-            const int64_t x = p0 + row;
-            const int64_t k = int64_t(c) * kKC + c16 * 8;
-            r[j] = (x < pe && k < a.ld16)
-                       ? *reinterpret_cast<const uint4*>(a.X16 + x * a.ld16 + k)
-                       : make_uint4(0, 0, 0, 0);
-        }
-    };
-    auto store_chunk = [&](int buf, const uint4 (&r)[4]) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int e = threadIdx.x + kTThreads * j;
-            const int row = e >> 5, c16 = e & 31;
-            *reinterpret_cast<uint4*>(&xs[buf][row * kRowPad + c16 * 8]) = r[j];
-        }
-    };
-    if (ntile > 0) {
-        uint4 r[4];
-        load_chunk(pb, 0, r);
-        store_chunk(0, r);
+    for (int j = 0; j < kDmaPerWave; ++j) {
+        const int inst = wave + kTWaves * j;
+        drow[j] = 4 * inst + (lane >> 4);
+        dk[j] = uint32_t(((lane & 15) ^ (drow[j] & 15)) * 8);
     }
-    __syncthreads();
-    int stage = 0;
-    for (int64_t t = 0; t < ntile; ++t) {
-        const int64_t p0 = pb + t * kTP;
-        // operands of this tile's epilogue, fetched ahead of the MFMA loop
-        // (one per thread): the visited words of the 128 queries for points
-        // p0..p0+31 and p0+32..p0+63, and the squared norms of the 64 points
-        uint32_t pre = 0;
-        {
-            const int tid = threadIdx.x;
-            if (tid < 2 * kTQ) {
-                const int qq = blockIdx.x * kTQ + (tid >> 1);
-                const int64_t x = p0 + 32 * (tid & 1);
-                pre = (qq < a.nq && x < pe) ? a.vis[int64_t(qq) * a.vw + (x >> 5)] : 0u;
-            } else if (tid < 2 * kTQ + kTP) {
-                const int64_t x = p0 + (tid - 2 * kTQ);
-                pre = (x < pe) ? __float_as_uint(a.norm16[x]) : 0u;
-            }
+    // B-operand LDS element offsets within a stage for k step s (block b adds 2048 b)
+    int ldsel[kKS / 32];
+#pragma unroll
+    for (int s = 0; s < kKS / 32; ++s) ldsel[s] = col * 128 + (((4 * s + quarter) ^ col) * 8);
+
+    // issue cursor: the next stage to load is chunk ic of tile it, into ibuf
+    int it = 0, ic = 0, ibuf = 0;
+    auto set_rows = [&]() {
+#pragma unroll
+        for (int j = 0; j < kDmaPerWave; ++j) {
+            const int r = it * kTP + drow[j];
+            trow[j] = uint32_t(r < npts ? r : 0) * rowbytes;
         }
+    };
+    auto issue_next = [&]() {
+        const uint32_t dst = xs0 + uint32_t(ibuf) * kStageBytes;
+#pragma unroll
+        for (int j = 0; j < kDmaPerWave; ++j) {
+            const uint32_t k = uint32_t(ic * kKS) + dk[j];
+            const uint32_t koff = k < uint32_t(a.ld16) ? 2u * k : 0u;
+            dma_16s(xbase, trow[j] + koff, dst + uint32_t(wave + kTWaves * j) * 1024u);
+        }
+        ibuf = (ibuf + 1) & (kNBuf - 1);
+        if (++ic == NC) {
+            ic = 0;
+            ++it;
+            set_rows();
+        }
+    };
+    // wave 0 loads the tile's candidate words, wave 1 its norms, waves 2 and
+    // 3 the block's thresholds
+    auto issue_epi = [&](int t) {
+        const int xl = t * kTP + lane;
+        const int xc = xl < npts ? xl : 0;
+        if (wave == 0) {
+            dma_16(visb + int64_t(xc) * a.cw, epi0 + 4u * kEpiVis);
+        } else if (wave == 1) {
+            dma_4(a.norm16 + pb + xc, epi0 + 4u * kEpiNorm);
+        } else if (wave < 4) {
+            const int qq = blockIdx.x * kTQ + (wave - 2) * kWave + lane;
+            dma_4(a.gthr + (qq < a.nq ? qq : 0), epi0 + 4u * (kEpiThr + (wave - 2) * kWave));
+        }
+    };
+    set_rows();
+    for (int p = 0; p < kNBuf - 1 && it < ntile; ++p) issue_next();
+
+    const int wv = wave >> 1;                       // this wave's candidate word
+    const int bit0 = 16 * (wave & 1) + 4 * quarter;  // bit of query q0 + 4 quarter
+    int buf = 0, left = ntile * NC;                  // stages not yet consumed
+    for (int t = 0; t < ntile; ++t) {
         f4 acc[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int c = 0; c < kMaxChunks; ++c) {
-            if (c < nchunks) {
-                const bool last = (c + 1 == nchunks);
-                const bool more = !last || (t + 1 < ntile);
-                uint4 nxt[4];
-                if (more) load_chunk(last ? p0 + kTP : p0, last ? 0 : c + 1, nxt);
-                const uint16_t* xb = xs[stage & 1];
+        for (int c = 0; c < NC; ++c) {
+            // Loads complete in issue order.  After the current stage's
+            // loads, those of min(kNBuf - 2, left - 1) later stages (and
+            // possibly the epilogue loads) were issued: waiting down to that
+            // many stages' worth completes the current stage for this wave,
+            // and the barrier then covers every wave (and frees the previous
+            // stage's buffer for reuse).
+            static_assert(kNBuf == 4, "wait immediates assume two stages in flight");
+            asm volatile("" ::: "memory");
+            if (left > 2) __builtin_amdgcn_s_waitcnt(kWaitVm(2 * kDmaPerWave));
+            else if (left == 2) __builtin_amdgcn_s_waitcnt(kWaitVm(kDmaPerWave));
+            else __builtin_amdgcn_s_waitcnt(kWaitVm(0));
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (it < ntile) issue_next();
+            if (c == 0) issue_epi(t);
+            const uint16_t* xb = xs + buf * (kStageBytes / 2);
 #pragma unroll
-                for (int s = 0; s < kKC / 32; ++s) {
-                    const int S = c * (kKC / 32) + s;
-                    if (S < KSTEPS && S < ks) {
+            for (int s = 0; s < kKS / 32; ++s) {
+                const int S = c * (kKS / 32) + s;
+                if (S < KSTEPS) {
+                    uint4 v[4];
 #pragma unroll
-                        for (int b = 0; b < 4; ++b) {
-                            const uint4 v = *reinterpret_cast<const uint4*>(
-                                xb + (16 * b + col) * kRowPad + 32 * s + 8 * quarter);
-                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                qa[S], __builtin_bit_cast(bf16x8, v), acc[b], 0, 0, 0);
-                        }
-                    }
+                    for (int b = 0; b < 4; ++b)
+                        v[b] = *reinterpret_cast<const uint4*>(xb + ldsel[s] + 2048 * b);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            qa[S], __builtin_bit_cast(bf16x8, v[b]), acc[b], 0, 0, 0);
                 }
-                if (more) store_chunk((stage + 1) & 1, nxt);
-                __syncthreads();
-                ++stage;
             }
+            buf = (buf + 1) & (kNBuf - 1);
+            --left;
         }
-        if (threadIdx.x < 2 * kTQ) epi_vis[threadIdx.x] = pre;
-        else if (threadIdx.x < 2 * kTQ + kTP) epi_norm[threadIdx.x - 2 * kTQ] = __uint_as_float(pre);
-        __syncthreads();
-        // epilogue: C[row 4 quarter + i][col] of block b = q(row) . x(16 b + col)
+        // The epilogue loads were issued at this tile's first stage, and the
+        // stages issued after them are those that exist among the next
+        // NC - 1.  With at least kNBuf chunks per tile and a next tile,
+        // kNBuf - 1 stages followed, so their loads may stay outstanding;
+        // otherwise wait for everything.
+        asm volatile("" ::: "memory");
+        if (NC >= kNBuf && t + 1 < ntile)
+            __builtin_amdgcn_s_waitcnt(kWaitVm(kDmaPerWave * (kNBuf - 1)));
+        else
+            __builtin_amdgcn_s_waitcnt(kWaitVm(0));
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        // epilogue: C[row 4 quarter + i][col] of block b = q(row) . x(16 b + col).
+        // A point enters a query's list only if it is a candidate of the
+        // query and its score is at most both the list's worst and the
+        // shared bound (an upper bound on the query's kTileList-th best over
+        // all splits, so nothing it excludes can be in the final lists); the
+        // insertion re-checks the exact (score, id) order.
+        uint32_t word[4];
+        float nx[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int64_t x = p0 + 16 * b + col;
-            const bool xin = x < pe;
-            const float nxb = epi_norm[16 * b + col];
+            const int xl = t * kTP + 16 * b + col;
+            const uint32_t w = epi[kEpiVis + (16 * b + col) * 4 + wv] >> bit0;
+            word[b] = xl < npts ? w : 0u;
+            nx[b] = __uint_as_float(epi[kEpiNorm + 16 * b + col]);
+        }
+        float lim[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            lim[i] = fminf(ts[i], key_score(epi[kEpiThr + wave * 16 + 4 * quarter + i]));
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int x = int(pb) + t * kTP + 16 * b + col;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int q = q0 + 4 * quarter + i;
-                bool cand = false;
-                float sc = __builtin_inff();
-                const uint32_t vword = epi_vis[2 * (wave * 16 + 4 * quarter + i) + (b >> 1)];
-                if (xin && q < a.nq && ((vword >> (x & 31)) & 1u)) {
-                    sc = nxb - 2.0f * acc[b][i];
-                    cand = entry_before(sc, int(x), ts[i], ti[i]);
-                }
+                const float sc = nx[b] - 2.0f * acc[b][i];
+                const bool cand = ((word[b] >> i) & 1u) && sc <= lim[i];
                 const int rbase = (wave * 16 + 4 * quarter + i) * kTileList;
-                quarter_offer(cand, sc, int(x), lst_s + rbase, lst_i + rbase, ts[i], ti[i]);
+                quarter_offer(cand, sc, x, lst_s + rbase, lst_i + rbase, ts[i], ti[i]);
+                lim[i] = fminf(lim[i], ts[i]);
             }
         }
+        // publish full lists' worst scores as bounds for the other splits
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = q0 + 4 * quarter + i;
+            const float g = key_score(epi[kEpiThr + wave * 16 + 4 * quarter + i]);
+            if (col == 0 && q < a.nq && ts[i] < g) atomicMin(a.gthr + q, score_key(ts[i]));
+        }
     }
+    __builtin_amdgcn_s_waitcnt(kWaitVm(0));
     // the 48 best of each query in this split
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -273,17 +398,52 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
 
 }  // namespace
 
-// Opened leaves -> visited bitmap of one query, written to vis[q][0 .. vw).
-__global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
-    extern __shared__ uint32_t smem[];
-    uint32_t* bm = smem;                                   // [vw]
-    const int q = blockIdx.x;
-    for (int64_t i = threadIdx.x; i < a.vw; i += kExpandThreads) bm[i] = 0u;
+// Opened leaves, query-major words -> per-leaf rows of query bits.  One
+// workgroup of 32 cw threads per (leaf word f, query chunk): thread i reads
+// query (chunk 32 cw + i)'s word f (32 leaves); each wave turns its 64
+// queries x 32 leaves into 32 leaves x 2 words with ballots; the 32 rows of
+// cw words are written whole.
+__global__ __launch_bounds__(1024) void k_open_transpose(ExpandArgs a) {
+    __shared__ uint32_t tile[32 * 32];
+    const int64_t f = blockIdx.x;
+    const int chunk = blockIdx.y;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int q = chunk * 32 * a.cw + int(threadIdx.x);
+    const uint32_t bits = q < a.nq ? a.leafbits[f * a.nq + q] : 0u;
+    if (f == 0 && q < a.nq) a.gthr[q] = 0xFF800000u;   // bound +inf
+    uint32_t mine = 0;
+#pragma unroll
+    for (int x = 0; x < 32; ++x) {
+        const uint64_t bal = __ballot((bits >> x) & 1u);
+        if (lane == x) mine = uint32_t(bal);
+        if (lane == 32 + x) mine = uint32_t(bal >> 32);
+    }
+    tile[(lane & 31) * a.cw + 2 * wave + (lane >> 5)] = mine;
     __syncthreads();
-    expand_opened_leaves(bm, a.leafbits, q, a.nq, a.m, a.W, a.H, a.permp, a.pp, threadIdx.x,
-                         kExpandThreads);
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < a.vw; i += kExpandThreads) a.vis[int64_t(q) * a.vw + i] = bm[i];
+    const int leaf = int(threadIdx.x) / a.cw, word = int(threadIdx.x) % a.cw;
+    const int64_t nleaf = int64_t{1} << a.H;
+    const int64_t tree = f / a.W;
+    const int64_t lt = (f % a.W) * 32 + leaf;
+    if (lt < nleaf)
+        a.openT[((int64_t(chunk) * a.m + tree) * nleaf + lt) * a.cw + word] = tile[leaf * a.cw + word];
+}
+
+// Point-major candidate sets: row x of chunk c is the OR over the trees of
+// the rows of the leaves holding x.  Thread (x, w) of a 256-thread group
+// covers 256 / cw points.
+__global__ __launch_bounds__(256) void k_expand_points(ExpandArgs a) {
+    const int per = 256 / a.cw;
+    const int64_t x = int64_t(blockIdx.x) * per + threadIdx.x / a.cw;
+    const int w = int(threadIdx.x) % a.cw;
+    const int chunk = blockIdx.y;
+    if (x >= a.n) return;
+    const int64_t rows = int64_t(a.m) << a.H;
+    const uint32_t* op = a.openT + int64_t(chunk) * rows * a.cw + w;
+    const uint32_t* lf = a.leafof + x * a.m;
+    uint32_t v = 0;
+    for (int j = 0; j < a.m; ++j) v |= op[int64_t(lf[j]) * a.cw];
+    a.visT[(int64_t(chunk) * a.n + x) * a.cw + w] = v;
 }
 
 // Best kk over the splits' lists, then the final ranking of the query.
@@ -323,28 +483,30 @@ __global__ __launch_bounds__(512) void k_merge_rerank(MergeArgs a) {
                  a.ids, a.dists);
 }
 
-size_t expand_lds_bytes(int64_t vw) { return size_t(vw) * 4; }
-
 hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeArgs& m,
                             hipStream_t st, hipEvent_t* ev) {
-    const size_t lds = expand_lds_bytes(e.vw);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_expand),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    const int64_t words = int64_t(e.m) * e.W;
+    if (e.cw < 4 || e.cw > 32 || (e.cw & (e.cw - 1)) || t.cw != e.cw) return hipErrorInvalidValue;
+    if (t.split_pts % kTP || t.split_pts * t.ld16 * 2 >= (int64_t{1} << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_open_transpose, dim3(unsigned(words), unsigned(e.nchunk)), dim3(32 * e.cw),
+                       0, st, e);
+    hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_expand, dim3(e.nq), dim3(kExpandThreads), lds, st, e);
+    const int per = 256 / e.cw;
+    hipLaunchKernelGGL(k_expand_points, dim3(unsigned((e.n + per - 1) / per), unsigned(e.nchunk)),
+                       dim3(256), 0, st, e);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
     dim3 grid((t.nq + kTQ - 1) / kTQ, t.nsplit);
     const int ks = int(t.ld16 / 32);
-    if (ks <= 4) hipLaunchKernelGGL(k_tile_bf16<4>, grid, dim3(kTThreads), 0, st, t);
-    else if (ks <= 8) hipLaunchKernelGGL(k_tile_bf16<8>, grid, dim3(kTThreads), 0, st, t);
-    else if (ks <= 16) hipLaunchKernelGGL(k_tile_bf16<16>, grid, dim3(kTThreads), 0, st, t);
-    else if (ks <= 24) hipLaunchKernelGGL(k_tile_bf16<24>, grid, dim3(kTThreads), 0, st, t);
-    else if (ks <= 30) hipLaunchKernelGGL(k_tile_bf16<30>, grid, dim3(kTThreads), 0, st, t);
-    else if (ks <= 32) hipLaunchKernelGGL(k_tile_bf16<32>, grid, dim3(kTThreads), 0, st, t);
+#define GF_TILE(KS) \
+    else if (ks <= KS) hipLaunchKernelGGL(k_tile_bf16<KS>, grid, dim3(kTThreads), 0, st, t);
+    if (ks < 1) return hipErrorInvalidValue;
+    GF_TILE(4) GF_TILE(8) GF_TILE(12) GF_TILE(16) GF_TILE(20) GF_TILE(24) GF_TILE(28) GF_TILE(30)
+    GF_TILE(32)
     else return hipErrorInvalidValue;
+#undef GF_TILE
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
