@@ -44,8 +44,14 @@ __device__ __forceinline__ int digit_shift(int pass) { return 56 - kDigitBits * 
 // Walk one tree for the 64 queries of this wavefront.  Calls
 // fn(chunk, eff[32], entry[32]) for every group of 2^CH consecutive leaves
 // (leaf index = chunk * 2^CH + x).  qd: LDS [t][64] query coordinates on the
-// split set D; pe/pn: LDS [(H-CH+1)][64] path state.
-template <int CH, class Fn>
+// split set D; pe/pn: LDS [(H-CH+1)][64] path state.  With ENTRY false the
+// entry nodes are not tracked (en[] stays undefined).
+//
+// Child eff from the parent's eff e >= 0 and gap g: the left child is the far
+// one exactly when g >= 0, so its eff is max(e, g) (which is e when g < 0),
+// and the right child's is max(e, -g).  Such a value may be -0 where the true
+// eff is 0; keys use the eff bits without the sign bit.
+template <int CH, bool ENTRY, class Fn>
 __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H,
                                           uint32_t chunk_begin, uint32_t chunk_end,
                                           const float* qd, float* pe, uint32_t* pn, Fn&& fn) {
@@ -58,22 +64,21 @@ __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H
         int h0 = (c == chunk_begin) ? 0 : (U - 1 - __builtin_ctz(c));
         if (c == chunk_begin) {
             pe[lane] = 0.0f;
-            pn[lane] = 0u;
+            if (ENTRY) pn[lane] = 0u;
         }
         for (int h = h0; h < U; ++h) {
             const uint32_t v = ((1u << h) - 1u) + (c >> (U - h));
             const uint2 nd = nodes[v];
             const float g = qd[nd.y * kWave + lane] - __uint_as_float(nd.x);
             const bool go_right = (c >> (U - 1 - h)) & 1u;
-            const bool near_right = !(g < 0.0f);
-            float e = pe[h * kWave + lane];
-            uint32_t en = pn[h * kWave + lane];
-            if (go_right != near_right) {
-                e = fmaxf(e, fabsf(g));
-                en = 2u * v + 1u + (go_right ? 1u : 0u);
+            const float e = pe[h * kWave + lane];
+            pe[(h + 1) * kWave + lane] = go_right ? fmaxf(e, -g) : fmaxf(e, g);
+            if (ENTRY) {
+                const bool near_right = !(g < 0.0f);
+                uint32_t en = pn[h * kWave + lane];
+                if (go_right != near_right) en = 2u * v + 1u + (go_right ? 1u : 0u);
+                pn[(h + 1) * kWave + lane] = en;
             }
-            pe[(h + 1) * kWave + lane] = e;
-            pn[(h + 1) * kWave + lane] = en;
         }
         // Chunk subtree: lane i < NI fetches its i-th node (breadth-first).
         uint32_t mval = 0, mslot = 0;
@@ -88,7 +93,7 @@ __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H
         float ef[NL];
         uint32_t en[NL];
         ef[0] = pe[U * kWave + lane];
-        en[0] = pn[U * kWave + lane];
+        if (ENTRY) en[0] = pn[U * kWave + lane];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
 #pragma unroll
@@ -97,23 +102,26 @@ __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H
                 const float val = __uint_as_float(__builtin_amdgcn_readlane(mval, i));
                 const uint32_t slot = __builtin_amdgcn_readlane(mslot, i);
                 const float g = qd[slot * kWave + lane] - val;
-                const bool near_right = !(g < 0.0f);
                 const float e = ef[x];
-                const uint32_t n = en[x];
-                const float efar = fmaxf(e, fabsf(g));
-                const uint32_t v = ((1u << (U + j)) - 1u) + (c << j) + uint32_t(x);
-                ef[2 * x] = near_right ? efar : e;
-                en[2 * x] = near_right ? 2u * v + 1u : n;
-                ef[2 * x + 1] = near_right ? e : efar;
-                en[2 * x + 1] = near_right ? n : 2u * v + 2u;
+                ef[2 * x] = fmaxf(e, g);
+                ef[2 * x + 1] = fmaxf(e, -g);
+                if (ENTRY) {
+                    const bool near_right = !(g < 0.0f);
+                    const uint32_t n = en[x];
+                    const uint32_t v = ((1u << (U + j)) - 1u) + (c << j) + uint32_t(x);
+                    en[2 * x] = near_right ? 2u * v + 1u : n;
+                    en[2 * x + 1] = near_right ? n : 2u * v + 2u;
+                }
             }
         }
         fn(c, ef, en);
     }
 }
 
+__device__ __forceinline__ uint32_t eff_bits(float eff) { return __float_as_uint(eff) & 0x7FFFFFFFu; }
+
 __device__ __forceinline__ uint64_t leaf_key(float eff, uint32_t tree, uint32_t entry) {
-    return (uint64_t(__float_as_uint(eff)) << 32) | (uint64_t(tree) << 24) | uint64_t(entry);
+    return (uint64_t(eff_bits(eff)) << 32) | (uint64_t(tree) << 24) | uint64_t(entry);
 }
 
 // Shared setup of a walk kernel: stage q_D of the 64 queries into LDS.
@@ -145,18 +153,35 @@ __global__ __launch_bounds__(64) void k_select_hist(SelectArgs a, int pass) {
     const uint32_t cb = blockIdx.z * per;
     const uint32_t ce = min(nchunks, cb + per);
     const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
-    walk_tree<CH>(nodes, a.H, cb, ce, qd, pe, pn,
-                  [&](uint32_t, const float* ef, const uint32_t* en) {
-                      if (!active) return;
+    auto count = [&](uint32_t dgt) {
+        atomicAdd(&hist[(dgt >> 1) * kWave + lane], (dgt & 1u) ? 65536u : 1u);
+    };
+    if (shift >= 32) {
+        // the digit and the fixed prefix lie within the eff bits
+        const int s32 = shift - 32;
+        const uint32_t pfx = uint32_t(prefix);
+        walk_tree<CH, false>(nodes, a.H, cb, ce, qd, pe, pn,
+                             [&](uint32_t, const float* ef, const uint32_t*) {
+                                 if (!active) return;
 #pragma unroll
-                      for (int x = 0; x < (1 << CH); ++x) {
-                          const uint64_t K = leaf_key(ef[x], tree, en[x]);
-                          if ((K >> (shift + kDigitBits)) == prefix) {
-                              const uint32_t dgt = uint32_t(K >> shift) & (kBins - 1);
-                              atomicAdd(&hist[(dgt >> 1) * kWave + lane], (dgt & 1u) ? 65536u : 1u);
-                          }
-                      }
-                  });
+                                 for (int x = 0; x < (1 << CH); ++x) {
+                                     const uint32_t E = eff_bits(ef[x]);
+                                     if ((E >> (s32 + kDigitBits)) == pfx)
+                                         count((E >> s32) & (kBins - 1));
+                                 }
+                             });
+    } else {
+        walk_tree<CH, true>(nodes, a.H, cb, ce, qd, pe, pn,
+                            [&](uint32_t, const float* ef, const uint32_t* en) {
+                                if (!active) return;
+#pragma unroll
+                                for (int x = 0; x < (1 << CH); ++x) {
+                                    const uint64_t K = leaf_key(ef[x], tree, en[x]);
+                                    if ((K >> (shift + kDigitBits)) == prefix)
+                                        count(uint32_t(K >> shift) & (kBins - 1));
+                                }
+                            });
+    }
     if (!active) return;
     const int slice = int(tree) * int(gridDim.z) + int(blockIdx.z);
     uint32_t* gh = a.hist + (int64_t(q) * a.nslice + slice) * kBins;
@@ -191,7 +216,7 @@ __global__ __launch_bounds__(64) void k_select_collect(SelectArgs a) {
     // this slice's share of the bin starts at coff[q][slice]
     const int slice = int(tree) * int(gridDim.z) + int(blockIdx.z);
     uint32_t pos = (q < a.nq && st.status == kSelReady) ? a.coff[int64_t(q) * a.nslice + slice] : 0u;
-    walk_tree<CH>(nodes, a.H, cb, ce, qd, pe, pn,
+    walk_tree<CH, true>(nodes, a.H, cb, ce, qd, pe, pn,
                   [&](uint32_t c, const float* ef, const uint32_t* en) {
                       if (q >= a.nq) return;
                       uint32_t bits = 0;

@@ -170,6 +170,12 @@ __device__ __forceinline__ void dma_4(const void* g, uint32_t lds) {
     asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off"
                  :: "v"(g), "{m0}"(__builtin_amdgcn_readfirstlane(lds)) : "memory");
 }
+// Device-scope variant (sc1: served by L2, not a CU cache) for values that
+// other workgroups update with atomics during the kernel.
+__device__ __forceinline__ void dma_4_dev(const void* g, uint32_t lds) {
+    asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off sc1"
+                 :: "v"(g), "{m0}"(__builtin_amdgcn_readfirstlane(lds)) : "memory");
+}
 
 // KSTEPS k steps of 32 (the row length rounded up; steps past the row have
 // zero A operands), in KSTEPS / 4 rounded up stages of 128 per tile.
@@ -280,7 +286,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             dma_4(a.norm16 + pb + xc, epi0 + 4u * kEpiNorm);
         } else if (wave < 4) {
             const int qq = blockIdx.x * kTQ + (wave - 2) * kWave + lane;
-            dma_4(a.gthr + (qq < a.nq ? qq : 0), epi0 + 4u * (kEpiThr + (wave - 2) * kWave));
+            dma_4_dev(a.gthr + (qq < a.nq ? qq : 0), epi0 + 4u * (kEpiThr + (wave - 2) * kWave));
         }
     };
     set_rows();
@@ -311,19 +317,31 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             if (it < ntile) issue_next();
             if (c == 0) issue_epi(t);
             const uint16_t* xb = xs + buf * (kStageBytes / 2);
+            // B fragments run two k steps ahead of the MFMAs that use them
+            constexpr int kSteps = kKS / 32;
+            uint4 v[2][4];
 #pragma unroll
-            for (int s = 0; s < kKS / 32; ++s) {
-                const int S = c * (kKS / 32) + s;
-                if (S < KSTEPS) {
-                    uint4 v[4];
+            for (int s = 0; s < 2; ++s)
+                if (c * kSteps + s < KSTEPS)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        v[b] = *reinterpret_cast<const uint4*>(xb + ldsel[s] + 2048 * b);
+                        v[s][b] = *reinterpret_cast<const uint4*>(xb + ldsel[s] + 2048 * b);
+            // keep the scheduler from sinking the reads down to their uses
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < kSteps; ++s) {
+                const int S = c * kSteps + s;
+                if (S < KSTEPS) {
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
                         acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            qa[S], __builtin_bit_cast(bf16x8, v[b]), acc[b], 0, 0, 0);
+                            qa[S], __builtin_bit_cast(bf16x8, v[s & 1][b]), acc[b], 0, 0, 0);
+                    if (s + 2 < kSteps && S + 2 < KSTEPS)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            v[s & 1][b] = *reinterpret_cast<const uint4*>(xb + ldsel[s + 2] + 2048 * b);
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
             buf = (buf + 1) & (kNBuf - 1);
             --left;
@@ -347,36 +365,45 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         // all splits, so nothing it excludes can be in the final lists); the
         // insertion re-checks the exact (score, id) order.
         uint32_t word[4];
-        float nx[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int xl = t * kTP + 16 * b + col;
             const uint32_t w = epi[kEpiVis + (16 * b + col) * 4 + wv] >> bit0;
             word[b] = xl < npts ? w : 0u;
-            nx[b] = __uint_as_float(epi[kEpiNorm + 16 * b + col]);
+            const float nx = __uint_as_float(epi[kEpiNorm + 16 * b + col]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[b][i] = nx - 2.0f * acc[b][i];   // scores
         }
-        float lim[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            lim[i] = fminf(ts[i], key_score(epi[kEpiThr + wave * 16 + 4 * quarter + i]));
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int x = int(pb) + t * kTP + 16 * b + col;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float sc = nx[b] - 2.0f * acc[b][i];
-                const bool cand = ((word[b] >> i) & 1u) && sc <= lim[i];
-                const int rbase = (wave * 16 + 4 * quarter + i) * kTileList;
-                quarter_offer(cand, sc, x, lst_s + rbase, lst_i + rbase, ts[i], ti[i]);
-                lim[i] = fminf(lim[i], ts[i]);
-            }
-        }
-        // publish full lists' worst scores as bounds for the other splits
+        float lim[4], bm[4];
+        bool any = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int q = q0 + 4 * quarter + i;
-            const float g = key_score(epi[kEpiThr + wave * 16 + 4 * quarter + i]);
-            if (col == 0 && q < a.nq && ts[i] < g) atomicMin(a.gthr + q, score_key(ts[i]));
+            lim[i] = fminf(ts[i], key_score(epi[kEpiThr + wave * 16 + 4 * quarter + i]));
+            bm[i] = __builtin_inff();
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if ((word[b] >> i) & 1u) bm[i] = fminf(bm[i], acc[b][i]);
+            any = any || bm[i] <= lim[i];
+        }
+        // Only queries with a candidate at or below their limit in this tile
+        // go through the (rare) insertions, one score at a time.
+        if (__ballot(any)) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (!__ballot(bm[i] <= lim[i])) continue;
+                const int rbase = (wave * 16 + 4 * quarter + i) * kTileList;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int x = int(pb) + t * kTP + 16 * b + col;
+                    const bool cand = ((word[b] >> i) & 1u) && acc[b][i] <= lim[i];
+                    quarter_offer(cand, acc[b][i], x, lst_s + rbase, lst_i + rbase, ts[i], ti[i]);
+                    lim[i] = fminf(lim[i], ts[i]);
+                }
+                // publish a full list's worst score as a bound for the other splits
+                const int q = q0 + 4 * quarter + i;
+                const float g = key_score(epi[kEpiThr + wave * 16 + 4 * quarter + i]);
+                if (col == 0 && q < a.nq && ts[i] < g) atomicMin(a.gthr + q, score_key(ts[i]));
+            }
         }
     }
     __builtin_amdgcn_s_waitcnt(kWaitVm(0));
@@ -411,7 +438,7 @@ __global__ __launch_bounds__(1024) void k_open_transpose(ExpandArgs a) {
     const int wave = threadIdx.x / kWave;
     const int q = chunk * 32 * a.cw + int(threadIdx.x);
     const uint32_t bits = q < a.nq ? a.leafbits[f * a.nq + q] : 0u;
-    if (f == 0 && q < a.nq) a.gthr[q] = 0xFF800000u;   // bound +inf
+    if (f == 0 && q < a.nq) a.gthr[q] = 0xFF800000u;   // shared bound +inf
     uint32_t mine = 0;
 #pragma unroll
     for (int x = 0; x < 32; ++x) {
@@ -441,8 +468,18 @@ __global__ __launch_bounds__(256) void k_expand_points(ExpandArgs a) {
     const int64_t rows = int64_t(a.m) << a.H;
     const uint32_t* op = a.openT + int64_t(chunk) * rows * a.cw + w;
     const uint32_t* lf = a.leafof + x * a.m;
+    // eight trees at a time: the leaf indices, then the rows, all in flight
     uint32_t v = 0;
-    for (int j = 0; j < a.m; ++j) v |= op[int64_t(lf[j]) * a.cw];
+    for (int j0 = 0; j0 < a.m; j0 += 8) {
+        uint32_t r[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = j0 + j < a.m ? lf[j0 + j] : 0u;
+        uint32_t o[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = j0 + j < a.m ? op[int64_t(r[j]) * a.cw] : 0u;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v |= o[j];
+    }
     a.visT[(int64_t(chunk) * a.n + x) * a.cw + w] = v;
 }
 
