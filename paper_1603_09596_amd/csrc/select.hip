@@ -131,27 +131,44 @@ __device__ __forceinline__ void stage_query_dims(const SelectArgs& a, int q, flo
         qd[j * kWave + lane] = (q < a.nq) ? a.Q[int64_t(q) * a.ldq + a.D[j]] : 0.0f;
 }
 
+// The four waves of a walk workgroup serve the same 64 queries (lane =
+// query) and split the slice's chunks into four consecutive ranges; they
+// share the staged query coordinates and the histogram (or the collect
+// counters), each keeping its own path state.
+constexpr int kSelWaves = 4;
+constexpr int kSelThreads = kSelWaves * kWave;
+
+__device__ __forceinline__ void wave_chunks(uint32_t nchunks, uint32_t& cb, uint32_t& ce) {
+    const uint32_t per = (nchunks + gridDim.z - 1) / gridDim.z;
+    const uint32_t zb = blockIdx.z * per;
+    const uint32_t ze = min(nchunks, zb + per);
+    const uint32_t wper = (ze > zb) ? (ze - zb + kSelWaves - 1) / kSelWaves : 0u;
+    const uint32_t w = threadIdx.x / kWave;
+    cb = min(ze, zb + w * wper);
+    ce = min(ze, cb + wper);
+}
+
 template <int CH>
-__global__ __launch_bounds__(64) void k_select_hist(SelectArgs a, int pass) {
+__global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a, int pass) {
     extern __shared__ uint32_t smem[];
-    float* qd = reinterpret_cast<float*>(smem);                 // [t][64]
-    float* pe = qd + a.t * kWave;                               // [U+1][64]
-    uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (a.H - CH + 1) * kWave);
-    uint32_t* hist = pn + (a.H - CH + 1) * kWave;               // [64][64] packed u16 pairs
-    const int lane = threadIdx.x;
+    const int U = a.H - CH;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    float* qd = reinterpret_cast<float*>(smem);                          // [t][64]
+    uint32_t* hist = reinterpret_cast<uint32_t*>(qd + a.t * kWave);      // [64][64] packed u16 pairs
+    float* pe = reinterpret_cast<float*>(hist + (kBins / 2) * kWave) + wave * 2 * (U + 1) * kWave;
+    uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (U + 1) * kWave);   // [U+1][64] per wave
     const int q = blockIdx.x * kWave + lane;
     const uint32_t tree = blockIdx.y;
     const SelState st = (q < a.nq) ? a.state[q] : SelState{};
     const bool active = (q < a.nq) && st.status == kSelSearching;
-    if (!__any(active)) return;
-    stage_query_dims(a, q, qd);
-    for (int b = 0; b < kBins / 2; ++b) hist[b * kWave + lane] = 0u;
+    if (!__any(active)) return;   // the same for every wave of the workgroup
+    if (wave == 0) stage_query_dims(a, q, qd);
+    for (int b = wave; b < kBins / 2; b += kSelWaves) hist[b * kWave + lane] = 0u;
+    __syncthreads();
     const int shift = digit_shift(pass);
     const uint64_t prefix = st.prefix;
-    const uint32_t nchunks = 1u << (a.H - CH);
-    const uint32_t per = (nchunks + gridDim.z - 1) / gridDim.z;
-    const uint32_t cb = blockIdx.z * per;
-    const uint32_t ce = min(nchunks, cb + per);
+    uint32_t cb, ce;
+    wave_chunks(1u << U, cb, ce);
     const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
     auto count = [&](uint32_t dgt) {
         atomicAdd(&hist[(dgt >> 1) * kWave + lane], (dgt & 1u) ? 65536u : 1u);
@@ -182,10 +199,11 @@ __global__ __launch_bounds__(64) void k_select_hist(SelectArgs a, int pass) {
                                 }
                             });
     }
+    __syncthreads();
     if (!active) return;
     const int slice = int(tree) * int(gridDim.z) + int(blockIdx.z);
     uint32_t* gh = a.hist + (int64_t(q) * a.nslice + slice) * kBins;
-    for (int b = 0; b < kBins / 2; ++b) {
+    for (int b = wave; b < kBins / 2; b += kSelWaves) {
         const uint32_t w = hist[b * kWave + lane];
         gh[2 * b] = w & 0xFFFFu;
         gh[2 * b + 1] = w >> 16;
@@ -193,49 +211,53 @@ __global__ __launch_bounds__(64) void k_select_hist(SelectArgs a, int pass) {
 }
 
 template <int CH>
-__global__ __launch_bounds__(64) void k_select_collect(SelectArgs a) {
+__global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
     extern __shared__ uint32_t smem[];
-    float* qd = reinterpret_cast<float*>(smem);
-    float* pe = qd + a.t * kWave;
-    uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (a.H - CH + 1) * kWave);
-    const int lane = threadIdx.x;
+    const int U = a.H - CH;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    float* qd = reinterpret_cast<float*>(smem);                          // [t][64]
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(qd + a.t * kWave);       // [64] next collect slot
+    float* pe = reinterpret_cast<float*>(cnt + kWave) + wave * 2 * (U + 1) * kWave;
+    uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (U + 1) * kWave);
     const int q = blockIdx.x * kWave + lane;
     const uint32_t tree = blockIdx.y;
     const SelState st = (q < a.nq) ? a.state[q] : SelState{};
-    stage_query_dims(a, q, qd);
     const bool all = st.status == kSelAll;
     // Bin [lo, hi): the key range still undecided after the last pass.
     const int shift = digit_shift(int(st.pass) - 1);
     const uint64_t lo = st.pass ? (st.prefix << shift) : 0ull;
     const uint64_t hi = st.pass ? ((st.prefix + 1ull) << shift) : 0ull;
-    const uint32_t nchunks = 1u << (a.H - CH);
-    const uint32_t per = (nchunks + gridDim.z - 1) / gridDim.z;
-    const uint32_t cb = blockIdx.z * per;
-    const uint32_t ce = min(nchunks, cb + per);
-    const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
-    // this slice's share of the bin starts at coff[q][slice]
+    // this slice's share of the bin starts at coff[q][slice]; the waves take
+    // slots from a shared counter (the order of the collected keys is free)
     const int slice = int(tree) * int(gridDim.z) + int(blockIdx.z);
-    uint32_t pos = (q < a.nq && st.status == kSelReady) ? a.coff[int64_t(q) * a.nslice + slice] : 0u;
+    if (wave == 0) {
+        stage_query_dims(a, q, qd);
+        cnt[lane] = (q < a.nq && st.status == kSelReady) ? a.coff[int64_t(q) * a.nslice + slice] : 0u;
+    }
+    __syncthreads();
+    uint32_t cb, ce;
+    wave_chunks(1u << U, cb, ce);
+    const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
     walk_tree<CH, true>(nodes, a.H, cb, ce, qd, pe, pn,
-                  [&](uint32_t c, const float* ef, const uint32_t* en) {
-                      if (q >= a.nq) return;
-                      uint32_t bits = 0;
+                        [&](uint32_t c, const float* ef, const uint32_t* en) {
+                            if (q >= a.nq) return;
+                            uint32_t bits = 0;
 #pragma unroll
-                      for (int x = 0; x < (1 << CH); ++x) {
-                          const uint64_t K = leaf_key(ef[x], tree, en[x]);
-                          if (all || K < lo) {
-                              bits |= 1u << x;
-                          } else if (K < hi) {
-                              if (pos < uint32_t(kCollectCap)) {
-                                  const int64_t o = int64_t(q) * kCollectCap + pos;
-                                  a.ckey[o] = K;
-                                  a.ccode[o] = (tree << 24) | ((c << CH) + uint32_t(x));
-                              }
-                              ++pos;
-                          }
-                      }
-                      a.leafbits[(int64_t(tree) * a.W + c) * a.nq + q] = bits;
-                  });
+                            for (int x = 0; x < (1 << CH); ++x) {
+                                const uint64_t K = leaf_key(ef[x], tree, en[x]);
+                                if (all || K < lo) {
+                                    bits |= 1u << x;
+                                } else if (K < hi) {
+                                    const uint32_t pos = atomicAdd(&cnt[lane], 1u);
+                                    if (pos < uint32_t(kCollectCap)) {
+                                        const int64_t o = int64_t(q) * kCollectCap + pos;
+                                        a.ckey[o] = K;
+                                        a.ccode[o] = (tree << 24) | ((c << CH) + uint32_t(x));
+                                    }
+                                }
+                            }
+                            a.leafbits[(int64_t(tree) * a.W + c) * a.nq + q] = bits;
+                        });
 }
 
 }  // namespace
@@ -358,17 +380,25 @@ int select_slices_per_tree(int H) {
 hipError_t launch_select_walk(const SelectArgs& a, int pass, bool collect, hipStream_t st) {
     const int CH = a.H < 5 ? a.H : 5;
     const int U = a.H - CH;
-    const size_t lds = size_t(a.t) * kWave * 4 + size_t(U + 1) * kWave * 8 +
-                       (collect ? 0 : size_t(kBins / 2) * kWave * 4);
+    const size_t lds = size_t(a.t) * kWave * 4 + (collect ? size_t(kWave) * 4 : size_t(kBins / 2) * kWave * 4) +
+                       size_t(kSelWaves) * 2 * (U + 1) * kWave * 4;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int zsplit = select_slices_per_tree(a.H);
     if (a.nslice != a.m * zsplit) return hipErrorInvalidValue;
     dim3 grid((a.nq + kWave - 1) / kWave, a.m, zsplit);
-#define GF_WALK(CHV)                                                                       \
-    case CHV:                                                                              \
-        if (collect)                                                                       \
-            hipLaunchKernelGGL(k_select_collect<CHV>, grid, dim3(kWave), lds, st, a);      \
-        else                                                                               \
-            hipLaunchKernelGGL(k_select_hist<CHV>, grid, dim3(kWave), lds, st, a, pass);   \
+#define GF_WALK(CHV)                                                                         \
+    case CHV:                                                                                \
+        if (collect) {                                                                       \
+            if (lds > 65536)                                                                 \
+                (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select_collect<CHV>), \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
+            hipLaunchKernelGGL(k_select_collect<CHV>, grid, dim3(kSelThreads), lds, st, a);  \
+        } else {                                                                             \
+            if (lds > 65536)                                                                 \
+                (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select_hist<CHV>), \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
+            hipLaunchKernelGGL(k_select_hist<CHV>, grid, dim3(kSelThreads), lds, st, a, pass); \
+        }                                                                                    \
         break;
     switch (CH) {
         GF_WALK(0) GF_WALK(1) GF_WALK(2) GF_WALK(3) GF_WALK(4) GF_WALK(5)
