@@ -121,10 +121,13 @@ __device__ __forceinline__ void quarter_offer(bool cand, float sc, int id, float
 // s_waitcnt immediates (gfx9 encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] at 15:14)
 constexpr int kWaitVm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
 
-constexpr int kKS = 128;                               // k (bf16 elements) per pipeline stage
-constexpr int kNBuf = 4;                               // LDS stages (prefetch distance kNBuf - 1)
-constexpr int kStageBytes = kTP * kKS * 2;             // 64 rows x 256 B = 16 KB
-constexpr int kDmaPerWave = kStageBytes / 1024 / kTWaves;   // 1 KB per wave instruction -> 2
+constexpr int kKS = 256;                               // k (bf16 elements) per pipeline stage
+constexpr int kNBuf = 3;                               // LDS stages (prefetch distance kNBuf - 1)
+constexpr int kStageBytes = kTP * kKS * 2;             // 64 rows x 512 B = 32 KB
+constexpr int kUnits = kKS / 8;                        // 16-byte units per staged row
+constexpr int kRowsPerInst = kWave / kUnits;           // rows per 1 KB wave instruction
+constexpr int kDmaPerWave = kStageBytes / 1024 / kTWaves;   // 4
+static_assert(kRowsPerInst * kUnits == kWave && kDmaPerWave * kTWaves * 1024 == kStageBytes, "stage shape");
 // epilogue operands per tile (dwords): 4 candidate words per point, the
 // points' norms, the block's 128 shared thresholds
 constexpr int kEpiVis = 0, kEpiNorm = 4 * kTP, kEpiThr = 5 * kTP;
@@ -178,11 +181,12 @@ __device__ __forceinline__ void dma_4_dev(const void* g, uint32_t lds) {
 }
 
 // KSTEPS k steps of 32 (the row length rounded up; steps past the row have
-// zero A operands), in KSTEPS / 4 rounded up stages of 128 per tile.
+// zero A operands), in stages of kKS per tile.
 template <int KSTEPS>
 __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
-    constexpr int NC = (KSTEPS + 3) / 4;
-    // X stages: row r of a stage holds its 16 k units (16 B each) at
+    constexpr int kSteps = kKS / 32;
+    constexpr int NC = (KSTEPS + kSteps - 1) / kSteps;
+    // X stages: row r of a stage holds its kUnits k units (16 B each) at
     // positions unit ^ (r & 15), so the contiguous 1 KB writes of the direct
     // loads and the 16-row B-operand reads are both free of bank conflicts.
     __shared__ __attribute__((aligned(1024))) uint16_t xs[kNBuf * kStageBytes / 2];
@@ -234,22 +238,24 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     const int qc = (4 * int(blockIdx.x)) / a.cw, wo = (4 * int(blockIdx.x)) % a.cw;
     const uint32_t* visb = a.visT + (int64_t(qc) * a.n + pb) * a.cw + wo;
 
-    // This wave's share of a stage: rows 4 inst .. 4 inst + 3 for inst =
-    // wave, wave + kTWaves; lane l loads k unit (l & 15) ^ (row & 15) of row
-    // 4 inst + l / 16.  Rows past the split and k past the row are clamped to
-    // valid addresses; that data is never used.
+    // This wave's share of a stage: instructions inst = wave + kTWaves j each
+    // load rows kRowsPerInst inst ..; lane l loads k unit
+    // (l % kUnits) ^ (row & 15) of row kRowsPerInst inst + l / kUnits.  Rows
+    // past the split and k past the row are clamped to valid addresses; that
+    // data is never used.
     int drow[kDmaPerWave];
     uint32_t dk[kDmaPerWave], trow[kDmaPerWave];
 #pragma unroll
     for (int j = 0; j < kDmaPerWave; ++j) {
         const int inst = wave + kTWaves * j;
-        drow[j] = 4 * inst + (lane >> 4);
-        dk[j] = uint32_t(((lane & 15) ^ (drow[j] & 15)) * 8);
+        drow[j] = kRowsPerInst * inst + lane / kUnits;
+        dk[j] = uint32_t(((lane % kUnits) ^ (drow[j] & 15)) * 8);
     }
-    // B-operand LDS element offsets within a stage for k step s (block b adds 2048 b)
-    int ldsel[kKS / 32];
+    // B-operand LDS element offsets within a stage for k step s (block b
+    // adds 16 kKS b): row col, unit (4 s + quarter) ^ col
+    int ldsel[kSteps];
 #pragma unroll
-    for (int s = 0; s < kKS / 32; ++s) ldsel[s] = col * 128 + (((4 * s + quarter) ^ col) * 8);
+    for (int s = 0; s < kSteps; ++s) ldsel[s] = col * kKS + (((4 * s + quarter) ^ col) * 8);
 
     // issue cursor: the next stage to load is chunk ic of tile it, into ibuf
     int it = 0, ic = 0, ibuf = 0;
@@ -268,7 +274,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             const uint32_t koff = k < uint32_t(a.ld16) ? 2u * k : 0u;
             dma_16s(xbase, trow[j] + koff, dst + uint32_t(wave + kTWaves * j) * 1024u);
         }
-        ibuf = (ibuf + 1) & (kNBuf - 1);
+        ibuf = (ibuf + 1 == kNBuf) ? 0 : ibuf + 1;
         if (++ic == NC) {
             ic = 0;
             ++it;
@@ -307,10 +313,10 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             // many stages' worth completes the current stage for this wave,
             // and the barrier then covers every wave (and frees the previous
             // stage's buffer for reuse).
-            static_assert(kNBuf == 4, "wait immediates assume two stages in flight");
+            static_assert(kNBuf == 3 || kNBuf == 4, "wait immediates for one or two stages ahead");
             asm volatile("" ::: "memory");
-            if (left > 2) __builtin_amdgcn_s_waitcnt(kWaitVm(2 * kDmaPerWave));
-            else if (left == 2) __builtin_amdgcn_s_waitcnt(kWaitVm(kDmaPerWave));
+            if (kNBuf == 4 && left > 2) __builtin_amdgcn_s_waitcnt(kWaitVm(2 * kDmaPerWave));
+            else if (left >= 2) __builtin_amdgcn_s_waitcnt(kWaitVm(kDmaPerWave));
             else __builtin_amdgcn_s_waitcnt(kWaitVm(0));
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
@@ -318,14 +324,13 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             if (c == 0) issue_epi(t);
             const uint16_t* xb = xs + buf * (kStageBytes / 2);
             // B fragments run two k steps ahead of the MFMAs that use them
-            constexpr int kSteps = kKS / 32;
             uint4 v[2][4];
 #pragma unroll
             for (int s = 0; s < 2; ++s)
                 if (c * kSteps + s < KSTEPS)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        v[s][b] = *reinterpret_cast<const uint4*>(xb + ldsel[s] + 2048 * b);
+                        v[s][b] = *reinterpret_cast<const uint4*>(xb + ldsel[s] + 16 * kKS * b);
             // keep the scheduler from sinking the reads down to their uses
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -339,11 +344,11 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
                     if (s + 2 < kSteps && S + 2 < KSTEPS)
 #pragma unroll
                         for (int b = 0; b < 4; ++b)
-                            v[s & 1][b] = *reinterpret_cast<const uint4*>(xb + ldsel[s + 2] + 2048 * b);
+                            v[s & 1][b] = *reinterpret_cast<const uint4*>(xb + ldsel[s + 2] + 16 * kKS * b);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
-            buf = (buf + 1) & (kNBuf - 1);
+            buf = (buf + 1 == kNBuf) ? 0 : buf + 1;
             --left;
         }
         // The epilogue loads were issued at this tile's first stage, and the
