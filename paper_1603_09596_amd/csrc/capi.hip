@@ -107,14 +107,36 @@ struct TilePlan {
     int cw = 0, nchunk = 0;
 };
 
+// The tile kernel runs one workgroup per CU at a time, so the batch takes
+// ceil(qblocks * ns / CUs) rounds of 1/ns of the work each; among split
+// counts the one with the least such time wins, with a small charge per
+// split for its list (every split fills and merges its own per-query list).
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
 TilePlan tile_plan(const gf_forest* F, int nb) {
     TilePlan p;
     const int64_t qblocks = (nb + 127) / 128;
-    int64_t ns = (2048 + qblocks - 1) / qblocks;
     const int64_t tiles = (F->host.n + 63) / 64;
     const int64_t max_tiles = ((int64_t{1} << 31) - 1) / (int64_t(F->ld16) * 2 * 64);
-    if (ns > tiles) ns = tiles;
-    if (ns < 1) ns = 1;
+    const int64_t cus = device_cus();
+    int64_t ns = 1;
+    double best = 1e300;
+    for (int64_t s = 1; s <= std::min<int64_t>(tiles, 256); ++s) {
+        const double rounds = double((qblocks * s + cus - 1) / cus);
+        const double cost = rounds / double(s) + 0.002 * double(s);
+        if (cost < best) { best = cost; ns = s; }
+    }
     if ((tiles + ns - 1) / ns > max_tiles) ns = (tiles + max_tiles - 1) / max_tiles;
     p.split_pts = ((tiles + ns - 1) / ns) * 64;
     p.nsplit = int((F->host.n + p.split_pts - 1) / p.split_pts);
