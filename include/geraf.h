@@ -125,6 +125,49 @@ gf_status gf_query(const gf_forest *F, const float *Q, int64_t nq, int32_t k,
                    int32_t form, int32_t rerank, int32_t *ids, float *dists,
                    void *stream);
 
+/* One search request of a gf_query_multi call: the arguments of gf_query
+ * for one forest, with every buffer in device memory. */
+typedef struct gf_job {
+    const gf_forest *forest;
+    const float *Q;                    /* [nq][d] float32, device, finite */
+    int64_t nq;
+    int32_t k;                         /* 1..64 */
+    int32_t checks;                    /* >= 1, unless checks_per_query */
+    const int32_t *checks_per_query;   /* NULL or [nq] int32 >= 1, device */
+    double eps;                        /* >= 0 */
+    int32_t form;                      /* gf_form */
+    int32_t rerank;                    /* as for gf_query */
+    int32_t *ids;                      /* [nq][k] int32, device */
+    float *dists;                      /* [nq][k] float32, device */
+} gf_job;
+
+#define GF_MULTI_AUTOTUNE 1u  /* measure row vs tile path per (forest, form, batch size) once */
+#define GF_MULTI_EAGER 2u     /* launch kernel by kernel instead of one graph launch */
+
+/* Run many searches, over many forests of uneven n and d and with per-query
+ * budgets, as one launch (the batching the paper's Sec. 5 leaves for future
+ * work).  Every job gives the same results as gf_query with the same
+ * arguments and the same path; the path of each 16,384-query batch follows
+ * gf_query's rule, or with GF_MULTI_AUTOTUNE the faster of the two as
+ * measured on the first batch of each (forest, form, batch-size class,
+ * rerank), a choice the forest then keeps.
+ * All query rows are checked finite first (one readback for the call).  The
+ * launches of every batch are then captured into one HIP graph, which runs on
+ * `stream`.  The instantiated graph is kept (up to 16 of them, by least recent
+ * use) and launched again when a call repeats the same jobs, buffers and
+ * paths; freeing a forest drops the graphs that use it.
+ * All forests must live on the current device.  The call returns when the
+ * results are in place.  Calls on a forest wait for each other (the forest's
+ * workspace is shared).
+ * Errors: GF_EINVAL for bad arguments, host buffers, NaN/Inf in Q; GF_EHIP
+ * for HIP failures (nothing partially written is guaranteed then). */
+gf_status gf_query_multi(const gf_job *jobs, int32_t njobs, uint32_t flags, void *stream);
+
+/* Counters of the multi-index launch since the library was loaded: graphs
+ * captured, graph launches reused from an earlier identical call, path
+ * choices measured by the autotuner.  Any pointer may be NULL. */
+gf_status gf_multi_stats(int64_t *graphs_built, int64_t *graphs_reused, int64_t *tuned);
+
 /* The query path's intermediate sets, for parity checks:
  *   leaf_bits  [nq][m][W] uint32, W = max(1, 2^H / 32): bit (j % 32) of word
  *              j / 32 of tree i is set iff leaf j of tree i was opened;

@@ -6,7 +6,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -225,6 +228,7 @@ struct QueryJob {
     // outputs (host or device), any may be null
     int32_t* ids; float* dists; bool out_dev;
     uint32_t* leaf_bits; uint32_t* cand_bits; int64_t* ncand; bool trace_dev;
+    int path = -1;             // -1 by rule, 0 rows, 1 tile (when eligible)
 };
 
 // Whether a batch takes the tile path (BF16 scores of whole query blocks on
@@ -233,7 +237,16 @@ struct QueryJob {
 // path reads every candidate's row from HBM.  It pays off once the batch
 // fills 128-query blocks and each query's candidates are more than ~1/256
 // of the points.  GF_SCAN_PATH=rows|tile forces a path.
+bool tile_eligible(const gf_forest* F, const QueryJob& J) {
+    if (J.form != gf::kFormBF16 || J.leaf_bits || J.cand_bits || J.ncand) return false;
+    if (J.kk > gf::kTileList) return false;
+    if (F->ld16 > 1024) return false;
+    if (!gf::scan_supported(F->host.n, gf::kFormFP32, F->ld8)) return false;
+    return F->leafof != nullptr;
+}
+
 bool use_tile_path(const gf_forest* F, const QueryJob& J, int nb) {
+    if (J.path >= 0) return J.path == 1 && tile_eligible(F, J);
     if (J.form != gf::kFormBF16 || J.leaf_bits || J.cand_bits || J.ncand) return false;
     if (J.kk > gf::kTileList) return false;   // each split keeps kTileList entries per query
     if (F->ld16 > 1024) return false;
@@ -248,14 +261,135 @@ bool use_tile_path(const gf_forest* F, const QueryJob& J, int nb) {
     return cand_est * 256.0 >= double(F->host.n);
 }
 
-// Runs the whole query path for queries [q0, q0 + nb).
-gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStream_t st) {
+gf::SelectArgs make_select_args(const gf_forest* F, int nb, const Workspace& w, int64_t W) {
+    const gf::HostForest& h = F->host;
+    gf::SelectArgs sa{};
+    sa.Q = w.Qp; sa.ldq = F->ld32; sa.nq = nb; sa.m = h.m; sa.H = h.H; sa.t = h.t;
+    sa.n_internal = (int64_t{1} << h.H) - 1; sa.W = int(W); sa.nodes = F->nodes; sa.D = F->D;
+    sa.nslice = h.m * gf::select_slices_per_tree(h.H);
+    sa.state = w.state; sa.hist = w.hist; sa.coff = w.coff; sa.ckey = w.ckey;
+    sa.ccode = w.ccode; sa.leafbits = w.leafbits;
+    return sa;
+}
+
+// a2: the opened leaves.  With `more` a host flag ends the radix passes
+// early; without it every pass is launched.
+gf_status launch_selection(const gf_forest* F, const QueryJob& J, int nb, const Workspace& w,
+                           int64_t W, const int32_t* cpq, bool early_exit, hipStream_t st) {
+    const gf::SelectArgs sa = make_select_args(F, nb, w, W);
+    hipLaunchKernelGGL(gf::k_select_init, dim3((nb + 255) / 256), dim3(256), 0, st, sa,
+                       J.checks, cpq, J.eps);
+    GF_HIP(hipGetLastError());
+    for (int pass = 0; pass < gf::kMaxPasses; ++pass) {
+        if (early_exit) GF_HIP(hipMemsetAsync(w.flags + 1, 0, 4, st));
+        GF_HIP(gf::launch_select_walk(sa, pass, false, st));
+        hipLaunchKernelGGL(gf::k_select_pick, dim3(nb), dim3(128), 0, st, sa, pass, w.flags + 1);
+        GF_HIP(hipGetLastError());
+        if (early_exit) {
+            uint32_t more = 0;
+            GF_HIP(hipMemcpyAsync(&more, w.flags + 1, 4, hipMemcpyDeviceToHost, st));
+            GF_HIP(hipStreamSynchronize(st));
+            if (!more) break;
+        }
+    }
+    GF_HIP(gf::launch_select_walk(sa, 0, true, st));
+    hipLaunchKernelGGL(gf::k_select_finish, dim3(nb), dim3(256), 0, st, sa);
+    GF_HIP(hipGetLastError());
+    return GF_OK;
+}
+
+gf::ScanArgs make_scan_args(const gf_forest* F, const QueryJob& J, int64_t q0, int nb,
+                            const Workspace& w, int64_t W) {
+    const gf::HostForest& h = F->host;
+    gf::ScanArgs ca{};
+    ca.nq = nb; ca.k = J.k; ca.kk = J.kk; ca.n = h.n; ca.d = h.d; ca.m = h.m; ca.W = int(W); ca.H = h.H;
+    ca.leafbits = w.leafbits; ca.permp = F->permp; ca.pp = F->pp;
+    ca.Q = w.Qp; ca.ldq = F->ld32; ca.X32 = F->X32; ca.ld32 = F->ld32;
+    ca.X16 = F->X16; ca.ld16 = F->ld16; ca.norm16 = F->norm16;
+    ca.X8 = F->X8; ca.ld8 = F->ld8; ca.scale8 = F->scale8; ca.norm8 = F->norm8;
+    ca.Q16 = w.Q16; ca.Q8 = w.Q8; ca.qscale8 = w.qscale; ca.qnorm = w.qnorm;
+    ca.ids = J.out_dev && J.ids ? J.ids + q0 * J.k : w.ids;
+    ca.dists = J.out_dev && J.dists ? J.dists + q0 * J.k : w.dists;
+    return ca;
+}
+
+// a3-a6 on the tile path; ev (may be null) gets the expansion and tile marks.
+gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& w, int64_t W,
+                      const gf::ScanArgs& ca, hipStream_t st, hipEvent_t* ev) {
+    const gf::HostForest& h = F->host;
+    const TilePlan tp = tile_plan(F, nb);
+    gf::ExpandArgs ea{};
+    ea.nq = nb; ea.m = h.m; ea.W = int(W); ea.H = h.H; ea.n = h.n;
+    ea.cw = tp.cw; ea.nchunk = tp.nchunk;
+    ea.leafbits = w.leafbits; ea.leafof = F->leafof; ea.openT = w.openT; ea.visT = w.visT;
+    ea.gthr = w.gthr;
+    gf::TileArgs ta{};
+    ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.cw = tp.cw; ta.Q16 = w.Q16; ta.X16 = F->X16;
+    ta.norm16 = F->norm16; ta.visT = w.visT; ta.gthr = w.gthr; ta.nsplit = tp.nsplit;
+    ta.split_pts = tp.split_pts; ta.part_s = w.part_s; ta.part_i = w.part_i;
+    gf::MergeArgs ma{};
+    ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = tp.nsplit;
+    ma.part_s = w.part_s; ma.part_i = w.part_i; ma.Q = w.Qp; ma.ldq = F->ld32;
+    ma.X32 = F->X32; ma.ld32 = F->ld32; ma.ids = ca.ids; ma.dists = ca.dists;
+    GF_HIP(gf::launch_tile_path(ea, ta, ma, st, ev));
+    return GF_OK;
+}
+
+// The reduced query copies (BF16 / FP8 rows and norms) from the padded rows.
+gf_status launch_query_forms(const gf_forest* F, const QueryJob& J, int nb, const Workspace& w,
+                             hipStream_t st) {
+    const gf::HostForest& h = F->host;
+    if (J.form == gf::kFormBF16) {
+        hipLaunchKernelGGL(gf::k_to_bf16, dim3((nb + 3) / 4), dim3(256), 0, st, w.Qp, int64_t(nb),
+                           h.d, int64_t(F->ld32), w.Q16, int64_t(F->ld16), w.qnorm);
+        GF_HIP(hipGetLastError());
+    } else if (J.form == gf::kFormFP8) {
+        hipLaunchKernelGGL(gf::k_to_fp8, dim3((nb + 3) / 4), dim3(256), 0, st, w.Qp, int64_t(nb),
+                           h.d, int64_t(F->ld32), w.Q8, int64_t(F->ld8), w.qscale, w.qnorm);
+        GF_HIP(hipGetLastError());
+    }
+    return GF_OK;
+}
+
+// Graph-mode batch: device Q, budgets and outputs, queries already checked
+// finite; nothing waits on the host and no memset is issued, so every
+// launch can be captured into a graph.  The query rows are padded by a
+// kernel and all radix passes are launched (once each query's bin is
+// settled a pass finds no active query and its workgroups return at once).
+gf_status run_batch_graph(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStream_t st,
+                          const Workspace& w, bool tile, int64_t W) {
+    const gf::HostForest& h = F->host;
+    {
+        const int64_t tot = int64_t(nb) * F->ld32;
+        hipLaunchKernelGGL(gf::k_pad_rows, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st,
+                           J.Q + q0 * h.d, int64_t(nb), h.d, w.Qp, int64_t(F->ld32));
+        GF_HIP(hipGetLastError());
+    }
+    gf_status s = launch_query_forms(F, J, nb, w, st);
+    if (s != GF_OK) return s;
+    const int32_t* cpq = nullptr;
+    if (J.cpq) {
+        GF_HIP(hipMemcpyAsync(w.cpq, J.cpq + q0, size_t(nb) * 4, hipMemcpyDeviceToDevice, st));
+        cpq = w.cpq;
+    }
+    s = launch_selection(F, J, nb, w, W, cpq, false, st);
+    if (s != GF_OK) return s;
+    const gf::ScanArgs ca = make_scan_args(F, J, q0, nb, w, W);
+    if (tile) return launch_tile(F, J, nb, w, W, ca, st, nullptr);
+    GF_HIP(gf::launch_scan(ca, J.form, st));
+    return GF_OK;
+}
+
+// Runs the whole query path for queries [q0, q0 + nb); graph mode as above.
+gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStream_t st,
+                    bool graph = false) {
     const gf::HostForest& h = F->host;
     Workspace w;
     const bool tile = use_tile_path(F, J, nb);
     gf_status s = get_workspace(F, nb, J.k, J.form, tile, w);
     if (s != GF_OK) return s;
     const int64_t W = std::max<int64_t>(1, (int64_t{1} << h.H) / 32);
+    if (graph) return run_batch_graph(F, J, q0, nb, st, w, tile, W);
 
     hipEvent_t ev[6];
     for (auto& e : ev) GF_HIP(hipEventCreate(&e));
@@ -273,15 +407,8 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
                            w.Qp, int64_t(nb), h.d, int64_t(F->ld32), w.flags);
         GF_HIP(hipGetLastError());
     }
-    if (J.form == gf::kFormBF16) {
-        hipLaunchKernelGGL(gf::k_to_bf16, dim3((nb + 3) / 4), dim3(256), 0, st, w.Qp, int64_t(nb),
-                           h.d, int64_t(F->ld32), w.Q16, int64_t(F->ld16), w.qnorm);
-        GF_HIP(hipGetLastError());
-    } else if (J.form == gf::kFormFP8) {
-        hipLaunchKernelGGL(gf::k_to_fp8, dim3((nb + 3) / 4), dim3(256), 0, st, w.Qp, int64_t(nb),
-                           h.d, int64_t(F->ld32), w.Q8, int64_t(F->ld8), w.qscale, w.qnorm);
-        GF_HIP(hipGetLastError());
-    }
+    s = launch_query_forms(F, J, nb, w, st);
+    if (s != GF_OK) return s;
     const int32_t* cpq = nullptr;
     if (J.cpq) {
         GF_HIP(hipMemcpyAsync(w.cpq, J.cpq + q0, size_t(nb) * 4,
@@ -295,40 +422,12 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
 
     // a2: leaf selection
     GF_HIP(hipEventRecord(ev[1], st));
-    gf::SelectArgs sa{};
-    sa.Q = w.Qp; sa.ldq = F->ld32; sa.nq = nb; sa.m = h.m; sa.H = h.H; sa.t = h.t;
-    sa.n_internal = (int64_t{1} << h.H) - 1; sa.W = int(W); sa.nodes = F->nodes; sa.D = F->D;
-    sa.nslice = h.m * gf::select_slices_per_tree(h.H);
-    sa.state = w.state; sa.hist = w.hist; sa.coff = w.coff; sa.ckey = w.ckey;
-    sa.ccode = w.ccode; sa.leafbits = w.leafbits;
-    hipLaunchKernelGGL(gf::k_select_init, dim3((nb + 255) / 256), dim3(256), 0, st, sa,
-                       J.checks, cpq, J.eps);
-    GF_HIP(hipGetLastError());
-    for (int pass = 0; pass < gf::kMaxPasses; ++pass) {
-        GF_HIP(hipMemsetAsync(w.flags + 1, 0, 4, st));
-        GF_HIP(gf::launch_select_walk(sa, pass, false, st));
-        hipLaunchKernelGGL(gf::k_select_pick, dim3(nb), dim3(128), 0, st, sa, pass, w.flags + 1);
-        GF_HIP(hipGetLastError());
-        uint32_t more = 0;
-        GF_HIP(hipMemcpyAsync(&more, w.flags + 1, 4, hipMemcpyDeviceToHost, st));
-        GF_HIP(hipStreamSynchronize(st));
-        if (!more) break;
-    }
-    GF_HIP(gf::launch_select_walk(sa, 0, true, st));
-    hipLaunchKernelGGL(gf::k_select_finish, dim3(nb), dim3(256), 0, st, sa);
-    GF_HIP(hipGetLastError());
+    s = launch_selection(F, J, nb, w, W, cpq, true, st);
+    if (s != GF_OK) return s;
 
     // a3-a6: candidates, distances, best k, re-rank, ties
     const int64_t nbmw = (h.n + 31) / 32;
-    gf::ScanArgs ca{};
-    ca.nq = nb; ca.k = J.k; ca.kk = J.kk; ca.n = h.n; ca.d = h.d; ca.m = h.m; ca.W = int(W); ca.H = h.H;
-    ca.leafbits = w.leafbits; ca.permp = F->permp; ca.pp = F->pp;
-    ca.Q = w.Qp; ca.ldq = F->ld32; ca.X32 = F->X32; ca.ld32 = F->ld32;
-    ca.X16 = F->X16; ca.ld16 = F->ld16; ca.norm16 = F->norm16;
-    ca.X8 = F->X8; ca.ld8 = F->ld8; ca.scale8 = F->scale8; ca.norm8 = F->norm8;
-    ca.Q16 = w.Q16; ca.Q8 = w.Q8; ca.qscale8 = w.qscale; ca.qnorm = w.qnorm;
-    ca.ids = J.out_dev && J.ids ? J.ids + q0 * J.k : w.ids;
-    ca.dists = J.out_dev && J.dists ? J.dists + q0 * J.k : w.dists;
+    gf::ScanArgs ca = make_scan_args(F, J, q0, nb, w, W);
     ca.cand_bits = (J.cand_bits && J.trace_dev) ? J.cand_bits + q0 * nbmw : nullptr;
     ca.ncand = (J.ncand && J.trace_dev) ? J.ncand + q0 : nullptr;
     std::unique_ptr<uint32_t, decltype(&hipFree)> tmp_bits(nullptr, &hipFree);
@@ -347,21 +446,8 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     }
     GF_HIP(hipEventRecord(ev[2], st));
     if (tile) {
-        const TilePlan tp = tile_plan(F, nb);
-        gf::ExpandArgs ea{};
-        ea.nq = nb; ea.m = h.m; ea.W = int(W); ea.H = h.H; ea.n = h.n;
-        ea.cw = tp.cw; ea.nchunk = tp.nchunk;
-        ea.leafbits = w.leafbits; ea.leafof = F->leafof; ea.openT = w.openT; ea.visT = w.visT;
-        ea.gthr = w.gthr;
-        gf::TileArgs ta{};
-        ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.cw = tp.cw; ta.Q16 = w.Q16; ta.X16 = F->X16;
-        ta.norm16 = F->norm16; ta.visT = w.visT; ta.gthr = w.gthr; ta.nsplit = tp.nsplit; ta.split_pts = tp.split_pts;
-        ta.part_s = w.part_s; ta.part_i = w.part_i;
-        gf::MergeArgs ma{};
-        ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = tp.nsplit;
-        ma.part_s = w.part_s; ma.part_i = w.part_i; ma.Q = w.Qp; ma.ldq = F->ld32;
-        ma.X32 = F->X32; ma.ld32 = F->ld32; ma.ids = ca.ids; ma.dists = ca.dists;
-        GF_HIP(gf::launch_tile_path(ea, ta, ma, st, ev + 3));
+        s = launch_tile(F, J, nb, w, W, ca, st, ev + 3);
+        if (s != GF_OK) return s;
     } else {
         GF_HIP(gf::launch_scan(ca, J.form, st));
         GF_HIP(hipEventRecord(ev[3], st));
@@ -433,6 +519,265 @@ gf_status validate_query_common(const gf_forest* F, const float* Q, int64_t nq, 
     return GF_OK;
 }
 
+// Validation and setup shared by gf_query and gf_query_multi: parameters
+// first (no HIP call), then where each buffer lives.
+gf_status prepare_job(const gf_forest* Fc, const float* Q, int64_t nq, int32_t k, int32_t checks,
+                      const int32_t* checks_per_query, double eps, int32_t form, int32_t rerank,
+                      int32_t* ids, float* dists, QueryJob& J) {
+    gf_status s = validate_query_common(Fc, Q, nq, checks, checks_per_query, eps);
+    if (s != GF_OK) return s;
+    if (k < 1 || k > gf::kMaxK) return fail(GF_EINVAL, "k must be in [1, 64]");
+    if (nq > 0 && (!ids || !dists)) return fail(GF_EINVAL, "ids or dists is NULL");
+    if (form != GF_FORM_FP32 && form != GF_FORM_BF16 && form != GF_FORM_FP8)
+        return fail(GF_EINVAL, "unknown form");
+    const gf_forest* F = Fc;
+    if (form == GF_FORM_BF16 && !F->X16) return fail(GF_EINVAL, "forest was built without GF_KEEP_BF16");
+    if (form == GF_FORM_FP8 && !F->X8) return fail(GF_EINVAL, "forest was built without GF_KEEP_FP8");
+    int kk;
+    if (form == GF_FORM_FP32) {
+        kk = std::min(gf::kMaxK, k + 8);
+    } else {
+        if (rerank == 0) rerank = std::min(gf::kMaxK, 4 * k);
+        if (rerank < k || rerank > gf::kMaxK) return fail(GF_EINVAL, "rerank must be in [k, 64]");
+        kk = rerank;
+    }
+    if (!gf::scan_supported(F->host.n, form, F->ld8))
+        return fail(GF_EUNSUPPORTED, "n (or d in FP8) too large for the LDS-resident scan");
+    J = QueryJob{};
+    J.nq = nq; J.k = k; J.checks = checks; J.eps = eps; J.form = form; J.kk = kk;
+    J.ids = ids; J.dists = dists;
+    if (nq == 0) return GF_OK;
+    J.Q = Q; J.q_dev = is_device_ptr(Q);
+    J.cpq = checks_per_query; J.cpq_dev = checks_per_query && is_device_ptr(checks_per_query);
+    if (checks_per_query && !J.cpq_dev) {
+        for (int64_t i = 0; i < nq; ++i)
+            if (checks_per_query[i] < 1) return fail(GF_EINVAL, "checks_per_query has a value < 1");
+    }
+    J.out_dev = is_device_ptr(ids);
+    if (J.out_dev != is_device_ptr(dists)) return fail(GF_EINVAL, "ids and dists must both be host or both device");
+    return GF_OK;
+}
+
+// ------------------------------------------------------- multi-index launch
+
+std::atomic<int64_t> g_graphs_built{0}, g_graphs_reused{0}, g_tuned{0};
+std::atomic<uint64_t> g_next_uid{1};
+
+// Instantiated graphs of earlier calls, keyed by everything the captured
+// launches depend on: each batch's forest (by unique id), buffers, sizes,
+// parameters and path, and the workspace address it was carved from.
+struct GraphEntry {
+    std::vector<uint64_t> key;
+    std::vector<uint64_t> uids;
+    hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mutex;
+std::vector<GraphEntry> g_graphs;   // most recent last
+constexpr size_t kGraphCache = 16;
+
+void drop_graphs_of(uint64_t uid) {
+    std::lock_guard<std::mutex> lock(g_graph_mutex);
+    for (size_t i = 0; i < g_graphs.size();) {
+        const auto& u = g_graphs[i].uids;
+        if (std::find(u.begin(), u.end(), uid) != u.end()) {
+            (void)hipGraphExecDestroy(g_graphs[i].exec);
+            g_graphs.erase(g_graphs.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+struct MultiBatch {
+    gf_forest* F;
+    int job;
+    int64_t q0;
+    int nb;
+    bool tile;
+};
+
+// Batch-size class of the autotuner (powers of two).
+int size_class(int nb) {
+    int c = 0;
+    while ((1 << c) < nb) ++c;
+    return c;
+}
+
+gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream_t st) {
+    if (njobs < 0 || (njobs > 0 && !jobs)) return fail(GF_EINVAL, "jobs is NULL or njobs < 0");
+    if (flags & ~uint32_t(GF_MULTI_AUTOTUNE | GF_MULTI_EAGER)) return fail(GF_EINVAL, "unknown bits in flags");
+    for (int i = 0; i < njobs; ++i) {
+        const gf_job& j = jobs[i];
+        gf_status s = validate_query_common(j.forest, j.Q, j.nq, j.checks, j.checks_per_query, j.eps);
+        if (s != GF_OK) return s;
+    }
+    std::vector<QueryJob> J(size_t(std::max(njobs, 0)));
+    std::vector<gf_forest*> Fs;
+    for (int i = 0; i < njobs; ++i) {
+        const gf_job& j = jobs[i];
+        gf_status s = prepare_job(j.forest, j.Q, j.nq, j.k, j.checks, j.checks_per_query, j.eps,
+                                  j.form, j.rerank, j.ids, j.dists, J[i]);
+        if (s != GF_OK) return s;
+        if (j.nq == 0) continue;
+        if (!J[i].q_dev || !J[i].out_dev || (J[i].cpq && !J[i].cpq_dev))
+            return fail(GF_EINVAL, "gf_query_multi takes device buffers for Q, budgets and outputs");
+        gf_forest* F = const_cast<gf_forest*>(j.forest);
+        if (!Fs.empty() && F->device != Fs[0]->device)
+            return fail(GF_EINVAL, "all forests of one gf_query_multi call must be on one device");
+        Fs.push_back(F);
+    }
+    if (Fs.empty()) return GF_OK;
+    std::sort(Fs.begin(), Fs.end());
+    Fs.erase(std::unique(Fs.begin(), Fs.end()), Fs.end());
+    GF_HIP(hipSetDevice(Fs[0]->device));
+    std::vector<std::unique_lock<std::mutex>> locks;
+    for (gf_forest* F : Fs) locks.emplace_back(F->ws_mutex);   // address order
+
+    // Every query row finite (one readback for the whole call).
+    {
+        static thread_local uint32_t* flag = nullptr;
+        static thread_local int flag_dev = -1;
+        if (flag_dev != Fs[0]->device) {
+            flag = nullptr;
+            GF_HIP(hipMalloc(&flag, 4));
+            flag_dev = Fs[0]->device;
+        }
+        GF_HIP(hipMemsetAsync(flag, 0, 4, st));
+        for (int i = 0; i < njobs; ++i) {
+            if (jobs[i].nq == 0) continue;
+            const int64_t tot = jobs[i].nq * int64_t(jobs[i].forest->host.d);
+            hipLaunchKernelGGL(gf::k_check_finite, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st,
+                               jobs[i].Q, jobs[i].nq, jobs[i].forest->host.d,
+                               int64_t(jobs[i].forest->host.d), flag);
+            GF_HIP(hipGetLastError());
+        }
+        uint32_t bad = 0;
+        GF_HIP(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st));
+        GF_HIP(hipStreamSynchronize(st));
+        if (bad) return fail(GF_EINVAL, "Q contains a non-finite value");
+    }
+
+    // Batches, and the path of each: by rule, or measured once per
+    // (forest, form, batch-size class, re-rank depth) when autotuning.
+    std::vector<MultiBatch> B;
+    for (int i = 0; i < njobs; ++i) {
+        gf_forest* F = const_cast<gf_forest*>(jobs[i].forest);
+        for (int64_t q0 = 0; q0 < jobs[i].nq; q0 += kMaxBatch) {
+            const int nb = int(std::min<int64_t>(kMaxBatch, jobs[i].nq - q0));
+            QueryJob Jb = J[i];
+            bool tile = use_tile_path(F, Jb, nb);
+            if ((flags & GF_MULTI_AUTOTUNE) && tile_eligible(F, Jb)) {
+                const uint64_t key = (uint64_t(Jb.form) << 40) | (uint64_t(size_class(nb)) << 32) | uint64_t(Jb.kk);
+                auto it = F->tuned.find(key);
+                if (it == F->tuned.end()) {
+                    float ms[2] = {0.0f, 0.0f};
+                    hipEvent_t e0, e1;
+                    GF_HIP(hipEventCreate(&e0));
+                    GF_HIP(hipEventCreate(&e1));
+                    gf_status s = GF_OK;
+                    for (int path = 0; path < 2 && s == GF_OK; ++path) {
+                        Jb.path = path;
+                        for (int rep = 0; rep < 2 && s == GF_OK; ++rep) {   // first run warms up
+                            (void)hipEventRecord(e0, st);
+                            s = run_batch(F, Jb, q0, nb, st, true);
+                            (void)hipEventRecord(e1, st);
+                            (void)hipEventSynchronize(e1);
+                        }
+                        (void)hipEventElapsedTime(&ms[path], e0, e1);
+                    }
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    if (s != GF_OK) return s;
+                    it = F->tuned.emplace(key, ms[1] < ms[0] ? 1 : 0).first;
+                    g_tuned.fetch_add(1);
+                }
+                tile = it->second == 1;
+            }
+            B.push_back(MultiBatch{F, i, q0, nb, tile});
+        }
+    }
+    // Grow every workspace to its largest batch before any capture.
+    for (const MultiBatch& b : B) {
+        Workspace w;
+        gf_status s = get_workspace(b.F, b.nb, J[b.job].k, J[b.job].form, b.tile, w);
+        if (s != GF_OK) return s;
+    }
+    auto launch_all = [&](hipStream_t s_) -> gf_status {
+        for (const MultiBatch& b : B) {
+            QueryJob Jb = J[b.job];
+            Jb.path = b.tile ? 1 : 0;
+            gf_status s = run_batch(b.F, Jb, b.q0, b.nb, s_, true);
+            if (s != GF_OK) return s;
+        }
+        return GF_OK;
+    };
+    if (flags & GF_MULTI_EAGER) {
+        gf_status s = launch_all(st);
+        if (s != GF_OK) return s;
+        GF_HIP(hipStreamSynchronize(st));
+        return GF_OK;
+    }
+    std::vector<uint64_t> key;
+    std::vector<uint64_t> uids;
+    for (const MultiBatch& b : B) {
+        const gf_job& j = jobs[b.job];
+        const uint64_t vals[] = {b.F->uid, uint64_t(uintptr_t(b.F->ws)), uint64_t(b.F->ws_bytes),
+                                 uint64_t(uintptr_t(j.Q)), uint64_t(uintptr_t(j.checks_per_query)),
+                                 uint64_t(uintptr_t(j.ids)), uint64_t(uintptr_t(j.dists)),
+                                 uint64_t(b.q0), uint64_t(b.nb), uint64_t(j.k), uint64_t(uint32_t(j.checks)),
+                                 uint64_t(J[b.job].kk), uint64_t(j.form), uint64_t(b.tile),
+                                 uint64_t(std::llround(j.eps * 1e12))};
+        key.insert(key.end(), std::begin(vals), std::end(vals));
+        uids.push_back(b.F->uid);
+    }
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_graph_mutex);
+        for (size_t i = 0; i < g_graphs.size(); ++i) {
+            if (g_graphs[i].key == key) {
+                exec = g_graphs[i].exec;
+                std::rotate(g_graphs.begin() + i, g_graphs.begin() + i + 1, g_graphs.end());
+                break;
+            }
+        }
+    }
+    if (exec) {
+        g_graphs_reused.fetch_add(1);
+    } else {
+        // Capture on a stream of our own (the caller's may be the null
+        // stream, which cannot be captured); the graph runs on the caller's.
+        static thread_local hipStream_t cap = nullptr;
+        static thread_local int cap_dev = -1;
+        if (cap_dev != Fs[0]->device) {
+            cap = nullptr;
+            GF_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            cap_dev = Fs[0]->device;
+        }
+        GF_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        gf_status s = launch_all(cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cap, &graph);
+        if (s != GF_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        GF_HIP(ec);
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        GF_HIP(ei);
+        g_graphs_built.fetch_add(1);
+        std::lock_guard<std::mutex> lock(g_graph_mutex);
+        if (g_graphs.size() >= kGraphCache) {
+            (void)hipGraphExecDestroy(g_graphs.front().exec);
+            g_graphs.erase(g_graphs.begin());
+        }
+        g_graphs.push_back(GraphEntry{key, uids, exec});
+    }
+    GF_HIP(hipGraphLaunch(exec, st));
+    GF_HIP(hipStreamSynchronize(st));
+    return GF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -477,6 +822,7 @@ gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32
     std::string err = gf::build_host_forest(Xh, n, d, m, t, leaf, seed, F->host);
     if (!err.empty()) return fail(GF_EINTERNAL, err);
     GF_HIP(hipGetDevice(&F->device));
+    F->uid = g_next_uid.fetch_add(1);
     const gf::HostForest& h = F->host;
     F->ld32 = int32_t(round_up(d, 4));
     F->ld16 = int32_t(round_up(d, 32));   // multiple of one MFMA k step (32 bf16)
@@ -558,6 +904,7 @@ gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32
 gf_status gf_free_forest(gf_forest* F) {
     if (!F) return GF_OK;
     (void)hipSetDevice(F->device);
+    drop_graphs_of(F->uid);
     free_forest_device(F);
     delete F;
     return GF_OK;
@@ -590,37 +937,21 @@ gf_status gf_export_tree(const gf_forest* F, int32_t* D, int32_t* split_dim, flo
 gf_status gf_query(const gf_forest* Fc, const float* Q, int64_t nq, int32_t k, int32_t checks,
                    const int32_t* checks_per_query, double eps, int32_t form, int32_t rerank,
                    int32_t* ids, float* dists, void* stream) {
-    gf_status s = validate_query_common(Fc, Q, nq, checks, checks_per_query, eps);
-    if (s != GF_OK) return s;
-    if (k < 1 || k > gf::kMaxK) return fail(GF_EINVAL, "k must be in [1, 64]");
-    if (nq > 0 && (!ids || !dists)) return fail(GF_EINVAL, "ids or dists is NULL");
-    if (form != GF_FORM_FP32 && form != GF_FORM_BF16 && form != GF_FORM_FP8)
-        return fail(GF_EINVAL, "unknown form");
-    gf_forest* F = const_cast<gf_forest*>(Fc);
-    if (form == GF_FORM_BF16 && !F->X16) return fail(GF_EINVAL, "forest was built without GF_KEEP_BF16");
-    if (form == GF_FORM_FP8 && !F->X8) return fail(GF_EINVAL, "forest was built without GF_KEEP_FP8");
-    int kk;
-    if (form == GF_FORM_FP32) {
-        kk = std::min(gf::kMaxK, k + 8);
-    } else {
-        if (rerank == 0) rerank = std::min(gf::kMaxK, 4 * k);
-        if (rerank < k || rerank > gf::kMaxK) return fail(GF_EINVAL, "rerank must be in [k, 64]");
-        kk = rerank;
-    }
-    if (!gf::scan_supported(F->host.n, form, F->ld8))
-        return fail(GF_EUNSUPPORTED, "n (or d in FP8) too large for the LDS-resident scan");
-    if (nq == 0) return GF_OK;
     QueryJob J{};
-    J.Q = Q; J.q_dev = is_device_ptr(Q);
-    J.cpq = checks_per_query; J.cpq_dev = checks_per_query && is_device_ptr(checks_per_query);
-    if (checks_per_query && !J.cpq_dev) {
-        for (int64_t i = 0; i < nq; ++i)
-            if (checks_per_query[i] < 1) return fail(GF_EINVAL, "checks_per_query has a value < 1");
-    }
-    J.nq = nq; J.k = k; J.checks = checks; J.eps = eps; J.form = form; J.kk = kk;
-    J.ids = ids; J.dists = dists; J.out_dev = is_device_ptr(ids);
-    if (J.out_dev != is_device_ptr(dists)) return fail(GF_EINVAL, "ids and dists must both be host or both device");
-    return run_query(F, J, static_cast<hipStream_t>(stream));
+    gf_status s = prepare_job(Fc, Q, nq, k, checks, checks_per_query, eps, form, rerank, ids, dists, J);
+    if (s != GF_OK || nq == 0) return s;
+    return run_query(const_cast<gf_forest*>(Fc), J, static_cast<hipStream_t>(stream));
+}
+
+gf_status gf_query_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, void* stream) {
+    return run_multi(jobs, njobs, flags, static_cast<hipStream_t>(stream));
+}
+
+gf_status gf_multi_stats(int64_t* graphs_built, int64_t* graphs_reused, int64_t* tuned) {
+    if (graphs_built) *graphs_built = g_graphs_built.load();
+    if (graphs_reused) *graphs_reused = g_graphs_reused.load();
+    if (tuned) *tuned = g_tuned.load();
+    return GF_OK;
 }
 
 gf_status gf_query_trace(const gf_forest* Fc, const float* Q, int64_t nq, int32_t checks,

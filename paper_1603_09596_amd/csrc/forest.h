@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -68,4 +69,8 @@ struct gf_forest {
     std::mutex ws_mutex;
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    uint64_t uid = 0;               // unique per forest built in this process
+    // path choices measured by the multi-index autotuner, keyed by
+    // (form, batch-size class, re-rank depth): 0 rows, 1 tile
+    std::map<uint64_t, int> tuned;
 };

@@ -23,8 +23,18 @@ KEEP_BF16, KEEP_FP8 = 1 << 1, 1 << 2
 FORMS = {"fp32": FORM_FP32, "bf16": FORM_BF16, "fp8": FORM_FP8}
 
 EXPORTED = ["gf_build_forest", "gf_free_forest", "gf_forest_info", "gf_export_tree", "gf_query",
-            "gf_query_trace", "gf_fp8_tables", "gf_last_query_timing", "gf_last_error",
-            "gf_version"]
+            "gf_query_multi", "gf_multi_stats", "gf_query_trace", "gf_fp8_tables",
+            "gf_last_query_timing", "gf_last_error", "gf_version"]
+MULTI_AUTOTUNE, MULTI_EAGER = 1, 2
+
+
+class Job(ctypes.Structure):
+    """gf_job (include/geraf.h)."""
+    _fields_ = [("forest", ctypes.c_void_p), ("Q", ctypes.c_void_p), ("nq", ctypes.c_int64),
+                ("k", ctypes.c_int32), ("checks", ctypes.c_int32),
+                ("checks_per_query", ctypes.c_void_p), ("eps", ctypes.c_double),
+                ("form", ctypes.c_int32), ("rerank", ctypes.c_int32), ("ids", ctypes.c_void_p),
+                ("dists", ctypes.c_void_p)]
 
 _lib = None
 
@@ -52,6 +62,8 @@ def load():
     lib.gf_export_tree.argtypes = [P, P, P, P, P, P]
     lib.gf_query.argtypes = [P, P, i64, i32, i32, P, f64, i32, i32, P, P, P]
     lib.gf_query_trace.argtypes = [P, P, i64, i32, P, f64, P, P, P, P]
+    lib.gf_query_multi.argtypes = [ctypes.POINTER(Job), i32, u32, P]
+    lib.gf_multi_stats.argtypes = [P, P, P]
     lib.gf_fp8_tables.argtypes = [P, P, P, i32, P]
     lib.gf_last_query_timing.argtypes = [P, i32, P, P]
     lib.gf_last_error.restype = ctypes.c_char_p
@@ -160,6 +172,29 @@ def query(F: Forest, Q, k: int, checks: int, ids, dists, checks_per_query=None, 
     st = stream if stream is not None else _stream_of(Q, ids)
     _check(load().gf_query(F.handle, _ptr(Q), nq, k, checks, _ptr(checks_per_query), float(eps),
                            FORMS[form], rerank, _ptr(ids), _ptr(dists), st))
+
+
+def query_multi(jobs, autotune: bool = False, eager: bool = False, stream=None):
+    """gf_query_multi.  jobs: sequence of dicts with the keys of gf_query
+    (forest, Q, k, checks, ids, dists; optional checks_per_query, eps, form,
+    rerank), every tensor on the device; outputs are filled in place."""
+    arr = (Job * len(jobs))()
+    for i, j in enumerate(jobs):
+        Q = j["Q"]
+        arr[i] = Job(j["forest"].handle, _ptr(Q), Q.shape[0], j["k"], j.get("checks", 1),
+                     _ptr(j.get("checks_per_query")), float(j.get("eps", 0.0)),
+                     FORMS[j.get("form", "fp32")], j.get("rerank", 0), _ptr(j["ids"]),
+                     _ptr(j["dists"]))
+    st = stream if stream is not None else _stream_of(*[j["Q"] for j in jobs])
+    flags = (MULTI_AUTOTUNE if autotune else 0) | (MULTI_EAGER if eager else 0)
+    _check(load().gf_query_multi(arr, len(jobs), flags, st))
+
+
+def multi_stats() -> dict:
+    """gf_multi_stats counters."""
+    b, r, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().gf_multi_stats(ctypes.byref(b), ctypes.byref(r), ctypes.byref(t)))
+    return dict(graphs_built=b.value, graphs_reused=r.value, tuned=t.value)
 
 
 def query_trace(F: Forest, Q, checks: int, leaf_bits=None, cand_bits=None, ncand=None,

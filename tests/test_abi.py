@@ -83,3 +83,18 @@ def test_query_rejects_bad_arguments_before_hip(lib):
     assert lib.gf_forest_info(None, None, None, None, None, None, None) == geraf.GF_EINVAL
     assert lib.gf_export_tree(None, None, None, None, None, None) == geraf.GF_EINVAL
     assert lib.gf_free_forest(None) == geraf.GF_OK
+
+
+def test_query_multi_rejects_bad_arguments_before_hip(lib):
+    M = lib.gf_query_multi
+    jobs = (geraf.Job * 1)()
+    assert M(None, 1, 0, None) == geraf.GF_EINVAL          # no jobs array
+    assert M(jobs, -1, 0, None) == geraf.GF_EINVAL         # negative count
+    assert M(jobs, 0, 1 << 5, None) == geraf.GF_EINVAL     # unknown flag bit
+    assert M(jobs, 0, 0, None) == geraf.GF_OK              # nothing to do
+    Q = np.zeros((3, 4), np.float32)
+    jobs[0] = geraf.Job(None, Q.ctypes.data_as(ctypes.c_void_p), 3, 2, 8, None, 0.0, 0, 0, None, None)
+    assert M(jobs, 1, 0, None) == geraf.GF_EINVAL          # forest is NULL
+    assert b"forest" in lib.gf_last_error()
+    b, r, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    assert lib.gf_multi_stats(ctypes.byref(b), ctypes.byref(r), ctypes.byref(t)) == geraf.GF_OK
