@@ -17,6 +17,11 @@ Prints one JSON line.  Also reports:
                 query stream during the timed steps;
   cpu_baseline  the FP64 oracle, searching a bounded sample of the same
                 queries on the host's cores (its own forest build excluded).
+
+`--multi` measures the multi-index launch instead and prints its own line:
+the multi-20 recipe (20 indexes of uneven n and d, per-query budgets,
+scaled by --multi-scale), FP32 form, as one gf_query_multi graph launch,
+as the same launches issued eagerly, and as one gf_query call per index.
 """
 from __future__ import annotations
 
@@ -123,6 +128,60 @@ def cpu_baseline(w, idx_all, checks, seconds, threads):
                        f"thread; forest build excluded")
 
 
+def multi_bench(args, torch, geraf, workloads, dev):
+    """The multi-index launch over the multi-20 recipe (FP32 form)."""
+    t0 = time.perf_counter()
+    ws = workloads.multi_index(seed=3, count=20, scale=args.multi_scale)
+    forests = [geraf.build_forest(w.X, w.m, w.t, w.p, w.seed) for w in ws]
+    log(f"[bench] multi-20 x{args.multi_scale}: {sum(len(w.Q) for w in ws)} queries over "
+        f"{len(ws)} indexes, data + forests {time.perf_counter() - t0:.1f}s")
+    jobs = []
+    for w, F in zip(ws, forests):
+        nq = len(w.Q)
+        jobs.append(dict(forest=F, Q=torch.from_numpy(w.Q).to(dev), k=w.k, checks=1,
+                         checks_per_query=torch.from_numpy(w.checks).to(dev), form="fp32",
+                         ids=torch.empty((nq, w.k), dtype=torch.int32, device=dev),
+                         dists=torch.empty((nq, w.k), dtype=torch.float32, device=dev)))
+    total = sum(len(w.Q) for w in ws)
+
+    def per_index():
+        for j in jobs:
+            geraf.query(j["forest"], j["Q"], j["k"], 1, j["ids"], j["dists"],
+                        checks_per_query=j["checks_per_query"], form="fp32")
+
+    modes = {"graph": lambda: geraf.query_multi(jobs),
+             "eager": lambda: geraf.query_multi(jobs, eager=True),
+             "per_index_calls": per_index}
+    res = {}
+    for name, fn in modes.items():
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[name] = dict(value=round(total / dt, 2), ms_per_step=round(dt * 1e3, 3))
+        log(f"[bench] multi {name}: {dt * 1e3:.2f} ms per step, {total / dt:.0f} queries/s")
+    out = {
+        "metric": "queries/s over a batch of 20 indexes with per-query budgets (multi-20)",
+        "value": res["graph"]["value"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["graph"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "multi-20", "scale": args.multi_scale, "indexes": len(ws),
+                   "queries": total, "n": [len(w.X) for w in ws], "d": [w.X.shape[1] for w in ws],
+                   "m": 8, "t": 5, "leaf": 16, "k": 10, "checks": "uniform 256..8192 per query",
+                   "form": "fp32"},
+        "eager": res["eager"], "per_index_calls": res["per_index_calls"],
+        "graph_stats": geraf.multi_stats(),
+    }
+    print(json.dumps(out), flush=True)
+    for F in forests:
+        F.free()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +193,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--multi", action="store_true",
+                    help="measure the multi-index launch (multi-20 recipe) instead")
+    ap.add_argument("--multi-scale", type=float, default=0.25,
+                    help="size factor of the multi-20 indexes and query counts")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a plain copy "
                          "kernel of known size that scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -151,6 +214,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     geraf.load()
+    if args.multi:
+        return multi_bench(args, torch, geraf, workloads, dev)
     t0 = time.perf_counter()
     w = workloads.make(WORKLOAD, nq=args.nq)
     log(f"[bench] workload {WORKLOAD}: X {w.X.shape} Q {w.Q.shape} in {time.perf_counter() - t0:.1f}s")

@@ -153,7 +153,8 @@ typedef struct gf_job {
  * rerank), a choice the forest then keeps.
  * All query rows are checked finite first (one readback for the call).  The
  * launches of every batch are then captured into one HIP graph, which runs on
- * `stream`.  The instantiated graph is kept (up to 16 of them, by least recent
+ * `stream`: the batches of one forest in order on one branch (they share the
+ * forest's workspace), the branches of different forests concurrently.  The instantiated graph is kept (up to 16 of them, by least recent
  * use) and launched again when a call repeats the same jobs, buffers and
  * paths; freeing a forest drops the graphs that use it.
  * All forests must live on the current device.  The call returns when the

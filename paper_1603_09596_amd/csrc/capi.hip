@@ -744,19 +744,44 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
     if (exec) {
         g_graphs_reused.fetch_add(1);
     } else {
-        // Capture on a stream of our own (the caller's may be the null
+        // Capture on streams of our own (the caller's may be the null
         // stream, which cannot be captured); the graph runs on the caller's.
+        // The batches of each forest form one branch of the graph (they
+        // share the forest's workspace); branches of different forests run
+        // concurrently, up to kBranches at a time.
+        constexpr int kBranches = 8;
         static thread_local hipStream_t cap = nullptr;
+        static thread_local hipStream_t br[kBranches] = {};
+        static thread_local hipEvent_t fork = nullptr, join[kBranches] = {};
         static thread_local int cap_dev = -1;
         if (cap_dev != Fs[0]->device) {
-            cap = nullptr;
             GF_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            GF_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+            for (int i = 0; i < kBranches; ++i) {
+                GF_HIP(hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking));
+                GF_HIP(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
+            }
             cap_dev = Fs[0]->device;
         }
+        const int nbr = std::min<int>(kBranches, int(Fs.size()));
         GF_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-        gf_status s = launch_all(cap);
+        gf_status s = GF_OK;
+        hipError_t eb = hipEventRecord(fork, cap);
+        for (int i = 0; i < nbr && eb == hipSuccess; ++i) eb = hipStreamWaitEvent(br[i], fork, 0);
+        for (const MultiBatch& b : B) {
+            if (eb != hipSuccess || s != GF_OK) break;
+            const int g = int(std::lower_bound(Fs.begin(), Fs.end(), b.F) - Fs.begin()) % nbr;
+            QueryJob Jb = J[b.job];
+            Jb.path = b.tile ? 1 : 0;
+            s = run_batch(b.F, Jb, b.q0, b.nb, br[g], true);
+        }
+        for (int i = 0; i < nbr && eb == hipSuccess; ++i) {
+            eb = hipEventRecord(join[i], br[i]);
+            if (eb == hipSuccess) eb = hipStreamWaitEvent(cap, join[i], 0);
+        }
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(cap, &graph);
+        if (s == GF_OK && eb != hipSuccess) s = fail(GF_EHIP, std::string("graph branches: ") + hipGetErrorString(eb));
         if (s != GF_OK) {
             if (graph) (void)hipGraphDestroy(graph);
             return s;
