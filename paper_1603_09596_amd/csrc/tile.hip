@@ -336,8 +336,6 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             else __builtin_amdgcn_s_waitcnt(kWaitVm(0));
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
-            if (it < ntile) issue_next();
-            if (c == 0) issue_epi(t);
             const uint16_t* xb = xs + buf * (kStageBytes / 2);
             // B fragments run two of this wave's k steps ahead of their MFMAs
             uint4 v[2][4];
@@ -363,6 +361,12 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
 #pragma unroll
                         for (int b = 0; b < 4; ++b)
                             v[u & 1][b] = *reinterpret_cast<const uint4*>(xb + ldsel[u + 2] + 16 * kKS * b);
+                }
+                if (u == 0) {
+                    // the next loads go out once the MFMA pipe is busy (their
+                    // buffer has been free since the barrier)
+                    if (it < ntile) issue_next();
+                    if (c == 0) issue_epi(t);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
