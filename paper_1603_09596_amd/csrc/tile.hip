@@ -120,8 +120,6 @@ __device__ __forceinline__ void quarter_offer(bool cand, float sc, int id, float
 
 // s_waitcnt immediates (gfx9 encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] at 15:14)
 constexpr int kWaitVm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
-// the same, and every LDS access of this wave complete (lgkmcnt 0)
-constexpr int kWaitVmLds(int n) { return (n & 15) | (7 << 4) | (((n >> 4) & 3) << 14); }
 
 constexpr int kKS = 256;                               // k (bf16 elements) per pipeline stage
 constexpr int kNBuf = 3;                               // LDS stages (prefetch distance kNBuf - 1)
@@ -201,29 +199,18 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     const int q0 = blockIdx.x * kTQ + wave * 16;
     const int ks = int(a.ld16 / 32);
 
-    // Waves 2p and 2p + 1 share the 32 queries of pair p and split the k
-    // steps: wave half h multiplies steps S = 2 j + h only, for both 16-query
-    // blocks of the pair, so every B fragment it reads feeds two MFMAs.  At
-    // the end of a tile the two waves swap partial sums: each then holds the
-    // full scores of its own 16 queries (block h).
-    const int half = wave & 1;
-    const int pq = blockIdx.x * kTQ + (wave >> 1) * 32;     // first query of the pair
-    constexpr int KH = KSTEPS / 2;                          // KSTEPS is even
-    static_assert(KSTEPS % 2 == 0, "k steps split evenly over a wave pair");
-    // A operands: query row pq + 16 m + col, elements k = 32 S + 8 quarter .. + 8
-    bf16x8 qa[2][KH];
+    // A operands: query row q0 + col, elements k = 32 s + 8 quarter .. + 8
+    bf16x8 qa[KSTEPS];
+    {
+        const int qrow = q0 + col;
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        const int qrow = pq + 16 * m + col;
-#pragma unroll
-        for (int j = 0; j < KH; ++j) {
-            const int S = 2 * j + half;
-            if (qrow < a.nq && S < ks) {
+        for (int s = 0; s < KSTEPS; ++s) {
+            if (qrow < a.nq && s < ks) {
                 const uint4 v = *reinterpret_cast<const uint4*>(a.Q16 + int64_t(qrow) * a.ld16 +
-                                                                32 * S + 8 * quarter);
-                qa[m][j] = __builtin_bit_cast(bf16x8, v);
+                                                                32 * s + 8 * quarter);
+                qa[s] = __builtin_bit_cast(bf16x8, v);
             } else {
-                qa[m][j] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+                qa[s] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
             }
         }
     }
@@ -264,12 +251,11 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         drow[j] = kRowsPerInst * inst + lane / kUnits;
         dk[j] = uint32_t(((lane % kUnits) ^ (drow[j] & 15)) * 8);
     }
-    // B-operand LDS element offsets within a stage for this wave's k steps
-    // s = 2 u + half (block b adds 16 kKS b): row col, unit (4 s + quarter) ^ col
-    constexpr int kMine = kSteps / 2;
-    int ldsel[kMine];
+    // B-operand LDS element offsets within a stage for k step s (block b
+    // adds 16 kKS b): row col, unit (4 s + quarter) ^ col
+    int ldsel[kSteps];
 #pragma unroll
-    for (int u = 0; u < kMine; ++u) ldsel[u] = col * kKS + (((4 * (2 * u + half) + quarter) ^ col) * 8);
+    for (int s = 0; s < kSteps; ++s) ldsel[s] = col * kKS + (((4 * s + quarter) ^ col) * 8);
 
     // issue cursor: the next stage to load is chunk ic of tile it, into ibuf
     int it = 0, ic = 0, ibuf = 0;
@@ -316,11 +302,9 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     const int bit0 = 16 * (wave & 1) + 4 * quarter;  // bit of query q0 + 4 quarter
     int buf = 0, left = ntile * NC;                  // stages not yet consumed
     for (int t = 0; t < ntile; ++t) {
-        f4 acc2[2][4];
+        f4 acc[4];
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc2[m][b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int b = 0; b < 4; ++b) acc[b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             // Loads complete in issue order.  After the current stage's
@@ -337,32 +321,30 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
             const uint16_t* xb = xs + buf * (kStageBytes / 2);
-            // B fragments run two of this wave's k steps ahead of their MFMAs
+            // B fragments run two k steps ahead of the MFMAs that use them
             uint4 v[2][4];
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
-                if (c * kMine + u < KH)
+            for (int s = 0; s < 2; ++s)
+                if (c * kSteps + s < KSTEPS)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        v[u][b] = *reinterpret_cast<const uint4*>(xb + ldsel[u] + 16 * kKS * b);
+                        v[s][b] = *reinterpret_cast<const uint4*>(xb + ldsel[s] + 16 * kKS * b);
             // keep the scheduler from sinking the reads down to their uses
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < kMine; ++u) {
-                const int j = c * kMine + u;
-                if (j < KH) {
+            for (int s = 0; s < kSteps; ++s) {
+                const int S = c * kSteps + s;
+                if (S < KSTEPS) {
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-#pragma unroll
-                        for (int m = 0; m < 2; ++m)
-                            acc2[m][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                qa[m][j], __builtin_bit_cast(bf16x8, v[u & 1][b]), acc2[m][b], 0, 0, 0);
-                    if (u + 2 < kMine && j + 2 < KH)
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            qa[S], __builtin_bit_cast(bf16x8, v[s & 1][b]), acc[b], 0, 0, 0);
+                    if (s + 2 < kSteps && S + 2 < KSTEPS)
 #pragma unroll
                         for (int b = 0; b < 4; ++b)
-                            v[u & 1][b] = *reinterpret_cast<const uint4*>(xb + ldsel[u + 2] + 16 * kKS * b);
+                            v[s & 1][b] = *reinterpret_cast<const uint4*>(xb + ldsel[s + 2] + 16 * kKS * b);
                 }
-                if (u == 0) {
+                if (s == 0) {
                     // the next loads go out once the MFMA pipe is busy (their
                     // buffer has been free since the barrier)
                     if (it < ntile) issue_next();
@@ -373,49 +355,17 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             buf = (buf + 1 == kNBuf) ? 0 : buf + 1;
             --left;
         }
-        // Swap partial sums within the pair through the buffer of the stage
-        // just consumed: no load targets it before the next stage's barrier.
-        // Wave w stores its sums for the partner's block, then reads the
-        // partner's sums for its own block after the epilogue barrier.
-        const int last = (buf == 0) ? kNBuf - 1 : buf - 1;
-        // selects of values, component by component (a select of array
-        // elements would become an indexed, memory-resident array)
-        const bool hb = half != 0;
-        auto pick = [&](const f4 x, const f4 y) {
-            f4 r;
-            r.x = hb ? x.x : y.x;
-            r.y = hb ? x.y : y.y;
-            r.z = hb ? x.z : y.z;
-            r.w = hb ? x.w : y.w;
-            return r;
-        };
-        uint4* xch = reinterpret_cast<uint4*>(xs + last * (kStageBytes / 2));
-        __builtin_amdgcn_s_barrier();   // every wave is done with that buffer
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const f4 o = pick(acc2[0][b], acc2[1][b]);
-            xch[(wave * 4 + b) * kWave + lane] = __builtin_bit_cast(uint4, o);
-        }
-        // The epilogue loads were issued at this tile's first stage, and the
-        // stages issued after them are those that exist among the next
-        // NC - 1.  With at least kNBuf chunks per tile and a next tile,
-        // kNBuf - 1 stages followed, so their loads may stay outstanding;
-        // otherwise wait for everything.
-        // The partial sums just stored must be complete too (lgkmcnt 0).
-        asm volatile("" ::: "memory");
-        if (NC >= kNBuf && t + 1 < ntile)
-            __builtin_amdgcn_s_waitcnt(kWaitVmLds(kDmaPerWave * (kNBuf - 1)));
-        else
-            __builtin_amdgcn_s_waitcnt(kWaitVmLds(0));
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-        f4 acc[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const f4 own = pick(acc2[1][b], acc2[0][b]);
-            const f4 other = __builtin_bit_cast(f4, xch[((wave ^ 1) * 4 + b) * kWave + lane]);
-            acc[b] = own + other;
+        // The epilogue loads went out in this tile's first stage, right after
+        // the loads of the stage kNBuf - 1 ahead.  With NC > kNBuf stages per
+        // tile the wait before the last stage's barrier (for that stage's
+        // loads, issued later) already covered them in every wave.  Shorter
+        // tiles wait here for everything.
+        static_assert(kNBuf == 3, "the epilogue-load argument counts three buffers");
+        if (NC <= kNBuf) {
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_waitcnt(kWaitVm(0));
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
         }
         // epilogue: C[row 4 quarter + i][col] of block b = q(row) . x(16 b + col).
         // A point enters a query's list only if it is a candidate of the
@@ -441,7 +391,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             bm[i] = __builtin_inff();
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                if ((word[b] >> i) & 1u) bm[i] = fminf(bm[i], acc[b][i]);
+                bm[i] = (((word[b] >> i) & 1u) && acc[b][i] < bm[i]) ? acc[b][i] : bm[i];
             any = any || bm[i] <= lim[i];
         }
         // Only queries with a candidate at or below their limit in this tile
