@@ -47,6 +47,7 @@ constexpr int kTQ = kTWaves * 16;     // queries per workgroup
 constexpr int kTP = 64;               // points per tile
 constexpr int kSlots = 3;             // list entries per lane and query (x 16 lanes)
 constexpr int kExpandThreads = 1024;
+constexpr int kXcds = 8;              // XCDs of an MI355X (32 CUs each)
 
 // One DPP step of a 16-lane reduction (a DPP row is a quarter-wave).
 template <int CTRL>
@@ -196,7 +197,21 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int quarter = lane >> 4, col = lane & 15;
-    const int q0 = blockIdx.x * kTQ + wave * 16;
+    // Workgroups are dispatched to the XCDs round-robin (workgroup i to XCD
+    // i % kXcds).  Each XCD takes a consecutive run of the (split, query
+    // block) list instead, so the workgroups sharing an L2 stream the same
+    // split's rows at about the same time.
+    int qblk, split;
+    {
+        const int nqb = (a.nq + kTQ - 1) / kTQ;
+        const int total = nqb * a.nsplit;
+        const int i = int(blockIdx.x), x = i % kXcds, j = i / kXcds;
+        const int base = total / kXcds, rem = total % kXcds;
+        const int L = (x < rem) ? x * (base + 1) + j : rem * (base + 1) + (x - rem) * base + j;
+        split = L / nqb;
+        qblk = L - split * nqb;
+    }
+    const int q0 = qblk * kTQ + wave * 16;
     const int ks = int(a.ld16 / 32);
 
     // A operands: query row q0 + col, elements k = 32 s + 8 quarter .. + 8
@@ -228,14 +243,14 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         for (int j = 0; j < kSlots; ++j) { lst_s[base + j] = __builtin_inff(); lst_i[base + j] = 0x7FFFFFFF; }
     }
 
-    const int64_t pb = int64_t(blockIdx.y) * a.split_pts;
+    const int64_t pb = int64_t(split) * a.split_pts;
     const int npts = int((pb + a.split_pts < a.n) ? a.split_pts : a.n - pb);
     const int ntile = (npts + kTP - 1) / kTP;
     const uint32_t xs0 = lds_offset(xs), epi0 = lds_offset(epi);
     const void* xbase = uniform_ptr(a.X16 + pb * a.ld16);
     const uint32_t rowbytes = uint32_t(a.ld16) * 2u;
     // this block's 128 queries: words wo .. wo + 3 of query chunk qc
-    const int qc = (4 * int(blockIdx.x)) / a.cw, wo = (4 * int(blockIdx.x)) % a.cw;
+    const int qc = (4 * qblk) / a.cw, wo = (4 * qblk) % a.cw;
     const uint32_t* visb = a.visT + (int64_t(qc) * a.n + pb) * a.cw + wo;
 
     // This wave's share of a stage: instructions inst = wave + kTWaves j each
@@ -291,7 +306,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         } else if (wave == 1) {
             dma_4(a.norm16 + pb + xc, epi0 + 4u * kEpiNorm);
         } else if (wave < 4) {
-            const int qq = blockIdx.x * kTQ + (wave - 2) * kWave + lane;
+            const int qq = qblk * kTQ + (wave - 2) * kWave + lane;
             dma_4_dev(a.gthr + (qq < a.nq ? qq : 0), epi0 + 4u * (kEpiThr + (wave - 2) * kWave));
         }
     };
@@ -421,7 +436,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     for (int i = 0; i < 4; ++i) {
         const int q = q0 + 4 * quarter + i;
         if (q < a.nq) {
-            const int64_t base = (int64_t(q) * a.nsplit + blockIdx.y) * kTileList;
+            const int64_t base = (int64_t(q) * a.nsplit + split) * kTileList;
             const int rbase = (wave * 16 + 4 * quarter + i) * kTileList;
 #pragma unroll
             for (int j = 0; j < kSlots; ++j) {
@@ -544,7 +559,7 @@ hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeA
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
-    dim3 grid((t.nq + kTQ - 1) / kTQ, t.nsplit);
+    dim3 grid(unsigned(((t.nq + kTQ - 1) / kTQ) * t.nsplit));   // 1-D: see the XCD mapping
     const int ks = int(t.ld16 / 32);
 #define GF_TILE(KS) \
     else if (ks <= KS) hipLaunchKernelGGL(k_tile_bf16<KS>, grid, dim3(kTThreads), 0, st, t);
