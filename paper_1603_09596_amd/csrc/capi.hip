@@ -72,12 +72,13 @@ bool all_finite_host(const float* X, int64_t count) {
 
 void free_forest_device(gf_forest* F) {
     void* ptrs[] = {F->X32, F->X16, F->norm16, F->X8, F->scale8, F->norm8,
-                    F->nodes, F->perm, F->leaf_off, F->permp, F->leafof, F->D, F->ws};
+                    F->nodes, F->perm, F->leaf_off, F->permp, F->leafof, F->D, F->drange, F->ws};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     F->X32 = nullptr; F->X16 = nullptr; F->norm16 = nullptr; F->X8 = nullptr;
     F->scale8 = nullptr; F->norm8 = nullptr; F->nodes = nullptr; F->perm = nullptr;
-    F->leaf_off = nullptr; F->permp = nullptr; F->leafof = nullptr; F->D = nullptr; F->ws = nullptr;
+    F->leaf_off = nullptr; F->permp = nullptr; F->leafof = nullptr; F->D = nullptr; F->drange = nullptr;
+    F->ws = nullptr;
     F->ws_bytes = 0;
 }
 
@@ -266,6 +267,7 @@ gf::SelectArgs make_select_args(const gf_forest* F, int nb, const Workspace& w, 
     gf::SelectArgs sa{};
     sa.Q = w.Qp; sa.ldq = F->ld32; sa.nq = nb; sa.m = h.m; sa.H = h.H; sa.t = h.t;
     sa.n_internal = (int64_t{1} << h.H) - 1; sa.W = int(W); sa.nodes = F->nodes; sa.D = F->D;
+    sa.drange = F->drange;
     sa.nslice = h.m * gf::select_slices_per_tree(h.H);
     sa.state = w.state; sa.hist = w.hist; sa.coff = w.coff; sa.ckey = w.ckey;
     sa.ccode = w.ccode; sa.leafbits = w.leafbits;
@@ -280,16 +282,22 @@ gf_status launch_selection(const gf_forest* F, const QueryJob& J, int nb, const 
     hipLaunchKernelGGL(gf::k_select_init, dim3((nb + 255) / 256), dim3(256), 0, st, sa,
                        J.checks, cpq, J.eps);
     GF_HIP(hipGetLastError());
-    for (int pass = 0; pass < gf::kMaxPasses; ++pass) {
-        if (early_exit) GF_HIP(hipMemsetAsync(w.flags + 1, 0, 4, st));
-        GF_HIP(gf::launch_select_walk(sa, pass, false, st));
-        hipLaunchKernelGGL(gf::k_select_pick, dim3(nb), dim3(128), 0, st, sa, pass, w.flags + 1);
+    // sample walk, window walk, then radix passes while some query needs one.
+    // flags[1]: any query left for a radix pass, flags[2]: how many.  With
+    // the host readback, a pass for a few queries splits each tree finer.
+    uint32_t more[2] = {1u, uint32_t(nb)};
+    for (int step = 0; step < gf::kMaxPasses + 2 && more[0]; ++step) {
+        const int phase = step == 0 ? gf::kPhSample : (step == 1 ? gf::kPhWindow : gf::kPhRadix);
+        // the flags collect the window walk's queries and those the sample
+        // walk sent straight to radix passes
+        if (early_exit && phase != gf::kPhWindow) GF_HIP(hipMemsetAsync(w.flags + 1, 0, 8, st));
+        const int zfine = (early_exit && phase == gf::kPhRadix && int64_t(more[1]) * 16 <= nb) ? 16 : 1;
+        GF_HIP(gf::launch_select_walk(sa, phase, false, st, zfine));
+        hipLaunchKernelGGL(gf::k_select_pick, dim3(nb), dim3(128), 0, st, sa, phase, w.flags + 1);
         GF_HIP(hipGetLastError());
-        if (early_exit) {
-            uint32_t more = 0;
-            GF_HIP(hipMemcpyAsync(&more, w.flags + 1, 4, hipMemcpyDeviceToHost, st));
+        if (early_exit && phase != gf::kPhSample) {
+            GF_HIP(hipMemcpyAsync(more, w.flags + 1, 8, hipMemcpyDeviceToHost, st));
             GF_HIP(hipStreamSynchronize(st));
-            if (!more) break;
         }
     }
     GF_HIP(gf::launch_select_walk(sa, 0, true, st));
@@ -896,6 +904,20 @@ gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32
     }
     GF_HIP_B(hipMalloc(&F->D, size_t(t) * 4));
     GF_HIP_B(hipMemcpyAsync(F->D, h.D.data(), size_t(t) * 4, hipMemcpyHostToDevice, st));
+    {
+        // range of the split values on each slot of D (0, 0 for an unused slot)
+        std::vector<float2> rng(size_t(t), make_float2(0.0f, 0.0f));
+        std::vector<char> used(size_t(t), 0);
+        for (int64_t i = 0; i < int64_t(m) * nint; ++i) {
+            const int j = h.split_slot[i];
+            const float v = h.split_val[i];
+            if (!used[j]) { rng[j] = make_float2(v, v); used[j] = 1; }
+            rng[j].x = std::min(rng[j].x, v);
+            rng[j].y = std::max(rng[j].y, v);
+        }
+        GF_HIP_B(hipMalloc(&F->drange, size_t(t) * sizeof(float2)));
+        GF_HIP_B(hipMemcpy(F->drange, rng.data(), size_t(t) * sizeof(float2), hipMemcpyHostToDevice));
+    }
     if (forms & GF_KEEP_BF16) {
         // leaf of every point in every tree, point-major (tile path)
         const int64_t nleaf = int64_t{1} << h.H;

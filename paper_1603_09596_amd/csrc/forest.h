@@ -64,6 +64,7 @@ struct gf_forest {
     int32_t pp = 0;                 // ids per padded leaf row: pow2 >= max leaf size, >= 4
     uint32_t* leafof = nullptr;     // [n][m] tree * 2^H + leaf of each point (BF16 form)
     int32_t* D = nullptr;           // [t]
+    float2* drange = nullptr;       // [t] smallest and largest split value per slot of D
     // Grow-only scratch for queries.  Calls on one forest are serialised by
     // this mutex (concurrent queries on one forest wait for each other).
     std::mutex ws_mutex;

@@ -9,14 +9,22 @@ namespace gf {
 
 // ---------------------------------------------------------------- selection
 
-constexpr int kCollectCap = 32768;  // keys resolved by the final per-query radix select
+constexpr int kCollectCap = 32768;  // keys resolved by the final per-query select
 constexpr int kMaxPasses = 9;       // 63 significant key bits / 7-bit digits
 
 enum : uint32_t { kSelSearching = 0, kSelReady = 1, kSelAll = 2, kSelDone = 3 };
 
+// Counting walks of the selection, in launch order: a sample walk over tree
+// 0 that estimates each query's threshold, one walk over every tree that
+// counts a window of bins around the estimate, then radix passes for the
+// queries whose window missed or whose bin is still too large.
+enum : int { kPhSample = 0, kPhWindow = 1, kPhRadix = 2 };
+
 struct SelState {
-    uint64_t prefix;      // key digits fixed so far
-    uint32_t pass;        // number of digits fixed
+    uint64_t prefix;      // key bits above bit cs, fixed so far (K >> cs)
+    uint32_t cs;          // bits of the key below the fixed prefix
+    uint32_t phase;       // next counting walk that serves this query
+    uint32_t base;        // sample / window walks: bin b >= 1 holds (E >> shift) == base + b
     uint32_t below;       // leaves whose key is below the current bin
     uint32_t budget;      // B of this query
     uint32_t status;
@@ -33,20 +41,26 @@ struct SelectArgs {
     int W;                 // leaf-bitmap words per tree
     const uint2* nodes;    // [m][n_internal]
     const int32_t* D;      // [t]
+    const float2* drange;  // [t] smallest and largest split value on each slot of D
     int nslice;            // m * (leaf ranges per tree)
     SelState* state;       // [nq]
     uint32_t* hist;        // [nq][nslice][128]
     uint32_t* coff;        // [nq][nslice] collect offsets
-    uint64_t* ckey;        // [nq][kCollectCap]
+    uint64_t* ckey;        // [nq][kCollectCap] keys (or eff bits and tie keys, as u32 pairs)
     uint32_t* ccode;       // [nq][kCollectCap]
     uint32_t* leafbits;    // [m][W][nq]  (word-major, query fastest)
 };
 
 __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps);
-__global__ void k_select_pick(SelectArgs a, int pass, uint32_t* any_searching);
+// flags[0]: set when some query goes on to a radix pass; flags[1]: how many
+__global__ void k_select_pick(SelectArgs a, int phase, uint32_t* flags);
 int select_slices_per_tree(int H);
 __global__ void k_select_finish(SelectArgs a);
-hipError_t launch_select_walk(const SelectArgs& a, int pass, bool collect, hipStream_t st);
+// phase: kPhSample / kPhWindow / kPhRadix for a counting walk (ignored with
+// collect).  zfine > 1 splits each slice of a radix walk over zfine
+// workgroups (for few remaining queries: shorter walks per workgroup).
+hipError_t launch_select_walk(const SelectArgs& a, int phase, bool collect, hipStream_t st,
+                              int zfine = 1);
 
 // --------------------------------------------------------------------- scan
 

@@ -15,13 +15,23 @@
 //     the same tree in lockstep: node loads are uniform (scalar / broadcast),
 //     each lane keeps its own eff and entry, and the bottom five levels are
 //     expanded breadth-first in registers, 32 leaves at a time;
-//   * a radix select on the 64-bit key K (7-bit digits, per-lane histograms
-//     in LDS, written out per (query, tree slice) without atomics) that
-//     narrows each query's threshold to a bin of at most kCollectCap leaves;
+//   * counting walks that narrow each query's threshold to a bin of at most
+//     kCollectCap leaves (per-lane histograms in LDS, written out per (query,
+//     tree slice) without atomics).  The trees are drawn alike, so the
+//     ceil(2B/m)-th smallest eff of trees 0 and 1 lies close to the B-th
+//     smallest of the forest: a walk over those two trees finds it in bins
+//     of 1/8 octave, and one walk over every tree then counts 126 bins of 1/128
+//     octave around it, plus a bin for all keys below the window and one for
+//     all keys above.  The estimate only places the window; the counts are
+//     exact.  A query whose B-th key falls outside the window, or whose bin
+//     still holds more than kCollectCap leaves, continues with exact radix
+//     passes over the 64-bit key (7-bit digits);
 //   * a final walk that marks every leaf below the bin in the query's leaf
-//     bitmap and writes the bin's keys to per-slice offsets of the query's
-//     collect buffer (again without atomics); a per-query radix select over
-//     those keys (8-bit digits, LDS histogram) finds the exact B-th key.
+//     bitmap and writes the bin's eff bits and leaf codes to per-slice
+//     offsets of the query's collect buffer (again without atomics); a
+//     per-query radix select over those eff bits finds the B-th eff, and only
+//     where leaves tie at that eff across the budget are their (tree, entry)
+//     keys recomputed from the root paths to order them.
 //
 // Key layout: bits 63..32 = eff as float bits (eff >= 0, so the bit pattern
 // orders like the value), 31..24 = tree, 23..0 = entry node (heap index).
@@ -29,6 +39,7 @@
 
 #include <cstdint>
 
+#include "forest.h"
 #include "kernels.h"
 
 namespace gf {
@@ -39,7 +50,16 @@ constexpr int kWave = 64;
 constexpr int kDigitBits = 7;
 constexpr int kBins = 1 << kDigitBits;   // 128
 
-__device__ __forceinline__ int digit_shift(int pass) { return 56 - kDigitBits * pass; }
+// Bins of the sample walk: eff bits >> 20 (exponent and 3 mantissa bits,
+// 1/8 octave); of the window walk: eff bits >> 16 (1/128 octave).  Window
+// bins 1..126 are centred on the sampled bin.
+constexpr int kSampleShift = 20;
+constexpr int kWindowShift = 16;
+constexpr uint32_t kWindowHalf = 63;
+
+// Trees walked by the sample walk: two where the forest has them (the
+// estimate's spread over queries shrinks with the sampled leaves).
+__host__ __device__ inline int sample_trees(int m) { return m >= 2 ? 2 : 1; }
 
 // Walk one tree for the 64 queries of this wavefront.  Calls
 // fn(chunk, eff[32], entry[32]) for every group of 2^CH consecutive leaves
@@ -57,18 +77,28 @@ __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H
                                           const float* qd, float* pe, uint32_t* pn, Fn&& fn) {
     const int lane = threadIdx.x & (kWave - 1);
     const int U = H - CH;
-    constexpr int NI = (1 << CH) - 1;
     constexpr int NL = 1 << CH;
-    for (uint32_t c = chunk_begin; c < chunk_end; ++c) {
+    // the chunk range is the same for the whole wavefront: node indices are
+    // uniform, and the nodes (read-only during the walk) are read through the
+    // constant address space, so the loads are scalar
+#if defined(__HIP_DEVICE_COMPILE__)
+    using cnode = const __attribute__((address_space(4))) uint2;
+#else
+    using cnode = const uint2;
+#endif
+    cnode* cnodes = (cnode*)(nodes);
+    const uint32_t cb = __builtin_amdgcn_readfirstlane(chunk_begin);
+    const uint32_t ce = __builtin_amdgcn_readfirstlane(chunk_end);
+    for (uint32_t c = cb; c < ce; ++c) {
         // Upper path: levels h0..U-1 change between chunk c-1 and chunk c.
-        int h0 = (c == chunk_begin) ? 0 : (U - 1 - __builtin_ctz(c));
-        if (c == chunk_begin) {
+        int h0 = (c == cb) ? 0 : (U - 1 - __builtin_ctz(c));
+        if (c == cb) {
             pe[lane] = 0.0f;
             if (ENTRY) pn[lane] = 0u;
         }
         for (int h = h0; h < U; ++h) {
             const uint32_t v = ((1u << h) - 1u) + (c >> (U - h));
-            const uint2 nd = nodes[v];
+            const uint2 nd = cnodes[v];
             const float g = qd[nd.y * kWave + lane] - __uint_as_float(nd.x);
             const bool go_right = (c >> (U - 1 - h)) & 1u;
             const float e = pe[h * kWave + lane];
@@ -80,35 +110,25 @@ __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H
                 pn[(h + 1) * kWave + lane] = en;
             }
         }
-        // Chunk subtree: lane i < NI fetches its i-th node (breadth-first).
-        uint32_t mval = 0, mslot = 0;
-        if (lane < NI) {
-            const int j = 31 - __clz(lane + 1);
-            const uint32_t x = uint32_t(lane + 1) - (1u << j);
-            const uint32_t v = ((1u << (U + j)) - 1u) + (c << j) + x;
-            const uint2 nd = nodes[v];
-            mval = nd.x;
-            mslot = nd.y;
-        }
+        // Chunk subtree, breadth-first: level j holds nodes base_j + (c << j) + x.
         float ef[NL];
         uint32_t en[NL];
         ef[0] = pe[U * kWave + lane];
         if (ENTRY) en[0] = pn[U * kWave + lane];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
+            const uint32_t row = ((1u << (U + j)) - 1u) + (c << j);
 #pragma unroll
             for (int x = (1 << j) - 1; x >= 0; --x) {
-                const int i = (1 << j) - 1 + x;
-                const float val = __uint_as_float(__builtin_amdgcn_readlane(mval, i));
-                const uint32_t slot = __builtin_amdgcn_readlane(mslot, i);
-                const float g = qd[slot * kWave + lane] - val;
+                const uint2 nd = cnodes[row + uint32_t(x)];
+                const float g = qd[nd.y * kWave + lane] - __uint_as_float(nd.x);
                 const float e = ef[x];
                 ef[2 * x] = fmaxf(e, g);
                 ef[2 * x + 1] = fmaxf(e, -g);
                 if (ENTRY) {
                     const bool near_right = !(g < 0.0f);
                     const uint32_t n = en[x];
-                    const uint32_t v = ((1u << (U + j)) - 1u) + (c << j) + uint32_t(x);
+                    const uint32_t v = row + uint32_t(x);
                     en[2 * x] = near_right ? 2u * v + 1u : n;
                     en[2 * x + 1] = near_right ? n : 2u * v + 2u;
                 }
@@ -148,121 +168,256 @@ __device__ __forceinline__ void wave_chunks(uint32_t nchunks, uint32_t& cb, uint
     ce = min(ze, cb + wper);
 }
 
-template <int CH>
-__global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a, int pass) {
+// One counting walk (PHASE kPhSample, kPhWindow or kPhRadix) for the
+// queries whose next walk it is.  The sample walk counts every leaf of its
+// trees, bin 0 taking all keys at or below the window (whose top bin holds
+// the bound on every eff).  The window walk counts the leaves inside its 126
+// bins, keeps the number below the window in a register (bin 0) and drops
+// those above it.  A radix walk counts the leaves under the fixed prefix by
+// their next digit.
+template <int CH, int PHASE>
+__global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
     extern __shared__ uint32_t smem[];
     const int U = a.H - CH;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     float* qd = reinterpret_cast<float*>(smem);                          // [t][64]
     uint32_t* hist = reinterpret_cast<uint32_t*>(qd + a.t * kWave);      // [64][64] packed u16 pairs
-    float* pe = reinterpret_cast<float*>(hist + (kBins / 2) * kWave) + wave * 2 * (U + 1) * kWave;
+    // path state per wave: eff, and the entry node where a walk tracks it
+    constexpr int kPath = (PHASE == kPhRadix) ? 2 : 1;
+    float* pe = reinterpret_cast<float*>(hist + (kBins / 2) * kWave) + wave * kPath * (U + 1) * kWave;
     uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (U + 1) * kWave);   // [U+1][64] per wave
     const int q = blockIdx.x * kWave + lane;
     const uint32_t tree = blockIdx.y;
     const SelState st = (q < a.nq) ? a.state[q] : SelState{};
-    const bool active = (q < a.nq) && st.status == kSelSearching;
+    const bool active = (q < a.nq) && st.status == kSelSearching && st.phase == uint32_t(PHASE);
     if (!__any(active)) return;   // the same for every wave of the workgroup
     if (wave == 0) stage_query_dims(a, q, qd);
     for (int b = wave; b < kBins / 2; b += kSelWaves) hist[b * kWave + lane] = 0u;
     __syncthreads();
-    const int shift = digit_shift(pass);
-    const uint64_t prefix = st.prefix;
     uint32_t cb, ce;
     wave_chunks(1u << U, cb, ce);
     const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
     auto count = [&](uint32_t dgt) {
         atomicAdd(&hist[(dgt >> 1) * kWave + lane], (dgt & 1u) ? 65536u : 1u);
     };
-    if (shift >= 32) {
-        // the digit and the fixed prefix lie within the eff bits
-        const int s32 = shift - 32;
-        const uint32_t pfx = uint32_t(prefix);
+    if (PHASE == kPhSample) {
+        const uint32_t base = st.base;
         walk_tree<CH, false>(nodes, a.H, cb, ce, qd, pe, pn,
                              [&](uint32_t, const float* ef, const uint32_t*) {
                                  if (!active) return;
 #pragma unroll
                                  for (int x = 0; x < (1 << CH); ++x) {
-                                     const uint32_t E = eff_bits(ef[x]);
-                                     if ((E >> (s32 + kDigitBits)) == pfx)
-                                         count((E >> s32) & (kBins - 1));
+                                     const uint32_t v = eff_bits(ef[x]) >> kSampleShift;
+                                     count(v <= base ? 0u : min(v - base, uint32_t(kBins - 1)));
                                  }
                              });
-    } else {
-        walk_tree<CH, true>(nodes, a.H, cb, ce, qd, pe, pn,
-                            [&](uint32_t, const float* ef, const uint32_t* en) {
-                                if (!active) return;
+    } else if (PHASE == kPhWindow) {
+        const uint32_t base = st.base;
+        uint32_t under = 0;
+        walk_tree<CH, false>(nodes, a.H, cb, ce, qd, pe, pn,
+                             [&](uint32_t, const float* ef, const uint32_t*) {
+                                 if (!active) return;
 #pragma unroll
-                                for (int x = 0; x < (1 << CH); ++x) {
-                                    const uint64_t K = leaf_key(ef[x], tree, en[x]);
-                                    if ((K >> (shift + kDigitBits)) == prefix)
-                                        count(uint32_t(K >> shift) & (kBins - 1));
-                                }
-                            });
+                                 for (int x = 0; x < (1 << CH); ++x) {
+                                     const uint32_t v = eff_bits(ef[x]) >> kWindowShift;
+                                     under += (v <= base) ? 1u : 0u;
+                                     const uint32_t r = v - base - 1u;   // bin - 1
+                                     if (r < uint32_t(kBins - 2)) count(r + 1u);
+                                 }
+                             });
+        // a slice holds at most 2^15 leaves: the low half of word 0 cannot carry
+        if (active) atomicAdd(&hist[lane], under);
+    } else {
+        const int cs = int(st.cs);
+        if (__any(active && cs < 32 + kDigitBits)) {
+            // some digit reaches below the eff bits: full keys for every lane
+            const int fshift = cs > kDigitBits ? cs - kDigitBits : 0;
+            const uint32_t fmask = (1u << (cs - fshift)) - 1u;
+            walk_tree<CH, true>(nodes, a.H, cb, ce, qd, pe, pn,
+                                [&](uint32_t, const float* ef, const uint32_t* en) {
+                                    if (!active) return;
+#pragma unroll
+                                    for (int x = 0; x < (1 << CH); ++x) {
+                                        const uint64_t K = leaf_key(ef[x], tree, en[x]);
+                                        if ((K >> cs) == st.prefix) count(uint32_t(K >> fshift) & fmask);
+                                    }
+                                });
+        } else {
+            const int sh = cs - 32 - kDigitBits;
+            const uint32_t base = uint32_t(st.prefix) << kDigitBits;
+            walk_tree<CH, false>(nodes, a.H, cb, ce, qd, pe, pn,
+                                 [&](uint32_t, const float* ef, const uint32_t*) {
+                                     if (!active) return;
+#pragma unroll
+                                     for (int x = 0; x < (1 << CH); ++x) {
+                                         const uint32_t r = (eff_bits(ef[x]) >> sh) - base;
+                                         if (r < uint32_t(kBins)) count(r);
+                                     }
+                                 });
+        }
     }
     __syncthreads();
     if (!active) return;
-    const int slice = int(tree) * int(gridDim.z) + int(blockIdx.z);
+    // A radix walk may run zf = gridDim.z / zsplit workgroups per slice (few
+    // queries left): those add into the slice's row, which the pick that
+    // sent the query here has cleared.
+    const int zsplit = a.nslice / a.m;
+    const int zf = (PHASE == kPhRadix) ? int(gridDim.z) / zsplit : 1;
+    const int slice = int(tree) * (int(gridDim.z) / zf) + int(blockIdx.z) / zf;
     uint32_t* gh = a.hist + (int64_t(q) * a.nslice + slice) * kBins;
     for (int b = wave; b < kBins / 2; b += kSelWaves) {
         const uint32_t w = hist[b * kWave + lane];
-        gh[2 * b] = w & 0xFFFFu;
-        gh[2 * b + 1] = w >> 16;
+        if (zf > 1) {
+            if (w & 0xFFFFu) atomicAdd(&gh[2 * b], w & 0xFFFFu);
+            if (w >> 16) atomicAdd(&gh[2 * b + 1], w >> 16);
+        } else {
+            gh[2 * b] = w & 0xFFFFu;
+            gh[2 * b + 1] = w >> 16;
+        }
     }
 }
 
-template <int CH>
+// The final walk: marks the leaves below the query's bin and writes the
+// bin's leaves to the collect buffer.  A bin fixed on eff bits alone (cs >=
+// 32) stores eff bits (u32, first half of the query's key area); a bin that
+// reaches into the (tree, entry) bits stores full 64-bit keys.  It is
+// launched twice: FULL = false serves the workgroups whose bins are all
+// eff-bit bins, FULL = true the others (rare), each with the registers its
+// walk needs.
+template <int CH, bool FULL>
 __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
     extern __shared__ uint32_t smem[];
     const int U = a.H - CH;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     float* qd = reinterpret_cast<float*>(smem);                          // [t][64]
     uint32_t* cnt = reinterpret_cast<uint32_t*>(qd + a.t * kWave);       // [64] next collect slot
-    float* pe = reinterpret_cast<float*>(cnt + kWave) + wave * 2 * (U + 1) * kWave;
+    constexpr int kPath = FULL ? 2 : 1;
+    float* pe = reinterpret_cast<float*>(cnt + kWave) + wave * kPath * (U + 1) * kWave;
     uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (U + 1) * kWave);
     const int q = blockIdx.x * kWave + lane;
     const uint32_t tree = blockIdx.y;
-    const SelState st = (q < a.nq) ? a.state[q] : SelState{};
-    const bool all = st.status == kSelAll;
-    // Bin [lo, hi): the key range still undecided after the last pass.
-    const int shift = digit_shift(int(st.pass) - 1);
-    const uint64_t lo = st.pass ? (st.prefix << shift) : 0ull;
-    const uint64_t hi = st.pass ? ((st.prefix + 1ull) << shift) : 0ull;
+    const bool valid = q < a.nq;
+    const SelState st = valid ? a.state[q] : SelState{};
+    const bool all = valid && st.status == kSelAll;
+    const bool ready = valid && st.status == kSelReady;
+    const bool full = ready && st.cs < 32u;
+    if (__any(full) != FULL) return;   // the same for every wave of the workgroup
     // this slice's share of the bin starts at coff[q][slice]; the waves take
     // slots from a shared counter (the order of the collected keys is free)
     const int slice = int(tree) * int(gridDim.z) + int(blockIdx.z);
     if (wave == 0) {
         stage_query_dims(a, q, qd);
-        cnt[lane] = (q < a.nq && st.status == kSelReady) ? a.coff[int64_t(q) * a.nslice + slice] : 0u;
+        cnt[lane] = ready ? a.coff[int64_t(q) * a.nslice + slice] : 0u;
     }
     __syncthreads();
     uint32_t cb, ce;
     wave_chunks(1u << U, cb, ce);
     const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
-    walk_tree<CH, true>(nodes, a.H, cb, ce, qd, pe, pn,
-                        [&](uint32_t c, const float* ef, const uint32_t* en) {
-                            if (q >= a.nq) return;
-                            uint32_t bits = 0;
+    uint64_t* keys = a.ckey + int64_t(q) * kCollectCap;
+    uint32_t* effs = reinterpret_cast<uint32_t*>(keys);
+    uint32_t* codes = a.ccode + int64_t(q) * kCollectCap;
+    if (FULL) {
+        // full-key bounds for every lane: [lo, hi) is the bin, all keys of an
+        // exhausted budget lie below lo = ~0
+        uint64_t lo = 0, hi = 0;
+        if (all) {
+            lo = hi = ~0ull;
+        } else if (ready) {
+            lo = st.prefix << st.cs;
+            hi = (st.prefix + 1ull) << st.cs;
+        }
+        walk_tree<CH, true>(nodes, a.H, cb, ce, qd, pe, pn,
+                            [&](uint32_t c, const float* ef, const uint32_t* en) {
+                                if (!valid) return;
+                                uint32_t bits = 0;
 #pragma unroll
-                            for (int x = 0; x < (1 << CH); ++x) {
-                                const uint64_t K = leaf_key(ef[x], tree, en[x]);
-                                if (all || K < lo) {
-                                    bits |= 1u << x;
-                                } else if (K < hi) {
-                                    const uint32_t pos = atomicAdd(&cnt[lane], 1u);
-                                    if (pos < uint32_t(kCollectCap)) {
-                                        const int64_t o = int64_t(q) * kCollectCap + pos;
-                                        a.ckey[o] = K;
-                                        a.ccode[o] = (tree << 24) | ((c << CH) + uint32_t(x));
+                                for (int x = 0; x < (1 << CH); ++x) {
+                                    const uint64_t K = leaf_key(ef[x], tree, en[x]);
+                                    bits |= (K < lo ? 1u : 0u) << x;
+                                    if (K - lo < hi - lo) {
+                                        const uint32_t pos = atomicAdd(&cnt[lane], 1u);
+                                        if (pos < uint32_t(kCollectCap)) {
+                                            if (full)
+                                                keys[pos] = K;
+                                            else
+                                                effs[pos] = uint32_t(K >> 32);
+                                            codes[pos] = (tree << 24) | ((c << CH) + uint32_t(x));
+                                        }
                                     }
                                 }
-                            }
-                            a.leafbits[(int64_t(tree) * a.W + c) * a.nq + q] = bits;
-                        });
+                                a.leafbits[(int64_t(tree) * a.W + c) * a.nq + q] = bits;
+                            });
+    } else {
+        uint32_t elo = 0, ehi = 0;
+        if (all) {
+            elo = ehi = ~0u;
+        } else if (ready) {
+            const int r = int(st.cs) - 32;
+            elo = uint32_t(st.prefix << r);
+            ehi = uint32_t((st.prefix + 1ull) << r);
+        }
+        walk_tree<CH, false>(nodes, a.H, cb, ce, qd, pe, pn,
+                             [&](uint32_t c, const float* ef, const uint32_t*) {
+                                 if (!valid) return;
+                                 uint32_t bits = 0;
+#pragma unroll
+                                 for (int x = 0; x < (1 << CH); ++x) {
+                                     const uint32_t E = eff_bits(ef[x]);
+                                     bits |= (E < elo ? 1u : 0u) << x;
+                                     if (E - elo < ehi - elo) {
+                                         const uint32_t pos = atomicAdd(&cnt[lane], 1u);
+                                         if (pos < uint32_t(kCollectCap)) {
+                                             effs[pos] = E;
+                                             codes[pos] = (tree << 24) | ((c << CH) + uint32_t(x));
+                                         }
+                                     }
+                                 }
+                                 a.leafbits[(int64_t(tree) * a.W + c) * a.nq + q] = bits;
+                             });
+    }
+}
+
+// Entry node of leaf `leaf` of tree `tree` for a query (coordinates on D in
+// qd): the deepest child on the root path that lies on the far side of its
+// parent's split, or the root.  The same float32 gaps as the walk.
+__device__ uint32_t entry_node(const SelectArgs& a, const float* qd, uint32_t tree, uint32_t leaf) {
+    const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
+    uint32_t v = 0, en = 0;
+    for (int h = 0; h < a.H; ++h) {
+        const uint2 nd = nodes[v];
+        const float g = qd[nd.y] - __uint_as_float(nd.x);
+        const bool go_right = (leaf >> (a.H - 1 - h)) & 1u;
+        const bool near_right = !(g < 0.0f);
+        const uint32_t child = 2u * v + 1u + (go_right ? 1u : 0u);
+        if (go_right != near_right) en = child;
+        v = child;
+    }
+    return en;
+}
+
+// Block-wide step of a radix select over 256 bins: with hist[] complete,
+// thread 0 finds the bin holding the `left`-th smallest and publishes the
+// extended prefix, the rank left inside that bin and the bin's size.
+__device__ __forceinline__ void pick_bin(const uint32_t* hist, uint32_t cur, int w, uint32_t left,
+                                         uint32_t* out) {
+    if (threadIdx.x == 0) {
+        uint32_t d = (1u << w) - 1u;
+        for (uint32_t b = 0; b < (1u << w); ++b) {
+            if (hist[b] >= left) { d = b; break; }
+            left -= hist[b];
+        }
+        out[0] = (cur << w) | d;
+        out[1] = left;
+        out[2] = hist[d];
+    }
 }
 
 }  // namespace
 
-// Per-query initialisation: budget, state, histogram.
+// Per-query initialisation: budget and state.  Every gap's split value lies
+// within its slot's range, and float subtraction is monotone, so no eff
+// exceeds gmax = max over slots of |q - lo| and |q - hi|: the sample walk's
+// bins end at gmax's bin and reach 127 bins (15.9 octaves) below it.
 __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.nq) return;
@@ -272,100 +427,234 @@ __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, 
     const int64_t total = int64_t(a.m) << a.H;
     if (B > total) B = total;
     if (B < 0) B = 0;
+    float gmax = 0.0f;
+    for (int j = 0; j < a.t; ++j) {
+        const float v = a.Q[int64_t(q) * a.ldq + a.D[j]];
+        const float2 r = a.drange[j];
+        gmax = fmaxf(gmax, fmaxf(fabsf(v - r.x), fabsf(v - r.y)));
+    }
+    const uint32_t top = eff_bits(gmax) >> kSampleShift;
     SelState s{};
     s.budget = uint32_t(B);
+    s.cs = 63;
+    s.phase = kPhSample;
+    s.base = top > uint32_t(kBins - 1) ? top - uint32_t(kBins - 1) : 0u;
     s.status = (B == total) ? kSelAll : (B == 0 ? kSelDone : kSelSearching);
     a.state[q] = s;
 }
 
-// After a histogram pass: fix the digit holding the B-th smallest key (one
-// workgroup of 128 threads per query: thread b sums bin b over the slices),
-// and the offsets at which each slice will write its share of that bin.
-__global__ __launch_bounds__(kBins) void k_select_pick(SelectArgs a, int pass,
-                                                       uint32_t* any_searching) {
-    __shared__ uint32_t tot[kBins];
+// The decision after a counting walk for one query, given the bin totals:
+//   sample: place the window on the bin of the ceil(ns B/m)-th smallest eff
+//           of the ns sampled trees (or go to radix passes if that bin is
+//           the lowest one);
+//   window: fix the 1/128-octave bin of the B-th key if it is inside the
+//           window, else start radix passes from the top of the key;
+//   radix:  fix the digit holding the B-th key.
+// A query whose bin holds at most kCollectCap leaves is ready, and the
+// offsets at which each slice will write its share of the bin are set.
+// Returns whether the query's next walk is a radix pass; such queries set
+// flags[0] and are counted in flags[1].
+__device__ bool pick_one(const SelectArgs& a, int phase, SelState s, const uint32_t* tot,
+                         const uint32_t* h, uint32_t* flags) {
     const int q = blockIdx.x;
-    SelState s = a.state[q];
-    if (s.status != kSelSearching) return;
-    const uint32_t* h = a.hist + int64_t(q) * a.nslice * kBins;
-    uint32_t sum = 0;
-    for (int sl = 0; sl < a.nslice; ++sl) sum += h[int64_t(sl) * kBins + threadIdx.x];
-    tot[threadIdx.x] = sum;
-    __syncthreads();
-    if (threadIdx.x != 0) return;
+    const uint32_t ns = uint32_t(sample_trees(a.m));
+    // the sample covers ns of the m trees: aim at the same share of its leaves
+    const uint32_t target = (phase == kPhSample)
+                                ? uint32_t((uint64_t(s.budget) * ns + uint32_t(a.m) - 1u) / uint32_t(a.m))
+                                : s.budget;
     uint32_t cum = s.below;
     int dgt = kBins - 1;
     for (int b = 0; b < kBins; ++b) {
-        if (cum + tot[b] >= s.budget) { dgt = b; break; }
+        if (cum + tot[b] >= target) { dgt = b; break; }
         cum += tot[b];
     }
-    s.below = cum;
-    s.bincount = tot[dgt];
-    s.prefix = (s.prefix << kDigitBits) | uint64_t(dgt);
-    s.pass = uint32_t(pass + 1);
-    if (s.bincount <= uint32_t(kCollectCap) || s.pass == uint32_t(kMaxPasses)) {
-        s.status = kSelReady;
-        uint32_t off = 0;
-        for (int sl = 0; sl < a.nslice; ++sl) {
-            a.coff[int64_t(q) * a.nslice + sl] = off;
-            off += h[int64_t(sl) * kBins + dgt];
+    bool radix = false;
+    if (phase == kPhSample) {
+        if (dgt == 0) {
+            s.phase = kPhRadix;
+            radix = true;
+        } else {
+            constexpr int kRatio = kSampleShift - kWindowShift;
+            const uint32_t centre = ((s.base + uint32_t(dgt)) << kRatio) + (1u << (kRatio - 1));
+            s.base = (centre > kWindowHalf ? centre - kWindowHalf : 1u) - 1u;
+            s.phase = kPhWindow;
         }
+    } else if (phase == kPhWindow && (dgt == 0 || dgt == kBins - 1)) {
+        // outside the window: radix passes from the top (cs 63, prefix 0, below 0)
+        s.phase = kPhRadix;
+        radix = true;
     } else {
-        atomicOr(any_searching, 1u);
+        if (phase == kPhWindow) {
+            s.prefix = uint64_t(s.base) + uint64_t(dgt);   // eff bits >> kWindowShift
+            s.cs = 32u + kWindowShift;
+            s.phase = kPhRadix;
+        } else {
+            const uint32_t shift = s.cs > uint32_t(kDigitBits) ? s.cs - kDigitBits : 0u;
+            s.prefix = (s.prefix << (s.cs - shift)) | uint64_t(dgt);
+            s.cs = shift;
+        }
+        s.below = cum;
+        s.bincount = tot[dgt];
+        if (s.bincount <= uint32_t(kCollectCap) || s.cs == 0u) {
+            s.status = kSelReady;
+            uint32_t off = 0;
+            for (int sl = 0; sl < a.nslice; ++sl) {
+                a.coff[int64_t(q) * a.nslice + sl] = off;
+                off += h[int64_t(sl) * kBins + dgt];
+            }
+        } else {
+            radix = true;
+        }
+    }
+    if (radix) {
+        atomicOr(&flags[0], 1u);
+        atomicAdd(&flags[1], 1u);
     }
     a.state[q] = s;
+    return radix;
 }
 
-// Resolve the bin: a radix select (8-bit digits, from the top) over the
-// collected keys finds the (B - below)-th smallest; every collected leaf with
-// a key up to it is marked.  Keys are distinct, so exactly B leaves end up
-// marked in total.
+// After a counting walk: for the queries it served, sum each bin over the
+// slices (one workgroup of 128 threads per query, thread b takes bin b) and
+// move the query on (pick_one).
+__global__ __launch_bounds__(kBins) void k_select_pick(SelectArgs a, int phase, uint32_t* flags) {
+    __shared__ uint32_t tot[kBins];
+    __shared__ uint32_t again;
+    const int q = blockIdx.x;
+    const SelState s = a.state[q];
+    if (s.status != kSelSearching || s.phase != uint32_t(phase)) return;
+    uint32_t* h = a.hist + int64_t(q) * a.nslice * kBins;
+    // the sample walk writes the first ns * (nslice / ns) slices
+    const int ns = sample_trees(a.m);
+    const int nsl = (phase == kPhSample) ? ns * (a.nslice / ns) : a.nslice;
+    uint32_t sum = 0;
+    for (int sl = 0; sl < nsl; ++sl) sum += h[int64_t(sl) * kBins + threadIdx.x];
+    tot[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) again = pick_one(a, phase, s, tot, h, flags) ? 1u : 0u;
+    __syncthreads();
+    // a query that goes on to a radix pass gets cleared rows (that pass may
+    // add into them); thread b clears bin b, which only it has read
+    if (again)
+        for (int sl = 0; sl < a.nslice; ++sl) h[int64_t(sl) * kBins + threadIdx.x] = 0u;
+}
+
+// Resolve the bin.  The (B - below) smallest collected keys are marked in the
+// leaf bitmap; keys are distinct, so exactly B leaves end up marked in total.
+//   eff-bit bins: a radix select (8-bit digits) over the eff bits below the
+//   bin's prefix finds the threshold eff E*.  If the leaves at E* are not all
+//   taken, their (tree, entry) keys are recomputed and a second radix select
+//   over those orders the ties.
+//   full-key bins: a radix select over the 64-bit keys.
 __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
     __shared__ uint32_t hist[256];
+    __shared__ uint32_t pub[3];
+    __shared__ float qd[kMaxT];
     __shared__ uint64_t sh_prefix;
     __shared__ uint32_t sh_need;
     const int q = blockIdx.x;
     const SelState s = a.state[q];
     if (s.status != kSelReady) return;
     const uint32_t cnt = min(s.bincount, uint32_t(kCollectCap));
-    const uint64_t* keys = a.ckey + int64_t(q) * kCollectCap;
+    const uint32_t need = s.budget - s.below;
     const uint32_t* codes = a.ccode + int64_t(q) * kCollectCap;
-    if (threadIdx.x == 0) {
-        sh_prefix = 0;
-        sh_need = s.budget - s.below;
-    }
-    __syncthreads();
-    uint64_t kstar = ~0ull;
-    if (sh_need < cnt) {
-        for (int pass = 0; pass < 8; ++pass) {
-            const int shift = 56 - 8 * pass;
-            hist[threadIdx.x] = 0;
-            __syncthreads();
-            const uint64_t prefix = sh_prefix;
-            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-                const uint64_t K = keys[i];
-                if (pass == 0 || (K >> (shift + 8)) == prefix)
-                    atomicAdd(&hist[(K >> shift) & 255u], 1u);
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                uint32_t need = sh_need, d = 255;
-                for (uint32_t b = 0; b < 256; ++b) {
-                    if (hist[b] >= need) { d = b; break; }
-                    need -= hist[b];
-                }
-                sh_need = need;
-                sh_prefix = (prefix << 8) | d;
-            }
-            __syncthreads();
+    auto mark = [&](uint32_t code) {
+        const uint32_t tree = code >> 24, leaf = code & 0xFFFFFFu;
+        atomicOr(&a.leafbits[(int64_t(tree) * a.W + (leaf >> 5)) * a.nq + q], 1u << (leaf & 31u));
+    };
+    if (s.cs < 32u) {
+        const uint64_t* keys = a.ckey + int64_t(q) * kCollectCap;
+        if (threadIdx.x == 0) {
+            sh_prefix = 0;
+            sh_need = need;
         }
-        kstar = sh_prefix;
+        __syncthreads();
+        uint64_t kstar = ~0ull;
+        if (need < cnt) {
+            for (int pass = 0; pass < 8; ++pass) {
+                const int shift = 56 - 8 * pass;
+                hist[threadIdx.x] = 0;
+                __syncthreads();
+                const uint64_t prefix = sh_prefix;
+                for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+                    const uint64_t K = keys[i];
+                    if (pass == 0 || (K >> (shift + 8)) == prefix)
+                        atomicAdd(&hist[(K >> shift) & 255u], 1u);
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    uint32_t left = sh_need, d = 255;
+                    for (uint32_t b = 0; b < 256; ++b) {
+                        if (hist[b] >= left) { d = b; break; }
+                        left -= hist[b];
+                    }
+                    sh_need = left;
+                    sh_prefix = (prefix << 8) | d;
+                }
+                __syncthreads();
+            }
+            kstar = sh_prefix;
+        }
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x)
+            if (keys[i] <= kstar) mark(codes[i]);
+        return;
+    }
+    const uint32_t* effs = reinterpret_cast<const uint32_t*>(a.ckey + int64_t(q) * kCollectCap);
+    if (need >= cnt) {
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) mark(codes[i]);
+        return;
+    }
+    // the threshold eff: every collected key has (E >> r) == prefix at r = cs - 32
+    uint32_t cur = uint32_t(s.prefix), left = need, ties = cnt;
+    for (int r = int(s.cs) - 32; r > 0;) {
+        const int w = r < 8 ? r : 8, sh = r - w;
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+            const uint32_t E = effs[i];
+            if ((E >> r) == cur) atomicAdd(&hist[(E >> sh) & ((1u << w) - 1u)], 1u);
+        }
+        __syncthreads();
+        pick_bin(hist, cur, w, left, pub);
+        __syncthreads();
+        cur = pub[0];
+        left = pub[1];
+        ties = pub[2];
+        r = sh;
+    }
+    const uint32_t estar = cur;
+    if (left == ties) {
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x)
+            if (effs[i] <= estar) mark(codes[i]);
+        return;
+    }
+    // ties at E* cross the budget: order them by (tree, entry node)
+    for (int j = threadIdx.x; j < a.t; j += blockDim.x) qd[j] = a.Q[int64_t(q) * a.ldq + a.D[j]];
+    __syncthreads();
+    auto tie_key = [&](uint32_t code) {
+        const uint32_t tree = code >> 24;
+        return (tree << 24) | entry_node(a, qd, tree, code & 0xFFFFFFu);
+    };
+    uint32_t tcur = 0;
+    for (int r = 32; r > 0;) {
+        const int sh = r - 8;
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+            if (effs[i] != estar) continue;
+            const uint32_t tk = tie_key(codes[i]);
+            if (r == 32 || (tk >> r) == tcur) atomicAdd(&hist[(tk >> sh) & 255u], 1u);
+        }
+        __syncthreads();
+        pick_bin(hist, tcur, 8, left, pub);
+        __syncthreads();
+        tcur = pub[0];
+        left = pub[1];
+        r = sh;
     }
     for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-        if (keys[i] <= kstar) {
-            const uint32_t tree = codes[i] >> 24, leaf = codes[i] & 0xFFFFFFu;
-            atomicOr(&a.leafbits[(int64_t(tree) * a.W + (leaf >> 5)) * a.nq + q], 1u << (leaf & 31u));
-        }
+        const uint32_t E = effs[i];
+        if (E < estar || (E == estar && tie_key(codes[i]) <= tcur)) mark(codes[i]);
     }
 }
 
@@ -377,35 +666,50 @@ int select_slices_per_tree(int H) {
     return z;
 }
 
-hipError_t launch_select_walk(const SelectArgs& a, int pass, bool collect, hipStream_t st) {
+hipError_t launch_select_walk(const SelectArgs& a, int phase, bool collect, hipStream_t st,
+                              int zfine) {
     const int CH = a.H < 5 ? a.H : 5;
     const int U = a.H - CH;
-    const size_t lds = size_t(a.t) * kWave * 4 + (collect ? size_t(kWave) * 4 : size_t(kBins / 2) * kWave * 4) +
-                       size_t(kSelWaves) * 2 * (U + 1) * kWave * 4;
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    // staged query dims, histogram or collect counters, path state (eff, plus
+    // the entry node in walks that may need full keys)
+    auto lds_of = [&](bool entry) {
+        return size_t(a.t) * kWave * 4 + (collect ? size_t(kWave) * 4 : size_t(kBins / 2) * kWave * 4) +
+               size_t(kSelWaves) * (entry ? 2 : 1) * (U + 1) * kWave * 4;
+    };
+    if (lds_of(true) > 160 * 1024) return hipErrorInvalidValue;
     const int zsplit = select_slices_per_tree(a.H);
     if (a.nslice != a.m * zsplit) return hipErrorInvalidValue;
-    dim3 grid((a.nq + kWave - 1) / kWave, a.m, zsplit);
+    // the sample walk covers the first sample_trees(m) trees, in as many
+    // slices as a full walk has
+    const bool sample = !collect && phase == kPhSample;
+    const int ns = sample_trees(a.m);
+    const bool fine = !collect && phase == kPhRadix && zfine > 1;
+    dim3 grid((a.nq + kWave - 1) / kWave, sample ? ns : a.m,
+              sample ? a.nslice / ns : (fine ? zsplit * zfine : zsplit));
+    auto go = [&](const void* fn, bool entry) {
+        const size_t lds = lds_of(entry);
+        if (lds > 65536)
+            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        void* args[] = {const_cast<SelectArgs*>(&a)};
+        return hipLaunchKernel(fn, grid, dim3(kSelThreads), args, lds, st);
+    };
 #define GF_WALK(CHV)                                                                         \
     case CHV:                                                                                \
         if (collect) {                                                                       \
-            if (lds > 65536)                                                                 \
-                (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select_collect<CHV>), \
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
-            hipLaunchKernelGGL(k_select_collect<CHV>, grid, dim3(kSelThreads), lds, st, a);  \
-        } else {                                                                             \
-            if (lds > 65536)                                                                 \
-                (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select_hist<CHV>), \
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
-            hipLaunchKernelGGL(k_select_hist<CHV>, grid, dim3(kSelThreads), lds, st, a, pass); \
+            const hipError_t e = go(reinterpret_cast<const void*>(&k_select_collect<CHV, false>), false); \
+            if (e != hipSuccess) return e;                                                   \
+            return go(reinterpret_cast<const void*>(&k_select_collect<CHV, true>), true);        \
         }                                                                                    \
-        break;
+        if (phase == kPhSample)                                                              \
+            return go(reinterpret_cast<const void*>(&k_select_hist<CHV, kPhSample>), false);     \
+        if (phase == kPhWindow)                                                              \
+            return go(reinterpret_cast<const void*>(&k_select_hist<CHV, kPhWindow>), false);     \
+        return go(reinterpret_cast<const void*>(&k_select_hist<CHV, kPhRadix>), true);
     switch (CH) {
         GF_WALK(0) GF_WALK(1) GF_WALK(2) GF_WALK(3) GF_WALK(4) GF_WALK(5)
         default: return hipErrorInvalidValue;
     }
 #undef GF_WALK
-    return hipGetLastError();
 }
 
 }  // namespace gf

@@ -58,6 +58,22 @@ def case_data(name):
         X = rng.integers(0, 8, (5000, 40)).astype(np.float32)
         Q = (X[rng.integers(0, 5000, 60)] + rng.integers(-1, 2, (60, 40))).astype(np.float32)
         return X, Q, 4, 6, 8
+    if name == "scales":
+        # per-dimension scales over six decades: trees whose top splits fall
+        # on different dimensions have very different eff distributions
+        rng = np.random.default_rng(11)
+        sc = 10.0 ** rng.uniform(-3, 3, 16)
+        X = (rng.standard_normal((8000, 16)) * sc).astype(np.float32)
+        Q = (X[rng.integers(0, 8000, 60)] + 0.05 * sc * rng.standard_normal((60, 16))).astype(np.float32)
+        return X, Q, 4, 6, 8
+    if name == "binary-ties":
+        # 0/1 coordinates and queries at 0.5: every gap is +-0.5, so all
+        # leaves but the home leaves share one eff (131,070 of them)
+        rng = np.random.default_rng(21)
+        prob = np.linspace(0.1, 0.45, 8)
+        X = (rng.random((40_000, 8)) < prob).astype(np.float32)
+        Q = np.full((6, 8), 0.5, np.float32)
+        return X, Q, 2, 4, 1
     raise KeyError(name)
 
 
@@ -86,6 +102,16 @@ CASES = [  # (name, k, c, eps)
     ("multi-d2048", 10, 512, 0.0),
     ("single-leaf", 4, 1, 0.0),
     ("quantised", 5, 150, 0.0),
+    # budgets below the number of trees (the sample's lowest bin), windows
+    # that miss the threshold, ties at the threshold crossing the budget, and
+    # a bin that stays above the collect capacity down into the (tree, entry) bits
+    ("quantised", 5, 1, 0.0),
+    ("quantised", 5, 37, 0.0),
+    ("ragged-3001-77", 7, 3, 0.0),
+    ("scales", 10, 20, 0.0),
+    ("scales", 10, 200, 0.0),
+    ("scales", 10, 900, 0.0),
+    ("binary-ties", 3, 50_000, 0.0),
 ]
 
 
@@ -154,6 +180,23 @@ def test_per_query_budgets():
         ref = oracle.search(Fo, X, Q[i:i + 1], 3, int(cpq[i]))
         assert leaf_set_from_bits(lb[i]) == set(ref["opened"][0].tolist())
         check_knn(ids[i:i + 1], dd[i:i + 1], ref["ids"], ref["dists"], X=X, Q=Q[i:i + 1])
+
+
+def test_few_queries_left_for_radix_passes():
+    """Budgets of one or two leaves (below what the sample walk can place)
+    send a handful of queries to radix passes while the rest take the
+    window: those passes run split finer than the tree slices, adding into
+    the slice histograms."""
+    X, Q, Fg, Fo, _ = forests("gauss-10k-128")
+    cpq = np.full(len(Q), 256, np.int32)
+    cpq[[0, 17, 50, 99]] = [1, 2, 1, 2]
+    lb = np.zeros((len(Q), Fg.m, Fg.leaf_words), np.uint32)
+    geraf.query_trace(Fg, Q, 1, leaf_bits=lb, checks_per_query=cpq)
+    for c in np.unique(cpq):
+        sel = np.nonzero(cpq == c)[0]
+        ref = oracle.search(Fo, X, np.ascontiguousarray(Q[sel]), 1, int(c))
+        for j, i in enumerate(sel):
+            assert leaf_set_from_bits(lb[i]) == set(ref["opened"][j].tolist()), f"query {i}"
 
 
 def test_exhaustive_budget_is_brute_force():
