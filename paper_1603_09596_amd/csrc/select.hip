@@ -20,10 +20,10 @@
 //     tree slice) without atomics).  The trees are drawn alike, so the
 //     ceil(2B/m)-th smallest eff of trees 0 and 1 lies close to the B-th
 //     smallest of the forest: a walk over those two trees finds it in bins
-//     of 1/8 octave, and one walk over every tree then counts 126 bins of 1/128
-//     octave around it, plus a bin for all keys below the window and one for
-//     all keys above.  The estimate only places the window; the counts are
-//     exact.  A query whose B-th key falls outside the window, or whose bin
+//     of 1/8 octave, and one walk over every tree then counts 62 bins of
+//     1/128 octave around it (a quarter octave either way) and the keys
+//     below the window.  The estimate only places the window; the counts
+//     are exact.  A query whose B-th key falls outside the window, or whose bin
 //     still holds more than kCollectCap leaves, continues with exact radix
 //     passes over the 64-bit key (7-bit digits);
 //   * a final walk that marks every leaf below the bin in the query's leaf
@@ -52,10 +52,11 @@ constexpr int kBins = 1 << kDigitBits;   // 128
 
 // Bins of the sample walk: eff bits >> 20 (exponent and 3 mantissa bits,
 // 1/8 octave); of the window walk: eff bits >> 16 (1/128 octave).  Window
-// bins 1..126 are centred on the sampled bin.
+// bins 1..62 are centred on the sampled bin.
 constexpr int kSampleShift = 20;
 constexpr int kWindowShift = 16;
-constexpr uint32_t kWindowHalf = 63;
+constexpr int kWinBins = 64;          // window bins 1..62 inside, 0 below
+constexpr uint32_t kWindowHalf = 31;   // bin 1 lies 31 bins below the centre
 
 // Trees walked by the sample walk: two where the forest has them (the
 // estimate's spread over queries shrinks with the sampled leaves).
@@ -63,18 +64,21 @@ __host__ __device__ inline int sample_trees(int m) { return m >= 2 ? 2 : 1; }
 
 // Walk one tree for the 64 queries of this wavefront.  Calls
 // fn(chunk, eff[32], entry[32]) for every group of 2^CH consecutive leaves
-// (leaf index = chunk * 2^CH + x).  qd: LDS [t][64] query coordinates on the
-// split set D; pe/pn: LDS [(H-CH+1)][64] path state.  With ENTRY false the
-// entry nodes are not tracked (en[] stays undefined).
+// (leaf index = chunk * 2^CH + x), eff[] holding each leaf's eff as the bit
+// pattern of a float >= +0.  qd: LDS [t][64] query coordinates on the split
+// set D; pe/pn: LDS [(H-CH+1)][64] path state.  With ENTRY false the entry
+// nodes are not tracked (en[] stays undefined).
 //
-// Child eff from the parent's eff e >= 0 and gap g: the left child is the far
-// one exactly when g >= 0, so its eff is max(e, g) (which is e when g < 0),
-// and the right child's is max(e, -g).  Such a value may be -0 where the true
-// eff is 0; keys use the eff bits without the sign bit.
+// Child eff from the parent's eff e >= +0 and gap g = q - v: the left child
+// is the far one exactly when g >= 0, so its eff is max(e, g) (which is e
+// when g < 0), and the right child's is max(e, v - q), v - q being exactly
+// -g.  For e >= +0 the float maximum equals the signed-integer maximum of
+// the bit patterns (a negative float is a negative integer, below every
+// e); the integer form needs no sign handling and never yields -0.
 template <int CH, bool ENTRY, class Fn>
 __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H,
                                           uint32_t chunk_begin, uint32_t chunk_end,
-                                          const float* qd, float* pe, uint32_t* pn, Fn&& fn) {
+                                          const float* qd, int32_t* pe, uint32_t* pn, Fn&& fn) {
     const int lane = threadIdx.x & (kWave - 1);
     const int U = H - CH;
     constexpr int NL = 1 << CH;
@@ -93,16 +97,17 @@ __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H
         // Upper path: levels h0..U-1 change between chunk c-1 and chunk c.
         int h0 = (c == cb) ? 0 : (U - 1 - __builtin_ctz(c));
         if (c == cb) {
-            pe[lane] = 0.0f;
+            pe[lane] = 0;
             if (ENTRY) pn[lane] = 0u;
         }
         for (int h = h0; h < U; ++h) {
             const uint32_t v = ((1u << h) - 1u) + (c >> (U - h));
             const uint2 nd = cnodes[v];
-            const float g = qd[nd.y * kWave + lane] - __uint_as_float(nd.x);
+            const float qv = qd[nd.y * kWave + lane], sv = __uint_as_float(nd.x);
+            const float g = qv - sv;
             const bool go_right = (c >> (U - 1 - h)) & 1u;
-            const float e = pe[h * kWave + lane];
-            pe[(h + 1) * kWave + lane] = go_right ? fmaxf(e, -g) : fmaxf(e, g);
+            const int32_t e = pe[h * kWave + lane];
+            pe[(h + 1) * kWave + lane] = max(e, __float_as_int(go_right ? sv - qv : g));
             if (ENTRY) {
                 const bool near_right = !(g < 0.0f);
                 uint32_t en = pn[h * kWave + lane];
@@ -111,20 +116,22 @@ __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H
             }
         }
         // Chunk subtree, breadth-first: level j holds nodes base_j + (c << j) + x.
-        float ef[NL];
+        int32_t ef[NL];
         uint32_t en[NL];
         ef[0] = pe[U * kWave + lane];
         if (ENTRY) en[0] = pn[U * kWave + lane];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const uint32_t row = ((1u << (U + j)) - 1u) + (c << j);
+            cnode* rowp = cnodes + row;
 #pragma unroll
             for (int x = (1 << j) - 1; x >= 0; --x) {
-                const uint2 nd = cnodes[row + uint32_t(x)];
-                const float g = qd[nd.y * kWave + lane] - __uint_as_float(nd.x);
-                const float e = ef[x];
-                ef[2 * x] = fmaxf(e, g);
-                ef[2 * x + 1] = fmaxf(e, -g);
+                const uint2 nd = rowp[x];
+                const float qv = qd[nd.y * kWave + lane], sv = __uint_as_float(nd.x);
+                const float g = qv - sv;
+                const int32_t e = ef[x];
+                ef[2 * x] = max(e, __float_as_int(g));
+                ef[2 * x + 1] = max(e, __float_as_int(sv - qv));
                 if (ENTRY) {
                     const bool near_right = !(g < 0.0f);
                     const uint32_t n = en[x];
@@ -134,14 +141,16 @@ __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H
                 }
             }
         }
-        fn(c, ef, en);
+        fn(c, reinterpret_cast<const uint32_t*>(ef), en);
     }
 }
 
 __device__ __forceinline__ uint32_t eff_bits(float eff) { return __float_as_uint(eff) & 0x7FFFFFFFu; }
 
-__device__ __forceinline__ uint64_t leaf_key(float eff, uint32_t tree, uint32_t entry) {
-    return (uint64_t(eff_bits(eff)) << 32) | (uint64_t(tree) << 24) | uint64_t(entry);
+// eff bits of a walk (already free of the sign bit)
+
+__device__ __forceinline__ uint64_t leaf_key(uint32_t eff, uint32_t tree, uint32_t entry) {
+    return (uint64_t(eff) << 32) | (uint64_t(tree) << 24) | uint64_t(entry);
 }
 
 // Shared setup of a walk kernel: stage q_D of the 64 queries into LDS.
@@ -171,7 +180,7 @@ __device__ __forceinline__ void wave_chunks(uint32_t nchunks, uint32_t& cb, uint
 // One counting walk (PHASE kPhSample, kPhWindow or kPhRadix) for the
 // queries whose next walk it is.  The sample walk counts every leaf of its
 // trees, bin 0 taking all keys at or below the window (whose top bin holds
-// the bound on every eff).  The window walk counts the leaves inside its 126
+// the bound on every eff).  The window walk counts the leaves inside its 62
 // bins, keeps the number below the window in a register (bin 0) and drops
 // those above it.  A radix walk counts the leaves under the fixed prefix by
 // their next digit.
@@ -184,7 +193,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
     uint32_t* hist = reinterpret_cast<uint32_t*>(qd + a.t * kWave);      // [64][64] packed u16 pairs
     // path state per wave: eff, and the entry node where a walk tracks it
     constexpr int kPath = (PHASE == kPhRadix) ? 2 : 1;
-    float* pe = reinterpret_cast<float*>(hist + (kBins / 2) * kWave) + wave * kPath * (U + 1) * kWave;
+    int32_t* pe = reinterpret_cast<int32_t*>(hist + (kBins / 2) * kWave) + wave * kPath * (U + 1) * kWave;
     uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (U + 1) * kWave);   // [U+1][64] per wave
     const int q = blockIdx.x * kWave + lane;
     const uint32_t tree = blockIdx.y;
@@ -203,30 +212,29 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
     if (PHASE == kPhSample) {
         const uint32_t base = st.base;
         walk_tree<CH, false>(nodes, a.H, cb, ce, qd, pe, pn,
-                             [&](uint32_t, const float* ef, const uint32_t*) {
+                             [&](uint32_t, const uint32_t* ef, const uint32_t*) {
                                  if (!active) return;
 #pragma unroll
                                  for (int x = 0; x < (1 << CH); ++x) {
-                                     const uint32_t v = eff_bits(ef[x]) >> kSampleShift;
+                                     const uint32_t v = ef[x] >> kSampleShift;
                                      count(v <= base ? 0u : min(v - base, uint32_t(kBins - 1)));
                                  }
                              });
     } else if (PHASE == kPhWindow) {
-        const uint32_t base = st.base;
-        uint32_t under = 0;
+        // plain 32-bit counters, kWinBins per lane: bin b = 1..kWinBins-2 holds
+        // (E >> kWindowShift) == base + b, bin 0 everything below, bin
+        // kWinBins-1 everything above (every leaf is counted, no branch)
+        const int base = int(st.base);
         walk_tree<CH, false>(nodes, a.H, cb, ce, qd, pe, pn,
-                             [&](uint32_t, const float* ef, const uint32_t*) {
+                             [&](uint32_t, const uint32_t* ef, const uint32_t*) {
                                  if (!active) return;
 #pragma unroll
                                  for (int x = 0; x < (1 << CH); ++x) {
-                                     const uint32_t v = eff_bits(ef[x]) >> kWindowShift;
-                                     under += (v <= base) ? 1u : 0u;
-                                     const uint32_t r = v - base - 1u;   // bin - 1
-                                     if (r < uint32_t(kBins - 2)) count(r + 1u);
+                                     const int v = int(ef[x] >> kWindowShift);
+                                     const int bin = min(max(v - base, 0), kWinBins - 1);
+                                     atomicAdd(&hist[bin * kWave + lane], 1u);
                                  }
                              });
-        // a slice holds at most 2^15 leaves: the low half of word 0 cannot carry
-        if (active) atomicAdd(&hist[lane], under);
     } else {
         const int cs = int(st.cs);
         if (__any(active && cs < 32 + kDigitBits)) {
@@ -234,7 +242,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
             const int fshift = cs > kDigitBits ? cs - kDigitBits : 0;
             const uint32_t fmask = (1u << (cs - fshift)) - 1u;
             walk_tree<CH, true>(nodes, a.H, cb, ce, qd, pe, pn,
-                                [&](uint32_t, const float* ef, const uint32_t* en) {
+                                [&](uint32_t, const uint32_t* ef, const uint32_t* en) {
                                     if (!active) return;
 #pragma unroll
                                     for (int x = 0; x < (1 << CH); ++x) {
@@ -246,11 +254,11 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
             const int sh = cs - 32 - kDigitBits;
             const uint32_t base = uint32_t(st.prefix) << kDigitBits;
             walk_tree<CH, false>(nodes, a.H, cb, ce, qd, pe, pn,
-                                 [&](uint32_t, const float* ef, const uint32_t*) {
+                                 [&](uint32_t, const uint32_t* ef, const uint32_t*) {
                                      if (!active) return;
 #pragma unroll
                                      for (int x = 0; x < (1 << CH); ++x) {
-                                         const uint32_t r = (eff_bits(ef[x]) >> sh) - base;
+                                         const uint32_t r = (ef[x] >> sh) - base;
                                          if (r < uint32_t(kBins)) count(r);
                                      }
                                  });
@@ -265,6 +273,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
     const int zf = (PHASE == kPhRadix) ? int(gridDim.z) / zsplit : 1;
     const int slice = int(tree) * (int(gridDim.z) / zf) + int(blockIdx.z) / zf;
     uint32_t* gh = a.hist + (int64_t(q) * a.nslice + slice) * kBins;
+    if (PHASE == kPhWindow) {
+        for (int b = wave; b < kBins; b += kSelWaves) gh[b] = b < kWinBins ? hist[b * kWave + lane] : 0u;
+        return;
+    }
     for (int b = wave; b < kBins / 2; b += kSelWaves) {
         const uint32_t w = hist[b * kWave + lane];
         if (zf > 1) {
@@ -292,7 +304,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
     float* qd = reinterpret_cast<float*>(smem);                          // [t][64]
     uint32_t* cnt = reinterpret_cast<uint32_t*>(qd + a.t * kWave);       // [64] next collect slot
     constexpr int kPath = FULL ? 2 : 1;
-    float* pe = reinterpret_cast<float*>(cnt + kWave) + wave * kPath * (U + 1) * kWave;
+    int32_t* pe = reinterpret_cast<int32_t*>(cnt + kWave) + wave * kPath * (U + 1) * kWave;
     uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (U + 1) * kWave);
     const int q = blockIdx.x * kWave + lane;
     const uint32_t tree = blockIdx.y;
@@ -327,7 +339,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
             hi = (st.prefix + 1ull) << st.cs;
         }
         walk_tree<CH, true>(nodes, a.H, cb, ce, qd, pe, pn,
-                            [&](uint32_t c, const float* ef, const uint32_t* en) {
+                            [&](uint32_t c, const uint32_t* ef, const uint32_t* en) {
                                 if (!valid) return;
                                 uint32_t bits = 0;
 #pragma unroll
@@ -348,6 +360,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
                                 a.leafbits[(int64_t(tree) * a.W + c) * a.nq + q] = bits;
                             });
     } else {
+        // the bin as eff bits [elo, ehi); an exhausted budget takes every
+        // leaf (elo above every eff)
         uint32_t elo = 0, ehi = 0;
         if (all) {
             elo = ehi = ~0u;
@@ -356,15 +370,17 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
             elo = uint32_t(st.prefix << r);
             ehi = uint32_t((st.prefix + 1ull) << r);
         }
+        const uint32_t width = ehi - elo;
         walk_tree<CH, false>(nodes, a.H, cb, ce, qd, pe, pn,
-                             [&](uint32_t c, const float* ef, const uint32_t*) {
+                             [&](uint32_t c, const uint32_t* ef, const uint32_t*) {
                                  if (!valid) return;
                                  uint32_t bits = 0;
+                                 // leaves from the last down: bits doubles and takes the next bit
 #pragma unroll
-                                 for (int x = 0; x < (1 << CH); ++x) {
-                                     const uint32_t E = eff_bits(ef[x]);
-                                     bits |= (E < elo ? 1u : 0u) << x;
-                                     if (E - elo < ehi - elo) {
+                                 for (int x = (1 << CH) - 1; x >= 0; --x) {
+                                     const uint32_t E = ef[x];
+                                     bits = bits + bits + (E < elo ? 1u : 0u);
+                                     if (E - elo < width) {
                                          const uint32_t pos = atomicAdd(&cnt[lane], 1u);
                                          if (pos < uint32_t(kCollectCap)) {
                                              effs[pos] = E;
@@ -479,7 +495,7 @@ __device__ bool pick_one(const SelectArgs& a, int phase, SelState s, const uint3
             s.base = (centre > kWindowHalf ? centre - kWindowHalf : 1u) - 1u;
             s.phase = kPhWindow;
         }
-    } else if (phase == kPhWindow && (dgt == 0 || dgt == kBins - 1)) {
+    } else if (phase == kPhWindow && (dgt == 0 || dgt >= kWinBins - 1)) {
         // outside the window: radix passes from the top (cs 63, prefix 0, below 0)
         s.phase = kPhRadix;
         radix = true;
