@@ -289,6 +289,14 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
     }
 }
 
+// Whether the collect walk marks the whole bin (eff-bit bins only): when more
+// than half of it is opened, the finish then clears the rest, which takes
+// fewer scattered updates than marking the opened part.
+__device__ __forceinline__ bool premark_bin(const SelState& s) {
+    const uint32_t cnt = min(s.bincount, uint32_t(kCollectCap));
+    return s.cs >= 32u && 2u * (s.budget - s.below) > cnt;
+}
+
 // The final walk: marks the leaves below the query's bin and writes the
 // bin's leaves to the collect buffer.  A bin fixed on eff bits alone (cs >=
 // 32) stores eff bits (u32, first half of the query's key area); a bin that
@@ -371,6 +379,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
             ehi = uint32_t((st.prefix + 1ull) << r);
         }
         const uint32_t width = ehi - elo;
+        // marked here: below the bin, or below its top where the bin is premarked
+        const uint32_t mlo = (ready && premark_bin(st)) ? ehi : elo;
         walk_tree<CH, false>(nodes, a.H, cb, ce, qd, pe, pn,
                              [&](uint32_t c, const uint32_t* ef, const uint32_t*) {
                                  if (!valid) return;
@@ -379,7 +389,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
 #pragma unroll
                                  for (int x = (1 << CH) - 1; x >= 0; --x) {
                                      const uint32_t E = ef[x];
-                                     bits = bits + bits + (E < elo ? 1u : 0u);
+                                     bits = bits + bits + (E < mlo ? 1u : 0u);
                                      if (E - elo < width) {
                                          const uint32_t pos = atomicAdd(&cnt[lane], 1u);
                                          if (pos < uint32_t(kCollectCap)) {
@@ -395,18 +405,22 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
 
 // Entry node of leaf `leaf` of tree `tree` for a query (coordinates on D in
 // qd): the deepest child on the root path that lies on the far side of its
-// parent's split, or the root.  The same float32 gaps as the walk.
+// parent's split, or the root.  The same float32 gaps as the walk.  The path
+// follows from the leaf index alone, so all node loads are independent.
 __device__ uint32_t entry_node(const SelectArgs& a, const float* qd, uint32_t tree, uint32_t leaf) {
     const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
-    uint32_t v = 0, en = 0;
-    for (int h = 0; h < a.H; ++h) {
-        const uint2 nd = nodes[v];
-        const float g = qd[nd.y] - __uint_as_float(nd.x);
-        const bool go_right = (leaf >> (a.H - 1 - h)) & 1u;
-        const bool near_right = !(g < 0.0f);
-        const uint32_t child = 2u * v + 1u + (go_right ? 1u : 0u);
-        if (go_right != near_right) en = child;
-        v = child;
+    const int H = a.H;
+    uint32_t en = 0;
+#pragma unroll
+    for (int h = 0; h < 24; ++h) {   // tree depth is at most 23
+        if (h < H) {
+            const uint32_t v = ((1u << h) - 1u) + (leaf >> (H - h));
+            const uint2 nd = nodes[v];
+            const float g = qd[nd.y] - __uint_as_float(nd.x);
+            const bool go_right = (leaf >> (H - 1 - h)) & 1u;
+            const bool near_right = !(g < 0.0f);
+            if (go_right != near_right) en = 2u * v + 1u + (go_right ? 1u : 0u);
+        }
     }
     return en;
 }
@@ -616,62 +630,83 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
         return;
     }
     const uint32_t* effs = reinterpret_cast<const uint32_t*>(a.ckey + int64_t(q) * kCollectCap);
-    if (need >= cnt) {
-        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) mark(codes[i]);
-        return;
-    }
-    // the threshold eff: every collected key has (E >> r) == prefix at r = cs - 32
-    uint32_t cur = uint32_t(s.prefix), left = need, ties = cnt;
-    for (int r = int(s.cs) - 32; r > 0;) {
-        const int w = r < 8 ? r : 8, sh = r - w;
-        hist[threadIdx.x] = 0;
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-            const uint32_t E = effs[i];
-            if ((E >> r) == cur) atomicAdd(&hist[(E >> sh) & ((1u << w) - 1u)], 1u);
-        }
-        __syncthreads();
-        pick_bin(hist, cur, w, left, pub);
-        __syncthreads();
-        cur = pub[0];
-        left = pub[1];
-        ties = pub[2];
-        r = sh;
-    }
-    const uint32_t estar = cur;
-    if (left == ties) {
-        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x)
-            if (effs[i] <= estar) mark(codes[i]);
-        return;
-    }
-    // ties at E* cross the budget: order them by (tree, entry node)
-    for (int j = threadIdx.x; j < a.t; j += blockDim.x) qd[j] = a.Q[int64_t(q) * a.ldq + a.D[j]];
-    __syncthreads();
-    auto tie_key = [&](uint32_t code) {
-        const uint32_t tree = code >> 24;
-        return (tree << 24) | entry_node(a, qd, tree, code & 0xFFFFFFu);
+    // a premarked bin (the collect walk marked all of it) clears the keys
+    // above the threshold instead of marking those up to it
+    const bool pre = premark_bin(s);
+    auto clear = [&](uint32_t code) {
+        const uint32_t tree = code >> 24, leaf = code & 0xFFFFFFu;
+        atomicAnd(&a.leafbits[(int64_t(tree) * a.W + (leaf >> 5)) * a.nq + q], ~(1u << (leaf & 31u)));
     };
-    uint32_t tcur = 0;
-    for (int r = 32; r > 0;) {
-        const int sh = r - 8;
-        hist[threadIdx.x] = 0;
+    if (need >= cnt) {
+        if (!pre)
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) mark(codes[i]);
+        return;
+    }
+    uint32_t* tks = reinterpret_cast<uint32_t*>(a.ckey + int64_t(q) * kCollectCap) + kCollectCap;
+    // keys: the eff bits, from LDS where the bin fits there
+    auto resolve = [&](const uint32_t* keys) {
+        // the threshold eff: every collected key has (E >> r) == prefix at r = cs - 32
+        uint32_t cur = uint32_t(s.prefix), left = need, ties = cnt;
+        for (int r = int(s.cs) - 32; r > 0;) {
+            const int w = r < 8 ? r : 8, sh = r - w;
+            hist[threadIdx.x] = 0;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+                const uint32_t E = keys[i];
+                if ((E >> r) == cur) atomicAdd(&hist[(E >> sh) & ((1u << w) - 1u)], 1u);
+            }
+            __syncthreads();
+            pick_bin(hist, cur, w, left, pub);
+            __syncthreads();
+            cur = pub[0];
+            left = pub[1];
+            ties = pub[2];
+            r = sh;
+        }
+        const uint32_t estar = cur;
+        if (left == ties) {
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+                const bool take = keys[i] <= estar;
+                if (pre && !take) clear(codes[i]);
+                if (!pre && take) mark(codes[i]);
+            }
+            return;
+        }
+        // ties at E* cross the budget: order them by (tree, entry node).  Each
+        // thread computes the tie keys of its own slots once, into the second
+        // half of the query's key area, and reads back only those.
+        for (int j = threadIdx.x; j < a.t; j += blockDim.x) qd[j] = a.Q[int64_t(q) * a.ldq + a.D[j]];
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-            if (effs[i] != estar) continue;
-            const uint32_t tk = tie_key(codes[i]);
-            if (r == 32 || (tk >> r) == tcur) atomicAdd(&hist[(tk >> sh) & 255u], 1u);
+            if (keys[i] != estar) continue;
+            const uint32_t code = codes[i], tree = code >> 24;
+            tks[i] = (tree << 24) | entry_node(a, qd, tree, code & 0xFFFFFFu);
         }
-        __syncthreads();
-        pick_bin(hist, tcur, 8, left, pub);
-        __syncthreads();
-        tcur = pub[0];
-        left = pub[1];
-        r = sh;
-    }
-    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const uint32_t E = effs[i];
-        if (E < estar || (E == estar && tie_key(codes[i]) <= tcur)) mark(codes[i]);
-    }
+        uint32_t tcur = 0;
+        for (int r = 32; r > 0;) {
+            const int sh = r - 8;
+            hist[threadIdx.x] = 0;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+                if (keys[i] != estar) continue;
+                const uint32_t tk = tks[i];
+                if (r == 32 || (tk >> r) == tcur) atomicAdd(&hist[(tk >> sh) & 255u], 1u);
+            }
+            __syncthreads();
+            pick_bin(hist, tcur, 8, left, pub);
+            __syncthreads();
+            tcur = pub[0];
+            left = pub[1];
+            r = sh;
+        }
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+            const uint32_t E = keys[i];
+            const bool take = E < estar || (E == estar && tks[i] <= tcur);
+            if (pre && !take) clear(codes[i]);
+            if (!pre && take) mark(codes[i]);
+        }
+    };
+    resolve(effs);
 }
 
 // Each tree is walked in ranges of at most 2^15 leaves (one workgroup per

@@ -19,8 +19,8 @@
 //                    holding it = the queries having the point as candidate.
 //   k_tile_bf16      grid (query blocks of 128, point splits): each wave keeps
 //                    its 16 queries' BF16 rows in registers as MFMA A operands;
-//                    64-point x 128-k stages of X stream into four LDS buffers
-//                    with direct global->LDS loads (three stages in flight) as
+//                    64-point x 256-k stages of X stream into three LDS buffers
+//                    with direct global->LDS loads (two stages in flight) as
 //                    B operands; the epilogue masks by the candidate bits and
 //                    keeps, per query and split, the 48 best (score, id) pairs
 //                    in LDS, shared by the 16 lanes that hold that query's row
@@ -449,6 +449,10 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
 
 }  // namespace
 
+// Point groups each workgroup of the expansion handles in turn (fewer,
+// longer-lived workgroups than one per group).
+constexpr int kExpandRepeat = 8;
+
 // Opened leaves, query-major words -> per-leaf rows of query bits.  One
 // workgroup of 32 cw threads per (leaf word f, query chunk): thread i reads
 // query (chunk 32 cw + i)'s word f (32 leaves); each wave turns its 64
@@ -482,29 +486,31 @@ __global__ __launch_bounds__(1024) void k_open_transpose(ExpandArgs a) {
 
 // Point-major candidate sets: row x of chunk c is the OR over the trees of
 // the rows of the leaves holding x.  Thread (x, w) of a 256-thread group
-// covers 256 / cw points.
+// covers 256 / cw points at a time, kExpandRepeat times.
 __global__ __launch_bounds__(256) void k_expand_points(ExpandArgs a) {
     const int per = 256 / a.cw;
-    const int64_t x = int64_t(blockIdx.x) * per + threadIdx.x / a.cw;
     const int w = int(threadIdx.x) % a.cw;
     const int chunk = blockIdx.y;
-    if (x >= a.n) return;
     const int64_t rows = int64_t(a.m) << a.H;
     const uint32_t* op = a.openT + int64_t(chunk) * rows * a.cw + w;
-    const uint32_t* lf = a.leafof + x * a.m;
-    // eight trees at a time: the leaf indices, then the rows, all in flight
-    uint32_t v = 0;
-    for (int j0 = 0; j0 < a.m; j0 += 8) {
-        uint32_t r[8];
+    for (int rep = 0; rep < kExpandRepeat; ++rep) {
+        const int64_t x = (int64_t(blockIdx.x) * kExpandRepeat + rep) * per + threadIdx.x / a.cw;
+        if (x >= a.n) return;
+        const uint32_t* lf = a.leafof + x * a.m;
+        // eight trees at a time: the leaf indices, then the rows, all in flight
+        uint32_t v = 0;
+        for (int j0 = 0; j0 < a.m; j0 += 8) {
+            uint32_t r[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) r[j] = j0 + j < a.m ? lf[j0 + j] : 0u;
-        uint32_t o[8];
+            for (int j = 0; j < 8; ++j) r[j] = j0 + j < a.m ? lf[j0 + j] : 0u;
+            uint32_t o[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) o[j] = j0 + j < a.m ? op[int64_t(r[j]) * a.cw] : 0u;
+            for (int j = 0; j < 8; ++j) o[j] = j0 + j < a.m ? op[int64_t(r[j]) * a.cw] : 0u;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v |= o[j];
+            for (int j = 0; j < 8; ++j) v |= o[j];
+        }
+        a.visT[(int64_t(chunk) * a.n + x) * a.cw + w] = v;
     }
-    a.visT[(int64_t(chunk) * a.n + x) * a.cw + w] = v;
 }
 
 // Best kk over the splits' lists, then the final ranking of the query.
@@ -554,7 +560,8 @@ hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeA
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int per = 256 / e.cw;
-    hipLaunchKernelGGL(k_expand_points, dim3(unsigned((e.n + per - 1) / per), unsigned(e.nchunk)),
+    const int64_t per_group = int64_t(per) * kExpandRepeat;
+    hipLaunchKernelGGL(k_expand_points, dim3(unsigned((e.n + per_group - 1) / per_group), unsigned(e.nchunk)),
                        dim3(256), 0, st, e);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
