@@ -97,7 +97,7 @@ struct Carve {
 struct Workspace {
     float* Qp; uint16_t* Q16; uint8_t* Q8; float* qscale; float* qnorm; int32_t* cpq;
     gf::SelState* state; uint32_t* hist; uint32_t* coff; uint64_t* ckey; uint32_t* ccode;
-    uint32_t* leafbits; uint32_t* flags; int32_t* ids; float* dists;
+    uint32_t* leafbits; uint32_t* flags; uint32_t* qlist; int32_t* ids; float* dists;
     uint32_t* openT; uint32_t* visT; uint32_t* gthr; float* part_s; int* part_i;   // tile path only
 };
 
@@ -168,6 +168,7 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Worksp
     size_t occ = c.take<uint32_t>(size_t(nb) * gf::kCollectCap);
     size_t olb = c.take<uint32_t>(size_t(nb) * F->host.m * W);
     size_t ofl = c.take<uint32_t>(8);
+    size_t oql = c.take<uint32_t>(nb);
     size_t oids = c.take<int32_t>(size_t(nb) * k);
     size_t odst = c.take<float>(size_t(nb) * k);
     size_t oopen = 0, ovis = 0, othr = 0, ops = 0, opi = 0;
@@ -205,6 +206,7 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Worksp
     w.ccode = reinterpret_cast<uint32_t*>(b + occ);
     w.leafbits = reinterpret_cast<uint32_t*>(b + olb);
     w.flags = reinterpret_cast<uint32_t*>(b + ofl);
+    w.qlist = reinterpret_cast<uint32_t*>(b + oql);
     w.ids = reinterpret_cast<int32_t*>(b + oids);
     w.dists = reinterpret_cast<float*>(b + odst);
     w.openT = tile ? reinterpret_cast<uint32_t*>(b + oopen) : nullptr;
@@ -270,7 +272,7 @@ gf::SelectArgs make_select_args(const gf_forest* F, int nb, const Workspace& w, 
     sa.drange = F->drange;
     sa.nslice = h.m * gf::select_slices_per_tree(h.H);
     sa.state = w.state; sa.hist = w.hist; sa.coff = w.coff; sa.ckey = w.ckey;
-    sa.ccode = w.ccode; sa.leafbits = w.leafbits;
+    sa.ccode = w.ccode; sa.leafbits = w.leafbits; sa.qlist = w.qlist; sa.nlist = 0;
     return sa;
 }
 
@@ -291,8 +293,12 @@ gf_status launch_selection(const gf_forest* F, const QueryJob& J, int nb, const 
         // the flags collect the window walk's queries and those the sample
         // walk sent straight to radix passes
         if (early_exit && phase != gf::kPhWindow) GF_HIP(hipMemsetAsync(w.flags + 1, 0, 8, st));
-        const int zfine = (early_exit && phase == gf::kPhRadix && int64_t(more[1]) * 16 <= nb) ? 16 : 1;
-        GF_HIP(gf::launch_select_walk(sa, phase, false, st, zfine));
+        // few queries left: a compact walk over the listed queries, each
+        // tree split finer
+        const bool sparse = early_exit && phase == gf::kPhRadix && int64_t(more[1]) * 16 <= nb;
+        gf::SelectArgs sw = sa;
+        if (sparse) sw.nlist = int(more[1]);
+        GF_HIP(gf::launch_select_walk(sw, phase, false, st, sparse ? 16 : 1));
         hipLaunchKernelGGL(gf::k_select_pick, dim3(nb), dim3(128), 0, st, sa, phase, w.flags + 1);
         GF_HIP(hipGetLastError());
         if (early_exit && phase != gf::kPhSample) {

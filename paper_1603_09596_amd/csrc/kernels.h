@@ -49,6 +49,8 @@ struct SelectArgs {
     uint64_t* ckey;        // [nq][kCollectCap] keys (or eff bits and tie keys, as u32 pairs)
     uint32_t* ccode;       // [nq][kCollectCap]
     uint32_t* leafbits;    // [m][W][nq]  (word-major, query fastest)
+    uint32_t* qlist;       // [nq] queries sent to the next radix pass, in flags[1] order
+    int nlist;             // > 0: a radix walk serves qlist[0 .. nlist) only
 };
 
 __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps);

@@ -195,7 +195,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
     constexpr int kPath = (PHASE == kPhRadix) ? 2 : 1;
     int32_t* pe = reinterpret_cast<int32_t*>(hist + (kBins / 2) * kWave) + wave * kPath * (U + 1) * kWave;
     uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (U + 1) * kWave);   // [U+1][64] per wave
-    const int q = blockIdx.x * kWave + lane;
+    // a compact radix walk serves the listed queries only
+    const int slot = int(blockIdx.x) * kWave + lane;
+    const int q = (PHASE == kPhRadix && a.nlist > 0) ? (slot < a.nlist ? int(a.qlist[slot]) : a.nq) : slot;
     const uint32_t tree = blockIdx.y;
     const SelState st = (q < a.nq) ? a.state[q] : SelState{};
     const bool active = (q < a.nq) && st.status == kSelSearching && st.phase == uint32_t(PHASE);
@@ -483,7 +485,7 @@ __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, 
 // A query whose bin holds at most kCollectCap leaves is ready, and the
 // offsets at which each slice will write its share of the bin are set.
 // Returns whether the query's next walk is a radix pass; such queries set
-// flags[0] and are counted in flags[1].
+// flags[0] and are listed in qlist at positions counted in flags[1].
 __device__ bool pick_one(const SelectArgs& a, int phase, SelState s, const uint32_t* tot,
                          const uint32_t* h, uint32_t* flags) {
     const int q = blockIdx.x;
@@ -504,8 +506,12 @@ __device__ bool pick_one(const SelectArgs& a, int phase, SelState s, const uint3
             s.phase = kPhRadix;
             radix = true;
         } else {
+            // centre: the target's place inside the sampled bin, by its rank
+            // there (linear in the bin's 16 window bins)
             constexpr int kRatio = kSampleShift - kWindowShift;
-            const uint32_t centre = ((s.base + uint32_t(dgt)) << kRatio) + (1u << (kRatio - 1));
+            const uint32_t within =
+                min(uint32_t((uint64_t(target - cum) << kRatio) / max(tot[dgt], 1u)), (1u << kRatio) - 1u);
+            const uint32_t centre = ((s.base + uint32_t(dgt)) << kRatio) + within;
             s.base = (centre > kWindowHalf ? centre - kWindowHalf : 1u) - 1u;
             s.phase = kPhWindow;
         }
@@ -538,7 +544,7 @@ __device__ bool pick_one(const SelectArgs& a, int phase, SelState s, const uint3
     }
     if (radix) {
         atomicOr(&flags[0], 1u);
-        atomicAdd(&flags[1], 1u);
+        a.qlist[atomicAdd(&flags[1], 1u)] = uint32_t(q);
     }
     a.state[q] = s;
     return radix;
@@ -735,7 +741,8 @@ hipError_t launch_select_walk(const SelectArgs& a, int phase, bool collect, hipS
     const bool sample = !collect && phase == kPhSample;
     const int ns = sample_trees(a.m);
     const bool fine = !collect && phase == kPhRadix && zfine > 1;
-    dim3 grid((a.nq + kWave - 1) / kWave, sample ? ns : a.m,
+    const int nserved = (!collect && phase == kPhRadix && a.nlist > 0) ? a.nlist : a.nq;
+    dim3 grid((nserved + kWave - 1) / kWave, sample ? ns : a.m,
               sample ? a.nslice / ns : (fine ? zsplit * zfine : zsplit));
     auto go = [&](const void* fn, bool entry) {
         const size_t lds = lds_of(entry);
