@@ -67,12 +67,12 @@ __device__ __forceinline__ void quarter_max(float& s, int& i) {
 }
 
 // Offer every lane's (sc, id) with cand set to the list of its quarter-wave.
-// The 16 lanes 16u..16u+15 share one query's list of 48 entries in LDS
-// (lane c owns entries 3c..3c+2, unsorted) and keep its current worst entry
-// (ts, ti) in registers.  The four quarters insert in parallel; a candidate
+// The 16 lanes 16u..16u+15 share one query's list of 48 entries (lane c
+// holds entries 3c..3c+2 in registers, unsorted) and keep its current worst
+// entry (ts, ti).  The four quarters insert in parallel; a candidate
 // replaces the worst entry when it precedes it.
-__device__ __forceinline__ void quarter_offer(bool cand, float sc, int id, float* rs, int* ri,
-                                              float& ts, int& ti) {
+__device__ __forceinline__ void quarter_offer(bool cand, float sc, int id, float (&vs)[kSlots],
+                                              int (&vi)[kSlots], float& ts, int& ti) {
     const int lane = threadIdx.x & (kWave - 1);
     const int quarter = lane >> 4, col = lane & 15;
     uint64_t m = __ballot(cand);
@@ -82,25 +82,16 @@ __device__ __forceinline__ void quarter_offer(bool cand, float sc, int id, float
         const float cs = __shfl(sc, src);
         const int ci = __shfl(id, src);
         const bool ins = qm != 0 && entry_before(cs, ci, ts, ti);
-        float vs[kSlots];
-        int vi[kSlots];
         int slot = -1;
 #pragma unroll
-        for (int j = 0; j < kSlots; ++j) {
-            vs[j] = rs[col * kSlots + j];
-            vi[j] = ri[col * kSlots + j];
+        for (int j = 0; j < kSlots; ++j)
             if (vs[j] == ts && vi[j] == ti) slot = j;
-        }
         const uint64_t hb = __ballot(ins && slot >= 0);
         const uint32_t hq = uint32_t(hb >> (16 * quarter)) & 0xFFFFu;
         if (ins && hq && col == __builtin_ctz(hq)) {
 #pragma unroll
             for (int j = 0; j < kSlots; ++j)
-                if (j == slot) {
-                    vs[j] = cs; vi[j] = ci;
-                    rs[col * kSlots + j] = cs;
-                    ri[col * kSlots + j] = ci;
-                }
+                if (j == slot) { vs[j] = cs; vi[j] = ci; }
         }
         float ws = vs[0];
         int wi = vi[0];
@@ -191,8 +182,6 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     // positions unit ^ (r & 15), so the contiguous 1 KB writes of the direct
     // loads and the 16-row B-operand reads are both free of bank conflicts.
     __shared__ __attribute__((aligned(1024))) uint16_t xs[kNBuf * kStageBytes / 2];
-    __shared__ float lst_s[kTWaves * 16 * kTileList];   // per wave: 16 queries x 48 entries
-    __shared__ int lst_i[kTWaves * 16 * kTileList];
     __shared__ __attribute__((aligned(1024))) uint32_t epi[kEpi];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
@@ -232,15 +221,15 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     // the A operands are complete before any direct load is issued, so the
     // compiler has no pending load of its own to wait for inside the loop
     __builtin_amdgcn_s_waitcnt(kWaitVm(0));
-    float ts[4];
-    int ti[4];
+    // the lists of this lane's four queries: kSlots entries each, in registers
+    float ts[4], ls[4][kSlots];
+    int ti[4], li[4][kSlots];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         ts[i] = __builtin_inff();
         ti[i] = 0x7FFFFFFF;
-        const int base = (wave * 16 + 4 * quarter + i) * kTileList + col * kSlots;
 #pragma unroll
-        for (int j = 0; j < kSlots; ++j) { lst_s[base + j] = __builtin_inff(); lst_i[base + j] = 0x7FFFFFFF; }
+        for (int j = 0; j < kSlots; ++j) { ls[i][j] = __builtin_inff(); li[i][j] = 0x7FFFFFFF; }
     }
 
     const int64_t pb = int64_t(split) * a.split_pts;
@@ -415,12 +404,11 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (!__ballot(bm[i] <= lim[i])) continue;
-                const int rbase = (wave * 16 + 4 * quarter + i) * kTileList;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const int x = int(pb) + t * kTP + 16 * b + col;
                     const bool cand = ((word[b] >> i) & 1u) && acc[b][i] <= lim[i];
-                    quarter_offer(cand, acc[b][i], x, lst_s + rbase, lst_i + rbase, ts[i], ti[i]);
+                    quarter_offer(cand, acc[b][i], x, ls[i], li[i], ts[i], ti[i]);
                     lim[i] = fminf(lim[i], ts[i]);
                 }
                 // publish a full list's worst score as a bound for the other splits
@@ -437,11 +425,10 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         const int q = q0 + 4 * quarter + i;
         if (q < a.nq) {
             const int64_t base = (int64_t(q) * a.nsplit + split) * kTileList;
-            const int rbase = (wave * 16 + 4 * quarter + i) * kTileList;
 #pragma unroll
             for (int j = 0; j < kSlots; ++j) {
-                a.part_s[base + col * kSlots + j] = lst_s[rbase + col * kSlots + j];
-                a.part_i[base + col * kSlots + j] = lst_i[rbase + col * kSlots + j];
+                a.part_s[base + col * kSlots + j] = ls[i][j];
+                a.part_i[base + col * kSlots + j] = li[i][j];
             }
         }
     }
