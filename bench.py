@@ -202,8 +202,8 @@ def main():
                          "kernel of known size that scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the query path is "
-              "measured on one MI355X and multi-GPU runs are not part of this build.",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the query path is "
+              "measured on a single MI355X; sharding across GPUs is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -45,7 +45,7 @@ typedef enum {
     GF_EINVAL = -1,          /* invalid argument (nothing was launched) */
     GF_ENOMEM = -2,          /* host or device allocation failed */
     GF_EHIP = -3,            /* a HIP runtime call failed */
-    GF_EUNSUPPORTED = -4,    /* valid request outside this build's limits */
+    GF_EUNSUPPORTED = -4,    /* valid request outside the library's limits */
     GF_EINTERNAL = -5        /* an internal consistency check failed */
 } gf_status;
 
