@@ -18,6 +18,11 @@ Prints one JSON line.  Also reports:
   cpu_baseline  the FP64 oracle, searching a bounded sample of the same
                 queries on the host's cores (its own forest build excluded).
 
+`--workload` runs one of the other recipes in its own form and at its own
+budget instead (gauss-10k-128 and sphere-100k-1000 in FP32, gauss-200k-10000
+in FP8 with FP32 re-rank of the best 40), with the same line and the same
+roofline and baseline objects; the FP32 form is timed beside the FP8 one.
+
 `--multi` measures the multi-index launch instead and prints its own line:
 the multi-20 recipe (20 indexes of uneven n and d, per-query budgets,
 scaled by --multi-scale), FP32 form, as one gf_query_multi graph launch,
@@ -39,9 +44,11 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "desc-1m-960"
 CHECKS_AT_090 = 114688         # smallest c on a 8192 grid with recall@10 >= 0.90 (oracle 200-query and GPU 500-query samples)
+# the form each recipe is measured in (the FP32 form is timed beside the reduced ones)
+FORMS = {"desc-1m-960": "bf16", "gauss-200k-10000": "fp8",
+         "sphere-100k-1000": "fp32", "gauss-10k-128": "fp32"}
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16
-PMC_FILE = os.path.join(ROOT, "profiles", "pmc_desc-1m-960.txt")
 
 
 def log(*a):
@@ -67,11 +74,16 @@ def scan_bytes_per_launch(F, nq, ncand_total, form, k, kk, checks):
     rows (+ their norms), opened leaves' point ids, leaf-bitmap words, the
     FP32 rows re-measured by the re-rank, the query rows, the outputs."""
     ld32 = (F.d + 3) // 4 * 4
-    ld16 = (F.d + 7) // 8 * 8
+    ld16 = (F.d + 31) // 32 * 32
+    ld8 = (F.d + 15) // 16 * 16
     if form == "bf16":
         row = ld16 * 2 + 4
         rerank = nq * kk * ld32 * 4
         qrow = ld16 * 2 + ld32 * 4
+    elif form == "fp8":
+        row = ld8 + 8                      # e4m3 row, its scale and its norm
+        rerank = nq * kk * ld32 * 4
+        qrow = ld8 + ld32 * 4
     else:
         row = ld32 * 4
         rerank = 0
@@ -82,14 +94,15 @@ def scan_bytes_per_launch(F, nq, ncand_total, form, k, kk, checks):
     return ncand_total * row + rerank + perm + bits + nq * qrow + nq * k * 8
 
 
-def pmc_traffic(kernel):
+def pmc_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
-    summary, or None when absent, for another kernel, or taken on a
-    different source of that kernel."""
-    if not os.path.exists(PMC_FILE):
+    summary of `workload`, or None when absent, for another kernel, or taken
+    on a different source of that kernel."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{workload}.txt")
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(PMC_FILE):
+    for line in open(path):
         if ":" in line:
             key, v = line.split(":", 1)
             vals[key.strip()] = v.strip()
@@ -187,8 +200,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--checks", type=int, default=CHECKS_AT_090)
-    ap.add_argument("--nq", type=int, default=10_000)
+    ap.add_argument("--workload", default=WORKLOAD, choices=sorted(FORMS),
+                    help="recipe to measure (default: the headline desc-1m-960, BF16 form)")
+    ap.add_argument("--checks", type=int, default=None,
+                    help="budget c (default: the smallest c reaching recall@10 >= 0.90 on "
+                         "desc-1m-960, the recipe's own c otherwise)")
+    ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--recall-sample", type=int, default=500)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -216,14 +233,17 @@ def main():
     geraf.load()
     if args.multi:
         return multi_bench(args, torch, geraf, workloads, dev)
+    name = args.workload
+    form = FORMS[name]
     t0 = time.perf_counter()
-    w = workloads.make(WORKLOAD, nq=args.nq)
-    log(f"[bench] workload {WORKLOAD}: X {w.X.shape} Q {w.Q.shape} in {time.perf_counter() - t0:.1f}s")
+    w = workloads.make(name, nq=args.nq)
+    log(f"[bench] workload {name}: X {w.X.shape} Q {w.Q.shape} in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    F = geraf.build_forest(w.X, w.m, w.t, w.p, w.seed, forms=("bf16",))
+    F = geraf.build_forest(w.X, w.m, w.t, w.p, w.seed, forms=() if form == "fp32" else (form,))
     log(f"[bench] forest build + upload {time.perf_counter() - t0:.1f}s (H={F.H})")
     Q = torch.from_numpy(w.Q).to(dev)
-    nq, k, c = len(w.Q), w.k, args.checks
+    nq, k = len(w.Q), w.k
+    c = args.checks if args.checks is not None else (CHECKS_AT_090 if name == WORKLOAD else w.c)
     kk = min(64, 4 * k)
     ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
@@ -260,22 +280,33 @@ def main():
         mean["path"] = phases[-1]["path"]
         return wall, mean, ids.cpu().numpy()
 
-    wall, ph, ids_bf16 = timed("bf16", args.steps, args.warmup)
+    def scan_roofline(f, ms):
+        # the row scan (gathers + distances + best-k): algorithmic bytes per launch
+        algo = scan_bytes_per_launch(F, nq, ncand_total, f, k, kk, c)
+        achieved = algo / (ms / 1000.0) / 1e9
+        return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=pmc_traffic(f"k_scan ({f})", name),
+                    kernel=f"k_scan ({f})", bytes_per_launch=int(algo), ms_per_launch=round(ms, 3))
+
+    wall, ph, ids_main = timed(form, args.steps, args.warmup)
     value = args.steps * nq / wall
     fp32 = None
-    if not args.no_fp32:
+    if form != "fp32" and not args.no_fp32:
         wall32, ph32, ids_fp32 = timed("fp32", max(1, args.steps), 1)
         fp32 = dict(value=round(args.steps * nq / wall32, 2), path=ph32["path"],
                     scan_ms=round(ph32["scan_or_expand_ms"], 2),
                     ms_per_step=round(1000 * wall32 / max(1, args.steps), 2))
+        if ph32["path"] == "rows":
+            # the candidate gathers of the FP32 form against the HBM peak
+            fp32["roofline"] = scan_roofline("fp32", ph32["scan_or_expand_ms"])
 
     # recall@10 on a query sample against exact FP64 neighbours
     idx = np.linspace(0, nq - 1, min(args.recall_sample, nq)).astype(np.int64)
     t0 = time.perf_counter()
     gt, _ = bf.knn_ground_truth(w.X, w.Q[idx], k)
     log(f"[bench] ground truth for {len(idx)} queries {time.perf_counter() - t0:.1f}s")
-    rec_bf16 = recall_at(ids_bf16[idx], gt)
-    one_bf16 = float(np.mean([gt[i, 0] in set(ids_bf16[j].tolist()) for i, j in enumerate(idx)]))
+    rec_main = recall_at(ids_main[idx], gt)
+    one_main = float(np.mean([gt[i, 0] in set(ids_main[j].tolist()) for i, j in enumerate(idx)]))
     if fp32 is not None:
         fp32["recall@10"] = round(recall_at(ids_fp32[idx], gt), 4)
 
@@ -285,22 +316,21 @@ def main():
         achieved = flops / (ph["tile_ms"] / 1000.0) / 1e12
         roofline = dict(bound="mfma", achieved=round(achieved, 1), peak=MFMA_BF16_PEAK_TFLOPS,
                         unit="TFLOP/s", frac=round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
-                        traffic=pmc_traffic("k_tile_bf16"), kernel="k_tile_bf16",
+                        traffic=pmc_traffic("k_tile_bf16", name), kernel="k_tile_bf16",
                         flops_per_launch=int(flops), ms_per_launch=round(ph["tile_ms"], 3))
     else:
-        algo = scan_bytes_per_launch(F, nq, ncand_total, "bf16", k, kk, c)
-        achieved = algo / (ph["scan_or_expand_ms"] / 1000.0) / 1e9
-        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=pmc_traffic("k_scan"),
-                        kernel="k_scan (bf16)", bytes_per_launch=int(algo),
-                        ms_per_launch=round(ph["scan_or_expand_ms"], 3))
+        roofline = scan_roofline(form, ph["scan_or_expand_ms"])
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, idx, c, args.cpu_seconds, host_threads())
 
+    if name == WORKLOAD:
+        metric = "queries/s at recall@10>=0.90, 1Mx960, 16 trees; BF16 vs FP32 form"
+    else:
+        metric = f"queries/s, {name}, {form.upper()} form, c={c}, k={k}"
     out = {
-        "metric": "queries/s at recall@10>=0.90, 1Mx960, 16 trees; BF16 vs FP32 form",
+        "metric": metric,
         "value": round(value, 2),
         "unit": "queries/s",
         "n_gpus": 1,
@@ -310,13 +340,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": form,
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": int(F.n), "d": int(F.d), "m": int(F.m),
+        "config": {"workload": name, "n": int(F.n), "d": int(F.d), "m": int(F.m),
                    "t": int(F.t), "leaf": int(F.leaf), "checks": c, "k": k, "nq": nq,
-                   "form": "bf16", "rerank": kk},
-        "recall@10": round(rec_bf16, 4),
-        "1-recall@10": round(one_bf16, 4),
+                   "form": form, "rerank": kk if form != "fp32" else None},
+        f"recall@{k}": round(rec_main, 4),
+        f"1-recall@{k}": round(one_main, 4),
         "recall_sample": len(idx),
         "mean_candidates": round(ncand_total / nq, 1),
         "path": ph["path"],

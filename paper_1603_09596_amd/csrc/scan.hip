@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
+#include <cstring>
 
 #include "kernels.h"
 #include "rank.h"
@@ -121,9 +123,13 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     using C = Chunk<FORM>;
     using T = typename C::T;
     constexpr int G = kWave / LPR;     // rows per load instruction
-    // CPL == 0: rows wider than the register-resident tiles; each lane
-    // streams its chunks and reads the query from global memory (cached).
-    constexpr bool kStream = (CPL == 0);
+    // CPL <= 0: rows wider than the register-resident tiles; each lane
+    // streams its chunks.  CPL == -1 (FP32, BF16) reads the query from a copy
+    // in LDS, so the row stream cannot evict it from L2; CPL == 0 reads it
+    // from global memory, for rows whose copy would not fit beside the bitmap.
+    constexpr bool kStream = (CPL <= 0);
+    constexpr bool kQStage = (CPL < 0);
+    static_assert(!(kQStage && FORM == kFormFP8), "the FP8 query is always decoded into LDS");
     constexpr int CPLR = kStream ? 1 : CPL;
     constexpr int U = kStream ? 1 : ((FORM == kFormFP8 && CPL > 8) ? 1 : 2);
     extern __shared__ uint32_t smem[];
@@ -137,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     float* mg_d = reinterpret_cast<float*>(lists + kWaves * kListCap);   // [kWaves][64]
     int* mg_i = reinterpret_cast<int*>(mg_d + kWaves * kWave);           // [kWaves][64]
     float* rr_d = reinterpret_cast<float*>(mg_i + kWaves * kWave);       // [64]
-    float* q8f = rr_d + kWave;                                           // [ld8] (FP8 form)
+    float* q8f = rr_d + kWave;          // [ld8] decoded FP8 query, or the staged FP32 / BF16 query
 
     // 1. visited bitmap <- union of the opened leaves
     for (int64_t i = threadIdx.x; i < nbmw_pad; i += kThreads) bm[i] = 0u;
@@ -188,6 +194,11 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
         }
         __syncthreads();
         qv[0] = T{};
+    } else if constexpr (kQStage) {
+        T* qt = reinterpret_cast<T*>(q8f);
+        for (int64_t i = threadIdx.x; i < nchunks_row; i += kThreads) qt[i] = Qrow[i];
+        __syncthreads();
+        qv[0] = T{};
     } else if constexpr (kStream) {
         qv[0] = T{};
     } else {
@@ -197,6 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
             qv[j] = (ci < nchunks_row) ? Qrow[ci] : T{};
         }
     }
+    const T* Qsrc = kQStage ? reinterpret_cast<const T*>(q8f) : Qrow;
     float qn = 0.0f, qs = 0.0f;
     if (FORM != kFormFP32) qn = a.qnorm[q];
     if (FORM == kFormFP8) qs = a.qscale8[q];
@@ -260,15 +272,15 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
                                 a2 += C::score_lds(q8f + (ci + 2 * LPR) * 16, x2);
                                 a3 += C::score_lds(q8f + (ci + 3 * LPR) * 16, x3);
                             } else {
-                                a0 += C::score(Qrow[ci], x0);
-                                a1 += C::score(Qrow[ci + LPR], x1);
-                                a2 += C::score(Qrow[ci + 2 * LPR], x2);
-                                a3 += C::score(Qrow[ci + 3 * LPR], x3);
+                                a0 += C::score(Qsrc[ci], x0);
+                                a1 += C::score(Qsrc[ci + LPR], x1);
+                                a2 += C::score(Qsrc[ci + 2 * LPR], x2);
+                                a3 += C::score(Qsrc[ci + 3 * LPR], x3);
                             }
                         }
                         for (; ci < nchunks_row; ci += LPR) {
                             if constexpr (FORM == kFormFP8) a0 += C::score_lds(q8f + ci * 16, xr[ci]);
-                            else a0 += C::score(Qrow[ci], xr[ci]);
+                            else a0 += C::score(Qsrc[ci], xr[ci]);
                         }
                         acc = (a0 + a1) + (a2 + a3);
                     }
@@ -360,6 +372,20 @@ hipError_t launch_form(const ScanArgs& a, hipStream_t st, size_t lds) {
     GF_TRY(64, 8)
     GF_TRY(64, 16)
 #undef GF_TRY
+    if constexpr (FORM != kFormFP8) {
+        // wide rows: stage the query in LDS when it fits beside the bitmap
+        // (GF_SCAN_WIDE_QUERY=global keeps it in global memory, as for rows
+        // whose copy would not fit; both give the same sums)
+        const size_t lq = lds + size_t(nchunks_row) * 16;
+        const char* wq = std::getenv("GF_SCAN_WIDE_QUERY");
+        if (lq <= 160 * 1024 && !(wq && std::strcmp(wq, "global") == 0)) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan<FORM, 64, -1>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lq));
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_scan<FORM, 64, -1>), grid, block, lq, st, a);
+            return hipGetLastError();
+        }
+    }
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan<FORM, 64, 0>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;

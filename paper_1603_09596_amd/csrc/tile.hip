@@ -23,8 +23,8 @@
 //                    with direct global->LDS loads (two stages in flight) as
 //                    B operands; the epilogue masks by the candidate bits and
 //                    keeps, per query and split, the 48 best (score, id) pairs
-//                    in LDS, shared by the 16 lanes that hold that query's row
-//                    of the MFMA result.
+//                    in registers, three on each of the 16 lanes that hold
+//                    that query's row of the MFMA result.
 //   k_merge_rerank   one workgroup per query: best `kk` over the splits, then
 //                    FP32 compensated re-rank and FP64 tie re-check.
 #include <hip/hip_runtime.h>

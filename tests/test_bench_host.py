@@ -1,0 +1,39 @@
+"""Host logic of bench.py: the single-GPU guard and the algorithmic byte
+model behind roofline.achieved on the row path (no GPU needed)."""
+import os
+import subprocess
+import sys
+from types import SimpleNamespace
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("form,row", [("fp32", 1000 * 4), ("bf16", 1024 * 2 + 4), ("fp8", 1008 + 8)])
+def test_scan_bytes_per_candidate_row(form, row):
+    # d = 1000: FP32 rows padded to 1000 floats, BF16 to 1024 (one MFMA k
+    # step is 32), FP8 to 1008 bytes plus the row's scale and norm
+    F = SimpleNamespace(d=1000, n=4096, H=8, m=4, leaf_words=8)
+    base = bench.scan_bytes_per_launch(F, 3, 0, form, 10, 40, 64)
+    more = bench.scan_bytes_per_launch(F, 3, 7, form, 10, 40, 64)
+    assert more - base == 7 * row
+
+
+def test_scan_bytes_count_rerank_only_for_reduced_forms():
+    F = SimpleNamespace(d=960, n=1 << 20, H=15, m=16, leaf_words=1024)
+    nq, kk = 5, 40
+    b32 = bench.scan_bytes_per_launch(F, nq, 0, "fp32", 10, kk, 1)
+    b16 = bench.scan_bytes_per_launch(F, nq, 0, "bf16", 10, kk, 1)
+    # query rows differ by the BF16 copy (960 x 2 B); the re-rank reads kk FP32 rows
+    assert b16 - b32 == nq * 960 * 2 + nq * kk * 960 * 4

@@ -252,6 +252,7 @@ def test_repeat_runs_bit_identical():
                                            ("multi-d2048", "bf16", 10, 512),
                                            ("gauss-10k-128", "bf16", 10, 700),
                                            ("gauss-4k-10000", "fp8", 10, 2048),
+                                           ("gauss-4k-10000", "bf16", 10, 2048),
                                            ("ragged-3001-77", "fp8", 7, 300),
                                            ("sphere-20k-1000", "fp8", 5, 1024)])
 def test_reduced_precision_forms(name, form, k, c):
@@ -274,6 +275,24 @@ def test_reduced_precision_forms(name, form, k, c):
     recall = hits / max(1, int((ref["ids"] >= 0).sum()))
     print(f"{name} {form}: recall vs FP64 oracle = {recall:.4f}")
     assert recall >= 0.98
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+def test_wide_rows_query_in_lds_matches_global(form, monkeypatch):
+    """Rows wider than the register tiles (d = 10,000): the scan reads the
+    query from a copy in LDS, or from global memory where that copy would
+    not fit beside the bitmap.  Same chunks, same order: identical output."""
+    X, Q, Fg, Fo, _ = forests("gauss-4k-10000", forms=() if form == "fp32" else (form,))
+    outs = []
+    for where in ("lds", "global"):
+        if where == "global":
+            monkeypatch.setenv("GF_SCAN_WIDE_QUERY", "global")
+        ids = np.zeros((len(Q), 10), np.int32)
+        dd = np.zeros((len(Q), 10), np.float32)
+        geraf.query(Fg, Q, 10, 2048, ids, dd, form=form)
+        outs.append((ids, dd))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
 
 
 def test_fp8_hardware_decode_matches_definition():
