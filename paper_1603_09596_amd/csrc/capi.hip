@@ -339,7 +339,7 @@ gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& 
     ea.gthr = w.gthr;
     gf::TileArgs ta{};
     ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.cw = tp.cw; ta.Q16 = w.Q16; ta.X16 = F->X16;
-    ta.norm16 = F->norm16; ta.visT = w.visT; ta.gthr = w.gthr; ta.nsplit = tp.nsplit;
+    ta.norm16 = F->norm16; ta.visT = w.visT; ta.gthr = w.gthr; ta.cap = J.kk; ta.nsplit = tp.nsplit;
     ta.split_pts = tp.split_pts; ta.part_s = w.part_s; ta.part_i = w.part_i;
     gf::MergeArgs ma{};
     ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = tp.nsplit;

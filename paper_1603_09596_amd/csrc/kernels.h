@@ -127,7 +127,8 @@ struct TileArgs {
     const float* norm16;        // [n]
     const uint32_t* visT;       // [nchunk][n][cw]
     uint32_t* gthr;             // [nq] order-preserving bits of an upper bound on
-                                // each query's kTileList-th best score
+                                // each query's cap-th best score
+    int cap;                    // list capacity per (query, split): the merge's kk, <= kTileList
     int nsplit;
     int64_t split_pts;          // points per split, multiple of 64, split_pts * ld16 * 2 < 2^31
     float* part_s;              // [nq][nsplit][kTileList]

@@ -22,7 +22,7 @@
 //                    64-point x 256-k stages of X stream into three LDS buffers
 //                    with direct global->LDS loads (two stages in flight) as
 //                    B operands; the epilogue masks by the candidate bits and
-//                    keeps, per query and split, the 48 best (score, id) pairs
+//                    keeps, per query and split, the `cap` best (score, id) pairs
 //                    in registers, three on each of the 16 lanes that hold
 //                    that query's row of the MFMA result.
 //   k_merge_rerank   one workgroup per query: best `kk` over the splits, then
@@ -67,7 +67,7 @@ __device__ __forceinline__ void quarter_max(float& s, int& i) {
 }
 
 // Offer every lane's (sc, id) with cand set to the list of its quarter-wave.
-// The 16 lanes 16u..16u+15 share one query's list of 48 entries (lane c
+// The 16 lanes 16u..16u+15 share one query's list of 48 slots (lane c
 // holds entries 3c..3c+2 in registers, unsorted) and keep its current worst
 // entry (ts, ti).  The four quarters insert in parallel; a candidate
 // replaces the worst entry when it precedes it.
@@ -221,7 +221,9 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     // the A operands are complete before any direct load is issued, so the
     // compiler has no pending load of its own to wait for inside the loop
     __builtin_amdgcn_s_waitcnt(kWaitVm(0));
-    // the lists of this lane's four queries: kSlots entries each, in registers
+    // the lists of this lane's four queries: kSlots entries each, in registers.
+    // Entries past the capacity hold (-inf, -1), which precede every score,
+    // so they are never the worst entry: a list then keeps its cap best.
     float ts[4], ls[4][kSlots];
     int ti[4], li[4][kSlots];
 #pragma unroll
@@ -229,7 +231,11 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         ts[i] = __builtin_inff();
         ti[i] = 0x7FFFFFFF;
 #pragma unroll
-        for (int j = 0; j < kSlots; ++j) { ls[i][j] = __builtin_inff(); li[i][j] = 0x7FFFFFFF; }
+        for (int j = 0; j < kSlots; ++j) {
+            const bool pad = col * kSlots + j >= a.cap;
+            ls[i][j] = pad ? -__builtin_inff() : __builtin_inff();
+            li[i][j] = pad ? -1 : 0x7FFFFFFF;
+        }
     }
 
     const int64_t pb = int64_t(split) * a.split_pts;
@@ -374,7 +380,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         // epilogue: C[row 4 quarter + i][col] of block b = q(row) . x(16 b + col).
         // A point enters a query's list only if it is a candidate of the
         // query and its score is at most both the list's worst and the
-        // shared bound (an upper bound on the query's kTileList-th best over
+        // shared bound (an upper bound on the query's cap-th best over
         // all splits, so nothing it excludes can be in the final lists); the
         // insertion re-checks the exact (score, id) order.
         uint32_t word[4];
@@ -419,7 +425,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         }
     }
     __builtin_amdgcn_s_waitcnt(kWaitVm(0));
-    // the 48 best of each query in this split
+    // the cap best of each query in this split (padding entries written empty)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int q = q0 + 4 * quarter + i;
@@ -427,8 +433,9 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             const int64_t base = (int64_t(q) * a.nsplit + split) * kTileList;
 #pragma unroll
             for (int j = 0; j < kSlots; ++j) {
-                a.part_s[base + col * kSlots + j] = ls[i][j];
-                a.part_i[base + col * kSlots + j] = li[i][j];
+                const bool pad = li[i][j] < 0;
+                a.part_s[base + col * kSlots + j] = pad ? __builtin_inff() : ls[i][j];
+                a.part_i[base + col * kSlots + j] = pad ? 0x7FFFFFFF : li[i][j];
             }
         }
     }
