@@ -23,6 +23,11 @@ budget instead (gauss-10k-128 and sphere-100k-1000 in FP32, gauss-200k-10000
 in FP8 with FP32 re-rank of the best 40), with the same line and the same
 roofline and baseline objects; the FP32 form is timed beside the FP8 one.
 
+`--sweep eps|p` measures accuracy and time against the approximation factor
+eps or the points per leaf p on noisy-sphere stand-ins shaped like the
+paper's synthetic Sphere sets (k = 1): miss %, eps-failure %, build and
+search time per setting, in one line with a row per setting.
+
 `--multi` measures the multi-index launch instead and prints its own line:
 the multi-20 recipe (20 indexes of uneven n and d, per-query budgets,
 scaled by --multi-scale), FP32 form, as one gf_query_multi graph launch,
@@ -92,6 +97,88 @@ def scan_bytes_per_launch(F, nq, ncand_total, form, k, kk, checks):
     perm = nq * checks * leaf_pts * 4
     bits = nq * F.m * F.leaf_words * 4
     return ncand_total * row + rerank + perm + bits + nq * qrow + nq * k * 8
+
+
+def nn_quality(d_true, d_got, eps, tie=1e-12):
+    """Accuracy of 1-NN answers as Sec. 4 measures it, from squared FP64
+    distances: miss % is the share of queries whose reported neighbour is
+    farther than the exact nearest (a point at the same distance counts as
+    correct); eps-failure % is the share whose reported distance exceeds
+    (1 + eps) times the nearest distance (Def. 1).  A query with no answer
+    (distance inf) counts as both."""
+    d_true = np.asarray(d_true, dtype=np.float64)
+    d_got = np.asarray(d_got, dtype=np.float64)
+    miss = ~(d_got <= d_true * (1.0 + tie))
+    fail = ~(d_got <= d_true * (1.0 + eps) ** 2 * (1.0 + tie))
+    return 100.0 * float(miss.mean()), 100.0 * float(fail.mean())
+
+
+# eps sweep: the two Sphere shapes of the paper's search table; p sweep: the
+# shape of its points-per-leaf table (there on a Klein bottle, here a sphere)
+SWEEPS = {
+    "eps": dict(cases=[(1000, 10000), (100000, 100)], eps=(0.0, 0.1, 0.5, 0.9), p=(16,)),
+    "p": dict(cases=[(10000, 100)], eps=(0.0,), p=(256, 128, 64, 32, 16, 4, 2, 1)),
+}
+SWEEP_M, SWEEP_T, SWEEP_NQ, SWEEP_SEED, SWEEP_SIGMA = 8, 5, 1000, 5, 0.1
+
+
+def sweep_bench(args, torch, geraf, workloads, dev):
+    """eps or p sweep on noisy-sphere stand-ins (FP32 form, k = 1)."""
+    from oracle import bruteforce as bf
+    spec = SWEEPS[args.sweep]
+    m, t, nq, seed = SWEEP_M, SWEEP_T, SWEEP_NQ, SWEEP_SEED
+    rows = []
+    for n, d in spec["cases"]:
+        X, Q = workloads.noisy_sphere(n, d, nq, SWEEP_SIGMA, seed)
+        _, gt_d = bf.knn_ground_truth(X, Q, 1)
+        Qd = torch.from_numpy(Q).to(dev)
+        ids = torch.empty((nq, 1), dtype=torch.int32, device=dev)
+        dd = torch.empty((nq, 1), dtype=torch.float32, device=dev)
+        for p in spec["p"]:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F = geraf.build_forest(X, m, t, p, seed)
+            torch.cuda.synchronize()
+            build_s = time.perf_counter() - t0
+            leaves = m << F.H
+            c = args.checks if args.checks is not None else (
+                256 if args.sweep == "p" else max(1, leaves // 16))
+            for eps in spec["eps"]:
+                geraf.query(F, Qd, 1, c, ids, dd, eps=eps)
+                torch.cuda.synchronize()
+                times = []
+                for _ in range(max(1, args.steps)):
+                    t0 = time.perf_counter()
+                    geraf.query(F, Qd, 1, c, ids, dd, eps=eps)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                ms = 1e3 * float(np.median(times))
+                got = ids.cpu().numpy()[:, 0].astype(np.int64)
+                d_got = np.full(nq, np.inf)
+                ok = got >= 0
+                diff = X[got[ok]].astype(np.float64) - Q[ok].astype(np.float64)
+                d_got[ok] = np.einsum("ij,ij->i", diff, diff)
+                miss, fail = nn_quality(gt_d[:, 0], d_got, eps)
+                budget = min(int(np.ceil(c / (1.0 + eps))), leaves)
+                rows.append(dict(dataset=f"noisy-sphere-{n}x{d}", n=n, d=d, p=p, H=int(F.H),
+                                 eps=eps, checks=c, leaves_opened=budget,
+                                 build_s=round(build_s, 4), search_ms=round(ms, 3),
+                                 us_per_query=round(1e3 * ms / nq, 3),
+                                 miss_pct=round(miss, 1), eps_fail_pct=round(fail, 1)))
+                log(f"[bench] sweep {rows[-1]}")
+            F.free()
+    first = rows[0]
+    out = {
+        "metric": f"{args.sweep} sweep: miss %, eps-failure % and search time (noisy-sphere)",
+        "value": round(nq / (first["search_ms"] / 1e3), 2), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": first["search_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"noisy-sphere {args.sweep} sweep", "m": m, "t": t, "k": 1,
+                   "nq": nq, "sigma": SWEEP_SIGMA, "seed": seed, "form": "fp32"},
+        "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def pmc_traffic(kernel, workload):
@@ -210,6 +297,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--sweep", choices=sorted(SWEEPS),
+                    help="accuracy/time sweep over eps or points per leaf (noisy-sphere)")
     ap.add_argument("--multi", action="store_true",
                     help="measure the multi-index launch (multi-20 recipe) instead")
     ap.add_argument("--multi-scale", type=float, default=0.25,
@@ -233,6 +322,8 @@ def main():
     geraf.load()
     if args.multi:
         return multi_bench(args, torch, geraf, workloads, dev)
+    if args.sweep:
+        return sweep_bench(args, torch, geraf, workloads, dev)
     name = args.workload
     form = FORMS[name]
     t0 = time.perf_counter()

@@ -26,6 +26,11 @@ Workloads (name: shape; points; queries; forest/search parameters):
                     {128, 512, 960, 2048}, iid N(0,1); 100..5,000 queries each
                     (point + N(0, 0.05^2)), per-query c uniform in [256, 8192];
                     m=8 t=5 p=16 k=10
+  noisy sphere      (for the eps and points-per-leaf sweeps) points uniform on
+                    the unit sphere plus N(0, sigma^2) on every coordinate, and
+                    queries drawn the same way (not planted), as the synthetic
+                    Sphere sets of Sec. 4 are described; queries are then
+                    nearly equidistant from the points
 """
 from __future__ import annotations
 
@@ -121,6 +126,21 @@ def sphere(n: int, d: int, nq: int, qdist: float, seed: int):
     u = _normalise_rows(qrng.standard_normal((nq, d), dtype=np.float32))
     Q = (X[src] + qdist * u).astype(np.float32)
     return X, Q, src
+
+
+def noisy_sphere(n: int, d: int, nq: int, sigma: float, seed: int):
+    """Points and queries alike: uniform on the unit sphere, then N(0, sigma^2)
+    added to every coordinate.  Returns X, Q (no planted source)."""
+    root = np.random.SeedSequence(seed)
+    _, data_ss, q_ss = root.spawn(3)
+
+    def chunk(rng, rows, dd):
+        u = _normalise_rows(rng.standard_normal((rows, dd), dtype=np.float32))
+        return (u + sigma * rng.standard_normal((rows, dd), dtype=np.float32)).astype(np.float32)
+
+    X = _fill_rows(n, d, data_ss, chunk)
+    Q = chunk(np.random.default_rng(q_ss), nq, d)
+    return X, Q
 
 
 def descriptor(n: int, d: int, nq: int, noise: float, seed: int):

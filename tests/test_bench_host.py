@@ -37,3 +37,25 @@ def test_scan_bytes_count_rerank_only_for_reduced_forms():
     b16 = bench.scan_bytes_per_launch(F, nq, 0, "bf16", 10, kk, 1)
     # query rows differ by the BF16 copy (960 x 2 B); the re-rank reads kk FP32 rows
     assert b16 - b32 == nq * 960 * 2 + nq * kk * 960 * 4
+
+
+def test_nn_quality_tie_rule_and_eps_bound():
+    # squared distances: exact nearest 1, 4, 9, 16; reported 1 (exact), 4 up
+    # to a last-bit difference (a tie counts as correct), 9.5, no answer
+    d_true = [1.0, 4.0, 9.0, 16.0]
+    d_got = [1.0, 4.0 * (1 + 1e-15), 9.5, float("inf")]
+    miss, fail = bench.nn_quality(d_true, d_got, 0.0)
+    assert miss == pytest.approx(50.0) and fail == pytest.approx(50.0)
+    # eps = 0.1 bounds the distance by 1.1 * 3 = 3.3, i.e. the square by 10.89
+    miss, fail = bench.nn_quality(d_true, d_got, 0.1)
+    assert miss == pytest.approx(50.0) and fail == pytest.approx(25.0)
+    miss, fail = bench.nn_quality([9.0], [9.0 * 1.1 ** 2], 0.1)
+    assert fail == 0.0 and miss == 100.0
+    _, fail = bench.nn_quality([9.0], [9.0 * 1.1 ** 2 * (1 + 1e-9)], 0.1)
+    assert fail == 100.0
+
+
+def test_sweep_settings_cover_the_paper_tables():
+    # the four eps values and the eight points-per-leaf values of the tables
+    assert bench.SWEEPS["eps"]["eps"] == (0.0, 0.1, 0.5, 0.9)
+    assert bench.SWEEPS["p"]["p"] == (256, 128, 64, 32, 16, 4, 2, 1)
