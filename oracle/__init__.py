@@ -16,6 +16,12 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
                         m = t = 1, nesting in c, exhaustive budget = brute force
   search (literal key)  diagnostic only; parity unpinned beyond sharing the
                         same exhaustive-budget and home-leaf behaviour
+  householder / build and search with the isometry
+                        pinned: u unit and deterministic; u = e_0 (a
+                        reflection that negates one coordinate) gives the
+                        forest and searches of the plain method on the data
+                        with that column negated; exhaustive budget = brute
+                        force
 """
 from __future__ import annotations
 
@@ -63,10 +69,12 @@ def _load():
     lib.orc_depth.restype = i32
     lib.orc_budget.argtypes = [i64, f64, i64]
     lib.orc_budget.restype = i64
-    lib.orc_build.argtypes = [P, i64, i32, i32, i32, i32, u64, i32, P, P, P, P, P]
+    lib.orc_householder.argtypes = [u64, i32, i32, P]
+    lib.orc_householder.restype = ctypes.c_int
+    lib.orc_build.argtypes = [P, i64, i32, i32, i32, i32, u64, i32, P, P, P, P, P, P]
     lib.orc_build.restype = ctypes.c_int
     lib.orc_search.argtypes = [P, i64, i32, i32, i32, P, P, P, P, P, i64, i32, i64, f64,
-                               i32, i32, P, P, P, P, P, P, i64]
+                               i32, i32, P, P, P, P, P, P, i64, P]
     lib.orc_search.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -110,10 +118,28 @@ def budget(c: int, eps: float, total_leaves: int) -> int:
     return int(_load().orc_budget(c, eps, total_leaves))
 
 
-def build_forest(X: np.ndarray, m: int, t: int, p: int, seed: int, nthreads: int = 0) -> dict:
-    """Alg. 1.  Returns the forest arrays (see oracle.c, orc_build)."""
+def householder(seed: int, tree: int, d: int) -> np.ndarray:
+    """The reflector u of tree `tree` (FP64, unit norm; see orc_householder)."""
+    u = np.empty(d, dtype=np.float64)
+    st = _load().orc_householder(seed & 0xFFFFFFFFFFFFFFFF, tree, d, _ptr(u))
+    if st != 0:
+        raise ValueError(f"orc_householder failed: {st}")
+    return u
+
+
+def build_forest(X: np.ndarray, m: int, t: int, p: int, seed: int, nthreads: int = 0,
+                 householder_variant: bool = False, u: Optional[np.ndarray] = None) -> dict:
+    """Alg. 1.  Returns the forest arrays (see oracle.c, orc_build).  With
+    householder_variant, tree i is built on the points reflected by
+    I - 2 u_i u_i' (u_i from householder(seed, i, d), or the rows of `u`
+    when given) and the forest carries "u" for search()."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     n, d = X.shape
+    U = None
+    if u is not None:
+        U = np.ascontiguousarray(u, dtype=np.float64).reshape(m, d)
+    elif householder_variant:
+        U = np.stack([householder(seed, i, d) for i in range(m)])
     H = depth(n, p)
     n_int = (1 << H) - 1
     D = np.empty(t, dtype=np.int32)
@@ -124,12 +150,12 @@ def build_forest(X: np.ndarray, m: int, t: int, p: int, seed: int, nthreads: int
     if nthreads <= 0:
         nthreads = os.cpu_count() or 1
     st = _load().orc_build(_ptr(X), n, d, m, t, p, seed & 0xFFFFFFFFFFFFFFFF, nthreads, _ptr(D),
-                           _ptr(split_dim), _ptr(split_val), _ptr(perm), _ptr(leaf_off))
+                           _ptr(split_dim), _ptr(split_val), _ptr(perm), _ptr(leaf_off), _ptr(U))
     if st != 0:
         raise ValueError(f"orc_build failed: {st}")
     return dict(n=n, d=d, m=m, t=t, p=p, seed=seed, H=H, D=D,
                 split_dim=split_dim[:, :n_int], split_val=split_val[:, :n_int],
-                perm=perm, leaf_off=leaf_off)
+                perm=perm, leaf_off=leaf_off, u=U)
 
 
 def search(forest: dict, X: np.ndarray, Q: np.ndarray, k: int, c: int, eps: float = 0.0,
@@ -165,7 +191,7 @@ def search(forest: dict, X: np.ndarray, Q: np.ndarray, k: int, c: int, eps: floa
                             _ptr(np.ascontiguousarray(forest["leaf_off"])),
                             _ptr(Q), nq, k, c, float(eps), int(bool(literal)), nthreads,
                             _ptr(ids), _ptr(dists), _ptr(opened), _ptr(okey), _ptr(ncand),
-                            _ptr(cand), cap)
+                            _ptr(cand), cap, _ptr(forest.get("u")))
     if st != 0:
         raise ValueError(f"orc_search failed: {st}")
     out = dict(ids=ids, dists=dists, B=B)
@@ -183,4 +209,4 @@ def leaf_code(tree, leaf):
 
 
 __all__ = ["build", "splitmix64", "draw", "variance", "top_dims", "depth", "budget",
-           "build_forest", "search", "leaf_code"]
+           "householder", "build_forest", "search", "leaf_code"]

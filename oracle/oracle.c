@@ -24,9 +24,12 @@
  *   orc_top_dims               the t dimensions of largest variance (Alg. 1).
  *   orc_depth                  depth of the perfect tree (Sec. 3 "Tree
  *                              structure": trees are perfect).
+ *   orc_householder            the per-tree reflector of the isometry variant
+ *                              (Sec. 2.1 "Rotation", Sec. 2.2): P = I - 2uu'.
  *   orc_build                  Alg. 1: m trees, split dimension drawn from the
  *                              top-t set, split at the median, per-tree random
- *                              tie key ("shuffling", Sec. 2.1).
+ *                              tie key ("shuffling", Sec. 2.1); optionally on
+ *                              the reflected coordinates of each tree.
  *   orc_search                 Alg. 2 + Sec. 2.3: one shared min-priority
  *                              queue over all trees, no backtracking, stop
  *                              after B leaves, visited array so no point is
@@ -130,6 +133,50 @@ int32_t orc_depth(int64_t n, int32_t p)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Isometry variant (Sec. 2.1 "Rotation", Sec. 2.2): each tree is built on   */
+/* the points reflected by its own Householder matrix P = I - 2uu', and the  */
+/* query is reflected the same way before that tree is descended; distances */
+/* stay between the original points and query.                              */
+/* ------------------------------------------------------------------------ */
+
+/* u of tree `tree`: w_j uniform in [-1, 1) from the top 53 bits of
+ * draw(seed, 4, tree, j), then u = w / ||w|| (FP64, the squares summed in
+ * index order, IEEE sqrt and division). */
+int orc_householder(uint64_t seed, int32_t tree, int32_t d, double *u)
+{
+    if (!u || d < 1) return ORC_EINVAL;
+    double s = 0.0;
+    for (int32_t j = 0; j < d; ++j) {
+        double w = (double)(orc_draw(seed, 4, (uint64_t)tree, (uint64_t)j) >> 11) * 0x1p-53 * 2.0 - 1.0;
+        u[j] = w;
+        s = s + w * w;
+    }
+    if (!(s > 0.0)) return ORC_EINVAL;
+    double nrm = sqrt(s);
+    for (int32_t j = 0; j < d; ++j) u[j] = u[j] / nrm;
+    return ORC_OK;
+}
+
+/* u . x in FP64: each product rounded, then added in index order. */
+static double dot_u(const double *u, const float *x, int32_t d)
+{
+    double t = 0.0;
+    for (int32_t j = 0; j < d; ++j) {
+        double p = u[j] * (double)x[j];
+        t = t + p;
+    }
+    return t;
+}
+
+/* Coordinate s of Px = x - 2 (u.x) u given t = u.x: the FP64 value
+ * x_s - (2t) u_s, rounded once to float32. */
+static float reflect_coord(float x_s, double t, double u_s)
+{
+    double r = (2.0 * t) * u_s;
+    return (float)((double)x_s - r);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Build (Alg. 1).                                                           */
 /* ------------------------------------------------------------------------ */
 
@@ -162,6 +209,8 @@ typedef struct {
     uint64_t *tiekey;     /* n entries, scratch for one tree */
     orc_item *items;      /* n entries, scratch for one tree */
     int32_t tree;
+    const double *U;      /* [m][d] reflectors, or NULL (no isometry) */
+    double *tdot;         /* n entries: u . x of every point, for one tree */
 } orc_build_ctx;
 
 /* Recursive build of node v (heap index, root 0) at the given depth, whose
@@ -182,7 +231,9 @@ static void build_node(orc_build_ctx *c, int64_t v, int32_t depth,
     /* v <- median of X in dimension s: rank split at floor(len/2), ties
      * resolved by the tree's random key, then by id. */
     for (int64_t i = 0; i < len; ++i) {
-        c->items[i].x = c->X[(int64_t)ids[i] * c->d + s];
+        const float xs = c->X[(int64_t)ids[i] * c->d + s];
+        c->items[i].x = c->U ? reflect_coord(xs, c->tdot[ids[i]], c->U[(int64_t)c->tree * c->d + s])
+                             : xs;
         c->items[i].key = c->tiekey[ids[i]];
         c->items[i].id = ids[i];
     }
@@ -209,9 +260,13 @@ static void *build_worker(void *arg)
     orc_build_ctx c = job->base;
     c.tiekey = (uint64_t *)malloc((size_t)c.n * sizeof(uint64_t));
     c.items = (orc_item *)malloc((size_t)c.n * sizeof(orc_item));
-    if (!c.tiekey || !c.items) { job->status = ORC_ENOMEM; goto done; }
+    c.tdot = c.U ? (double *)malloc((size_t)c.n * sizeof(double)) : NULL;
+    if (!c.tiekey || !c.items || (c.U && !c.tdot)) { job->status = ORC_ENOMEM; goto done; }
     for (int32_t tr = job->first_tree; tr < job->m; tr += job->tree_step) {
         c.tree = tr;
+        if (c.U)
+            for (int64_t i = 0; i < c.n; ++i)
+                c.tdot[i] = dot_u(c.U + (int64_t)tr * c.d, c.X + i * c.d, c.d);
         for (int64_t i = 0; i < c.n; ++i)
             c.tiekey[i] = orc_draw(c.seed, 2, (uint64_t)tr, (uint64_t)i);
         uint32_t *ids = c.perm + (int64_t)tr * c.n;
@@ -222,6 +277,7 @@ static void *build_worker(void *arg)
 done:
     free(c.tiekey);
     free(c.items);
+    free(c.tdot);
     return NULL;
 }
 
@@ -233,12 +289,15 @@ done:
  *                                 (each leaf ascending by id)
  *   leaf_off[2^H + 1]             leaf j holds perm[tree][leaf_off[j] .. leaf_off[j+1])
  *                                 (identical for every tree: sizes depend on n only)
- * Internal node v has children 2v+1 (left) and 2v+2 (right).  The isometry
- * and split-value jitter of Sec. 2.1 are off, as the paper runs it (Sec. 4). */
+ * Internal node v has children 2v+1 (left) and 2v+2 (right).  U = NULL
+ * builds on the points themselves, as the paper runs it (Sec. 4); otherwise
+ * U[m][d] holds each tree's reflector u (orc_householder) and tree i splits
+ * the coordinates of P_i x, rounded to float32, while D stays the top-variance
+ * set of X itself.  Split-value jitter (Sec. 2.1) is not built. */
 int orc_build(const float *X, int64_t n, int32_t d, int32_t m, int32_t t,
               int32_t p, uint64_t seed, int32_t nthreads,
               int32_t *D, int32_t *split_dim, float *split_val,
-              uint32_t *perm, uint32_t *leaf_off)
+              uint32_t *perm, uint32_t *leaf_off, const double *U)
 {
     if (!X || n < 1 || n > 0xFFFFFFFFLL || d < 1 || m < 1 || t < 1 || t > d || p < 1)
         return ORC_EINVAL;
@@ -258,7 +317,7 @@ int orc_build(const float *X, int64_t n, int32_t d, int32_t m, int32_t t,
     if (!jobs || !th) { free(jobs); free(th); return ORC_ENOMEM; }
     for (int32_t w = 0; w < nthreads; ++w) {
         orc_build_ctx b = {X, n, d, t, H, seed, D, split_dim, split_val, perm, leaf_off,
-                           NULL, NULL, 0};
+                           NULL, NULL, 0, U, NULL};
         jobs[w].base = b;
         jobs[w].first_tree = w;
         jobs[w].tree_step = nthreads;
@@ -369,6 +428,7 @@ typedef struct {
     /* threading */
     int64_t q_first, q_step;
     int status;
+    const double *U;      /* [m][d] reflectors of the isometry variant, or NULL */
 } orc_search_job;
 
 /* One query through Alg. 2.  Queue entries are (key, tree, node) triples
@@ -388,11 +448,13 @@ typedef struct {
  *   - the k best are the k smallest (distance, id) pairs, ascending, padded
  *     with id -1 / +inf when fewer than k points were checked. */
 static int search_one(const orc_search_job *J, int64_t qi, unsigned char *visited,
-                      uint32_t *touched, orc_cand *cands, orc_heap *heap)
+                      uint32_t *touched, orc_cand *cands, orc_heap *heap, double *tq)
 {
     const float *q = J->Q + qi * J->d;
     const int64_t n_internal = ((int64_t)1 << J->H) - 1;
     int64_t ntouched = 0;
+    if (J->U)   /* u_i . q per tree: the query is reflected before descending tree i */
+        for (int32_t tr = 0; tr < J->m; ++tr) tq[tr] = dot_u(J->U + (int64_t)tr * J->d, q, J->d);
     heap->size = 0;
     for (int32_t tr = 0; tr < J->m; ++tr) {
         orc_entry root = {0.0, tr, 0};
@@ -405,7 +467,10 @@ static int search_one(const orc_search_job *J, int64_t qi, unsigned char *visite
         const int32_t *sd = J->split_dim + (int64_t)e.tree * n_internal;
         const float *sv = J->split_val + (int64_t)e.tree * n_internal;
         while (v < n_internal) {                         /* descend(q, N, check) */
-            double g = gap_f32(q[sd[v]], sv[v]);
+            const int32_t s = sd[v];
+            const float qs = J->U ? reflect_coord(q[s], tq[e.tree], J->U[(int64_t)e.tree * J->d + s])
+                                  : q[s];
+            double g = gap_f32(qs, sv[v]);
             int64_t near_child, far_child;
             if (g < 0.0) { near_child = 2 * v + 1; far_child = 2 * v + 2; }
             else         { near_child = 2 * v + 2; far_child = 2 * v + 1; }
@@ -473,11 +538,12 @@ static void *search_worker(void *arg)
     uint32_t *touched = (uint32_t *)malloc((size_t)(cap + 1) * sizeof(uint32_t));
     orc_cand *cands = (orc_cand *)malloc((size_t)(cap + 1) * sizeof(orc_cand));
     orc_heap heap = {NULL, 0, 0};
+    double *tq = (double *)malloc((size_t)J->m * sizeof(double));
     J->status = ORC_OK;
-    if (!visited || !touched || !cands) J->status = ORC_ENOMEM;
+    if (!visited || !touched || !cands || !tq) J->status = ORC_ENOMEM;
     for (int64_t qi = J->q_first; J->status == ORC_OK && qi < J->nq; qi += J->q_step)
-        J->status = search_one(J, qi, visited, touched, cands, &heap);
-    free(visited); free(touched); free(cands); free(heap.a);
+        J->status = search_one(J, qi, visited, touched, cands, &heap, tq);
+    free(visited); free(touched); free(cands); free(heap.a); free(tq);
     return NULL;
 }
 
@@ -486,14 +552,15 @@ static void *search_worker(void *arg)
  *   ids[nq][k] int32, dists[nq][k] FP64 squared distances;
  *   opened[nq][B] (tree << 24 | leaf) in pop order and opened_key[nq][B]
  *   (may be NULL); ncand[nq] and cand[nq][cand_cap] = the checked point ids,
- *   ascending (may be NULL).  B = orc_budget(c, eps, m * 2^H). */
+ *   ascending (may be NULL).  B = orc_budget(c, eps, m * 2^H).  U: the
+ *   forest's reflectors (orc_build) or NULL. */
 int orc_search(const float *X, int64_t n, int32_t d, int32_t m, int32_t H,
                const int32_t *split_dim, const float *split_val,
                const uint32_t *perm, const uint32_t *leaf_off,
                const float *Q, int64_t nq, int32_t k, int64_t c, double eps,
                int32_t literal, int32_t nthreads,
                int32_t *ids, double *dists, uint32_t *opened, double *opened_key,
-               int64_t *ncand, uint32_t *cand, int64_t cand_cap)
+               int64_t *ncand, uint32_t *cand, int64_t cand_cap, const double *U)
 {
     if (!X || !Q || !ids || !dists || n < 1 || d < 1 || m < 1 || H < 0 || H > 23 ||
         m > 255 || nq < 0 || k < 1 || c < 0 || !(eps >= 0.0))
@@ -508,7 +575,7 @@ int orc_search(const float *X, int64_t n, int32_t d, int32_t m, int32_t H,
     for (int32_t w = 0; w < nthreads; ++w) {
         orc_search_job J = {X, n, d, m, H, split_dim, split_val, perm, leaf_off,
                             Q, nq, k, B, literal, ids, dists, opened, opened_key,
-                            ncand, cand, cand_cap, w, nthreads, ORC_OK};
+                            ncand, cand, cand_cap, w, nthreads, ORC_OK, U};
         jobs[w] = J;
         pthread_create(&th[w], NULL, search_worker, &jobs[w]);
     }

@@ -398,3 +398,72 @@ def test_search_threads_do_not_change_results():
     r4 = oracle.search(F1, X, Q, 5, 77, nthreads=4)
     for key in ("ids", "dists", "opened", "opened_key"):
         assert np.array_equal(r1[key], r4[key])
+
+
+# ---------------------------------------------------------------- isometry
+# The variant of Sec. 2.1 ("Rotation") with the Householder reflector of
+# Sec. 2.2: tree i splits the coordinates of (I - 2 u_i u_i') x.
+
+
+def test_householder_vectors_unit_deterministic_distinct():
+    u0 = oracle.householder(7, 0, 300)
+    assert np.array_equal(u0, oracle.householder(7, 0, 300))
+    assert abs(float(np.dot(u0, u0)) - 1.0) < 1e-14
+    u1 = oracle.householder(7, 1, 300)
+    assert not np.allclose(u0, u1)
+    # the reflector is an isometry and an involution (FP64, to rounding)
+    rng = np.random.default_rng(2)
+    x, y = rng.standard_normal(300), rng.standard_normal(300)
+    P = lambda v: v - 2.0 * np.dot(u0, v) * u0
+    assert abs(np.linalg.norm(P(x) - P(y)) - np.linalg.norm(x - y)) < 1e-12
+    assert np.allclose(P(P(x)), x, rtol=0, atol=1e-13)
+
+
+def test_householder_e0_is_the_plain_method_on_a_negated_column():
+    # u = e_0 reflects across the plane x_0 = 0: every reflected coordinate is
+    # exact (-x_0, and x_s for s != 0), variances are unchanged, and so are
+    # all distances.  The forest and every search must equal the plain ones
+    # on the data with column 0 negated.
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((2000, 8)).astype(np.float32)
+    X[:, 0] *= 3.0                        # column 0 among the top-variance dims
+    Q = rng.standard_normal((30, 8)).astype(np.float32)
+    Xn, Qn = X.copy(), Q.copy()
+    Xn[:, 0] = -Xn[:, 0]
+    Qn[:, 0] = -Qn[:, 0]
+    m = 3
+    U = np.zeros((m, 8))
+    U[:, 0] = 1.0
+    Fi = oracle.build_forest(X, m, 4, 8, 21, u=U)
+    Fp = oracle.build_forest(Xn, m, 4, 8, 21)
+    assert 0 in Fi["D"].tolist()
+    for key in ("D", "split_dim", "split_val", "perm", "leaf_off"):
+        assert np.array_equal(Fi[key], Fp[key]), key
+    for c in (1, 5, 40):
+        ri = oracle.search(Fi, X, Q, 5, c, candidates=True)
+        rp = oracle.search(Fp, Xn, Qn, 5, c, candidates=True)
+        assert np.array_equal(ri["opened"], rp["opened"])
+        assert np.array_equal(ri["ids"], rp["ids"])
+        assert np.array_equal(ri["dists"], rp["dists"])
+
+
+def test_householder_forest_differs_and_exhaustive_budget_is_exact_knn():
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((1500, 20)).astype(np.float32)
+    Q = rng.standard_normal((25, 20)).astype(np.float32)
+    Fi = oracle.build_forest(X, 3, 4, 6, 6, householder_variant=True)
+    Fp = oracle.build_forest(X, 3, 4, 6, 6)
+    assert np.array_equal(Fi["D"], Fp["D"])           # D comes from X itself
+    assert not np.array_equal(Fi["perm"], Fp["perm"])
+    for tr in range(3):                                 # every tree partitions all points
+        assert np.array_equal(np.sort(Fi["perm"][tr]), np.arange(1500, dtype=np.uint32))
+    assert set(Fi["split_dim"].ravel().tolist()) <= set(Fi["D"].tolist())
+    r = oracle.search(Fi, X, Q, 10, 3 << Fi["H"], candidates=True)
+    assert all(len(cq) == 1500 for cq in r["cand"])
+    ei, ed = bf.knn_exact(X, Q, 10)
+    assert np.array_equal(r["ids"], ei)
+    assert np.allclose(r["dists"], ed, rtol=1e-13, atol=0)
+    # a small budget opens different leaves than the plain forest does
+    ri = oracle.search(Fi, X, Q, 10, 4)
+    rp = oracle.search(Fp, X, Q, 10, 4)
+    assert not np.array_equal(ri["opened"], rp["opened"])
