@@ -205,10 +205,11 @@ def pmc_traffic(kernel, workload):
         return None
 
 
-def cpu_baseline(w, idx_all, checks, seconds, threads):
+def cpu_baseline(w, idx_all, checks, seconds, threads, householder=False):
     import oracle
     t0 = time.perf_counter()
-    F = oracle.build_forest(w.X, w.m, w.t, w.p, w.seed, nthreads=threads)
+    F = oracle.build_forest(w.X, w.m, w.t, w.p, w.seed, nthreads=threads,
+                            householder_variant=householder)
     log(f"[bench] oracle build {time.perf_counter() - t0:.1f}s")
     # calibrate on one query per thread, then size the sample to ~`seconds`
     probe = idx_all[:threads]
@@ -297,6 +298,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--householder", action="store_true",
+                    help="build the forest with the per-tree Householder isometry variant")
     ap.add_argument("--sweep", choices=sorted(SWEEPS),
                     help="accuracy/time sweep over eps or points per leaf (noisy-sphere)")
     ap.add_argument("--multi", action="store_true",
@@ -330,7 +333,8 @@ def main():
     w = workloads.make(name, nq=args.nq)
     log(f"[bench] workload {name}: X {w.X.shape} Q {w.Q.shape} in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    F = geraf.build_forest(w.X, w.m, w.t, w.p, w.seed, forms=() if form == "fp32" else (form,))
+    F = geraf.build_forest(w.X, w.m, w.t, w.p, w.seed, forms=() if form == "fp32" else (form,),
+                           householder=args.householder)
     log(f"[bench] forest build + upload {time.perf_counter() - t0:.1f}s (H={F.H})")
     Q = torch.from_numpy(w.Q).to(dev)
     nq, k = len(w.Q), w.k
@@ -414,12 +418,13 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, idx, c, args.cpu_seconds, host_threads())
+        cpu = cpu_baseline(w, idx, c, args.cpu_seconds, host_threads(), args.householder)
 
-    if name == WORKLOAD:
+    if name == WORKLOAD and not args.householder:
         metric = "queries/s at recall@10>=0.90, 1Mx960, 16 trees; BF16 vs FP32 form"
     else:
-        metric = f"queries/s, {name}, {form.upper()} form, c={c}, k={k}"
+        metric = f"queries/s, {name}, {form.upper()} form, c={c}, k={k}" + (
+            ", Householder isometry variant" if args.householder else "")
     out = {
         "metric": metric,
         "value": round(value, 2),
@@ -435,7 +440,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "n": int(F.n), "d": int(F.d), "m": int(F.m),
                    "t": int(F.t), "leaf": int(F.leaf), "checks": c, "k": k, "nq": nq,
-                   "form": form, "rerank": kk if form != "fp32" else None},
+                   "form": form, "rerank": kk if form != "fp32" else None,
+                   "variant": "householder" if args.householder else None},
         f"recall@{k}": round(rec_main, 4),
         f"1-recall@{k}": round(one_main, 4),
         "recall_sample": len(idx),

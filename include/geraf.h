@@ -80,6 +80,23 @@ gf_status gf_build_forest(const float *X, int64_t n, int32_t d, int32_t m, int32
                           int32_t leaf, uint64_t seed, uint32_t forms, void *stream,
                           gf_forest **out);
 
+/* Bits of gf_build_forest_ex's `variants` argument. */
+#define GF_VARIANT_HOUSEHOLDER (1u << 0)
+
+/* gf_build_forest with randomisation variants.  variants = 0 is exactly
+ * gf_build_forest.  GF_VARIANT_HOUSEHOLDER is the isometry of Sec. 2.1
+ * ("Rotation") in the Householder form of Sec. 2.2: tree i gets a reflector
+ * P_i = I - 2 u_i u_i', u_i drawn from the RNG (stream 4: components uniform
+ * in [-1, 1), then normalised in FP64), and splits the coordinates of P_i x
+ * rounded to float32, with u_i . x summed in FP64 in index order; D is still
+ * the top-variance set of X.  gf_query reflects each query the same way
+ * before that tree's descent and measures distances on the original points
+ * and query.  Other bits are rejected with GF_EINVAL; split-value jitter
+ * (Sec. 2.1 "Split value") is not provided. */
+gf_status gf_build_forest_ex(const float *X, int64_t n, int32_t d, int32_t m, int32_t t,
+                             int32_t leaf, uint64_t seed, uint32_t forms, uint32_t variants,
+                             void *stream, gf_forest **out);
+
 /* Release a forest and all its device memory.  NULL is accepted. */
 gf_status gf_free_forest(gf_forest *F);
 

@@ -72,12 +72,13 @@ bool all_finite_host(const float* X, int64_t count) {
 
 void free_forest_device(gf_forest* F) {
     void* ptrs[] = {F->X32, F->X16, F->norm16, F->X8, F->scale8, F->norm8,
-                    F->nodes, F->perm, F->leaf_off, F->permp, F->leafof, F->D, F->drange, F->ws};
+                    F->nodes, F->perm, F->leaf_off, F->permp, F->leafof, F->D, F->drange, F->U, F->ws};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     F->X32 = nullptr; F->X16 = nullptr; F->norm16 = nullptr; F->X8 = nullptr;
     F->scale8 = nullptr; F->norm8 = nullptr; F->nodes = nullptr; F->perm = nullptr;
     F->leaf_off = nullptr; F->permp = nullptr; F->leafof = nullptr; F->D = nullptr; F->drange = nullptr;
+    F->U = nullptr;
     F->ws = nullptr;
     F->ws_bytes = 0;
 }
@@ -99,6 +100,7 @@ struct Workspace {
     gf::SelState* state; uint32_t* hist; uint32_t* coff; uint64_t* ckey; uint32_t* ccode;
     uint32_t* leafbits; uint32_t* flags; uint32_t* qlist; int32_t* ids; float* dists;
     uint32_t* openT; uint32_t* visT; uint32_t* gthr; float* part_s; int* part_i;   // tile path only
+    float* qt;   // [m][nb][t] reflected query coordinates (isometry variant only)
 };
 
 // Split of the points for the tile path: enough (query block, split)
@@ -171,6 +173,7 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Worksp
     size_t oql = c.take<uint32_t>(nb);
     size_t oids = c.take<int32_t>(size_t(nb) * k);
     size_t odst = c.take<float>(size_t(nb) * k);
+    size_t oqt = F->U ? c.take<float>(size_t(nb) * F->host.m * F->host.t) : 0;
     size_t oopen = 0, ovis = 0, othr = 0, ops = 0, opi = 0;
     if (tile) {
         const TilePlan tp = tile_plan(F, nb);
@@ -209,6 +212,7 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Worksp
     w.qlist = reinterpret_cast<uint32_t*>(b + oql);
     w.ids = reinterpret_cast<int32_t*>(b + oids);
     w.dists = reinterpret_cast<float*>(b + odst);
+    w.qt = F->U ? reinterpret_cast<float*>(b + oqt) : nullptr;
     w.openT = tile ? reinterpret_cast<uint32_t*>(b + oopen) : nullptr;
     w.visT = tile ? reinterpret_cast<uint32_t*>(b + ovis) : nullptr;
     w.gthr = tile ? reinterpret_cast<uint32_t*>(b + othr) : nullptr;
@@ -273,6 +277,7 @@ gf::SelectArgs make_select_args(const gf_forest* F, int nb, const Workspace& w, 
     sa.nslice = h.m * gf::select_slices_per_tree(h.H);
     sa.state = w.state; sa.hist = w.hist; sa.coff = w.coff; sa.ckey = w.ckey;
     sa.ccode = w.ccode; sa.leafbits = w.leafbits; sa.qlist = w.qlist; sa.nlist = 0;
+    sa.qt = F->U ? w.qt : nullptr;
     return sa;
 }
 
@@ -281,6 +286,14 @@ gf::SelectArgs make_select_args(const gf_forest* F, int nb, const Workspace& w, 
 gf_status launch_selection(const gf_forest* F, const QueryJob& J, int nb, const Workspace& w,
                            int64_t W, const int32_t* cpq, bool early_exit, hipStream_t st) {
     const gf::SelectArgs sa = make_select_args(F, nb, w, W);
+    if (F->U) {
+        // isometry variant: each tree's reflected query coordinates on D
+        hipLaunchKernelGGL(gf::k_reflect_queries, dim3((nb + 127) / 128, unsigned(F->host.m)),
+                           dim3(128), 0, st, static_cast<const float*>(w.Qp), int64_t(F->ld32), nb,
+                           F->host.d, F->host.m, F->host.t, static_cast<const int32_t*>(F->D),
+                           static_cast<const double*>(F->U), w.qt);
+        GF_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(gf::k_select_init, dim3((nb + 255) / 256), dim3(256), 0, st, sa,
                        J.checks, cpq, J.eps);
     GF_HIP(hipGetLastError());
@@ -835,6 +848,12 @@ gf_status gf_last_query_timing(double* phase_ms, int32_t nphase, int32_t* path, 
 
 gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32_t t, int32_t leaf,
                           uint64_t seed, uint32_t forms, void* stream, gf_forest** out) {
+    return gf_build_forest_ex(X, n, d, m, t, leaf, seed, forms, 0u, stream, out);
+}
+
+gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, int32_t t,
+                             int32_t leaf, uint64_t seed, uint32_t forms, uint32_t variants,
+                             void* stream, gf_forest** out) {
     if (!out) return fail(GF_EINVAL, "out is NULL");
     *out = nullptr;
     if (!X) return fail(GF_EINVAL, "X is NULL");
@@ -845,6 +864,7 @@ gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32
     if (t > gf::kMaxT) return fail(GF_EUNSUPPORTED, "t above 64");
     if (leaf < 1) return fail(GF_EINVAL, "leaf < 1");
     if (forms & ~(GF_KEEP_BF16 | GF_KEEP_FP8)) return fail(GF_EINVAL, "unknown bits in forms");
+    if (variants & ~GF_VARIANT_HOUSEHOLDER) return fail(GF_EINVAL, "unknown bits in variants");
     if (gf::perfect_depth(n, leaf) > 23) return fail(GF_EUNSUPPORTED, "tree depth above 23");
     hipStream_t st = static_cast<hipStream_t>(stream);
 
@@ -858,7 +878,8 @@ gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32
     if (!all_finite_host(Xh, n * int64_t(d))) return fail(GF_EINVAL, "X contains a non-finite value");
 
     std::unique_ptr<gf_forest> F(new gf_forest());
-    std::string err = gf::build_host_forest(Xh, n, d, m, t, leaf, seed, F->host);
+    std::string err = gf::build_host_forest(Xh, n, d, m, t, leaf, seed,
+                                            (variants & GF_VARIANT_HOUSEHOLDER) != 0, F->host);
     if (!err.empty()) return fail(GF_EINTERNAL, err);
     GF_HIP(hipGetDevice(&F->device));
     F->uid = g_next_uid.fetch_add(1);
@@ -923,6 +944,10 @@ gf_status gf_build_forest(const float* X, int64_t n, int32_t d, int32_t m, int32
         }
         GF_HIP_B(hipMalloc(&F->drange, size_t(t) * sizeof(float2)));
         GF_HIP_B(hipMemcpy(F->drange, rng.data(), size_t(t) * sizeof(float2), hipMemcpyHostToDevice));
+    }
+    if (!h.U.empty()) {
+        GF_HIP_B(hipMalloc(&F->U, h.U.size() * sizeof(double)));
+        GF_HIP_B(hipMemcpy(F->U, h.U.data(), h.U.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     if (forms & GF_KEEP_BF16) {
         // leaf of every point in every tree, point-major (tile path)

@@ -29,6 +29,7 @@ struct HostForest {
     std::vector<float> split_val;     // [m][2^H - 1]
     std::vector<uint32_t> perm;       // [m][n] leaf-ordered point ids
     std::vector<uint32_t> leaf_off;   // [2^H + 1]
+    std::vector<double> U;            // [m][d] reflectors of the isometry variant, or empty
 };
 
 // Counter-based RNG (splitmix64 output function, keyed).
@@ -37,10 +38,16 @@ uint64_t keyed_draw(uint64_t seed, uint64_t stream, uint64_t tree, uint64_t idx)
 
 int32_t perfect_depth(int64_t n, int32_t p);
 
-// Builds the host arrays; X is host memory [n][d].  Returns an empty string
-// on success, else the error text.
+// Builds the host arrays; X is host memory [n][d].  With householder, tree i
+// splits the reflected coordinates float32((I - 2 u_i u_i') x) (Sec. 2.1
+// "Rotation", Sec. 2.2).  Returns an empty string on success, else the error.
 std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, int32_t t,
-                              int32_t p, uint64_t seed, HostForest& out);
+                              int32_t p, uint64_t seed, bool householder, HostForest& out);
+
+// Reflector of tree `tree`: w_j uniform in [-1, 1) from the top 53 bits of
+// keyed_draw(seed, 4, tree, j), normalised in FP64 (squares summed in index
+// order).
+void householder_vector(uint64_t seed, int32_t tree, int32_t d, double* u);
 
 }  // namespace gf
 
@@ -65,6 +72,7 @@ struct gf_forest {
     uint32_t* leafof = nullptr;     // [n][m] tree * 2^H + leaf of each point (BF16 form)
     int32_t* D = nullptr;           // [t]
     float2* drange = nullptr;       // [t] smallest and largest split value per slot of D
+    double* U = nullptr;            // [m][d] reflectors (isometry variant), or null
     // Grow-only scratch for queries.  Calls on one forest are serialised by
     // this mutex (concurrent queries on one forest wait for each other).
     std::mutex ws_mutex;

@@ -43,6 +43,26 @@ namespace {
 
 constexpr uint64_t kStreamSplitDim = 1;
 constexpr uint64_t kStreamTieKey = 2;
+constexpr uint64_t kStreamReflector = 4;
+
+// u . x in FP64: each product rounded, then added in index order (no fused
+// multiply-add, so the device reproduces it bit for bit).
+double reflector_dot(const double* u, const float* x, int32_t d) {
+#pragma clang fp contract(off)
+    double acc = 0.0;
+    for (int32_t j = 0; j < d; ++j) {
+        const double prod = u[j] * double(x[j]);
+        acc = acc + prod;
+    }
+    return acc;
+}
+
+// Coordinate s of (I - 2uu') x given t = u . x, rounded once to float32.
+float reflected(float xs, double t, double us) {
+#pragma clang fp contract(off)
+    const double r = (2.0 * t) * us;
+    return float(double(xs) - r);
+}
 
 unsigned worker_count(int64_t jobs) {
     unsigned hw = std::max(1u, std::thread::hardware_concurrency());
@@ -114,6 +134,10 @@ void build_tree(const float* X, int64_t n, int32_t d, const HostForest& F, int32
     const int64_t nint = (int64_t{1} << H) - 1;
     std::vector<uint64_t> tie(n);
     for (int64_t i = 0; i < n; ++i) tie[i] = keyed_draw(F.seed, kStreamTieKey, tree, uint64_t(i));
+    // isometry variant: u . x of every point under this tree's reflector
+    const double* u = F.U.empty() ? nullptr : F.U.data() + size_t(tree) * d;
+    std::vector<double> tdot(u ? n : 0);
+    for (int64_t i = 0; i < int64_t(tdot.size()); ++i) tdot[i] = reflector_dot(u, X + i * d, d);
     for (int64_t i = 0; i < n; ++i) ids[i] = uint32_t(i);
     std::vector<Item> items;
     // sizes/offsets of the nodes of the current level
@@ -131,7 +155,8 @@ void build_tree(const float* X, int64_t n, int32_t d, const HostForest& F, int32
             items.resize(len);
             for (int64_t a = 0; a < len; ++a) {
                 uint32_t id = ids[o + a];
-                items[a] = Item{X[int64_t(id) * d + s], tie[id], id};
+                const float xs = X[int64_t(id) * d + s];
+                items[a] = Item{u ? reflected(xs, tdot[id], u[s]) : xs, tie[id], id};
             }
             const int64_t nl = len / 2;
             std::nth_element(items.begin(), items.begin() + nl, items.end(), item_less);
@@ -153,12 +178,30 @@ void build_tree(const float* X, int64_t n, int32_t d, const HostForest& F, int32
 
 }  // namespace
 
+void householder_vector(uint64_t seed, int32_t tree, int32_t d, double* u) {
+#pragma clang fp contract(off)
+    double ss = 0.0;
+    for (int32_t j = 0; j < d; ++j) {
+        const uint64_t r = keyed_draw(seed, kStreamReflector, uint64_t(tree), uint64_t(j));
+        const double w = double(r >> 11) * 0x1p-53 * 2.0 - 1.0;   // exact
+        u[j] = w;
+        const double sq = w * w;
+        ss = ss + sq;
+    }
+    const double nrm = std::sqrt(ss);
+    for (int32_t j = 0; j < d; ++j) u[j] = u[j] / nrm;
+}
+
 std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, int32_t t,
-                              int32_t p, uint64_t seed, HostForest& F) {
+                              int32_t p, uint64_t seed, bool householder, HostForest& F) {
     F = HostForest{};
     F.n = n; F.d = d; F.m = m; F.t = t; F.p = p; F.seed = seed;
     F.H = perfect_depth(n, p);
     if (F.H > 23) return "tree depth above 23 (n/leaf too large)";
+    if (householder) {
+        F.U.resize(size_t(m) * d);
+        for (int32_t tr = 0; tr < m; ++tr) householder_vector(seed, tr, d, F.U.data() + size_t(tr) * d);
+    }
     const int64_t nint = (int64_t{1} << F.H) - 1;
     const int64_t nleaf = int64_t{1} << F.H;
 

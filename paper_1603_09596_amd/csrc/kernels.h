@@ -51,7 +51,14 @@ struct SelectArgs {
     uint32_t* leafbits;    // [m][W][nq]  (word-major, query fastest)
     uint32_t* qlist;       // [nq] queries sent to the next radix pass, in flags[1] order
     int nlist;             // > 0: a radix walk serves qlist[0 .. nlist) only
+    const float* qt;       // [m][nq][t] reflected query coordinates on D (isometry
+                           // variant), or null: tree i then reads qt, else Q[q][D[j]]
 };
+
+// Isometry variant: qt[i][q][j] = float32(q_s - (2 u_i.q) u_i[s]) for s = D[j],
+// with u_i.q summed in FP64 in index order (the build's definition).
+__global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, int m, int t,
+                                  const int32_t* D, const double* U, float* qt);
 
 __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps);
 // flags[0]: set when some query goes on to a radix pass; flags[1]: how many

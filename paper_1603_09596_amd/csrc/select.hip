@@ -153,11 +153,17 @@ __device__ __forceinline__ uint64_t leaf_key(uint32_t eff, uint32_t tree, uint32
     return (uint64_t(eff) << 32) | (uint64_t(tree) << 24) | uint64_t(entry);
 }
 
-// Shared setup of a walk kernel: stage q_D of the 64 queries into LDS.
-__device__ __forceinline__ void stage_query_dims(const SelectArgs& a, int q, float* qd) {
+// Shared setup of a walk kernel: stage the coordinates of the 64 queries on
+// D into LDS (for the isometry variant, those of the query reflected for
+// this tree).
+__device__ __forceinline__ void stage_query_dims(const SelectArgs& a, int q, uint32_t tree, float* qd) {
     const int lane = threadIdx.x & (kWave - 1);
-    for (int j = 0; j < a.t; ++j)
-        qd[j * kWave + lane] = (q < a.nq) ? a.Q[int64_t(q) * a.ldq + a.D[j]] : 0.0f;
+    for (int j = 0; j < a.t; ++j) {
+        float v = 0.0f;
+        if (q < a.nq)
+            v = a.qt ? a.qt[(int64_t(tree) * a.nq + q) * a.t + j] : a.Q[int64_t(q) * a.ldq + a.D[j]];
+        qd[j * kWave + lane] = v;
+    }
 }
 
 // The four waves of a walk workgroup serve the same 64 queries (lane =
@@ -202,7 +208,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
     const SelState st = (q < a.nq) ? a.state[q] : SelState{};
     const bool active = (q < a.nq) && st.status == kSelSearching && st.phase == uint32_t(PHASE);
     if (!__any(active)) return;   // the same for every wave of the workgroup
-    if (wave == 0) stage_query_dims(a, q, qd);
+    if (wave == 0) stage_query_dims(a, q, tree, qd);
     for (int b = wave; b < kBins / 2; b += kSelWaves) hist[b * kWave + lane] = 0u;
     __syncthreads();
     uint32_t cb, ce;
@@ -328,7 +334,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
     // slots from a shared counter (the order of the collected keys is free)
     const int slice = int(tree) * int(gridDim.z) + int(blockIdx.z);
     if (wave == 0) {
-        stage_query_dims(a, q, qd);
+        stage_query_dims(a, q, tree, qd);
         cnt[lane] = ready ? a.coff[int64_t(q) * a.nslice + slice] : 0u;
     }
     __syncthreads();
@@ -446,6 +452,30 @@ __device__ __forceinline__ void pick_bin(const uint32_t* hist, uint32_t cur, int
 
 }  // namespace
 
+// Isometry variant (Sec. 2.1 "Rotation", Sec. 2.2): one thread per (query,
+// tree) forms u.q in FP64 in index order, each product rounded before it is
+// added (no fused multiply-add, the same sums as the build), then each
+// coordinate on D of the reflected query, rounded once to float32.
+__global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, int m, int t,
+                                  const int32_t* D, const double* U, float* qt) {
+#pragma clang fp contract(off)
+    const int q = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
+    const int tree = int(blockIdx.y);
+    if (q >= nq || tree >= m) return;
+    const float* x = Q + int64_t(q) * ldq;
+    const double* u = U + int64_t(tree) * d;
+    double acc = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const double prod = u[j] * double(x[j]);
+        acc = acc + prod;
+    }
+    for (int j = 0; j < t; ++j) {
+        const int s = D[j];
+        const double r = (2.0 * acc) * u[s];
+        qt[(int64_t(tree) * nq + q) * t + j] = float(double(x[s]) - r);
+    }
+}
+
 // Per-query initialisation: budget and state.  Every gap's split value lies
 // within its slot's range, and float subtraction is monotone, so no eff
 // exceeds gmax = max over slots of |q - lo| and |q - hi|: the sample walk's
@@ -460,11 +490,13 @@ __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, 
     if (B > total) B = total;
     if (B < 0) B = 0;
     float gmax = 0.0f;
-    for (int j = 0; j < a.t; ++j) {
-        const float v = a.Q[int64_t(q) * a.ldq + a.D[j]];
-        const float2 r = a.drange[j];
-        gmax = fmaxf(gmax, fmaxf(fabsf(v - r.x), fabsf(v - r.y)));
-    }
+    const int ntq = a.qt ? a.m : 1;    // the isometry variant: every tree's reflected query
+    for (int i = 0; i < ntq; ++i)
+        for (int j = 0; j < a.t; ++j) {
+            const float v = a.qt ? a.qt[(int64_t(i) * a.nq + q) * a.t + j] : a.Q[int64_t(q) * a.ldq + a.D[j]];
+            const float2 r = a.drange[j];
+            gmax = fmaxf(gmax, fmaxf(fabsf(v - r.x), fabsf(v - r.y)));
+        }
     const uint32_t top = eff_bits(gmax) >> kSampleShift;
     SelState s{};
     s.budget = uint32_t(B);
@@ -681,12 +713,16 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
         // ties at E* cross the budget: order them by (tree, entry node).  Each
         // thread computes the tie keys of its own slots once, into the second
         // half of the query's key area, and reads back only those.
-        for (int j = threadIdx.x; j < a.t; j += blockDim.x) qd[j] = a.Q[int64_t(q) * a.ldq + a.D[j]];
+        for (int j = threadIdx.x; j < a.t; j += blockDim.x)
+            qd[j] = a.qt ? 0.0f : a.Q[int64_t(q) * a.ldq + a.D[j]];
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
             if (keys[i] != estar) continue;
             const uint32_t code = codes[i], tree = code >> 24;
-            tks[i] = (tree << 24) | entry_node(a, qd, tree, code & 0xFFFFFFu);
+            const uint32_t en = a.qt ? entry_node(a, a.qt + (int64_t(tree) * a.nq + q) * a.t, tree,
+                                                  code & 0xFFFFFFu)
+                                     : entry_node(a, qd, tree, code & 0xFFFFFFu);
+            tks[i] = (tree << 24) | en;
         }
         uint32_t tcur = 0;
         for (int r = 32; r > 0;) {

@@ -20,9 +20,10 @@ LIB_PATH = os.path.join(_HERE, "libgeraf.so")
 GF_OK, GF_EINVAL, GF_ENOMEM, GF_EHIP, GF_EUNSUPPORTED, GF_EINTERNAL = 0, -1, -2, -3, -4, -5
 FORM_FP32, FORM_BF16, FORM_FP8 = 0, 1, 2
 KEEP_BF16, KEEP_FP8 = 1 << 1, 1 << 2
+VARIANT_HOUSEHOLDER = 1 << 0
 FORMS = {"fp32": FORM_FP32, "bf16": FORM_BF16, "fp8": FORM_FP8}
 
-EXPORTED = ["gf_build_forest", "gf_free_forest", "gf_forest_info", "gf_export_tree", "gf_query",
+EXPORTED = ["gf_build_forest", "gf_build_forest_ex", "gf_free_forest", "gf_forest_info", "gf_export_tree", "gf_query",
             "gf_query_multi", "gf_multi_stats", "gf_query_trace", "gf_fp8_tables",
             "gf_last_query_timing", "gf_last_error", "gf_version"]
 MULTI_AUTOTUNE, MULTI_EAGER = 1, 2
@@ -57,6 +58,8 @@ def load():
     P, i32, i64, u32, u64, f64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                   ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double)
     lib.gf_build_forest.argtypes = [P, i64, i32, i32, i32, i32, u64, u32, P, ctypes.POINTER(P)]
+    lib.gf_build_forest_ex.argtypes = [P, i64, i32, i32, i32, i32, u64, u32, u32, P,
+                                       ctypes.POINTER(P)]
     lib.gf_free_forest.argtypes = [P]
     lib.gf_forest_info.argtypes = [P, P, P, P, P, P, P]
     lib.gf_export_tree.argtypes = [P, P, P, P, P, P]
@@ -152,16 +155,22 @@ class Forest:
                     split_dim=sd[:, :nint], split_val=sv[:, :nint], perm=perm, leaf_off=lo)
 
 
-def build_forest(X, m: int, t: int, leaf: int, seed: int, forms=(), stream=None) -> Forest:
-    """gf_build_forest.  X: [n, d] float32 (numpy or torch, host or device)."""
+def build_forest(X, m: int, t: int, leaf: int, seed: int, forms=(), stream=None,
+                 householder: bool = False) -> Forest:
+    """gf_build_forest, or gf_build_forest_ex with the Householder isometry
+    variant.  X: [n, d] float32 (numpy or torch, host or device)."""
     n, d = X.shape
     mask = 0
     for f in forms:
         mask |= {"bf16": KEEP_BF16, "fp8": KEEP_FP8}[f]
     h = ctypes.c_void_p()
     st = stream if stream is not None else _stream_of(X)
-    _check(load().gf_build_forest(_ptr(X), n, d, m, t, leaf, seed & 0xFFFFFFFFFFFFFFFF, mask, st,
-                                  ctypes.byref(h)))
+    if householder:
+        _check(load().gf_build_forest_ex(_ptr(X), n, d, m, t, leaf, seed & 0xFFFFFFFFFFFFFFFF, mask,
+                                         VARIANT_HOUSEHOLDER, st, ctypes.byref(h)))
+    else:
+        _check(load().gf_build_forest(_ptr(X), n, d, m, t, leaf, seed & 0xFFFFFFFFFFFFFFFF, mask,
+                                      st, ctypes.byref(h)))
     return Forest(h)
 
 

@@ -72,6 +72,19 @@ def test_build_rejects_bad_arguments_before_hip(lib):
     assert B(p, 1 << 25, 4, 2, 2, 1, 0, 0, None, ctypes.byref(out)) == geraf.GF_EUNSUPPORTED
 
 
+def test_build_ex_rejects_unknown_variants_before_hip(lib):
+    out = ctypes.c_void_p()
+    X = np.zeros((10, 4), np.float32)
+    p = X.ctypes.data_as(ctypes.c_void_p)
+    B = lib.gf_build_forest_ex
+    assert B(p, 10, 4, 2, 2, 2, 0, 0, 1 << 1, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert b"variants" in lib.gf_last_error()
+    assert B(p, 10, 4, 2, 2, 2, 0, 1 << 7, geraf.VARIANT_HOUSEHOLDER, None,
+             ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(None, 10, 4, 2, 2, 2, 0, 0, geraf.VARIANT_HOUSEHOLDER, None,
+             ctypes.byref(out)) == geraf.GF_EINVAL
+
+
 def test_query_rejects_bad_arguments_before_hip(lib):
     Q = np.zeros((3, 4), np.float32)
     ids = np.zeros((3, 2), np.int32)
