@@ -7,6 +7,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <atomic>
+#include <chrono>
+#include <cstdio>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -68,6 +70,49 @@ bool all_finite_host(const float* X, int64_t count) {
     for (char c : ok)
         if (!c) return false;
     return true;
+}
+
+// X (pageable host memory) -> dst [n][ld] on the device, rows zero-padded
+// to ld.  Pageable sources are copied slowly by the runtime, so the rows go
+// through two pinned buffers: host threads fill one while the other is
+// copied.  Returns the first HIP error, after the stream has drained.
+hipError_t upload_rows(float* dst, const float* Xh, int64_t n, int32_t d, int32_t ld, hipStream_t st) {
+    const size_t row_bytes = size_t(ld) * 4;
+    const int64_t rows_per = std::min<int64_t>(n, std::max<int64_t>(1, int64_t((size_t{128} << 20) / row_bytes)));
+    const int64_t nchunk = (n + rows_per - 1) / rows_per;
+    const int nbuf = nchunk > 1 ? 2 : 1;
+    void* buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t err = hipSuccess;
+    for (int b = 0; b < nbuf && err == hipSuccess; ++b) {
+        err = hipHostMalloc(&buf[b], size_t(rows_per) * row_bytes, hipHostMallocDefault);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&ev[b], hipEventDisableTiming);
+    }
+    const unsigned nw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    for (int64_t c = 0; c < nchunk && err == hipSuccess; ++c) {
+        const int b = int(c % nbuf);
+        if (c >= nbuf && (err = hipEventSynchronize(ev[b])) != hipSuccess) break;   // buffer free again
+        const int64_t r0 = c * rows_per, rows = std::min(rows_per, n - r0);
+        float* hb = static_cast<float*>(buf[b]);
+        std::vector<std::thread> th;
+        for (unsigned w = 0; w < nw; ++w)
+            th.emplace_back([=] {
+                for (int64_t i = rows * w / nw; i < rows * (w + 1) / nw; ++i) {
+                    std::memcpy(hb + i * ld, Xh + (r0 + i) * d, size_t(d) * 4);
+                    if (ld > d) std::memset(hb + i * ld + d, 0, size_t(ld - d) * 4);
+                }
+            });
+        for (auto& x : th) x.join();
+        err = hipMemcpyAsync(dst + r0 * ld, hb, size_t(rows) * row_bytes, hipMemcpyHostToDevice, st);
+        if (err == hipSuccess) err = hipEventRecord(ev[b], st);
+    }
+    const hipError_t sync = hipStreamSynchronize(st);
+    if (err == hipSuccess) err = sync;
+    for (int b = 0; b < 2; ++b) {
+        if (ev[b]) (void)hipEventDestroy(ev[b]);
+        if (buf[b]) (void)hipHostFree(buf[b]);
+    }
+    return err;
 }
 
 void free_forest_device(gf_forest* F) {
@@ -867,6 +912,18 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
     if (variants & ~GF_VARIANT_HOUSEHOLDER) return fail(GF_EINVAL, "unknown bits in variants");
     if (gf::perfect_depth(n, leaf) > 23) return fail(GF_EUNSUPPORTED, "tree depth above 23");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // GF_BUILD_TIMING=1 prints the wall time of each build phase to stderr
+    const char* tenv = std::getenv("GF_BUILD_TIMING");
+    const bool timing = tenv && tenv[0] == '1';
+    auto tprev = std::chrono::steady_clock::now();
+    auto phase = [&](const char* what) {
+        if (!timing) return;
+        (void)hipStreamSynchronize(st);
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[gf_build_forest] %-28s %8.3f s\n", what,
+                     std::chrono::duration<double>(now - tprev).count());
+        tprev = now;
+    };
 
     std::vector<float> staged;
     const float* Xh = X;
@@ -876,11 +933,13 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         Xh = staged.data();
     }
     if (!all_finite_host(Xh, n * int64_t(d))) return fail(GF_EINVAL, "X contains a non-finite value");
+    phase("stage + finiteness check");
 
     std::unique_ptr<gf_forest> F(new gf_forest());
     std::string err = gf::build_host_forest(Xh, n, d, m, t, leaf, seed,
                                             (variants & GF_VARIANT_HOUSEHOLDER) != 0, F->host);
     if (!err.empty()) return fail(GF_EINTERNAL, err);
+    phase("host trees");
     GF_HIP(hipGetDevice(&F->device));
     F->uid = g_next_uid.fetch_add(1);
     const gf::HostForest& h = F->host;
@@ -898,9 +957,15 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
     } while (0)
 
     GF_HIP_B(hipMalloc(&F->X32, size_t(n) * F->ld32 * 4));
-    GF_HIP_B(hipMemsetAsync(F->X32, 0, size_t(n) * F->ld32 * 4, st));
-    GF_HIP_B(hipMemcpy2DAsync(F->X32, size_t(F->ld32) * 4, Xh, size_t(d) * 4, size_t(d) * 4, n,
-                              hipMemcpyHostToDevice, st));
+    if (Xh != X) {
+        // X is already on the device: copy the rows into the padded layout
+        if (F->ld32 > d) GF_HIP_B(hipMemsetAsync(F->X32, 0, size_t(n) * F->ld32 * 4, st));
+        GF_HIP_B(hipMemcpy2DAsync(F->X32, size_t(F->ld32) * 4, X, size_t(d) * 4, size_t(d) * 4, n,
+                                  hipMemcpyDeviceToDevice, st));
+    } else {
+        GF_HIP_B(upload_rows(F->X32, Xh, n, d, F->ld32, st));
+    }
+    phase("X upload");
     std::vector<uint2> nodes(size_t(m) * std::max<int64_t>(nint, 1));
     for (int64_t i = 0; i < int64_t(m) * nint; ++i) {
         uint32_t bits;
@@ -929,6 +994,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         GF_HIP_B(hipMalloc(&F->permp, padded.size() * 4));
         GF_HIP_B(hipMemcpy(F->permp, padded.data(), padded.size() * 4, hipMemcpyHostToDevice));
     }
+    phase("nodes, perm, padded leaves");
     GF_HIP_B(hipMalloc(&F->D, size_t(t) * 4));
     GF_HIP_B(hipMemcpyAsync(F->D, h.D.data(), size_t(t) * 4, hipMemcpyHostToDevice, st));
     {
@@ -959,6 +1025,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
                     lof[size_t(h.perm[size_t(tr) * n + i]) * m + tr] = uint32_t(tr * nleaf + j);
         GF_HIP_B(hipMalloc(&F->leafof, lof.size() * 4));
         GF_HIP_B(hipMemcpy(F->leafof, lof.data(), lof.size() * 4, hipMemcpyHostToDevice));
+        phase("leaf of each point");
         GF_HIP_B(hipMalloc(&F->X16, size_t(n) * F->ld16 * 2));
         GF_HIP_B(hipMalloc(&F->norm16, size_t(n) * 4));
         hipLaunchKernelGGL(gf::k_to_bf16, dim3((n + 3) / 4), dim3(256), 0, st, F->X32, n, d,
@@ -974,6 +1041,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         GF_HIP_B(hipGetLastError());
     }
     GF_HIP_B(hipStreamSynchronize(st));
+    phase("reduced-precision copies");
 #undef GF_HIP_B
     *out = F.release();
     return GF_OK;
