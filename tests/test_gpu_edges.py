@@ -1,0 +1,98 @@
+"""Shapes at the edges of the library's limits against the oracle: one
+dimension, one point, one tree with t = d, the maximum of 255 trees, and the
+maximum k = 64 (FP32, and BF16 with a re-rank depth of 64).  Tree arrays,
+opened leaves and candidate sets bit-exact; neighbours by the acceptance
+rule (FP32) or exact distances and recall (BF16)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_09596_amd import geraf
+from parity import check_knn, ids_from_bits, leaf_set_from_bits
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    geraf.load()
+
+
+def shape(name):
+    rng = np.random.default_rng(sum(name.encode()))
+    if name == "d1":                 # one dimension: t = 1, rows padded to 4 floats
+        X = rng.standard_normal((3000, 1)).astype(np.float32)
+        Q = rng.standard_normal((20, 1)).astype(np.float32)
+        return X, Q, 3, 1, 4, 10, 50
+    if name == "n1":                 # one point: H = 0, k above n pads
+        X = rng.standard_normal((1, 5)).astype(np.float32)
+        Q = rng.standard_normal((4, 5)).astype(np.float32)
+        return X, Q, 2, 2, 1, 3, 1
+    if name == "m1-t=d":             # one tree, every dimension in D
+        X = rng.standard_normal((2000, 16)).astype(np.float32)
+        Q = (X[:25] + 0.1 * rng.standard_normal((25, 16))).astype(np.float32)
+        return X, Q, 1, 16, 8, 5, 20
+    if name == "m255":               # the largest forest the ABI accepts
+        X = rng.standard_normal((600, 8)).astype(np.float32)
+        Q = (X[:30] + 0.1 * rng.standard_normal((30, 8))).astype(np.float32)
+        return X, Q, 255, 3, 16, 10, 300
+    if name == "k64":                # the largest k
+        X = rng.standard_normal((5000, 32)).astype(np.float32)
+        Q = (X[:30] + 0.2 * rng.standard_normal((30, 32))).astype(np.float32)
+        return X, Q, 4, 5, 8, 64, 200
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["d1", "n1", "m1-t=d", "m255", "k64"])
+def test_edge_shape_fp32(name):
+    X, Q, m, t, p, k, c = shape(name)
+    seed = 3 + len(name)
+    Fg = geraf.build_forest(X, m, t, p, seed)
+    Fo = oracle.build_forest(X, m, t, p, seed)
+    try:
+        T = Fg.export_tree()
+        for key in ("D", "split_dim", "split_val", "perm", "leaf_off"):
+            assert np.array_equal(T[key], Fo[key]), key
+        ref = oracle.search(Fo, X, Q, k, c, candidates=True)
+        nq = len(Q)
+        lb = np.zeros((nq, Fg.m, Fg.leaf_words), np.uint32)
+        cb = np.zeros((nq, (Fg.n + 31) // 32), np.uint32)
+        nc = np.zeros(nq, np.int64)
+        geraf.query_trace(Fg, Q, c, leaf_bits=lb, cand_bits=cb, ncand=nc)
+        for i in range(nq):
+            assert leaf_set_from_bits(lb[i]) == set(ref["opened"][i].tolist()), f"query {i}"
+            assert np.array_equal(ids_from_bits(cb[i], Fg.n), ref["cand"][i]), f"query {i}"
+        ids = np.zeros((nq, k), np.int32)
+        dd = np.zeros((nq, k), np.float32)
+        geraf.query(Fg, Q, k, c, ids, dd)
+        check_knn(ids, dd, ref["ids"], ref["dists"], X=X, Q=Q)
+    finally:
+        Fg.free()
+
+
+def test_k64_bf16_rerank_64():
+    X, Q, m, t, p, k, c = shape("k64")
+    Fg = geraf.build_forest(X, m, t, p, 9, forms=("bf16",))
+    Fo = oracle.build_forest(X, m, t, p, 9)
+    try:
+        ref = oracle.search(Fo, X, Q, k, c, trace=False)
+        ids = np.zeros((len(Q), k), np.int32)
+        dd = np.zeros((len(Q), k), np.float32)
+        geraf.query(Fg, Q, k, c, ids, dd, form="bf16", rerank=64)
+        hits = 0
+        for i in range(len(Q)):
+            got = ids[i][ids[i] >= 0]
+            for j, gid in enumerate(got.tolist()):
+                diff = X[gid].astype(np.float64) - Q[i].astype(np.float64)
+                true_d = float(diff @ diff)
+                assert abs(dd[i][j] - true_d) <= 1e-5 * true_d
+            hits += len(set(got.tolist()) & set(ref["ids"][i].tolist()))
+        # with the re-rank depth equal to k, the BF16 selection alone decides
+        # membership: the floor is what this seeded case reaches
+        assert hits / ref["ids"].size >= 0.95
+    finally:
+        Fg.free()
