@@ -182,27 +182,29 @@ def sweep_bench(args, torch, geraf, workloads, dev):
 
 
 def pmc_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
-    summary of `workload`, or None when absent, for another kernel, or taken
-    on a different source of that kernel."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{workload}.txt")
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    for line in open(path):
-        if ":" in line:
-            key, v = line.split(":", 1)
-            vals[key.strip()] = v.strip()
-    src = vals.get("source_file")
-    if vals.get("kernel") != kernel or not src:
-        return None
-    cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
-    if vals.get("source_sha256") != cur:
-        return None
-    try:
-        return float(vals["hbm_bytes_per_dispatch"])
-    except (KeyError, ValueError):
-        return None
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc
+    summary of `workload` (profiles/pmc_<workload>.txt or
+    profiles/pmc_<workload>_<part>.txt), or None when none records that
+    kernel, or the one that does was taken on a different source of it."""
+    import glob
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", f"pmc_{glob.escape(workload)}*.txt")))
+    for path in paths:
+        vals = {}
+        for line in open(path):
+            if ":" in line:
+                key, v = line.split(":", 1)
+                vals[key.strip()] = v.strip()
+        src = vals.get("source_file")
+        if vals.get("kernel") != kernel or not src:
+            continue
+        cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+        if vals.get("source_sha256") != cur:
+            return None
+        try:
+            return float(vals["hbm_bytes_per_dispatch"])
+        except (KeyError, ValueError):
+            return None
+    return None
 
 
 def cpu_baseline(w, idx_all, checks, seconds, threads, householder=False):

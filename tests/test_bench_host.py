@@ -59,3 +59,12 @@ def test_sweep_settings_cover_the_paper_tables():
     # the four eps values and the eight points-per-leaf values of the tables
     assert bench.SWEEPS["eps"]["eps"] == (0.0, 0.1, 0.5, 0.9)
     assert bench.SWEEPS["p"]["p"] == (256, 128, 64, 32, 16, 4, 2, 1)
+
+
+def test_pmc_traffic_reads_the_record_of_the_named_kernel():
+    # the committed records: the tile kernel of the headline workload and the
+    # FP8 scan of the 10,000-dim one; no record for an unknown kernel
+    for kernel, workload in (("k_tile_bf16", "desc-1m-960"), ("k_scan (fp8)", "gauss-200k-10000")):
+        v = bench.pmc_traffic(kernel, workload)
+        assert v is None or v > 1e9
+    assert bench.pmc_traffic("no_such_kernel", "desc-1m-960") is None
