@@ -82,3 +82,36 @@ def test_reflected_forest_tile_path(monkeypatch):
             assert abs(dd[i][j] - true_d) <= 1e-5 * true_d
         hits += len(set(got.tolist()) & set(ref["ids"][i].tolist()))
     assert hits / ref["ids"].size >= 0.98
+
+
+def test_reflected_forests_in_the_multi_index_graph():
+    """gf_query_multi captures the per-tree query reflection in its graph:
+    a reflected forest beside a plain one gives what single calls give, on a
+    first launch and on a replay with the buffers refilled."""
+    Xr, _, m, t, p = case_data("ragged-3001-77")
+    plain = geraf.build_forest(Xr, m, t, p, 5)
+    cases = [("gauss-10k-128", forests("gauss-10k-128")[0], 300),
+             ("ragged-3001-77", plain, 100),
+             ("quantised", forests("quantised")[0], 150)]
+    ref, jobs = [], []
+    for name, Fg, c in cases:
+        _, Q, _, _, _ = case_data(name)
+        Qd = torch.from_numpy(Q).to("cuda:0")
+        ids = torch.empty((len(Q), 5), dtype=torch.int32, device="cuda:0")
+        dd = torch.empty((len(Q), 5), dtype=torch.float32, device="cuda:0")
+        geraf.query(Fg, Qd, 5, c, ids, dd)
+        torch.cuda.synchronize()
+        ref.append((ids.cpu().numpy(), dd.cpu().numpy()))
+        jobs.append(dict(forest=Fg, Q=Qd, k=5, checks=c, form="fp32",
+                         ids=torch.full((len(Q), 5), -7, dtype=torch.int32, device="cuda:0"),
+                         dists=torch.full((len(Q), 5), -7.0, dtype=torch.float32, device="cuda:0")))
+    for _ in range(2):
+        geraf.query_multi(jobs)
+        torch.cuda.synchronize()
+        for j, r in zip(jobs, ref):
+            assert np.array_equal(j["ids"].cpu().numpy(), r[0])
+            assert np.array_equal(j["dists"].cpu().numpy(), r[1])
+            j["ids"].fill_(-3)
+            j["dists"].fill_(-3.0)
+        torch.cuda.synchronize()
+    plain.free()
