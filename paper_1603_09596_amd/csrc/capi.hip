@@ -72,6 +72,24 @@ bool all_finite_host(const float* X, int64_t count) {
     return true;
 }
 
+// rows [n][d] -> dst [n][ld] in host memory, zero-padded, with host threads
+// for large copies (about one per 4 MB, at most 16).
+void pad_rows(float* dst, const float* src, int64_t n, int32_t d, int32_t ld) {
+    const size_t bytes = size_t(n) * size_t(ld) * 4;
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const unsigned nw = unsigned(std::max<size_t>(1, std::min<size_t>(hw, bytes >> 22)));
+    auto part = [=](unsigned w) {
+        for (int64_t i = n * w / nw; i < n * (w + 1) / nw; ++i) {
+            std::memcpy(dst + i * ld, src + i * d, size_t(d) * 4);
+            if (ld > d) std::memset(dst + i * ld + d, 0, size_t(ld - d) * 4);
+        }
+    };
+    if (nw == 1) { part(0); return; }
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nw; ++w) th.emplace_back(part, w);
+    for (auto& x : th) x.join();
+}
+
 // X (pageable host memory) -> dst [n][ld] on the device, rows zero-padded
 // to ld.  Pageable sources are copied slowly by the runtime, so the rows go
 // through two pinned buffers: host threads fill one while the other is
@@ -88,21 +106,12 @@ hipError_t upload_rows(float* dst, const float* Xh, int64_t n, int32_t d, int32_
         err = hipHostMalloc(&buf[b], size_t(rows_per) * row_bytes, hipHostMallocDefault);
         if (err == hipSuccess) err = hipEventCreateWithFlags(&ev[b], hipEventDisableTiming);
     }
-    const unsigned nw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     for (int64_t c = 0; c < nchunk && err == hipSuccess; ++c) {
         const int b = int(c % nbuf);
         if (c >= nbuf && (err = hipEventSynchronize(ev[b])) != hipSuccess) break;   // buffer free again
         const int64_t r0 = c * rows_per, rows = std::min(rows_per, n - r0);
         float* hb = static_cast<float*>(buf[b]);
-        std::vector<std::thread> th;
-        for (unsigned w = 0; w < nw; ++w)
-            th.emplace_back([=] {
-                for (int64_t i = rows * w / nw; i < rows * (w + 1) / nw; ++i) {
-                    std::memcpy(hb + i * ld, Xh + (r0 + i) * d, size_t(d) * 4);
-                    if (ld > d) std::memset(hb + i * ld + d, 0, size_t(ld - d) * 4);
-                }
-            });
-        for (auto& x : th) x.join();
+        pad_rows(hb, Xh + r0 * d, rows, d, ld);
         err = hipMemcpyAsync(dst + r0 * ld, hb, size_t(rows) * row_bytes, hipMemcpyHostToDevice, st);
         if (err == hipSuccess) err = hipEventRecord(ev[b], st);
     }
@@ -115,6 +124,25 @@ hipError_t upload_rows(float* dst, const float* Xh, int64_t n, int32_t d, int32_
     return err;
 }
 
+// Host query rows -> dst [rows][ld] on the device through the forest's
+// pinned staging buffer (grown on demand).  The stream is drained first, so
+// the buffer is free to refill; the caller synchronises before the next use.
+hipError_t stage_host_rows(gf_forest* F, float* dst, const float* src, int64_t rows, int32_t d,
+                           int32_t ld, hipStream_t st) {
+    const size_t bytes = size_t(rows) * size_t(ld) * 4;
+    hipError_t err = hipStreamSynchronize(st);
+    if (err != hipSuccess) return err;
+    if (bytes > F->hstage_bytes) {
+        if (F->hstage) (void)hipHostFree(F->hstage);
+        F->hstage = nullptr;
+        F->hstage_bytes = 0;
+        if ((err = hipHostMalloc(&F->hstage, bytes, hipHostMallocDefault)) != hipSuccess) return err;
+        F->hstage_bytes = bytes;
+    }
+    pad_rows(static_cast<float*>(F->hstage), src, rows, d, ld);
+    return hipMemcpyAsync(dst, F->hstage, bytes, hipMemcpyHostToDevice, st);
+}
+
 void free_forest_device(gf_forest* F) {
     void* ptrs[] = {F->X32, F->X16, F->norm16, F->X8, F->scale8, F->norm8,
                     F->nodes, F->perm, F->leaf_off, F->permp, F->leafof, F->D, F->drange, F->U, F->ws};
@@ -124,6 +152,9 @@ void free_forest_device(gf_forest* F) {
     F->scale8 = nullptr; F->norm8 = nullptr; F->nodes = nullptr; F->perm = nullptr;
     F->leaf_off = nullptr; F->permp = nullptr; F->leafof = nullptr; F->D = nullptr; F->drange = nullptr;
     F->U = nullptr;
+    if (F->hstage) (void)hipHostFree(F->hstage);
+    F->hstage = nullptr;
+    F->hstage_bytes = 0;
     F->ws = nullptr;
     F->ws_bytes = 0;
 }
@@ -468,10 +499,14 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     struct EvGuard { hipEvent_t* e; ~EvGuard() { for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]); } } evg{ev};
     GF_HIP(hipEventRecord(ev[0], st));
     // a1: query prep -- padded FP32 rows, finiteness, reduced copies
-    GF_HIP(hipMemsetAsync(w.Qp, 0, size_t(nb) * F->ld32 * 4, st));
-    GF_HIP(hipMemcpy2DAsync(w.Qp, size_t(F->ld32) * 4, J.Q + q0 * h.d, size_t(h.d) * 4,
-                            size_t(h.d) * 4, nb,
-                            J.q_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    if (J.q_dev) {
+        GF_HIP(hipMemsetAsync(w.Qp, 0, size_t(nb) * F->ld32 * 4, st));
+        GF_HIP(hipMemcpy2DAsync(w.Qp, size_t(F->ld32) * 4, J.Q + q0 * h.d, size_t(h.d) * 4,
+                                size_t(h.d) * 4, nb, hipMemcpyDeviceToDevice, st));
+    } else {
+        // pageable host rows would be copied slowly by the runtime
+        GF_HIP(stage_host_rows(F, w.Qp, J.Q + q0 * h.d, nb, h.d, F->ld32, st));
+    }
     GF_HIP(hipMemsetAsync(w.flags, 0, 8 * 4, st));
     {
         const int64_t tot = int64_t(nb) * h.d;

@@ -78,6 +78,9 @@ struct gf_forest {
     std::mutex ws_mutex;
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    // Grow-only pinned host buffer that stages host query rows (same mutex).
+    void* hstage = nullptr;
+    size_t hstage_bytes = 0;
     uint64_t uid = 0;               // unique per forest built in this process
     // path choices measured by the multi-index autotuner, keyed by
     // (form, batch-size class, re-rank depth): 0 rows, 1 tile
