@@ -126,7 +126,10 @@ gf_status gf_export_tree(const gf_forest *F, int32_t *D, int32_t *split_dim,
  * BF16 scores of 128-query blocks against all points on MFMA and keeps only
  * those of each query's candidates.  The environment variable GF_SCAN_PATH
  * (= rows | tile) overrides the choice where the tile path is available.
- *   Q                 [nq][d] float32, host-or-device, finite.
+ *   Q                 [nq][d] float32, host-or-device, finite.  Host rows are
+ *                     copied through a pinned host buffer that the forest
+ *                     keeps and grows to its largest batch (at most 16,384
+ *                     padded rows); gf_free_forest releases it.
  *   k                 neighbours per query (1..64).
  *   checks            the paper's c: leaves to check per query (>= 1).
  *   checks_per_query  NULL, or nq int32 budgets (host-or-device) that
