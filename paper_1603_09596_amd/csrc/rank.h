@@ -47,20 +47,35 @@ struct WaveList {
 // (q - x) split exactly into s + e (two-sum), s^2 split exactly into p + r
 // (two-product with FMA), the p's summed with two-sum and every rounding
 // error collected in a second accumulator (Ogita, Rump, Oishi 2005).
+// Each lane takes j = lane, lane + 64, ... in order; the loads of kRowUnroll
+// steps are issued before any is used (a position past d reads as zero, and
+// a zero term leaves sum and err exactly as they were).
+constexpr int kRowUnroll = 8;
+
 __device__ __forceinline__ float row_dist_fp32_comp(const float* q, const float* x, int d) {
     const int lane = threadIdx.x & (kWave - 1);
     float sum = 0.0f, err = 0.0f;
-    for (int j = lane; j < d; j += kWave) {
-        const float a = q[j], b = -x[j];
-        const float s = a + b;
-        const float bb = s - a;
-        const float e = (a - (s - bb)) + (b - bb);
-        const float p = s * s;
-        const float r = fmaf(s, s, -p);
-        const float t = sum + p;
-        const float tp = t - sum;
-        err += ((sum - (t - tp)) + (p - tp)) + r + fmaf(2.0f * s, e, e * e);
-        sum = t;
+    for (int j0 = lane; j0 < d; j0 += kRowUnroll * kWave) {
+        float qa[kRowUnroll], xb[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int j = j0 + u * kWave;
+            qa[u] = j < d ? q[j] : 0.0f;
+            xb[u] = j < d ? x[j] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const float a = qa[u], b = -xb[u];
+            const float s = a + b;
+            const float bb = s - a;
+            const float e = (a - (s - bb)) + (b - bb);
+            const float p = s * s;
+            const float r = fmaf(s, s, -p);
+            const float t = sum + p;
+            const float tp = t - sum;
+            err += ((sum - (t - tp)) + (p - tp)) + r + fmaf(2.0f * s, e, e * e);
+            sum = t;
+        }
     }
 #pragma unroll
     for (int o = kWave / 2; o >= 1; o >>= 1) {
@@ -77,9 +92,19 @@ __device__ __forceinline__ float row_dist_fp32_comp(const float* q, const float*
 __device__ __forceinline__ double row_dist_fp64(const float* q, const float* x, int d) {
     const int lane = threadIdx.x & (kWave - 1);
     double acc = 0.0;
-    for (int j = lane; j < d; j += kWave) {
-        const double diff = double(q[j]) - double(x[j]);
-        acc = fma(diff, diff, acc);
+    for (int j0 = lane; j0 < d; j0 += kRowUnroll * kWave) {
+        float qa[kRowUnroll], xb[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int j = j0 + u * kWave;
+            qa[u] = j < d ? q[j] : 0.0f;
+            xb[u] = j < d ? x[j] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const double diff = double(qa[u]) - double(xb[u]);
+            acc = fma(diff, diff, acc);
+        }
     }
 #pragma unroll
     for (int o = kWave / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
