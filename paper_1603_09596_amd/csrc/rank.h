@@ -170,13 +170,30 @@ __device__ __forceinline__ void finish_query(bool rerank, int kk, int k, int q, 
             if (lane == 0) lds_rr[e] = dv;
         }
         __syncthreads();
-        if (wave == 0) {
-            L.init();
-            for (int e = 0; e < kk; ++e) {
-                const float dc = lds_rr[e];
-                if (!(dc < __builtin_inff())) continue;
-                L.offer(dc, lds_i[e], kk);
+        // order the re-measured entries: thread e takes the rank of entry e
+        // among them by (distance, id) (ids are distinct, so ranks are too)
+        const int t = int(threadIdx.x);
+        float dv = __builtin_inff();
+        int iv = 0x7FFFFFFF, rank = kk;
+        if (t < kk) {
+            dv = lds_rr[t];
+            iv = lds_i[t];
+            if (dv < __builtin_inff()) {
+                rank = 0;
+                for (int f = 0; f < kk; ++f) {
+                    const float fd = lds_rr[f];
+                    if (fd < __builtin_inff() && entry_before(fd, lds_i[f], dv, iv)) ++rank;
+                }
             }
+        }
+        __syncthreads();
+        if (t < kk) { lds_d[t] = __builtin_inff(); lds_i[t] = 0x7FFFFFFF; }
+        __syncthreads();
+        if (rank < kk) { lds_d[rank] = dv; lds_i[rank] = iv; }
+        __syncthreads();
+        if (wave == 0) {
+            L.d = lane < kk ? lds_d[lane] : __builtin_inff();
+            L.id = lane < kk ? lds_i[lane] : 0x7FFFFFFF;
         }
     }
     if (wave == 0) {

@@ -508,7 +508,8 @@ __global__ __launch_bounds__(256) void k_expand_points(ExpandArgs a) {
 }
 
 // Best kk over the splits' lists, then the final ranking of the query.
-__global__ __launch_bounds__(512) void k_merge_rerank(MergeArgs a) {
+constexpr int kMergeMax = 512;   // the workgroup: up to this many list entries are ranked at once
+__global__ __launch_bounds__(kMergeMax) void k_merge_rerank(MergeArgs a) {
     __shared__ float md[kWave];
     __shared__ int mi[kWave];
     __shared__ float mr[kWave];
@@ -517,10 +518,34 @@ __global__ __launch_bounds__(512) void k_merge_rerank(MergeArgs a) {
     const int wave = threadIdx.x / kWave;
     WaveList L;
     L.init();
-    if (wave == 0) {
-        const int64_t tot = int64_t(a.nsplit) * kTileList;
-        const float* ps = a.part_s + int64_t(q) * tot;
-        const int* pi = a.part_i + int64_t(q) * tot;
+    const int64_t tot = int64_t(a.nsplit) * kTileList;
+    const float* ps = a.part_s + int64_t(q) * tot;
+    const int* pi = a.part_i + int64_t(q) * tot;
+    if (tot <= int64_t(blockDim.x)) {
+        // every entry at once: thread e takes the rank of entry e among the
+        // filled ones by (score, id); ids are distinct (each point lies in
+        // one split), so the ranks below kk give the kk best in order
+        __shared__ float es[kMergeMax];
+        __shared__ int ei[kMergeMax];
+        const int t = int(threadIdx.x);
+        float sv = __builtin_inff();
+        int iv = 0x7FFFFFFF;
+        if (t < tot) { sv = ps[t]; iv = pi[t]; }
+        if (t < kMergeMax) { es[t] = sv; ei[t] = iv; }
+        if (t < kWave) { md[t] = __builtin_inff(); mi[t] = 0x7FFFFFFF; }
+        __syncthreads();
+        if (sv < __builtin_inff()) {
+            int rank = 0;
+            for (int f = 0; f < int(tot); ++f)
+                if (es[f] < __builtin_inff() && entry_before(es[f], ei[f], sv, iv)) ++rank;
+            if (rank < a.kk) { md[rank] = sv; mi[rank] = iv; }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            L.d = lane < a.kk ? md[lane] : __builtin_inff();
+            L.id = lane < a.kk ? mi[lane] : 0x7FFFFFFF;
+        }
+    } else if (wave == 0) {
         for (int64_t e0 = 0; e0 < tot; e0 += kWave) {
             const int64_t e = e0 + lane;
             const float s = e < tot ? ps[e] : __builtin_inff();
