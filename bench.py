@@ -223,12 +223,31 @@ def cpu_baseline(w, idx_all, checks, seconds, threads, householder=False):
     nsample = (nsample + threads - 1) // threads * threads
     sample = idx_all[:nsample]
     t0 = time.perf_counter()
-    oracle.search(F, w.X, w.Q[sample], w.k, checks, nthreads=threads, trace=False)
+    ref = oracle.search(F, w.X, w.Q[sample], w.k, checks, nthreads=threads, trace=False)
     dt = time.perf_counter() - t0
     return dict(value=round(len(sample) / dt, 3), unit="queries/s", cores=threads, kind="oracle",
                 sample=f"first {len(sample)} of the {len(w.Q)} queries (evenly spaced), "
                        f"c={checks}, k={w.k}; FP64 sequential queue per query, one query per "
-                       f"thread; forest build excluded")
+                       f"thread; forest build excluded"), sample, ref
+
+
+def vs_oracle(X, Q, ids, dists, ref):
+    """The GPU answers of the oracle's sample against the oracle: recall of
+    the oracle's k (its FP64 top-k at the same budget) and the relative error
+    of every returned distance against its FP64 value."""
+    hits, errs = 0, []
+    for j in range(len(Q)):
+        got = ids[j][ids[j] >= 0]
+        hits += len(set(got.tolist()) & set(ref["ids"][j][ref["ids"][j] >= 0].tolist()))
+        for r, gid in enumerate(got.tolist()):
+            diff = X[gid].astype(np.float64) - Q[j].astype(np.float64)
+            true_d = float(diff @ diff)
+            errs.append(abs(float(dists[j][r]) - true_d) / true_d if true_d > 0 else 0.0)
+    n_ref = max(1, int((ref["ids"] >= 0).sum()))
+    return {f"recall@{ids.shape[1]}": round(hits / n_ref, 4),
+            "max_rel_dist_err": float(f"{max(errs):.3g}") if errs else 0.0,
+            "mean_rel_dist_err": float(f"{np.mean(errs):.3g}") if errs else 0.0,
+            "queries": len(Q)}
 
 
 def multi_bench(args, torch, geraf, workloads, dev):
@@ -375,7 +394,7 @@ def main():
         mean = {key: float(np.mean([p[key] for p in phases]))
                 for key in ("prep_ms", "select_ms", "scan_or_expand_ms", "tile_ms", "merge_ms")}
         mean["path"] = phases[-1]["path"]
-        return wall, mean, ids.cpu().numpy()
+        return wall, mean, ids.cpu().numpy(), dists.cpu().numpy()
 
     def scan_roofline(f, ms):
         # the row scan (gathers + distances + best-k): algorithmic bytes per launch
@@ -385,11 +404,11 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=pmc_traffic(f"k_scan ({f})", name),
                     kernel=f"k_scan ({f})", bytes_per_launch=int(algo), ms_per_launch=round(ms, 3))
 
-    wall, ph, ids_main = timed(form, args.steps, args.warmup)
+    wall, ph, ids_main, dists_main = timed(form, args.steps, args.warmup)
     value = args.steps * nq / wall
     fp32 = None
     if form != "fp32" and not args.no_fp32:
-        wall32, ph32, ids_fp32 = timed("fp32", max(1, args.steps), 1)
+        wall32, ph32, ids_fp32, _ = timed("fp32", max(1, args.steps), 1)
         fp32 = dict(value=round(args.steps * nq / wall32, 2), path=ph32["path"],
                     scan_ms=round(ph32["scan_or_expand_ms"], 2),
                     ms_per_step=round(1000 * wall32 / max(1, args.steps), 2))
@@ -400,12 +419,19 @@ def main():
     # recall@10 on a query sample against exact FP64 neighbours
     idx = np.linspace(0, nq - 1, min(args.recall_sample, nq)).astype(np.int64)
     t0 = time.perf_counter()
-    gt, _ = bf.knn_ground_truth(w.X, w.Q[idx], k)
+    gt, gt_dist = bf.knn_ground_truth(w.X, w.Q[idx], k)
     log(f"[bench] ground truth for {len(idx)} queries {time.perf_counter() - t0:.1f}s")
     rec_main = recall_at(ids_main[idx], gt)
     one_main = float(np.mean([gt[i, 0] in set(ids_main[j].tolist()) for i, j in enumerate(idx)]))
+    # the paper's 1-NN miss rate (Sec. 4): the first answer farther than the exact nearest
+    first = ids_main[idx, 0].astype(np.int64)
+    d_first = np.full(len(idx), np.inf)
+    ok = first >= 0
+    diff = w.X[first[ok]].astype(np.float64) - w.Q[idx[ok]].astype(np.float64)
+    d_first[ok] = np.einsum("ij,ij->i", diff, diff)
+    miss_1nn, _ = nn_quality(gt_dist[:, 0], d_first, 0.0)
     if fp32 is not None:
-        fp32["recall@10"] = round(recall_at(ids_fp32[idx], gt), 4)
+        fp32[f"recall@{k}"] = round(recall_at(ids_fp32[idx], gt), 4)
 
     if ph["path"] == "tile":
         # dominant kernel: the MFMA score kernel, 2*nq*n*d flops per launch
@@ -418,9 +444,10 @@ def main():
     else:
         roofline = scan_roofline(form, ph["scan_or_expand_ms"])
 
-    cpu = None
+    cpu, oracle_cmp = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, idx, c, args.cpu_seconds, host_threads(), args.householder)
+        cpu, sample, ref = cpu_baseline(w, idx, c, args.cpu_seconds, host_threads(), args.householder)
+        oracle_cmp = vs_oracle(w.X, w.Q[sample], ids_main[sample], dists_main[sample], ref)
 
     if name == WORKLOAD and not args.householder:
         metric = "queries/s at recall@10>=0.90, 1Mx960, 16 trees; BF16 vs FP32 form"
@@ -446,6 +473,8 @@ def main():
                    "variant": "householder" if args.householder else None},
         f"recall@{k}": round(rec_main, 4),
         f"1-recall@{k}": round(one_main, 4),
+        "miss_pct_1nn": round(miss_1nn, 2),
+        "vs_oracle": oracle_cmp,
         "recall_sample": len(idx),
         "mean_candidates": round(ncand_total / nq, 1),
         "path": ph["path"],

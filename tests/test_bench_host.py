@@ -68,3 +68,17 @@ def test_pmc_traffic_reads_the_record_of_the_named_kernel():
         v = bench.pmc_traffic(kernel, workload)
         assert v is None or v > 1e9
     assert bench.pmc_traffic("no_such_kernel", "desc-1m-960") is None
+
+
+def test_vs_oracle_recall_and_distance_errors():
+    import numpy as np
+    X = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 2.0], [3.0, 0.0]], np.float32)
+    Q = np.array([[0.0, 0.0], [1.0, 0.0]], np.float32)
+    # oracle's 2 best: query 0 -> ids 0, 1; query 1 -> ids 1, 0
+    ref = {"ids": np.array([[0, 1], [1, 0]]), "dists": np.array([[0.0, 1.0], [0.0, 1.0]])}
+    ids = np.array([[0, 1], [1, 3]], np.int32)           # query 1 misses id 0
+    dists = np.array([[0.0, 1.0], [0.0, 4.0 * (1 + 1e-6)]], np.float32)
+    out = bench.vs_oracle(X, Q, ids, dists, ref)
+    assert out["recall@2"] == pytest.approx(0.75)
+    assert out["queries"] == 2
+    assert 5e-7 < out["max_rel_dist_err"] < 2e-6
