@@ -225,7 +225,13 @@ def cpu_baseline(w, idx_all, checks, seconds, threads, householder=False):
     t0 = time.perf_counter()
     ref = oracle.search(F, w.X, w.Q[sample], w.k, checks, nthreads=threads, trace=False)
     dt = time.perf_counter() - t0
+    # one thread, on the first queries of the same sample (about 5 s)
+    n1 = int(max(1, min(len(sample), 5.0 / max(per_q * threads, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.search(F, w.X, w.Q[sample[:n1]], w.k, checks, nthreads=1, trace=False)
+    dt1 = time.perf_counter() - t0
     return dict(value=round(len(sample) / dt, 3), unit="queries/s", cores=threads, kind="oracle",
+                single_thread=dict(value=round(n1 / dt1, 3), queries=n1),
                 sample=f"first {len(sample)} of the {len(w.Q)} queries (evenly spaced), "
                        f"c={checks}, k={w.k}; FP64 sequential queue per query, one query per "
                        f"thread; forest build excluded"), sample, ref
