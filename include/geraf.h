@@ -75,7 +75,9 @@ typedef enum { GF_FORM_FP32 = 0, GF_FORM_BF16 = 1, GF_FORM_FP8 = 2 } gf_form;
  *   out    receives the new forest; release it with gf_free_forest.
  * The build runs on the host (threads over trees, Sec. 3 "Parallelization");
  * the arrays, the FP32 rows and the requested reduced-precision copies are
- * then uploaded on `stream`. */
+ * then uploaded on `stream` (host rows through pinned staging buffers).
+ * With the environment variable GF_BUILD_TIMING=1 each phase's wall time is
+ * printed to stderr. */
 gf_status gf_build_forest(const float *X, int64_t n, int32_t d, int32_t m, int32_t t,
                           int32_t leaf, uint64_t seed, uint32_t forms, void *stream,
                           gf_forest **out);
@@ -126,6 +128,10 @@ gf_status gf_export_tree(const gf_forest *F, int32_t *D, int32_t *split_dim,
  * BF16 scores of 128-query blocks against all points on MFMA and keeps only
  * those of each query's candidates.  The environment variable GF_SCAN_PATH
  * (= rows | tile) overrides the choice where the tile path is available.
+ * Rows wider than 4,096 FP32 (8,192 BF16) elements are streamed against a
+ * copy of the query in LDS where it fits beside the visited bitmap;
+ * GF_SCAN_WIDE_QUERY=global reads it from device memory instead (same
+ * results; for testing).
  *   Q                 [nq][d] float32, host-or-device, finite.  Host rows are
  *                     copied through a pinned host buffer that the forest
  *                     keeps and grows to its largest batch (at most 16,384
