@@ -96,17 +96,18 @@ struct Chunk<kFormFP8> {
         acc = dot4(q.z, x.z, acc);
         return dot4(q.w, x.w, acc);
     }
-    // x (16 codes) against the decoded query held in LDS
-    __device__ static float score_lds(const float* q, const uint4& x) {
+    // x (16 codes of chunk ci) against the decoded query held in LDS as four
+    // planes: plane i holds values 4i .. 4i+3 of every chunk, so lanes
+    // reading consecutive chunks read consecutive 16-byte words
+    __device__ static float score_lds(const float4* qp, int64_t ci, int64_t nch, const uint4& x) {
         typedef float f2 __attribute__((ext_vector_type(2)));
         const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-        const float4* q4 = reinterpret_cast<const float4*>(q);
         float acc = 0.0f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const f2 lo = __builtin_amdgcn_cvt_pk_f32_fp8(w[i], false);
             const f2 hi = __builtin_amdgcn_cvt_pk_f32_fp8(w[i], true);
-            const float4 qq = q4[i];
+            const float4 qq = qp[i * nch + ci];
             acc = fmaf(lo.x, qq.x, acc);
             acc = fmaf(lo.y, qq.y, acc);
             acc = fmaf(hi.x, qq.z, acc);
@@ -190,7 +191,9 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
             const uint32_t wv = q8w[i];
             const f2 lo = __builtin_amdgcn_cvt_pk_f32_fp8(wv, false);
             const f2 hi = __builtin_amdgcn_cvt_pk_f32_fp8(wv, true);
-            q8f[4 * i] = lo.x; q8f[4 * i + 1] = lo.y; q8f[4 * i + 2] = hi.x; q8f[4 * i + 3] = hi.y;
+            // word i = values 4i .. 4i+3 = plane i % 4 of chunk i / 4
+            reinterpret_cast<float4*>(q8f)[(i & 3) * (a.ld8 / 16) + (i >> 2)] =
+                make_float4(lo.x, lo.y, hi.x, hi.y);
         }
         __syncthreads();
         qv[0] = T{};
@@ -209,6 +212,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
         }
     }
     const T* Qsrc = kQStage ? reinterpret_cast<const T*>(q8f) : Qrow;
+    const float4* q8p = reinterpret_cast<const float4*>(q8f);   // FP8: the planes of the decoded query
     float qn = 0.0f, qs = 0.0f;
     if (FORM != kFormFP32) qn = a.qnorm[q];
     if (FORM == kFormFP8) qs = a.qscale8[q];
@@ -267,10 +271,10 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
                             const T x0 = xr[ci], x1 = xr[ci + LPR], x2 = xr[ci + 2 * LPR],
                                     x3 = xr[ci + 3 * LPR];
                             if constexpr (FORM == kFormFP8) {
-                                a0 += C::score_lds(q8f + ci * 16, x0);
-                                a1 += C::score_lds(q8f + (ci + LPR) * 16, x1);
-                                a2 += C::score_lds(q8f + (ci + 2 * LPR) * 16, x2);
-                                a3 += C::score_lds(q8f + (ci + 3 * LPR) * 16, x3);
+                                a0 += C::score_lds(q8p, ci, nchunks_row, x0);
+                                a1 += C::score_lds(q8p, ci + LPR, nchunks_row, x1);
+                                a2 += C::score_lds(q8p, ci + 2 * LPR, nchunks_row, x2);
+                                a3 += C::score_lds(q8p, ci + 3 * LPR, nchunks_row, x3);
                             } else {
                                 a0 += C::score(Qsrc[ci], x0);
                                 a1 += C::score(Qsrc[ci + LPR], x1);
@@ -279,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
                             }
                         }
                         for (; ci < nchunks_row; ci += LPR) {
-                            if constexpr (FORM == kFormFP8) a0 += C::score_lds(q8f + ci * 16, xr[ci]);
+                            if constexpr (FORM == kFormFP8) a0 += C::score_lds(q8p, ci, nchunks_row, xr[ci]);
                             else a0 += C::score(Qsrc[ci], xr[ci]);
                         }
                         acc = (a0 + a1) + (a2 + a3);
@@ -289,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
                     for (int j = 0; j < CPL; ++j) {
                         if constexpr (FORM == kFormFP8) {
                             const int64_t ci = sub + int64_t(j) * LPR;
-                            if (ci < nchunks_row) acc += C::score_lds(q8f + ci * 16, xv[u][j]);
+                            if (ci < nchunks_row) acc += C::score_lds(q8p, ci, nchunks_row, xv[u][j]);
                         } else {
                             acc += C::score(qv[QREG > 1 ? j : 0], xv[u][j]);
                         }
