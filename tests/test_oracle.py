@@ -467,3 +467,53 @@ def test_householder_forest_differs_and_exhaustive_budget_is_exact_knn():
     ri = oracle.search(Fi, X, Q, 10, 4)
     rp = oracle.search(Fp, X, Q, 10, 4)
     assert not np.array_equal(ri["opened"], rp["opened"])
+
+
+# ------------------------------------------------ sharding the trees (design)
+# Across GPUs the trees would be split into groups.  Each group ranks its own
+# leaves by the static key (eff, tree, entry) and keeps its B smallest; the B
+# smallest of the union are the opened set, because every key of the global
+# B smallest is among its own group's B smallest.  Each group then takes the
+# best k of its own candidates, and merging those lists with duplicates
+# removed (a point can be a candidate in several groups, with the same
+# distance) gives the global best k.
+
+
+@pytest.mark.parametrize("groups", [2, 3, 5])
+def test_tree_sharding_merge_equals_global_selection(groups):
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((3000, 12)).astype(np.float32)
+    Q = (X[rng.integers(0, 3000, 8)] + 0.1 * rng.standard_normal((8, 12))).astype(np.float32)
+    m, c, k = 6, 40, 5
+    F = oracle.build_forest(X, m, 5, 8, 23)
+    r = oracle.search(F, X, Q, k, c, candidates=True)
+    B = r["B"]
+    lo = F["leaf_off"].astype(np.int64)
+    for i in range(len(Q)):
+        # every leaf in (eff, tree, entry) order; a leaf's position in this
+        # list stands for its full key
+        codes, _ = static_leaf_order(F, Q[i])
+        trees = np.array([cd >> 24 for cd in codes])
+        shard_of_tree = np.arange(m) % groups
+        merged, local_best = [], []
+        for g in range(groups):
+            mine = [j for j in range(len(codes)) if shard_of_tree[trees[j]] == g][:B]
+            merged += mine                                   # this group's B smallest keys
+        opened = [codes[j] for j in sorted(merged)[:B]]
+        assert opened == r["opened"][i].tolist()
+        # per group: candidates of its own opened leaves, best k, then merge
+        for g in range(groups):
+            ids = set()
+            for code in opened:
+                if shard_of_tree[code >> 24] == g:
+                    leaf = code & 0xFFFFFF
+                    ids.update(F["perm"][code >> 24][lo[leaf]:lo[leaf + 1]].tolist())
+            ids = np.array(sorted(ids), dtype=np.int64)
+            if ids.size:
+                diff = X[ids].astype(np.float64) - Q[i].astype(np.float64)
+                dd = np.einsum("ij,ij->i", diff, diff)
+                order = np.lexsort((ids, dd))[:k]
+                local_best += list(zip(dd[order].tolist(), ids[order].tolist()))
+        best = sorted(set(local_best))[:k]                   # duplicates are identical pairs
+        assert [b[1] for b in best] == r["ids"][i][:len(best)].tolist()
+        assert np.allclose([b[0] for b in best], r["dists"][i][:len(best)], rtol=1e-12, atol=0)
