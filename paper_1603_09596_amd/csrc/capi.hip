@@ -363,10 +363,14 @@ gf_status launch_selection(const gf_forest* F, const QueryJob& J, int nb, const 
                            int64_t W, const int32_t* cpq, bool early_exit, hipStream_t st) {
     const gf::SelectArgs sa = make_select_args(F, nb, w, W);
     if (F->U) {
-        // isometry variant: each tree's reflected query coordinates on D
-        hipLaunchKernelGGL(gf::k_reflect_queries, dim3((nb + 127) / 128, unsigned(F->host.m)),
-                           dim3(128), 0, st, static_cast<const float*>(w.Qp), int64_t(F->ld32), nb,
-                           F->host.d, F->host.m, F->host.t, static_cast<const int32_t*>(F->D),
+        // isometry variant: each tree's reflected query coordinates on D,
+        // the trees of a query on neighbouring lanes
+        int mp = 1;
+        while (mp < F->host.m) mp <<= 1;                 // m <= 255, so mp <= 256
+        const int qpb = 256 / mp;
+        hipLaunchKernelGGL(gf::k_reflect_queries, dim3((nb + qpb - 1) / qpb), dim3(256), 0, st,
+                           static_cast<const float*>(w.Qp), int64_t(F->ld32), nb, F->host.d,
+                           F->host.m, mp, F->host.t, static_cast<const int32_t*>(F->D),
                            static_cast<const double*>(F->U), w.qt);
         GF_HIP(hipGetLastError());
     }
@@ -1047,8 +1051,12 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         GF_HIP_B(hipMemcpy(F->drange, rng.data(), size_t(t) * sizeof(float2), hipMemcpyHostToDevice));
     }
     if (!h.U.empty()) {
-        GF_HIP_B(hipMalloc(&F->U, h.U.size() * sizeof(double)));
-        GF_HIP_B(hipMemcpy(F->U, h.U.data(), h.U.size() * sizeof(double), hipMemcpyHostToDevice));
+        // device copy transposed to [d][m]: the trees of one query read one row
+        std::vector<double> ut(h.U.size());
+        for (int32_t tr = 0; tr < m; ++tr)
+            for (int32_t j = 0; j < d; ++j) ut[size_t(j) * m + tr] = h.U[size_t(tr) * d + j];
+        GF_HIP_B(hipMalloc(&F->U, ut.size() * sizeof(double)));
+        GF_HIP_B(hipMemcpy(F->U, ut.data(), ut.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     if (forms & GF_KEEP_BF16) {
         // leaf of every point in every tree, point-major (tile path)

@@ -72,7 +72,7 @@ struct gf_forest {
     uint32_t* leafof = nullptr;     // [n][m] tree * 2^H + leaf of each point (BF16 form)
     int32_t* D = nullptr;           // [t]
     float2* drange = nullptr;       // [t] smallest and largest split value per slot of D
-    double* U = nullptr;            // [m][d] reflectors (isometry variant), or null
+    double* U = nullptr;            // [d][m] reflectors, transposed (isometry variant), or null
     // Grow-only scratch for queries.  Calls on one forest are serialised by
     // this mutex (concurrent queries on one forest wait for each other).
     std::mutex ws_mutex;

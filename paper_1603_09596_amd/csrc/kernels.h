@@ -56,9 +56,11 @@ struct SelectArgs {
 };
 
 // Isometry variant: qt[i][q][j] = float32(q_s - (2 u_i.q) u_i[s]) for s = D[j],
-// with u_i.q summed in FP64 in index order (the build's definition).
-__global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, int m, int t,
-                                  const int32_t* D, const double* U, float* qt);
+// with u_i.q summed in FP64 in index order (the build's definition).  UT is
+// [d][m] (u_i[j] at UT[j m + i]); blocks of blockDim.x threads serve
+// blockDim.x / mp queries, mp >= m a power of two dividing blockDim.x.
+__global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, int m, int mp, int t,
+                                  const int32_t* D, const double* UT, float* qt);
 
 __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps);
 // flags[0]: set when some query goes on to a radix pass; flags[1]: how many

@@ -453,25 +453,26 @@ __device__ __forceinline__ void pick_bin(const uint32_t* hist, uint32_t cur, int
 }  // namespace
 
 // Isometry variant (Sec. 2.1 "Rotation", Sec. 2.2): one thread per (query,
-// tree) forms u.q in FP64 in index order, each product rounded before it is
-// added (no fused multiply-add, the same sums as the build), then each
-// coordinate on D of the reflected query, rounded once to float32.
-__global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, int m, int t,
-                                  const int32_t* D, const double* U, float* qt) {
+// tree), mp >= m lanes per query side by side, forms u.q in FP64 in index order,
+// each product rounded before it is added (no fused multiply-add, the same
+// sums as the build), then each coordinate on D of the reflected query,
+// rounded once to float32.  UT is [d][m], so the lanes of one query read one
+// row of it and one value of the query at each step.
+__global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, int m, int mp, int t,
+                                  const int32_t* D, const double* UT, float* qt) {
 #pragma clang fp contract(off)
-    const int q = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
-    const int tree = int(blockIdx.y);
+    const int tree = int(threadIdx.x) % mp;
+    const int q = int(blockIdx.x) * (int(blockDim.x) / mp) + int(threadIdx.x) / mp;
     if (q >= nq || tree >= m) return;
     const float* x = Q + int64_t(q) * ldq;
-    const double* u = U + int64_t(tree) * d;
     double acc = 0.0;
     for (int j = 0; j < d; ++j) {
-        const double prod = u[j] * double(x[j]);
+        const double prod = UT[int64_t(j) * m + tree] * double(x[j]);
         acc = acc + prod;
     }
     for (int j = 0; j < t; ++j) {
         const int s = D[j];
-        const double r = (2.0 * acc) * u[s];
+        const double r = (2.0 * acc) * UT[int64_t(s) * m + tree];
         qt[(int64_t(tree) * nq + q) * t + j] = float(double(x[s]) - r);
     }
 }
