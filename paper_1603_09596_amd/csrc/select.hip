@@ -433,20 +433,43 @@ __device__ uint32_t entry_node(const SelectArgs& a, const float* qd, uint32_t tr
     return en;
 }
 
-// Block-wide step of a radix select over 256 bins: with hist[] complete,
-// thread 0 finds the bin holding the `left`-th smallest and publishes the
-// extended prefix, the rank left inside that bin and the bin's size.
+// Block-wide step of a radix select over 2^w <= 256 bins (256 threads, all
+// calling): with hist[] complete, the bin holding the `left`-th smallest is
+// the first whose inclusive prefix count reaches `left`.  The block finds it
+// with a prefix sum over the bins (one bin per thread) and publishes the
+// extended prefix, the rank left inside that bin and the bin's size in
+// out[0..2]; the caller synchronises before reading them.  left = 0 gives
+// bin 0, and a total below `left` the last bin with the total subtracted,
+// as a bin-by-bin search would.  wsum: 4 words of LDS.
 __device__ __forceinline__ void pick_bin(const uint32_t* hist, uint32_t cur, int w, uint32_t left,
-                                         uint32_t* out) {
-    if (threadIdx.x == 0) {
-        uint32_t d = (1u << w) - 1u;
-        for (uint32_t b = 0; b < (1u << w); ++b) {
-            if (hist[b] >= left) { d = b; break; }
-            left -= hist[b];
-        }
-        out[0] = (cur << w) | d;
-        out[1] = left;
-        out[2] = hist[d];
+                                         uint32_t* out, uint32_t* wsum) {
+    const int nb = 1 << w;
+    const int t = int(threadIdx.x), lane = t & (kWave - 1), wv = t / kWave;
+    const uint32_t v = t < nb ? hist[t] : 0u;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t ws = wsum[k];
+        if (k < wv) base += ws;
+        total += ws;
+    }
+    incl += base;
+    const uint32_t excl = incl - v;
+    if (left == 0u) {
+        if (t == 0) { out[0] = cur << w; out[1] = 0u; out[2] = hist[0]; }
+    } else if (total < left) {
+        if (t == 0) { out[0] = (cur << w) | uint32_t(nb - 1); out[1] = left - total; out[2] = hist[nb - 1]; }
+    } else if (t < nb && excl < left && incl >= left) {
+        out[0] = (cur << w) | uint32_t(t);
+        out[1] = left - excl;
+        out[2] = v;
     }
 }
 
@@ -618,6 +641,7 @@ __global__ __launch_bounds__(kBins) void k_select_pick(SelectArgs a, int phase, 
 __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
     __shared__ uint32_t hist[256];
     __shared__ uint32_t pub[3];
+    __shared__ uint32_t wsum[4];
     __shared__ float qd[kMaxT];
     __shared__ uint64_t sh_prefix;
     __shared__ uint32_t sh_need;
@@ -651,14 +675,11 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
                         atomicAdd(&hist[(K >> shift) & 255u], 1u);
                 }
                 __syncthreads();
+                pick_bin(hist, 0u, 8, sh_need, pub, wsum);
+                __syncthreads();
                 if (threadIdx.x == 0) {
-                    uint32_t left = sh_need, d = 255;
-                    for (uint32_t b = 0; b < 256; ++b) {
-                        if (hist[b] >= left) { d = b; break; }
-                        left -= hist[b];
-                    }
-                    sh_need = left;
-                    sh_prefix = (prefix << 8) | d;
+                    sh_need = pub[1];
+                    sh_prefix = (prefix << 8) | pub[0];
                 }
                 __syncthreads();
             }
@@ -695,7 +716,7 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
                 if ((E >> r) == cur) atomicAdd(&hist[(E >> sh) & ((1u << w) - 1u)], 1u);
             }
             __syncthreads();
-            pick_bin(hist, cur, w, left, pub);
+            pick_bin(hist, cur, w, left, pub, wsum);
             __syncthreads();
             cur = pub[0];
             left = pub[1];
@@ -736,7 +757,7 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
                 if (r == 32 || (tk >> r) == tcur) atomicAdd(&hist[(tk >> sh) & 255u], 1u);
             }
             __syncthreads();
-            pick_bin(hist, tcur, 8, left, pub);
+            pick_bin(hist, tcur, 8, left, pub, wsum);
             __syncthreads();
             tcur = pub[0];
             left = pub[1];
