@@ -638,6 +638,8 @@ __global__ __launch_bounds__(kBins) void k_select_pick(SelectArgs a, int phase, 
 //   taken, their (tree, entry) keys are recomputed and a second radix select
 //   over those orders the ties.
 //   full-key bins: a radix select over the 64-bit keys.
+constexpr int kFinishUnroll = 4;
+
 __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
     __shared__ uint32_t hist[256];
     __shared__ uint32_t pub[3];
@@ -697,9 +699,22 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
         const uint32_t tree = code >> 24, leaf = code & 0xFFFFFFu;
         atomicAnd(&a.leafbits[(int64_t(tree) * a.W + (leaf >> 5)) * a.nq + q], ~(1u << (leaf & 31u)));
     };
+    // the passes over the collected keys take kFinishUnroll keys per thread at
+    // a time, their loads issued before any is used
+    const uint32_t bstep = blockDim.x;
     if (need >= cnt) {
         if (!pre)
-            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) mark(codes[i]);
+            for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += kFinishUnroll * bstep) {
+                uint32_t cv[kFinishUnroll];
+#pragma unroll
+                for (int u = 0; u < kFinishUnroll; ++u) {
+                    const uint32_t i = i0 + u * bstep;
+                    cv[u] = i < cnt ? codes[i] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < kFinishUnroll; ++u)
+                    if (i0 + u * bstep < cnt) mark(cv[u]);
+            }
         return;
     }
     uint32_t* tks = reinterpret_cast<uint32_t*>(a.ckey + int64_t(q) * kCollectCap) + kCollectCap;
@@ -711,9 +726,17 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
             const int w = r < 8 ? r : 8, sh = r - w;
             hist[threadIdx.x] = 0;
             __syncthreads();
-            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-                const uint32_t E = keys[i];
-                if ((E >> r) == cur) atomicAdd(&hist[(E >> sh) & ((1u << w) - 1u)], 1u);
+            for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += kFinishUnroll * bstep) {
+                uint32_t ev[kFinishUnroll];
+#pragma unroll
+                for (int u = 0; u < kFinishUnroll; ++u) {
+                    const uint32_t i = i0 + u * bstep;
+                    ev[u] = i < cnt ? keys[i] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < kFinishUnroll; ++u)
+                    if (i0 + u * bstep < cnt && (ev[u] >> r) == cur)
+                        atomicAdd(&hist[(ev[u] >> sh) & ((1u << w) - 1u)], 1u);
             }
             __syncthreads();
             pick_bin(hist, cur, w, left, pub, wsum);
@@ -725,10 +748,21 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
         }
         const uint32_t estar = cur;
         if (left == ties) {
-            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-                const bool take = keys[i] <= estar;
-                if (pre && !take) clear(codes[i]);
-                if (!pre && take) mark(codes[i]);
+            for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += kFinishUnroll * bstep) {
+                uint32_t ev[kFinishUnroll], cv[kFinishUnroll];
+#pragma unroll
+                for (int u = 0; u < kFinishUnroll; ++u) {
+                    const uint32_t i = i0 + u * bstep;
+                    ev[u] = i < cnt ? keys[i] : 0u;
+                    cv[u] = i < cnt ? codes[i] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < kFinishUnroll; ++u) {
+                    if (i0 + u * bstep >= cnt) continue;
+                    const bool take = ev[u] <= estar;
+                    if (pre && !take) clear(cv[u]);
+                    if (!pre && take) mark(cv[u]);
+                }
             }
             return;
         }
