@@ -6,7 +6,7 @@ with the GPU library.  ``oracle.c`` holds the method (Alg. 1-3, Sec. 2.3);
 this module compiles it with gcc and marshals numpy arrays through ctypes.
 ``bruteforce.py`` holds the exact k-NN definition used to pin it.
 
-Parity status of each function (what pins it is in tests/test_oracle_*.py):
+Parity status of each function (what pins it is in tests/test_oracle.py):
   splitmix64 / draw     pinned: published splitmix64 outputs for state 0
   variance / top dims   pinned: numpy.var(ddof=1), hand-made columns
   build                 pinned: partition / median / leaf-size invariants,
@@ -14,8 +14,9 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   search (eff key)      pinned: static leaf ranking (every leaf's key by an
                         independent traversal), the 1-D closed form for
                         m = t = 1, nesting in c, exhaustive budget = brute force
-  search (literal key)  diagnostic only; parity unpinned beyond sharing the
-                        same exhaustive-budget and home-leaf behaviour
+  search (literal key)  diagnostic only; pinned by the hand-worked 2-D
+                        example (pop order, keys and best 3 for c = 1..4),
+                        the exhaustive budget and home-leaf behaviour
   householder / build and search with the isometry
                         pinned: u unit and deterministic; u = e_0 (a
                         reflection that negates one coordinate) gives the
