@@ -1,6 +1,7 @@
 """Shapes at the edges of the library's limits against the oracle: one
 dimension, one point, one tree with t = d, the maximum of 255 trees, and the
-maximum k = 64 (FP32, and BF16 with a re-rank depth of 64).  Tree arrays,
+maximum k = 64 (FP32, and BF16 with a re-rank depth of 64), and a call of
+more queries than one batch holds, on both paths.  Tree arrays,
 opened leaves and candidate sets bit-exact; neighbours by the acceptance
 rule (FP32) or exact distances and recall (BF16)."""
 import numpy as np
@@ -96,3 +97,53 @@ def test_k64_bf16_rerank_64():
         assert hits / ref["ids"].size >= 0.95
     finally:
         Fg.free()
+
+
+@pytest.mark.parametrize("form,path", [("fp32", "rows"), ("bf16", "tile")])
+def test_more_queries_than_one_batch(form, path, monkeypatch):
+    """16,684 queries, more than the 16,384 one batch holds: the call runs
+    two batches, and with host buffers the pinned staging buffer is refilled
+    for the second.  Host and device buffers must give identical results,
+    every query the result of a call over a small group holding it, and the
+    queries on both sides of the batch boundary must match the oracle."""
+    rng = np.random.default_rng(31)
+    n, d, nq = 6000, 48, 16384 + 300
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Q = (X[rng.integers(0, n, nq)] + 0.1 * rng.standard_normal((nq, d))).astype(np.float32)
+    m, t, p, k, c, seed = 4, 5, 8, 5, 60, 17
+    monkeypatch.setenv("GF_SCAN_PATH", path)
+    Fg = geraf.build_forest(X, m, t, p, seed, forms=("bf16",) if form == "bf16" else ())
+    try:
+        ids_h = np.zeros((nq, k), np.int32)
+        dd_h = np.zeros((nq, k), np.float32)
+        geraf.query(Fg, Q, k, c, ids_h, dd_h, form=form)
+        timing = geraf.last_query_timing()
+        assert timing["path"] == path and timing["batches"] == 2
+        ids = torch.zeros((nq, k), dtype=torch.int32, device="cuda:0")
+        dd = torch.zeros((nq, k), dtype=torch.float32, device="cuda:0")
+        geraf.query(Fg, torch.from_numpy(Q).to("cuda:0"), k, c, ids, dd, form=form)
+        assert np.array_equal(ids.cpu().numpy(), ids_h)
+        assert np.array_equal(dd.cpu().numpy(), dd_h)
+        for lo in (0, 16384 - 150, nq - 300):
+            sub_i = np.zeros((300, k), np.int32)
+            sub_d = np.zeros((300, k), np.float32)
+            geraf.query(Fg, np.ascontiguousarray(Q[lo:lo + 300]), k, c, sub_i, sub_d, form=form)
+            assert np.array_equal(sub_i, ids_h[lo:lo + 300]), lo
+            assert np.array_equal(sub_d, dd_h[lo:lo + 300]), lo
+    finally:
+        Fg.free()
+    idx = np.r_[0:4, 16380:16388, nq - 4:nq]
+    Qs = np.ascontiguousarray(Q[idx])
+    ref = oracle.search(oracle.build_forest(X, m, t, p, seed), X, Qs, k, c, trace=False)
+    if form == "fp32":
+        check_knn(ids_h[idx], dd_h[idx], ref["ids"], ref["dists"], X=X, Q=Qs)
+        return
+    hits = 0
+    for j, i in enumerate(idx):
+        got = ids_h[i][ids_h[i] >= 0]
+        for r, gid in enumerate(got.tolist()):
+            diff = X[gid].astype(np.float64) - Qs[j].astype(np.float64)
+            true_d = float(diff @ diff)
+            assert abs(dd_h[i][r] - true_d) <= 1e-5 * true_d
+        hits += len(set(got.tolist()) & set(ref["ids"][j].tolist()))
+    assert hits / ref["ids"].size >= 0.95

@@ -4,7 +4,7 @@ the oracle.
 Each job of a multi call must give exactly what gf_query gives for the same
 arguments on the same path (the same kernels run, launched from one graph),
 in graph mode and eagerly, on the first call and when a cached graph is
-reused.  An FP32 job is also checked against the FP64 oracle by the
+reused, also over several replays with eager calls between them.  An FP32 job is also checked against the FP64 oracle by the
 acceptance rule, and the autotuned choice must reproduce one of the two
 single-call paths.
 """
@@ -108,6 +108,35 @@ def test_multi_graph_reuse(indexes):
     for j, f in zip(jobs, first):
         assert np.array_equal(j["ids"].cpu().numpy(), f[0])
         assert np.array_equal(j["dists"].cpu().numpy(), f[1])
+
+
+def test_multi_graph_replays_match_eager(indexes):
+    """Four launches of one cached graph, with eager single-index calls and
+    host synchronisations between them: every replay must reproduce the
+    eager results exactly (replays after the first start from the
+    workspace contents the previous call and the eager work left)."""
+    ref = [single(e) for e in indexes]
+    jobs = jobs_of(indexes)
+    geraf.query_multi(jobs)
+    torch.cuda.synchronize()
+    before = geraf.multi_stats()
+    for rep in range(4):
+        for j in jobs:
+            j["ids"].fill_(-3 - rep)
+            j["dists"].fill_(-3.0 - rep)
+        geraf.query_multi(jobs)
+        torch.cuda.synchronize()
+        for e, j, r in zip(indexes, jobs, ref):
+            assert np.array_equal(j["ids"].cpu().numpy(), r[0]), (rep, e["w"].name)
+            assert np.array_equal(j["dists"].cpu().numpy(), r[1]), (rep, e["w"].name)
+        # the program's own eager work between replays, on the same forests
+        e = indexes[rep % len(indexes)]
+        got = single(e)
+        r = ref[rep % len(indexes)]
+        assert np.array_equal(got[0], r[0]) and np.array_equal(got[1], r[1])
+    after = geraf.multi_stats()
+    assert after["graphs_reused"] == before["graphs_reused"] + 4
+    assert after["graphs_built"] == before["graphs_built"]
 
 
 def test_multi_fp32_job_against_oracle(indexes):
