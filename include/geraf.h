@@ -21,6 +21,10 @@
  *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
  *     Query entry points enqueue their kernels on it and return once the
  *     results are in the caller's buffers (they synchronise the stream).
+ *   - Host threads may call concurrently.  Calls on one forest share its
+ *     workspace and wait for each other (a lock per forest); calls on
+ *     different forests run side by side.  gf_free_forest must not overlap
+ *     a call on the same forest.
  *   - Pointers marked host-or-device may point to either; the library checks
  *     with hipPointerGetAttributes and stages host buffers itself.
  *   - Distances are SQUARED Euclidean distances.  Result rows are sorted by
