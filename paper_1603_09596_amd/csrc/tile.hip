@@ -449,9 +449,13 @@ constexpr int kExpandRepeat = 8;
 
 // Opened leaves, query-major words -> per-leaf rows of query bits.  One
 // workgroup of 32 cw threads per (leaf word f, query chunk): thread i reads
-// query (chunk 32 cw + i)'s word f (32 leaves); each wave turns its 64
-// queries x 32 leaves into 32 leaves x 2 words with ballots; the 32 rows of
-// cw words are written whole.
+// query (chunk 32 cw + i)'s word f (32 leaves); each half-wave transposes its
+// 32 queries x 32 leaves bit matrix, so that lane x (or 32 + x) holds leaf
+// x's word of the wave's low (or high) 32 queries; the 32 rows of cw words
+// are written whole.  The transpose is five butterfly stages: at width j the
+// lanes l and l ^ j swap the off-diagonal j x j blocks of each 2j x 2j block
+// (the lane with bit j clear keeps its low halves and takes the partner's
+// low halves into its high ones, the other the reverse).
 __global__ __launch_bounds__(1024) void k_open_transpose(ExpandArgs a) {
     __shared__ uint32_t tile[32 * 32];
     const int64_t f = blockIdx.x;
@@ -461,12 +465,14 @@ __global__ __launch_bounds__(1024) void k_open_transpose(ExpandArgs a) {
     const int q = chunk * 32 * a.cw + int(threadIdx.x);
     const uint32_t bits = q < a.nq ? a.leafbits[f * a.nq + q] : 0u;
     if (f == 0 && q < a.nq) a.gthr[q] = 0xFF800000u;   // shared bound +inf
-    uint32_t mine = 0;
+    constexpr uint32_t kLow[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+    uint32_t mine = bits;
 #pragma unroll
-    for (int x = 0; x < 32; ++x) {
-        const uint64_t bal = __ballot((bits >> x) & 1u);
-        if (lane == x) mine = uint32_t(bal);
-        if (lane == 32 + x) mine = uint32_t(bal >> 32);
+    for (int s = 0; s < 5; ++s) {
+        const int j = 16 >> s;
+        const uint32_t lo = kLow[s];
+        const uint32_t y = uint32_t(__shfl_xor(int(mine), j));
+        mine = (lane & j) ? ((mine & ~lo) | ((y & ~lo) >> j)) : ((mine & lo) | ((y & lo) << j));
     }
     tile[(lane & 31) * a.cw + 2 * wave + (lane >> 5)] = mine;
     __syncthreads();
