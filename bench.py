@@ -237,6 +237,20 @@ def cpu_baseline(w, idx_all, checks, seconds, threads, householder=False):
                        f"thread; forest build excluded"), sample, ref
 
 
+def hbm_probe(torch, geraf, dev, gib=4, reps=5):
+    """Streaming read bandwidth of this machine, beside the 8 TB/s peak: the
+    library's read probe (gf_hbm_probe: 16-byte non-temporal loads over
+    contiguous 64 KB spans, sixteen in flight per thread, nothing written)
+    over a `gib` GiB device buffer, `reps` timed launches after a warm-up."""
+    buf = torch.empty(gib << 30, dtype=torch.uint8, device=dev)
+    rate = geraf.hbm_probe(buf, reps)
+    torch.cuda.synchronize()
+    del buf
+    torch.cuda.empty_cache()
+    return {"read_GB_s": round(rate, 1), "frac_of_peak": round(rate / HBM_PEAK_GBS, 4),
+            "gib": gib, "kernel": "k_read_probe"}
+
+
 def vs_oracle(X, Q, ids, dists, ref):
     """The GPU answers of the oracle's sample against the oracle: recall of
     the oracle's k (its FP64 top-k at the same budget) and the relative error
@@ -325,6 +339,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the streaming-bandwidth probe reported beside the rooflines")
     ap.add_argument("--householder", action="store_true",
                     help="build the forest with the per-tree Householder isometry variant")
     ap.add_argument("--sweep", choices=sorted(SWEEPS),
@@ -450,6 +466,10 @@ def main():
     else:
         roofline = scan_roofline(form, ph["scan_or_expand_ms"])
 
+    probe = None if args.no_probe else hbm_probe(torch, geraf, dev)
+    if probe:
+        log(f"[bench] streaming read probe: {probe['read_GB_s']} GB/s")
+
     cpu, oracle_cmp = None, None
     if not args.no_cpu_baseline:
         cpu, sample, ref = cpu_baseline(w, idx, c, args.cpu_seconds, host_threads(), args.householder)
@@ -487,6 +507,7 @@ def main():
         "phases_ms": {key: round(v, 2) for key, v in ph.items() if key != "path"},
         "fp32_form": fp32,
         "roofline": roofline,
+        "hbm_probe": probe,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

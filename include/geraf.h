@@ -222,6 +222,17 @@ gf_status gf_query_trace(const gf_forest *F, const float *Q, int64_t nq, int32_t
 gf_status gf_fp8_tables(float *hw_decode, float *def_decode, const float *enc_in,
                         int32_t n_enc, uint8_t *enc_out);
 
+/* Measurement utility (not part of the method): the device's streaming
+ * read bandwidth, the practical ceiling beside the 8 TB/s peak that the
+ * row-gather rooflines are priced against.  One warm-up and then `reps`
+ * launches of a kernel that reads the `bytes` (rounded down to 16) of `buf`
+ * in 16-byte words, contiguous 64 KB spans per workgroup with sixteen
+ * non-temporal loads in flight per thread, and writes nothing to it; *read_gb_s = bytes read / time between HIP events on `stream`, in
+ * GB/s.  buf: device memory, 16-byte aligned, caller-owned, contents
+ * unchanged.  GF_EINVAL for a host or misaligned buf, bytes < 16, reps < 1. */
+gf_status gf_hbm_probe(const void *buf, int64_t bytes, int32_t reps, double *read_gb_s,
+                       void *stream);
+
 /* Device time of the phases of the last successful gf_query or
  * gf_query_trace on the calling thread, in milliseconds, from HIP events
  * recorded on the query's stream, summed over its batches (a call is split

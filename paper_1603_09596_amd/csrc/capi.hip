@@ -914,6 +914,39 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
     return GF_OK;
 }
 
+// Streaming read of n16 16-byte words, nothing written: what the memory
+// system delivers to a plain read stream on this device, the ceiling beside
+// the rooflines' 8 TB/s.  Workgroups take contiguous spans of 16 x 256
+// words (64 KB) in turn, each thread with its sixteen non-temporal loads in
+// flight; the block that owns the last, partial span reads it word by word.  The XOR of the
+// data keeps the loads; the sink (external, so it cannot be proven unread)
+// is written only if it hits a constant.
+constexpr int kProbeUnroll = 16;
+}  // namespace
+__device__ uint32_t gf_probe_sink;
+namespace {
+__global__ __launch_bounds__(256) void k_read_probe(const uint4* __restrict__ p, int64_t n16) {
+    const int64_t span = int64_t(blockDim.x) * kProbeUnroll;
+    const int64_t step = int64_t(gridDim.x) * span;
+    int64_t base = int64_t(blockIdx.x) * span;
+    uint32_t acc = 0;
+    typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+    const v4u32* q = reinterpret_cast<const v4u32*>(p);
+    for (; base + span <= n16; base += step) {
+        v4u32 v[kProbeUnroll];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u)
+            v[u] = __builtin_nontemporal_load(q + base + u * int64_t(blockDim.x) + threadIdx.x);
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+    for (int64_t i = base + threadIdx.x; i < n16; i += blockDim.x) {
+        const uint4 a = p[i];
+        acc ^= a.x ^ a.y ^ a.z ^ a.w;
+    }
+    if (acc == 0x9E3779B9u) gf_probe_sink = acc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1164,6 +1197,34 @@ gf_status gf_query_trace(const gf_forest* Fc, const float* Q, int64_t nq, int32_
     const void* any = leaf_bits ? (const void*)leaf_bits : cand_bits ? (const void*)cand_bits : (const void*)ncand;
     J.trace_dev = any && is_device_ptr(any);
     return run_query(F, J, static_cast<hipStream_t>(stream));
+}
+
+gf_status gf_hbm_probe(const void* buf, int64_t bytes, int32_t reps, double* read_gb_s,
+                       void* stream) {
+    if (!buf || bytes < 16 || reps < 1 || !read_gb_s)
+        return fail(GF_EINVAL, "buf, bytes >= 16, reps >= 1 and read_gb_s are required");
+    if (reinterpret_cast<uintptr_t>(buf) % 16 != 0) return fail(GF_EINVAL, "buf must be 16-byte aligned");
+    if (!is_device_ptr(buf)) return fail(GF_EINVAL, "buf must be device memory");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n16 = bytes / 16;
+    const dim3 grid(2048), block(256);
+    hipEvent_t ev[2];
+    GF_HIP(hipEventCreate(&ev[0]));
+    struct EvGuard { hipEvent_t* e; int n; ~EvGuard() { for (int i = 0; i < n; ++i) (void)hipEventDestroy(e[i]); } } evg{ev, 1};
+    GF_HIP(hipEventCreate(&ev[1]));
+    evg.n = 2;
+    const uint4* p = static_cast<const uint4*>(buf);
+    hipLaunchKernelGGL(k_read_probe, grid, block, 0, st, p, n16);   // warm-up
+    GF_HIP(hipGetLastError());
+    GF_HIP(hipEventRecord(ev[0], st));
+    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_read_probe, grid, block, 0, st, p, n16);
+    GF_HIP(hipGetLastError());
+    GF_HIP(hipEventRecord(ev[1], st));
+    GF_HIP(hipEventSynchronize(ev[1]));
+    float ms = 0.0f;
+    GF_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    *read_gb_s = double(reps) * double(n16) * 16.0 / (double(ms) / 1e3) / 1e9;
+    return GF_OK;
 }
 
 gf_status gf_fp8_tables(float* hw_decode, float* def_decode, const float* enc_in, int32_t n_enc,

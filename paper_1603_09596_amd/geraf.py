@@ -24,7 +24,7 @@ VARIANT_HOUSEHOLDER = 1 << 0
 FORMS = {"fp32": FORM_FP32, "bf16": FORM_BF16, "fp8": FORM_FP8}
 
 EXPORTED = ["gf_build_forest", "gf_build_forest_ex", "gf_free_forest", "gf_forest_info", "gf_export_tree", "gf_query",
-            "gf_query_multi", "gf_multi_stats", "gf_query_trace", "gf_fp8_tables",
+            "gf_query_multi", "gf_multi_stats", "gf_query_trace", "gf_fp8_tables", "gf_hbm_probe",
             "gf_last_query_timing", "gf_last_error", "gf_version"]
 MULTI_AUTOTUNE, MULTI_EAGER = 1, 2
 
@@ -68,6 +68,7 @@ def load():
     lib.gf_query_multi.argtypes = [ctypes.POINTER(Job), i32, u32, P]
     lib.gf_multi_stats.argtypes = [P, P, P]
     lib.gf_fp8_tables.argtypes = [P, P, P, i32, P]
+    lib.gf_hbm_probe.argtypes = [P, i64, i32, P, P]
     lib.gf_last_query_timing.argtypes = [P, i32, P, P]
     lib.gf_last_error.restype = ctypes.c_char_p
     lib.gf_version.restype = ctypes.c_char_p
@@ -241,3 +242,12 @@ def fp8_tables(enc_in: Optional[np.ndarray] = None):
     _check(load().gf_fp8_tables(_ptr(hw), _ptr(sw), _ptr(enc_in) if enc_in.size else None,
                                 enc_in.size, _ptr(out) if enc_in.size else None))
     return hw, sw, out
+
+
+def hbm_probe(buf, reps: int = 5, stream=None) -> float:
+    """gf_hbm_probe: streaming read GB/s over the bytes of device tensor `buf`."""
+    out = ctypes.c_double(0.0)
+    st = stream if stream is not None else _stream_of(buf)
+    nbytes = buf.numel() * buf.element_size() if _is_torch(buf) else buf.nbytes
+    _check(load().gf_hbm_probe(_ptr(buf), nbytes, reps, ctypes.byref(out), st))
+    return out.value
