@@ -26,7 +26,9 @@ roofline and baseline objects; the FP32 form is timed beside the FP8 one.
 `--sweep eps|p` measures accuracy and time against the approximation factor
 eps or the points per leaf p on noisy-sphere stand-ins shaped like the
 paper's synthetic Sphere sets (k = 1): miss %, eps-failure %, build and
-search time per setting, in one line with a row per setting.
+search time per setting, in one line with a row per setting.  `--sweep c`
+gives the recall-against-budget curve of the headline recipe (recall@10,
+1-recall@10, candidates per query and queries/s per c).
 
 `--multi` measures the multi-index launch instead and prints its own line:
 the multi-20 recipe (20 indexes of uneven n and d, per-query budgets,
@@ -118,6 +120,8 @@ def nn_quality(d_true, d_got, eps, tie=1e-12):
 SWEEPS = {
     "eps": dict(cases=[(1000, 10000), (100000, 100)], eps=(0.0, 0.1, 0.5, 0.9), p=(16,)),
     "p": dict(cases=[(10000, 100)], eps=(0.0,), p=(256, 128, 64, 32, 16, 4, 2, 1)),
+    # recall against the budget on the headline recipe: the curve that fixes its c
+    "c": dict(budgets=(4096, 8192, 16384, 32768, 65536, 98304, 106496, 114688, 131072)),
 }
 SWEEP_M, SWEEP_T, SWEEP_NQ, SWEEP_SEED, SWEEP_SIGMA = 8, 5, 1000, 5, 0.1
 
@@ -176,6 +180,58 @@ def sweep_bench(args, torch, geraf, workloads, dev):
         "data": "synthetic",
         "config": {"workload": f"noisy-sphere {args.sweep} sweep", "m": m, "t": t, "k": 1,
                    "nq": nq, "sigma": SWEEP_SIGMA, "seed": seed, "form": "fp32"},
+        "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def c_sweep_bench(args, torch, geraf, workloads, dev):
+    """recall@10, 1-recall@10, candidates per query and queries/s against the
+    budget c on the headline recipe (desc-1m-960, BF16 form with FP32
+    re-rank of 4k): the curve from which the headline c is the smallest
+    budget on the grid reaching recall@10 >= 0.90."""
+    from oracle import bruteforce as bf
+    w = workloads.make(WORKLOAD, nq=args.nq)
+    F = geraf.build_forest(w.X, w.m, w.t, w.p, w.seed, forms=("bf16",))
+    Q = torch.from_numpy(w.Q).to(dev)
+    nq, k = len(w.Q), w.k
+    idx = np.linspace(0, nq - 1, min(args.recall_sample, nq)).astype(np.int64)
+    gt, _ = bf.knn_ground_truth(w.X, w.Q[idx], k)
+    Qs = torch.from_numpy(np.ascontiguousarray(w.Q[idx])).to(dev)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    nc = torch.empty(len(idx), dtype=torch.int64, device=dev)
+    rows = []
+    for c in SWEEPS["c"]["budgets"]:
+        geraf.query(F, Q, k, c, ids, dists, form="bf16")
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            geraf.query(F, Q, k, c, ids, dists, form="bf16")
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        path = geraf.last_query_timing()["path"]
+        ms = 1e3 * float(np.median(times))
+        got = ids.cpu().numpy()[idx]
+        geraf.query_trace(F, Qs, c, ncand=nc)
+        torch.cuda.synchronize()
+        one = float(np.mean([gt[i, 0] in set(got[i].tolist()) for i in range(len(idx))]))
+        rows.append(dict(checks=c, **{f"recall@{k}": round(recall_at(got, gt), 4),
+                                     f"1-recall@{k}": round(one, 4)},
+                         mean_candidates=round(float(nc.float().mean().item()), 1),
+                         path=path, ms=round(ms, 2), queries_per_s=round(nq / (ms / 1e3), 1)))
+        log(f"[bench] c sweep {rows[-1]}")
+    F.free()
+    head = next(r for r in rows if r["checks"] == CHECKS_AT_090)
+    out = {
+        "metric": f"recall@{k} and queries/s against the budget c, {WORKLOAD}, BF16 form",
+        "value": head["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": head["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD} c sweep", "nq": nq, "k": k, "form": "bf16",
+                   "recall_sample": len(idx)},
         "rows": rows,
     }
     print(json.dumps(out), flush=True)
@@ -344,7 +400,8 @@ def main():
     ap.add_argument("--householder", action="store_true",
                     help="build the forest with the per-tree Householder isometry variant")
     ap.add_argument("--sweep", choices=sorted(SWEEPS),
-                    help="accuracy/time sweep over eps or points per leaf (noisy-sphere)")
+                    help="accuracy/time sweep over eps or points per leaf (noisy-sphere), "
+                         "or recall against the budget c on desc-1m-960")
     ap.add_argument("--multi", action="store_true",
                     help="measure the multi-index launch (multi-20 recipe) instead")
     ap.add_argument("--multi-scale", type=float, default=0.25,
@@ -368,6 +425,8 @@ def main():
     geraf.load()
     if args.multi:
         return multi_bench(args, torch, geraf, workloads, dev)
+    if args.sweep == "c":
+        return c_sweep_bench(args, torch, geraf, workloads, dev)
     if args.sweep:
         return sweep_bench(args, torch, geraf, workloads, dev)
     name = args.workload

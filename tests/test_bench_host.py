@@ -59,6 +59,9 @@ def test_sweep_settings_cover_the_paper_tables():
     # the four eps values and the eight points-per-leaf values of the tables
     assert bench.SWEEPS["eps"]["eps"] == (0.0, 0.1, 0.5, 0.9)
     assert bench.SWEEPS["p"]["p"] == (256, 128, 64, 32, 16, 4, 2, 1)
+    # the budget grid starts at the smallest c of the protocol and holds the headline c
+    b = bench.SWEEPS["c"]["budgets"]
+    assert b[0] == 4096 and bench.CHECKS_AT_090 in b and list(b) == sorted(set(b))
 
 
 def test_pmc_traffic_reads_the_record_of_the_named_kernel():
