@@ -429,6 +429,7 @@ gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& 
     ea.nq = nb; ea.m = h.m; ea.W = int(W); ea.H = h.H; ea.n = h.n;
     ea.cw = tp.cw; ea.nchunk = tp.nchunk;
     ea.leafbits = w.leafbits; ea.leafof = F->leafof; ea.openT = w.openT; ea.visT = w.visT;
+    ea.order = F->perm;   // tree 0's row of perm: every point once, leaf by leaf
     ea.gthr = w.gthr;
     gf::TileArgs ta{};
     ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.cw = tp.cw; ta.Q16 = w.Q16; ta.X16 = F->X16;

@@ -122,6 +122,7 @@ struct ExpandArgs {
     int cw, nchunk;
     const uint32_t* leafbits;   // [m][W][nq] opened leaves, query fastest
     const uint32_t* leafof;     // [n][m] tree * 2^H + leaf holding each point
+    const uint32_t* order;      // [n] point ids in tree 0's leaf order (the expansion's order)
     uint32_t* openT;            // [nchunk][m 2^H][cw] queries that opened each leaf
     uint32_t* visT;             // [nchunk][n][cw] queries having each point as candidate
     uint32_t* gthr;             // [nq] set to the bits of +inf here

@@ -486,7 +486,9 @@ __global__ __launch_bounds__(1024) void k_open_transpose(ExpandArgs a) {
 
 // Point-major candidate sets: row x of chunk c is the OR over the trees of
 // the rows of the leaves holding x.  Thread (x, w) of a 256-thread group
-// covers 256 / cw points at a time, kExpandRepeat times.
+// covers 256 / cw points at a time, kExpandRepeat times.  Points are taken
+// in tree 0's leaf order, so the points of one tree-0 leaf run together and
+// that tree's row is read from memory once and then from L2.
 __global__ __launch_bounds__(256) void k_expand_points(ExpandArgs a) {
     const int per = 256 / a.cw;
     const int w = int(threadIdx.x) % a.cw;
@@ -494,8 +496,9 @@ __global__ __launch_bounds__(256) void k_expand_points(ExpandArgs a) {
     const int64_t rows = int64_t(a.m) << a.H;
     const uint32_t* op = a.openT + int64_t(chunk) * rows * a.cw + w;
     for (int rep = 0; rep < kExpandRepeat; ++rep) {
-        const int64_t x = (int64_t(blockIdx.x) * kExpandRepeat + rep) * per + threadIdx.x / a.cw;
-        if (x >= a.n) return;
+        const int64_t i = (int64_t(blockIdx.x) * kExpandRepeat + rep) * per + threadIdx.x / a.cw;
+        if (i >= a.n) return;
+        const int64_t x = a.order[i];
         const uint32_t* lf = a.leafof + x * a.m;
         // eight trees at a time: the leaf indices, then the rows, all in flight
         uint32_t v = 0;
