@@ -446,10 +446,13 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
 // Point groups each workgroup of the expansion handles in turn (fewer,
 // longer-lived workgroups than one per group).
 constexpr int kExpandRepeat = 8;
+// Leaf words each workgroup of the transpose handles (one LDS tile each).
+constexpr int kTransposeWords = 4;
 
 // Opened leaves, query-major words -> per-leaf rows of query bits.  One
-// workgroup of 32 cw threads per (leaf word f, query chunk): thread i reads
-// query (chunk 32 cw + i)'s word f (32 leaves); each half-wave transposes its
+// workgroup of 32 cw threads per (kTransposeWords leaf words from f0, query
+// chunk): thread i reads query (chunk 32 cw + i)'s words f0.. (32 leaves
+// each), all loads in flight; each half-wave transposes its
 // 32 queries x 32 leaves bit matrix, so that lane x (or 32 + x) holds leaf
 // x's word of the wave's low (or high) 32 queries; the 32 rows of cw words
 // are written whole.  The transpose is five butterfly stages: at width j the
@@ -457,31 +460,42 @@ constexpr int kExpandRepeat = 8;
 // (the lane with bit j clear keeps its low halves and takes the partner's
 // low halves into its high ones, the other the reverse).
 __global__ __launch_bounds__(1024) void k_open_transpose(ExpandArgs a) {
-    __shared__ uint32_t tile[32 * 32];
-    const int64_t f = blockIdx.x;
+    __shared__ uint32_t tile[kTransposeWords][32 * 32];
+    const int64_t words = int64_t(a.m) * a.W;
+    const int64_t f0 = int64_t(blockIdx.x) * kTransposeWords;
     const int chunk = blockIdx.y;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int q = chunk * 32 * a.cw + int(threadIdx.x);
-    const uint32_t bits = q < a.nq ? a.leafbits[f * a.nq + q] : 0u;
-    if (f == 0 && q < a.nq) a.gthr[q] = 0xFF800000u;   // shared bound +inf
-    constexpr uint32_t kLow[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
-    uint32_t mine = bits;
+    uint32_t bits[kTransposeWords];
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
-        const int j = 16 >> s;
-        const uint32_t lo = kLow[s];
-        const uint32_t y = uint32_t(__shfl_xor(int(mine), j));
-        mine = (lane & j) ? ((mine & ~lo) | ((y & ~lo) >> j)) : ((mine & lo) | ((y & lo) << j));
+    for (int u = 0; u < kTransposeWords; ++u)
+        bits[u] = (q < a.nq && f0 + u < words) ? a.leafbits[(f0 + u) * a.nq + q] : 0u;
+    if (f0 == 0 && q < a.nq) a.gthr[q] = 0xFF800000u;   // shared bound +inf
+    constexpr uint32_t kLow[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+    for (int u = 0; u < kTransposeWords; ++u) {
+        uint32_t mine = bits[u];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            const int j = 16 >> s;
+            const uint32_t lo = kLow[s];
+            const uint32_t y = uint32_t(__shfl_xor(int(mine), j));
+            mine = (lane & j) ? ((mine & ~lo) | ((y & ~lo) >> j)) : ((mine & lo) | ((y & lo) << j));
+        }
+        tile[u][(lane & 31) * a.cw + 2 * wave + (lane >> 5)] = mine;
     }
-    tile[(lane & 31) * a.cw + 2 * wave + (lane >> 5)] = mine;
     __syncthreads();
     const int leaf = int(threadIdx.x) / a.cw, word = int(threadIdx.x) % a.cw;
     const int64_t nleaf = int64_t{1} << a.H;
-    const int64_t tree = f / a.W;
-    const int64_t lt = (f % a.W) * 32 + leaf;
-    if (lt < nleaf)
-        a.openT[((int64_t(chunk) * a.m + tree) * nleaf + lt) * a.cw + word] = tile[leaf * a.cw + word];
+#pragma unroll
+    for (int u = 0; u < kTransposeWords; ++u) {
+        const int64_t f = f0 + u;
+        const int64_t tree = f / a.W;
+        const int64_t lt = (f % a.W) * 32 + leaf;
+        if (f < words && lt < nleaf)
+            a.openT[((int64_t(chunk) * a.m + tree) * nleaf + lt) * a.cw + word] = tile[u][leaf * a.cw + word];
+    }
 }
 
 // Point-major candidate sets: row x of chunk c is the OR over the trees of
@@ -583,8 +597,9 @@ hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeA
     const int64_t words = int64_t(e.m) * e.W;
     if (e.cw < 4 || e.cw > 32 || (e.cw & (e.cw - 1)) || t.cw != e.cw) return hipErrorInvalidValue;
     if (t.split_pts % kTP || t.split_pts * t.ld16 * 2 >= (int64_t{1} << 31)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_open_transpose, dim3(unsigned(words), unsigned(e.nchunk)), dim3(32 * e.cw),
-                       0, st, e);
+    hipLaunchKernelGGL(k_open_transpose, dim3(unsigned((words + kTransposeWords - 1) / kTransposeWords),
+                                              unsigned(e.nchunk)),
+                       dim3(32 * e.cw), 0, st, e);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int per = 256 / e.cw;
