@@ -29,6 +29,7 @@
 //                    FP32 compensated re-rank and FP64 tie re-check.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -621,7 +622,10 @@ hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeA
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_merge_rerank, dim3(m.nq), dim3(512), 0, st, m);
+    // threads: enough to rank every list entry at once (up to kMergeMax), in whole waves
+    const int64_t tot = int64_t(m.nsplit) * kTileList;
+    const unsigned mthreads = unsigned(std::min<int64_t>(kMergeMax, std::max<int64_t>(256, (tot + kWave - 1) / kWave * kWave)));
+    hipLaunchKernelGGL(k_merge_rerank, dim3(m.nq), dim3(mthreads), 0, st, m);
     return hipGetLastError();
 }
 
