@@ -11,12 +11,18 @@ Parity status of each function (what pins it is in tests/test_oracle.py):
   variance / top dims   pinned: numpy.var(ddof=1), hand-made columns
   build                 pinned: partition / median / leaf-size invariants,
                         the closed form for t = 1 (contiguous rank blocks)
-  search (eff key)      pinned: static leaf ranking (every leaf's key by an
-                        independent traversal), the 1-D closed form for
-                        m = t = 1, nesting in c, exhaustive budget = brute force
-  search (literal key)  diagnostic only; pinned by the hand-worked 2-D
-                        example (pop order, keys and best 3 for c = 1..4),
-                        the exhaustive budget and home-leaf behaviour
+  build, near-tie guard pinned: duplicated and nearly equal columns at the
+                        rank-t boundary are refused, separated ones pass
+  search (Alg. 2 key,   pinned: the pop ORDER equals the sort of every leaf's
+   the reference)       static key (the strictly decreasing suffix maxima of
+                        the gaps on its root path, by an independent
+                        traversal in the test); hand-worked examples (a far
+                        gap below its entry's key, an exactly zero gap, the
+                        2-D and 1-D cases); the 1-D closed form for m = t = 1;
+                        nesting in c; exhaustive budget = brute force
+  search (eff key)      diagnostic variant only (key = max along the chain):
+                        pinned by its own static ranking; it differs from the
+                        Alg. 2 key inside groups of equal eff
   householder / build and search with the isometry
                         pinned: u unit and deterministic; u = e_0 (a
                         reflection that negates one coordinate) gives the
@@ -66,6 +72,8 @@ def _load():
     lib.orc_variance.restype = ctypes.c_int
     lib.orc_top_dims.argtypes = [P, i32, i32, P]
     lib.orc_top_dims.restype = ctypes.c_int
+    lib.orc_dims_ambiguous.argtypes = [P, i64, i32, i32, P]
+    lib.orc_dims_ambiguous.restype = ctypes.c_int
     lib.orc_depth.argtypes = [i64, i32]
     lib.orc_depth.restype = i32
     lib.orc_budget.argtypes = [i64, f64, i64]
@@ -111,6 +119,18 @@ def top_dims(V: np.ndarray, t: int) -> np.ndarray:
     return D
 
 
+def dims_ambiguous(X: np.ndarray, t: int) -> bool:
+    """Whether the t-th and (t+1)-th largest variances of X are too close
+    for the top-t set to be defined (see orc_dims_ambiguous)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    V = variance(X)
+    return bool(_load().orc_dims_ambiguous(_ptr(X), X.shape[0], X.shape[1], t, _ptr(V)))
+
+
+class NearTieError(ValueError):
+    """The build refused data whose top-t variance set is not determined."""
+
+
 def depth(n: int, p: int) -> int:
     return int(_load().orc_depth(n, p))
 
@@ -152,6 +172,9 @@ def build_forest(X: np.ndarray, m: int, t: int, p: int, seed: int, nthreads: int
         nthreads = os.cpu_count() or 1
     st = _load().orc_build(_ptr(X), n, d, m, t, p, seed & 0xFFFFFFFFFFFFFFFF, nthreads, _ptr(D),
                            _ptr(split_dim), _ptr(split_val), _ptr(perm), _ptr(leaf_off), _ptr(U))
+    if st == -3:
+        raise NearTieError("near-tie in D: the t-th and (t+1)-th largest variances are "
+                           "within rounding of each other")
     if st != 0:
         raise ValueError(f"orc_build failed: {st}")
     return dict(n=n, d=d, m=m, t=t, p=p, seed=seed, H=H, D=D,
@@ -160,11 +183,13 @@ def build_forest(X: np.ndarray, m: int, t: int, p: int, seed: int, nthreads: int
 
 
 def search(forest: dict, X: np.ndarray, Q: np.ndarray, k: int, c: int, eps: float = 0.0,
-           literal: bool = False, nthreads: int = 0, trace: bool = True,
+           eff_key: bool = False, nthreads: int = 0, trace: bool = True,
            candidates: bool = False) -> dict:
     """Alg. 2 for every row of Q.  Returns ids [nq,k], dists [nq,k] (FP64,
     squared), and with trace=True the opened (tree<<24|leaf) codes and keys in
-    pop order; with candidates=True the checked point ids per query."""
+    pop order; with candidates=True the checked point ids per query.  The
+    queue key is Alg. 2's |gap|; eff_key=True selects the diagnostic variant
+    whose key is the maximum gap along the chain."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     Q = np.ascontiguousarray(Q, dtype=np.float32)
     n, d = X.shape
@@ -190,7 +215,7 @@ def search(forest: dict, X: np.ndarray, Q: np.ndarray, k: int, c: int, eps: floa
     st = _load().orc_search(_ptr(X), n, d, m, H, _ptr(sd), _ptr(sv),
                             _ptr(np.ascontiguousarray(forest["perm"])),
                             _ptr(np.ascontiguousarray(forest["leaf_off"])),
-                            _ptr(Q), nq, k, c, float(eps), int(bool(literal)), nthreads,
+                            _ptr(Q), nq, k, c, float(eps), int(bool(eff_key)), nthreads,
                             _ptr(ids), _ptr(dists), _ptr(opened), _ptr(okey), _ptr(ncand),
                             _ptr(cand), cap, _ptr(forest.get("u")))
     if st != 0:
@@ -209,5 +234,6 @@ def leaf_code(tree, leaf):
     return (np.asarray(tree, dtype=np.uint32) << np.uint32(24)) | np.asarray(leaf, dtype=np.uint32)
 
 
-__all__ = ["build", "splitmix64", "draw", "variance", "top_dims", "depth", "budget",
+__all__ = ["build", "splitmix64", "draw", "variance", "top_dims", "dims_ambiguous",
+           "NearTieError", "depth", "budget",
            "householder", "build_forest", "search", "leaf_code"]

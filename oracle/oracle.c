@@ -44,6 +44,7 @@
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
 #define ORC_ENOMEM (-2)
+#define ORC_ENEARTIE (-3)   /* D is not determined by the data (see orc_dims_ambiguous) */
 
 /* ------------------------------------------------------------------------ */
 /* RNG: splitmix64 output function; stream ids: 1 split dim, 2 tie key.      */
@@ -115,6 +116,47 @@ int orc_top_dims(const double *V, int32_t d, int32_t t, int32_t *D)
         if (taken[j]) D[w++] = j;
     free(taken);
     return ORC_OK;
+}
+
+/* Whether D is ill-determined.  The variance is defined exactly but any
+ * FP64 evaluation of it is rounded (this file sums two passes; Alg. 3 uses
+ * Knuth's online update), and the rounding error scales with the column's
+ * mean square, V + mean^2.  When the t-th and (t+1)-th largest variances
+ * differ by no more than 1e-12 of the larger mean square of the two columns,
+ * two correct evaluations may rank them differently, so the top-t set is
+ * not a property of the data: the build refuses such input rather than pick
+ * one side silently.  Columns of mean square 0 (all zero) and n < 2 (V = 0
+ * by definition) are exact and never ambiguous.  Returns 1 if ambiguous. */
+int orc_dims_ambiguous(const float *X, int64_t n, int32_t d, int32_t t, const double *V)
+{
+    if (!X || !V || t < 1 || t > d) return 0;
+    if (n < 2 || t == d) return 0;
+    /* the t-th and (t+1)-th largest variances, ties to the lower index */
+    unsigned char *taken = (unsigned char *)calloc((size_t)d, 1);
+    if (!taken) return 0;
+    int32_t rank_t = -1, rank_t1 = -1;
+    for (int32_t r = 0; r <= t; ++r) {
+        int32_t best = -1;
+        for (int32_t j = 0; j < d; ++j) {
+            if (taken[j]) continue;
+            if (best < 0 || V[j] > V[best]) best = j;
+        }
+        taken[best] = 1;
+        if (r == t - 1) rank_t = best;
+        if (r == t) rank_t1 = best;
+    }
+    free(taken);
+    double ms[2] = {0.0, 0.0};
+    int32_t cols[2] = {rank_t, rank_t1};
+    for (int c = 0; c < 2; ++c) {
+        double sum = 0.0;
+        for (int64_t i = 0; i < n; ++i) sum += (double)X[i * d + cols[c]];
+        double mean = sum / (double)n;
+        ms[c] = V[cols[c]] + mean * mean;
+    }
+    double scale = ms[0] > ms[1] ? ms[0] : ms[1];
+    if (!(scale > 0.0)) return 0;
+    return (V[rank_t] - V[rank_t1]) <= 1e-12 * scale;
 }
 
 /* Perfect-tree depth: the smallest H with ceil(n / 2^H) <= p.  A node of s
@@ -305,6 +347,7 @@ int orc_build(const float *X, int64_t n, int32_t d, int32_t m, int32_t t,
     double *V = (double *)malloc((size_t)d * sizeof(double));
     if (!V) return ORC_ENOMEM;
     int st = orc_variance(X, n, d, V);
+    if (st == ORC_OK && orc_dims_ambiguous(X, n, d, t, V)) st = ORC_ENEARTIE;
     if (st == ORC_OK) st = orc_top_dims(V, d, t, D);
     free(V);
     if (st != ORC_OK) return st;
@@ -420,7 +463,7 @@ typedef struct {
     const int32_t *split_dim; const float *split_val;
     const uint32_t *perm; const uint32_t *leaf_off;
     /* queries */
-    const float *Q; int64_t nq; int32_t k; int64_t B; int32_t literal;
+    const float *Q; int64_t nq; int32_t k; int64_t B; int32_t eff_key;
     /* outputs */
     int32_t *ids; double *dists;
     uint32_t *opened; double *opened_key;
@@ -439,9 +482,11 @@ typedef struct {
  *   - every tree's root enters the queue with key 0, so the first m pops
  *     descend each tree once and check its home leaf ("all visited nodes
  *     are stored in Q"); every checked leaf counts against the budget;
- *   - the key of a pushed child is max(key of the entry being descended,
- *     |gap|) (the default "eff" key); with literal != 0 it is |gap| alone,
- *     exactly as printed in Alg. 2 (diagnostic mode);
+ *   - the key of a pushed child is |gap| at the node where it was left
+ *     behind (Alg. 2 inserts the far child with the absolute signed
+ *     distance of Eq. 1; Sec. 2.3).  With eff_key != 0 it is instead
+ *     max(key of the entry being descended, |gap|), a variant kept only as
+ *     a diagnostic: it opens the same leaves except where keys tie;
  *   - gap < 0 descends left and stores the right child; gap >= 0 (including
  *     a zero gap) descends right and stores the left child;
  *   - distances are squared Euclidean, summed in FP64;
@@ -476,7 +521,7 @@ static int search_one(const orc_search_job *J, int64_t qi, unsigned char *visite
             else         { near_child = 2 * v + 2; far_child = 2 * v + 1; }
             double ag = fabs(g);
             orc_entry child;
-            child.key = J->literal ? ag : (ag > e.key ? ag : e.key);
+            child.key = J->eff_key ? (ag > e.key ? ag : e.key) : ag;
             child.tree = e.tree;
             child.node = (int32_t)far_child;
             if (heap_push(heap, child) != ORC_OK) return ORC_ENOMEM;
@@ -558,7 +603,7 @@ int orc_search(const float *X, int64_t n, int32_t d, int32_t m, int32_t H,
                const int32_t *split_dim, const float *split_val,
                const uint32_t *perm, const uint32_t *leaf_off,
                const float *Q, int64_t nq, int32_t k, int64_t c, double eps,
-               int32_t literal, int32_t nthreads,
+               int32_t eff_key, int32_t nthreads,
                int32_t *ids, double *dists, uint32_t *opened, double *opened_key,
                int64_t *ncand, uint32_t *cand, int64_t cand_cap, const double *U)
 {
@@ -574,7 +619,7 @@ int orc_search(const float *X, int64_t n, int32_t d, int32_t m, int32_t H,
     int st = ORC_OK;
     for (int32_t w = 0; w < nthreads; ++w) {
         orc_search_job J = {X, n, d, m, H, split_dim, split_val, perm, leaf_off,
-                            Q, nq, k, B, literal, ids, dists, opened, opened_key,
+                            Q, nq, k, B, eff_key, ids, dists, opened, opened_key,
                             ncand, cand, cand_cap, w, nthreads, ORC_OK, U};
         jobs[w] = J;
         pthread_create(&th[w], NULL, search_worker, &jobs[w]);

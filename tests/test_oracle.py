@@ -77,6 +77,48 @@ def test_top_dims_ties_go_to_lower_index_and_sorted():
 
 # ------------------------------------------------------------------ depth
 
+def _near_tie_data(kind):
+    rng = np.random.default_rng(44)
+    X = rng.standard_normal((500, 6)).astype(np.float32)
+    X[:, 0] *= 3.0
+    X[:, 1] *= 2.0                                  # ranks 1 and 2 well separated
+    if kind == "duplicate":
+        X[:, 3] = X[:, 2] * np.float32(1.5)
+        X[:, 2] = X[:, 3]                           # ranks 3 and 4 equal exactly
+    elif kind == "permuted":
+        X[:, 2] *= 1.5
+        X[:, 3] = X[::-1, 2]                        # same values, other order: equal up to rounding
+    elif kind == "one-ulp":
+        X[:, 2] *= 1.5
+        X[:, 3] = X[:, 2]
+        X[7, 3] = np.nextafter(X[7, 3], np.float32(np.inf))   # ~3e-11 relative: resolvable
+    elif kind == "zero-columns":
+        X[:, 3:] = 0.0                              # ranks 4.. all exactly 0
+    return X
+
+
+@pytest.mark.parametrize("kind,t,ambiguous", [("duplicate", 3, True), ("permuted", 3, True),
+                                              ("one-ulp", 3, False), ("duplicate", 2, False),
+                                              ("duplicate", 4, False), ("zero-columns", 4, False),
+                                              ("separated", 3, False)])
+def test_build_refuses_a_near_tie_at_rank_t(kind, t, ambiguous):
+    X = _near_tie_data(kind)
+    assert oracle.dims_ambiguous(X, t) == ambiguous
+    if ambiguous:
+        with pytest.raises(oracle.NearTieError):
+            oracle.build_forest(X, 2, t, 8, 1)
+    else:
+        F = oracle.build_forest(X, 2, t, 8, 1)
+        V = np.var(X.astype(np.float64), axis=0, ddof=1)
+        assert set(F["D"].tolist()) == set(np.argsort(-V, kind="stable")[:t].tolist())
+
+
+def test_build_near_tie_guard_exempts_single_point():
+    X = np.zeros((1, 5), np.float32)
+    F = oracle.build_forest(X, 2, 2, 1, 3)            # V = 0 by definition: D = {0, 1}
+    assert F["D"].tolist() == [0, 1]
+
+
 @pytest.mark.parametrize("n,p,H", [(10_000, 8, 11), (100_000, 16, 13), (1_000_000, 32, 15),
                                    (200_000, 16, 14), (5, 5, 0), (5, 9, 0), (6, 5, 1),
                                    (1, 1, 0), (2, 1, 1), (9, 2, 3), (8, 2, 2), (17, 4, 3)])
@@ -196,65 +238,196 @@ def test_build_hand_worked_example():
 
 # ------------------------------------------------------------------ search
 
-def search_hand_example(literal):
+def _inf(v):
+    return math.inf if v == "inf" else float(v)
+
+
+def search_hand_example(eff_key):
     g = json.load(open(os.path.join(GOLD, "tiny_2d.json")))
     X = np.array(g["X"], dtype=np.float32)
     q = np.array([g["q"]], dtype=np.float32)
     F = oracle.build_forest(X, g["m"], g["t"], g["p"], g["seed"])
     for c in range(1, 5):
-        r = oracle.search(F, X, q, 3, c, literal=literal)
+        r = oracle.search(F, X, q, 3, c, eff_key=eff_key)
         assert (r["opened"][0] & 0xFFFFFF).tolist() == g["pops"]["leaves"][:c]
         assert r["opened_key"][0].tolist() == g["pops"]["keys"][:c]
         exp = g["k3_by_c"][str(c)]
         assert r["ids"][0].tolist() == exp["ids"]
-        assert r["dists"][0].tolist() == [float(x) for x in exp["dists"]]
+        assert r["dists"][0].tolist() == [_inf(x) for x in exp["dists"]]
 
 
 def test_search_hand_worked_example():
     search_hand_example(False)
 
 
-def test_search_hand_worked_example_literal_key():
+def test_search_hand_worked_example_max_key_variant():
+    # one split dimension: the gaps grow along every chain, so the diagnostic
+    # max-key variant pops the same sequence
     search_hand_example(True)
 
 
-def static_leaf_order(F, q):
-    """Every leaf's (eff, tree, entry) by an independent top-down traversal:
-    the near child inherits the parent's eff and entry, the far child gets
-    max(eff, |gap|) and becomes its own entry (gap = float32 q_s - v).
-    Returns the leaf codes sorted by that key, and the keys."""
+def _golden_forest(name):
+    g = json.load(open(os.path.join(GOLD, name)))
+    X = np.array(g["X"], dtype=np.float32)
+    q = np.array([g["q"]], dtype=np.float32)
+    F = oracle.build_forest(X, g["m"], g["t"], g["p"], g["seed"])
+    tr = g["tree"]
+    assert F["H"] == tr["H"] and F["D"].tolist() == tr["D"]
+    for i in range(g["m"]):
+        assert F["split_dim"][i].tolist() == tr["split_dim"]
+        assert F["split_val"][i].tolist() == tr["split_val"]
+        assert F["perm"][i].tolist() == tr["perm"]
+    assert F["leaf_off"].tolist() == tr["leaf_off"]
+    return g, X, q, F
+
+
+def test_search_far_gap_below_its_entry_key():
+    """Alg. 2 keys a left-behind child by its own |gap|, which can be below the
+    key of the entry whose descent pushed it; the max-key variant would pop
+    another leaf third and return another best 3 at c = 3."""
+    g, X, q, F = _golden_forest("gap_below_entry_2d.json")
+    B = len(g["pops"]["leaves"])
+    r = oracle.search(F, X, q, 3, B)
+    assert (r["opened"][0] & 0xFFFFFF).tolist() == g["pops"]["leaves"]
+    assert r["opened_key"][0].tolist() == g["pops"]["keys"]
+    for c, exp in g["k3_by_c"].items():
+        r = oracle.search(F, X, q, 3, int(c))
+        assert r["ids"][0].tolist() == exp["ids"], c
+        assert r["dists"][0].tolist() == [_inf(x) for x in exp["dists"]], c
+    v = oracle.search(F, X, q, 3, B, eff_key=True)
+    assert (v["opened"][0] & 0xFFFFFF).tolist() == g["pops_max_key_variant"]["leaves"]
+    assert v["opened_key"][0].tolist() == g["pops_max_key_variant"]["keys"]
+    v3 = oracle.search(F, X, q, 3, 3, eff_key=True)
+    assert v3["ids"][0].tolist() == g["k3_c3_max_key_variant"]["ids"]
+
+
+def test_search_zero_gap_descends_right_and_ties_go_to_lower_tree():
+    g, X, q, F = _golden_forest("zero_gap_two_trees.json")
+    B = len(g["pops"]["leaves"])
+    r = oracle.search(F, X, q, 2, B, candidates=True)
+    assert (r["opened"][0] >> 24).tolist() == g["pops"]["trees"]
+    assert (r["opened"][0] & 0xFFFFFF).tolist() == g["pops"]["leaves"]
+    assert r["opened_key"][0].tolist() == g["pops"]["keys"]
+    for c, exp in g["k2_by_c"].items():
+        rc = oracle.search(F, X, q, 2, int(c))
+        assert rc["ids"][0].tolist() == exp["ids"], c
+        assert rc["dists"][0].tolist() == exp["dists"], c
+    for c, nc in g["ncand_by_c"].items():
+        rc = oracle.search(F, X, q, 1, int(c), candidates=True)
+        assert int(rc["ncand"][0]) == nc, c
+
+
+def _leaf_chains(F, q):
+    """Every leaf's chain of (|gap|, tree, entry node) from an independent
+    top-down traversal: the root contributes (0, tree, 0); each node where
+    the leaf lies on the far side contributes (|q_s - v| as float32, tree,
+    far child).  Yields (tree, leaf, chain)."""
     H, m = F["H"], F["m"]
     nint = (1 << H) - 1
-    items = []
     for tr in range(m):
-        stack = [(0, np.float32(0), 0)]
+        stack = [(0, [(0.0, tr, 0)])]
         while stack:
-            v, eff, entry = stack.pop()
+            v, chain = stack.pop()
             if v >= nint:
-                items.append((float(eff), tr, entry, (tr << 24) | (v - nint)))
+                yield tr, v - nint, chain
                 continue
             s = F["split_dim"][tr, v]
             g = np.float32(q[s]) - np.float32(F["split_val"][tr, v])
             near, far = (2 * v + 1, 2 * v + 2) if g < 0 else (2 * v + 2, 2 * v + 1)
-            stack.append((near, eff, entry))
-            stack.append((far, max(eff, np.float32(abs(g))), far))
+            stack.append((near, chain))
+            stack.append((far, chain + [(float(abs(g)), tr, far)]))
+
+
+def static_leaf_order_gap(F, q):
+    """Static characterisation of Alg. 2's pop order.  A leaf's key is the
+    subsequence of its chain made of the entries strictly larger than every
+    entry after them (the strictly decreasing suffix maxima), compared
+    lexicographically by (|gap|, tree, node), a prefix first.  Reason: pops
+    come in non-decreasing order of the chain maximum; among equal maxima,
+    the entries at that value head groups that the queue empties one after
+    the other, in (tree, node) order (a child head has a larger node index);
+    inside a group the same argument applies to the chain below its head.
+    Returns the leaf codes in that order and each one's last chain key (the
+    key it is popped with)."""
+    items = []
+    for tr, leaf, chain in _leaf_chains(F, q):
+        seq, best = [], -1.0
+        for e in reversed(chain):
+            if e[0] > best:
+                seq.append(e)
+                best = e[0]
+        seq.reverse()
+        items.append((seq, (tr << 24) | leaf, chain[-1][0]))
+    items.sort(key=lambda it: it[0])
+    return [it[1] for it in items], [it[2] for it in items]
+
+
+def static_leaf_order_eff(F, q):
+    """The diagnostic max-key variant: every leaf's (eff, tree, entry), eff
+    the largest |gap| on its chain, entry its deepest far child."""
+    items = []
+    for tr, leaf, chain in _leaf_chains(F, q):
+        eff = max(e[0] for e in chain)
+        items.append((eff, tr, chain[-1][2], (tr << 24) | leaf))
     items.sort()
     return [it[3] for it in items], [it[0] for it in items]
 
 
-@pytest.mark.parametrize("n,d,m,t,p,c,seed", [(2000, 24, 4, 5, 8, 100, 0),
-                                              (1000, 16, 3, 2, 3, 333, 1),
-                                              (333, 8, 5, 8, 2, 50, 2)])
-def test_search_pop_order_equals_static_leaf_ranking(n, d, m, t, p, c, seed):
+SEARCH_CASES = [(2000, 24, 4, 5, 8, 100, 0, "gauss"),
+                (1000, 16, 3, 2, 3, 333, 1, "gauss"),
+                (333, 8, 5, 8, 2, 50, 2, "gauss"),
+                (1500, 12, 3, 4, 4, 120, 3, "quantised"),
+                (2400, 6, 2, 4, 1, 900, 4, "binary")]
+
+
+def _search_case_data(n, d, seed, kind):
     rng = np.random.default_rng(seed)
-    X = rng.standard_normal((n, d)).astype(np.float32)
-    Q = (X[rng.integers(0, n, 12)] + 0.1 * rng.standard_normal((12, d))).astype(np.float32)
+    if kind == "gauss":
+        X = rng.standard_normal((n, d)).astype(np.float32)
+        Q = (X[rng.integers(0, n, 12)] + 0.1 * rng.standard_normal((12, d))).astype(np.float32)
+    elif kind == "quantised":
+        # integer coordinates: equal gaps at different nodes and trees
+        X = rng.integers(0, 4, (n, d)).astype(np.float32)
+        Q = (X[rng.integers(0, n, 12)] + rng.integers(-1, 2, (12, d))).astype(np.float32)
+    else:
+        # 0/1 coordinates, queries at 0.5: every gap is 0.5
+        X = (rng.random((n, d)) < np.linspace(0.1, 0.45, d)).astype(np.float32)
+        Q = np.full((4, d), 0.5, np.float32)
+    return X, Q
+
+
+@pytest.mark.parametrize("n,d,m,t,p,c,seed,kind", SEARCH_CASES)
+def test_search_pop_order_equals_static_leaf_ranking(n, d, m, t, p, c, seed, kind):
+    X, Q = _search_case_data(n, d, seed, kind)
     F = oracle.build_forest(X, m, t, p, seed)
     r = oracle.search(F, X, Q, 3, c)
     for i in range(len(Q)):
-        codes, keys = static_leaf_order(F, Q[i])
+        codes, keys = static_leaf_order_gap(F, Q[i])
         assert r["opened"][i].tolist() == codes[:r["B"]]
         assert r["opened_key"][i].tolist() == keys[:r["B"]]
+
+
+@pytest.mark.parametrize("n,d,m,t,p,c,seed,kind", SEARCH_CASES)
+def test_search_max_key_variant_equals_its_static_ranking(n, d, m, t, p, c, seed, kind):
+    X, Q = _search_case_data(n, d, seed, kind)
+    F = oracle.build_forest(X, m, t, p, seed)
+    r = oracle.search(F, X, Q, 3, c, eff_key=True)
+    for i in range(len(Q)):
+        codes, keys = static_leaf_order_eff(F, Q[i])
+        assert r["opened"][i].tolist() == codes[:r["B"]]
+        assert r["opened_key"][i].tolist() == keys[:r["B"]]
+
+
+def test_search_key_variants_open_different_leaves():
+    # with several split dimensions the two keys disagree inside groups of
+    # equal chain maximum: the reference must not be the variant
+    X, Q = _search_case_data(2000, 24, 0, "gauss")
+    F = oracle.build_forest(X, 4, 5, 8, 0)
+    a = oracle.search(F, X, Q, 3, 100)
+    b = oracle.search(F, X, Q, 3, 100, eff_key=True)
+    differ = sum(set(a["opened"][i].tolist()) != set(b["opened"][i].tolist())
+                 for i in range(len(Q)))
+    assert differ >= 1
 
 
 def test_search_1d_closed_form_nearest_cells():
@@ -336,13 +509,13 @@ def test_search_candidates_union_and_topk_over_them():
     assert np.allclose(r["dists"], ed, rtol=1e-13, atol=0)
 
 
-@pytest.mark.parametrize("literal", [False, True])
-def test_search_exhaustive_budget_is_exact_knn(literal):
+@pytest.mark.parametrize("eff_key", [False, True])
+def test_search_exhaustive_budget_is_exact_knn(eff_key):
     rng = np.random.default_rng(6)
     X = rng.standard_normal((1500, 20)).astype(np.float32)
     Q = rng.standard_normal((25, 20)).astype(np.float32)
     F = oracle.build_forest(X, 3, 4, 6, 6)
-    r = oracle.search(F, X, Q, 10, 3 << F["H"], literal=literal, candidates=True)
+    r = oracle.search(F, X, Q, 10, 3 << F["H"], eff_key=eff_key, candidates=True)
     assert all(len(cq) == 1500 for cq in r["cand"])
     ei, ed = bf.knn_exact(X, Q, 10)
     assert np.array_equal(r["ids"], ei)
@@ -380,8 +553,8 @@ def test_search_home_leaves_first():
     X = rng.standard_normal((800, 10)).astype(np.float32)
     Q = rng.standard_normal((6, 10)).astype(np.float32)
     F = oracle.build_forest(X, 5, 3, 4, 4)
-    for literal in (False, True):
-        r = oracle.search(F, X, Q, 1, 40, literal=literal)
+    for eff_key in (False, True):
+        r = oracle.search(F, X, Q, 1, 40, eff_key=eff_key)
         assert np.all(r["opened_key"][:, :5] == 0)
         assert ((r["opened"][:, :5] >> 24) == np.arange(5)).all()
 
@@ -471,7 +644,8 @@ def test_householder_forest_differs_and_exhaustive_budget_is_exact_knn():
 
 # ------------------------------------------------ sharding the trees (design)
 # Across GPUs the trees would be split into groups.  Each group ranks its own
-# leaves by the static key (eff, tree, entry) and keeps its B smallest; the B
+# leaves by the static key of Alg. 2's order (a leaf's strictly decreasing
+# suffix maxima of (|gap|, tree, node)) and keeps its B smallest; the B
 # smallest of the union are the opened set, because every key of the global
 # B smallest is among its own group's B smallest.  Each group then takes the
 # best k of its own candidates, and merging those lists with duplicates
@@ -490,9 +664,9 @@ def test_tree_sharding_merge_equals_global_selection(groups):
     B = r["B"]
     lo = F["leaf_off"].astype(np.int64)
     for i in range(len(Q)):
-        # every leaf in (eff, tree, entry) order; a leaf's position in this
+        # every leaf in Alg. 2's static order; a leaf's position in this
         # list stands for its full key
-        codes, _ = static_leaf_order(F, Q[i])
+        codes, _ = static_leaf_order_gap(F, Q[i])
         trees = np.array([cd >> 24 for cd in codes])
         shard_of_tree = np.arange(m) % groups
         merged, local_best = [], []
