@@ -81,7 +81,12 @@ typedef enum { GF_FORM_FP32 = 0, GF_FORM_BF16 = 1, GF_FORM_FP8 = 2 } gf_form;
  * the arrays, the FP32 rows and the requested reduced-precision copies are
  * then uploaded on `stream` (host rows through pinned staging buffers).
  * With the environment variable GF_BUILD_TIMING=1 each phase's wall time is
- * printed to stderr. */
+ * printed to stderr.
+ * GF_EINVAL also when D is not determined by the data: the t-th and
+ * (t+1)-th largest column variances differ by at most 1e-12 of the larger
+ * of the two columns' mean squares (V + mean^2), the scale of FP64
+ * rounding in the variance, so that another correct evaluation could pick a
+ * different set (Alg. 1). */
 gf_status gf_build_forest(const float *X, int64_t n, int32_t d, int32_t m, int32_t t,
                           int32_t leaf, uint64_t seed, uint32_t forms, void *stream,
                           gf_forest **out);
@@ -123,7 +128,10 @@ gf_status gf_export_tree(const gf_forest *F, int32_t *D, int32_t *split_dim,
                          float *split_val, uint32_t *perm, uint32_t *leaf_off);
 
 /* Search every row of Q (Alg. 2): the leaves opened per query are the first
- * B = min(ceil(checks/(1+eps)), m * 2^H) of the shared queue's pop order;
+ * B = min(ceil(checks/(1+eps)), m * 2^H) of the shared queue's pop order
+ * (every root enters at key 0; each child left behind during a descent
+ * enters with its own |gap| of Eq. 1, gap = float32(q_s - v), a zero gap
+ * descending right; equal keys pop the lower tree, then the lower node);
  * the candidates are the distinct points of those leaves; the result is the
  * k best candidates.
  * Two execution paths give the same candidate sets: the row path gathers
@@ -206,10 +214,28 @@ gf_status gf_multi_stats(int64_t *graphs_built, int64_t *graphs_reused, int64_t 
  *              candidate (the visited array after all opened leaves);
  *   ncand      [nq] int64: number of candidates.
  * All three are host-or-device; any may be NULL.  Same budget rules as
- * gf_query.  Runs the same selection and expansion kernels as gf_query. */
+ * gf_query.  Runs the same selection kernels as gf_query, and the row
+ * path's expansion: the candidate set is the visited bitmap that the row
+ * scan builds (the visited array of Sec. 2.3).  Equal to
+ * gf_query_trace_ex(..., GF_TRACE_ROWS, ...). */
 gf_status gf_query_trace(const gf_forest *F, const float *Q, int64_t nq, int32_t checks,
                          const int32_t *checks_per_query, double eps, uint32_t *leaf_bits,
                          uint32_t *cand_bits, int64_t *ncand, void *stream);
+
+/* Which expansion gf_query_trace_ex reports the candidates of. */
+#define GF_TRACE_ROWS 0   /* the row scan's visited bitmap */
+#define GF_TRACE_TILE 1   /* the tile path's per-point words of query bits */
+
+/* gf_query_trace with the expansion chosen by `path`.  GF_TRACE_TILE runs
+ * the tile path's expansion kernels (opened leaves -> per-leaf rows of
+ * query bits -> per-point words of query bits, the words the MFMA tile
+ * kernel masks its scores with) and returns those words turned back into
+ * the per-query layout of cand_bits; it needs a forest built with
+ * GF_KEEP_BF16 (GF_EINVAL otherwise).  Other values of path: GF_EINVAL. */
+gf_status gf_query_trace_ex(const gf_forest *F, const float *Q, int64_t nq, int32_t checks,
+                            const int32_t *checks_per_query, double eps, int32_t path,
+                            uint32_t *leaf_bits, uint32_t *cand_bits, int64_t *ncand,
+                            void *stream);
 
 /* Diagnostics of the FP8 e4m3 storage format (used by the tests):
  *   hw_decode[256]   every byte decoded by the gfx950 conversion instruction

@@ -242,8 +242,9 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Worksp
     const int nslice = F->host.m * gf::select_slices_per_tree(F->host.H);
     size_t ohist = c.take<uint32_t>(size_t(nb) * nslice * 128);
     size_t onc = c.take<uint32_t>(size_t(nb) * nslice);
-    size_t ock = c.take<uint64_t>(size_t(nb) * gf::kCollectCap);
-    size_t occ = c.take<uint32_t>(size_t(nb) * gf::kCollectCap);
+    const int64_t ccap = gf::collect_capacity(F->host.H);
+    size_t ock = c.take<uint64_t>(size_t(nb) * ccap);
+    size_t occ = c.take<uint32_t>(size_t(nb) * ccap);
     size_t olb = c.take<uint32_t>(size_t(nb) * F->host.m * W);
     size_t ofl = c.take<uint32_t>(8);
     size_t oql = c.take<uint32_t>(nb);
@@ -299,6 +300,14 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Worksp
 
 constexpr int kMaxBatch = 16384;
 
+// Queries per batch: kMaxBatch, fewer for trees deeper than 16 levels, whose
+// collect buffers grow with the largest group of leaves (so the batch's
+// collect area stays at what 16,384 queries take at depth <= 16, 6 GiB).
+int max_batch(const gf_forest* F) {
+    const int64_t per = gf::collect_capacity(F->host.H);
+    return int(std::max<int64_t>(1, std::min<int64_t>(kMaxBatch, int64_t{kMaxBatch} * gf::kCollectCap / per)));
+}
+
 struct QueryJob {
     const float* Q;            // caller's rows (host or device)
     bool q_dev;
@@ -306,12 +315,14 @@ struct QueryJob {
     bool cpq_dev;
     int64_t nq;
     int32_t k, checks;
+    double checks_mean;        // mean budget over the queries (the path rule's estimate)
     double eps;
     int form, kk;
     // outputs (host or device), any may be null
     int32_t* ids; float* dists; bool out_dev;
     uint32_t* leaf_bits; uint32_t* cand_bits; int64_t* ncand; bool trace_dev;
     int path = -1;             // -1 by rule, 0 rows, 1 tile (when eligible)
+    bool trace_tile = false;   // trace: candidates as the tile path builds them
 };
 
 // Whether a batch takes the tile path (BF16 scores of whole query blocks on
@@ -340,7 +351,7 @@ bool use_tile_path(const gf_forest* F, const QueryJob& J, int nb) {
     if (env && std::strcmp(env, "tile") == 0) return true;
     if (nb < 128) return false;
     const double leaf_pts = double(F->host.n) / double(int64_t{1} << F->host.H);
-    const double cand_est = double(J.cpq ? J.checks : J.checks) * leaf_pts * 0.5;
+    const double cand_est = J.checks_mean * leaf_pts * 0.5;
     return cand_est * 256.0 >= double(F->host.n);
 }
 
@@ -352,6 +363,7 @@ gf::SelectArgs make_select_args(const gf_forest* F, int nb, const Workspace& w, 
     sa.drange = F->drange;
     sa.nslice = h.m * gf::select_slices_per_tree(h.H);
     sa.state = w.state; sa.hist = w.hist; sa.coff = w.coff; sa.ckey = w.ckey;
+    sa.ccap = gf::collect_capacity(h.H);
     sa.ccode = w.ccode; sa.leafbits = w.leafbits; sa.qlist = w.qlist; sa.nlist = 0;
     sa.qt = F->U ? w.qt : nullptr;
     return sa;
@@ -375,7 +387,7 @@ gf_status launch_selection(const gf_forest* F, const QueryJob& J, int nb, const 
         GF_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(gf::k_select_init, dim3((nb + 255) / 256), dim3(256), 0, st, sa,
-                       J.checks, cpq, J.eps);
+                       J.checks, cpq, J.eps, w.flags + 1);
     GF_HIP(hipGetLastError());
     // sample walk, window walk, then radix passes while some query needs one.
     // flags[1]: any query left for a radix pass, flags[2]: how many.  With
@@ -420,9 +432,7 @@ gf::ScanArgs make_scan_args(const gf_forest* F, const QueryJob& J, int64_t q0, i
     return ca;
 }
 
-// a3-a6 on the tile path; ev (may be null) gets the expansion and tile marks.
-gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& w, int64_t W,
-                      const gf::ScanArgs& ca, hipStream_t st, hipEvent_t* ev) {
+gf::ExpandArgs make_expand_args(const gf_forest* F, int nb, const Workspace& w, int64_t W) {
     const gf::HostForest& h = F->host;
     const TilePlan tp = tile_plan(F, nb);
     gf::ExpandArgs ea{};
@@ -431,6 +441,15 @@ gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& 
     ea.leafbits = w.leafbits; ea.leafof = F->leafof; ea.openT = w.openT; ea.visT = w.visT;
     ea.order = F->perm;   // tree 0's row of perm: every point once, leaf by leaf
     ea.gthr = w.gthr;
+    return ea;
+}
+
+// a3-a6 on the tile path; ev (may be null) gets the expansion and tile marks.
+gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& w, int64_t W,
+                      const gf::ScanArgs& ca, hipStream_t st, hipEvent_t* ev) {
+    const gf::HostForest& h = F->host;
+    const TilePlan tp = tile_plan(F, nb);
+    const gf::ExpandArgs ea = make_expand_args(F, nb, w, W);
     gf::TileArgs ta{};
     ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.cw = tp.cw; ta.Q16 = w.Q16; ta.X16 = F->X16;
     ta.norm16 = F->norm16; ta.visT = w.visT; ta.gthr = w.gthr; ta.cap = J.kk; ta.nsplit = tp.nsplit;
@@ -493,7 +512,7 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
                     bool graph = false) {
     const gf::HostForest& h = F->host;
     Workspace w;
-    const bool tile = use_tile_path(F, J, nb);
+    const bool tile = J.trace_tile || use_tile_path(F, J, nb);
     gf_status s = get_workspace(F, nb, J.k, J.form, tile, w);
     if (s != GF_OK) return s;
     const int64_t W = std::max<int64_t>(1, (int64_t{1} << h.H) / 32);
@@ -544,7 +563,7 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     ca.ncand = (J.ncand && J.trace_dev) ? J.ncand + q0 : nullptr;
     std::unique_ptr<uint32_t, decltype(&hipFree)> tmp_bits(nullptr, &hipFree);
     std::unique_ptr<int64_t, decltype(&hipFree)> tmp_nc(nullptr, &hipFree);
-    if (J.cand_bits && !J.trace_dev) {
+    if ((J.cand_bits && !J.trace_dev) || (J.trace_tile && !ca.cand_bits && J.ncand)) {
         uint32_t* p = nullptr;
         GF_HIP(hipMalloc(&p, size_t(nb) * nbmw * 4));
         tmp_bits.reset(p);
@@ -557,7 +576,15 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
         ca.ncand = p;
     }
     GF_HIP(hipEventRecord(ev[2], st));
-    if (tile) {
+    if (J.trace_tile) {
+        // the tile path's own candidate words, turned back into query rows
+        if (ca.cand_bits)
+            GF_HIP(gf::launch_tile_trace(make_expand_args(F, nb, w, W), ca.cand_bits, ca.ncand, st));
+        else
+            GF_HIP(gf::launch_tile_expand(make_expand_args(F, nb, w, W), st));
+        GF_HIP(hipEventRecord(ev[3], st));
+        GF_HIP(hipEventRecord(ev[4], st));
+    } else if (tile) {
         s = launch_tile(F, J, nb, w, W, ca, st, ev + 3);
         if (s != GF_OK) return s;
     } else {
@@ -613,8 +640,9 @@ gf_status run_query(gf_forest* F, QueryJob& J, hipStream_t st) {
     std::lock_guard<std::mutex> lock(F->ws_mutex);
     for (double& x : g_phase_ms) x = 0.0;
     g_batches = 0;
-    for (int64_t q0 = 0; q0 < J.nq; q0 += kMaxBatch) {
-        const int nb = int(std::min<int64_t>(kMaxBatch, J.nq - q0));
+    const int mb = max_batch(F);
+    for (int64_t q0 = 0; q0 < J.nq; q0 += mb) {
+        const int nb = int(std::min<int64_t>(mb, J.nq - q0));
         gf_status s = run_batch(F, J, q0, nb, st);
         if (s != GF_OK) return s;
     }
@@ -661,9 +689,23 @@ gf_status prepare_job(const gf_forest* Fc, const float* Q, int64_t nq, int32_t k
     if (nq == 0) return GF_OK;
     J.Q = Q; J.q_dev = is_device_ptr(Q);
     J.cpq = checks_per_query; J.cpq_dev = checks_per_query && is_device_ptr(checks_per_query);
-    if (checks_per_query && !J.cpq_dev) {
-        for (int64_t i = 0; i < nq; ++i)
-            if (checks_per_query[i] < 1) return fail(GF_EINVAL, "checks_per_query has a value < 1");
+    J.checks_mean = double(checks);
+    if (checks_per_query) {
+        // every budget >= 1, and their mean for the path rule (device
+        // budgets are read back once here)
+        std::vector<int32_t> staged;
+        const int32_t* c = checks_per_query;
+        if (J.cpq_dev) {
+            staged.resize(size_t(nq));
+            GF_HIP(hipMemcpy(staged.data(), checks_per_query, size_t(nq) * 4, hipMemcpyDeviceToHost));
+            c = staged.data();
+        }
+        double sum = 0.0;
+        for (int64_t i = 0; i < nq; ++i) {
+            if (c[i] < 1) return fail(GF_EINVAL, "checks_per_query has a value < 1");
+            sum += double(c[i]);
+        }
+        J.checks_mean = sum / double(nq);
     }
     J.out_dev = is_device_ptr(ids);
     if (J.out_dev != is_device_ptr(dists)) return fail(GF_EINVAL, "ids and dists must both be host or both device");
@@ -747,13 +789,26 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
 
     // Every query row finite (one readback for the whole call).
     {
-        static thread_local uint32_t* flag = nullptr;
-        static thread_local int flag_dev = -1;
-        if (flag_dev != Fs[0]->device) {
-            flag = nullptr;
-            GF_HIP(hipMalloc(&flag, 4));
-            flag_dev = Fs[0]->device;
+        // a 4-byte flag from a per-device pool: taken for this call, returned
+        // at its end, reused by later calls (the pool only grows to the
+        // number of calls running at once)
+        static std::mutex flag_mutex;
+        static std::map<int, std::vector<uint32_t*>> pool;
+        const int dev = Fs[0]->device;
+        uint32_t* flag = nullptr;
+        {
+            std::lock_guard<std::mutex> lock(flag_mutex);
+            std::vector<uint32_t*>& free_list = pool[dev];
+            if (!free_list.empty()) {
+                flag = free_list.back();
+                free_list.pop_back();
+            }
         }
+        if (!flag) GF_HIP(hipMalloc(&flag, 4));
+        struct FlagBack {
+            uint32_t* f; int dev;
+            ~FlagBack() { std::lock_guard<std::mutex> lock(flag_mutex); pool[dev].push_back(f); }
+        } flag_back{flag, dev};
         GF_HIP(hipMemsetAsync(flag, 0, 4, st));
         for (int i = 0; i < njobs; ++i) {
             if (jobs[i].nq == 0) continue;
@@ -774,8 +829,9 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
     std::vector<MultiBatch> B;
     for (int i = 0; i < njobs; ++i) {
         gf_forest* F = const_cast<gf_forest*>(jobs[i].forest);
-        for (int64_t q0 = 0; q0 < jobs[i].nq; q0 += kMaxBatch) {
-            const int nb = int(std::min<int64_t>(kMaxBatch, jobs[i].nq - q0));
+        const int mb = max_batch(F);
+        for (int64_t q0 = 0; q0 < jobs[i].nq; q0 += mb) {
+            const int nb = int(std::min<int64_t>(mb, jobs[i].nq - q0));
             QueryJob Jb = J[i];
             bool tile = use_tile_path(F, Jb, nb);
             if ((flags & GF_MULTI_AUTOTUNE) && tile_eligible(F, Jb)) {
@@ -1011,7 +1067,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
     std::unique_ptr<gf_forest> F(new gf_forest());
     std::string err = gf::build_host_forest(Xh, n, d, m, t, leaf, seed,
                                             (variants & GF_VARIANT_HOUSEHOLDER) != 0, F->host);
-    if (!err.empty()) return fail(GF_EINTERNAL, err);
+    if (!err.empty()) return fail(err.rfind("near-tie", 0) == 0 ? GF_EINVAL : GF_EINTERNAL, err);
     phase("host trees");
     GF_HIP(hipGetDevice(&F->device));
     F->uid = g_next_uid.fetch_add(1);
@@ -1180,10 +1236,20 @@ gf_status gf_multi_stats(int64_t* graphs_built, int64_t* graphs_reused, int64_t*
 gf_status gf_query_trace(const gf_forest* Fc, const float* Q, int64_t nq, int32_t checks,
                          const int32_t* checks_per_query, double eps, uint32_t* leaf_bits,
                          uint32_t* cand_bits, int64_t* ncand, void* stream) {
+    return gf_query_trace_ex(Fc, Q, nq, checks, checks_per_query, eps, GF_TRACE_ROWS, leaf_bits,
+                             cand_bits, ncand, stream);
+}
+
+gf_status gf_query_trace_ex(const gf_forest* Fc, const float* Q, int64_t nq, int32_t checks,
+                            const int32_t* checks_per_query, double eps, int32_t path,
+                            uint32_t* leaf_bits, uint32_t* cand_bits, int64_t* ncand, void* stream) {
     gf_status s = validate_query_common(Fc, Q, nq, checks, checks_per_query, eps);
     if (s != GF_OK) return s;
+    if (path != GF_TRACE_ROWS && path != GF_TRACE_TILE) return fail(GF_EINVAL, "unknown trace path");
     gf_forest* F = const_cast<gf_forest*>(Fc);
-    if (!gf::scan_supported(F->host.n, GF_FORM_FP32, F->ld8))
+    if (path == GF_TRACE_TILE && !F->leafof)
+        return fail(GF_EINVAL, "the tile path's trace needs a forest built with GF_KEEP_BF16");
+    if (path == GF_TRACE_ROWS && !gf::scan_supported(F->host.n, GF_FORM_FP32, F->ld8))
         return fail(GF_EUNSUPPORTED, "n too large for the LDS visited bitmap");
     if (nq == 0) return GF_OK;
     QueryJob J{};
@@ -1195,6 +1261,7 @@ gf_status gf_query_trace(const gf_forest* Fc, const float* Q, int64_t nq, int32_
     }
     J.nq = nq; J.k = 1; J.checks = checks; J.eps = eps; J.form = GF_FORM_FP32; J.kk = 1;
     J.leaf_bits = leaf_bits; J.cand_bits = cand_bits; J.ncand = ncand;
+    J.trace_tile = path == GF_TRACE_TILE;
     const void* any = leaf_bits ? (const void*)leaf_bits : cand_bits ? (const void*)cand_bits : (const void*)ncand;
     J.trace_dev = any && is_device_ptr(any);
     return run_query(F, J, static_cast<hipStream_t>(stream));

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <thread>
 
 #include "forest.h"
@@ -72,8 +73,10 @@ unsigned worker_count(int64_t jobs) {
 // Per-dimension variance with Knuth's online update (Alg. 3), run over a
 // block of rows per thread; the per-block (count, mean, M2) triples are then
 // combined pairwise (Chan, Golub, LeVeque).
-void column_variance(const float* X, int64_t n, int32_t d, std::vector<double>& V) {
+void column_variance(const float* X, int64_t n, int32_t d, std::vector<double>& V,
+                     std::vector<double>& M) {
     V.assign(d, 0.0);
+    M.assign(d, 0.0);
     if (n < 2) return;
     const unsigned nw = worker_count(n / 4096 + 1);
     std::vector<std::vector<double>> mean(nw, std::vector<double>(d, 0.0));
@@ -112,6 +115,24 @@ void column_variance(const float* X, int64_t n, int32_t d, std::vector<double>& 
         na = nt;
     }
     for (int32_t j = 0; j < d; ++j) V[j] = v[j] / double(n - 1);
+    M = mu;
+}
+
+// Whether the top-t set is not determined by the data: the t-th and
+// (t+1)-th largest variances (order: variance descending, index ascending)
+// differ by at most 1e-12 of the larger mean square V + mean^2 of the two
+// columns, the scale of the rounding error of any FP64 evaluation.  Two
+// correct evaluations (this online update, a two-pass sum) could then rank
+// them differently.  n < 2 (V = 0 by definition) and columns of mean square
+// 0 are exact.
+bool dims_ambiguous(const std::vector<double>& V, const std::vector<double>& M,
+                    const std::vector<int32_t>& order, int64_t n, int32_t t) {
+    const int32_t d = int32_t(V.size());
+    if (n < 2 || t >= d) return false;
+    const int32_t a = order[t - 1], b = order[t];
+    const double scale = std::max(V[a] + M[a] * M[a], V[b] + M[b] * M[b]);
+    if (!(scale > 0.0)) return false;
+    return V[a] - V[b] <= 1e-12 * scale;
 }
 
 struct Item {
@@ -207,12 +228,16 @@ std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, i
 
     // V <- variances; D <- the t dimensions of largest variance (lower index
     // first among equal variances), kept in ascending index order.
-    std::vector<double> V;
-    column_variance(X, n, d, V);
+    std::vector<double> V, M;
+    column_variance(X, n, d, V, M);
     std::vector<int32_t> order(d);
     for (int32_t j = 0; j < d; ++j) order[j] = j;
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return V[a] > V[b]; });
+    if (dims_ambiguous(V, M, order, n, t))
+        return "near-tie in D: the t-th and (t+1)-th largest variances are within rounding of "
+               "each other (columns " + std::to_string(order[t - 1]) + " and " +
+               std::to_string(order[t]) + ")";
     F.D.assign(order.begin(), order.begin() + t);
     std::sort(F.D.begin(), F.D.end());
 

@@ -9,7 +9,14 @@ namespace gf {
 
 // ---------------------------------------------------------------- selection
 
-constexpr int kCollectCap = 32768;  // keys resolved by the final per-query select
+// A bin of the first-level key is resolved by the final per-query select
+// once it holds at most kCollectCap leaves.  The narrowest bin, one key,
+// holds one group: the leaves below a head at depth >= 1, at most 2^(H-1),
+// so the collect buffer per query holds max(kCollectCap, 2^(H-1)) slots.
+constexpr int kCollectCap = 32768;
+inline int64_t collect_capacity(int H) {
+    return H - 1 > 15 ? (int64_t{1} << (H - 1)) : int64_t{kCollectCap};
+}
 constexpr int kMaxPasses = 9;       // 63 significant key bits / 7-bit digits
 
 enum : uint32_t { kSelSearching = 0, kSelReady = 1, kSelAll = 2, kSelDone = 3 };
@@ -46,8 +53,9 @@ struct SelectArgs {
     SelState* state;       // [nq]
     uint32_t* hist;        // [nq][nslice][128]
     uint32_t* coff;        // [nq][nslice] collect offsets
-    uint64_t* ckey;        // [nq][kCollectCap] keys (or eff bits and tie keys, as u32 pairs)
-    uint32_t* ccode;       // [nq][kCollectCap]
+    int64_t ccap;          // collect slots per query: collect_capacity(H)
+    uint64_t* ckey;        // [nq][ccap] keys (or M bits and tie keys, as two u32 halves)
+    uint32_t* ccode;       // [nq][ccap]
     uint32_t* leafbits;    // [m][W][nq]  (word-major, query fastest)
     uint32_t* qlist;       // [nq] queries sent to the next radix pass, in flags[1] order
     int nlist;             // > 0: a radix walk serves qlist[0 .. nlist) only
@@ -62,7 +70,9 @@ struct SelectArgs {
 __global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, int m, int mp, int t,
                                   const int32_t* D, const double* UT, float* qt);
 
-__global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps);
+// Also clears flags[0..1] (the radix-pass flags of k_select_pick).
+__global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps,
+                              uint32_t* flags);
 // flags[0]: set when some query goes on to a radix pass; flags[1]: how many
 __global__ void k_select_pick(SelectArgs a, int phase, uint32_t* flags);
 int select_slices_per_tree(int H);
@@ -157,6 +167,11 @@ struct MergeArgs {
     float* dists;
 };
 
+// The expansion alone: openT and visT from the opened-leaf bits.
+hipError_t launch_tile_expand(const ExpandArgs& e, hipStream_t st);
+// The expansion, then visT in query-major form (cand_bits [nq][ceil(n/32)])
+// and, if ncand is not null, each query's candidate count.
+hipError_t launch_tile_trace(const ExpandArgs& e, uint32_t* cand_bits, int64_t* ncand, hipStream_t st);
 // Records ev[0] after the expansion and ev[1] after the tile kernel (ev may
 // be null).
 hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeArgs& m,

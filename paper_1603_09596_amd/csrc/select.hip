@@ -1,40 +1,54 @@
 // select.hip -- which leaves each query opens (Alg. 2, Sec. 2.3) on gfx950.
 //
-// The queue of Alg. 2 pops entries in the order of the key
-//     (eff, tree, node),  eff = max(eff of the entry being descended, |gap|),
-// where gap is the float32 difference of Eq. (1) and every tree's root enters
-// at eff 0.  Under this order a parent entry always precedes the entries it
-// pushes, so the pop sequence is the sorted order of the static per-leaf key
-//     K(L) = (eff(L), tree, entry(L)),
-// eff(L) being the largest gap on L's root path among the nodes where L lies
-// on the far side, and entry(L) the deepest such far child (the root if none).
-// The first B pops are therefore the B smallest K(L) over every leaf of the
-// forest, and this file computes exactly that set without a sequential queue:
+// Alg. 2 keeps one queue over all trees.  Every tree's root enters at key 0;
+// popping an entry descends to a leaf, and each node passed on the way
+// leaves its far child behind with key |gap|, gap being the float32
+// difference of Eq. (1).  Ties go to the lower tree, then the lower node.
+//
+// The pop order is a sort by a static per-leaf key.  Write a leaf's chain
+// as the root (key 0) followed by the far children on its root path, each
+// with its own |gap|.  Its static key is the subsequence of chain entries
+// strictly larger than every entry after them (the strictly decreasing
+// suffix maxima), compared lexicographically by (|gap|, tree, node), a
+// prefix first.  Why: (1) no entry with a smaller chain maximum can wait
+// behind a popped one, so pops come in non-decreasing order of the chain
+// maximum M; (2) among the leaves of maximum M, every chain entry of key M
+// heads a group (the entries below it reached through keys < M), the
+// queue empties one group before it pops the next head, and heads come out
+// in (tree, node) order because a head found inside a group is a
+// descendant, with a larger node index, of that group's head; (3) inside a
+// group the same argument applies to the chain below its head.  The head of
+// a leaf's group, S1, is the deepest chain entry of key M.
+//
+// This file computes the set of the B first leaves in that order without a
+// sequential queue:
 //
 //   * a tree walk in which the 64 lanes of a wavefront are 64 queries walking
 //     the same tree in lockstep: node loads are uniform (scalar / broadcast),
-//     each lane keeps its own eff and entry, and the bottom five levels are
+//     each lane keeps its own M and S1, and the bottom five levels are
 //     expanded breadth-first in registers, 32 leaves at a time;
 //   * counting walks that narrow each query's threshold to a bin of at most
-//     kCollectCap leaves (per-lane histograms in LDS, written out per (query,
-//     tree slice) without atomics).  The trees are drawn alike, so the
-//     ceil(2B/m)-th smallest eff of trees 0 and 1 lies close to the B-th
-//     smallest of the forest: a walk over those two trees finds it in bins
-//     of 1/8 octave, and one walk over every tree then counts 62 bins of
-//     1/128 octave around it (a quarter octave either way) and the keys
-//     below the window.  The estimate only places the window; the counts
-//     are exact.  A query whose B-th key falls outside the window, or whose bin
-//     still holds more than kCollectCap leaves, continues with exact radix
-//     passes over the 64-bit key (7-bit digits);
+//     kCollectCap leaves of the first-level key (M, tree, S1) (per-lane
+//     histograms in LDS, written out per (query, tree slice) without
+//     atomics).  The trees are drawn alike, so the ceil(2B/m)-th smallest M
+//     of trees 0 and 1 lies close to the B-th smallest of the forest: a walk
+//     over those two trees finds it in bins of 1/8 octave, and one walk over
+//     every tree then counts 62 bins of 1/128 octave around it (a quarter
+//     octave either way) and the keys below the window.  The estimate only
+//     places the window; the counts are exact.  A query whose B-th key falls
+//     outside the window, or whose bin still holds more than kCollectCap
+//     leaves, continues with exact radix passes over the 64-bit first-level
+//     key (7-bit digits);
 //   * a final walk that marks every leaf below the bin in the query's leaf
-//     bitmap and writes the bin's eff bits and leaf codes to per-slice
-//     offsets of the query's collect buffer (again without atomics); a
-//     per-query radix select over those eff bits finds the B-th eff, and only
-//     where leaves tie at that eff across the budget are their (tree, entry)
-//     keys recomputed from the root paths to order them.
+//     bitmap and writes the bin's keys and leaf codes to per-slice offsets
+//     of the query's collect buffer (again without atomics); a per-query
+//     radix select over those keys finds the threshold, and where the group
+//     at the threshold crosses the budget the deeper levels of the static
+//     key are computed from the root paths of its leaves, one level at a
+//     time, until the group no longer crosses it.
 //
-// Key layout: bits 63..32 = eff as float bits (eff >= 0, so the bit pattern
-// orders like the value), 31..24 = tree, 23..0 = entry node (heap index).
+// First-level key layout: bits 63..32 = M as float bits (M >= 0, so the bit
+// pattern orders like the value), 31..24 = tree, 23..0 = S1 (heap index).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -63,18 +77,21 @@ constexpr uint32_t kWindowHalf = 31;   // bin 1 lies 31 bins below the centre
 __host__ __device__ inline int sample_trees(int m) { return m >= 2 ? 2 : 1; }
 
 // Walk one tree for the 64 queries of this wavefront.  Calls
-// fn(chunk, eff[32], entry[32]) for every group of 2^CH consecutive leaves
-// (leaf index = chunk * 2^CH + x), eff[] holding each leaf's eff as the bit
-// pattern of a float >= +0.  qd: LDS [t][64] query coordinates on the split
-// set D; pe/pn: LDS [(H-CH+1)][64] path state.  With ENTRY false the entry
-// nodes are not tracked (en[] stays undefined).
+// fn(chunk, M[32], S1[32]) for every group of 2^CH consecutive leaves
+// (leaf index = chunk * 2^CH + x), M[] holding each leaf's chain maximum
+// as the bit pattern of a float >= +0.  qd: LDS [t][64] query coordinates
+// on the split set D; pe/pn: LDS [(H-CH+1)][64] path state.  With ENTRY
+// false the heads S1 are not tracked (the array stays undefined).
 //
-// Child eff from the parent's eff e >= +0 and gap g = q - v: the left child
-// is the far one exactly when g >= 0, so its eff is max(e, g) (which is e
-// when g < 0), and the right child's is max(e, v - q), v - q being exactly
-// -g.  For e >= +0 the float maximum equals the signed-integer maximum of
-// the bit patterns (a negative float is a negative integer, below every
-// e); the integer form needs no sign handling and never yields -0.
+// Child state from the parent's (M, S1), M >= +0, and gap g = q - v: the
+// left child is the far one exactly when g >= 0 (including g = -0), with
+// key |g|; the right one when g < 0, with key v - q = -g exactly.  The far
+// child's M is max(M, key), and it becomes S1 when key >= M (the deepest
+// entry attaining the maximum).  For M >= +0 the float maximum equals the
+// signed-integer maximum of the bit patterns (a negative float is a
+// negative integer, below every M), so M is formed without sign handling;
+// S1's comparison uses the key's magnitude bits, so that g = -0 counts as
+// key 0.
 template <int CH, bool ENTRY, class Fn>
 __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H,
                                           uint32_t chunk_begin, uint32_t chunk_end,
@@ -107,11 +124,12 @@ __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H
             const float g = qv - sv;
             const bool go_right = (c >> (U - 1 - h)) & 1u;
             const int32_t e = pe[h * kWave + lane];
-            pe[(h + 1) * kWave + lane] = max(e, __float_as_int(go_right ? sv - qv : g));
+            const int32_t kb = __float_as_int(go_right ? sv - qv : g);
+            pe[(h + 1) * kWave + lane] = max(e, kb);
             if (ENTRY) {
                 const bool near_right = !(g < 0.0f);
                 uint32_t en = pn[h * kWave + lane];
-                if (go_right != near_right) en = 2u * v + 1u + (go_right ? 1u : 0u);
+                if (go_right != near_right && (kb & 0x7FFFFFFF) >= e) en = 2u * v + 1u + (go_right ? 1u : 0u);
                 pn[(h + 1) * kWave + lane] = en;
             }
         }
@@ -130,14 +148,15 @@ __device__ __forceinline__ void walk_tree(const uint2* __restrict__ nodes, int H
                 const float qv = qd[nd.y * kWave + lane], sv = __uint_as_float(nd.x);
                 const float g = qv - sv;
                 const int32_t e = ef[x];
-                ef[2 * x] = max(e, __float_as_int(g));
-                ef[2 * x + 1] = max(e, __float_as_int(sv - qv));
+                const int32_t kl = __float_as_int(g), kr = __float_as_int(sv - qv);
+                ef[2 * x] = max(e, kl);
+                ef[2 * x + 1] = max(e, kr);
                 if (ENTRY) {
                     const bool near_right = !(g < 0.0f);
                     const uint32_t n = en[x];
                     const uint32_t v = row + uint32_t(x);
-                    en[2 * x] = near_right ? 2u * v + 1u : n;
-                    en[2 * x + 1] = near_right ? n : 2u * v + 2u;
+                    en[2 * x] = (near_right && (kl & 0x7FFFFFFF) >= e) ? 2u * v + 1u : n;
+                    en[2 * x + 1] = (!near_right && kr >= e) ? 2u * v + 2u : n;
                 }
             }
         }
@@ -341,9 +360,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
     uint32_t cb, ce;
     wave_chunks(1u << U, cb, ce);
     const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
-    uint64_t* keys = a.ckey + int64_t(q) * kCollectCap;
+    uint64_t* keys = a.ckey + int64_t(q) * a.ccap;
     uint32_t* effs = reinterpret_cast<uint32_t*>(keys);
-    uint32_t* codes = a.ccode + int64_t(q) * kCollectCap;
+    uint32_t* codes = a.ccode + int64_t(q) * a.ccap;
     if (FULL) {
         // full-key bounds for every lane: [lo, hi) is the bin, all keys of an
         // exhausted budget lie below lo = ~0
@@ -354,6 +373,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
             lo = st.prefix << st.cs;
             hi = (st.prefix + 1ull) << st.cs;
         }
+        // marked here: below the bin, or below its top where the bin is
+        // premarked (an M-bit bin of a query sharing this workgroup with a
+        // full-key query: the finish then only clears what it does not take)
+        const uint64_t mlo = (ready && premark_bin(st)) ? hi : lo;
         walk_tree<CH, true>(nodes, a.H, cb, ce, qd, pe, pn,
                             [&](uint32_t c, const uint32_t* ef, const uint32_t* en) {
                                 if (!valid) return;
@@ -361,10 +384,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
 #pragma unroll
                                 for (int x = 0; x < (1 << CH); ++x) {
                                     const uint64_t K = leaf_key(ef[x], tree, en[x]);
-                                    bits |= (K < lo ? 1u : 0u) << x;
+                                    bits |= (K < mlo ? 1u : 0u) << x;
                                     if (K - lo < hi - lo) {
                                         const uint32_t pos = atomicAdd(&cnt[lane], 1u);
-                                        if (pos < uint32_t(kCollectCap)) {
+                                        if (pos < uint32_t(a.ccap)) {
                                             if (full)
                                                 keys[pos] = K;
                                             else
@@ -400,7 +423,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
                                      bits = bits + bits + (E < mlo ? 1u : 0u);
                                      if (E - elo < width) {
                                          const uint32_t pos = atomicAdd(&cnt[lane], 1u);
-                                         if (pos < uint32_t(kCollectCap)) {
+                                         if (pos < uint32_t(a.ccap)) {
                                              effs[pos] = E;
                                              codes[pos] = (tree << 24) | ((c << CH) + uint32_t(x));
                                          }
@@ -411,26 +434,61 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
     }
 }
 
-// Entry node of leaf `leaf` of tree `tree` for a query (coordinates on D in
-// qd): the deepest child on the root path that lies on the far side of its
-// parent's split, or the root.  The same float32 gaps as the walk.  The path
-// follows from the leaf index alone, so all node loads are independent.
-__device__ uint32_t entry_node(const SelectArgs& a, const float* qd, uint32_t tree, uint32_t leaf) {
+// Head S1 of leaf `leaf` of tree `tree` for a query (coordinates on D in
+// qd): the deepest entry of its chain whose |gap| equals the chain maximum
+// (the root, key 0, when no far-side key reaches it).  The same float32 gaps
+// as the walk.  The path follows from the leaf index alone, so all node
+// loads are independent.
+__device__ uint32_t head_node(const SelectArgs& a, const float* qd, uint32_t tree, uint32_t leaf) {
     const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
     const int H = a.H;
     uint32_t en = 0;
+    int32_t e = 0;
 #pragma unroll
     for (int h = 0; h < 24; ++h) {   // tree depth is at most 23
         if (h < H) {
             const uint32_t v = ((1u << h) - 1u) + (leaf >> (H - h));
             const uint2 nd = nodes[v];
-            const float g = qd[nd.y] - __uint_as_float(nd.x);
+            const float qv = qd[nd.y], sv = __uint_as_float(nd.x);
+            const float g = qv - sv;
             const bool go_right = (leaf >> (H - 1 - h)) & 1u;
             const bool near_right = !(g < 0.0f);
-            if (go_right != near_right) en = 2u * v + 1u + (go_right ? 1u : 0u);
+            const int32_t kb = __float_as_int(go_right ? sv - qv : g) & 0x7FFFFFFF;
+            if (go_right != near_right && kb >= e) {
+                en = 2u * v + 1u + (go_right ? 1u : 0u);
+                e = kb;
+            }
         }
     }
     return en;
+}
+
+// The next level of a leaf's static key below a head it shares with the
+// rest of its group: the largest |gap| among the far-side nodes of its path
+// strictly below the head node, and the deepest far child attaining it,
+// encoded as ((|gap| bits + 1) << 24) | node; 0 when the path has no far
+// side below the head (that leaf comes first: it is reached from the head
+// by near descents only, and is unique).
+__device__ uint64_t next_level_key(const SelectArgs& a, const float* qd, uint32_t tree, uint32_t leaf,
+                                   uint32_t head) {
+    const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
+    const int H = a.H;
+    const int dh = 31 - __builtin_clz(head + 1u);   // depth of the head
+    uint32_t best = 0, node = 0;                    // best = bits + 1 (0: none)
+    for (int h = dh; h < H; ++h) {
+        const uint32_t v = ((1u << h) - 1u) + (leaf >> (H - h));
+        const uint2 nd = nodes[v];
+        const float qv = qd[nd.y], sv = __uint_as_float(nd.x);
+        const float g = qv - sv;
+        const bool go_right = (leaf >> (H - 1 - h)) & 1u;
+        const bool near_right = !(g < 0.0f);
+        const uint32_t kb = (__float_as_uint(go_right ? sv - qv : g) & 0x7FFFFFFFu) + 1u;
+        if (go_right != near_right && kb >= best) {
+            best = kb;
+            node = 2u * v + 1u + (go_right ? 1u : 0u);
+        }
+    }
+    return best ? (uint64_t(best) << 24) | node : 0ull;
 }
 
 // Block-wide step of a radix select over 2^w <= 256 bins (256 threads, all
@@ -504,8 +562,13 @@ __global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, in
 // within its slot's range, and float subtraction is monotone, so no eff
 // exceeds gmax = max over slots of |q - lo| and |q - hi|: the sample walk's
 // bins end at gmax's bin and reach 127 bins (15.9 octaves) below it.
-__global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps) {
+__global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps,
+                              uint32_t* flags) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) {   // the radix-pass flag and list count of k_select_pick
+        flags[0] = 0u;
+        flags[1] = 0u;
+    }
     if (q >= a.nq) return;
     const int64_t c = cpq ? int64_t(cpq[q]) : int64_t(checks);
     // Alg. 2 checks leaves while l < c/(1+eps): ceil(c/(1+eps)) of them.
@@ -600,7 +663,10 @@ __device__ bool pick_one(const SelectArgs& a, int phase, SelState s, const uint3
     }
     if (radix) {
         atomicOr(&flags[0], 1u);
-        a.qlist[atomicAdd(&flags[1], 1u)] = uint32_t(q);
+        // the list holds nq entries; a pass adds each query at most once,
+        // and the count starts at 0 (k_select_init, or a reset per pass)
+        const uint32_t slot = atomicAdd(&flags[1], 1u);
+        if (slot < uint32_t(a.nq)) a.qlist[slot] = uint32_t(q);
     }
     a.state[q] = s;
     return radix;
@@ -631,14 +697,57 @@ __global__ __launch_bounds__(kBins) void k_select_pick(SelectArgs a, int phase, 
         for (int sl = 0; sl < a.nslice; ++sl) h[int64_t(sl) * kBins + threadIdx.x] = 0u;
 }
 
-// Resolve the bin.  The (B - below) smallest collected keys are marked in the
-// leaf bitmap; keys are distinct, so exactly B leaves end up marked in total.
-//   eff-bit bins: a radix select (8-bit digits) over the eff bits below the
-//   bin's prefix finds the threshold eff E*.  If the leaves at E* are not all
-//   taken, their (tree, entry) keys are recomputed and a second radix select
-//   over those orders the ties.
-//   full-key bins: a radix select over the 64-bit keys.
+// Resolve the bin: exactly (B - below) of the collected leaves are taken
+// (marked in the leaf bitmap), those first in the static order.
+//   eff-bit bins: a radix select (8-bit digits) over the M bits finds the
+//   threshold M*.  If the leaves at M* are not all taken, their (tree, S1)
+//   are recomputed from the root paths and a second radix select orders
+//   them; the group at the threshold (tree, S1), if it still crosses the
+//   budget, goes to the deeper levels.
+//   full-key bins: a radix select over the 64-bit first-level keys, then
+//   the deeper levels for the group at the threshold key.
+// Deeper levels: each leaf of the group gets the next element of its static
+// key below the group's head (next_level_key), a radix select over those
+// 56-bit values splits the group, and the part at the threshold, if it
+// still crosses the budget, repeats one level further down.  A head is
+// deeper at every level, so at most H levels run.
 constexpr int kFinishUnroll = 4;
+
+namespace {
+
+// Radix select over up to 56-bit values of the collected slots for which
+// get(i, v) returns true: finds the value kstar holding the need-th
+// smallest (1-based), the rank left of the need-th inside kstar's group and
+// that group's size.  All 256 threads call it.
+template <class Get>
+__device__ void select56(uint32_t cnt, uint32_t need, Get get, uint32_t* hist, uint32_t* pub,
+                         uint32_t* wsum, uint64_t* sh_prefix, uint64_t& kstar, uint32_t& left,
+                         uint32_t& ties) {
+    uint64_t prefix = 0;
+    left = need;
+    ties = 0;
+    for (int shift = 48; shift >= 0; shift -= 8) {
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+            uint64_t v;
+            if (get(i, v) && (shift == 48 || (v >> (shift + 8)) == prefix))
+                atomicAdd(&hist[(v >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        pick_bin(hist, 0u, 8, left, pub, wsum);
+        __syncthreads();
+        if (threadIdx.x == 0) *sh_prefix = (prefix << 8) | pub[0];
+        left = pub[1];
+        ties = pub[2];
+        __syncthreads();
+        prefix = *sh_prefix;
+        __syncthreads();
+    }
+    kstar = prefix;
+}
+
+}  // namespace
 
 __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
     __shared__ uint32_t hist[256];
@@ -650,21 +759,68 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
     const int q = blockIdx.x;
     const SelState s = a.state[q];
     if (s.status != kSelReady) return;
-    const uint32_t cnt = min(s.bincount, uint32_t(kCollectCap));
+    const int64_t cap = a.ccap;
+    const uint32_t cnt = min(s.bincount, uint32_t(cap));
     const uint32_t need = s.budget - s.below;
-    const uint32_t* codes = a.ccode + int64_t(q) * kCollectCap;
+    const uint32_t* codes = a.ccode + int64_t(q) * cap;
     auto mark = [&](uint32_t code) {
         const uint32_t tree = code >> 24, leaf = code & 0xFFFFFFu;
         atomicOr(&a.leafbits[(int64_t(tree) * a.W + (leaf >> 5)) * a.nq + q], 1u << (leaf & 31u));
     };
+    auto clear = [&](uint32_t code) {
+        const uint32_t tree = code >> 24, leaf = code & 0xFFFFFFu;
+        atomicAnd(&a.leafbits[(int64_t(tree) * a.W + (leaf >> 5)) * a.nq + q], ~(1u << (leaf & 31u)));
+    };
+    // the query's coordinates on D for recomputing paths (the isometry
+    // variant reads each tree's reflected coordinates from qt instead)
+    for (int j = threadIdx.x; j < a.t; j += blockDim.x)
+        qd[j] = a.qt ? 0.0f : a.Q[int64_t(q) * a.ldq + a.D[j]];
+    __syncthreads();
+    auto coords = [&](uint32_t tree) -> const float* {
+        return a.qt ? a.qt + (int64_t(tree) * a.nq + q) * a.t : qd;
+    };
+    // The deeper levels for a group sharing `head` in `tree`, of which the
+    // first `left` are taken.  member(i) / store(i, v) / drop(i) access the
+    // group's slots; take_i / skip_i apply a decision to slot i.
+    auto deeper = [&](uint32_t tree, uint32_t head, uint32_t left, auto member, auto store, auto drop,
+                      auto take_i, auto skip_i) {
+        const float* cq = coords(tree);
+        for (int level = 0; level < 25; ++level) {
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+                uint64_t v;
+                if (member(i, v)) store(i, next_level_key(a, cq, tree, codes[i] & 0xFFFFFFu, head));
+            }
+            __syncthreads();
+            uint64_t kstar;
+            uint32_t l2, t2;
+            select56(cnt, left, member, hist, pub, wsum, &sh_prefix, kstar, l2, t2);
+            const bool done = l2 == t2;
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+                uint64_t v;
+                if (!member(i, v)) continue;
+                if (v < kstar || (v == kstar && done)) {
+                    take_i(i);
+                    drop(i);
+                } else if (v > kstar) {
+                    skip_i(i);
+                    drop(i);
+                }
+            }
+            __syncthreads();
+            if (done) return;
+            head = uint32_t(kstar) & 0xFFFFFFu;
+            left = l2;
+        }
+    };
     if (s.cs < 32u) {
-        const uint64_t* keys = a.ckey + int64_t(q) * kCollectCap;
+        uint64_t* keys = a.ckey + int64_t(q) * cap;
         if (threadIdx.x == 0) {
             sh_prefix = 0;
             sh_need = need;
         }
         __syncthreads();
         uint64_t kstar = ~0ull;
+        uint32_t left = 0, ties = 0;
         if (need < cnt) {
             for (int pass = 0; pass < 8; ++pass) {
                 const int shift = 56 - 8 * pass;
@@ -679,6 +835,8 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
                 __syncthreads();
                 pick_bin(hist, 0u, 8, sh_need, pub, wsum);
                 __syncthreads();
+                left = pub[1];
+                ties = pub[2];
                 if (threadIdx.x == 0) {
                     sh_need = pub[1];
                     sh_prefix = (prefix << 8) | pub[0];
@@ -687,18 +845,32 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
             }
             kstar = sh_prefix;
         }
-        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x)
-            if (keys[i] <= kstar) mark(codes[i]);
+        if (kstar == ~0ull || left == ties) {
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x)
+                if (keys[i] <= kstar) mark(codes[i]);
+            return;
+        }
+        // the group at kstar crosses the budget: decide the rest, then flag
+        // the group's slots (bit 63) and hold their deeper keys there
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+            const uint64_t K = keys[i];
+            if (K < kstar) mark(codes[i]);
+            keys[i] = (K == kstar) ? (1ull << 63) : 0ull;
+        }
+        __syncthreads();
+        constexpr uint64_t kFlag = 1ull << 63;
+        deeper(uint32_t(kstar >> 24) & 0xFFu, uint32_t(kstar) & 0xFFFFFFu, left,
+               [&](uint32_t i, uint64_t& v) { const uint64_t x = keys[i]; v = x & ~kFlag; return (x & kFlag) != 0; },
+               [&](uint32_t i, uint64_t v) { keys[i] = kFlag | v; },
+               [&](uint32_t i) { keys[i] = 0ull; },
+               [&](uint32_t i) { mark(codes[i]); },
+               [&](uint32_t) {});
         return;
     }
-    const uint32_t* effs = reinterpret_cast<const uint32_t*>(a.ckey + int64_t(q) * kCollectCap);
+    uint32_t* effs = reinterpret_cast<uint32_t*>(a.ckey + int64_t(q) * cap);
     // a premarked bin (the collect walk marked all of it) clears the keys
     // above the threshold instead of marking those up to it
     const bool pre = premark_bin(s);
-    auto clear = [&](uint32_t code) {
-        const uint32_t tree = code >> 24, leaf = code & 0xFFFFFFu;
-        atomicAnd(&a.leafbits[(int64_t(tree) * a.W + (leaf >> 5)) * a.nq + q], ~(1u << (leaf & 31u)));
-    };
     // the passes over the collected keys take kFinishUnroll keys per thread at
     // a time, their loads issued before any is used
     const uint32_t bstep = blockDim.x;
@@ -717,94 +889,110 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
             }
         return;
     }
-    uint32_t* tks = reinterpret_cast<uint32_t*>(a.ckey + int64_t(q) * kCollectCap) + kCollectCap;
-    // keys: the eff bits, from LDS where the bin fits there
-    auto resolve = [&](const uint32_t* keys) {
-        // the threshold eff: every collected key has (E >> r) == prefix at r = cs - 32
-        uint32_t cur = uint32_t(s.prefix), left = need, ties = cnt;
-        for (int r = int(s.cs) - 32; r > 0;) {
-            const int w = r < 8 ? r : 8, sh = r - w;
-            hist[threadIdx.x] = 0;
-            __syncthreads();
-            for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += kFinishUnroll * bstep) {
-                uint32_t ev[kFinishUnroll];
+    uint32_t* tks = effs + cap;
+    // the threshold M*: every collected key has (E >> r) == prefix at r = cs - 32
+    uint32_t cur = uint32_t(s.prefix), left = need, ties = cnt;
+    for (int r = int(s.cs) - 32; r > 0;) {
+        const int w = r < 8 ? r : 8, sh = r - w;
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += kFinishUnroll * bstep) {
+            uint32_t ev[kFinishUnroll];
 #pragma unroll
-                for (int u = 0; u < kFinishUnroll; ++u) {
-                    const uint32_t i = i0 + u * bstep;
-                    ev[u] = i < cnt ? keys[i] : 0u;
-                }
-#pragma unroll
-                for (int u = 0; u < kFinishUnroll; ++u)
-                    if (i0 + u * bstep < cnt && (ev[u] >> r) == cur)
-                        atomicAdd(&hist[(ev[u] >> sh) & ((1u << w) - 1u)], 1u);
+            for (int u = 0; u < kFinishUnroll; ++u) {
+                const uint32_t i = i0 + u * bstep;
+                ev[u] = i < cnt ? effs[i] : 0u;
             }
-            __syncthreads();
-            pick_bin(hist, cur, w, left, pub, wsum);
-            __syncthreads();
-            cur = pub[0];
-            left = pub[1];
-            ties = pub[2];
-            r = sh;
+#pragma unroll
+            for (int u = 0; u < kFinishUnroll; ++u)
+                if (i0 + u * bstep < cnt && (ev[u] >> r) == cur)
+                    atomicAdd(&hist[(ev[u] >> sh) & ((1u << w) - 1u)], 1u);
         }
-        const uint32_t estar = cur;
-        if (left == ties) {
-            for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += kFinishUnroll * bstep) {
-                uint32_t ev[kFinishUnroll], cv[kFinishUnroll];
+        __syncthreads();
+        pick_bin(hist, cur, w, left, pub, wsum);
+        __syncthreads();
+        cur = pub[0];
+        left = pub[1];
+        ties = pub[2];
+        r = sh;
+        __syncthreads();
+    }
+    const uint32_t estar = cur;
+    if (left == ties) {
+        for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += kFinishUnroll * bstep) {
+            uint32_t ev[kFinishUnroll], cv[kFinishUnroll];
 #pragma unroll
-                for (int u = 0; u < kFinishUnroll; ++u) {
-                    const uint32_t i = i0 + u * bstep;
-                    ev[u] = i < cnt ? keys[i] : 0u;
-                    cv[u] = i < cnt ? codes[i] : 0u;
-                }
-#pragma unroll
-                for (int u = 0; u < kFinishUnroll; ++u) {
-                    if (i0 + u * bstep >= cnt) continue;
-                    const bool take = ev[u] <= estar;
-                    if (pre && !take) clear(cv[u]);
-                    if (!pre && take) mark(cv[u]);
-                }
+            for (int u = 0; u < kFinishUnroll; ++u) {
+                const uint32_t i = i0 + u * bstep;
+                ev[u] = i < cnt ? effs[i] : 0u;
+                cv[u] = i < cnt ? codes[i] : 0u;
             }
-            return;
+#pragma unroll
+            for (int u = 0; u < kFinishUnroll; ++u) {
+                if (i0 + u * bstep >= cnt) continue;
+                const bool take = ev[u] <= estar;
+                if (pre && !take) clear(cv[u]);
+                if (!pre && take) mark(cv[u]);
+            }
         }
-        // ties at E* cross the budget: order them by (tree, entry node).  Each
-        // thread computes the tie keys of its own slots once, into the second
-        // half of the query's key area, and reads back only those.
-        for (int j = threadIdx.x; j < a.t; j += blockDim.x)
-            qd[j] = a.qt ? 0.0f : a.Q[int64_t(q) * a.ldq + a.D[j]];
+        return;
+    }
+    // leaves at M* cross the budget: order them by (tree, S1).  Each thread
+    // computes the keys of its own slots once, into the second half of the
+    // query's key area, and reads back only those.
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        if (effs[i] != estar) continue;
+        const uint32_t code = codes[i], tree = code >> 24;
+        tks[i] = (tree << 24) | head_node(a, coords(tree), tree, code & 0xFFFFFFu);
+    }
+    uint32_t tcur = 0, tties = 0;
+    for (int r = 32; r > 0;) {
+        const int sh = r - 8;
+        hist[threadIdx.x] = 0;
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-            if (keys[i] != estar) continue;
-            const uint32_t code = codes[i], tree = code >> 24;
-            const uint32_t en = a.qt ? entry_node(a, a.qt + (int64_t(tree) * a.nq + q) * a.t, tree,
-                                                  code & 0xFFFFFFu)
-                                     : entry_node(a, qd, tree, code & 0xFFFFFFu);
-            tks[i] = (tree << 24) | en;
+            if (effs[i] != estar) continue;
+            const uint32_t tk = tks[i];
+            if (r == 32 || (tk >> r) == tcur) atomicAdd(&hist[(tk >> sh) & 255u], 1u);
         }
-        uint32_t tcur = 0;
-        for (int r = 32; r > 0;) {
-            const int sh = r - 8;
-            hist[threadIdx.x] = 0;
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-                if (keys[i] != estar) continue;
-                const uint32_t tk = tks[i];
-                if (r == 32 || (tk >> r) == tcur) atomicAdd(&hist[(tk >> sh) & 255u], 1u);
-            }
-            __syncthreads();
-            pick_bin(hist, tcur, 8, left, pub, wsum);
-            __syncthreads();
-            tcur = pub[0];
-            left = pub[1];
-            r = sh;
-        }
-        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-            const uint32_t E = keys[i];
-            const bool take = E < estar || (E == estar && tks[i] <= tcur);
+        __syncthreads();
+        pick_bin(hist, tcur, 8, left, pub, wsum);
+        __syncthreads();
+        tcur = pub[0];
+        left = pub[1];
+        tties = pub[2];
+        r = sh;
+        __syncthreads();
+    }
+    const bool done = left == tties;
+    // decide every slot outside the group at (M*, tcur); flag the group's
+    // slots (bit 31 of tks) and hold their deeper keys as (effs, tks & 2^24-1)
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const uint32_t E = effs[i];
+        const uint32_t tk = (E == estar) ? tks[i] : 0u;
+        const bool grp = !done && E == estar && tk == tcur;
+        if (!grp) {
+            const bool take = E < estar || (E == estar && tk <= tcur);
             if (pre && !take) clear(codes[i]);
             if (!pre && take) mark(codes[i]);
         }
-    };
-    resolve(effs);
+        tks[i] = grp ? 0x80000000u : 0u;
+    }
+    __syncthreads();
+    if (done) return;
+    deeper(tcur >> 24, tcur & 0xFFFFFFu, left,
+           [&](uint32_t i, uint64_t& v) {
+               const uint32_t lo = tks[i];
+               v = (uint64_t(effs[i]) << 24) | (lo & 0xFFFFFFu);
+               return (lo & 0x80000000u) != 0;
+           },
+           [&](uint32_t i, uint64_t v) {
+               effs[i] = uint32_t(v >> 24);
+               tks[i] = 0x80000000u | (uint32_t(v) & 0xFFFFFFu);
+           },
+           [&](uint32_t i) { tks[i] = 0u; },
+           [&](uint32_t i) { if (!pre) mark(codes[i]); },
+           [&](uint32_t i) { if (pre) clear(codes[i]); });
 }
 
 // Each tree is walked in ranges of at most 2^15 leaves (one workgroup per

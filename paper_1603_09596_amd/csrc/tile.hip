@@ -593,11 +593,44 @@ __global__ __launch_bounds__(kMergeMax) void k_merge_rerank(MergeArgs a) {
                  a.ids, a.dists);
 }
 
-hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeArgs& m,
-                            hipStream_t st, hipEvent_t* ev) {
+// Candidate bits of the tile path, back in query-major form: bit j of word
+// w of query q is set when point 32 w + j is a candidate of q in visT (the
+// rows k_tile_bf16 masks its scores with).  Thread per (query, word).
+__global__ __launch_bounds__(256) void k_vis_to_query_bits(const uint32_t* __restrict__ visT, int nq,
+                                                           int64_t n, int cw, int64_t nbmw,
+                                                           uint32_t* __restrict__ bits) {
+    const int q = blockIdx.y;
+    const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= nq || w >= nbmw) return;
+    const int chunk = q / (32 * cw), word = (q >> 5) % cw, bit = q & 31;
+    uint32_t out = 0;
+    for (int j = 0; j < 32; ++j) {
+        const int64_t x = w * 32 + j;
+        if (x < n) out |= ((visT[(int64_t(chunk) * n + x) * cw + word] >> bit) & 1u) << j;
+    }
+    bits[int64_t(q) * nbmw + w] = out;
+}
+
+// Candidates per query: the population count of its bit row.
+__global__ __launch_bounds__(256) void k_count_bits(const uint32_t* __restrict__ bits, int64_t nbmw,
+                                                    int64_t* __restrict__ count) {
+    __shared__ int64_t part[256 / kWave];
+    const int q = blockIdx.x;
+    int64_t c = 0;
+    for (int64_t w = threadIdx.x; w < nbmw; w += blockDim.x) c += __popc(bits[int64_t(q) * nbmw + w]);
+    for (int o = kWave / 2; o > 0; o >>= 1) c += __shfl_down(c, o);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int i = 0; i < int(blockDim.x) / kWave; ++i) t += part[i];
+        count[q] = t;
+    }
+}
+
+hipError_t launch_tile_expand(const ExpandArgs& e, hipStream_t st) {
     const int64_t words = int64_t(e.m) * e.W;
-    if (e.cw < 4 || e.cw > 32 || (e.cw & (e.cw - 1)) || t.cw != e.cw) return hipErrorInvalidValue;
-    if (t.split_pts % kTP || t.split_pts * t.ld16 * 2 >= (int64_t{1} << 31)) return hipErrorInvalidValue;
+    if (e.cw < 4 || e.cw > 32 || (e.cw & (e.cw - 1))) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_open_transpose, dim3(unsigned((words + kTransposeWords - 1) / kTransposeWords),
                                               unsigned(e.nchunk)),
                        dim3(32 * e.cw), 0, st, e);
@@ -607,7 +640,29 @@ hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeA
     const int64_t per_group = int64_t(per) * kExpandRepeat;
     hipLaunchKernelGGL(k_expand_points, dim3(unsigned((e.n + per_group - 1) / per_group), unsigned(e.nchunk)),
                        dim3(256), 0, st, e);
-    err = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_trace(const ExpandArgs& e, uint32_t* cand_bits, int64_t* ncand, hipStream_t st) {
+    hipError_t err = launch_tile_expand(e, st);
+    if (err != hipSuccess) return err;
+    const int64_t nbmw = (e.n + 31) / 32;
+    hipLaunchKernelGGL(k_vis_to_query_bits, dim3(unsigned((nbmw + 255) / 256), unsigned(e.nq)), dim3(256), 0,
+                       st, static_cast<const uint32_t*>(e.visT), e.nq, e.n, e.cw, nbmw, cand_bits);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (ncand) {
+        hipLaunchKernelGGL(k_count_bits, dim3(unsigned(e.nq)), dim3(256), 0, st,
+                           static_cast<const uint32_t*>(cand_bits), nbmw, ncand);
+        err = hipGetLastError();
+    }
+    return err;
+}
+
+hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeArgs& m,
+                            hipStream_t st, hipEvent_t* ev) {
+    if (t.cw != e.cw) return hipErrorInvalidValue;
+    if (t.split_pts % kTP || t.split_pts * t.ld16 * 2 >= (int64_t{1} << 31)) return hipErrorInvalidValue;
+    hipError_t err = launch_tile_expand(e, st);
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
     dim3 grid(unsigned(((t.nq + kTQ - 1) / kTQ) * t.nsplit));   // 1-D: see the XCD mapping

@@ -24,7 +24,8 @@ VARIANT_HOUSEHOLDER = 1 << 0
 FORMS = {"fp32": FORM_FP32, "bf16": FORM_BF16, "fp8": FORM_FP8}
 
 EXPORTED = ["gf_build_forest", "gf_build_forest_ex", "gf_free_forest", "gf_forest_info", "gf_export_tree", "gf_query",
-            "gf_query_multi", "gf_multi_stats", "gf_query_trace", "gf_fp8_tables", "gf_hbm_probe",
+            "gf_query_multi", "gf_multi_stats", "gf_query_trace", "gf_query_trace_ex",
+            "gf_fp8_tables", "gf_hbm_probe",
             "gf_last_query_timing", "gf_last_error", "gf_version"]
 MULTI_AUTOTUNE, MULTI_EAGER = 1, 2
 
@@ -65,6 +66,7 @@ def load():
     lib.gf_export_tree.argtypes = [P, P, P, P, P, P]
     lib.gf_query.argtypes = [P, P, i64, i32, i32, P, f64, i32, i32, P, P, P]
     lib.gf_query_trace.argtypes = [P, P, i64, i32, P, f64, P, P, P, P]
+    lib.gf_query_trace_ex.argtypes = [P, P, i64, i32, P, f64, i32, P, P, P, P]
     lib.gf_query_multi.argtypes = [ctypes.POINTER(Job), i32, u32, P]
     lib.gf_multi_stats.argtypes = [P, P, P]
     lib.gf_fp8_tables.argtypes = [P, P, P, i32, P]
@@ -207,14 +209,20 @@ def multi_stats() -> dict:
     return dict(graphs_built=b.value, graphs_reused=r.value, tuned=t.value)
 
 
+TRACE_PATHS = {"rows": 0, "tile": 1}
+
+
 def query_trace(F: Forest, Q, checks: int, leaf_bits=None, cand_bits=None, ncand=None,
-                checks_per_query=None, eps: float = 0.0, stream=None):
-    """gf_query_trace: opened-leaf bits [nq, m, W], candidate bits [nq, ceil(n/32)],
-    candidate counts [nq]; any output may be None."""
+                checks_per_query=None, eps: float = 0.0, stream=None, path: str = "rows"):
+    """gf_query_trace_ex: opened-leaf bits [nq, m, W], candidate bits
+    [nq, ceil(n/32)], candidate counts [nq]; any output may be None.  path
+    "rows" reports the row scan's visited bitmap, "tile" the tile path's
+    per-point candidate words (forest built with bf16)."""
     nq = Q.shape[0]
     st = stream if stream is not None else _stream_of(Q, leaf_bits, cand_bits, ncand)
-    _check(load().gf_query_trace(F.handle, _ptr(Q), nq, checks, _ptr(checks_per_query),
-                                 float(eps), _ptr(leaf_bits), _ptr(cand_bits), _ptr(ncand), st))
+    _check(load().gf_query_trace_ex(F.handle, _ptr(Q), nq, checks, _ptr(checks_per_query),
+                                    float(eps), TRACE_PATHS[path], _ptr(leaf_bits), _ptr(cand_bits),
+                                    _ptr(ncand), st))
 
 
 def last_query_timing() -> dict:

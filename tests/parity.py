@@ -21,14 +21,20 @@ def ids_from_bits(bits_row: np.ndarray, n: int) -> np.ndarray:
     return np.nonzero(bits)[0]
 
 
-def check_knn(got_ids, got_d, ref_ids, ref_d64, rel=1e-5, tie=1e-6, X=None, Q=None):
+def check_knn(got_ids, got_d, ref_ids, ref_d64, rel=1e-5, tie=1e-6, X=None, Q=None, cand=None):
     """The acceptance rule for neighbours: let dk be the oracle's k-th FP64
     distance; every oracle id with distance < dk(1 - tie) must be returned,
     every returned id's true distance must be <= dk(1 + tie), returned
     distances must be within `rel` of the oracle's (relative), and padding
-    must agree.  Returns the number of queries checked."""
+    must agree.  With cand (the oracle's candidate set of each query, sorted
+    ids) every returned id must also be one of the query's candidates.
+    Returns the number of queries checked."""
     nq, k = ref_ids.shape
     for i in range(nq):
+        if cand is not None:
+            got_all = got_ids[i][got_ids[i] >= 0]
+            inside = np.isin(got_all, cand[i])
+            assert inside.all(), f"query {i}: ids {got_all[~inside].tolist()} are not candidates"
         valid = ref_ids[i] >= 0
         assert np.array_equal(got_ids[i] >= 0, valid), f"query {i}: padding differs"
         if not valid.any():

@@ -111,3 +111,20 @@ def test_query_multi_rejects_bad_arguments_before_hip(lib):
     assert b"forest" in lib.gf_last_error()
     b, r, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     assert lib.gf_multi_stats(ctypes.byref(b), ctypes.byref(r), ctypes.byref(t)) == geraf.GF_OK
+
+
+def test_build_refuses_a_near_tie_in_D_before_hip(lib):
+    """Columns 2 and 3 hold the same values: their variances are equal, so
+    the top-3 set is not determined by the data (the oracle refuses the same
+    input)."""
+    rng = np.random.default_rng(44)
+    X = rng.standard_normal((500, 6)).astype(np.float32)
+    X[:, 0] *= 3.0
+    X[:, 1] *= 2.0
+    X[:, 2] *= 1.5
+    X[:, 3] = X[:, 2]
+    out = ctypes.c_void_p()
+    p = X.ctypes.data_as(ctypes.c_void_p)
+    assert lib.gf_build_forest(p, 500, 6, 2, 3, 8, 1, 0, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert b"near-tie" in lib.gf_last_error()
+    assert not out.value

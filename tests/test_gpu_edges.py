@@ -70,7 +70,7 @@ def test_edge_shape_fp32(name):
         ids = np.zeros((nq, k), np.int32)
         dd = np.zeros((nq, k), np.float32)
         geraf.query(Fg, Q, k, c, ids, dd)
-        check_knn(ids, dd, ref["ids"], ref["dists"], X=X, Q=Q)
+        check_knn(ids, dd, ref["ids"], ref["dists"], X=X, Q=Q, cand=ref["cand"])
     finally:
         Fg.free()
 

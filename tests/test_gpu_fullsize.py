@@ -54,6 +54,14 @@ def run_case(w, c, form, sample, forms):
         assert leaf_set_from_bits(lb[j]) == set(ref["opened"][j].tolist()), f"query {idx[j]}"
         assert np.array_equal(ids_from_bits(cb[j], Fg.n), ref["cand"][j]), f"query {idx[j]}"
     assert np.array_equal(nc, ref["ncand"])
+    if "bf16" in forms:
+        # the tile path's own candidate words for the same sample
+        cbt = np.zeros_like(cb)
+        nct = np.zeros_like(nc)
+        geraf.query_trace(Fg, Qs, c, cand_bits=cbt, ncand=nct, path="tile")
+        for j in range(len(idx)):
+            assert np.array_equal(ids_from_bits(cbt[j], Fg.n), ref["cand"][j]), f"tile, query {idx[j]}"
+        assert np.array_equal(nct, ref["ncand"])
     Fg.free()
     return ids[idx], dd[idx], ref, Qs, timing
 
@@ -62,6 +70,7 @@ def check_reduced(w, ids, dd, ref, Qs, floor):
     hits = 0
     for j in range(len(Qs)):
         got = ids[j][ids[j] >= 0]
+        assert np.isin(got, ref["cand"][j]).all(), f"query {j}: a returned id is not a candidate"
         for r, gid in enumerate(got.tolist()):
             diff = w.X[gid].astype(np.float64) - Qs[j].astype(np.float64)
             true_d = float(diff @ diff)
@@ -83,13 +92,13 @@ def test_desc_1m_960_bench_configuration():
 def test_desc_1m_960_fp32_form():
     w = W.make("desc-1m-960", nq=2000)
     ids, dd, ref, Qs, _ = run_case(w, 16384, "fp32", 12, ())
-    check_knn(ids, dd, ref["ids"], ref["dists"], X=w.X, Q=Qs)
+    check_knn(ids, dd, ref["ids"], ref["dists"], X=w.X, Q=Qs, cand=ref["cand"])
 
 
 def test_sphere_100k_1000_full():
     w = W.make("sphere-100k-1000")
     ids, dd, ref, Qs, _ = run_case(w, w.c, "fp32", 24, ())
-    check_knn(ids, dd, ref["ids"], ref["dists"], X=w.X, Q=Qs)
+    check_knn(ids, dd, ref["ids"], ref["dists"], X=w.X, Q=Qs, cand=ref["cand"])
 
 
 def test_gauss_200k_10000_fp8_full():

@@ -61,7 +61,7 @@ def test_reflected_forest_bit_exact(name, k, c):
     ids = np.zeros((nq, k), np.int32)
     dd = np.zeros((nq, k), np.float32)
     geraf.query(Fg, Q, k, c, ids, dd)
-    check_knn(ids, dd, ref["ids"], ref["dists"], X=X, Q=Q)
+    check_knn(ids, dd, ref["ids"], ref["dists"], X=X, Q=Q, cand=ref["cand"])
 
 
 def test_reflected_forest_tile_path(monkeypatch):

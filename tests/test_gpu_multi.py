@@ -139,19 +139,64 @@ def test_multi_graph_replays_match_eager(indexes):
     assert after["graphs_built"] == before["graphs_built"]
 
 
-def test_multi_fp32_job_against_oracle(indexes):
-    e = indexes[0]
-    assert e["form"] == "fp32"
-    w = e["w"]
+def test_multi_every_job_against_oracle(indexes):
+    """Every job of one graph launch against the FP64 oracle on a sample of
+    its queries (each with its own budget): FP32 jobs by the acceptance rule,
+    BF16 / FP8 jobs by exact returned distances and recall; in every form a
+    returned id must be one of the query's candidates."""
     jobs = jobs_of(indexes)
     geraf.query_multi(jobs)
-    Fo = oracle.build_forest(w.X, w.m, w.t, w.p, w.seed)
-    got_i, got_d = jobs[0]["ids"].cpu().numpy(), jobs[0]["dists"].cpu().numpy()
-    for c in np.unique(w.checks):   # the oracle takes one budget per call
-        sel = np.nonzero(w.checks == c)[0]
-        Qs = np.ascontiguousarray(w.Q[sel])
-        ref = oracle.search(Fo, w.X, Qs, w.k, int(c), trace=False)
-        check_knn(got_i[sel], got_d[sel], ref["ids"], ref["dists"], X=w.X, Q=Qs)
+    torch.cuda.synchronize()
+    for e, j in zip(indexes, jobs):
+        w = e["w"]
+        Fo = oracle.build_forest(w.X, w.m, w.t, w.p, w.seed)
+        got_i, got_d = j["ids"].cpu().numpy(), j["dists"].cpu().numpy()
+        sample = np.linspace(0, len(w.Q) - 1, min(len(w.Q), 24)).astype(np.int64)
+        hits = total = 0
+        for i in sample:
+            Qs = np.ascontiguousarray(w.Q[i:i + 1])
+            ref = oracle.search(Fo, w.X, Qs, w.k, int(w.checks[i]), trace=False, candidates=True)
+            if e["form"] == "fp32":
+                check_knn(got_i[i:i + 1], got_d[i:i + 1], ref["ids"], ref["dists"], X=w.X, Q=Qs,
+                          cand=ref["cand"])
+                continue
+            got = got_i[i][got_i[i] >= 0]
+            assert np.isin(got, ref["cand"][0]).all(), (w.name, int(i))
+            for r, gid in enumerate(got.tolist()):
+                diff = w.X[gid].astype(np.float64) - Qs[0].astype(np.float64)
+                true_d = float(diff @ diff)
+                assert abs(got_d[i][r] - true_d) <= 1e-5 * true_d, (w.name, int(i))
+            hits += len(set(got.tolist()) & set(ref["ids"][0][ref["ids"][0] >= 0].tolist()))
+            total += int((ref["ids"][0] >= 0).sum())
+        if total:
+            print(f"{w.name} {e['form']}: recall vs FP64 oracle {hits / total:.4f}")
+            assert hits / total >= 0.95, w.name
+
+
+def test_multi_graph_64_replays_with_radix_passes():
+    """A budget of 37 leaves on quantised data sends queries through radix
+    passes (and their list of queries) in every replay.  64 launches of the
+    cached graph with nothing between them must all equal the eager call."""
+    rng = np.random.default_rng(5)
+    X = rng.integers(0, 8, (5000, 40)).astype(np.float32)
+    Q = (X[rng.integers(0, 5000, 60)] + rng.integers(-1, 2, (60, 40))).astype(np.float32)
+    F = geraf.build_forest(X, 4, 6, 8, 1234 + len("quantised"))
+    try:
+        e = dict(w=W.Workload("quantised", X, Q, np.arange(60), m=4, t=6, p=8, c=37, k=5,
+                              seed=0, checks=np.full(60, 37, np.int32)),
+                 F=F, form="fp32", checks=np.full(60, 37, np.int32), scalar=37)
+        r = single(e)
+        jobs = jobs_of([e])
+        geraf.query_multi(jobs)
+        torch.cuda.synchronize()
+        for rep in range(64):
+            jobs[0]["ids"].fill_(-3)
+            jobs[0]["dists"].fill_(-3.0)
+            geraf.query_multi(jobs)
+            assert np.array_equal(jobs[0]["ids"].cpu().numpy(), r[0]), rep
+            assert np.array_equal(jobs[0]["dists"].cpu().numpy(), r[1]), rep
+    finally:
+        F.free()
 
 
 def test_multi_autotune_matches_a_path(indexes, monkeypatch):

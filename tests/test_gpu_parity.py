@@ -74,8 +74,28 @@ def case_data(name):
         X = (rng.random((40_000, 8)) < prob).astype(np.float32)
         Q = np.full((6, 8), 0.5, np.float32)
         return X, Q, 2, 4, 1
+    if name == "quant-h16":
+        # integers 0..3, queries at half-integers: gaps take few values, so
+        # more than 32,768 leaves share the chain maximum at the threshold
+        # (bins narrowed into the (tree, head) bits) and groups of hundreds
+        # of leaves under one head cross the budget (deeper levels)
+        rng = np.random.default_rng(8)
+        X = rng.integers(0, 4, (65536, 8)).astype(np.float32)
+        Q = (X[rng.integers(0, 65536, 24)] + rng.integers(-1, 2, (24, 8)) + 0.5).astype(np.float32)
+        return X, Q, 2, 4, 1
+    if name == "deep-h17":
+        # depth 17; one coordinate spans 1000x the others, so for query 4
+        # a single group of 37,040 leaves under one head (more than the
+        # 32,768-key resolution bin) crosses a budget of 60,000
+        rng = np.random.default_rng(5)
+        X = rng.standard_normal((1 << 17, 32)).astype(np.float32)
+        X[:, 0] *= 1000
+        Q = (X[rng.integers(0, 1 << 17, 6)] + 0.05 * rng.standard_normal((6, 32))).astype(np.float32)
+        return X, Q, 1, 32, 1
     raise KeyError(name)
 
+
+SEEDS = {"deep-h17": 0, "quant-h16": 3}
 
 _cache = {}
 
@@ -84,7 +104,7 @@ def forests(name, forms=()):
     key = (name, tuple(forms))
     if key not in _cache:
         X, Q, m, t, p = case_data(name)
-        seed = 1234 + len(name)
+        seed = SEEDS.get(name, 1234 + len(name))
         Fg = geraf.build_forest(dev(X), m, t, p, seed, forms=forms)
         Fo = oracle.build_forest(X, m, t, p, seed)
         _cache[key] = (X, Q, Fg, Fo, seed)
@@ -112,6 +132,12 @@ CASES = [  # (name, k, c, eps)
     ("scales", 10, 200, 0.0),
     ("scales", 10, 900, 0.0),
     ("binary-ties", 3, 50_000, 0.0),
+    # Alg. 2's order inside groups of equal chain maximum: full-key bins
+    # whose threshold group crosses the budget, and a group larger than the
+    # default resolution bin at depth 17
+    ("quant-h16", 5, 20_000, 0.0),
+    ("quant-h16", 5, 60_000, 0.0),
+    ("deep-h17", 5, 60_000, 0.0),
 ]
 
 
@@ -144,15 +170,39 @@ def test_opened_leaves_and_candidates_bit_exact(name, k, c, eps):
     assert np.array_equal(nc, ref["ncand"])
 
 
+@pytest.mark.parametrize("name,c", [("desc-60k-960", 4096), ("gauss-10k-128", 700),
+                                    ("sphere-20k-1000", 1024), ("ragged-3001-77", 300),
+                                    ("quantised", 37), ("scales", 200), ("quant-h16", 20_000)])
+def test_tile_path_candidates_bit_exact(name, c):
+    """The per-point candidate words the MFMA tile kernel masks its scores
+    with, turned back into per-query rows: bit-equal to the oracle's
+    candidate sets (the visited array of Sec. 2.3)."""
+    X, Q, Fg, Fo, _ = forests(name, forms=("bf16",))
+    ref = oracle.search(Fo, X, Q, 1, c, trace=False, candidates=True)
+    nq = len(Q)
+    cb = np.zeros((nq, (Fg.n + 31) // 32), np.uint32)
+    nc = np.zeros(nq, np.int64)
+    lb = np.zeros((nq, Fg.m, Fg.leaf_words), np.uint32)
+    geraf.query_trace(Fg, Q, c, leaf_bits=lb, cand_bits=cb, ncand=nc, path="tile")
+    for i in range(nq):
+        assert np.array_equal(ids_from_bits(cb[i], Fg.n), ref["cand"][i]), f"query {i}"
+    assert np.array_equal(nc, ref["ncand"])
+    # the same selection as the row path's trace
+    lb_rows = np.zeros_like(lb)
+    geraf.query_trace(Fg, Q, c, leaf_bits=lb_rows)
+    assert np.array_equal(lb, lb_rows)
+
+
 @pytest.mark.parametrize("name,k,c,eps", CASES)
 def test_fp32_neighbours(name, k, c, eps):
     X, Q, Fg, Fo, _ = forests(name)
-    ref = oracle.search(Fo, X, Q, k, c, eps=eps, trace=False)
+    ref = oracle.search(Fo, X, Q, k, c, eps=eps, trace=False, candidates=True)
     ids = torch.full((len(Q), k), -7, dtype=torch.int32, device="cuda:0")
     dd = torch.full((len(Q), k), -7.0, dtype=torch.float32, device="cuda:0")
     geraf.query(Fg, dev(Q), k, c, ids, dd, eps=eps)
     torch.cuda.synchronize()
-    check_knn(ids.cpu().numpy(), dd.cpu().numpy(), ref["ids"], ref["dists"], X=X, Q=Q)
+    check_knn(ids.cpu().numpy(), dd.cpu().numpy(), ref["ids"], ref["dists"], X=X, Q=Q,
+              cand=ref["cand"])
 
 
 def test_host_buffers_match_device_buffers():
@@ -260,13 +310,14 @@ def test_reduced_precision_forms(name, form, k, c):
     exact (1e-5), and the result agrees with the oracle's top-k (recall
     stated; the floor below is what these seeded cases reach)."""
     X, Q, Fg, Fo, _ = forests(name, forms=(form,))
-    ref = oracle.search(Fo, X, Q, k, c, trace=False)
+    ref = oracle.search(Fo, X, Q, k, c, trace=False, candidates=True)
     ids = np.zeros((len(Q), k), np.int32)
     dd = np.zeros((len(Q), k), np.float32)
     geraf.query(Fg, Q, k, c, ids, dd, form=form)
     hits = 0
     for i in range(len(Q)):
         got = ids[i][ids[i] >= 0]
+        assert np.isin(got, ref["cand"][i]).all(), f"query {i}: a returned id is not a candidate"
         for j, gid in enumerate(got.tolist()):
             diff = X[gid].astype(np.float64) - Q[i].astype(np.float64)
             true_d = float(diff @ diff)
@@ -356,7 +407,7 @@ def test_tile_path_bf16(name, k, c, nq, scan_path):
         X, Q, Fg, Fo, _ = _cache[key]
     else:
         X, Q, Fg, Fo, _ = forests(name, forms=("bf16",))
-    ref = oracle.search(Fo, X, Q, k, c, trace=False)
+    ref = oracle.search(Fo, X, Q, k, c, trace=False, candidates=True)
     out = {}
     for path in ("tile", "rows"):
         scan_path(path)
@@ -368,6 +419,7 @@ def test_tile_path_bf16(name, k, c, nq, scan_path):
     hits, agree = 0, 0
     for i in range(len(Q)):
         got = ids[i][ids[i] >= 0]
+        assert np.isin(got, ref["cand"][i]).all(), f"query {i}: a returned id is not a candidate"
         for j, gid in enumerate(got.tolist()):
             diff = X[gid].astype(np.float64) - Q[i].astype(np.float64)
             true_d = float(diff @ diff)

@@ -63,4 +63,4 @@ def test_sweep_grid_bit_exact(p, eps):
     ids = np.zeros((nq, 1), np.int32)
     dd = np.zeros((nq, 1), np.float32)
     geraf.query(Fg, Q, 1, c, ids, dd, eps=eps)
-    check_knn(ids, dd, ref["ids"], ref["dists"], X=X, Q=Q)
+    check_knn(ids, dd, ref["ids"], ref["dists"], X=X, Q=Q, cand=ref["cand"])
