@@ -202,6 +202,28 @@ typedef struct gf_job {
  * for HIP failures (nothing partially written is guaranteed then). */
 gf_status gf_query_multi(const gf_job *jobs, int32_t njobs, uint32_t flags, void *stream);
 
+/* gf_query for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and results as gf_query on its row path (GF_SCAN_PATH=rows), but
+ * the call allocates nothing: no hipMalloc / hipFree, no events, no pinned
+ * staging.  Its workspace is a static device array of 128 MiB, one copy per
+ * GPU, held until the process ends; queries run in batches sized to fit it.
+ *   Q, checks_per_query, ids, dists  device buffers only (GF_EINVAL for host
+ *                    memory); device budgets are used as given (a budget
+ *                    below 1 opens no leaf), not read back.
+ *   GF_EUNSUPPORTED  when one query's workspace exceeds 128 MiB (very deep
+ *                    or very many trees), or the device index is above 63.
+ * Calls on one GPU share that array: the library runs them one at a time
+ * (a lock per device), and each returns after its work has finished, so
+ * they cannot overlap from one process; kernels that a caller enqueues on
+ * its own into that memory would race.  Every call rewrites what it reads,
+ * nothing is assumed zero from an earlier call.  gf_last_query_timing is
+ * not updated by this call. */
+gf_status gf_query_noalloc(const gf_forest *F, const float *Q, int64_t nq, int32_t k,
+                           int32_t checks, const int32_t *checks_per_query, double eps,
+                           int32_t form, int32_t rerank, int32_t *ids, float *dists,
+                           void *stream);
+
 /* Counters of the multi-index launch since the library was loaded: graphs
  * captured, graph launches reused from an earlier identical call, path
  * choices measured by the autotuner.  Any pointer may be NULL. */

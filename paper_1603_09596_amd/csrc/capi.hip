@@ -229,72 +229,88 @@ TilePlan tile_plan(const gf_forest* F, int nb) {
     return p;
 }
 
-gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Workspace& w) {
+// Offsets of a batch's workspace (nb queries, bytes from a 256-aligned base).
+struct WsLayout {
+    size_t oQp = 0, oQ16 = 0, oQ8 = 0, oqs = 0, oqn = 0, ocpq = 0, ost = 0, ohist = 0, onc = 0;
+    size_t ock = 0, occ = 0, olb = 0, ofl = 0, oql = 0, oids = 0, odst = 0, oqt = 0;
+    size_t oopen = 0, ovis = 0, othr = 0, ops = 0, opi = 0;
+    size_t need = 0;   // bytes
+};
+
+WsLayout ws_layout(const gf_forest* F, int nb, int k, int form, bool tile) {
     const int64_t W = std::max<int64_t>(1, (int64_t{1} << F->host.H) / 32);
     Carve c;
-    size_t oQp = c.take<float>(size_t(nb) * F->ld32);
-    size_t oQ16 = form == gf::kFormBF16 ? c.take<uint16_t>(size_t(nb) * F->ld16) : 0;
-    size_t oQ8 = form == gf::kFormFP8 ? c.take<uint8_t>(size_t(nb) * F->ld8) : 0;
-    size_t oqs = c.take<float>(nb);
-    size_t oqn = c.take<float>(nb);
-    size_t ocpq = c.take<int32_t>(nb);
-    size_t ost = c.take<gf::SelState>(nb);
+    WsLayout L;
+    L.oQp = c.take<float>(size_t(nb) * F->ld32);
+    L.oQ16 = form == gf::kFormBF16 ? c.take<uint16_t>(size_t(nb) * F->ld16) : 0;
+    L.oQ8 = form == gf::kFormFP8 ? c.take<uint8_t>(size_t(nb) * F->ld8) : 0;
+    L.oqs = c.take<float>(nb);
+    L.oqn = c.take<float>(nb);
+    L.ocpq = c.take<int32_t>(nb);
+    L.ost = c.take<gf::SelState>(nb);
     const int nslice = F->host.m * gf::select_slices_per_tree(F->host.H);
-    size_t ohist = c.take<uint32_t>(size_t(nb) * nslice * 128);
-    size_t onc = c.take<uint32_t>(size_t(nb) * nslice);
+    L.ohist = c.take<uint32_t>(size_t(nb) * nslice * 128);
+    L.onc = c.take<uint32_t>(size_t(nb) * nslice);
     const int64_t ccap = gf::collect_capacity(F->host.H);
-    size_t ock = c.take<uint64_t>(size_t(nb) * ccap);
-    size_t occ = c.take<uint32_t>(size_t(nb) * ccap);
-    size_t olb = c.take<uint32_t>(size_t(nb) * F->host.m * W);
-    size_t ofl = c.take<uint32_t>(8);
-    size_t oql = c.take<uint32_t>(nb);
-    size_t oids = c.take<int32_t>(size_t(nb) * k);
-    size_t odst = c.take<float>(size_t(nb) * k);
-    size_t oqt = F->U ? c.take<float>(size_t(nb) * F->host.m * F->host.t) : 0;
-    size_t oopen = 0, ovis = 0, othr = 0, ops = 0, opi = 0;
+    L.ock = c.take<uint64_t>(size_t(nb) * ccap);
+    L.occ = c.take<uint32_t>(size_t(nb) * ccap);
+    L.olb = c.take<uint32_t>(size_t(nb) * F->host.m * W);
+    L.ofl = c.take<uint32_t>(8);
+    L.oql = c.take<uint32_t>(nb);
+    L.oids = c.take<int32_t>(size_t(nb) * k);
+    L.odst = c.take<float>(size_t(nb) * k);
+    L.oqt = F->U ? c.take<float>(size_t(nb) * F->host.m * F->host.t) : 0;
     if (tile) {
         const TilePlan tp = tile_plan(F, nb);
-        oopen = c.take<uint32_t>(size_t(tp.nchunk) * F->host.m * (size_t{1} << F->host.H) * tp.cw);
-        ovis = c.take<uint32_t>(size_t(tp.nchunk) * F->host.n * tp.cw);
-        othr = c.take<uint32_t>(nb);
-        ops = c.take<float>(size_t(nb) * tp.nsplit * gf::kTileList);
-        opi = c.take<int>(size_t(nb) * tp.nsplit * gf::kTileList);
+        L.oopen = c.take<uint32_t>(size_t(tp.nchunk) * F->host.m * (size_t{1} << F->host.H) * tp.cw);
+        L.ovis = c.take<uint32_t>(size_t(tp.nchunk) * F->host.n * tp.cw);
+        L.othr = c.take<uint32_t>(nb);
+        L.ops = c.take<float>(size_t(nb) * tp.nsplit * gf::kTileList);
+        L.opi = c.take<int>(size_t(nb) * tp.nsplit * gf::kTileList);
     }
-    size_t need = c.off + 256;
-    if (need > F->ws_bytes) {
+    L.need = c.off + 256;
+    return L;
+}
+
+void ws_bind(const gf_forest* F, const WsLayout& L, char* b, int form, bool tile, Workspace& w) {
+    w.Qp = reinterpret_cast<float*>(b + L.oQp);
+    w.Q16 = form == gf::kFormBF16 ? reinterpret_cast<uint16_t*>(b + L.oQ16) : nullptr;
+    w.Q8 = form == gf::kFormFP8 ? reinterpret_cast<uint8_t*>(b + L.oQ8) : nullptr;
+    w.qscale = reinterpret_cast<float*>(b + L.oqs);
+    w.qnorm = reinterpret_cast<float*>(b + L.oqn);
+    w.cpq = reinterpret_cast<int32_t*>(b + L.ocpq);
+    w.state = reinterpret_cast<gf::SelState*>(b + L.ost);
+    w.hist = reinterpret_cast<uint32_t*>(b + L.ohist);
+    w.coff = reinterpret_cast<uint32_t*>(b + L.onc);
+    w.ckey = reinterpret_cast<uint64_t*>(b + L.ock);
+    w.ccode = reinterpret_cast<uint32_t*>(b + L.occ);
+    w.leafbits = reinterpret_cast<uint32_t*>(b + L.olb);
+    w.flags = reinterpret_cast<uint32_t*>(b + L.ofl);
+    w.qlist = reinterpret_cast<uint32_t*>(b + L.oql);
+    w.ids = reinterpret_cast<int32_t*>(b + L.oids);
+    w.dists = reinterpret_cast<float*>(b + L.odst);
+    w.qt = F->U ? reinterpret_cast<float*>(b + L.oqt) : nullptr;
+    w.openT = tile ? reinterpret_cast<uint32_t*>(b + L.oopen) : nullptr;
+    w.visT = tile ? reinterpret_cast<uint32_t*>(b + L.ovis) : nullptr;
+    w.gthr = tile ? reinterpret_cast<uint32_t*>(b + L.othr) : nullptr;
+    w.part_s = tile ? reinterpret_cast<float*>(b + L.ops) : nullptr;
+    w.part_i = tile ? reinterpret_cast<int*>(b + L.opi) : nullptr;
+}
+
+gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Workspace& w) {
+    const WsLayout L = ws_layout(F, nb, k, form, tile);
+    if (L.need > F->ws_bytes) {
         if (F->ws) (void)hipFree(F->ws);
         F->ws = nullptr;
         F->ws_bytes = 0;
-        if (hipMalloc(&F->ws, need) != hipSuccess) {
+        if (hipMalloc(&F->ws, L.need) != hipSuccess) {
             (void)hipGetLastError();
-            return fail(GF_ENOMEM, "device workspace allocation of " + std::to_string(need) +
+            return fail(GF_ENOMEM, "device workspace allocation of " + std::to_string(L.need) +
                                        " bytes failed");
         }
-        F->ws_bytes = need;
+        F->ws_bytes = L.need;
     }
-    char* b = static_cast<char*>(F->ws);
-    w.Qp = reinterpret_cast<float*>(b + oQp);
-    w.Q16 = form == gf::kFormBF16 ? reinterpret_cast<uint16_t*>(b + oQ16) : nullptr;
-    w.Q8 = form == gf::kFormFP8 ? reinterpret_cast<uint8_t*>(b + oQ8) : nullptr;
-    w.qscale = reinterpret_cast<float*>(b + oqs);
-    w.qnorm = reinterpret_cast<float*>(b + oqn);
-    w.cpq = reinterpret_cast<int32_t*>(b + ocpq);
-    w.state = reinterpret_cast<gf::SelState*>(b + ost);
-    w.hist = reinterpret_cast<uint32_t*>(b + ohist);
-    w.coff = reinterpret_cast<uint32_t*>(b + onc);
-    w.ckey = reinterpret_cast<uint64_t*>(b + ock);
-    w.ccode = reinterpret_cast<uint32_t*>(b + occ);
-    w.leafbits = reinterpret_cast<uint32_t*>(b + olb);
-    w.flags = reinterpret_cast<uint32_t*>(b + ofl);
-    w.qlist = reinterpret_cast<uint32_t*>(b + oql);
-    w.ids = reinterpret_cast<int32_t*>(b + oids);
-    w.dists = reinterpret_cast<float*>(b + odst);
-    w.qt = F->U ? reinterpret_cast<float*>(b + oqt) : nullptr;
-    w.openT = tile ? reinterpret_cast<uint32_t*>(b + oopen) : nullptr;
-    w.visT = tile ? reinterpret_cast<uint32_t*>(b + ovis) : nullptr;
-    w.gthr = tile ? reinterpret_cast<uint32_t*>(b + othr) : nullptr;
-    w.part_s = tile ? reinterpret_cast<float*>(b + ops) : nullptr;
-    w.part_i = tile ? reinterpret_cast<int*>(b + opi) : nullptr;
+    ws_bind(F, L, static_cast<char*>(F->ws), form, tile, w);
     return GF_OK;
 }
 
@@ -508,20 +524,32 @@ gf_status run_batch_graph(gf_forest* F, const QueryJob& J, int64_t q0, int nb, h
 }
 
 // Runs the whole query path for queries [q0, q0 + nb); graph mode as above.
+// With `scratch` (device memory the caller sized with ws_layout for the row
+// path) the batch allocates nothing: no workspace growth, no staging, no
+// events; Q, budgets and outputs are then device buffers.
 gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStream_t st,
-                    bool graph = false) {
+                    bool graph = false, char* scratch = nullptr) {
     const gf::HostForest& h = F->host;
     Workspace w;
-    const bool tile = J.trace_tile || use_tile_path(F, J, nb);
-    gf_status s = get_workspace(F, nb, J.k, J.form, tile, w);
-    if (s != GF_OK) return s;
+    const bool tile = !scratch && (J.trace_tile || use_tile_path(F, J, nb));
+    if (scratch) {
+        ws_bind(F, ws_layout(F, nb, J.k, J.form, false), scratch, J.form, false, w);
+    } else {
+        gf_status s0 = get_workspace(F, nb, J.k, J.form, tile, w);
+        if (s0 != GF_OK) return s0;
+    }
+    gf_status s = GF_OK;
     const int64_t W = std::max<int64_t>(1, (int64_t{1} << h.H) / 32);
     if (graph) return run_batch_graph(F, J, q0, nb, st, w, tile, W);
 
-    hipEvent_t ev[6];
-    for (auto& e : ev) GF_HIP(hipEventCreate(&e));
-    struct EvGuard { hipEvent_t* e; ~EvGuard() { for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]); } } evg{ev};
-    GF_HIP(hipEventRecord(ev[0], st));
+    // phase marks (none in the allocation-free mode)
+    hipEvent_t ev[6] = {};
+    const bool timed = scratch == nullptr;
+    struct EvGuard { hipEvent_t* e; ~EvGuard() { for (int i = 0; i < 6; ++i) if (e[i]) (void)hipEventDestroy(e[i]); } } evg{ev};
+    if (timed)
+        for (auto& e : ev) GF_HIP(hipEventCreate(&e));
+    auto mark_phase = [&](int i) -> hipError_t { return timed ? hipEventRecord(ev[i], st) : hipSuccess; };
+    GF_HIP(mark_phase(0));
     // a1: query prep -- padded FP32 rows, finiteness, reduced copies
     if (J.q_dev) {
         GF_HIP(hipMemsetAsync(w.Qp, 0, size_t(nb) * F->ld32 * 4, st));
@@ -552,7 +580,7 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     if (bad) return fail(GF_EINVAL, "Q contains a non-finite value");
 
     // a2: leaf selection
-    GF_HIP(hipEventRecord(ev[1], st));
+    GF_HIP(mark_phase(1));
     s = launch_selection(F, J, nb, w, W, cpq, true, st);
     if (s != GF_OK) return s;
 
@@ -575,24 +603,24 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
         tmp_nc.reset(p);
         ca.ncand = p;
     }
-    GF_HIP(hipEventRecord(ev[2], st));
+    GF_HIP(mark_phase(2));
     if (J.trace_tile) {
         // the tile path's own candidate words, turned back into query rows
         if (ca.cand_bits)
             GF_HIP(gf::launch_tile_trace(make_expand_args(F, nb, w, W), ca.cand_bits, ca.ncand, st));
         else
             GF_HIP(gf::launch_tile_expand(make_expand_args(F, nb, w, W), st));
-        GF_HIP(hipEventRecord(ev[3], st));
-        GF_HIP(hipEventRecord(ev[4], st));
+        GF_HIP(mark_phase(3));
+        GF_HIP(mark_phase(4));
     } else if (tile) {
-        s = launch_tile(F, J, nb, w, W, ca, st, ev + 3);
+        s = launch_tile(F, J, nb, w, W, ca, st, timed ? ev + 3 : nullptr);
         if (s != GF_OK) return s;
     } else {
         GF_HIP(gf::launch_scan(ca, J.form, st));
-        GF_HIP(hipEventRecord(ev[3], st));
-        GF_HIP(hipEventRecord(ev[4], st));
+        GF_HIP(mark_phase(3));
+        GF_HIP(mark_phase(4));
     }
-    GF_HIP(hipEventRecord(ev[5], st));
+    GF_HIP(mark_phase(5));
 
     // outputs
     if (J.ids && !J.out_dev)
@@ -625,7 +653,7 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
         }
     }
     GF_HIP(hipStreamSynchronize(st));
-    for (int i = 0; i < kPhases; ++i) {
+    for (int i = 0; timed && i < kPhases; ++i) {
         float ms = 0.0f;
         GF_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
         g_phase_ms[i] += ms;
@@ -661,9 +689,11 @@ gf_status validate_query_common(const gf_forest* F, const float* Q, int64_t nq, 
 
 // Validation and setup shared by gf_query and gf_query_multi: parameters
 // first (no HIP call), then where each buffer lives.
+// With noalloc (gf_query_noalloc) every buffer must be device memory and
+// device budgets are used as they are (not read back).
 gf_status prepare_job(const gf_forest* Fc, const float* Q, int64_t nq, int32_t k, int32_t checks,
                       const int32_t* checks_per_query, double eps, int32_t form, int32_t rerank,
-                      int32_t* ids, float* dists, QueryJob& J) {
+                      int32_t* ids, float* dists, QueryJob& J, bool noalloc = false) {
     gf_status s = validate_query_common(Fc, Q, nq, checks, checks_per_query, eps);
     if (s != GF_OK) return s;
     if (k < 1 || k > gf::kMaxK) return fail(GF_EINVAL, "k must be in [1, 64]");
@@ -690,6 +720,12 @@ gf_status prepare_job(const gf_forest* Fc, const float* Q, int64_t nq, int32_t k
     J.Q = Q; J.q_dev = is_device_ptr(Q);
     J.cpq = checks_per_query; J.cpq_dev = checks_per_query && is_device_ptr(checks_per_query);
     J.checks_mean = double(checks);
+    if (noalloc) {
+        if (!J.q_dev || !is_device_ptr(ids) || !is_device_ptr(dists) || (checks_per_query && !J.cpq_dev))
+            return fail(GF_EINVAL, "gf_query_noalloc takes device buffers for Q, budgets and outputs");
+        J.out_dev = true;
+        return GF_OK;
+    }
     if (checks_per_query) {
         // every budget >= 1, and their mean for the path rule (device
         // budgets are read back once here)
@@ -1006,9 +1042,71 @@ __global__ __launch_bounds__(256) void k_read_probe(const uint4* __restrict__ p,
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free queries
+// The workspace of gf_query_noalloc: one file-scope device array, a copy on
+// every GPU the library runs on, held until the process ends.  In host code
+// its name is only a stand-in: the device address of each GPU's copy comes
+// from hipGetSymbolAddress, taken once per device with that device current
+// (scratch_base), and only that address is handed to kernels and copies.
+constexpr size_t kNoAllocScratchBytes = size_t{128} << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;                  // guards g_scratch_ptr
+char* g_scratch_ptr[kMaxDevices] = {};       // device address of each GPU's copy
+std::mutex g_scratch_call[kMaxDevices];      // one call at a time per GPU
+
+// Device address of the current device's copy of `scratch` (dev current).
+gf_status scratch_base(int dev, char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(GF_EUNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GF_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return GF_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* gf_last_error(void) { return g_last_error.c_str(); }
+
+gf_status gf_query_noalloc(const gf_forest* Fc, const float* Q, int64_t nq, int32_t k,
+                           int32_t checks, const int32_t* checks_per_query, double eps,
+                           int32_t form, int32_t rerank, int32_t* ids, float* dists, void* stream) {
+    QueryJob J{};
+    gf_status s = prepare_job(Fc, Q, nq, k, checks, checks_per_query, eps, form, rerank, ids, dists,
+                              J, true);
+    if (s != GF_OK || nq == 0) return s;
+    gf_forest* F = const_cast<gf_forest*>(Fc);
+    J.path = 0;
+    // the largest batch whose row-path workspace fits the scratch array
+    const size_t one = ws_layout(F, 1, J.k, J.form, false).need;
+    if (one > kNoAllocScratchBytes)
+        return fail(GF_EUNSUPPORTED, "one query's workspace (" + std::to_string(one) +
+                                         " bytes) exceeds the 128 MiB scratch of gf_query_noalloc");
+    const size_t per = ws_layout(F, 2, J.k, J.form, false).need - one + 256;
+    int nb = int(std::min<int64_t>(max_batch(F), int64_t((kNoAllocScratchBytes - one) / per) + 1));
+    while (nb > 1 && ws_layout(F, nb, J.k, J.form, false).need > kNoAllocScratchBytes) --nb;
+    GF_HIP(hipSetDevice(F->device));
+    char* base = nullptr;
+    if ((s = scratch_base(F->device, &base)) != GF_OK) return s;
+    std::lock_guard<std::mutex> lock(g_scratch_call[F->device]);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int64_t q0 = 0; q0 < nq; q0 += nb) {
+        const int b = int(std::min<int64_t>(nb, nq - q0));
+        if ((s = run_batch(F, J, q0, b, st, false, base)) != GF_OK) return s;
+    }
+    return GF_OK;
+}
 
 const char* gf_version(void) { return "geraf-gfx950 0.1"; }
 

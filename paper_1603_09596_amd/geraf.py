@@ -25,6 +25,7 @@ FORMS = {"fp32": FORM_FP32, "bf16": FORM_BF16, "fp8": FORM_FP8}
 
 EXPORTED = ["gf_build_forest", "gf_build_forest_ex", "gf_free_forest", "gf_forest_info", "gf_export_tree", "gf_query",
             "gf_query_multi", "gf_multi_stats", "gf_query_trace", "gf_query_trace_ex",
+            "gf_query_noalloc",
             "gf_fp8_tables", "gf_hbm_probe",
             "gf_last_query_timing", "gf_last_error", "gf_version"]
 MULTI_AUTOTUNE, MULTI_EAGER = 1, 2
@@ -65,6 +66,7 @@ def load():
     lib.gf_forest_info.argtypes = [P, P, P, P, P, P, P]
     lib.gf_export_tree.argtypes = [P, P, P, P, P, P]
     lib.gf_query.argtypes = [P, P, i64, i32, i32, P, f64, i32, i32, P, P, P]
+    lib.gf_query_noalloc.argtypes = [P, P, i64, i32, i32, P, f64, i32, i32, P, P, P]
     lib.gf_query_trace.argtypes = [P, P, i64, i32, P, f64, P, P, P, P]
     lib.gf_query_trace_ex.argtypes = [P, P, i64, i32, P, f64, i32, P, P, P, P]
     lib.gf_query_multi.argtypes = [ctypes.POINTER(Job), i32, u32, P]
@@ -184,6 +186,16 @@ def query(F: Forest, Q, k: int, checks: int, ids, dists, checks_per_query=None, 
     st = stream if stream is not None else _stream_of(Q, ids)
     _check(load().gf_query(F.handle, _ptr(Q), nq, k, checks, _ptr(checks_per_query), float(eps),
                            FORMS[form], rerank, _ptr(ids), _ptr(dists), st))
+
+
+def query_noalloc(F: Forest, Q, k: int, checks: int, ids, dists, checks_per_query=None,
+                  eps: float = 0.0, form: str = "fp32", rerank: int = 0, stream=None):
+    """gf_query_noalloc: gf_query's row path with no device allocation (the
+    library's static scratch array); every tensor on the device."""
+    nq = Q.shape[0]
+    st = stream if stream is not None else _stream_of(Q, ids)
+    _check(load().gf_query_noalloc(F.handle, _ptr(Q), nq, k, checks, _ptr(checks_per_query),
+                                   float(eps), FORMS[form], rerank, _ptr(ids), _ptr(dists), st))
 
 
 def query_multi(jobs, autotune: bool = False, eager: bool = False, stream=None):
