@@ -175,7 +175,8 @@ struct Workspace {
     float* Qp; uint16_t* Q16; uint8_t* Q8; float* qscale; float* qnorm; int32_t* cpq;
     gf::SelState* state; uint32_t* hist; uint32_t* coff; uint64_t* ckey; uint32_t* ccode;
     uint32_t* leafbits; uint32_t* flags; uint32_t* qlist; int32_t* ids; float* dists;
-    uint32_t* openT; uint32_t* visT; uint32_t* gthr; float* part_s; int* part_i;   // tile path only
+    uint32_t* openT; uint32_t* visT; uint32_t* gthr; float* part_s; int* part_i;   // tile paths only
+    uint64_t* masks8; uint32_t* offs8; uint32_t* total8; float* out_s8; int* out_i8;   // FP8 tile path
     float* qt;   // [m][nb][t] reflected query coordinates (isometry variant only)
 };
 
@@ -187,6 +188,10 @@ struct TilePlan {
     int nsplit = 0;
     int64_t split_pts = 0;
     int cw = 0, nchunk = 0;
+    // FP8 tile path: tiles of 128 points, splits of split_tiles tiles, and
+    // the candidate slots per query
+    int ntiles8 = 0, nsplit8 = 0, split_tiles8 = 0;
+    int64_t cap8 = 0;
 };
 
 // The tile kernel runs one workgroup per CU at a time, so the batch takes
@@ -206,8 +211,27 @@ int device_cus() {
     return cus;
 }
 
-TilePlan tile_plan(const gf_forest* F, int nb) {
+TilePlan tile_plan(const gf_forest* F, int nb, int form = gf::kFormBF16, int64_t checks_max = 0) {
     TilePlan p;
+    if (form == gf::kFormFP8) {
+        // one workgroup per CU at a time, each a 128-query block and a split
+        // of the tiles: the split count with the least time in whole rounds
+        const int64_t qblocks = (nb + 127) / 128;
+        const int64_t tiles = gf::tile8_ntiles(F->host.n);
+        const int64_t cus = device_cus();
+        int64_t ns = 1;
+        double best = 1e300;
+        for (int64_t s = 1; s <= std::min<int64_t>(tiles, 512); ++s) {
+            const double rounds = double((qblocks * s + cus - 1) / cus);
+            const double cost = rounds / double(s) + 0.002 * double(s);
+            if (cost < best) { best = cost; ns = s; }
+        }
+        p.ntiles8 = int(tiles);
+        p.split_tiles8 = int((tiles + ns - 1) / ns);
+        p.nsplit8 = int((tiles + p.split_tiles8 - 1) / p.split_tiles8);
+        p.cap8 = std::max<int64_t>(1, std::min<int64_t>(F->host.n, std::max<int64_t>(1, checks_max) *
+                                                                         int64_t(std::max(1, F->maxleaf))));
+    }
     const int64_t qblocks = (nb + 127) / 128;
     const int64_t tiles = (F->host.n + 63) / 64;
     const int64_t max_tiles = ((int64_t{1} << 31) - 1) / (int64_t(F->ld16) * 2 * 64);
@@ -234,10 +258,11 @@ struct WsLayout {
     size_t oQp = 0, oQ16 = 0, oQ8 = 0, oqs = 0, oqn = 0, ocpq = 0, ost = 0, ohist = 0, onc = 0;
     size_t ock = 0, occ = 0, olb = 0, ofl = 0, oql = 0, oids = 0, odst = 0, oqt = 0;
     size_t oopen = 0, ovis = 0, othr = 0, ops = 0, opi = 0;
+    size_t omask = 0, ooff = 0, otot = 0, oos = 0, ooi = 0;
     size_t need = 0;   // bytes
 };
 
-WsLayout ws_layout(const gf_forest* F, int nb, int k, int form, bool tile) {
+WsLayout ws_layout(const gf_forest* F, int nb, int k, int form, bool tile, int64_t checks_max = 0) {
     const int64_t W = std::max<int64_t>(1, (int64_t{1} << F->host.H) / 32);
     Carve c;
     WsLayout L;
@@ -261,12 +286,20 @@ WsLayout ws_layout(const gf_forest* F, int nb, int k, int form, bool tile) {
     L.odst = c.take<float>(size_t(nb) * k);
     L.oqt = F->U ? c.take<float>(size_t(nb) * F->host.m * F->host.t) : 0;
     if (tile) {
-        const TilePlan tp = tile_plan(F, nb);
+        const TilePlan tp = tile_plan(F, nb, form, checks_max);
         L.oopen = c.take<uint32_t>(size_t(tp.nchunk) * F->host.m * (size_t{1} << F->host.H) * tp.cw);
         L.ovis = c.take<uint32_t>(size_t(tp.nchunk) * F->host.n * tp.cw);
         L.othr = c.take<uint32_t>(nb);
-        L.ops = c.take<float>(size_t(nb) * tp.nsplit * gf::kTileList);
-        L.opi = c.take<int>(size_t(nb) * tp.nsplit * gf::kTileList);
+        const size_t lists = form == gf::kFormFP8 ? 1 : size_t(tp.nsplit);
+        L.ops = c.take<float>(size_t(nb) * lists * gf::kTileList);
+        L.opi = c.take<int>(size_t(nb) * lists * gf::kTileList);
+        if (form == gf::kFormFP8) {
+            L.omask = c.take<uint64_t>(size_t(nb) * tp.ntiles8 * 2);
+            L.ooff = c.take<uint32_t>(size_t(nb) * tp.ntiles8);
+            L.otot = c.take<uint32_t>(nb);
+            L.oos = c.take<float>(size_t(nb) * tp.cap8);
+            L.ooi = c.take<int>(size_t(nb) * tp.cap8);
+        }
     }
     L.need = c.off + 256;
     return L;
@@ -295,10 +328,17 @@ void ws_bind(const gf_forest* F, const WsLayout& L, char* b, int form, bool tile
     w.gthr = tile ? reinterpret_cast<uint32_t*>(b + L.othr) : nullptr;
     w.part_s = tile ? reinterpret_cast<float*>(b + L.ops) : nullptr;
     w.part_i = tile ? reinterpret_cast<int*>(b + L.opi) : nullptr;
+    const bool t8 = tile && form == gf::kFormFP8;
+    w.masks8 = t8 ? reinterpret_cast<uint64_t*>(b + L.omask) : nullptr;
+    w.offs8 = t8 ? reinterpret_cast<uint32_t*>(b + L.ooff) : nullptr;
+    w.total8 = t8 ? reinterpret_cast<uint32_t*>(b + L.otot) : nullptr;
+    w.out_s8 = t8 ? reinterpret_cast<float*>(b + L.oos) : nullptr;
+    w.out_i8 = t8 ? reinterpret_cast<int*>(b + L.ooi) : nullptr;
 }
 
-gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Workspace& w) {
-    const WsLayout L = ws_layout(F, nb, k, form, tile);
+gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Workspace& w,
+                        int64_t checks_max = 0) {
+    const WsLayout L = ws_layout(F, nb, k, form, tile, checks_max);
     if (L.need > F->ws_bytes) {
         if (F->ws) (void)hipFree(F->ws);
         F->ws = nullptr;
@@ -332,6 +372,7 @@ struct QueryJob {
     int64_t nq;
     int32_t k, checks;
     double checks_mean;        // mean budget over the queries (the path rule's estimate)
+    int64_t checks_max;        // largest budget (bounds a query's candidates)
     double eps;
     int form, kk;
     // outputs (host or device), any may be null
@@ -347,28 +388,32 @@ struct QueryJob {
 // path reads every candidate's row from HBM.  It pays off once the batch
 // fills 128-query blocks and each query's candidates are more than ~1/256
 // of the points.  GF_SCAN_PATH=rows|tile forces a path.
+//
+// The FP8 form has a tile path of its own (tile8.hip) for wide rows: dense
+// FP8 scores of 128-query blocks against 128-point tiles, the candidates'
+// scores compacted per query.  Its product reads every row once per query
+// block at 5 PFLOP/s where the gathers read each candidate's row at HBM
+// rate; it pays off from about 1/192 of the points per query.
 bool tile_eligible(const gf_forest* F, const QueryJob& J) {
-    if (J.form != gf::kFormBF16 || J.leaf_bits || J.cand_bits || J.ncand) return false;
-    if (J.kk > gf::kTileList) return false;
-    if (F->ld16 > 1024) return false;
-    if (!gf::scan_supported(F->host.n, gf::kFormFP32, F->ld8)) return false;
-    return F->leafof != nullptr;
+    if (J.leaf_bits || J.cand_bits || J.ncand || !F->leafof) return false;
+    if (J.kk > gf::kTileList) return false;   // lists of kTileList entries per query
+    if (J.form == gf::kFormBF16) {
+        if (F->ld16 > 1024) return false;
+        return gf::scan_supported(F->host.n, gf::kFormFP32, F->ld8);
+    }
+    return J.form == gf::kFormFP8;
 }
 
 bool use_tile_path(const gf_forest* F, const QueryJob& J, int nb) {
     if (J.path >= 0) return J.path == 1 && tile_eligible(F, J);
-    if (J.form != gf::kFormBF16 || J.leaf_bits || J.cand_bits || J.ncand) return false;
-    if (J.kk > gf::kTileList) return false;   // each split keeps kTileList entries per query
-    if (F->ld16 > 1024) return false;
-    if (!gf::scan_supported(F->host.n, gf::kFormFP32, F->ld8)) return false;
-    if (!F->leafof) return false;
+    if (!tile_eligible(F, J)) return false;
     const char* env = std::getenv("GF_SCAN_PATH");
     if (env && std::strcmp(env, "rows") == 0) return false;
     if (env && std::strcmp(env, "tile") == 0) return true;
     if (nb < 128) return false;
     const double leaf_pts = double(F->host.n) / double(int64_t{1} << F->host.H);
     const double cand_est = J.checks_mean * leaf_pts * 0.5;
-    return cand_est * 256.0 >= double(F->host.n);
+    return cand_est * (J.form == gf::kFormFP8 ? 192.0 : 256.0) >= double(F->host.n);
 }
 
 gf::SelectArgs make_select_args(const gf_forest* F, int nb, const Workspace& w, int64_t W) {
@@ -464,8 +509,26 @@ gf::ExpandArgs make_expand_args(const gf_forest* F, int nb, const Workspace& w, 
 gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& w, int64_t W,
                       const gf::ScanArgs& ca, hipStream_t st, hipEvent_t* ev) {
     const gf::HostForest& h = F->host;
-    const TilePlan tp = tile_plan(F, nb);
+    const TilePlan tp = tile_plan(F, nb, J.form, J.checks_max);
     const gf::ExpandArgs ea = make_expand_args(F, nb, w, W);
+    if (J.form == gf::kFormFP8) {
+        GF_HIP(gf::launch_tile_expand(ea, st));
+        if (ev) GF_HIP(hipEventRecord(ev[0], st));
+        gf::Tile8Args t8{};
+        t8.nq = nb; t8.n = h.n; t8.ld8 = F->ld8; t8.cw = tp.cw; t8.ntiles = tp.ntiles8;
+        t8.nsplit = tp.nsplit8; t8.split_tiles = tp.split_tiles8; t8.cap = tp.cap8; t8.kk = J.kk;
+        t8.Q8 = w.Q8; t8.X8 = F->X8; t8.qscale = w.qscale; t8.norm8 = F->norm8; t8.scale8 = F->scale8;
+        t8.visT = w.visT; t8.masks = w.masks8; t8.offs = w.offs8; t8.total = w.total8;
+        t8.out_s = w.out_s8; t8.out_i = w.out_i8; t8.part_s = w.part_s; t8.part_i = w.part_i;
+        GF_HIP(gf::launch_tile8(t8, (nb + 31) / 32, st));
+        if (ev) GF_HIP(hipEventRecord(ev[1], st));
+        gf::MergeArgs ma{};
+        ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = 1;
+        ma.part_s = w.part_s; ma.part_i = w.part_i; ma.Q = w.Qp; ma.ldq = F->ld32;
+        ma.X32 = F->X32; ma.ld32 = F->ld32; ma.ids = ca.ids; ma.dists = ca.dists;
+        GF_HIP(gf::launch_merge(ma, st));
+        return GF_OK;
+    }
     gf::TileArgs ta{};
     ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.cw = tp.cw; ta.Q16 = w.Q16; ta.X16 = F->X16;
     ta.norm16 = F->norm16; ta.visT = w.visT; ta.gthr = w.gthr; ta.cap = J.kk; ta.nsplit = tp.nsplit;
@@ -535,7 +598,7 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     if (scratch) {
         ws_bind(F, ws_layout(F, nb, J.k, J.form, false), scratch, J.form, false, w);
     } else {
-        gf_status s0 = get_workspace(F, nb, J.k, J.form, tile, w);
+        gf_status s0 = get_workspace(F, nb, J.k, J.form, tile, w, J.checks_max);
         if (s0 != GF_OK) return s0;
     }
     gf_status s = GF_OK;
@@ -720,6 +783,7 @@ gf_status prepare_job(const gf_forest* Fc, const float* Q, int64_t nq, int32_t k
     J.Q = Q; J.q_dev = is_device_ptr(Q);
     J.cpq = checks_per_query; J.cpq_dev = checks_per_query && is_device_ptr(checks_per_query);
     J.checks_mean = double(checks);
+    J.checks_max = checks;
     if (noalloc) {
         if (!J.q_dev || !is_device_ptr(ids) || !is_device_ptr(dists) || (checks_per_query && !J.cpq_dev))
             return fail(GF_EINVAL, "gf_query_noalloc takes device buffers for Q, budgets and outputs");
@@ -737,11 +801,14 @@ gf_status prepare_job(const gf_forest* Fc, const float* Q, int64_t nq, int32_t k
             c = staged.data();
         }
         double sum = 0.0;
+        int64_t mx = 1;
         for (int64_t i = 0; i < nq; ++i) {
             if (c[i] < 1) return fail(GF_EINVAL, "checks_per_query has a value < 1");
             sum += double(c[i]);
+            mx = std::max<int64_t>(mx, c[i]);
         }
         J.checks_mean = sum / double(nq);
+        J.checks_max = mx;
     }
     J.out_dev = is_device_ptr(ids);
     if (J.out_dev != is_device_ptr(dists)) return fail(GF_EINVAL, "ids and dists must both be host or both device");
@@ -903,7 +970,7 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
     // Grow every workspace to its largest batch before any capture.
     for (const MultiBatch& b : B) {
         Workspace w;
-        gf_status s = get_workspace(b.F, b.nb, J[b.job].k, J[b.job].form, b.tile, w);
+        gf_status s = get_workspace(b.F, b.nb, J[b.job].k, J[b.job].form, b.tile, w, J[b.job].checks_max);
         if (s != GF_OK) return s;
     }
     auto launch_all = [&](hipStream_t s_) -> gf_status {
@@ -1246,8 +1313,8 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         GF_HIP_B(hipMalloc(&F->U, ut.size() * sizeof(double)));
         GF_HIP_B(hipMemcpy(F->U, ut.data(), ut.size() * sizeof(double), hipMemcpyHostToDevice));
     }
-    if (forms & GF_KEEP_BF16) {
-        // leaf of every point in every tree, point-major (tile path)
+    if (forms & (GF_KEEP_BF16 | GF_KEEP_FP8)) {
+        // leaf of every point in every tree, point-major (tile paths)
         const int64_t nleaf = int64_t{1} << h.H;
         std::vector<uint32_t> lof(size_t(n) * m);
         for (int32_t tr = 0; tr < m; ++tr)
@@ -1257,6 +1324,14 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         GF_HIP_B(hipMalloc(&F->leafof, lof.size() * 4));
         GF_HIP_B(hipMemcpy(F->leafof, lof.data(), lof.size() * 4, hipMemcpyHostToDevice));
         phase("leaf of each point");
+    }
+    {
+        uint32_t maxleaf = 0;
+        for (size_t j = 0; j + 1 < h.leaf_off.size(); ++j)
+            maxleaf = std::max(maxleaf, h.leaf_off[j + 1] - h.leaf_off[j]);
+        F->maxleaf = int32_t(maxleaf);
+    }
+    if (forms & GF_KEEP_BF16) {
         GF_HIP_B(hipMalloc(&F->X16, size_t(n) * F->ld16 * 2));
         GF_HIP_B(hipMalloc(&F->norm16, size_t(n) * 4));
         hipLaunchKernelGGL(gf::k_to_bf16, dim3((n + 3) / 4), dim3(256), 0, st, F->X32, n, d,

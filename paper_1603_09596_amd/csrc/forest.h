@@ -69,7 +69,8 @@ struct gf_forest {
     uint32_t* leaf_off = nullptr;   // [2^H + 1]
     uint32_t* permp = nullptr;      // [m][2^H][pp] leaf rows padded with 0xFFFFFFFF
     int32_t pp = 0;                 // ids per padded leaf row: pow2 >= max leaf size, >= 4
-    uint32_t* leafof = nullptr;     // [n][m] tree * 2^H + leaf of each point (BF16 form)
+    uint32_t* leafof = nullptr;     // [n][m] tree * 2^H + leaf of each point (BF16 / FP8 forms)
+    int32_t maxleaf = 0;            // points in the largest leaf
     int32_t* D = nullptr;           // [t]
     float2* drange = nullptr;       // [t] smallest and largest split value per slot of D
     double* U = nullptr;            // [d][m] reflectors, transposed (isometry variant), or null

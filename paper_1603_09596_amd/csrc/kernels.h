@@ -167,6 +167,37 @@ struct MergeArgs {
     float* dists;
 };
 
+// FP8 tile path (wide rows): dense FP8 MFMA scores of 128-query blocks
+// against 128-point tiles, kept only for each query's candidates, written
+// compactly per query, then the kk best per query.
+struct Tile8Args {
+    int nq;
+    int64_t n, ld8;             // ld8: a multiple of 16
+    int cw;                     // query words per chunk of visT
+    int ntiles;                 // ceil(n / 128)
+    int nsplit, split_tiles;    // point splits of split_tiles tiles each
+    int64_t cap;                // candidate slots per query (>= its candidate count)
+    int kk;                     // best entries kept per query (<= kTileList)
+    const uint8_t* Q8;          // [nq][ld8] e4m3 queries
+    const uint8_t* X8;          // [n][ld8] e4m3 points
+    const float* qscale;        // [nq]
+    const float* norm8;         // [n] ||dequantised x||^2
+    const float* scale8;        // [n]
+    const uint32_t* visT;       // [nchunk][n][cw] from the expansion
+    uint64_t* masks;            // [nq][ntiles][2] candidate points of each tile
+    uint32_t* offs;             // [nq][ntiles] candidates of the query before each tile
+    uint32_t* total;            // [nq]
+    float* out_s;               // [nq][cap] candidate scores, compacted
+    int* out_i;                 // [nq][cap]
+    float* part_s;              // [nq][kTileList] the kk best (rest +inf)
+    int* part_i;
+};
+int tile8_ntiles(int64_t n);
+// masks, prefix, scores and the per-query selection (nqw = ceil(nq / 32)).
+hipError_t launch_tile8(const Tile8Args& t, int nqw, hipStream_t st);
+// The tile path's merge of per-split lists, FP32 re-rank and FP64 ties.
+hipError_t launch_merge(const MergeArgs& m, hipStream_t st);
+
 // The expansion alone: openT and visT from the opened-leaf bits.
 hipError_t launch_tile_expand(const ExpandArgs& e, hipStream_t st);
 // The expansion, then visT in query-major form (cand_bits [nq][ceil(n/32)])

@@ -677,6 +677,10 @@ hipError_t launch_tile_path(const ExpandArgs& e, const TileArgs& t, const MergeA
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
+    return launch_merge(m, st);
+}
+
+hipError_t launch_merge(const MergeArgs& m, hipStream_t st) {
     // threads: enough to rank every list entry at once (up to kMergeMax), in whole waves
     const int64_t tot = int64_t(m.nsplit) * kTileList;
     const unsigned mthreads = unsigned(std::min<int64_t>(kMergeMax, std::max<int64_t>(256, (tot + kWave - 1) / kWave * kWave)));

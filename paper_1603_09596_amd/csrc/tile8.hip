@@ -1,0 +1,349 @@
+// tile8.hip -- the FP8 (e4m3, per-row scale) selection score of many
+// queries at once, on MFMA, for wide rows.
+//
+// At d = 10,000 a query's candidates (Sec. 2.3) are a few percent of the
+// points, yet gathering them row by row reads 10 KB per candidate from HBM,
+// while the dense product of a 128-query block with a 128-point tile costs
+// 0.3 GFLOP on the FP8 matrix cores (5 PFLOP/s): scoring every pair of a
+// block is cheaper than gathering the pairs that count.  The forest then
+// decides which scores are kept, through the per-point candidate words of
+// the tile path's expansion, and only those are written out, compacted:
+//
+//   k_cand_masks   per (query, tile of 128 points): the 128-bit mask of the
+//                  tile's points that are candidates of the query, from the
+//                  per-point words of query bits (ballots over the points);
+//   k_cand_prefix  per query: the exclusive prefix count of its candidates
+//                  over the tiles, so that every candidate has its own slot;
+//   k_tile_fp8     grid (query blocks of 128, point splits): A (queries) and
+//                  B (points) stream through LDS in 128-byte k stages, both
+//                  double-buffered; each wave computes a 64 x 64 block with
+//                  v_mfma_scale_f32_16x16x128_f8f6f4 (neutral scales, FP32
+//                  accumulation); the epilogue forms ||x||^2 - 2 s_q s_x q.x
+//                  for the candidates only and writes (score, id) to the
+//                  query's slots;
+//   k_topk_select  per query: a radix select over the (score, id) keys of its
+//                  candidates keeps the kk best, handed to the tile path's
+//                  merge, FP32 compensated re-rank and FP64 tie re-check.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace gf {
+
+namespace {
+
+constexpr int kW = 64;                 // wavefront
+constexpr int kQB = 128;               // queries per workgroup
+constexpr int kTP8 = 128;              // points per tile
+constexpr int kKS8 = 128;              // k bytes per stage (one MFMA depth)
+constexpr int kT8Threads = 256;        // 4 waves, each a 64 x 64 block
+constexpr int kStage8 = kQB * kKS8;    // bytes of one operand stage (16 KB)
+constexpr int kXcd8 = 8;               // XCDs of an MI355X
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Order-preserving map of float scores to uint32 (a < b <=> key(a) < key(b)).
+__device__ __forceinline__ uint32_t fkey(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ int popc128_below(uint64_t m0, uint64_t m1, int xl) {
+    if (xl < 64) return __popcll(m0 & ((uint64_t{1} << xl) - 1u));
+    return __popcll(m0) + __popcll(m1 & ((uint64_t{1} << (xl - 64)) - 1u));
+}
+
+}  // namespace
+
+// One workgroup of 128 threads per (tile, word of 32 queries): thread x
+// holds the word of point 128 T + x; 32 ballots give the 32 queries' masks
+// over the tile's halves.  Ragged tails (points past n, queries past nq)
+// are zero or skipped.
+__global__ __launch_bounds__(128) void k_cand_masks(const uint32_t* __restrict__ visT, int nq,
+                                                    int64_t n, int cw, int ntiles,
+                                                    uint64_t* __restrict__ masks) {
+    const int T = blockIdx.x, gw = blockIdx.y;
+    const int c = gw / cw, w = gw % cw;
+    const int64_t x = int64_t(T) * kTP8 + threadIdx.x;
+    const uint32_t word = x < n ? visT[(int64_t(c) * n + x) * cw + w] : 0u;
+    const int lane = threadIdx.x & (kW - 1), half = threadIdx.x / kW;
+#pragma unroll 4
+    for (int b = 0; b < 32; ++b) {
+        const uint64_t m = __ballot((word >> b) & 1u);
+        const int q = gw * 32 + b;
+        if (lane == 0 && q < nq) masks[(int64_t(q) * ntiles + T) * 2 + half] = m;
+    }
+}
+
+// One workgroup of 256 threads per query: offs[q][T] = candidates of q in
+// tiles before T; total[q] = all of them.
+__global__ __launch_bounds__(256) void k_cand_prefix(const uint64_t* __restrict__ masks, int ntiles,
+                                                     uint32_t* __restrict__ offs,
+                                                     uint32_t* __restrict__ total) {
+    __shared__ uint32_t part[256];
+    const int q = blockIdx.x;
+    const int per = (ntiles + 255) / 256;
+    const int t0 = int(threadIdx.x) * per, t1 = min(ntiles, t0 + per);
+    const uint64_t* m = masks + int64_t(q) * ntiles * 2;
+    uint32_t s = 0;
+    for (int t = t0; t < t1; ++t) s += uint32_t(__popcll(m[2 * t]) + __popcll(m[2 * t + 1]));
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < 256; ++i) {
+            const uint32_t v = part[i];
+            part[i] = run;
+            run += v;
+        }
+        total[q] = run;
+    }
+    __syncthreads();
+    uint32_t run = part[threadIdx.x];
+    for (int t = t0; t < t1; ++t) {
+        offs[int64_t(q) * ntiles + t] = run;
+        run += uint32_t(__popcll(m[2 * t]) + __popcll(m[2 * t + 1]));
+    }
+}
+
+// The score kernel.  Workgroups are dispatched to the XCDs round-robin
+// (workgroup i to XCD i % 8); each XCD takes a consecutive run of the
+// split-major (split, query block) list, so the query blocks of one split
+// run on one XCD and share its L2 for the split's rows.
+//
+// LDS per operand stage: row r (a query or a point) holds its 128 k bytes as
+// eight 16-byte units, unit u at position u ^ (r & 7): the 16-byte stores
+// of a row's eight threads and the MFMA operand reads of eight consecutive
+// rows both spread over all banks.
+__global__ __launch_bounds__(kT8Threads) void k_tile_fp8(Tile8Args a) {
+    __shared__ __attribute__((aligned(1024))) uint8_t sA[2][kStage8];
+    __shared__ __attribute__((aligned(1024))) uint8_t sB[2][kStage8];
+    __shared__ uint64_t sMask[kQB][2];
+    __shared__ uint32_t sOff[kQB];
+    __shared__ float sQs[kQB];
+    __shared__ float sXn[kTP8], sXs[kTP8];
+    const int tid = threadIdx.x, lane = tid & (kW - 1), wave = tid / kW;
+    int qblk, split;
+    {
+        const int nqb = (a.nq + kQB - 1) / kQB;
+        const int total = nqb * a.nsplit;
+        const int i = int(blockIdx.x), x = i % kXcd8, j = i / kXcd8;
+        const int base = total / kXcd8, rem = total % kXcd8;
+        const int L = (x < rem) ? x * (base + 1) + j : rem * (base + 1) + (x - rem) * base + j;
+        split = L / nqb;
+        qblk = L - split * nqb;
+    }
+    const int q0 = qblk * kQB;
+    const int t_begin = split * a.split_tiles;
+    const int t_end = min(a.ntiles, t_begin + a.split_tiles);
+    const int nk = int((a.ld8 + kKS8 - 1) / kKS8);
+    if (tid < kQB) sQs[tid] = (q0 + tid < a.nq) ? a.qscale[q0 + tid] : 0.0f;
+
+    // staging: thread tid moves unit u = tid & 7 of rows r0 + 32 j, j < 4,
+    // of both operands
+    const int su = tid & 7, sr0 = tid >> 3;
+    // MFMA operands: wave = (query half, point half); lane l reads row
+    // (l & 15) of each 16-row fragment, k bytes 32 (l >> 4) .. + 32
+    const int qh = wave >> 1, ph = wave & 1;
+    const int fr = lane & 15, fg = lane >> 4;
+
+    for (int T = t_begin; T < t_end; ++T) {
+        const int64_t x0 = int64_t(T) * kTP8;
+        uint4 ra[4], rb[4];
+        auto load_stage = [&](int kc) {
+            const int64_t kb = int64_t(kc) * kKS8 + 16 * su;
+            const bool kin = kb < a.ld8;   // ld8 is a multiple of 16: whole units in or out
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = sr0 + 32 * j;
+                const int q = q0 + r;
+                const int64_t x = x0 + r;
+                ra[j] = (kin && q < a.nq) ? *reinterpret_cast<const uint4*>(a.Q8 + int64_t(q) * a.ld8 + kb)
+                                          : make_uint4(0, 0, 0, 0);
+                rb[j] = (kin && x < a.n) ? *reinterpret_cast<const uint4*>(a.X8 + x * a.ld8 + kb)
+                                         : make_uint4(0, 0, 0, 0);
+            }
+        };
+        auto store_stage = [&](int buf) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = sr0 + 32 * j;
+                const int off = r * kKS8 + ((su ^ (r & 7)) << 4);
+                *reinterpret_cast<uint4*>(&sA[buf][off]) = ra[j];
+                *reinterpret_cast<uint4*>(&sB[buf][off]) = rb[j];
+            }
+        };
+        f4v acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+        load_stage(0);
+        __syncthreads();   // the previous tile's epilogue is done with its LDS operands
+        store_stage(0);
+        __syncthreads();
+        for (int kc = 0; kc < nk; ++kc) {
+            const int buf = kc & 1;
+            if (kc + 1 < nk) load_stage(kc + 1);   // in flight during the MFMAs
+            v8i fa[4], fb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 64 * qh + 16 * i + fr;
+                const uint4 lo = *reinterpret_cast<const uint4*>(&sA[buf][r * kKS8 + (((2 * fg) ^ (r & 7)) << 4)]);
+                const uint4 hi = *reinterpret_cast<const uint4*>(&sA[buf][r * kKS8 + (((2 * fg + 1) ^ (r & 7)) << 4)]);
+                fa[i] = v8i{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = 64 * ph + 16 * j + fr;
+                const uint4 lo = *reinterpret_cast<const uint4*>(&sB[buf][r * kKS8 + (((2 * fg) ^ (r & 7)) << 4)]);
+                const uint4 hi = *reinterpret_cast<const uint4*>(&sB[buf][r * kKS8 + (((2 * fg + 1) ^ (r & 7)) << 4)]);
+                fb[j] = v8i{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[i], fb[j], acc[i][j],
+                                                                                0, 0, 0, 127, 0, 127);
+            if (kc + 1 < nk) store_stage(buf ^ 1);   // that buffer was released by the last barrier
+            __syncthreads();
+        }
+        // epilogue operands of this tile: the block's masks and offsets, the
+        // points' norms and scales
+        if (tid < kQB) {
+            const int q = q0 + tid;
+            if (q < a.nq) {
+                const int64_t mi = (int64_t(q) * a.ntiles + T) * 2;
+                sMask[tid][0] = a.masks[mi];
+                sMask[tid][1] = a.masks[mi + 1];
+                sOff[tid] = a.offs[int64_t(q) * a.ntiles + T];
+            } else {
+                sMask[tid][0] = 0;
+                sMask[tid][1] = 0;
+                sOff[tid] = 0;
+            }
+        } else {
+            const int xl = tid - kQB;
+            const int64_t x = x0 + xl;
+            sXn[xl] = x < a.n ? a.norm8[x] : 0.0f;
+            sXs[xl] = x < a.n ? a.scale8[x] : 0.0f;
+        }
+        __syncthreads();
+        // C[row 4 fg + i][col fr] of fragment (i, j): query 64 qh + 16 ii + 4 fg + e,
+        // point 64 ph + 16 j + fr of the tile
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ql = 64 * qh + 16 * ii + 4 * fg + e;
+                const uint64_t m0 = sMask[ql][0], m1 = sMask[ql][1];
+                if (!(m0 | m1)) continue;
+                const int64_t slot0 = int64_t(q0 + ql) * a.cap + sOff[ql];
+                const float qs2 = 2.0f * sQs[ql];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int xl = 64 * ph + 16 * j + fr;
+                    const bool cand = ((xl < 64 ? (m0 >> xl) : (m1 >> (xl - 64))) & 1u) != 0;
+                    if (cand) {
+                        const int64_t slot = slot0 + popc128_below(m0, m1, xl);
+                        a.out_s[slot] = sXn[xl] - qs2 * sXs[xl] * acc[ii][j][e];
+                        a.out_i[slot] = int(x0 + xl);
+                    }
+                }
+            }
+    }
+}
+
+// The kk best (score, id) of each query among its candidates: a radix select
+// over the 64-bit keys (order-preserving score bits, id) in eight 8-bit
+// digits; keys are distinct (ids are), so exactly min(kk, count) entries are
+// at or below the threshold.  They go to the first kk slots of the query's
+// list, the rest of its kTileList slots hold (+inf, max id).
+__global__ __launch_bounds__(256) void k_topk_select(const float* __restrict__ out_s,
+                                                     const int* __restrict__ out_i,
+                                                     const uint32_t* __restrict__ total, int64_t cap,
+                                                     int kk, float* __restrict__ part_s,
+                                                     int* __restrict__ part_i) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t sh_prefix;
+    __shared__ uint32_t sh_left, sh_pos;
+    const int q = blockIdx.x;
+    const uint32_t cnt = min(total[q], uint32_t(cap));
+    const float* s = out_s + int64_t(q) * cap;
+    const int* id = out_i + int64_t(q) * cap;
+    auto key = [&](uint32_t i) { return (uint64_t(fkey(s[i])) << 32) | uint32_t(id[i]); };
+    uint64_t kstar = ~0ull;
+    if (cnt > uint32_t(kk)) {
+        if (threadIdx.x == 0) {
+            sh_prefix = 0;
+            sh_left = uint32_t(kk);
+        }
+        __syncthreads();
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 56 - 8 * pass;
+            hist[threadIdx.x] = 0;
+            __syncthreads();
+            const uint64_t prefix = sh_prefix;
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+                const uint64_t K = key(i);
+                if (pass == 0 || (K >> (shift + 8)) == prefix) atomicAdd(&hist[(K >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t left = sh_left, b = 0;
+                for (; b < 255u && hist[b] < left; ++b) left -= hist[b];
+                sh_left = left;
+                sh_prefix = (prefix << 8) | b;
+            }
+            __syncthreads();
+        }
+        kstar = sh_prefix;
+    }
+    if (threadIdx.x == 0) sh_pos = 0;
+    __syncthreads();
+    float* ps = part_s + int64_t(q) * kTileList;
+    int* pi = part_i + int64_t(q) * kTileList;
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        if (key(i) <= kstar) {
+            const uint32_t p = atomicAdd(&sh_pos, 1u);
+            if (p < uint32_t(kTileList)) {
+                ps[p] = s[i];
+                pi[p] = id[i];
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t p = sh_pos + threadIdx.x; p < uint32_t(kTileList); p += blockDim.x) {
+        ps[p] = __builtin_inff();
+        pi[p] = 0x7FFFFFFF;
+    }
+}
+
+int tile8_ntiles(int64_t n) { return int((n + kTP8 - 1) / kTP8); }
+
+hipError_t launch_tile8(const Tile8Args& t, int nqw, hipStream_t st) {
+    if (t.cw < 4 || t.cw > 32 || t.ld8 % 16 || t.ntiles != tile8_ntiles(t.n) || t.split_tiles < 1 ||
+        t.nsplit * t.split_tiles < t.ntiles)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cand_masks, dim3(unsigned(t.ntiles), unsigned(nqw)), dim3(128), 0, st,
+                       t.visT, t.nq, t.n, t.cw, t.ntiles, t.masks);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_cand_prefix, dim3(unsigned(t.nq)), dim3(256), 0, st,
+                       static_cast<const uint64_t*>(t.masks), t.ntiles, t.offs, t.total);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    const int nqb = (t.nq + kQB - 1) / kQB;
+    hipLaunchKernelGGL(k_tile_fp8, dim3(unsigned(nqb * t.nsplit)), dim3(kT8Threads), 0, st, t);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_topk_select, dim3(unsigned(t.nq)), dim3(256), 0, st,
+                       static_cast<const float*>(t.out_s), static_cast<const int*>(t.out_i),
+                       static_cast<const uint32_t*>(t.total), t.cap, t.kk, t.part_s, t.part_i);
+    return hipGetLastError();
+}
+
+}  // namespace gf

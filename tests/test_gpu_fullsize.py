@@ -54,7 +54,7 @@ def run_case(w, c, form, sample, forms):
         assert leaf_set_from_bits(lb[j]) == set(ref["opened"][j].tolist()), f"query {idx[j]}"
         assert np.array_equal(ids_from_bits(cb[j], Fg.n), ref["cand"][j]), f"query {idx[j]}"
     assert np.array_equal(nc, ref["ncand"])
-    if "bf16" in forms:
+    if "bf16" in forms or "fp8" in forms:
         # the tile path's own candidate words for the same sample
         cbt = np.zeros_like(cb)
         nct = np.zeros_like(nc)
@@ -103,5 +103,6 @@ def test_sphere_100k_1000_full():
 
 def test_gauss_200k_10000_fp8_full():
     w = W.make("gauss-200k-10000")
-    ids, dd, ref, Qs, _ = run_case(w, w.c, "fp8", 16, ("fp8",))
+    ids, dd, ref, Qs, timing = run_case(w, w.c, "fp8", 16, ("fp8",))
+    assert timing["path"] == "tile"
     check_reduced(w, ids, dd, ref, Qs, 0.97)

@@ -432,3 +432,38 @@ def test_tile_path_bf16(name, k, c, nq, scan_path):
     print(f"{name} tile path: recall vs oracle {recall:.4f}, agreement with rows path {agreement:.4f}")
     assert np.array_equal(ids >= 0, ref["ids"] >= 0)
     assert recall >= 0.98 and agreement >= 0.99
+
+
+@pytest.mark.parametrize("name,k,c", [("gauss-4k-10000", 10, 2048), ("ragged-3001-77", 7, 300),
+                                      ("sphere-20k-1000", 5, 1024), ("quantised", 5, 150)])
+def test_tile_path_fp8(name, k, c, scan_path):
+    """The FP8 tile path (dense FP8 MFMA scores of 128-query blocks, kept for
+    each query's candidates) against the oracle and the FP8 row path: every
+    returned id a candidate, every distance exact to 1e-5, recall stated."""
+    X, Q, Fg, Fo, _ = forests(name, forms=("fp8",))
+    ref = oracle.search(Fo, X, Q, k, c, trace=False, candidates=True)
+    out = {}
+    for path in ("tile", "rows"):
+        scan_path(path)
+        ids = np.zeros((len(Q), k), np.int32)
+        dd = np.zeros((len(Q), k), np.float32)
+        geraf.query(Fg, Q, k, c, ids, dd, form="fp8")
+        assert geraf.last_query_timing()["path"] == path
+        out[path] = (ids, dd)
+    ids, dd = out["tile"]
+    hits = agree = 0
+    for i in range(len(Q)):
+        got = ids[i][ids[i] >= 0]
+        assert np.isin(got, ref["cand"][i]).all(), f"query {i}: a returned id is not a candidate"
+        for j, gid in enumerate(got.tolist()):
+            diff = X[gid].astype(np.float64) - Q[i].astype(np.float64)
+            true_d = float(diff @ diff)
+            assert abs(dd[i][j] - true_d) <= 1e-5 * true_d
+        assert np.all(np.diff(dd[i][ids[i] >= 0]) >= 0)
+        hits += len(set(got.tolist()) & set(ref["ids"][i][ref["ids"][i] >= 0].tolist()))
+        agree += len(set(got.tolist()) & set(out["rows"][0][i][out["rows"][0][i] >= 0].tolist()))
+    n_ref = max(1, int((ref["ids"] >= 0).sum()))
+    recall, agreement = hits / n_ref, agree / n_ref
+    print(f"{name} fp8 tile path: recall vs oracle {recall:.4f}, agreement with rows path {agreement:.4f}")
+    assert np.array_equal(ids >= 0, ref["ids"] >= 0)
+    assert recall >= 0.97 and agreement >= 0.97
