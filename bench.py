@@ -56,6 +56,8 @@ FORMS = {"desc-1m-960": "bf16", "gauss-200k-10000": "fp8",
          "sphere-100k-1000": "fp32", "gauss-10k-128": "fp32"}
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16
+MFMA_FP8_PEAK_TFLOPS = 5000.0    # MI355X dense FP8
+TILE_KERNELS = {"bf16": ("k_tile_bf16", MFMA_BF16_PEAK_TFLOPS), "fp8": ("k_tile_fp8", MFMA_FP8_PEAK_TFLOPS)}
 
 
 def log(*a):
@@ -397,6 +399,10 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the streaming-bandwidth probe reported beside the rooflines")
+    ap.add_argument("--no-exhaustive", action="store_true",
+                    help="skip the exhaustive comparator (every leaf opened) on the tile path")
+    ap.add_argument("--no-small-batches", action="store_true",
+                    help="skip the per-call times of 1, 16, 128 and 1024 queries on both paths")
     ap.add_argument("--householder", action="store_true",
                     help="build the forest with the per-tree Householder isometry variant")
     ap.add_argument("--sweep", choices=sorted(SWEEPS),
@@ -515,15 +521,70 @@ def main():
         fp32[f"recall@{k}"] = round(recall_at(ids_fp32[idx], gt), 4)
 
     if ph["path"] == "tile":
-        # dominant kernel: the MFMA score kernel, 2*nq*n*d flops per launch
+        # dominant kernel: the MFMA score kernel.  It scores every (query,
+        # point) pair of its blocks, 2*nq*n*d flops per launch (dense); the
+        # method's own work is 2*d flops per (query, candidate) pair, beside it
+        kname, peak = TILE_KERNELS[form]
         flops = 2.0 * nq * F.n * F.d
         achieved = flops / (ph["tile_ms"] / 1000.0) / 1e12
-        roofline = dict(bound="mfma", achieved=round(achieved, 1), peak=MFMA_BF16_PEAK_TFLOPS,
-                        unit="TFLOP/s", frac=round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
-                        traffic=pmc_traffic("k_tile_bf16", name), kernel="k_tile_bf16",
-                        flops_per_launch=int(flops), ms_per_launch=round(ph["tile_ms"], 3))
+        mflops = 2.0 * F.d * ncand_total
+        m_ach = mflops / (ph["tile_ms"] / 1000.0) / 1e12
+        roofline = dict(bound="mfma", achieved=round(achieved, 1), peak=peak,
+                        unit="TFLOP/s", frac=round(achieved / peak, 4),
+                        traffic=pmc_traffic(kname, name), kernel=kname,
+                        flops_per_launch=int(flops), ms_per_launch=round(ph["tile_ms"], 3),
+                        method_work=dict(flops_per_launch=int(mflops), achieved=round(m_ach, 1),
+                                         frac=round(m_ach / peak, 4),
+                                         share_of_dense=round(mflops / flops, 4)))
     else:
         roofline = scan_roofline(form, ph["scan_or_expand_ms"])
+
+    # the same tile kernel with every candidate bit set (the whole forest
+    # opened: exhaustive reduced-precision search, FP32 re-rank), timed the
+    # same way, with its recall: the comparator of the forest's budget
+    exhaustive = None
+    if ph["path"] == "tile" and not args.no_exhaustive:
+        call = m_total = F.m << F.H
+        for _ in range(args.warmup):
+            geraf.query(F, Q, k, call, ids, dists, form=form)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            geraf.query(F, Q, k, call, ids, dists, form=form)
+        torch.cuda.synchronize()
+        ex_wall = (time.perf_counter() - t0) / args.steps
+        ex_ph = geraf.last_query_timing()
+        ex_ids = ids.cpu().numpy()
+        exhaustive = dict(checks=m_total, value=round(nq / ex_wall, 2), ms_per_step=round(1e3 * ex_wall, 2),
+                          tile_ms=round(ex_ph["tile_ms"], 3), path=ex_ph["path"],
+                          **{f"recall@{k}": round(recall_at(ex_ids[idx], gt), 4)})
+        log(f"[bench] exhaustive comparator: {exhaustive}")
+
+    # small batches, the forest's own regime (the paper searches one query at
+    # a time): per-call time of nq in {1, 16, 128, 1024} on each path
+    small = None
+    if not args.no_small_batches:
+        small = []
+        for b in (1, 16, 128, 1024):
+            Qb = Q[:b].contiguous()
+            ib = torch.empty((b, k), dtype=torch.int32, device=dev)
+            db = torch.empty((b, k), dtype=torch.float32, device=dev)
+            row = dict(nq=b)
+            for path in ("rows", "tile"):
+                os.environ["GF_SCAN_PATH"] = path
+                geraf.query(F, Qb, k, c, ib, db, form=form)
+                torch.cuda.synchronize()
+                reps = 5 if b <= 128 else 2
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    geraf.query(F, Qb, k, c, ib, db, form=form)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps
+                row[f"{path}_ms"] = round(1e3 * dt, 3)
+                row[f"{path}_qps"] = round(b / dt, 1)
+            os.environ.pop("GF_SCAN_PATH", None)
+            small.append(row)
+            log(f"[bench] small batch {row}")
 
     probe = None if args.no_probe else hbm_probe(torch, geraf, dev)
     if probe:
@@ -566,6 +627,8 @@ def main():
         "phases_ms": {key: round(v, 2) for key, v in ph.items() if key != "path"},
         "fp32_form": fp32,
         "roofline": roofline,
+        "exhaustive_comparator": exhaustive,
+        "small_batches": small,
         "hbm_probe": probe,
         "cpu_baseline": cpu,
     }

@@ -262,7 +262,8 @@ struct WsLayout {
     size_t need = 0;   // bytes
 };
 
-WsLayout ws_layout(const gf_forest* F, int nb, int k, int form, bool tile, int64_t checks_max = 0) {
+WsLayout ws_layout(const gf_forest* F, int nb, int k, int form, bool tile, int64_t checks_max = 0,
+                   int scan_nslice = 1) {
     const int64_t W = std::max<int64_t>(1, (int64_t{1} << F->host.H) / 32);
     Carve c;
     WsLayout L;
@@ -300,6 +301,10 @@ WsLayout ws_layout(const gf_forest* F, int nb, int k, int form, bool tile, int64
             L.oos = c.take<float>(size_t(nb) * tp.cap8);
             L.ooi = c.take<int>(size_t(nb) * tp.cap8);
         }
+    } else if (scan_nslice > 1) {
+        // the sliced row scan's per-slice lists
+        L.ops = c.take<float>(size_t(nb) * scan_nslice * gf::kTileList);
+        L.opi = c.take<int>(size_t(nb) * scan_nslice * gf::kTileList);
     }
     L.need = c.off + 256;
     return L;
@@ -326,8 +331,8 @@ void ws_bind(const gf_forest* F, const WsLayout& L, char* b, int form, bool tile
     w.openT = tile ? reinterpret_cast<uint32_t*>(b + L.oopen) : nullptr;
     w.visT = tile ? reinterpret_cast<uint32_t*>(b + L.ovis) : nullptr;
     w.gthr = tile ? reinterpret_cast<uint32_t*>(b + L.othr) : nullptr;
-    w.part_s = tile ? reinterpret_cast<float*>(b + L.ops) : nullptr;
-    w.part_i = tile ? reinterpret_cast<int*>(b + L.opi) : nullptr;
+    w.part_s = (tile || L.ops) ? reinterpret_cast<float*>(b + L.ops) : nullptr;
+    w.part_i = (tile || L.opi) ? reinterpret_cast<int*>(b + L.opi) : nullptr;
     const bool t8 = tile && form == gf::kFormFP8;
     w.masks8 = t8 ? reinterpret_cast<uint64_t*>(b + L.omask) : nullptr;
     w.offs8 = t8 ? reinterpret_cast<uint32_t*>(b + L.ooff) : nullptr;
@@ -337,8 +342,8 @@ void ws_bind(const gf_forest* F, const WsLayout& L, char* b, int form, bool tile
 }
 
 gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Workspace& w,
-                        int64_t checks_max = 0) {
-    const WsLayout L = ws_layout(F, nb, k, form, tile, checks_max);
+                        int64_t checks_max = 0, int nslice = 1) {
+    const WsLayout L = ws_layout(F, nb, k, form, tile, checks_max, nslice);
     if (L.need > F->ws_bytes) {
         if (F->ws) (void)hipFree(F->ws);
         F->ws = nullptr;
@@ -414,6 +419,40 @@ bool use_tile_path(const gf_forest* F, const QueryJob& J, int nb) {
     const double leaf_pts = double(F->host.n) / double(int64_t{1} << F->host.H);
     const double cand_est = J.checks_mean * leaf_pts * 0.5;
     return cand_est * (J.form == gf::kFormFP8 ? 192.0 : 256.0) >= double(F->host.n);
+}
+
+// Slices of the row scan.  One workgroup per query leaves most of the
+// device idle for small batches (a single query would stream its candidate
+// rows through one CU), so below two workgroups per CU each query's id range
+// is cut into slices, one workgroup each, whose best lists the tile path's
+// merge combines.  Traces keep one slice (they read the whole bitmap), and so
+// do re-rank depths above the merge's list length.  GF_SCAN_SLICES=<count>
+// forces a count (for tests).
+struct ScanSlices {
+    int nslice = 1;
+    int64_t words = 0;   // bitmap words per slice (a multiple of 16)
+};
+
+ScanSlices scan_slices(const gf_forest* F, const QueryJob& J, int nb) {
+    ScanSlices r;
+    if (J.cand_bits || J.ncand || J.kk > gf::kTileList) return r;
+    const int64_t nbmw = (F->host.n + 31) / 32;
+    int64_t want = 1;
+    const char* env = std::getenv("GF_SCAN_SLICES");
+    if (env && std::atoi(env) > 0) {
+        want = std::atoi(env);
+    } else {
+        const int64_t cus = device_cus();
+        if (int64_t(nb) < 2 * cus) want = std::min<int64_t>(256, (2 * cus + nb - 1) / nb);
+    }
+    if (want <= 1) return r;
+    int64_t words = (nbmw + want - 1) / want;
+    words = std::max<int64_t>(64, (words + 15) / 16 * 16);   // at least 2,048 ids per slice
+    const int64_t ns = (nbmw + words - 1) / words;
+    if (ns <= 1) return r;
+    r.nslice = int(ns);
+    r.words = words;
+    return r;
 }
 
 gf::SelectArgs make_select_args(const gf_forest* F, int nb, const Workspace& w, int64_t W) {
@@ -513,17 +552,16 @@ gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& 
     const gf::ExpandArgs ea = make_expand_args(F, nb, w, W);
     if (J.form == gf::kFormFP8) {
         GF_HIP(gf::launch_tile_expand(ea, st));
-        if (ev) GF_HIP(hipEventRecord(ev[0], st));
         gf::Tile8Args t8{};
         t8.nq = nb; t8.n = h.n; t8.ld8 = F->ld8; t8.cw = tp.cw; t8.ntiles = tp.ntiles8;
         t8.nsplit = tp.nsplit8; t8.split_tiles = tp.split_tiles8; t8.cap = tp.cap8; t8.kk = J.kk;
         t8.Q8 = w.Q8; t8.X8 = F->X8; t8.qscale = w.qscale; t8.norm8 = F->norm8; t8.scale8 = F->scale8;
         t8.visT = w.visT; t8.masks = w.masks8; t8.offs = w.offs8; t8.total = w.total8;
         t8.out_s = w.out_s8; t8.out_i = w.out_i8; t8.part_s = w.part_s; t8.part_i = w.part_i;
-        GF_HIP(gf::launch_tile8(t8, (nb + 31) / 32, st));
-        if (ev) GF_HIP(hipEventRecord(ev[1], st));
+        // phase marks: expansion with the masks and offsets, then the score kernel
+        GF_HIP(gf::launch_tile8(t8, (nb + 31) / 32, st, ev));
         gf::MergeArgs ma{};
-        ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = 1;
+        ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = 1; ma.rerank = true;
         ma.part_s = w.part_s; ma.part_i = w.part_i; ma.Q = w.Qp; ma.ldq = F->ld32;
         ma.X32 = F->X32; ma.ld32 = F->ld32; ma.ids = ca.ids; ma.dists = ca.dists;
         GF_HIP(gf::launch_merge(ma, st));
@@ -534,10 +572,33 @@ gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& 
     ta.norm16 = F->norm16; ta.visT = w.visT; ta.gthr = w.gthr; ta.cap = J.kk; ta.nsplit = tp.nsplit;
     ta.split_pts = tp.split_pts; ta.part_s = w.part_s; ta.part_i = w.part_i;
     gf::MergeArgs ma{};
-    ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = tp.nsplit;
+    ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = tp.nsplit; ma.rerank = true;
     ma.part_s = w.part_s; ma.part_i = w.part_i; ma.Q = w.Qp; ma.ldq = F->ld32;
     ma.X32 = F->X32; ma.ld32 = F->ld32; ma.ids = ca.ids; ma.dists = ca.dists;
     GF_HIP(gf::launch_tile_path(ea, ta, ma, st, ev));
+    return GF_OK;
+}
+
+// a3-a6 on the row path: the scan, and for a sliced scan the merge of the
+// slices' lists (re-ranked in FP32 for the reduced-precision forms, as the
+// unsliced scan does).
+gf_status launch_rows(const gf_forest* F, const QueryJob& J, int nb, const Workspace& w,
+                      gf::ScanArgs ca, const ScanSlices& sl, hipStream_t st) {
+    if (sl.nslice > 1) {
+        ca.nslice = sl.nslice;
+        ca.slice_words = sl.words;
+        ca.part_s = w.part_s;
+        ca.part_i = w.part_i;
+    }
+    GF_HIP(gf::launch_scan(ca, J.form, st));
+    if (sl.nslice > 1) {
+        gf::MergeArgs ma{};
+        ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = F->host.d; ma.nsplit = sl.nslice;
+        ma.rerank = J.form != gf::kFormFP32;
+        ma.part_s = w.part_s; ma.part_i = w.part_i; ma.Q = w.Qp; ma.ldq = F->ld32;
+        ma.X32 = F->X32; ma.ld32 = F->ld32; ma.ids = ca.ids; ma.dists = ca.dists;
+        GF_HIP(gf::launch_merge(ma, st));
+    }
     return GF_OK;
 }
 
@@ -563,7 +624,7 @@ gf_status launch_query_forms(const gf_forest* F, const QueryJob& J, int nb, cons
 // kernel and all radix passes are launched (once each query's bin is
 // settled a pass finds no active query and its workgroups return at once).
 gf_status run_batch_graph(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStream_t st,
-                          const Workspace& w, bool tile, int64_t W) {
+                          const Workspace& w, bool tile, int64_t W, const ScanSlices& sl) {
     const gf::HostForest& h = F->host;
     {
         const int64_t tot = int64_t(nb) * F->ld32;
@@ -582,8 +643,7 @@ gf_status run_batch_graph(gf_forest* F, const QueryJob& J, int64_t q0, int nb, h
     if (s != GF_OK) return s;
     const gf::ScanArgs ca = make_scan_args(F, J, q0, nb, w, W);
     if (tile) return launch_tile(F, J, nb, w, W, ca, st, nullptr);
-    GF_HIP(gf::launch_scan(ca, J.form, st));
-    return GF_OK;
+    return launch_rows(F, J, nb, w, ca, sl, st);
 }
 
 // Runs the whole query path for queries [q0, q0 + nb); graph mode as above.
@@ -595,15 +655,16 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     const gf::HostForest& h = F->host;
     Workspace w;
     const bool tile = !scratch && (J.trace_tile || use_tile_path(F, J, nb));
+    const ScanSlices sl = tile ? ScanSlices{} : scan_slices(F, J, nb);
     if (scratch) {
-        ws_bind(F, ws_layout(F, nb, J.k, J.form, false), scratch, J.form, false, w);
+        ws_bind(F, ws_layout(F, nb, J.k, J.form, false, 0, sl.nslice), scratch, J.form, false, w);
     } else {
-        gf_status s0 = get_workspace(F, nb, J.k, J.form, tile, w, J.checks_max);
+        gf_status s0 = get_workspace(F, nb, J.k, J.form, tile, w, J.checks_max, sl.nslice);
         if (s0 != GF_OK) return s0;
     }
     gf_status s = GF_OK;
     const int64_t W = std::max<int64_t>(1, (int64_t{1} << h.H) / 32);
-    if (graph) return run_batch_graph(F, J, q0, nb, st, w, tile, W);
+    if (graph) return run_batch_graph(F, J, q0, nb, st, w, tile, W, sl);
 
     // phase marks (none in the allocation-free mode)
     hipEvent_t ev[6] = {};
@@ -679,7 +740,8 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
         s = launch_tile(F, J, nb, w, W, ca, st, timed ? ev + 3 : nullptr);
         if (s != GF_OK) return s;
     } else {
-        GF_HIP(gf::launch_scan(ca, J.form, st));
+        s = launch_rows(F, J, nb, w, ca, sl, st);
+        if (s != GF_OK) return s;
         GF_HIP(mark_phase(3));
         GF_HIP(mark_phase(4));
     }
@@ -970,7 +1032,9 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
     // Grow every workspace to its largest batch before any capture.
     for (const MultiBatch& b : B) {
         Workspace w;
-        gf_status s = get_workspace(b.F, b.nb, J[b.job].k, J[b.job].form, b.tile, w, J[b.job].checks_max);
+        const ScanSlices sl = b.tile ? ScanSlices{} : scan_slices(b.F, J[b.job], b.nb);
+        gf_status s = get_workspace(b.F, b.nb, J[b.job].k, J[b.job].form, b.tile, w, J[b.job].checks_max,
+                                    sl.nslice);
         if (s != GF_OK) return s;
     }
     auto launch_all = [&](hipStream_t s_) -> gf_status {
@@ -1156,13 +1220,16 @@ gf_status gf_query_noalloc(const gf_forest* Fc, const float* Q, int64_t nq, int3
     gf_forest* F = const_cast<gf_forest*>(Fc);
     J.path = 0;
     // the largest batch whose row-path workspace fits the scratch array
-    const size_t one = ws_layout(F, 1, J.k, J.form, false).need;
+    auto need = [&](int b) {
+        return ws_layout(F, b, J.k, J.form, false, 0, scan_slices(F, J, b).nslice).need;
+    };
+    const size_t one = need(1);
     if (one > kNoAllocScratchBytes)
         return fail(GF_EUNSUPPORTED, "one query's workspace (" + std::to_string(one) +
                                          " bytes) exceeds the 128 MiB scratch of gf_query_noalloc");
-    const size_t per = ws_layout(F, 2, J.k, J.form, false).need - one + 256;
+    const size_t per = ws_layout(F, 2, J.k, J.form, false).need - ws_layout(F, 1, J.k, J.form, false).need + 256;
     int nb = int(std::min<int64_t>(max_batch(F), int64_t((kNoAllocScratchBytes - one) / per) + 1));
-    while (nb > 1 && ws_layout(F, nb, J.k, J.form, false).need > kNoAllocScratchBytes) --nb;
+    while (nb > 1 && need(nb) > kNoAllocScratchBytes) --nb;
     GF_HIP(hipSetDevice(F->device));
     char* base = nullptr;
     if ((s = scratch_base(F->device, &base)) != GF_OK) return s;

@@ -111,11 +111,22 @@ struct ScanArgs {
     float* dists;               // [nq][k]
     uint32_t* cand_bits;        // [nq][ceil(n/32)] or null
     int64_t* ncand;             // [nq] or null
+    // Slices: with nslice > 1 each query's id range is cut into nslice
+    // slices of slice_words bitmap words (a multiple of 16), one workgroup
+    // each; a slice writes its kk best to part_s / part_i
+    // [nq][nslice][kTileList] (rest +inf) for the merge, instead of
+    // finishing the query (cand_bits / ncand need nslice = 1).
+    int nslice;
+    int64_t slice_words;
+    float* part_s;
+    int* part_i;
 };
 
 // Scan kernel launch: one workgroup per query.  Returns hipErrorInvalidValue
 // when the (form, d) combination has no instantiation.
 hipError_t launch_scan(const ScanArgs& a, int form, hipStream_t st);
+// LDS of a scan workgroup whose bitmap covers `words` words (ceil(n/32) unsliced).
+size_t scan_lds_bytes_words(int64_t words, int form, int64_t ld8);
 size_t scan_lds_bytes(int64_t n, int form, int64_t ld8);
 bool scan_supported(int64_t n, int form, int64_t ld8);
 
@@ -157,6 +168,7 @@ struct TileArgs {
 
 struct MergeArgs {
     int nq, k, kk, d, nsplit;
+    bool rerank;                // re-measure the kk in compensated FP32 (reduced-precision scores)
     const float* part_s;
     const int* part_i;
     const float* Q;             // [nq][ldq] FP32 queries
@@ -193,8 +205,9 @@ struct Tile8Args {
     int* part_i;
 };
 int tile8_ntiles(int64_t n);
-// masks, prefix, scores and the per-query selection (nqw = ceil(nq / 32)).
-hipError_t launch_tile8(const Tile8Args& t, int nqw, hipStream_t st);
+// masks, prefix, scores and the per-query selection (nqw = ceil(nq / 32));
+// ev (may be null) gets marks before and after the score kernel.
+hipError_t launch_tile8(const Tile8Args& t, int nqw, hipStream_t st, hipEvent_t* ev);
 // The tile path's merge of per-split lists, FP32 re-rank and FP64 ties.
 hipError_t launch_merge(const MergeArgs& m, hipStream_t st);
 

@@ -210,11 +210,14 @@ __device__ __forceinline__ void finish_query(bool rerank, int kk, int k, int q, 
 // Threads take whole words (32 leaves of one tree) of the query's leaf
 // bitmap, strided by `stride`; each opened leaf is one padded row of pp ids
 // (16-byte aligned, unused slots 0xFFFFFFFF), read as 16-byte vectors, two
-// leaves in flight at a time.  leafbits: [m][W][nq] words.
+// leaves in flight at a time.  leafbits: [m][W][nq] words.  Only ids whose
+// bitmap word lies in [w_lo, w_hi) are kept, at word (id / 32) - w_lo (a
+// slice of the id range).
 __device__ __forceinline__ void expand_opened_leaves(uint32_t* bm, const uint32_t* leafbits, int q,
                                                      int nq, int m, int W, int H,
                                                      const uint32_t* permp, int pp, int first,
-                                                     int stride) {
+                                                     int stride, int64_t w_lo = 0,
+                                                     int64_t w_hi = int64_t(1) << 62) {
     const int64_t nwords = int64_t(m) * W;
     const int64_t nleaf = int64_t(1) << H;      // leaves per tree (rows per tree in permp)
     const int pp4 = pp / 4;
@@ -242,8 +245,11 @@ __device__ __forceinline__ void expand_opened_leaves(uint32_t* bm, const uint32_
                     const uint32_t ids[8] = {va[i].x, va[i].y, va[i].z, va[i].w,
                                              vb[i].x, vb[i].y, vb[i].z, vb[i].w};
 #pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                        if (ids[e] != 0xFFFFFFFFu) atomicOr(&bm[ids[e] >> 5], 1u << (ids[e] & 31u));
+                    for (int e = 0; e < 8; ++e) {
+                        const int64_t wd = int64_t(ids[e] >> 5);
+                        if (ids[e] != 0xFFFFFFFFu && wd >= w_lo && wd < w_hi)
+                            atomicOr(&bm[wd - w_lo], 1u << (ids[e] & 31u));
+                    }
                 }
             }
         }

@@ -137,7 +137,10 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     const int q = blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    const int64_t nbmw = (a.n + 31) / 32;
+    // this workgroup's slice of the id range: bitmap words [w_lo, w_lo + nbmw)
+    const int64_t nbmw_all = (a.n + 31) / 32;
+    const int64_t w_lo = int64_t(blockIdx.y) * a.slice_words;
+    const int64_t nbmw = a.nslice > 1 ? min(a.slice_words, nbmw_all - w_lo) : nbmw_all;
     const int64_t nbmw_pad = (nbmw + kListWords - 1) / kListWords * kListWords;
     uint32_t* bm = smem;                                        // [nbmw_pad]
     uint32_t* lists = bm + nbmw_pad;                            // [kWaves][kListCap]
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     for (int64_t i = threadIdx.x; i < nbmw_pad; i += kThreads) bm[i] = 0u;
     __syncthreads();
     expand_opened_leaves(bm, a.leafbits, q, a.nq, a.m, a.W, a.H, a.permp, a.pp, threadIdx.x,
-                         kThreads);
+                         kThreads, w_lo, w_lo + nbmw);
     __syncthreads();
     if (a.cand_bits) {
         for (int64_t i = threadIdx.x; i < nbmw; i += kThreads)
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
         const int total = __shfl(incl, kListWords - 1);
         if (total == 0) continue;
         int pos = incl - cnt;
-        const uint32_t base = uint32_t(step * kListWords + lane) * 32u;
+        const uint32_t base = uint32_t(w_lo + step * kListWords + lane) * 32u;
         while (w) {
             list[pos++] = base + uint32_t(__builtin_ctz(w));
             w &= w - 1;
@@ -344,7 +347,18 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
             mg_d[lane] = L.d;
             mg_i[lane] = L.id;
         }
+        if (a.nslice > 1) {
+            // a slice hands its kk best (in order) to the merge
+            // (lane e holds entry e of the sorted list; kTileList <= kWave)
+            const int64_t base = (int64_t(q) * a.nslice + blockIdx.y) * kTileList;
+            if (lane < kTileList) {
+                const bool have = lane < kk && L.d < __builtin_inff();
+                a.part_s[base + lane] = have ? L.d : __builtin_inff();
+                a.part_i[base + lane] = have ? L.id : 0x7FFFFFFF;
+            }
+        }
     }
+    if (a.nslice > 1) return;
     __syncthreads();
 
     finish_query(FORM != kFormFP32, kk, a.k, q, a.Q + int64_t(q) * a.ldq, a.X32, a.ld32, a.d,
@@ -359,7 +373,7 @@ template <int FORM>
 hipError_t launch_form(const ScanArgs& a, hipStream_t st, size_t lds) {
     const int64_t nchunks_row = (FORM == kFormFP32) ? (a.ld32 / 4)
                               : (FORM == kFormBF16) ? (a.ld16 / 8) : (a.ld8 / 16);
-    dim3 grid(a.nq), block(kThreads);
+    dim3 grid(a.nq, a.nslice > 1 ? a.nslice : 1), block(kThreads);
 #define GF_TRY(LPRV, CPLV)                                                                   \
     if (nchunks_row <= int64_t(LPRV) * CPLV) {                                               \
         hipError_t e = hipFuncSetAttribute(                                                  \
@@ -399,12 +413,15 @@ hipError_t launch_form(const ScanArgs& a, hipStream_t st, size_t lds) {
 
 }  // namespace
 
-size_t scan_lds_bytes(int64_t n, int form, int64_t ld8) {
-    const int64_t nbmw = (n + 31) / 32;
-    const int64_t nbmw_pad = (nbmw + kListWords - 1) / kListWords * kListWords;
+size_t scan_lds_bytes_words(int64_t words, int form, int64_t ld8) {
+    const int64_t nbmw_pad = (words + kListWords - 1) / kListWords * kListWords;
     // bitmap + per-wave id lists + merge area + re-rank staging (+ FP8 query)
     return size_t(nbmw_pad) * 4 + size_t(kWaves) * kListCap * 4 + size_t(kWaves) * kWave * 8 +
            size_t(kWave) * 4 + (form == kFormFP8 ? size_t(ld8) * 4 : 0);
+}
+
+size_t scan_lds_bytes(int64_t n, int form, int64_t ld8) {
+    return scan_lds_bytes_words((n + 31) / 32, form, ld8);
 }
 
 bool scan_supported(int64_t n, int form, int64_t ld8) {
@@ -412,7 +429,11 @@ bool scan_supported(int64_t n, int form, int64_t ld8) {
 }
 
 hipError_t launch_scan(const ScanArgs& a, int form, hipStream_t st) {
-    const size_t lds = scan_lds_bytes(a.n, form, a.ld8);
+    if (a.nslice > 1 && (a.slice_words % kListWords || a.cand_bits || a.ncand ||
+                         a.slice_words * a.nslice < (a.n + 31) / 32 || !a.part_s || !a.part_i))
+        return hipErrorInvalidValue;
+    const size_t lds = a.nslice > 1 ? scan_lds_bytes_words(a.slice_words, form, a.ld8)
+                                    : scan_lds_bytes(a.n, form, a.ld8);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     switch (form) {
         case kFormFP32: return launch_form<kFormFP32>(a, st, lds);

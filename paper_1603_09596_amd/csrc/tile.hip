@@ -589,7 +589,7 @@ __global__ __launch_bounds__(kMergeMax) void k_merge_rerank(MergeArgs a) {
         }
     }
     __syncthreads();
-    finish_query(true, a.kk, a.k, q, a.Q + int64_t(q) * a.ldq, a.X32, a.ld32, a.d, md, mi, mr, L,
+    finish_query(a.rerank, a.kk, a.k, q, a.Q + int64_t(q) * a.ldq, a.X32, a.ld32, a.d, md, mi, mr, L,
                  a.ids, a.dists);
 }
 

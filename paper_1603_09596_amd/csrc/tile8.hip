@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_topk_select(const float* __restrict__ o
 
 int tile8_ntiles(int64_t n) { return int((n + kTP8 - 1) / kTP8); }
 
-hipError_t launch_tile8(const Tile8Args& t, int nqw, hipStream_t st) {
+hipError_t launch_tile8(const Tile8Args& t, int nqw, hipStream_t st, hipEvent_t* ev) {
     if (t.cw < 4 || t.cw > 32 || t.ld8 % 16 || t.ntiles != tile8_ntiles(t.n) || t.split_tiles < 1 ||
         t.nsplit * t.split_tiles < t.ntiles)
         return hipErrorInvalidValue;
@@ -337,9 +337,11 @@ hipError_t launch_tile8(const Tile8Args& t, int nqw, hipStream_t st) {
     hipLaunchKernelGGL(k_cand_prefix, dim3(unsigned(t.nq)), dim3(256), 0, st,
                        static_cast<const uint64_t*>(t.masks), t.ntiles, t.offs, t.total);
     if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
     const int nqb = (t.nq + kQB - 1) / kQB;
     hipLaunchKernelGGL(k_tile_fp8, dim3(unsigned(nqb * t.nsplit)), dim3(kT8Threads), 0, st, t);
     if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
     hipLaunchKernelGGL(k_topk_select, dim3(unsigned(t.nq)), dim3(256), 0, st,
                        static_cast<const float*>(t.out_s), static_cast<const int*>(t.out_i),
                        static_cast<const uint32_t*>(t.total), t.cap, t.kk, t.part_s, t.part_i);

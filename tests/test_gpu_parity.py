@@ -467,3 +467,28 @@ def test_tile_path_fp8(name, k, c, scan_path):
     print(f"{name} fp8 tile path: recall vs oracle {recall:.4f}, agreement with rows path {agreement:.4f}")
     assert np.array_equal(ids >= 0, ref["ids"] >= 0)
     assert recall >= 0.97 and agreement >= 0.97
+
+
+@pytest.mark.parametrize("name,form,k,c", [("gauss-10k-128", "fp32", 10, 700),
+                                           ("ragged-3001-77", "fp32", 7, 300),
+                                           ("desc-60k-960", "bf16", 10, 4096),
+                                           ("gauss-4k-10000", "fp8", 10, 2048),
+                                           ("gauss-4k-10000", "fp32", 10, 2048)])
+def test_sliced_row_scan_equals_one_workgroup_per_query(name, form, k, c, monkeypatch):
+    """Small batches cut each query's id range into slices (one workgroup
+    each) whose lists are merged: the result must be bit-equal to one
+    workgroup per query, for the default slice count and a forced odd one."""
+    X, Q, Fg, Fo, _ = forests(name, forms=() if form == "fp32" else (form,))
+    monkeypatch.setenv("GF_SCAN_PATH", "rows")
+    out = []
+    for slices in ("1", None, "7"):
+        if slices is None:
+            monkeypatch.delenv("GF_SCAN_SLICES", raising=False)
+        else:
+            monkeypatch.setenv("GF_SCAN_SLICES", slices)
+        ids = np.zeros((len(Q), k), np.int32)
+        dd = np.zeros((len(Q), k), np.float32)
+        geraf.query(Fg, Q, k, c, ids, dd, form=form)
+        out.append((ids, dd))
+    for ids, dd in out[1:]:
+        assert np.array_equal(ids, out[0][0]) and np.array_equal(dd, out[0][1])
