@@ -329,17 +329,25 @@ def vs_oracle(X, Q, ids, dists, ref):
 
 
 def multi_bench(args, torch, geraf, workloads, dev):
-    """The multi-index launch over the multi-20 recipe (FP32 form)."""
+    """The multi-index launch over the multi-20 recipe: FP32 and BF16 jobs
+    (alternating by index), per-query budgets, as one gf_query_multi graph
+    launch (path by rule, then autotuned), as the same launches issued
+    eagerly, and as one gf_query call per index; then every job against the
+    FP64 oracle on a sample of its queries."""
+    import oracle
     t0 = time.perf_counter()
     ws = workloads.multi_index(seed=3, count=20, scale=args.multi_scale)
-    forests = [geraf.build_forest(w.X, w.m, w.t, w.p, w.seed) for w in ws]
+    forms = ["bf16" if i % 2 else "fp32" for i in range(len(ws))]
+    forests = [geraf.build_forest(w.X, w.m, w.t, w.p, w.seed, forms=() if f == "fp32" else (f,))
+               for w, f in zip(ws, forms)]
     log(f"[bench] multi-20 x{args.multi_scale}: {sum(len(w.Q) for w in ws)} queries over "
-        f"{len(ws)} indexes, data + forests {time.perf_counter() - t0:.1f}s")
+        f"{len(ws)} indexes, {sum(w.X.nbytes for w in ws) / 1e9:.1f} GB of rows, data + forests "
+        f"{time.perf_counter() - t0:.1f}s")
     jobs = []
-    for w, F in zip(ws, forests):
+    for w, F, f in zip(ws, forests, forms):
         nq = len(w.Q)
         jobs.append(dict(forest=F, Q=torch.from_numpy(w.Q).to(dev), k=w.k, checks=1,
-                         checks_per_query=torch.from_numpy(w.checks).to(dev), form="fp32",
+                         checks_per_query=torch.from_numpy(w.checks).to(dev), form=f,
                          ids=torch.empty((nq, w.k), dtype=torch.int32, device=dev),
                          dists=torch.empty((nq, w.k), dtype=torch.float32, device=dev)))
     total = sum(len(w.Q) for w in ws)
@@ -347,9 +355,10 @@ def multi_bench(args, torch, geraf, workloads, dev):
     def per_index():
         for j in jobs:
             geraf.query(j["forest"], j["Q"], j["k"], 1, j["ids"], j["dists"],
-                        checks_per_query=j["checks_per_query"], form="fp32")
+                        checks_per_query=j["checks_per_query"], form=j["form"])
 
     modes = {"graph": lambda: geraf.query_multi(jobs),
+             "graph_autotuned": lambda: geraf.query_multi(jobs, autotune=True),
              "eager": lambda: geraf.query_multi(jobs, eager=True),
              "per_index_calls": per_index}
     res = {}
@@ -364,18 +373,49 @@ def multi_bench(args, torch, geraf, workloads, dev):
         dt = (time.perf_counter() - t0) / args.steps
         res[name] = dict(value=round(total / dt, 2), ms_per_step=round(dt * 1e3, 3))
         log(f"[bench] multi {name}: {dt * 1e3:.2f} ms per step, {total / dt:.0f} queries/s")
+    # every job against the oracle on a sample of its queries (graph results)
+    geraf.query_multi(jobs)
+    torch.cuda.synchronize()
+    parity = []
+    t0 = time.perf_counter()
+    for w, j, f in zip(ws, jobs, forms):
+        Fo = oracle.build_forest(w.X, w.m, w.t, w.p, w.seed, nthreads=host_threads())
+        got_i, got_d = j["ids"].cpu().numpy(), j["dists"].cpu().numpy()
+        sample = np.linspace(0, len(w.Q) - 1, min(len(w.Q), args.multi_sample)).astype(np.int64)
+        hits = total_ref = 0
+        max_err = 0.0
+        not_cand = 0
+        for i in sample:
+            Qs = np.ascontiguousarray(w.Q[i:i + 1])
+            ref = oracle.search(Fo, w.X, Qs, w.k, int(w.checks[i]), trace=False, candidates=True,
+                                nthreads=1)
+            g = got_i[i][got_i[i] >= 0]
+            not_cand += int((~np.isin(g, ref["cand"][0])).sum())
+            r = ref["ids"][0][ref["ids"][0] >= 0]
+            hits += len(set(g.tolist()) & set(r.tolist()))
+            total_ref += len(r)
+            for rr, gid in enumerate(g.tolist()):
+                diff = w.X[gid].astype(np.float64) - Qs[0].astype(np.float64)
+                true_d = float(diff @ diff)
+                max_err = max(max_err, abs(float(got_d[i][rr]) - true_d) / true_d if true_d > 0 else 0.0)
+        parity.append(dict(index=w.name, form=f, n=int(w.X.shape[0]), d=int(w.X.shape[1]),
+                           queries=len(sample), recall_vs_oracle=round(hits / max(1, total_ref), 4),
+                           max_rel_dist_err=float(f"{max_err:.3g}"), ids_not_candidates=not_cand))
+    log(f"[bench] multi oracle comparison {time.perf_counter() - t0:.1f}s")
     out = {
         "metric": "queries/s over a batch of 20 indexes with per-query budgets (multi-20)",
         "value": res["graph"]["value"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": res["graph"]["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
         "data": "synthetic",
         "config": {"workload": "multi-20", "scale": args.multi_scale, "indexes": len(ws),
                    "queries": total, "n": [len(w.X) for w in ws], "d": [w.X.shape[1] for w in ws],
-                   "m": 8, "t": 5, "leaf": 16, "k": 10, "checks": "uniform 256..8192 per query",
-                   "form": "fp32"},
-        "eager": res["eager"], "per_index_calls": res["per_index_calls"],
+                   "forms": forms, "m": 8, "t": 5, "leaf": 16, "k": 10,
+                   "checks": "uniform 256..8192 per query"},
+        "graph_autotuned": res["graph_autotuned"], "eager": res["eager"],
+        "per_index_calls": res["per_index_calls"],
         "graph_stats": geraf.multi_stats(),
+        "vs_oracle": parity,
     }
     print(json.dumps(out), flush=True)
     for F in forests:
@@ -410,8 +450,10 @@ def main():
                          "or recall against the budget c on desc-1m-960")
     ap.add_argument("--multi", action="store_true",
                     help="measure the multi-index launch (multi-20 recipe) instead")
-    ap.add_argument("--multi-scale", type=float, default=0.25,
+    ap.add_argument("--multi-scale", type=float, default=1.0,
                     help="size factor of the multi-20 indexes and query counts")
+    ap.add_argument("--multi-sample", type=int, default=4,
+                    help="queries per index compared with the FP64 oracle")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a plain copy "
                          "kernel of known size that scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -580,8 +622,11 @@ def main():
                     geraf.query(F, Qb, k, c, ib, db, form=form)
                 torch.cuda.synchronize()
                 dt = (time.perf_counter() - t0) / reps
+                tm = geraf.last_query_timing()
                 row[f"{path}_ms"] = round(1e3 * dt, 3)
                 row[f"{path}_qps"] = round(b / dt, 1)
+                row[f"{path}_phases_ms"] = [round(tm[key], 3) for key in
+                                            ("prep_ms", "select_ms", "scan_or_expand_ms", "tile_ms", "merge_ms")]
             os.environ.pop("GF_SCAN_PATH", None)
             small.append(row)
             log(f"[bench] small batch {row}")

@@ -179,16 +179,19 @@ typedef struct gf_job {
     float *dists;                      /* [nq][k] float32, device */
 } gf_job;
 
-#define GF_MULTI_AUTOTUNE 1u  /* measure row vs tile path per (forest, form, batch size) once */
+#define GF_MULTI_AUTOTUNE 1u  /* measure the launch variants per (forest, form, batch size) once */
 #define GF_MULTI_EAGER 2u     /* launch kernel by kernel instead of one graph launch */
 
 /* Run many searches, over many forests of uneven n and d and with per-query
  * budgets, as one launch (the batching the paper's Sec. 5 leaves for future
  * work).  Every job gives the same results as gf_query with the same
  * arguments and the same path; the path of each 16,384-query batch follows
- * gf_query's rule, or with GF_MULTI_AUTOTUNE the faster of the two as
+ * gf_query's rule, or with GF_MULTI_AUTOTUNE the fastest launch variant as
  * measured on the first batch of each (forest, form, batch-size class,
- * rerank), a choice the forest then keeps.
+ * rerank), a choice the forest then keeps.  The variants are the row path
+ * with 1, 2 or 4 times the rule's slices of each query's id range (one
+ * workgroup per slice) and, where the form has one, the tile path; they give
+ * identical results.
  * All query rows are checked finite first (one readback for the call).  The
  * launches of every batch are then captured into one HIP graph, which runs on
  * `stream`: the batches of one forest in order on one branch (they share the

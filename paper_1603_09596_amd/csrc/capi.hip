@@ -385,6 +385,7 @@ struct QueryJob {
     uint32_t* leaf_bits; uint32_t* cand_bits; int64_t* ncand; bool trace_dev;
     int path = -1;             // -1 by rule, 0 rows, 1 tile (when eligible)
     bool trace_tile = false;   // trace: candidates as the tile path builds them
+    int slice_mult = 1;        // row path: slices per query times this (autotuner)
 };
 
 // Whether a batch takes the tile path (BF16 scores of whole query blocks on
@@ -444,6 +445,7 @@ ScanSlices scan_slices(const gf_forest* F, const QueryJob& J, int nb) {
     } else {
         const int64_t cus = device_cus();
         if (int64_t(nb) < 2 * cus) want = std::min<int64_t>(256, (2 * cus + nb - 1) / nb);
+        want = std::min<int64_t>(256, want * std::max(1, J.slice_mult));
     }
     if (want <= 1) return r;
     int64_t words = (nbmw + want - 1) / want;
@@ -913,7 +915,12 @@ struct MultiBatch {
     int64_t q0;
     int nb;
     bool tile;
+    int slice_mult;
 };
+
+// Launch variants the autotuner measures: the row path with 1, 2 or 4 times
+// the rule's slices per query, and the tile path where the job has one.
+constexpr int kTuneVariants = 4;
 
 // Batch-size class of the autotuner (powers of two).
 int size_class(int nb) {
@@ -999,40 +1006,53 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
             const int nb = int(std::min<int64_t>(mb, jobs[i].nq - q0));
             QueryJob Jb = J[i];
             bool tile = use_tile_path(F, Jb, nb);
-            if ((flags & GF_MULTI_AUTOTUNE) && tile_eligible(F, Jb)) {
+            int mult = 1;
+            if (flags & GF_MULTI_AUTOTUNE) {
                 const uint64_t key = (uint64_t(Jb.form) << 40) | (uint64_t(size_class(nb)) << 32) | uint64_t(Jb.kk);
                 auto it = F->tuned.find(key);
                 if (it == F->tuned.end()) {
-                    float ms[2] = {0.0f, 0.0f};
+                    float ms[kTuneVariants];
+                    int best = 0;
                     hipEvent_t e0, e1;
                     GF_HIP(hipEventCreate(&e0));
                     GF_HIP(hipEventCreate(&e1));
                     gf_status s = GF_OK;
-                    for (int path = 0; path < 2 && s == GF_OK; ++path) {
-                        Jb.path = path;
+                    for (int v = 0; v < kTuneVariants && s == GF_OK; ++v) {
+                        ms[v] = 1e30f;
+                        if (v == 3 && !tile_eligible(F, Jb)) continue;
+                        Jb.path = v == 3 ? 1 : 0;
+                        Jb.slice_mult = v == 3 ? 1 : (1 << v);
+                        // the workspace may grow for this variant: not inside the timing
+                        Workspace wtmp;
+                        const ScanSlices sl = v == 3 ? ScanSlices{} : scan_slices(F, Jb, nb);
+                        s = get_workspace(F, nb, Jb.k, Jb.form, v == 3, wtmp, Jb.checks_max, sl.nslice);
                         for (int rep = 0; rep < 2 && s == GF_OK; ++rep) {   // first run warms up
                             (void)hipEventRecord(e0, st);
                             s = run_batch(F, Jb, q0, nb, st, true);
                             (void)hipEventRecord(e1, st);
                             (void)hipEventSynchronize(e1);
                         }
-                        (void)hipEventElapsedTime(&ms[path], e0, e1);
+                        (void)hipEventElapsedTime(&ms[v], e0, e1);
+                        if (ms[v] < ms[best]) best = v;
                     }
                     (void)hipEventDestroy(e0);
                     (void)hipEventDestroy(e1);
                     if (s != GF_OK) return s;
-                    it = F->tuned.emplace(key, ms[1] < ms[0] ? 1 : 0).first;
+                    it = F->tuned.emplace(key, best).first;
                     g_tuned.fetch_add(1);
                 }
-                tile = it->second == 1;
+                tile = it->second == 3;
+                mult = tile ? 1 : (1 << it->second);
             }
-            B.push_back(MultiBatch{F, i, q0, nb, tile});
+            B.push_back(MultiBatch{F, i, q0, nb, tile, mult});
         }
     }
     // Grow every workspace to its largest batch before any capture.
     for (const MultiBatch& b : B) {
         Workspace w;
-        const ScanSlices sl = b.tile ? ScanSlices{} : scan_slices(b.F, J[b.job], b.nb);
+        QueryJob Jb = J[b.job];
+        Jb.slice_mult = b.slice_mult;
+        const ScanSlices sl = b.tile ? ScanSlices{} : scan_slices(b.F, Jb, b.nb);
         gf_status s = get_workspace(b.F, b.nb, J[b.job].k, J[b.job].form, b.tile, w, J[b.job].checks_max,
                                     sl.nslice);
         if (s != GF_OK) return s;
@@ -1041,6 +1061,7 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
         for (const MultiBatch& b : B) {
             QueryJob Jb = J[b.job];
             Jb.path = b.tile ? 1 : 0;
+            Jb.slice_mult = b.slice_mult;
             gf_status s = run_batch(b.F, Jb, b.q0, b.nb, s_, true);
             if (s != GF_OK) return s;
         }
@@ -1061,6 +1082,7 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
                                  uint64_t(uintptr_t(j.ids)), uint64_t(uintptr_t(j.dists)),
                                  uint64_t(b.q0), uint64_t(b.nb), uint64_t(j.k), uint64_t(uint32_t(j.checks)),
                                  uint64_t(J[b.job].kk), uint64_t(j.form), uint64_t(b.tile),
+                                 uint64_t(b.slice_mult),
                                  uint64_t(std::llround(j.eps * 1e12))};
         key.insert(key.end(), std::begin(vals), std::end(vals));
         uids.push_back(b.F->uid);
@@ -1108,6 +1130,7 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
             const int g = int(std::lower_bound(Fs.begin(), Fs.end(), b.F) - Fs.begin()) % nbr;
             QueryJob Jb = J[b.job];
             Jb.path = b.tile ? 1 : 0;
+            Jb.slice_mult = b.slice_mult;
             s = run_batch(b.F, Jb, b.q0, b.nb, br[g], true);
         }
         for (int i = 0; i < nbr && eb == hipSuccess; ++i) {
