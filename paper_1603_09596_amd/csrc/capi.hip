@@ -391,9 +391,10 @@ struct QueryJob {
 // Whether a batch takes the tile path (BF16 scores of whole query blocks on
 // MFMA, masked by each query's candidate bitmap) instead of per-query row
 // gathers.  The tile path computes nb * n scores at MFMA rate; the gather
-// path reads every candidate's row from HBM.  It pays off once the batch
-// fills 128-query blocks and each query's candidates are more than ~1/256
-// of the points.  GF_SCAN_PATH=rows|tile forces a path.
+// path reads every candidate's row from HBM.  It pays off once each query's
+// candidates are more than ~1/256 of the points and the batch is large
+// enough to amortise scoring every point (16 queries for BF16, 512 for FP8,
+// measured).  GF_SCAN_PATH=rows|tile forces a path.
 //
 // The FP8 form has a tile path of its own (tile8.hip) for wide rows: dense
 // FP8 scores of 128-query blocks against 128-point tiles, the candidates'
@@ -416,7 +417,10 @@ bool use_tile_path(const gf_forest* F, const QueryJob& J, int nb) {
     const char* env = std::getenv("GF_SCAN_PATH");
     if (env && std::strcmp(env, "rows") == 0) return false;
     if (env && std::strcmp(env, "tile") == 0) return true;
-    if (nb < 128) return false;
+    // batch sizes from which the tile path measured faster (1M x 960 BF16:
+    // 5.4 vs 7.0 ms at 16 queries; 200k x 10,000 FP8: 12.1 vs 26.6 ms at 1,024
+    // queries, 11.4 vs 4.7 ms at 128)
+    if (nb < (J.form == gf::kFormFP8 ? 512 : 16)) return false;
     const double leaf_pts = double(F->host.n) / double(int64_t{1} << F->host.H);
     const double cand_est = J.checks_mean * leaf_pts * 0.5;
     return cand_est * (J.form == gf::kFormFP8 ? 192.0 : 256.0) >= double(F->host.n);
