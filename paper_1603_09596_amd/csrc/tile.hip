@@ -17,14 +17,18 @@
 //                    opened it, in chunks of up to 1024 queries.
 //   k_expand_points  one row per point: the OR of the rows of the m leaves
 //                    holding it = the queries having the point as candidate.
-//   k_tile_bf16      grid (query blocks of 128, point splits): each wave keeps
-//                    its 16 queries' BF16 rows in registers as MFMA A operands;
-//                    64-point x 256-k stages of X stream into three LDS buffers
-//                    with direct global->LDS loads (two stages in flight) as
-//                    B operands; the epilogue masks by the candidate bits and
-//                    keeps, per query and split, the `cap` best (score, id) pairs
-//                    in registers, three on each of the 16 lanes that hold
-//                    that query's row of the MFMA result.
+//   k_tile_bf16      grid (query blocks of 128, point splits): the waves work in
+//                    pairs on 32 queries each, one wave of a pair holding the
+//                    BF16 rows' even k steps and the other the odd ones in
+//                    registers as MFMA A operands, so every B fragment read
+//                    from LDS feeds two MFMAs; 64-point x 256-k stages of X
+//                    stream into three LDS buffers with direct global->LDS
+//                    loads (two stages in flight) as B operands.  After a tile
+//                    the two waves swap half their partial sums through LDS,
+//                    and each finishes 16 queries: the epilogue masks by the
+//                    candidate bits and keeps, per query and split, the `cap`
+//                    best (score, id) pairs in registers, three on each of the
+//                    16 lanes that hold that query's row of the MFMA result.
 //   k_merge_rerank   one workgroup per query: best `kk` over the splits, then
 //                    FP32 compensated re-rank and FP64 tie re-check.
 #include <hip/hip_runtime.h>
@@ -44,7 +48,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTWaves = 8;
 constexpr int kTThreads = kTWaves * kWave;
-constexpr int kTQ = kTWaves * 16;     // queries per workgroup
+constexpr int kTQ = kTWaves * 16;     // queries per workgroup (32 per wave pair)
 constexpr int kTP = 64;               // points per tile
 constexpr int kSlots = 3;             // list entries per lane and query (x 16 lanes)
 constexpr int kExpandThreads = 1024;
@@ -113,6 +117,8 @@ __device__ __forceinline__ void quarter_offer(bool cand, float sc, int id, float
 
 // s_waitcnt immediates (gfx9 encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] at 15:14)
 constexpr int kWaitVm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
+// the same with every LDS access of this wave complete as well (lgkmcnt 0)
+constexpr int kWaitVmLds(int n) { return (n & 15) | (7 << 4) | (((n >> 4) & 3) << 14); }
 
 constexpr int kKS = 256;                               // k (bf16 elements) per pipeline stage
 constexpr int kNBuf = 3;                               // LDS stages (prefetch distance kNBuf - 1)
@@ -174,18 +180,26 @@ __device__ __forceinline__ void dma_4_dev(const void* g, uint32_t lds) {
 }
 
 // KSTEPS k steps of 32 (the row length rounded up; steps past the row have
-// zero A operands), in stages of kKS per tile.
+// zero A operands), in stages of kKS per tile.  Waves w and w + 4 form pair
+// w & 3 over queries 32 (w & 3) .. + 32 of the block; wave half = w >> 2
+// holds the k steps of parity `half` of both 16-query groups.
 template <int KSTEPS>
 __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
+    static_assert(KSTEPS % 2 == 0, "the k steps split evenly between the waves of a pair");
     constexpr int kSteps = kKS / 32;
+    constexpr int kHalf = kSteps / 2;            // k steps per wave and stage
+    constexpr int KH = KSTEPS / 2;               // k steps per wave and tile
     constexpr int NC = (KSTEPS + kSteps - 1) / kSteps;
     // X stages: row r of a stage holds its kUnits k units (16 B each) at
     // positions unit ^ (r & 15), so the contiguous 1 KB writes of the direct
     // loads and the 16-row B-operand reads are both free of bank conflicts.
     __shared__ __attribute__((aligned(1024))) uint16_t xs[kNBuf * kStageBytes / 2];
     __shared__ __attribute__((aligned(1024))) uint32_t epi[kEpi];
+    // partial sums handed to the other wave of the pair: [wave][block][lane]
+    __shared__ __attribute__((aligned(16))) f4 xch[kTWaves * 4 * kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
+    const int pair = wave & 3, half = wave >> 2;
     const int quarter = lane >> 4, col = lane & 15;
     // Workgroups are dispatched to the XCDs round-robin (workgroup i to XCD
     // i % kXcds).  Each XCD takes a consecutive run of the (split, query
@@ -201,21 +215,28 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         split = L / nqb;
         qblk = L - split * nqb;
     }
-    const int q0 = qblk * kTQ + wave * 16;
+    const int qp = qblk * kTQ + pair * 32;       // the pair's first query
+    const int q0 = qp + 16 * half;               // the 16 queries this wave finishes
     const int ks = int(a.ld16 / 32);
 
-    // A operands: query row q0 + col, elements k = 32 s + 8 quarter .. + 8
-    bf16x8 qa[KSTEPS];
+    // A operands: group g's query row qp + 16 (g ^ half) + col (group 0 is
+    // the one this wave finishes), k step S = 2 j + half, elements
+    // k = 32 S + 8 quarter .. + 8
+    bf16x8 qa[2][KH];
     {
-        const int qrow = q0 + col;
 #pragma unroll
-        for (int s = 0; s < KSTEPS; ++s) {
-            if (qrow < a.nq && s < ks) {
-                const uint4 v = *reinterpret_cast<const uint4*>(a.Q16 + int64_t(qrow) * a.ld16 +
-                                                                32 * s + 8 * quarter);
-                qa[s] = __builtin_bit_cast(bf16x8, v);
-            } else {
-                qa[s] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+        for (int g = 0; g < 2; ++g) {
+            const int qrow = qp + 16 * (g ^ half) + col;
+#pragma unroll
+            for (int j = 0; j < KH; ++j) {
+                const int S = 2 * j + half;
+                if (qrow < a.nq && S < ks) {
+                    const uint4 v = *reinterpret_cast<const uint4*>(a.Q16 + int64_t(qrow) * a.ld16 +
+                                                                    32 * S + 8 * quarter);
+                    qa[g][j] = __builtin_bit_cast(bf16x8, v);
+                } else {
+                    qa[g][j] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+                }
             }
         }
     }
@@ -253,27 +274,29 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     // load rows kRowsPerInst inst ..; lane l loads k unit
     // (l % kUnits) ^ (row & 15) of row kRowsPerInst inst + l / kUnits.  Rows
     // past the split and k past the row are clamped to valid addresses; that
-    // data is never used.
-    int drow[kDmaPerWave];
-    uint32_t dk[kDmaPerWave], trow[kDmaPerWave];
-#pragma unroll
-    for (int j = 0; j < kDmaPerWave; ++j) {
-        const int inst = wave + kTWaves * j;
-        drow[j] = kRowsPerInst * inst + lane / kUnits;
-        dk[j] = uint32_t(((lane % kUnits) ^ (drow[j] & 15)) * 8);
-    }
-    // B-operand LDS element offsets within a stage for k step s (block b
-    // adds 16 kKS b): row col, unit (4 s + quarter) ^ col
-    int ldsel[kSteps];
-#pragma unroll
-    for (int s = 0; s < kSteps; ++s) ldsel[s] = col * kKS + (((4 * s + quarter) ^ col) * 8);
+    // data is never used.  Row kRowsPerInst (wave + kTWaves j) + l / kUnits is
+    // 16 j rows past instruction 0's, so every instruction of a lane loads the
+    // same k unit.
+    static_assert(kRowsPerInst * kTWaves == 16, "instruction j loads rows 16 j past instruction 0's");
+    const int drow0 = kRowsPerInst * wave + lane / kUnits;
+    const uint32_t dk = uint32_t(((lane % kUnits) ^ (drow0 & 15)) * 8);
+    uint32_t trow[kDmaPerWave];
+    // B-operand LDS element offsets within a stage for this wave's k step j
+    // (stage step 2 j + half; block b adds 16 kKS b): row col, unit
+    // u = (4 (2 j + half) + quarter) ^ col.  With y = 4 half + quarter < 8,
+    // u = 8 (j ^ (col >> 3)) + (y ^ (col & 7)), so steps j and j + 2 lie
+    // 16 units apart and two lane offsets serve all four steps.
+    static_assert(kHalf == 4, "four k steps per wave and stage");
+    const int lsel0 = col * kKS + 8 * ((4 * half + quarter) ^ (col & 7)) + 64 * (col >> 3);
+    const int lsel1 = col * kKS + 8 * ((4 * half + quarter) ^ (col & 7)) + 64 * (1 - (col >> 3));
+    auto ldsel = [&](int j) { return ((j & 1) ? lsel1 : lsel0) + 128 * (j >> 1); };
 
     // issue cursor: the next stage to load is chunk ic of tile it, into ibuf
     int it = 0, ic = 0, ibuf = 0;
     auto set_rows = [&]() {
 #pragma unroll
         for (int j = 0; j < kDmaPerWave; ++j) {
-            const int r = it * kTP + drow[j];
+            const int r = it * kTP + drow0 + 16 * j;
             trow[j] = uint32_t(r < npts ? r : 0) * rowbytes;
         }
     };
@@ -281,7 +304,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         const uint32_t dst = xs0 + uint32_t(ibuf) * kStageBytes;
 #pragma unroll
         for (int j = 0; j < kDmaPerWave; ++j) {
-            const uint32_t k = uint32_t(ic * kKS) + dk[j];
+            const uint32_t k = uint32_t(ic * kKS) + dk;
             const uint32_t koff = k < uint32_t(a.ld16) ? 2u * k : 0u;
             dma_16s(xbase, trow[j] + koff, dst + uint32_t(wave + kTWaves * j) * 1024u);
         }
@@ -309,13 +332,17 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     set_rows();
     for (int p = 0; p < kNBuf - 1 && it < ntile; ++p) issue_next();
 
-    const int wv = wave >> 1;                       // this wave's candidate word
-    const int bit0 = 16 * (wave & 1) + 4 * quarter;  // bit of query q0 + 4 quarter
+    const int wv = pair;                            // the pair's candidate word
+    const int bit0 = 16 * half + 4 * quarter;       // bit of query q0 + 4 quarter
+    f4* const xout = xch + wave * 4 * kWave + lane;
+    const int xdelta = half ? -4 * 4 * kWave : 4 * 4 * kWave;   // to the partner's slot
     int buf = 0, left = ntile * NC;                  // stages not yet consumed
     for (int t = 0; t < ntile; ++t) {
-        f4 acc[4];
+        f4 acc[2][4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[g][b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             // Loads complete in issue order.  After the current stage's
@@ -332,28 +359,29 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
             const uint16_t* xb = xs + buf * (kStageBytes / 2);
-            // B fragments run two k steps ahead of the MFMAs that use them
-            uint4 v[2][4];
+            // B fragments run one k step ahead of the MFMAs that use them:
+            // block b's next fragment is read as soon as both query groups'
+            // MFMAs have taken the current one
+            uint4 v[4];
+            if (c * kHalf < KH)
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
-                if (c * kSteps + s < KSTEPS)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        v[s][b] = *reinterpret_cast<const uint4*>(xb + ldsel[s] + 16 * kKS * b);
+                for (int b = 0; b < 4; ++b)
+                    v[b] = *reinterpret_cast<const uint4*>(xb + ldsel(0) + 16 * kKS * b);
             // keep the scheduler from sinking the reads down to their uses
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int s = 0; s < kSteps; ++s) {
-                const int S = c * kSteps + s;
-                if (S < KSTEPS) {
+            for (int s = 0; s < kHalf; ++s) {
+                const int J = c * kHalf + s;
+                if (J < KH) {
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            qa[S], __builtin_bit_cast(bf16x8, v[s & 1][b]), acc[b], 0, 0, 0);
-                    if (s + 2 < kSteps && S + 2 < KSTEPS)
+                    for (int b = 0; b < 4; ++b) {
 #pragma unroll
-                        for (int b = 0; b < 4; ++b)
-                            v[s & 1][b] = *reinterpret_cast<const uint4*>(xb + ldsel[s + 2] + 16 * kKS * b);
+                        for (int g = 0; g < 2; ++g)
+                            acc[g][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                qa[g][J], __builtin_bit_cast(bf16x8, v[b]), acc[g][b], 0, 0, 0);
+                        if (s + 1 < kHalf && J + 1 < KH)
+                            v[b] = *reinterpret_cast<const uint4*>(xb + ldsel(s + 1) + 16 * kKS * b);
+                    }
                 }
                 if (s == 0) {
                     // the next loads go out once the MFMA pipe is busy (their
@@ -370,14 +398,27 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         // the loads of the stage kNBuf - 1 ahead.  With NC > kNBuf stages per
         // tile the wait before the last stage's barrier (for that stage's
         // loads, issued later) already covered them in every wave.  Shorter
-        // tiles wait here for everything.
+        // tiles wait for everything before the barrier of the swap below.
         static_assert(kNBuf == 3, "the epilogue-load argument counts three buffers");
-        if (NC <= kNBuf) {
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_s_waitcnt(kWaitVm(0));
-            __builtin_amdgcn_s_barrier();
-            asm volatile("" ::: "memory");
+        // Swap: this wave hands its partial sums of the other group to its
+        // partner and adds the partner's partial sums of its own group, so
+        // each score is (even k steps) + (odd k steps) in FP32 whichever wave
+        // finishes it.  The partner reads this wave's slot before it reaches
+        // the next tile's first barrier, and this wave writes it again only
+        // after that barrier.
+        f4 sum[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            xout[b * kWave] = acc[1][b];
+            sum[b] = acc[0][b];
         }
+        asm volatile("" ::: "memory");
+        if (NC <= kNBuf) __builtin_amdgcn_s_waitcnt(kWaitVmLds(0));
+        else __builtin_amdgcn_s_waitcnt(kWaitVmLds(63));
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int b = 0; b < 4; ++b) sum[b] += xout[xdelta + b * kWave];
         // epilogue: C[row 4 quarter + i][col] of block b = q(row) . x(16 b + col).
         // A point enters a query's list only if it is a candidate of the
         // query and its score is at most both the list's worst and the
@@ -392,17 +433,17 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             word[b] = xl < npts ? w : 0u;
             const float nx = __uint_as_float(epi[kEpiNorm + 16 * b + col]);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[b][i] = nx - 2.0f * acc[b][i];   // scores
+            for (int i = 0; i < 4; ++i) sum[b][i] = nx - 2.0f * sum[b][i];   // scores
         }
         float lim[4], bm[4];
         bool any = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            lim[i] = fminf(ts[i], key_score(epi[kEpiThr + wave * 16 + 4 * quarter + i]));
+            lim[i] = fminf(ts[i], key_score(epi[kEpiThr + q0 - qblk * kTQ + 4 * quarter + i]));
             bm[i] = __builtin_inff();
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                bm[i] = (((word[b] >> i) & 1u) && acc[b][i] < bm[i]) ? acc[b][i] : bm[i];
+                bm[i] = (((word[b] >> i) & 1u) && sum[b][i] < bm[i]) ? sum[b][i] : bm[i];
             any = any || bm[i] <= lim[i];
         }
         // Only queries with a candidate at or below their limit in this tile
@@ -414,13 +455,13 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const int x = int(pb) + t * kTP + 16 * b + col;
-                    const bool cand = ((word[b] >> i) & 1u) && acc[b][i] <= lim[i];
-                    quarter_offer(cand, acc[b][i], x, ls[i], li[i], ts[i], ti[i]);
+                    const bool cand = ((word[b] >> i) & 1u) && sum[b][i] <= lim[i];
+                    quarter_offer(cand, sum[b][i], x, ls[i], li[i], ts[i], ti[i]);
                     lim[i] = fminf(lim[i], ts[i]);
                 }
                 // publish a full list's worst score as a bound for the other splits
                 const int q = q0 + 4 * quarter + i;
-                const float g = key_score(epi[kEpiThr + wave * 16 + 4 * quarter + i]);
+                const float g = key_score(epi[kEpiThr + q0 - qblk * kTQ + 4 * quarter + i]);
                 if (col == 0 && q < a.nq && ts[i] < g) atomicMin(a.gthr + q, score_key(ts[i]));
             }
         }

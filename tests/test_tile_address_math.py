@@ -6,12 +6,13 @@ itself: per stage, instruction j of wave w has lane l read 16 bytes at byte
 offset trow[j] + koff of its split's rows and write them at LDS byte
 xs0 + buf * 32 KiB + (w + 8 j) * 1 KiB + 16 l; per tile, waves 0..3 load
 the candidate words, the norms and the block's shared bounds into the
-epilogue area.  This test recomputes those offsets with the kernel's
+epilogue area, and the two waves of each pair swap partial sums through a
+32 KiB exchange area.  This test recomputes those offsets with the kernel's
 formulas for every configuration launch_tile_path admits (the row stride,
 the template k depth, ragged point counts and splits, query chunkings) and
 asserts that every global access lies inside its buffer and every LDS target
 inside the kernel's static allocation (3 x 32 KiB stages + 448-word
-epilogue area = 97.75 KiB).  No GPU."""
+epilogue area + 32 KiB exchange = 129.75 KiB).  No GPU."""
 import numpy as np
 import pytest
 
@@ -22,7 +23,8 @@ KROWS_PER_INST = KWAVE // KUNITS            # rows per 1 KiB wave instruction
 KDMA_PER_WAVE = KSTAGE // 1024 // KTWAVES   # 4
 KEPI_VIS, KEPI_NORM, KEPI_THR = 0, 4 * KTP, 5 * KTP
 KEPI_WORDS = 5 * KTP + KTQ
-LDS_BYTES = KNBUF * KSTAGE + 4 * KEPI_WORDS
+KXCH_BYTES = KTWAVES * 4 * KWAVE * 16      # f4 partial sums [wave][block][lane]
+LDS_BYTES = KNBUF * KSTAGE + 4 * KEPI_WORDS + KXCH_BYTES
 KSTEPS_TEMPLATES = (4, 8, 12, 16, 20, 24, 28, 30, 32)
 
 
@@ -56,8 +58,13 @@ def check_stage_loads(n, ld16, split_pts):
     wave = np.arange(KTWAVES)[:, None, None]
     j = np.arange(KDMA_PER_WAVE)[None, :, None]
     inst = wave + KTWAVES * j
-    drow = KROWS_PER_INST * inst + lane // KUNITS
-    dk = ((lane % KUNITS) ^ (drow & 15)) * 8
+    # the kernel's form: instruction 0's row and k unit, rows 16 j further on
+    drow0 = KROWS_PER_INST * wave + lane // KUNITS
+    drow = drow0 + 16 * j
+    dk = ((lane % KUNITS) ^ (drow0 & 15)) * 8
+    # ... which is the swizzle of every instruction's own row
+    assert (drow == KROWS_PER_INST * inst + lane // KUNITS).all()
+    assert (dk == ((lane % KUNITS) ^ (drow & 15)) * 8).all()
     lds_hi = 0
     # interior splits are full splits shifted by whole splits: the first two
     # and the last two bound every one of them
@@ -118,9 +125,41 @@ def check_epilogue_loads(n, nq, cw, split_pts):
                 assert (4 * KEPI_NORM + 4 * lane + 4).max() <= 4 * KEPI_THR
 
 
-def test_static_lds_allocation_is_97_75_kib():
-    assert LDS_BYTES == 3 * 32768 + 1792
+def test_static_lds_allocation_is_129_75_kib():
+    assert LDS_BYTES == 3 * 32768 + 1792 + 32768
     assert LDS_BYTES <= 160 * 1024
+
+
+def test_pair_swap_stays_inside_the_exchange_area():
+    """Wave w writes its other group's partial sums of block b at f4 slot
+    (4 w + b) 64 + lane and reads its partner's (w ^ 4) slot, 16 KiB away."""
+    lane = np.arange(KWAVE)
+    seen = np.zeros(KTWAVES * 4 * KWAVE, dtype=int)
+    for w in range(KTWAVES):
+        half = w >> 2
+        xdelta = -4 * 4 * KWAVE if half else 4 * 4 * KWAVE
+        for b in range(4):
+            wr = (4 * w + b) * KWAVE + lane
+            rd = wr + xdelta
+            assert wr.min() >= 0 and wr.max() < KTWAVES * 4 * KWAVE
+            assert (rd == (4 * (w ^ 4) + b) * KWAVE + lane).all()
+            seen[wr] += 1
+    assert (seen == 1).all()          # every slot has exactly one writer
+
+
+def test_b_operand_reads_are_the_swizzled_units():
+    """The kernel reads k step j of wave half h at two lane offsets plus
+    128 (j >> 1) elements; that is row col, unit (4 (2 j + h) + quarter) ^ col."""
+    for half in (0, 1):
+        for lane in range(KWAVE):
+            quarter, col = lane >> 4, lane & 15
+            lsel0 = col * KKS + 8 * ((4 * half + quarter) ^ (col & 7)) + 64 * (col >> 3)
+            lsel1 = col * KKS + 8 * ((4 * half + quarter) ^ (col & 7)) + 64 * (1 - (col >> 3))
+            for j in range(4):
+                got = (lsel1 if j & 1 else lsel0) + 128 * (j >> 1)
+                want = col * KKS + (((4 * (2 * j + half) + quarter) ^ col) * 8)
+                assert got == want
+                assert 0 <= got and got + 8 + 16 * KKS * 3 <= KSTAGE // 2
 
 
 @pytest.mark.parametrize("ld16", list(range(32, 1025, 32)))
