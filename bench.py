@@ -443,6 +443,8 @@ def main():
                     help="skip the exhaustive comparator (every leaf opened) on the tile path")
     ap.add_argument("--no-small-batches", action="store_true",
                     help="skip the per-call times of 1, 16, 128 and 1024 queries on both paths")
+    ap.add_argument("--no-build-compare", action="store_true",
+                    help="skip the GPU forest build timed beside the host build")
     ap.add_argument("--householder", action="store_true",
                     help="build the forest with the per-tree Householder isometry variant")
     ap.add_argument("--sweep", choices=sorted(SWEEPS),
@@ -485,7 +487,27 @@ def main():
     t0 = time.perf_counter()
     F = geraf.build_forest(w.X, w.m, w.t, w.p, w.seed, forms=() if form == "fp32" else (form,),
                            householder=args.householder)
-    log(f"[bench] forest build + upload {time.perf_counter() - t0:.1f}s (H={F.H})")
+    host_build_s = time.perf_counter() - t0
+    log(f"[bench] forest build + upload {host_build_s:.1f}s (H={F.H})")
+    build = None
+    if not args.no_build_compare:
+        # the same forest built on the GPU from device rows (GF_BUILD_DEVICE):
+        # wall time of the whole call, and its arrays against the host build's
+        Xd = torch.from_numpy(w.X).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Fd = geraf.build_forest(Xd, w.m, w.t, w.p, w.seed, forms=() if form == "fp32" else (form,),
+                                householder=args.householder, device_build=True)
+        torch.cuda.synchronize()
+        dev_build_s = time.perf_counter() - t0
+        Th, Td = F.export_tree(), Fd.export_tree()
+        same = all(np.array_equal(Th[key], Td[key]) for key in ("D", "split_dim", "perm", "leaf_off")) \
+            and np.array_equal(Th["split_val"].view(np.uint32), Td["split_val"].view(np.uint32))
+        Fd.free()
+        del Xd, Th, Td
+        build = {"host_s": round(host_build_s, 3), "device_s": round(dev_build_s, 3),
+                 "host_input": "numpy rows", "device_input": "device rows", "arrays_equal": bool(same)}
+        log(f"[bench] forest build on the GPU {dev_build_s:.3f}s, arrays equal to the host build: {same}")
     Q = torch.from_numpy(w.Q).to(dev)
     nq, k = len(w.Q), w.k
     c = args.checks if args.checks is not None else (CHECKS_AT_090 if name == WORKLOAD else w.c)
@@ -672,6 +694,7 @@ def main():
         "phases_ms": {key: round(v, 2) for key, v in ph.items() if key != "path"},
         "fp32_form": fp32,
         "roofline": roofline,
+        "forest_build": build,
         "exhaustive_comparator": exhaustive,
         "small_batches": small,
         "hbm_probe": probe,

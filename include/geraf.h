@@ -62,9 +62,20 @@ typedef enum {
 typedef enum { GF_FORM_FP32 = 0, GF_FORM_BF16 = 1, GF_FORM_FP8 = 2 } gf_form;
 
 /* Bits of gf_build_forest's `forms` argument: which reduced-precision copies
- * of X to keep on the device (FP32 rows are always kept). */
+ * of X to keep on the device (FP32 rows are always kept), and where the trees
+ * are built. */
 #define GF_KEEP_BF16 (1u << 1)
 #define GF_KEEP_FP8  (1u << 2)
+/* Build on the GPU instead of the host (Alg. 1, Alg. 3; Sec. 3 "Median,
+ * variances" and "Parallelization"): FP64 column moments (Knuth's update
+ * over row chunks, combined in chunk order), then every tree level by level,
+ * one workgroup per node: the node's split coordinates, a radix select of
+ * the median item under (coordinate, tie key, id) and a stable partition of
+ * its ids.  The arrays are bit-identical to the host build's (the median
+ * item is unique under that strict order, and leaves are sorted by id);
+ * D is the same set except where the near-tie guard below sits within a few
+ * ulps of its bound.  GF_EUNSUPPORTED for leaves above 4096 points. */
+#define GF_BUILD_DEVICE (1u << 8)
 
 /* Build a forest of m randomized k-d trees over X (Alg. 1).
  *   X      [n][d] float32, host-or-device; read during the call only (the
@@ -75,11 +86,13 @@ typedef enum { GF_FORM_FP32 = 0, GF_FORM_BF16 = 1, GF_FORM_FP8 = 2 } gf_form;
  *   seed   key of the counter-based RNG (splitmix64 keyed by seed, stream,
  *          tree and node or point) that draws each node's split dimension
  *          from D and each tree's tie-break key per point ("shuffling").
- *   forms  GF_KEEP_* bits.
+ *   forms  GF_KEEP_* bits, and GF_BUILD_DEVICE.
  *   out    receives the new forest; release it with gf_free_forest.
- * The build runs on the host (threads over trees, Sec. 3 "Parallelization");
- * the arrays, the FP32 rows and the requested reduced-precision copies are
- * then uploaded on `stream` (host rows through pinned staging buffers).
+ * Without GF_BUILD_DEVICE the build runs on the host (threads over trees,
+ * Sec. 3 "Parallelization"); the arrays, the FP32 rows and the requested
+ * reduced-precision copies are then uploaded on `stream` (host rows through
+ * pinned staging buffers).  With it, the FP32 rows are uploaded first and
+ * the trees are built from them on the device.
  * With the environment variable GF_BUILD_TIMING=1 each phase's wall time is
  * printed to stderr.
  * GF_EINVAL also when D is not determined by the data: the t-th and

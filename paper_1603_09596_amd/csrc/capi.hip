@@ -1296,7 +1296,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
     if (t < 1 || t > d) return fail(GF_EINVAL, "t must be in [1, d]");
     if (t > gf::kMaxT) return fail(GF_EUNSUPPORTED, "t above 64");
     if (leaf < 1) return fail(GF_EINVAL, "leaf < 1");
-    if (forms & ~(GF_KEEP_BF16 | GF_KEEP_FP8)) return fail(GF_EINVAL, "unknown bits in forms");
+    if (forms & ~(GF_KEEP_BF16 | GF_KEEP_FP8 | GF_BUILD_DEVICE)) return fail(GF_EINVAL, "unknown bits in forms");
     if (variants & ~GF_VARIANT_HOUSEHOLDER) return fail(GF_EINVAL, "unknown bits in variants");
     if (gf::perfect_depth(n, leaf) > 23) return fail(GF_EUNSUPPORTED, "tree depth above 23");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1313,28 +1313,33 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         tprev = now;
     };
 
+    const bool on_device = (forms & GF_BUILD_DEVICE) != 0;
+    const bool reflect = (variants & GF_VARIANT_HOUSEHOLDER) != 0;
+    const bool xdev = is_device_ptr(X);
+    // host rows: the host build reads them; device rows are checked on the
+    // device when the build runs there
     std::vector<float> staged;
-    const float* Xh = X;
-    if (is_device_ptr(X)) {
+    const float* Xh = xdev ? nullptr : X;
+    if (xdev && !on_device) {
         staged.resize(size_t(n) * d);
         GF_HIP(hipMemcpy(staged.data(), X, staged.size() * 4, hipMemcpyDeviceToHost));
         Xh = staged.data();
     }
-    if (!all_finite_host(Xh, n * int64_t(d))) return fail(GF_EINVAL, "X contains a non-finite value");
+    if (Xh && !all_finite_host(Xh, n * int64_t(d))) return fail(GF_EINVAL, "X contains a non-finite value");
     phase("stage + finiteness check");
 
     std::unique_ptr<gf_forest> F(new gf_forest());
-    std::string err = gf::build_host_forest(Xh, n, d, m, t, leaf, seed,
-                                            (variants & GF_VARIANT_HOUSEHOLDER) != 0, F->host);
-    if (!err.empty()) return fail(err.rfind("near-tie", 0) == 0 ? GF_EINVAL : GF_EINTERNAL, err);
-    phase("host trees");
+    if (!on_device) {
+        std::string err = gf::build_host_forest(Xh, n, d, m, t, leaf, seed, reflect, F->host);
+        if (!err.empty()) return fail(err.rfind("near-tie", 0) == 0 ? GF_EINVAL : GF_EINTERNAL, err);
+        phase("host trees");
+    }
     GF_HIP(hipGetDevice(&F->device));
     F->uid = g_next_uid.fetch_add(1);
     const gf::HostForest& h = F->host;
     F->ld32 = int32_t(round_up(d, 4));
     F->ld16 = int32_t(round_up(d, 32));   // multiple of one MFMA k step (32 bf16)
     F->ld8 = int32_t(round_up(d, 16));
-    const int64_t nint = (int64_t{1} << h.H) - 1;
     auto cleanup = [&](gf_status s) { free_forest_device(F.get()); return s; };
 
 #define GF_HIP_B(expr)                                                                   \
@@ -1345,7 +1350,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
     } while (0)
 
     GF_HIP_B(hipMalloc(&F->X32, size_t(n) * F->ld32 * 4));
-    if (Xh != X) {
+    if (xdev) {
         // X is already on the device: copy the rows into the padded layout
         if (F->ld32 > d) GF_HIP_B(hipMemsetAsync(F->X32, 0, size_t(n) * F->ld32 * 4, st));
         GF_HIP_B(hipMemcpy2DAsync(F->X32, size_t(F->ld32) * 4, X, size_t(d) * 4, size_t(d) * 4, n,
@@ -1353,7 +1358,37 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
     } else {
         GF_HIP_B(upload_rows(F->X32, Xh, n, d, F->ld32, st));
     }
+    if (!Xh) {
+        // device rows that were not staged: every value finite
+        uint32_t* flag = nullptr;
+        GF_HIP_B(hipMalloc(&flag, 4));
+        uint32_t bad = 0;
+        hipError_t e = hipMemsetAsync(flag, 0, 4, st);
+        const int64_t tot = n * int64_t(d);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(gf::k_check_finite, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st,
+                               F->X32, n, d, int64_t(F->ld32), flag);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(flag);
+        GF_HIP_B(e);
+        if (bad) return cleanup(fail(GF_EINVAL, "X contains a non-finite value"));
+    }
     phase("X upload");
+    if (on_device) {
+        std::string err = gf::build_device_forest(F->X32, F->ld32, n, d, m, t, leaf, seed, reflect, st,
+                                                  F->host);
+        if (!err.empty()) {
+            const gf_status code = err.rfind("near-tie", 0) == 0 ? GF_EINVAL
+                                   : err.rfind("leaves above", 0) == 0 ? GF_EUNSUPPORTED
+                                   : GF_EHIP;
+            return cleanup(fail(code, err));
+        }
+        phase("device trees");
+    }
+    const int64_t nint = (int64_t{1} << h.H) - 1;
     std::vector<uint2> nodes(size_t(m) * std::max<int64_t>(nint, 1));
     for (int64_t i = 0; i < int64_t(m) * nint; ++i) {
         uint32_t bits;

@@ -44,6 +44,23 @@ int32_t perfect_depth(int64_t n, int32_t p);
 std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, int32_t t,
                               int32_t p, uint64_t seed, bool householder, HostForest& out);
 
+// D <- the t columns of largest variance V (variance descending, lower index
+// first among equals), in ascending index order.  Returns the near-tie error
+// when the t-th and (t+1)-th variances differ by at most 1e-12 of the larger
+// of their mean squares V + M^2, else an empty string.
+std::string select_dims(const std::vector<double>& V, const std::vector<double>& M, int64_t n,
+                        int32_t t, std::vector<int32_t>& D);
+
+// The same arrays built on the GPU (build.hip) from the device rows X32
+// [n][ld32]: FP64 column moments on the device, then every tree level by
+// level.  Equal to build_host_forest's arrays bit for bit, D included unless
+// the near-tie guard decides differently on the two evaluations of V (only
+// possible within a few ulps of its 1e-12 bound).  Leaves above 4096 points
+// are refused.  Returns an empty string on success, else the error.
+std::string build_device_forest(const float* X32, int64_t ld32, int64_t n, int32_t d, int32_t m,
+                                int32_t t, int32_t p, uint64_t seed, bool householder,
+                                hipStream_t st, HostForest& out);
+
 // Reflector of tree `tree`: w_j uniform in [-1, 1) from the top 53 bits of
 // keyed_draw(seed, 4, tree, j), normalised in FP64 (squares summed in index
 // order).

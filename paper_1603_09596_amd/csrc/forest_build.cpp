@@ -199,6 +199,24 @@ void build_tree(const float* X, int64_t n, int32_t d, const HostForest& F, int32
 
 }  // namespace
 
+std::string select_dims(const std::vector<double>& V, const std::vector<double>& M, int64_t n,
+                        int32_t t, std::vector<int32_t>& D) {
+    // the t dimensions of largest variance (lower index first among equal
+    // variances), kept in ascending index order
+    const int32_t d = int32_t(V.size());
+    std::vector<int32_t> order(d);
+    for (int32_t j = 0; j < d; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return V[a] > V[b]; });
+    if (dims_ambiguous(V, M, order, n, t))
+        return "near-tie in D: the t-th and (t+1)-th largest variances are within rounding of "
+               "each other (columns " + std::to_string(order[t - 1]) + " and " +
+               std::to_string(order[t]) + ")";
+    D.assign(order.begin(), order.begin() + t);
+    std::sort(D.begin(), D.end());
+    return {};
+}
+
 void householder_vector(uint64_t seed, int32_t tree, int32_t d, double* u) {
 #pragma clang fp contract(off)
     double ss = 0.0;
@@ -226,20 +244,11 @@ std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, i
     const int64_t nint = (int64_t{1} << F.H) - 1;
     const int64_t nleaf = int64_t{1} << F.H;
 
-    // V <- variances; D <- the t dimensions of largest variance (lower index
-    // first among equal variances), kept in ascending index order.
+    // V <- variances; D <- the t dimensions of largest variance
     std::vector<double> V, M;
     column_variance(X, n, d, V, M);
-    std::vector<int32_t> order(d);
-    for (int32_t j = 0; j < d; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return V[a] > V[b]; });
-    if (dims_ambiguous(V, M, order, n, t))
-        return "near-tie in D: the t-th and (t+1)-th largest variances are within rounding of "
-               "each other (columns " + std::to_string(order[t - 1]) + " and " +
-               std::to_string(order[t]) + ")";
-    F.D.assign(order.begin(), order.begin() + t);
-    std::sort(F.D.begin(), F.D.end());
+    std::string err = select_dims(V, M, n, t, F.D);
+    if (!err.empty()) return err;
 
     // Leaf offsets: node sizes split floor/ceil, so they depend on n only.
     std::vector<int64_t> size{n};

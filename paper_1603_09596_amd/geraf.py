@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgeraf.so")
 GF_OK, GF_EINVAL, GF_ENOMEM, GF_EHIP, GF_EUNSUPPORTED, GF_EINTERNAL = 0, -1, -2, -3, -4, -5
 FORM_FP32, FORM_BF16, FORM_FP8 = 0, 1, 2
 KEEP_BF16, KEEP_FP8 = 1 << 1, 1 << 2
+BUILD_DEVICE = 1 << 8
 VARIANT_HOUSEHOLDER = 1 << 0
 FORMS = {"fp32": FORM_FP32, "bf16": FORM_BF16, "fp8": FORM_FP8}
 
@@ -161,11 +162,12 @@ class Forest:
 
 
 def build_forest(X, m: int, t: int, leaf: int, seed: int, forms=(), stream=None,
-                 householder: bool = False) -> Forest:
+                 householder: bool = False, device_build: bool = False) -> Forest:
     """gf_build_forest, or gf_build_forest_ex with the Householder isometry
-    variant.  X: [n, d] float32 (numpy or torch, host or device)."""
+    variant.  X: [n, d] float32 (numpy or torch, host or device).  With
+    device_build the trees are built on the GPU (GF_BUILD_DEVICE)."""
     n, d = X.shape
-    mask = 0
+    mask = BUILD_DEVICE if device_build else 0
     for f in forms:
         mask |= {"bf16": KEEP_BF16, "fp8": KEEP_FP8}[f]
     h = ctypes.c_void_p()

@@ -1,0 +1,133 @@
+"""GPU forest build (GF_BUILD_DEVICE) against the FP64 oracle's build.
+
+Bar: D, split dimensions, split values (bit patterns), leaf-ordered ids and
+leaf offsets equal the oracle's arrays exactly (Alg. 1: median split on a
+dimension drawn from D, ties broken by the per-tree key, leaves sorted by
+id).  The cases cover continuous data, heavy coordinate ties (quantised and
+0/1 data, where the tie key decides the median), ragged sizes with leaves of
+one and zero points, a single leaf, one point, and the isometry variant.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_09596_amd import geraf, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    geraf.load()
+
+
+def build_case(name):
+    """(X, m, t, p, householder) of a named build case."""
+    if name == "gauss-10k-128":
+        w = W.make("gauss-10k-128")
+        return w.X, w.m, w.t, w.p, False
+    if name == "desc-60k-960":
+        X, _, _ = W.descriptor(60_000, 960, 4, 0.02, 2)
+        return X, 16, 5, 32, False
+    if name == "ragged-3001-77":
+        X, _, _ = W.gauss(3001, 77, 4, 0.2, 7)
+        return X, 3, 7, 5, False
+    if name == "quantised":
+        X = np.random.default_rng(5).integers(0, 8, (5000, 40)).astype(np.float32)
+        return X, 4, 6, 8, False
+    if name == "binary-ties":
+        prob = np.linspace(0.1, 0.45, 8)
+        X = (np.random.default_rng(21).random((40_000, 8)) < prob).astype(np.float32)
+        return X, 2, 4, 1, False
+    if name == "signed-zeros":
+        # -0 and +0 are equal coordinates: the tie key orders them
+        X = np.random.default_rng(3).integers(-2, 3, (2000, 6)).astype(np.float32)
+        X[X == 0] = np.where(np.random.default_rng(4).random(int((X == 0).sum())) < 0.5, -0.0, 0.0)
+        return X, 3, 4, 4, False
+    if name == "three-points":
+        return np.array([[0.0, 1.0], [2.0, -1.0], [1.0, 0.5]], np.float32), 2, 2, 1, False
+    if name == "one-point":
+        return np.array([[1.5, -2.0, 3.0]], np.float32), 2, 2, 1, False
+    if name == "single-leaf":
+        X, _, _ = W.gauss(50, 6, 2, 0.3, 3)
+        return X, 2, 2, 64, False
+    if name == "householder-gauss":
+        X, _, _ = W.gauss(6000, 48, 2, 0.2, 8)
+        return X, 4, 5, 8, True
+    if name == "householder-quantised":
+        X = np.random.default_rng(6).integers(0, 4, (3000, 24)).astype(np.float32)
+        return X, 3, 5, 4, True
+    raise KeyError(name)
+
+
+CASES = ["gauss-10k-128", "desc-60k-960", "ragged-3001-77", "quantised", "binary-ties",
+         "signed-zeros", "three-points", "one-point", "single-leaf", "householder-gauss",
+         "householder-quantised"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_device_build_equals_oracle(name):
+    X, m, t, p, hh = build_case(name)
+    seed = 0xC0FFEE + len(name)
+    Fo = oracle.build_forest(X, m, t, p, seed, householder_variant=hh)
+    Fg = geraf.build_forest(torch.from_numpy(X).to("cuda:0"), m, t, p, seed, householder=hh,
+                            device_build=True)
+    try:
+        T = Fg.export_tree()
+        assert T["H"] == Fo["H"]
+        for key in ("D", "split_dim", "perm", "leaf_off"):
+            assert np.array_equal(T[key], Fo[key]), key
+        assert np.array_equal(T["split_val"].view(np.uint32), Fo["split_val"].view(np.uint32))
+    finally:
+        Fg.free()
+
+
+def test_device_build_queries_equal_host_build():
+    """Both builds give the same forest, so the same search results."""
+    X, m, t, p, _ = build_case("quantised")
+    rng = np.random.default_rng(9)
+    Q = (X[rng.integers(0, len(X), 40)] + rng.integers(-1, 2, (40, X.shape[1]))).astype(np.float32)
+    out = []
+    for device_build in (False, True):
+        F = geraf.build_forest(X, m, t, p, 77, device_build=device_build)
+        ids = torch.empty((40, 5), dtype=torch.int32, device="cuda:0")
+        dists = torch.empty((40, 5), dtype=torch.float32, device="cuda:0")
+        geraf.query(F, torch.from_numpy(Q).to("cuda:0"), 5, 40, ids, dists)
+        torch.cuda.synchronize()
+        out.append((ids.cpu().numpy(), dists.cpu().numpy()))
+        F.free()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_device_build_refuses_leaves_above_4096():
+    X, _, _ = W.gauss(10_000, 8, 2, 0.3, 1)
+    with pytest.raises(geraf.GerafError) as e:
+        geraf.build_forest(X, 2, 3, 5000, 1, device_build=True)
+    assert e.value.status == geraf.GF_EUNSUPPORTED
+
+
+def test_device_build_near_tie_guard():
+    """Duplicated columns at the rank-t boundary are refused on both paths."""
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((3000, 6)).astype(np.float32) * np.float32([1, 3, 5, 7, 9, 11])
+    X[:, 4] = X[:, 1]                    # equal variances, adjacent in the order
+    order = np.argsort(-X.astype(np.float64).var(axis=0, ddof=1), kind="stable")
+    t = int(np.where(order == 1)[0][0]) + 1
+    assert order[t] == 4
+    for device_build in (False, True):
+        with pytest.raises(geraf.GerafError) as e:
+            geraf.build_forest(X, 2, t, 8, 1, device_build=device_build)
+        assert e.value.status == geraf.GF_EINVAL
+
+
+def test_device_build_rejects_non_finite_device_rows():
+    X, _, _ = W.gauss(500, 8, 2, 0.3, 1)
+    X[123, 5] = np.nan
+    with pytest.raises(geraf.GerafError) as e:
+        geraf.build_forest(torch.from_numpy(X).to("cuda:0"), 2, 3, 8, 1, device_build=True)
+    assert e.value.status == geraf.GF_EINVAL

@@ -29,13 +29,16 @@ def _gpu():
     geraf.load()
 
 
-def run_case(w, c, form, sample, forms):
+def run_case(w, c, form, sample, forms, device_build=False):
     dev = torch.device("cuda:0")
-    Fg = geraf.build_forest(w.X, w.m, w.t, w.p, w.seed, forms=forms)
+    X = torch.from_numpy(w.X).to(dev) if device_build else w.X
+    Fg = geraf.build_forest(X, w.m, w.t, w.p, w.seed, forms=forms, device_build=device_build)
+    del X
     Fo = oracle.build_forest(w.X, w.m, w.t, w.p, w.seed, nthreads=THREADS)
     T = Fg.export_tree()
-    for key in ("D", "split_dim", "split_val", "perm", "leaf_off"):
+    for key in ("D", "split_dim", "perm", "leaf_off"):
         assert np.array_equal(T[key], Fo[key]), key
+    assert np.array_equal(T["split_val"].view(np.uint32), Fo["split_val"].view(np.uint32))
     Q = torch.from_numpy(w.Q).to(dev)
     nq, k = len(w.Q), w.k
     ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
@@ -84,7 +87,9 @@ def check_reduced(w, ids, dd, ref, Qs, floor):
 def test_desc_1m_960_bench_configuration():
     import bench
     w = W.make("desc-1m-960")
-    ids, dd, ref, Qs, timing = run_case(w, bench.CHECKS_AT_090, "bf16", 12, ("bf16",))
+    # the forest built on the GPU (GF_BUILD_DEVICE), checked against the oracle's
+    ids, dd, ref, Qs, timing = run_case(w, bench.CHECKS_AT_090, "bf16", 12, ("bf16",),
+                                        device_build=True)
     assert timing["path"] == "tile"
     check_reduced(w, ids, dd, ref, Qs, 0.97)
 
