@@ -29,6 +29,14 @@ Parity status of each function (what pins it is in tests/test_oracle.py):
                         forest and searches of the plain method on the data
                         with that column negated; exhaustive budget = brute
                         force
+  build_jitter /        pinned: every split separates its points at the
+   search_jitter        split value (or is the median split when a side
+                        would be empty), lies within 3 Delta / sqrt(d) of the
+                        median, leaves hold <= p points and partition the
+                        ids; the approximate diameter lies in [Delta/2, Delta]
+                        of the brute-force one; the pop order equals the
+                        static-key order computed on the padded layout;
+                        exhaustive budget = brute force
 """
 from __future__ import annotations
 
@@ -85,6 +93,12 @@ def _load():
     lib.orc_search.argtypes = [P, i64, i32, i32, i32, P, P, P, P, P, i64, i32, i64, f64,
                                i32, i32, P, P, P, P, P, P, i64, P]
     lib.orc_search.restype = ctypes.c_int
+    lib.orc_build_jitter.argtypes = [P, i64, i32, i32, i32, i32, u64, i32, i64,
+                                     P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_build_jitter.restype = ctypes.c_int
+    lib.orc_search_jitter.argtypes = [P, i64, i32, i32, i32, i64, P, P, P, P, P, P, P, P, P, P,
+                                      P, i64, i32, i64, f64, P, P, P, P, P, P, i64]
+    lib.orc_search_jitter.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -182,6 +196,65 @@ def build_forest(X: np.ndarray, m: int, t: int, p: int, seed: int, nthreads: int
                 perm=perm, leaf_off=leaf_off, u=U)
 
 
+def build_forest_jitter(X: np.ndarray, m: int, t: int, p: int, seed: int,
+                        diameter: str = "approx") -> dict:
+    """Alg. 1 with the split-value jitter of Sec. 2.1 (see orc_build_jitter):
+    explicit trees (node arrays [m][ncap], per tree nnodes[tr] of them), the
+    leaf-ordered perm [m][n], D and H = the deepest leaf.  diameter: "approx"
+    or "exact"."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, d = X.shape
+    ncap = 2 * n
+    D = np.empty(t, np.int32)
+    arr = {name: np.zeros((m, ncap), dt) for name, dt in
+           (("dim", np.int32), ("val", np.float32), ("left", np.int32), ("right", np.int32),
+            ("heap", np.int32), ("depth", np.int32), ("off", np.uint32), ("len", np.uint32))}
+    perm = np.empty((m, n), np.uint32)
+    nnodes = np.zeros(m, np.int64)
+    H = ctypes.c_int32(0)
+    st = _load().orc_build_jitter(_ptr(X), n, d, m, t, p, seed & 0xFFFFFFFFFFFFFFFF,
+                                  int(diameter == "exact"), ncap, _ptr(D),
+                                  *[_ptr(arr[k]) for k in ("dim", "val", "left", "right", "heap",
+                                                            "depth", "off", "len")],
+                                  _ptr(perm), _ptr(nnodes), ctypes.byref(H))
+    if st == -3:
+        raise NearTieError("near-tie in D")
+    if st != 0:
+        raise ValueError(f"orc_build_jitter failed: {st}")
+    return dict(n=n, d=d, m=m, t=t, p=p, seed=seed, H=int(H.value), D=D, jitter=diameter,
+                ncap=ncap, nnodes=nnodes, perm=perm, **arr)
+
+
+def jitter_layout(F: dict) -> dict:
+    """The padded perfect layout of depth H of jittered trees: a real node
+    keeps its heap index; below a real leaf every internal position is a
+    pass-through node (dimension D[0], value +inf: points and queries all go
+    left), and the leaf sits at its leftmost position of depth H.  Returns
+    split_dim, split_val [m][2^H - 1], perm [m][n] and leaf_off [m][2^H + 1]."""
+    m, H, n = F["m"], F["H"], F["n"]
+    nint, nleaf = (1 << H) - 1, 1 << H
+    sd = np.full((m, max(nint, 1)), F["D"][0], np.int32)
+    sv = np.full((m, max(nint, 1)), np.inf, np.float32)
+    lo = np.zeros((m, nleaf + 1), np.uint32)
+    for tr in range(m):
+        starts = np.full(nleaf, -1, np.int64)
+        for i in range(int(F["nnodes"][tr])):
+            h, dep = int(F["heap"][tr, i]), int(F["depth"][tr, i])
+            if F["dim"][tr, i] >= 0:
+                sd[tr, h], sv[tr, h] = F["dim"][tr, i], F["val"][tr, i]
+            else:
+                j = h - ((1 << dep) - 1)
+                starts[j << (H - dep)] = int(F["off"][tr, i])
+        # empty leaves start where the next real leaf does (perm is in leaf order)
+        nxt = n
+        for L in range(nleaf - 1, -1, -1):
+            if starts[L] >= 0:
+                nxt = starts[L]
+            lo[tr, L] = nxt
+        lo[tr, nleaf] = n
+    return dict(split_dim=sd[:, :nint], split_val=sv[:, :nint], perm=F["perm"], leaf_off=lo)
+
+
 def search(forest: dict, X: np.ndarray, Q: np.ndarray, k: int, c: int, eps: float = 0.0,
            eff_key: bool = False, nthreads: int = 0, trace: bool = True,
            candidates: bool = False) -> dict:
@@ -192,6 +265,8 @@ def search(forest: dict, X: np.ndarray, Q: np.ndarray, k: int, c: int, eps: floa
     whose key is the maximum gap along the chain."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     Q = np.ascontiguousarray(Q, dtype=np.float32)
+    if forest.get("jitter"):
+        return _search_jitter(forest, X, Q, k, c, eps, trace, candidates)
     n, d = X.shape
     nq = Q.shape[0]
     m, H = forest["m"], forest["H"]
@@ -230,10 +305,40 @@ def search(forest: dict, X: np.ndarray, Q: np.ndarray, k: int, c: int, eps: floa
     return out
 
 
+def _search_jitter(F, X, Q, k, c, eps, trace, candidates):
+    n, d = X.shape
+    nq, m, H = Q.shape[0], F["m"], F["H"]
+    leaves = int(sum(int((F["dim"][tr, :F["nnodes"][tr]] < 0).sum()) for tr in range(m)))
+    B = budget(c, eps, leaves)
+    ids = np.empty((nq, k), np.int32)
+    dists = np.empty((nq, k), np.float64)
+    opened = np.empty((nq, max(B, 1)), np.uint32) if trace else None
+    okey = np.empty((nq, max(B, 1)), np.float64) if trace else None
+    ncand = np.empty(nq, np.int64) if candidates else None
+    cand = np.empty((nq, n), np.uint32) if candidates else None
+    st = _load().orc_search_jitter(_ptr(X), n, d, m, H, F["ncap"],
+                                   *[_ptr(F[key]) for key in ("dim", "val", "left", "right", "heap",
+                                                              "depth", "off", "len", "perm")],
+                                   _ptr(F["nnodes"]), _ptr(Q), nq, k, c, float(eps),
+                                   _ptr(ids), _ptr(dists), _ptr(opened), _ptr(okey),
+                                   _ptr(ncand), _ptr(cand), n if candidates else 0)
+    if st != 0:
+        raise ValueError(f"orc_search_jitter failed: {st}")
+    out = dict(ids=ids, dists=dists, B=B)
+    if trace:
+        out["opened"] = opened[:, :B]
+        out["opened_key"] = okey[:, :B]
+    if candidates:
+        out["ncand"] = ncand
+        out["cand"] = [cand[i, :ncand[i]].copy() for i in range(nq)]
+    return out
+
+
 def leaf_code(tree, leaf):
     return (np.asarray(tree, dtype=np.uint32) << np.uint32(24)) | np.asarray(leaf, dtype=np.uint32)
 
 
 __all__ = ["build", "splitmix64", "draw", "variance", "top_dims", "dims_ambiguous",
            "NearTieError", "depth", "budget",
-           "householder", "build_forest", "search", "leaf_code"]
+           "householder", "build_forest", "build_forest_jitter", "jitter_layout", "search",
+           "leaf_code"]

@@ -34,6 +34,11 @@
  *                              queue over all trees, no backtracking, stop
  *                              after B leaves, visited array so no point is
  *                              measured twice, k best by squared distance.
+ *   orc_build_jitter           Alg. 1 with the split-value jitter of Sec. 2.1
+ *                              ("Split value"): median plus a uniform delta
+ *                              scaled by the node's diameter; trees are then
+ *                              not perfect and are stored as explicit nodes.
+ *   orc_search_jitter          Alg. 2 over those explicit trees.
  */
 #include <math.h>
 #include <pthread.h>
@@ -401,7 +406,9 @@ int64_t orc_budget(int64_t c, double eps, int64_t total_leaves)
     return B;
 }
 
-typedef struct { double key; int32_t tree; int32_t node; } orc_entry;
+/* node: heap index (the tie order); idx: the node's own index in an
+ * explicit tree (the jittered trees below), unused for perfect trees. */
+typedef struct { double key; int32_t tree; int32_t node; int32_t idx; } orc_entry;
 
 static int entry_less(const orc_entry *a, const orc_entry *b)
 {
@@ -502,7 +509,7 @@ static int search_one(const orc_search_job *J, int64_t qi, unsigned char *visite
         for (int32_t tr = 0; tr < J->m; ++tr) tq[tr] = dot_u(J->U + (int64_t)tr * J->d, q, J->d);
     heap->size = 0;
     for (int32_t tr = 0; tr < J->m; ++tr) {
-        orc_entry root = {0.0, tr, 0};
+        orc_entry root = {0.0, tr, 0, 0};
         if (heap_push(heap, root) != ORC_OK) return ORC_ENOMEM;
     }
     int64_t checked = 0;
@@ -630,5 +637,259 @@ int orc_search(const float *X, int64_t n, int32_t d, int32_t m, int32_t H,
     }
     free(jobs);
     free(th);
+    return st;
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* Split-value jitter (Sec. 2.1 "Split value"): a node's split value is its  */
+/* median plus delta, delta uniform in [-3 Delta/sqrt(d), 3 Delta/sqrt(d)],   */
+/* Delta the diameter of the node's point set, drawn at every node.  Nodes   */
+/* then split unevenly, so the recursion of Alg. 1 stops where a node holds  */
+/* at most p points, at whatever depth.                                      */
+/*                                                                          */
+/* Readings taken here (the paper leaves them open):                        */
+/*   - the exact diameter is the largest pairwise distance; the approximate */
+/*     one is the largest distance from the node's point of smallest id,    */
+/*     which lies between half the diameter and the diameter;               */
+/*   - distances are Euclidean, squares summed in FP64 in index order, then */
+/*     the IEEE square root of the largest;                                 */
+/*   - delta = w * ((3 Delta) / sqrt(d)) with w uniform in [-1, 1) from the  */
+/*     top 53 bits of draw(seed, 3, tree, node), node the heap index;       */
+/*   - the split value is (float)(median + delta), the median being the      */
+/*     coordinate of the item of rank floor(|P|/2) under (coordinate, tie   */
+/*     key, id) as in the plain build; points with coordinate < value go    */
+/*     left, the rest right (the side a query with that coordinate takes);  */
+/*   - when that leaves a side empty, the node splits at the median as in   */
+/*     the plain build (left = the floor(|P|/2) first items, value = the    */
+/*     median), so every split makes progress;                              */
+/*   - a node of at most p points is a leaf; depth above 23 is refused.     */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_EDEPTH (-4)
+#define ORC_MAXDEPTH 23
+
+static double sqdist_pts(const float *X, int32_t d, uint32_t a, uint32_t b)
+{
+    const float *x = X + (int64_t)a * d, *y = X + (int64_t)b * d;
+    double acc = 0.0;
+    for (int32_t j = 0; j < d; ++j) {
+        double diff = (double)x[j] - (double)y[j];
+        acc = acc + diff * diff;
+    }
+    return acc;
+}
+
+static double node_diameter(const float *X, int32_t d, const uint32_t *ids, int64_t len, int exact)
+{
+    double best = 0.0;
+    if (exact) {
+        for (int64_t i = 0; i < len; ++i)
+            for (int64_t j = i + 1; j < len; ++j) {
+                double s2 = sqdist_pts(X, d, ids[i], ids[j]);
+                if (s2 > best) best = s2;
+            }
+    } else {
+        uint32_t anchor = ids[0];
+        for (int64_t i = 1; i < len; ++i)
+            if (ids[i] < anchor) anchor = ids[i];
+        for (int64_t i = 0; i < len; ++i) {
+            double s2 = sqdist_pts(X, d, anchor, ids[i]);
+            if (s2 > best) best = s2;
+        }
+    }
+    return sqrt(best);
+}
+
+/* Explicit trees: node i of tree tr at [tr * ncap + i]; root 0; dim -1 marks
+ * a leaf holding perm[tr][off .. off + len) (ascending ids). */
+typedef struct {
+    const float *X; int64_t n; int32_t d; int32_t t; int32_t p; int32_t exact;
+    uint64_t seed; const int32_t *D; int32_t tree; int64_t ncap;
+    int32_t *dim; float *val; int32_t *left; int32_t *right; int32_t *heap;
+    int32_t *depth; uint32_t *off; uint32_t *len;
+    uint32_t *perm;
+    orc_item *items; uint64_t *tiekey;
+    int64_t nnodes; int32_t maxdepth; int status;
+} orc_jctx;
+
+static int32_t jitter_node(orc_jctx *c, int64_t hv, int32_t dep, uint32_t *ids, int64_t len, int64_t offset)
+{
+    int64_t me = c->nnodes++;
+    int64_t at = (int64_t)c->tree * c->ncap + me;
+    c->heap[at] = (int32_t)hv;
+    c->depth[at] = dep;
+    if (dep > c->maxdepth) c->maxdepth = dep;
+    if (len <= c->p) {                                       /* leaf(X) */
+        qsort(ids, (size_t)len, sizeof(uint32_t), cmp_u32);
+        c->dim[at] = -1; c->val[at] = 0.0f; c->left[at] = -1; c->right[at] = -1;
+        c->off[at] = (uint32_t)offset; c->len[at] = (uint32_t)len;
+        return (int32_t)me;
+    }
+    if (dep >= ORC_MAXDEPTH) { c->status = ORC_EDEPTH; return (int32_t)me; }
+    int32_t s = c->D[orc_draw(c->seed, 1, (uint64_t)c->tree, (uint64_t)hv) % (uint64_t)c->t];
+    for (int64_t i = 0; i < len; ++i) {
+        c->items[i].x = c->X[(int64_t)ids[i] * c->d + s];
+        c->items[i].key = c->tiekey[ids[i]];
+        c->items[i].id = ids[i];
+    }
+    qsort(c->items, (size_t)len, sizeof(orc_item), cmp_item);
+    int64_t half = len / 2;
+    float median = c->items[half].x;
+    double delta_range = (3.0 * node_diameter(c->X, c->d, ids, len, c->exact)) / sqrt((double)c->d);
+    double w = (double)(orc_draw(c->seed, 3, (uint64_t)c->tree, (uint64_t)hv) >> 11) * 0x1p-53 * 2.0 - 1.0;
+    float value = (float)((double)median + w * delta_range);
+    int64_t nl = 0;
+    for (int64_t i = 0; i < len; ++i) nl += (c->items[i].x < value);
+    if (nl == 0 || nl == len) {            /* an empty side: the plain median split */
+        value = median;
+        nl = half;
+    }
+    /* the items are sorted by coordinate, so the first nl are those below value */
+    for (int64_t i = 0; i < len; ++i) ids[i] = c->items[i].id;
+    c->dim[at] = s;
+    c->val[at] = value;
+    c->off[at] = 0; c->len[at] = 0;
+    int32_t l = jitter_node(c, 2 * hv + 1, dep + 1, ids, nl, offset);
+    int32_t r = jitter_node(c, 2 * hv + 2, dep + 1, ids + nl, len - nl, offset + nl);
+    c->left[at] = l;
+    c->right[at] = r;
+    return (int32_t)me;
+}
+
+/* Alg. 1 with split-value jitter.  Outputs (caller-allocated, ncap >= 2n - 1
+ * nodes per tree):
+ *   D[t]; for every tree tr and node i < nnodes[tr], at [tr * ncap + i]:
+ *   dim (-1 for a leaf), val, left, right (explicit node indices), heap (the
+ *   node's heap index: root 0, children 2h+1 and 2h+2), depth, and for a
+ *   leaf its range off/len in perm[tr]; *H = the largest leaf depth.
+ * exact: 1 exact diameter, 0 approximate (see the readings above).
+ * Returns ORC_EDEPTH when a tree would need more than 23 levels. */
+int orc_build_jitter(const float *X, int64_t n, int32_t d, int32_t m, int32_t t,
+                     int32_t p, uint64_t seed, int32_t exact, int64_t ncap,
+                     int32_t *D, int32_t *dim, float *val, int32_t *left, int32_t *right,
+                     int32_t *heap, int32_t *depth, uint32_t *off, uint32_t *len,
+                     uint32_t *perm, int64_t *nnodes, int32_t *H)
+{
+    if (!X || n < 1 || n > 0xFFFFFFFFLL || d < 1 || m < 1 || t < 1 || t > d || p < 1 ||
+        ncap < 2 * n - 1)
+        return ORC_EINVAL;
+    double *V = (double *)malloc((size_t)d * sizeof(double));
+    if (!V) return ORC_ENOMEM;
+    int st = orc_variance(X, n, d, V);
+    if (st == ORC_OK && orc_dims_ambiguous(X, n, d, t, V)) st = ORC_ENEARTIE;
+    if (st == ORC_OK) st = orc_top_dims(V, d, t, D);
+    free(V);
+    if (st != ORC_OK) return st;
+    orc_jctx c;
+    memset(&c, 0, sizeof(c));
+    c.X = X; c.n = n; c.d = d; c.t = t; c.p = p; c.exact = exact; c.seed = seed; c.D = D;
+    c.ncap = ncap; c.dim = dim; c.val = val; c.left = left; c.right = right; c.heap = heap;
+    c.depth = depth; c.off = off; c.len = len; c.perm = perm;
+    c.items = (orc_item *)malloc((size_t)n * sizeof(orc_item));
+    c.tiekey = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    if (!c.items || !c.tiekey) { free(c.items); free(c.tiekey); return ORC_ENOMEM; }
+    *H = 0;
+    for (int32_t tr = 0; tr < m && c.status == ORC_OK; ++tr) {
+        c.tree = tr;
+        c.nnodes = 0;
+        c.maxdepth = 0;
+        for (int64_t i = 0; i < n; ++i) c.tiekey[i] = orc_draw(seed, 2, (uint64_t)tr, (uint64_t)i);
+        uint32_t *ids = perm + (int64_t)tr * n;
+        for (int64_t i = 0; i < n; ++i) ids[i] = (uint32_t)i;
+        jitter_node(&c, 0, 0, ids, n, 0);
+        nnodes[tr] = c.nnodes;
+        if (c.maxdepth > *H) *H = c.maxdepth;
+    }
+    free(c.items);
+    free(c.tiekey);
+    return c.status;
+}
+
+/* Alg. 2 over the explicit trees of orc_build_jitter: the same queue, keys
+ * and tie order (key, tree, heap index) as orc_search.  Opened leaves are
+ * reported as (tree << 24 | j << (H - depth)), j = heap - (2^depth - 1): a
+ * leaf's position at depth H when every leaf above depth H is put in place
+ * of the leftmost leaf below it.  B = orc_budget(c, eps, leaves of all the
+ * trees); ids/dists/opened/opened_key/ncand/cand as in orc_search. */
+int orc_search_jitter(const float *X, int64_t n, int32_t d, int32_t m, int32_t H, int64_t ncap,
+                      const int32_t *dim, const float *val, const int32_t *left,
+                      const int32_t *right, const int32_t *heap, const int32_t *depth,
+                      const uint32_t *off, const uint32_t *len, const uint32_t *perm,
+                      const int64_t *nnodes,
+                      const float *Q, int64_t nq, int32_t k, int64_t c, double eps,
+                      int32_t *ids, double *dists, uint32_t *opened, double *opened_key,
+                      int64_t *ncand, uint32_t *cand, int64_t cand_cap)
+{
+    if (!X || !Q || !ids || !dists || n < 1 || d < 1 || m < 1 || m > 255 || H < 0 ||
+        H > ORC_MAXDEPTH || nq < 0 || k < 1 || c < 0 || !(eps >= 0.0))
+        return ORC_EINVAL;
+    int64_t leaves = 0;
+    for (int32_t tr = 0; tr < m; ++tr)
+        for (int64_t i = 0; i < nnodes[tr]; ++i) leaves += (dim[(int64_t)tr * ncap + i] < 0);
+    int64_t B = orc_budget(c, eps, leaves);
+    unsigned char *visited = (unsigned char *)calloc((size_t)n, 1);
+    orc_cand *cands = (orc_cand *)malloc((size_t)n * sizeof(orc_cand));
+    uint32_t *touched = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    orc_heap hq = {NULL, 0, 0};
+    int st = (visited && cands && touched) ? ORC_OK : ORC_ENOMEM;
+    for (int64_t qi = 0; st == ORC_OK && qi < nq; ++qi) {
+        const float *q = Q + qi * d;
+        int64_t ntouched = 0, checked = 0;
+        hq.size = 0;
+        for (int32_t tr = 0; tr < m && st == ORC_OK; ++tr) {
+            orc_entry root = {0.0, tr, 0, 0};
+            st = heap_push(&hq, root);
+        }
+        while (st == ORC_OK && checked < B && hq.size > 0) {
+            orc_entry e = heap_pop(&hq);
+            int64_t base = (int64_t)e.tree * ncap;
+            int32_t i = e.idx;
+            while (dim[base + i] >= 0) {                      /* descend */
+                double g = gap_f32(q[dim[base + i]], val[base + i]);
+                int32_t near_i = g < 0.0 ? left[base + i] : right[base + i];
+                int32_t far_i = g < 0.0 ? right[base + i] : left[base + i];
+                orc_entry child = {fabs(g), e.tree, heap[base + far_i], far_i};
+                if ((st = heap_push(&hq, child)) != ORC_OK) break;
+                i = near_i;
+            }
+            if (st != ORC_OK) break;
+            int64_t dl = depth[base + i];
+            uint32_t j = (uint32_t)((int64_t)heap[base + i] - (((int64_t)1 << dl) - 1));
+            if (opened) opened[qi * B + checked] = ((uint32_t)e.tree << 24) | (j << (H - dl));
+            if (opened_key) opened_key[qi * B + checked] = e.key;
+            const uint32_t *pts = perm + (int64_t)e.tree * n;
+            for (uint32_t a = off[base + i]; a < off[base + i] + len[base + i]; ++a) {
+                uint32_t id = pts[a];
+                if (visited[id]) continue;
+                visited[id] = 1;
+                const float *x = X + (int64_t)id * d;
+                double acc = 0.0;
+                for (int32_t jj = 0; jj < d; ++jj) {
+                    double diff = (double)q[jj] - (double)x[jj];
+                    acc += diff * diff;
+                }
+                cands[ntouched].dist = acc;
+                cands[ntouched].id = id;
+                touched[ntouched++] = id;
+            }
+            ++checked;
+        }
+        if (st != ORC_OK) break;
+        if (ncand) ncand[qi] = ntouched;
+        if (cand) {
+            int64_t w = ntouched < cand_cap ? ntouched : cand_cap;
+            uint32_t *dst = cand + qi * cand_cap;
+            for (int64_t a = 0; a < w; ++a) dst[a] = touched[a];
+            qsort(dst, (size_t)w, sizeof(uint32_t), cmp_u32);
+        }
+        qsort(cands, (size_t)ntouched, sizeof(orc_cand), cmp_cand);
+        for (int32_t r = 0; r < k; ++r) {
+            ids[qi * k + r] = r < ntouched ? (int32_t)cands[r].id : -1;
+            dists[qi * k + r] = r < ntouched ? cands[r].dist : INFINITY;
+        }
+        for (int64_t a = 0; a < ntouched; ++a) visited[touched[a]] = 0;
+    }
+    free(visited); free(cands); free(touched); free(hq.a);
     return st;
 }

@@ -691,3 +691,149 @@ def test_tree_sharding_merge_equals_global_selection(groups):
         best = sorted(set(local_best))[:k]                   # duplicates are identical pairs
         assert [b[1] for b in best] == r["ids"][i][:len(best)].tolist()
         assert np.allclose([b[0] for b in best], r["dists"][i][:len(best)], rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------- split-value jitter (Sec. 2.1)
+
+JITTER_CASES = [("gauss", 2500, 16, 3, 5, 8, "approx"),
+                ("gauss", 600, 40, 2, 6, 4, "exact"),
+                ("quantised", 1800, 24, 3, 5, 6, "approx"),
+                ("wide", 900, 300, 2, 8, 5, "approx")]
+
+
+def _jitter_data(kind, n, d, seed=3):
+    rng = np.random.default_rng(seed)
+    if kind == "quantised":
+        return rng.integers(0, 6, (n, d)).astype(np.float32)
+    if kind == "wide":
+        return (rng.standard_normal((n, d)) * np.linspace(0.5, 2.0, d)).astype(np.float32)
+    if kind == "uniform":
+        return rng.random((n, d)).astype(np.float32)
+    return rng.standard_normal((n, d)).astype(np.float32)
+
+
+def _subtree_ids(F, tr, i):
+    """The point ids under explicit node i of tree tr."""
+    out, stack = [], [i]
+    while stack:
+        j = stack.pop()
+        if F["dim"][tr, j] < 0:
+            a = int(F["off"][tr, j])
+            out.extend(F["perm"][tr, a:a + int(F["len"][tr, j])].tolist())
+        else:
+            stack += [int(F["left"][tr, j]), int(F["right"][tr, j])]
+    return np.array(sorted(out), np.int64)
+
+
+def _diameter(P):
+    g = P.astype(np.float64)
+    sq = (g * g).sum(1)
+    d2 = np.maximum(sq[:, None] + sq[None, :] - 2.0 * g @ g.T, 0.0)
+    return math.sqrt(float(d2.max()))
+
+
+@pytest.mark.parametrize("kind,n,d,m,t,p,diam", JITTER_CASES)
+def test_jitter_splits_leaves_and_delta_range(kind, n, d, m, t, p, diam):
+    """Every internal node: its points split at the value (left < v <= right),
+    or, where that would leave a side empty, at the median with the median's
+    own value; v lies within 3 Delta / sqrt(d) of the median (Delta the
+    brute-force diameter, which bounds both readings of it); internal nodes
+    hold > p points, leaves <= p, ascending, and each tree's leaves partition
+    the ids.  Heap indices follow the tree's shape."""
+    X = _jitter_data(kind, n, d)
+    seed = 17
+    F = oracle.build_forest_jitter(X, m, t, p, seed, diameter=diam)
+    assert F["H"] <= 23
+    for tr in range(m):
+        nn = int(F["nnodes"][tr])
+        leaves = []
+        for i in range(nn):
+            ids = _subtree_ids(F, tr, i)
+            if F["dim"][tr, i] < 0:
+                assert len(ids) <= p
+                a = int(F["off"][tr, i])
+                seg = F["perm"][tr, a:a + int(F["len"][tr, i])]
+                assert np.all(np.diff(seg.astype(np.int64)) > 0)
+                leaves.append(seg)
+                continue
+            assert len(ids) > p
+            s, v = int(F["dim"][tr, i]), np.float32(F["val"][tr, i])
+            assert s in F["D"].tolist()
+            L = _subtree_ids(F, tr, int(F["left"][tr, i]))
+            R = _subtree_ids(F, tr, int(F["right"][tr, i]))
+            assert len(L) > 0 and len(R) > 0 and len(L) + len(R) == len(ids)
+            h = int(F["heap"][tr, i])
+            assert F["heap"][tr, F["left"][tr, i]] == 2 * h + 1
+            assert F["heap"][tr, F["right"][tr, i]] == 2 * h + 2
+            # the median item under (coordinate, tie key, id)
+            keys = sorted((float(X[j, s]), oracle.draw(seed, 2, tr, int(j)), int(j)) for j in ids)
+            med = np.float32(keys[len(ids) // 2][0])
+            if np.all(X[L, s] < v) and np.all(X[R, s] >= v):
+                bound = 3.0 * _diameter(X[ids]) / math.sqrt(d)
+                assert abs(float(v) - float(med)) <= bound * (1 + 1e-12) + float(np.spacing(np.float32(abs(v))))
+            else:
+                # the median split of the plain build
+                assert v == med
+                assert set(L.tolist()) == {k[2] for k in keys[:len(ids) // 2]}
+        allids = np.sort(np.concatenate(leaves))
+        assert np.array_equal(allids, np.arange(n))
+
+
+def test_jitter_delta_spans_its_range_and_the_approximate_diameter_bounds():
+    """On nearly collinear points in d = 900 (so 3 Delta / sqrt(d) = Delta / 10
+    keeps every split value inside the data), the root's |v - median| over 40
+    seeds, divided by 3 Delta / sqrt(d) with Delta the brute-force diameter,
+    stays below 1 for both readings, exceeds 0.8 for the exact one (w spans
+    [-1, 1)) and 0.4 for the approximate one (its Delta is >= Delta / 2)."""
+    rng = np.random.default_rng(8)
+    d = 900
+    X = (1e-3 * rng.standard_normal((60, d))).astype(np.float32)
+    X[:, 0] = rng.uniform(-1.0, 1.0, 60).astype(np.float32)
+    dm = _diameter(X)
+    ratios = {"approx": [], "exact": []}
+    for diam in ("approx", "exact"):
+        for seed in range(40):
+            F = oracle.build_forest_jitter(X, 1, 1, 59, seed, diameter=diam)
+            assert F["D"].tolist() == [0]
+            v = float(F["val"][0, 0])
+            keys = sorted((float(X[j, 0]), oracle.draw(seed, 2, 0, j), j) for j in range(60))
+            med = keys[30][0]
+            ratios[diam].append(abs(v - med) / (3.0 * dm / math.sqrt(d)))
+    assert max(ratios["exact"]) <= 1.0 + 1e-6 and max(ratios["approx"]) <= 1.0 + 1e-6
+    assert max(ratios["exact"]) > 0.8
+    assert max(ratios["approx"]) > 0.4
+
+
+@pytest.mark.parametrize("kind,n,d,m,t,p,diam", [("uniform", 1500, 8, 3, 5, 4, "exact"),
+                                                  ("quantised", 2000, 24, 3, 5, 6, "approx"),
+                                                  ("uniform", 3000, 64, 2, 5, 8, "approx")])
+def test_jitter_pop_order_equals_static_key_on_the_padded_layout(kind, n, d, m, t, p, diam):
+    """The explicit-tree queue's pops equal the static-key order computed on
+    the padded perfect layout (pass-through nodes of value +inf, whose far
+    sides carry an infinite gap): the layout reproduces the trees."""
+    X = _jitter_data(kind, n, d)
+    F = oracle.build_forest_jitter(X, m, t, p, 29, diameter=diam)
+    assert F["H"] <= 16
+    Lay = dict(oracle.jitter_layout(F), H=F["H"], m=m)
+    rng = np.random.default_rng(4)
+    Q = (X[rng.integers(0, n, 4)] + 0.3 * rng.standard_normal((4, d))).astype(np.float32)
+    nleaves = sum(int((F["dim"][tr, :F["nnodes"][tr]] < 0).sum()) for tr in range(m))
+    for c in (1, 7, nleaves // 3, nleaves):
+        r = oracle.search(F, X, Q, 3, c)
+        for i in range(len(Q)):
+            order, keys = static_leaf_order_gap(Lay, Q[i])
+            assert np.all(np.isfinite(keys[:nleaves])) and not np.any(np.isfinite(keys[nleaves:]))
+            assert r["opened"][i].tolist() == order[:r["B"]]
+
+
+@pytest.mark.parametrize("diam", ["approx", "exact"])
+def test_jitter_exhaustive_budget_is_exact_knn(diam):
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((700, 12)).astype(np.float32)
+    Q = rng.standard_normal((15, 12)).astype(np.float32)
+    F = oracle.build_forest_jitter(X, 3, 4, 5, 2, diameter=diam)
+    r = oracle.search(F, X, Q, 8, 10 ** 9, candidates=True)
+    assert all(len(cq) == 700 for cq in r["cand"])
+    ei, ed = bf.knn_exact(X, Q, 8)
+    assert np.array_equal(r["ids"], ei)
+    assert np.allclose(r["dists"], ed, rtol=1e-13, atol=0)
