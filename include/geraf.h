@@ -106,6 +106,8 @@ gf_status gf_build_forest(const float *X, int64_t n, int32_t d, int32_t m, int32
 
 /* Bits of gf_build_forest_ex's `variants` argument. */
 #define GF_VARIANT_HOUSEHOLDER (1u << 0)
+#define GF_VARIANT_JITTER (1u << 1)          /* split-value jitter, approximate diameter */
+#define GF_VARIANT_JITTER_EXACT (1u << 2)    /* split-value jitter, exact diameter */
 
 /* gf_build_forest with randomisation variants.  variants = 0 is exactly
  * gf_build_forest.  GF_VARIANT_HOUSEHOLDER is the isometry of Sec. 2.1
@@ -115,8 +117,25 @@ gf_status gf_build_forest(const float *X, int64_t n, int32_t d, int32_t m, int32
  * rounded to float32, with u_i . x summed in FP64 in index order; D is still
  * the top-variance set of X.  gf_query reflects each query the same way
  * before that tree's descent and measures distances on the original points
- * and query.  Other bits are rejected with GF_EINVAL; split-value jitter
- * (Sec. 2.1 "Split value") is not provided. */
+ * and query.
+ * GF_VARIANT_JITTER / GF_VARIANT_JITTER_EXACT: split-value jitter (Sec. 2.1
+ * "Split value").  Each node splits at its median (the plain build's) plus
+ * delta = w * (3 Delta / sqrt(d)), w uniform in [-1, 1) from the generator
+ * (stream 3, keyed by tree and node), Delta the diameter of the node's
+ * points: exact (largest pairwise distance, O(|P|^2 d) per node) or
+ * approximate (largest distance from the node's point of smallest id,
+ * between Delta/2 and Delta).  The value is float32(median + delta), points
+ * below it go left; a value that leaves a side empty is replaced by the
+ * median split.  Nodes split until they hold at most `leaf` points, so trees
+ * are no longer perfect: they are stored in the perfect layout of depth H =
+ * the deepest leaf (reported by gf_forest_info), every internal position
+ * below a leaf passing all points and queries left (value +inf, slot 0) and
+ * the leaf's points placed in the leftmost leaf below it.  Queries then open
+ * the trees' own leaves in Alg. 2's order, and never the empty padding
+ * leaves (the budget is capped at the trees' own leaves).  Built on the host
+ * only (GF_EUNSUPPORTED with GF_BUILD_DEVICE or GF_VARIANT_HOUSEHOLDER, or
+ * when a tree would need more than 23 levels).  Other bits are rejected with
+ * GF_EINVAL. */
 gf_status gf_build_forest_ex(const float *X, int64_t n, int32_t d, int32_t m, int32_t t,
                              int32_t leaf, uint64_t seed, uint32_t forms, uint32_t variants,
                              void *stream, gf_forest **out);
@@ -134,7 +153,9 @@ gf_status gf_forest_info(const gf_forest *F, int64_t *n, int32_t *d, int32_t *m,
  *   split_val[m][2^H - 1]        split value of each internal node;
  *   perm[m][n]                   per tree, point ids leaf by leaf, each leaf
  *                                ascending;
- *   leaf_off[2^H + 1]            leaf j = perm[tree][leaf_off[j] .. leaf_off[j+1]).
+ *   leaf_off[m][2^H + 1]         leaf j of tree i = perm[i][leaf_off[i][j] ..
+ *                                leaf_off[i][j+1]) (the same in every tree
+ *                                unless the trees are jittered).
  * Node v has children 2v+1 (left, coordinate < value) and 2v+2 (right).
  * Any pointer may be NULL to skip that array. */
 gf_status gf_export_tree(const gf_forest *F, int32_t *D, int32_t *split_dim,

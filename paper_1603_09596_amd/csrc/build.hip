@@ -408,13 +408,16 @@ std::string build_device_forest(const float* X32, int64_t ld32, int64_t n, int32
         size.swap(ns);
         off.swap(no);
     }
-    F.leaf_off.resize(nleaf + 1);
-    F.leaf_off[0] = 0;
+    std::vector<uint32_t> lo(nleaf + 1);     // the same in every tree
+    lo[0] = 0;
     uint32_t maxleaf = 0;
     for (int64_t j = 0; j < nleaf; ++j) {
-        F.leaf_off[j + 1] = uint32_t(F.leaf_off[j] + size[j]);
+        lo[j + 1] = uint32_t(lo[j] + size[j]);
         maxleaf = std::max(maxleaf, uint32_t(size[j]));
     }
+    F.leaf_off.resize(size_t(m) * (nleaf + 1));
+    for (int32_t tr = 0; tr < m; ++tr) std::copy(lo.begin(), lo.end(), F.leaf_off.begin() + size_t(tr) * (nleaf + 1));
+    F.real_leaves = int64_t(m) * nleaf;
     if (maxleaf > uint32_t(kMaxDeviceLeaf)) return "leaves above 4096 points are built on the host only";
 
     // V, M: column moments on the device; D and the near-tie guard from them
@@ -462,12 +465,12 @@ std::string build_device_forest(const float* X32, int64_t ld32, int64_t n, int32
     GF_TRY(keys.alloc(size_t(m) * n));
     GF_TRY(dnoff.alloc(noff.size()));
     GF_TRY(dnlen.alloc(nlen.size()));
-    GF_TRY(dlo.alloc(F.leaf_off.size()));
+    GF_TRY(dlo.alloc(lo.size()));
     GF_TRY(dslot.alloc(size_t(m) * std::max<int64_t>(nint, 1)));
     GF_TRY(dval.alloc(size_t(m) * std::max<int64_t>(nint, 1)));
     GF_TRY(hipMemcpyAsync(dnoff.p, noff.data(), noff.size() * 4, hipMemcpyHostToDevice, st));
     GF_TRY(hipMemcpyAsync(dnlen.p, nlen.data(), nlen.size() * 4, hipMemcpyHostToDevice, st));
-    GF_TRY(hipMemcpyAsync(dlo.p, F.leaf_off.data(), F.leaf_off.size() * 4, hipMemcpyHostToDevice, st));
+    GF_TRY(hipMemcpyAsync(dlo.p, lo.data(), lo.size() * 4, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_iota, dim3(unsigned((n + kBuildThreads - 1) / kBuildThreads), unsigned(m)),
                        dim3(kBuildThreads), 0, st, idsA.p, n);
     GF_TRY(hipGetLastError());

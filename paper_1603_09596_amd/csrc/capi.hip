@@ -421,7 +421,7 @@ bool use_tile_path(const gf_forest* F, const QueryJob& J, int nb) {
     // 5.4 vs 7.0 ms at 16 queries; 200k x 10,000 FP8: 12.1 vs 26.6 ms at 1,024
     // queries, 11.4 vs 4.7 ms at 128)
     if (nb < (J.form == gf::kFormFP8 ? 512 : 16)) return false;
-    const double leaf_pts = double(F->host.n) / double(int64_t{1} << F->host.H);
+    const double leaf_pts = double(F->host.n) * F->host.m / double(F->host.real_leaves);
     const double cand_est = J.checks_mean * leaf_pts * 0.5;
     return cand_est * (J.form == gf::kFormFP8 ? 192.0 : 256.0) >= double(F->host.n);
 }
@@ -467,6 +467,7 @@ gf::SelectArgs make_select_args(const gf_forest* F, int nb, const Workspace& w, 
     sa.Q = w.Qp; sa.ldq = F->ld32; sa.nq = nb; sa.m = h.m; sa.H = h.H; sa.t = h.t;
     sa.n_internal = (int64_t{1} << h.H) - 1; sa.W = int(W); sa.nodes = F->nodes; sa.D = F->D;
     sa.drange = F->drange;
+    sa.leaves = h.real_leaves;
     sa.nslice = h.m * gf::select_slices_per_tree(h.H);
     sa.state = w.state; sa.hist = w.hist; sa.coff = w.coff; sa.ckey = w.ckey;
     sa.ccap = gf::collect_capacity(h.H);
@@ -1297,7 +1298,13 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
     if (t > gf::kMaxT) return fail(GF_EUNSUPPORTED, "t above 64");
     if (leaf < 1) return fail(GF_EINVAL, "leaf < 1");
     if (forms & ~(GF_KEEP_BF16 | GF_KEEP_FP8 | GF_BUILD_DEVICE)) return fail(GF_EINVAL, "unknown bits in forms");
-    if (variants & ~GF_VARIANT_HOUSEHOLDER) return fail(GF_EINVAL, "unknown bits in variants");
+    if (variants & ~(GF_VARIANT_HOUSEHOLDER | GF_VARIANT_JITTER | GF_VARIANT_JITTER_EXACT))
+        return fail(GF_EINVAL, "unknown bits in variants");
+    const int jitter = (variants & GF_VARIANT_JITTER_EXACT) ? 2 : (variants & GF_VARIANT_JITTER) ? 1 : 0;
+    if (jitter && (variants & GF_VARIANT_HOUSEHOLDER))
+        return fail(GF_EUNSUPPORTED, "split-value jitter with the isometry variant");
+    if (jitter && (forms & GF_BUILD_DEVICE))
+        return fail(GF_EUNSUPPORTED, "split-value jitter is built on the host only");
     if (gf::perfect_depth(n, leaf) > 23) return fail(GF_EUNSUPPORTED, "tree depth above 23");
     hipStream_t st = static_cast<hipStream_t>(stream);
     // GF_BUILD_TIMING=1 prints the wall time of each build phase to stderr
@@ -1330,8 +1337,11 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
 
     std::unique_ptr<gf_forest> F(new gf_forest());
     if (!on_device) {
-        std::string err = gf::build_host_forest(Xh, n, d, m, t, leaf, seed, reflect, F->host);
-        if (!err.empty()) return fail(err.rfind("near-tie", 0) == 0 ? GF_EINVAL : GF_EINTERNAL, err);
+        std::string err = gf::build_host_forest(Xh, n, d, m, t, leaf, seed, reflect, F->host, jitter);
+        if (!err.empty())
+            return fail(err.rfind("near-tie", 0) == 0 ? GF_EINVAL
+                        : err.rfind("a jittered tree", 0) == 0 ? GF_EUNSUPPORTED
+                        : GF_EINTERNAL, err);
         phase("host trees");
     }
     GF_HIP(hipGetDevice(&F->device));
@@ -1405,15 +1415,21 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         // leaf rows padded to pp ids (pow2 >= the largest leaf, >= 4)
         const int64_t nleaf = int64_t{1} << h.H;
         uint32_t maxleaf = 0;
-        for (int64_t j = 0; j < nleaf; ++j) maxleaf = std::max(maxleaf, h.leaf_off[j + 1] - h.leaf_off[j]);
+        for (int32_t tr = 0; tr < m; ++tr) {
+            const uint32_t* lo = h.leaf_off.data() + size_t(tr) * (nleaf + 1);
+            for (int64_t j = 0; j < nleaf; ++j) maxleaf = std::max(maxleaf, lo[j + 1] - lo[j]);
+        }
         int32_t pp = 4;
         while (uint32_t(pp) < maxleaf) pp <<= 1;
         F->pp = pp;
+        F->maxleaf = int32_t(maxleaf);
         std::vector<uint32_t> padded(size_t(m) * nleaf * pp, 0xFFFFFFFFu);
-        for (int32_t tr = 0; tr < m; ++tr)
+        for (int32_t tr = 0; tr < m; ++tr) {
+            const uint32_t* lo = h.leaf_off.data() + size_t(tr) * (nleaf + 1);
             for (int64_t j = 0; j < nleaf; ++j)
-                for (uint32_t i = h.leaf_off[j]; i < h.leaf_off[j + 1]; ++i)
-                    padded[(size_t(tr) * nleaf + j) * pp + (i - h.leaf_off[j])] = h.perm[size_t(tr) * n + i];
+                for (uint32_t i = lo[j]; i < lo[j + 1]; ++i)
+                    padded[(size_t(tr) * nleaf + j) * pp + (i - lo[j])] = h.perm[size_t(tr) * n + i];
+        }
         GF_HIP_B(hipMalloc(&F->permp, padded.size() * 4));
         GF_HIP_B(hipMemcpy(F->permp, padded.data(), padded.size() * 4, hipMemcpyHostToDevice));
     }
@@ -1427,6 +1443,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         for (int64_t i = 0; i < int64_t(m) * nint; ++i) {
             const int j = h.split_slot[i];
             const float v = h.split_val[i];
+            if (!std::isfinite(v)) continue;   // pass-through node of a jittered tree
             if (!used[j]) { rng[j] = make_float2(v, v); used[j] = 1; }
             rng[j].x = std::min(rng[j].x, v);
             rng[j].y = std::max(rng[j].y, v);
@@ -1446,19 +1463,15 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         // leaf of every point in every tree, point-major (tile paths)
         const int64_t nleaf = int64_t{1} << h.H;
         std::vector<uint32_t> lof(size_t(n) * m);
-        for (int32_t tr = 0; tr < m; ++tr)
+        for (int32_t tr = 0; tr < m; ++tr) {
+            const uint32_t* lo = h.leaf_off.data() + size_t(tr) * (nleaf + 1);
             for (int64_t j = 0; j < nleaf; ++j)
-                for (uint32_t i = h.leaf_off[j]; i < h.leaf_off[j + 1]; ++i)
+                for (uint32_t i = lo[j]; i < lo[j + 1]; ++i)
                     lof[size_t(h.perm[size_t(tr) * n + i]) * m + tr] = uint32_t(tr * nleaf + j);
+        }
         GF_HIP_B(hipMalloc(&F->leafof, lof.size() * 4));
         GF_HIP_B(hipMemcpy(F->leafof, lof.data(), lof.size() * 4, hipMemcpyHostToDevice));
         phase("leaf of each point");
-    }
-    {
-        uint32_t maxleaf = 0;
-        for (size_t j = 0; j + 1 < h.leaf_off.size(); ++j)
-            maxleaf = std::max(maxleaf, h.leaf_off[j + 1] - h.leaf_off[j]);
-        F->maxleaf = int32_t(maxleaf);
     }
     if (forms & GF_KEEP_BF16) {
         GF_HIP_B(hipMalloc(&F->X16, size_t(n) * F->ld16 * 2));

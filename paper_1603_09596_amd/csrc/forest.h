@@ -28,8 +28,10 @@ struct HostForest {
     std::vector<uint8_t> split_slot;  // [m][2^H - 1] index into D
     std::vector<float> split_val;     // [m][2^H - 1]
     std::vector<uint32_t> perm;       // [m][n] leaf-ordered point ids
-    std::vector<uint32_t> leaf_off;   // [2^H + 1]
+    std::vector<uint32_t> leaf_off;   // [m][2^H + 1] leaf j of tree i: perm[i][off[i][j] .. off[i][j+1])
     std::vector<double> U;            // [m][d] reflectors of the isometry variant, or empty
+    int jitter = 0;                   // split-value jitter: 0 none, 1 approximate, 2 exact diameter
+    int64_t real_leaves = 0;          // leaves of the trees themselves (m 2^H without jitter)
 };
 
 // Counter-based RNG (splitmix64 output function, keyed).
@@ -40,9 +42,13 @@ int32_t perfect_depth(int64_t n, int32_t p);
 
 // Builds the host arrays; X is host memory [n][d].  With householder, tree i
 // splits the reflected coordinates float32((I - 2 u_i u_i') x) (Sec. 2.1
-// "Rotation", Sec. 2.2).  Returns an empty string on success, else the error.
+// "Rotation", Sec. 2.2).  jitter (1 approximate, 2 exact diameter) perturbs
+// every split value (Sec. 2.1 "Split value"): the trees are then built to
+// whatever depth their nodes need and padded to a perfect layout (see
+// forest_build.cpp).  Returns an empty string on success, else the error.
 std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, int32_t t,
-                              int32_t p, uint64_t seed, bool householder, HostForest& out);
+                              int32_t p, uint64_t seed, bool householder, HostForest& out,
+                              int jitter = 0);
 
 // D <- the t columns of largest variance V (variance descending, lower index
 // first among equals), in ascending index order.  Returns the near-tie error

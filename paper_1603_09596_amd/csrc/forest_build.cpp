@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <thread>
 
@@ -44,7 +45,9 @@ namespace {
 
 constexpr uint64_t kStreamSplitDim = 1;
 constexpr uint64_t kStreamTieKey = 2;
+constexpr uint64_t kStreamJitter = 3;
 constexpr uint64_t kStreamReflector = 4;
+constexpr int32_t kMaxDepth = 23;
 
 // u . x in FP64: each product rounded, then added in index order (no fused
 // multiply-add, so the device reproduces it bit for bit).
@@ -197,6 +200,163 @@ void build_tree(const float* X, int64_t n, int32_t d, const HostForest& F, int32
     for (size_t j = 0; j < size.size(); ++j) std::sort(ids + off[j], ids + off[j] + size[j]);
 }
 
+
+// ---------------------------------------------------------------- split-value jitter
+//
+// Sec. 2.1 "Split value": a node splits at its median plus delta, delta
+// uniform in [-3 Delta / sqrt(d), 3 Delta / sqrt(d)] with Delta the diameter
+// of the node's points, drawn at every node; nodes split until they hold at
+// most p points.  Readings (the paper leaves them open): the exact Delta is
+// the largest pairwise distance, the approximate one the largest distance
+// from the node's point of smallest id (between Delta/2 and Delta);
+// distances are FP64 sums of squares in index order and one IEEE square
+// root; delta = w ((3 Delta) / sqrt(d)), w in [-1, 1) from the top 53 bits of
+// keyed_draw(seed, 3, tree, node); the value is float32(median + delta) and
+// points with coordinate below it go left; a value that would leave a side
+// empty is replaced by the median split of the plain build.
+//
+// The trees are stored in the perfect layout of depth H = the deepest leaf
+// over all trees: a node keeps its heap index, every internal position below
+// a leaf passes everything left (value +inf, slot 0), and the leaf's points
+// sit in the leftmost leaf below it; the other leaves there are empty.  A
+// query descends a pass-through node to the left as well, and the right
+// side's gap is infinite, so the queue meets the trees' own leaves in their
+// own order and the empty ones last; the budget is capped at the number of
+// the trees' own leaves so that those are never opened.
+
+struct JNode {           // a node being split: heap index, depth, id range
+    int64_t heap;
+    int32_t depth;
+    int64_t off, len;
+};
+struct JSplit { int64_t heap; uint8_t slot; float value; };
+struct JLeaf { int64_t heap; int32_t depth; int64_t off, len; };
+
+double node_sq_dist(const float* a, const float* b, int32_t d) {
+#pragma clang fp contract(off)
+    double acc = 0.0;
+    for (int32_t j = 0; j < d; ++j) {
+        const double e = double(a[j]) - double(b[j]);
+        acc = acc + e * e;
+    }
+    return acc;
+}
+
+double node_diameter(const float* X, int32_t d, const uint32_t* ids, int64_t len, bool exact) {
+    double far2 = 0.0;
+    if (exact) {
+        for (int64_t i = 0; i + 1 < len; ++i)
+            for (int64_t j = i + 1; j < len; ++j)
+                far2 = std::max(far2, node_sq_dist(X + int64_t(ids[i]) * d, X + int64_t(ids[j]) * d, d));
+    } else {
+        const uint32_t a = *std::min_element(ids, ids + len);
+        for (int64_t i = 0; i < len; ++i)
+            far2 = std::max(far2, node_sq_dist(X + int64_t(a) * d, X + int64_t(ids[i]) * d, d));
+    }
+    return std::sqrt(far2);
+}
+
+// One tree: splits and leaves, ids reordered in place; returns the deepest
+// leaf's depth, or -1 past the depth limit.
+int32_t build_tree_jitter(const float* X, int64_t n, int32_t d, const HostForest& F, int32_t tree,
+                          bool exact, uint32_t* ids, std::vector<JSplit>& splits,
+                          std::vector<JLeaf>& leaves) {
+#pragma clang fp contract(off)
+    std::vector<uint64_t> tie(n);
+    for (int64_t i = 0; i < n; ++i) tie[i] = keyed_draw(F.seed, kStreamTieKey, tree, uint64_t(i));
+    for (int64_t i = 0; i < n; ++i) ids[i] = uint32_t(i);
+    std::vector<Item> items;
+    std::vector<JNode> todo{JNode{0, 0, 0, n}};
+    int32_t deepest = 0;
+    while (!todo.empty()) {
+        const JNode nd = todo.back();
+        todo.pop_back();
+        uint32_t* seg = ids + nd.off;
+        if (nd.len <= F.p) {
+            std::sort(seg, seg + nd.len);
+            leaves.push_back(JLeaf{nd.heap, nd.depth, nd.off, nd.len});
+            deepest = std::max(deepest, nd.depth);
+            continue;
+        }
+        if (nd.depth >= kMaxDepth) return -1;
+        const uint64_t r = keyed_draw(F.seed, kStreamSplitDim, tree, uint64_t(nd.heap));
+        const int32_t slot = int32_t(r % uint64_t(F.t));
+        const int32_t s = F.D[slot];
+        items.resize(nd.len);
+        for (int64_t a = 0; a < nd.len; ++a) items[a] = Item{X[int64_t(seg[a]) * d + s], tie[seg[a]], seg[a]};
+        std::sort(items.begin(), items.end(), item_less);
+        const int64_t half = nd.len / 2;
+        const float median = items[half].x;
+        const double range = (3.0 * node_diameter(X, d, seg, nd.len, exact)) / std::sqrt(double(d));
+        const uint64_t rw = keyed_draw(F.seed, kStreamJitter, tree, uint64_t(nd.heap));
+        const double w = double(rw >> 11) * 0x1p-53 * 2.0 - 1.0;
+        float value = float(double(median) + w * range);
+        // items are in coordinate order: those below the value come first
+        int64_t nl = std::partition_point(items.begin(), items.end(),
+                                          [&](const Item& it) { return it.x < value; }) - items.begin();
+        if (nl == 0 || nl == nd.len) {
+            value = median;
+            nl = half;
+        }
+        for (int64_t a = 0; a < nd.len; ++a) seg[a] = items[a].id;
+        splits.push_back(JSplit{nd.heap, uint8_t(slot), value});
+        todo.push_back(JNode{2 * nd.heap + 2, nd.depth + 1, nd.off + nl, nd.len - nl});
+        todo.push_back(JNode{2 * nd.heap + 1, nd.depth + 1, nd.off, nl});
+    }
+    return deepest;
+}
+
+std::string build_jitter_forest(const float* X, int64_t n, int32_t d, bool exact, HostForest& F) {
+    const int32_t m = F.m;
+    F.perm.resize(size_t(m) * n);
+    std::vector<std::vector<JSplit>> splits(m);
+    std::vector<std::vector<JLeaf>> leaves(m);
+    std::vector<int32_t> deep(m, 0);
+    const unsigned nw = worker_count(m);
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nw; ++w) {
+        th.emplace_back([&, w] {
+            for (int32_t tree = int32_t(w); tree < m; tree += int32_t(nw))
+                deep[tree] = build_tree_jitter(X, n, d, F, tree, exact, F.perm.data() + size_t(tree) * n,
+                                               splits[tree], leaves[tree]);
+        });
+    }
+    for (auto& x : th) x.join();
+    int32_t H = 0;
+    for (int32_t tree = 0; tree < m; ++tree) {
+        if (deep[tree] < 0) return "a jittered tree needs more than 23 levels";
+        H = std::max(H, deep[tree]);
+    }
+    F.H = H;
+    const int64_t nint = (int64_t{1} << H) - 1;
+    const int64_t nleaf = int64_t{1} << H;
+    // pass-through nodes everywhere, then each tree's own splits
+    F.split_slot.assign(size_t(m) * nint, 0);
+    F.split_val.assign(size_t(m) * nint, std::numeric_limits<float>::infinity());
+    F.split_dim.assign(size_t(m) * nint, F.D[0]);
+    F.leaf_off.assign(size_t(m) * (nleaf + 1), 0);
+    F.real_leaves = 0;
+    for (int32_t tree = 0; tree < m; ++tree) {
+        for (const JSplit& sp : splits[tree]) {
+            const size_t at = size_t(tree) * nint + size_t(sp.heap);
+            F.split_slot[at] = sp.slot;
+            F.split_val[at] = sp.value;
+            F.split_dim[at] = F.D[sp.slot];
+        }
+        // a leaf of depth h at heap index v sits at layout leaf (v - 2^h + 1) << (H - h);
+        // the ids are in leaf order, so an empty layout leaf starts where the next
+        // occupied one does
+        std::vector<int64_t> start(nleaf, -1);
+        for (const JLeaf& lf : leaves[tree])
+            start[((lf.heap - ((int64_t{1} << lf.depth) - 1)) << (H - lf.depth))] = lf.off;
+        uint32_t* lo = F.leaf_off.data() + size_t(tree) * (nleaf + 1);
+        lo[nleaf] = uint32_t(n);
+        for (int64_t j = nleaf - 1; j >= 0; --j) lo[j] = start[j] >= 0 ? uint32_t(start[j]) : lo[j + 1];
+        F.real_leaves += int64_t(leaves[tree].size());
+    }
+    return {};
+}
+
 }  // namespace
 
 std::string select_dims(const std::vector<double>& V, const std::vector<double>& M, int64_t n,
@@ -232,11 +392,12 @@ void householder_vector(uint64_t seed, int32_t tree, int32_t d, double* u) {
 }
 
 std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, int32_t t,
-                              int32_t p, uint64_t seed, bool householder, HostForest& F) {
+                              int32_t p, uint64_t seed, bool householder, HostForest& F, int jitter) {
     F = HostForest{};
     F.n = n; F.d = d; F.m = m; F.t = t; F.p = p; F.seed = seed;
+    F.jitter = jitter;
     F.H = perfect_depth(n, p);
-    if (F.H > 23) return "tree depth above 23 (n/leaf too large)";
+    if (!jitter && F.H > 23) return "tree depth above 23 (n/leaf too large)";
     if (householder) {
         F.U.resize(size_t(m) * d);
         for (int32_t tr = 0; tr < m; ++tr) householder_vector(seed, tr, d, F.U.data() + size_t(tr) * d);
@@ -249,6 +410,7 @@ std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, i
     column_variance(X, n, d, V, M);
     std::string err = select_dims(V, M, n, t, F.D);
     if (!err.empty()) return err;
+    if (jitter) return build_jitter_forest(X, n, d, jitter == 2, F);
 
     // Leaf offsets: node sizes split floor/ceil, so they depend on n only.
     std::vector<int64_t> size{n};
@@ -258,9 +420,14 @@ std::string build_host_forest(const float* X, int64_t n, int32_t d, int32_t m, i
         for (int64_t s : size) { nx.push_back(s / 2); nx.push_back(s - s / 2); }
         size.swap(nx);
     }
-    F.leaf_off.resize(nleaf + 1);
-    F.leaf_off[0] = 0;
-    for (int64_t j = 0; j < nleaf; ++j) F.leaf_off[j + 1] = uint32_t(F.leaf_off[j] + size[j]);
+    // the same offsets in every tree
+    F.leaf_off.resize(size_t(m) * (nleaf + 1));
+    for (int32_t tr = 0; tr < m; ++tr) {
+        uint32_t* lo = F.leaf_off.data() + size_t(tr) * (nleaf + 1);
+        lo[0] = 0;
+        for (int64_t j = 0; j < nleaf; ++j) lo[j + 1] = uint32_t(lo[j] + size[j]);
+    }
+    F.real_leaves = int64_t(m) * nleaf;
 
     F.split_dim.assign(size_t(m) * nint, 0);
     F.split_slot.assign(size_t(m) * nint, 0);

@@ -49,6 +49,8 @@ struct SelectArgs {
     const uint2* nodes;    // [m][n_internal]
     const int32_t* D;      // [t]
     const float2* drange;  // [t] smallest and largest split value on each slot of D
+    int64_t leaves;        // leaves of the trees themselves: the budget's cap (below
+                           // m 2^H for jittered trees, whose padding leaves stay closed)
     int nslice;            // m * (leaf ranges per tree)
     SelState* state;       // [nq]
     uint32_t* hist;        // [nq][nslice][128]

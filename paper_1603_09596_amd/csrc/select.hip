@@ -561,7 +561,10 @@ __global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, in
 // Per-query initialisation: budget and state.  Every gap's split value lies
 // within its slot's range, and float subtraction is monotone, so no eff
 // exceeds gmax = max over slots of |q - lo| and |q - hi|: the sample walk's
-// bins end at gmax's bin and reach 127 bins (15.9 octaves) below it.
+// bins end at gmax's bin and reach 127 bins (15.9 octaves) below it.  (The
+// pass-through nodes of jittered trees, value +inf, are left out of the
+// ranges: the leaves behind them have infinite keys, fall into the top bin
+// and lie beyond the budget, which is capped at the trees' own leaves.)
 __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps,
                               uint32_t* flags) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -574,7 +577,7 @@ __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, 
     // Alg. 2 checks leaves while l < c/(1+eps): ceil(c/(1+eps)) of them.
     int64_t B = int64_t(ceil(double(c) / (1.0 + eps)));
     const int64_t total = int64_t(a.m) << a.H;
-    if (B > total) B = total;
+    if (B > a.leaves) B = a.leaves;
     if (B < 0) B = 0;
     float gmax = 0.0f;
     const int ntq = a.qt ? a.m : 1;    // the isometry variant: every tree's reflected query

@@ -22,6 +22,7 @@ FORM_FP32, FORM_BF16, FORM_FP8 = 0, 1, 2
 KEEP_BF16, KEEP_FP8 = 1 << 1, 1 << 2
 BUILD_DEVICE = 1 << 8
 VARIANT_HOUSEHOLDER = 1 << 0
+VARIANT_JITTER, VARIANT_JITTER_EXACT = 1 << 1, 1 << 2
 FORMS = {"fp32": FORM_FP32, "bf16": FORM_BF16, "fp8": FORM_FP8}
 
 EXPORTED = ["gf_build_forest", "gf_build_forest_ex", "gf_free_forest", "gf_forest_info", "gf_export_tree", "gf_query",
@@ -155,16 +156,18 @@ class Forest:
         sd = np.empty((self.m, max(nint, 1)), np.int32)
         sv = np.empty((self.m, max(nint, 1)), np.float32)
         perm = np.empty((self.m, self.n), np.uint32)
-        lo = np.empty((1 << self.H) + 1, np.uint32)
+        lo = np.empty((self.m, (1 << self.H) + 1), np.uint32)
         _check(load().gf_export_tree(self._h, _ptr(D), _ptr(sd), _ptr(sv), _ptr(perm), _ptr(lo)))
         return dict(n=self.n, d=self.d, m=self.m, t=self.t, p=self.leaf, H=self.H, D=D,
                     split_dim=sd[:, :nint], split_val=sv[:, :nint], perm=perm, leaf_off=lo)
 
 
 def build_forest(X, m: int, t: int, leaf: int, seed: int, forms=(), stream=None,
-                 householder: bool = False, device_build: bool = False) -> Forest:
+                 householder: bool = False, device_build: bool = False,
+                 jitter: Optional[str] = None) -> Forest:
     """gf_build_forest, or gf_build_forest_ex with the Householder isometry
-    variant.  X: [n, d] float32 (numpy or torch, host or device).  With
+    variant or split-value jitter (jitter="approx" or "exact": the diameter
+    used).  X: [n, d] float32 (numpy or torch, host or device).  With
     device_build the trees are built on the GPU (GF_BUILD_DEVICE)."""
     n, d = X.shape
     mask = BUILD_DEVICE if device_build else 0
@@ -172,9 +175,11 @@ def build_forest(X, m: int, t: int, leaf: int, seed: int, forms=(), stream=None,
         mask |= {"bf16": KEEP_BF16, "fp8": KEEP_FP8}[f]
     h = ctypes.c_void_p()
     st = stream if stream is not None else _stream_of(X)
-    if householder:
+    variants = (VARIANT_HOUSEHOLDER if householder else 0) | \
+        {None: 0, "approx": VARIANT_JITTER, "exact": VARIANT_JITTER_EXACT}[jitter]
+    if variants:
         _check(load().gf_build_forest_ex(_ptr(X), n, d, m, t, leaf, seed & 0xFFFFFFFFFFFFFFFF, mask,
-                                         VARIANT_HOUSEHOLDER, st, ctypes.byref(h)))
+                                         variants, st, ctypes.byref(h)))
     else:
         _check(load().gf_build_forest(_ptr(X), n, d, m, t, leaf, seed & 0xFFFFFFFFFFFFFFFF, mask,
                                       st, ctypes.byref(h)))

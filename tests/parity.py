@@ -56,3 +56,17 @@ def check_knn(got_ids, got_d, ref_ids, ref_d64, rel=1e-5, tie=1e-6, X=None, Q=No
                 f"query {i}: distance of id {gid}: {got_d[i][j]} vs {true_d}"
         assert np.all(np.diff(got_d[i][got_ids[i] >= 0]) >= 0), f"query {i}: not sorted"
     return nq
+
+
+def assert_tree_arrays_equal(T, Fo):
+    """The library's exported tree arrays against the oracle's: D, split
+    dimensions, leaf-ordered ids, split values bit for bit, and per-tree leaf
+    offsets (the oracle's plain build holds one row shared by every tree)."""
+    assert T["H"] == Fo["H"]
+    for key in ("D", "split_dim", "perm"):
+        assert np.array_equal(T[key], Fo[key]), key
+    assert np.array_equal(T["split_val"].view(np.uint32), Fo["split_val"].view(np.uint32)), "split_val"
+    lo = np.asarray(Fo["leaf_off"])
+    if lo.ndim == 1:
+        lo = np.broadcast_to(lo, T["leaf_off"].shape)
+    assert np.array_equal(T["leaf_off"], lo), "leaf_off"

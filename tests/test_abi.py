@@ -77,8 +77,13 @@ def test_build_ex_rejects_unknown_variants_before_hip(lib):
     X = np.zeros((10, 4), np.float32)
     p = X.ctypes.data_as(ctypes.c_void_p)
     B = lib.gf_build_forest_ex
-    assert B(p, 10, 4, 2, 2, 2, 0, 0, 1 << 1, None, ctypes.byref(out)) == geraf.GF_EINVAL
+    assert B(p, 10, 4, 2, 2, 2, 0, 0, 1 << 5, None, ctypes.byref(out)) == geraf.GF_EINVAL
     assert b"variants" in lib.gf_last_error()
+    # split-value jitter is a host build without the isometry
+    assert B(p, 10, 4, 2, 2, 2, 0, 0, geraf.VARIANT_JITTER | geraf.VARIANT_HOUSEHOLDER, None,
+             ctypes.byref(out)) == geraf.GF_EUNSUPPORTED
+    assert B(p, 10, 4, 2, 2, 2, 0, geraf.BUILD_DEVICE, geraf.VARIANT_JITTER_EXACT, None,
+             ctypes.byref(out)) == geraf.GF_EUNSUPPORTED
     assert B(p, 10, 4, 2, 2, 2, 0, 1 << 7, geraf.VARIANT_HOUSEHOLDER, None,
              ctypes.byref(out)) == geraf.GF_EINVAL
     assert B(None, 10, 4, 2, 2, 2, 0, 0, geraf.VARIANT_HOUSEHOLDER, None,

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+from parity import assert_tree_arrays_equal
 from paper_1603_09596_amd import geraf, workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -78,10 +79,7 @@ def test_device_build_equals_oracle(name):
                             device_build=True)
     try:
         T = Fg.export_tree()
-        assert T["H"] == Fo["H"]
-        for key in ("D", "split_dim", "perm", "leaf_off"):
-            assert np.array_equal(T[key], Fo[key]), key
-        assert np.array_equal(T["split_val"].view(np.uint32), Fo["split_val"].view(np.uint32))
+        assert_tree_arrays_equal(T, Fo)
     finally:
         Fg.free()
 

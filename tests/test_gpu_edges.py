@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_1603_09596_amd import geraf
-from parity import check_knn, ids_from_bits, leaf_set_from_bits
+from parity import check_knn, ids_from_bits, leaf_set_from_bits, assert_tree_arrays_equal
 
 pytestmark = pytest.mark.gpu
 
@@ -56,8 +56,7 @@ def test_edge_shape_fp32(name):
     Fo = oracle.build_forest(X, m, t, p, seed)
     try:
         T = Fg.export_tree()
-        for key in ("D", "split_dim", "split_val", "perm", "leaf_off"):
-            assert np.array_equal(T[key], Fo[key]), key
+        assert_tree_arrays_equal(T, Fo)
         ref = oracle.search(Fo, X, Q, k, c, candidates=True)
         nq = len(Q)
         lb = np.zeros((nq, Fg.m, Fg.leaf_words), np.uint32)

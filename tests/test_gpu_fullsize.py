@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_1603_09596_amd import geraf, workloads as W
-from parity import check_knn, ids_from_bits, leaf_set_from_bits
+from parity import check_knn, ids_from_bits, leaf_set_from_bits, assert_tree_arrays_equal
 
 pytestmark = pytest.mark.gpu
 
@@ -36,9 +36,7 @@ def run_case(w, c, form, sample, forms, device_build=False):
     del X
     Fo = oracle.build_forest(w.X, w.m, w.t, w.p, w.seed, nthreads=THREADS)
     T = Fg.export_tree()
-    for key in ("D", "split_dim", "perm", "leaf_off"):
-        assert np.array_equal(T[key], Fo[key]), key
-    assert np.array_equal(T["split_val"].view(np.uint32), Fo["split_val"].view(np.uint32))
+    assert_tree_arrays_equal(T, Fo)
     Q = torch.from_numpy(w.Q).to(dev)
     nq, k = len(w.Q), w.k
     ids = torch.empty((nq, k), dtype=torch.int32, device=dev)

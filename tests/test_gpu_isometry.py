@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_1603_09596_amd import geraf
-from parity import check_knn, ids_from_bits, leaf_set_from_bits
+from parity import check_knn, ids_from_bits, leaf_set_from_bits, assert_tree_arrays_equal
 from test_gpu_parity import case_data
 
 pytestmark = pytest.mark.gpu
@@ -47,8 +47,7 @@ def test_reflected_forest_bit_exact(name, k, c):
     X, Q, _, _, _ = case_data(name)
     Fg, Fo = forests(name)
     T = Fg.export_tree()
-    for key in ("D", "split_dim", "split_val", "perm", "leaf_off"):
-        assert np.array_equal(T[key], Fo[key]), key
+    assert_tree_arrays_equal(T, Fo)
     ref = oracle.search(Fo, X, Q, k, c, candidates=True)
     nq = len(Q)
     lb = np.zeros((nq, Fg.m, Fg.leaf_words), np.uint32)

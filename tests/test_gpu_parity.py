@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_1603_09596_amd import geraf, workloads as W
-from parity import check_knn, ids_from_bits, leaf_set_from_bits
+from parity import check_knn, ids_from_bits, leaf_set_from_bits, assert_tree_arrays_equal
 
 pytestmark = pytest.mark.gpu
 
@@ -145,9 +145,7 @@ CASES = [  # (name, k, c, eps)
 def test_tree_arrays_bit_exact(name):
     X, Q, Fg, Fo, _ = forests(name)
     T = Fg.export_tree()
-    assert T["H"] == Fo["H"]
-    for key in ("D", "split_dim", "split_val", "perm", "leaf_off"):
-        assert np.array_equal(T[key], Fo[key]), key
+    assert_tree_arrays_equal(T, Fo)
 
 
 @pytest.mark.parametrize("name,k,c,eps", CASES)

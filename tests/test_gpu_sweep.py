@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_1603_09596_amd import geraf, workloads as W
-from parity import check_knn, ids_from_bits, leaf_set_from_bits
+from parity import check_knn, ids_from_bits, leaf_set_from_bits, assert_tree_arrays_equal
 
 pytestmark = pytest.mark.gpu
 
@@ -47,8 +47,7 @@ def test_sweep_grid_bit_exact(p, eps):
     X, Q = data()
     Fg, Fo = forests(p)
     T = Fg.export_tree()
-    for key in ("D", "split_dim", "split_val", "perm", "leaf_off"):
-        assert np.array_equal(T[key], Fo[key]), key
+    assert_tree_arrays_equal(T, Fo)
     c = 64
     ref = oracle.search(Fo, X, Q, 1, c, eps=eps, candidates=True)
     nq = len(Q)
