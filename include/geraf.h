@@ -47,7 +47,9 @@ typedef struct gf_forest gf_forest;   /* opaque; owned by the library */
 typedef enum {
     GF_OK = 0,
     GF_EINVAL = -1,          /* invalid argument (nothing was launched) */
-    GF_ENOMEM = -2,          /* host or device allocation failed */
+    GF_ENOMEM = -2,          /* host or device allocation failed, or the device
+                                memory the library holds would exceed the cap
+                                GF_MAX_DEVICE_BYTES (environment, bytes), when set */
     GF_EHIP = -3,            /* a HIP runtime call failed */
     GF_EUNSUPPORTED = -4,    /* valid request outside the library's limits */
     GF_EINTERNAL = -5        /* an internal consistency check failed */
@@ -342,6 +344,11 @@ const char *gf_last_error(void);
 
 /* Library version string. */
 const char *gf_version(void);
+
+/* Bytes of device memory the library holds right now (forests, their query
+ * workspaces and temporaries; not the fixed scratch of gf_query_noalloc):
+ * the total that GF_MAX_DEVICE_BYTES caps.  Never fails. */
+int64_t gf_device_bytes(void);
 
 #ifdef __cplusplus
 }

@@ -370,8 +370,10 @@ __global__ __launch_bounds__(kBuildThreads) void k_sort_leaves(uint32_t* __restr
 template <class T>
 struct DevBuf {
     T* p = nullptr;
-    hipError_t alloc(size_t count) { return hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)); }
-    ~DevBuf() { if (p) (void)hipFree(p); }
+    hipError_t alloc(size_t count) {
+        return dev_malloc(reinterpret_cast<void**>(&p), std::max<size_t>(count, 1) * sizeof(T));
+    }
+    ~DevBuf() { dev_free(p); }
 };
 
 }  // namespace

@@ -14,6 +14,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "forest.h"
@@ -36,14 +37,42 @@ gf_status fail(gf_status s, const std::string& msg) {
     return s;
 }
 
+// out-of-memory (the runtime's, or the cap below) reports GF_ENOMEM
 #define GF_HIP(expr)                                                                     \
     do {                                                                                 \
         hipError_t e_ = (expr);                                                          \
         if (e_ != hipSuccess)                                                            \
-            return fail(GF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+            return fail(e_ == hipErrorOutOfMemory ? GF_ENOMEM : GF_EHIP,                 \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));              \
     } while (0)
 
+// Device memory held by the library, against an optional cap: the
+// environment variable GF_MAX_DEVICE_BYTES (read at every allocation), when
+// set to a positive byte count, makes any allocation that would take the
+// library's total above it fail with hipErrorOutOfMemory (GF_ENOMEM).
+std::mutex g_alloc_mutex;
+std::unordered_map<void*, size_t> g_alloc_size;
+size_t g_alloc_total = 0;
+
+size_t device_cap() {
+    const char* e = std::getenv("GF_MAX_DEVICE_BYTES");
+    if (!e || !*e) return 0;
+    char* end = nullptr;
+    const unsigned long long v = std::strtoull(e, &end, 10);
+    return (end && *end == '\0') ? size_t(v) : 0;
+}
+
+bool exceeds_cap(size_t more) {
+    const size_t cap = device_cap();
+    std::lock_guard<std::mutex> lock(g_alloc_mutex);
+    return cap != 0 && g_alloc_total + more > cap;
+}
+
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+struct DevFree {
+    void operator()(void* p) const { gf::dev_free(p); }
+};
 
 bool is_device_ptr(const void* p) {
     hipPointerAttribute_t attr;
@@ -147,7 +176,7 @@ void free_forest_device(gf_forest* F) {
     void* ptrs[] = {F->X32, F->X16, F->norm16, F->X8, F->scale8, F->norm8,
                     F->nodes, F->perm, F->leaf_off, F->permp, F->leafof, F->D, F->drange, F->U, F->ws};
     for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+        gf::dev_free(p);
     F->X32 = nullptr; F->X16 = nullptr; F->norm16 = nullptr; F->X8 = nullptr;
     F->scale8 = nullptr; F->norm8 = nullptr; F->nodes = nullptr; F->perm = nullptr;
     F->leaf_off = nullptr; F->permp = nullptr; F->leafof = nullptr; F->D = nullptr; F->drange = nullptr;
@@ -345,10 +374,10 @@ gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Worksp
                         int64_t checks_max = 0, int nslice = 1) {
     const WsLayout L = ws_layout(F, nb, k, form, tile, checks_max, nslice);
     if (L.need > F->ws_bytes) {
-        if (F->ws) (void)hipFree(F->ws);
+        gf::dev_free(F->ws);
         F->ws = nullptr;
         F->ws_bytes = 0;
-        if (hipMalloc(&F->ws, L.need) != hipSuccess) {
+        if (gf::dev_malloc(&F->ws, L.need) != hipSuccess) {
             (void)hipGetLastError();
             return fail(GF_ENOMEM, "device workspace allocation of " + std::to_string(L.need) +
                                        " bytes failed");
@@ -404,10 +433,7 @@ struct QueryJob {
 bool tile_eligible(const gf_forest* F, const QueryJob& J) {
     if (J.leaf_bits || J.cand_bits || J.ncand || !F->leafof) return false;
     if (J.kk > gf::kTileList) return false;   // lists of kTileList entries per query
-    if (J.form == gf::kFormBF16) {
-        if (F->ld16 > 1024) return false;
-        return gf::scan_supported(F->host.n, gf::kFormFP32, F->ld8);
-    }
+    if (J.form == gf::kFormBF16) return F->ld16 <= 1024;   // A operands of one wave pair in registers
     return J.form == gf::kFormFP8;
 }
 
@@ -440,8 +466,19 @@ struct ScanSlices {
 
 ScanSlices scan_slices(const gf_forest* F, const QueryJob& J, int nb) {
     ScanSlices r;
-    if (J.cand_bits || J.ncand || J.kk > gf::kTileList) return r;
     const int64_t nbmw = (F->host.n + 31) / 32;
+    // id ranges above one workgroup's bitmap are always sliced (traces
+    // included: each slice writes its words of the candidate rows)
+    const int64_t wmax = gf::scan_max_slice_words(J.form, F->ld8);
+    if (wmax > 0 && nbmw > wmax) {
+        const int64_t ns = (nbmw + wmax - 1) / wmax;
+        int64_t words = (nbmw + ns - 1) / ns;
+        words = (words + 15) / 16 * 16;
+        r.nslice = int((nbmw + words - 1) / words);
+        r.words = words;
+        return r;
+    }
+    if (J.cand_bits || J.ncand || J.kk > gf::kTileList) return r;
     int64_t want = 1;
     const char* env = std::getenv("GF_SCAN_SLICES");
     if (env && std::atoi(env) > 0) {
@@ -591,13 +628,19 @@ gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& 
 // unsliced scan does).
 gf_status launch_rows(const gf_forest* F, const QueryJob& J, int nb, const Workspace& w,
                       gf::ScanArgs ca, const ScanSlices& sl, hipStream_t st) {
+    int64_t* ncand = nullptr;
     if (sl.nslice > 1) {
         ca.nslice = sl.nslice;
         ca.slice_words = sl.words;
         ca.part_s = w.part_s;
         ca.part_i = w.part_i;
+        // candidate counts of a sliced trace: summed from the bitmap rows
+        ncand = ca.ncand;
+        ca.ncand = nullptr;
+        if (ncand && !ca.cand_bits) return fail(GF_EINTERNAL, "sliced trace without a bitmap");
     }
     GF_HIP(gf::launch_scan(ca, J.form, st));
+    if (ncand) GF_HIP(gf::launch_count_bits(ca.cand_bits, nb, (F->host.n + 31) / 32, ncand, st));
     if (sl.nslice > 1) {
         gf::MergeArgs ma{};
         ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = F->host.d; ma.nsplit = sl.nslice;
@@ -720,17 +763,17 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     gf::ScanArgs ca = make_scan_args(F, J, q0, nb, w, W);
     ca.cand_bits = (J.cand_bits && J.trace_dev) ? J.cand_bits + q0 * nbmw : nullptr;
     ca.ncand = (J.ncand && J.trace_dev) ? J.ncand + q0 : nullptr;
-    std::unique_ptr<uint32_t, decltype(&hipFree)> tmp_bits(nullptr, &hipFree);
-    std::unique_ptr<int64_t, decltype(&hipFree)> tmp_nc(nullptr, &hipFree);
-    if ((J.cand_bits && !J.trace_dev) || (J.trace_tile && !ca.cand_bits && J.ncand)) {
+    std::unique_ptr<uint32_t, DevFree> tmp_bits;
+    std::unique_ptr<int64_t, DevFree> tmp_nc;
+    if ((J.cand_bits && !J.trace_dev) || ((J.trace_tile || sl.nslice > 1) && !ca.cand_bits && J.ncand)) {
         uint32_t* p = nullptr;
-        GF_HIP(hipMalloc(&p, size_t(nb) * nbmw * 4));
+        GF_HIP(gf::dev_malloc((void**)&p, size_t(nb) * nbmw * 4));
         tmp_bits.reset(p);
         ca.cand_bits = p;
     }
     if (J.ncand && !J.trace_dev) {
         int64_t* p = nullptr;
-        GF_HIP(hipMalloc(&p, size_t(nb) * 8));
+        GF_HIP(gf::dev_malloc((void**)&p, size_t(nb) * 8));
         tmp_nc.reset(p);
         ca.ncand = p;
     }
@@ -767,10 +810,10 @@ gf_status run_batch(gf_forest* F, const QueryJob& J, int64_t q0, int nb, hipStre
     if (J.leaf_bits) {
         const int64_t words = int64_t(h.m) * W;
         uint32_t* dst = J.leaf_bits + q0 * words;
-        std::unique_ptr<uint32_t, decltype(&hipFree)> tmp(nullptr, &hipFree);
+        std::unique_ptr<uint32_t, DevFree> tmp;
         if (!J.trace_dev) {
             uint32_t* p = nullptr;
-            GF_HIP(hipMalloc(&p, size_t(nb) * words * 4));
+            GF_HIP(gf::dev_malloc((void**)&p, size_t(nb) * words * 4));
             tmp.reset(p);
             dst = p;
         }
@@ -843,8 +886,11 @@ gf_status prepare_job(const gf_forest* Fc, const float* Q, int64_t nq, int32_t k
         if (rerank < k || rerank > gf::kMaxK) return fail(GF_EINVAL, "rerank must be in [k, 64]");
         kk = rerank;
     }
-    if (!gf::scan_supported(F->host.n, form, F->ld8))
-        return fail(GF_EUNSUPPORTED, "n (or d in FP8) too large for the LDS-resident scan");
+    if (gf::scan_max_slice_words(form, F->ld8) == 0)
+        return fail(GF_EUNSUPPORTED, "d too large to stage the FP8 query in the scan's LDS");
+    if (!gf::scan_supported(F->host.n, form, F->ld8) && kk > gf::kTileList)
+        return fail(GF_EUNSUPPORTED, "n above one workgroup's visited bitmap (sliced id ranges) "
+                                     "needs at most 48 list entries per query (k <= 40 in FP32)");
     J = QueryJob{};
     J.nq = nq; J.k = k; J.checks = checks; J.eps = eps; J.form = form; J.kk = kk;
     J.ids = ids; J.dists = dists;
@@ -981,7 +1027,7 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
                 free_list.pop_back();
             }
         }
-        if (!flag) GF_HIP(hipMalloc(&flag, 4));
+        if (!flag) GF_HIP(gf::dev_malloc((void**)&flag, 4));
         struct FlagBack {
             uint32_t* f; int dev;
             ~FlagBack() { std::lock_guard<std::mutex> lock(flag_mutex); pool[dev].push_back(f); }
@@ -1175,6 +1221,43 @@ gf_status run_multi(const gf_job* jobs, int32_t njobs, uint32_t flags, hipStream
 // is written only if it hits a constant.
 constexpr int kProbeUnroll = 16;
 }  // namespace
+
+namespace gf {
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    *p = nullptr;
+    const size_t cap = device_cap();
+    std::lock_guard<std::mutex> lock(g_alloc_mutex);
+    if (cap != 0 && g_alloc_total + bytes > cap) return hipErrorOutOfMemory;
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    g_alloc_size[*p] = bytes;
+    g_alloc_total += bytes;
+    return hipSuccess;
+}
+
+void dev_free(void* p) {
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mutex);
+        auto it = g_alloc_size.find(p);
+        if (it != g_alloc_size.end()) {
+            g_alloc_total -= it->second;
+            g_alloc_size.erase(it);
+        }
+    }
+    (void)hipFree(p);
+}
+
+size_t dev_bytes_held() {
+    std::lock_guard<std::mutex> lock(g_alloc_mutex);
+    return g_alloc_total;
+}
+
+}  // namespace gf
 __device__ uint32_t gf_probe_sink;
 namespace {
 __global__ __launch_bounds__(256) void k_read_probe(const uint4* __restrict__ p, int64_t n16) {
@@ -1272,6 +1355,8 @@ gf_status gf_query_noalloc(const gf_forest* Fc, const float* Q, int64_t nq, int3
 
 const char* gf_version(void) { return "geraf-gfx950 0.1"; }
 
+int64_t gf_device_bytes(void) { return int64_t(gf::dev_bytes_held()); }
+
 gf_status gf_last_query_timing(double* phase_ms, int32_t nphase, int32_t* path, int64_t* batches) {
     if (nphase < 0 || (nphase > 0 && !phase_ms)) return fail(GF_EINVAL, "bad phase buffer");
     for (int i = 0; i < nphase; ++i) phase_ms[i] = i < kPhases ? g_phase_ms[i] : 0.0;
@@ -1320,6 +1405,10 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         tprev = now;
     };
 
+    // the FP32 rows alone must fit under the device-memory cap (checked
+    // before any HIP call)
+    if (exceeds_cap(size_t(n) * size_t(round_up(d, 4)) * 4))
+        return fail(GF_ENOMEM, "the FP32 rows exceed GF_MAX_DEVICE_BYTES");
     const bool on_device = (forms & GF_BUILD_DEVICE) != 0;
     const bool reflect = (variants & GF_VARIANT_HOUSEHOLDER) != 0;
     const bool xdev = is_device_ptr(X);
@@ -1356,10 +1445,11 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
     do {                                                                                 \
         hipError_t e_ = (expr);                                                          \
         if (e_ != hipSuccess)                                                            \
-            return cleanup(fail(GF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+            return cleanup(fail(e_ == hipErrorOutOfMemory ? GF_ENOMEM : GF_EHIP,         \
+                                std::string(#expr) + ": " + hipGetErrorString(e_)));     \
     } while (0)
 
-    GF_HIP_B(hipMalloc(&F->X32, size_t(n) * F->ld32 * 4));
+    GF_HIP_B(gf::dev_malloc((void**)&F->X32, size_t(n) * F->ld32 * 4));
     if (xdev) {
         // X is already on the device: copy the rows into the padded layout
         if (F->ld32 > d) GF_HIP_B(hipMemsetAsync(F->X32, 0, size_t(n) * F->ld32 * 4, st));
@@ -1371,7 +1461,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
     if (!Xh) {
         // device rows that were not staged: every value finite
         uint32_t* flag = nullptr;
-        GF_HIP_B(hipMalloc(&flag, 4));
+        GF_HIP_B(gf::dev_malloc((void**)&flag, 4));
         uint32_t bad = 0;
         hipError_t e = hipMemsetAsync(flag, 0, 4, st);
         const int64_t tot = n * int64_t(d);
@@ -1382,7 +1472,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         }
         if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
-        (void)hipFree(flag);
+        gf::dev_free(flag);
         GF_HIP_B(e);
         if (bad) return cleanup(fail(GF_EINVAL, "X contains a non-finite value"));
     }
@@ -1405,11 +1495,11 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         std::memcpy(&bits, &h.split_val[i], 4);
         nodes[i] = make_uint2(bits, h.split_slot[i]);
     }
-    GF_HIP_B(hipMalloc(&F->nodes, nodes.size() * sizeof(uint2)));
+    GF_HIP_B(gf::dev_malloc((void**)&F->nodes, nodes.size() * sizeof(uint2)));
     GF_HIP_B(hipMemcpyAsync(F->nodes, nodes.data(), nodes.size() * sizeof(uint2), hipMemcpyHostToDevice, st));
-    GF_HIP_B(hipMalloc(&F->perm, h.perm.size() * 4));
+    GF_HIP_B(gf::dev_malloc((void**)&F->perm, h.perm.size() * 4));
     GF_HIP_B(hipMemcpyAsync(F->perm, h.perm.data(), h.perm.size() * 4, hipMemcpyHostToDevice, st));
-    GF_HIP_B(hipMalloc(&F->leaf_off, h.leaf_off.size() * 4));
+    GF_HIP_B(gf::dev_malloc((void**)&F->leaf_off, h.leaf_off.size() * 4));
     GF_HIP_B(hipMemcpyAsync(F->leaf_off, h.leaf_off.data(), h.leaf_off.size() * 4, hipMemcpyHostToDevice, st));
     {
         // leaf rows padded to pp ids (pow2 >= the largest leaf, >= 4)
@@ -1430,11 +1520,11 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
                 for (uint32_t i = lo[j]; i < lo[j + 1]; ++i)
                     padded[(size_t(tr) * nleaf + j) * pp + (i - lo[j])] = h.perm[size_t(tr) * n + i];
         }
-        GF_HIP_B(hipMalloc(&F->permp, padded.size() * 4));
+        GF_HIP_B(gf::dev_malloc((void**)&F->permp, padded.size() * 4));
         GF_HIP_B(hipMemcpy(F->permp, padded.data(), padded.size() * 4, hipMemcpyHostToDevice));
     }
     phase("nodes, perm, padded leaves");
-    GF_HIP_B(hipMalloc(&F->D, size_t(t) * 4));
+    GF_HIP_B(gf::dev_malloc((void**)&F->D, size_t(t) * 4));
     GF_HIP_B(hipMemcpyAsync(F->D, h.D.data(), size_t(t) * 4, hipMemcpyHostToDevice, st));
     {
         // range of the split values on each slot of D (0, 0 for an unused slot)
@@ -1448,7 +1538,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
             rng[j].x = std::min(rng[j].x, v);
             rng[j].y = std::max(rng[j].y, v);
         }
-        GF_HIP_B(hipMalloc(&F->drange, size_t(t) * sizeof(float2)));
+        GF_HIP_B(gf::dev_malloc((void**)&F->drange, size_t(t) * sizeof(float2)));
         GF_HIP_B(hipMemcpy(F->drange, rng.data(), size_t(t) * sizeof(float2), hipMemcpyHostToDevice));
     }
     if (!h.U.empty()) {
@@ -1456,7 +1546,7 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
         std::vector<double> ut(h.U.size());
         for (int32_t tr = 0; tr < m; ++tr)
             for (int32_t j = 0; j < d; ++j) ut[size_t(j) * m + tr] = h.U[size_t(tr) * d + j];
-        GF_HIP_B(hipMalloc(&F->U, ut.size() * sizeof(double)));
+        GF_HIP_B(gf::dev_malloc((void**)&F->U, ut.size() * sizeof(double)));
         GF_HIP_B(hipMemcpy(F->U, ut.data(), ut.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     if (forms & (GF_KEEP_BF16 | GF_KEEP_FP8)) {
@@ -1469,21 +1559,21 @@ gf_status gf_build_forest_ex(const float* X, int64_t n, int32_t d, int32_t m, in
                 for (uint32_t i = lo[j]; i < lo[j + 1]; ++i)
                     lof[size_t(h.perm[size_t(tr) * n + i]) * m + tr] = uint32_t(tr * nleaf + j);
         }
-        GF_HIP_B(hipMalloc(&F->leafof, lof.size() * 4));
+        GF_HIP_B(gf::dev_malloc((void**)&F->leafof, lof.size() * 4));
         GF_HIP_B(hipMemcpy(F->leafof, lof.data(), lof.size() * 4, hipMemcpyHostToDevice));
         phase("leaf of each point");
     }
     if (forms & GF_KEEP_BF16) {
-        GF_HIP_B(hipMalloc(&F->X16, size_t(n) * F->ld16 * 2));
-        GF_HIP_B(hipMalloc(&F->norm16, size_t(n) * 4));
+        GF_HIP_B(gf::dev_malloc((void**)&F->X16, size_t(n) * F->ld16 * 2));
+        GF_HIP_B(gf::dev_malloc((void**)&F->norm16, size_t(n) * 4));
         hipLaunchKernelGGL(gf::k_to_bf16, dim3((n + 3) / 4), dim3(256), 0, st, F->X32, n, d,
                            int64_t(F->ld32), F->X16, int64_t(F->ld16), F->norm16);
         GF_HIP_B(hipGetLastError());
     }
     if (forms & GF_KEEP_FP8) {
-        GF_HIP_B(hipMalloc(&F->X8, size_t(n) * F->ld8));
-        GF_HIP_B(hipMalloc(&F->scale8, size_t(n) * 4));
-        GF_HIP_B(hipMalloc(&F->norm8, size_t(n) * 4));
+        GF_HIP_B(gf::dev_malloc((void**)&F->X8, size_t(n) * F->ld8));
+        GF_HIP_B(gf::dev_malloc((void**)&F->scale8, size_t(n) * 4));
+        GF_HIP_B(gf::dev_malloc((void**)&F->norm8, size_t(n) * 4));
         hipLaunchKernelGGL(gf::k_to_fp8, dim3((n + 3) / 4), dim3(256), 0, st, F->X32, n, d,
                            int64_t(F->ld32), F->X8, int64_t(F->ld8), F->scale8, F->norm8);
         GF_HIP_B(hipGetLastError());
@@ -1564,8 +1654,8 @@ gf_status gf_query_trace_ex(const gf_forest* Fc, const float* Q, int64_t nq, int
     gf_forest* F = const_cast<gf_forest*>(Fc);
     if (path == GF_TRACE_TILE && !F->leafof)
         return fail(GF_EINVAL, "the tile path's trace needs a forest built with GF_KEEP_BF16");
-    if (path == GF_TRACE_ROWS && !gf::scan_supported(F->host.n, GF_FORM_FP32, F->ld8))
-        return fail(GF_EUNSUPPORTED, "n too large for the LDS visited bitmap");
+    if (path == GF_TRACE_ROWS && gf::scan_max_slice_words(GF_FORM_FP32, F->ld8) == 0)
+        return fail(GF_EUNSUPPORTED, "the row scan does not fit the LDS");
     if (nq == 0) return GF_OK;
     QueryJob J{};
     J.Q = Q; J.q_dev = is_device_ptr(Q);
@@ -1616,23 +1706,23 @@ gf_status gf_fp8_tables(float* hw_decode, float* def_decode, const float* enc_in
         return fail(GF_EINVAL, "bad arguments");
     float *dh = nullptr, *ds = nullptr, *din = nullptr;
     uint8_t* dout = nullptr;
-    GF_HIP(hipMalloc(&dh, 256 * 4));
-    GF_HIP(hipMalloc(&ds, 256 * 4));
+    GF_HIP(gf::dev_malloc((void**)&dh, 256 * 4));
+    GF_HIP(gf::dev_malloc((void**)&ds, 256 * 4));
     hipLaunchKernelGGL(gf::k_e4m3_decode_both, dim3(1), dim3(256), 0, 0, dh, ds);
     GF_HIP(hipGetLastError());
     GF_HIP(hipMemcpy(hw_decode, dh, 256 * 4, hipMemcpyDeviceToHost));
     GF_HIP(hipMemcpy(def_decode, ds, 256 * 4, hipMemcpyDeviceToHost));
-    (void)hipFree(dh);
-    (void)hipFree(ds);
+    gf::dev_free(dh);
+    gf::dev_free(ds);
     if (n_enc > 0) {
-        GF_HIP(hipMalloc(&din, size_t(n_enc) * 4));
-        GF_HIP(hipMalloc(&dout, size_t(n_enc)));
+        GF_HIP(gf::dev_malloc((void**)&din, size_t(n_enc) * 4));
+        GF_HIP(gf::dev_malloc((void**)&dout, size_t(n_enc)));
         GF_HIP(hipMemcpy(din, enc_in, size_t(n_enc) * 4, hipMemcpyHostToDevice));
         hipLaunchKernelGGL(gf::k_e4m3_encode, dim3((n_enc + 255) / 256), dim3(256), 0, 0, din, n_enc, dout);
         GF_HIP(hipGetLastError());
         GF_HIP(hipMemcpy(enc_out, dout, size_t(n_enc), hipMemcpyDeviceToHost));
-        (void)hipFree(din);
-        (void)hipFree(dout);
+        gf::dev_free(din);
+        gf::dev_free(dout);
     }
     return GF_OK;
 }

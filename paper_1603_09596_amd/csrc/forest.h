@@ -34,6 +34,13 @@ struct HostForest {
     int64_t real_leaves = 0;          // leaves of the trees themselves (m 2^H without jitter)
 };
 
+// Device memory of the library: hipMalloc / hipFree that keep a running
+// total, and refuse (hipErrorOutOfMemory) any allocation that would take it
+// above GF_MAX_DEVICE_BYTES when that environment variable is set.
+hipError_t dev_malloc(void** p, size_t bytes);
+void dev_free(void* p);
+size_t dev_bytes_held();
+
 // Counter-based RNG (splitmix64 output function, keyed).
 uint64_t splitmix64(uint64_t x);
 uint64_t keyed_draw(uint64_t seed, uint64_t stream, uint64_t tree, uint64_t idx);

@@ -129,6 +129,12 @@ struct ScanArgs {
 hipError_t launch_scan(const ScanArgs& a, int form, hipStream_t st);
 // LDS of a scan workgroup whose bitmap covers `words` words (ceil(n/32) unsliced).
 size_t scan_lds_bytes_words(int64_t words, int form, int64_t ld8);
+// Most bitmap words one scan workgroup's LDS holds (a multiple of 16), 0
+// when not even one step fits (FP8 rows too wide to stage the query).  Id
+// ranges above it are cut into slices of at most this many words.
+int64_t scan_max_slice_words(int form, int64_t ld8);
+// Number of set bits of each query's row of an [nq][nbmw] bitmap.
+hipError_t launch_count_bits(const uint32_t* bits, int nq, int64_t nbmw, int64_t* count, hipStream_t st);
 size_t scan_lds_bytes(int64_t n, int form, int64_t ld8);
 bool scan_supported(int64_t n, int form, int64_t ld8);
 

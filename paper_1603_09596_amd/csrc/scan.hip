@@ -156,8 +156,9 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
                          kThreads, w_lo, w_lo + nbmw);
     __syncthreads();
     if (a.cand_bits) {
+        // this slice's words of the query's row of the candidate bitmap
         for (int64_t i = threadIdx.x; i < nbmw; i += kThreads)
-            a.cand_bits[int64_t(q) * nbmw + i] = bm[i];
+            a.cand_bits[int64_t(q) * nbmw_all + w_lo + i] = bm[i];
     }
     if (a.ncand) {
         uint32_t cnt = 0;
@@ -428,8 +429,14 @@ bool scan_supported(int64_t n, int form, int64_t ld8) {
     return scan_lds_bytes(n, form, ld8) <= 160 * 1024;
 }
 
+int64_t scan_max_slice_words(int form, int64_t ld8) {
+    const size_t fixed = scan_lds_bytes_words(0, form, ld8);
+    if (fixed + size_t(kListWords) * 4 > 160 * 1024) return 0;
+    return int64_t((160 * 1024 - fixed) / 4) / kListWords * kListWords;
+}
+
 hipError_t launch_scan(const ScanArgs& a, int form, hipStream_t st) {
-    if (a.nslice > 1 && (a.slice_words % kListWords || a.cand_bits || a.ncand ||
+    if (a.nslice > 1 && (a.slice_words % kListWords || a.ncand ||
                          a.slice_words * a.nslice < (a.n + 31) / 32 || !a.part_s || !a.part_i))
         return hipErrorInvalidValue;
     const size_t lds = a.nslice > 1 ? scan_lds_bytes_words(a.slice_words, form, a.ld8)

@@ -684,6 +684,12 @@ hipError_t launch_tile_expand(const ExpandArgs& e, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_count_bits(const uint32_t* bits, int nq, int64_t nbmw, int64_t* count, hipStream_t st) {
+    if (nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_bits, dim3(unsigned(nq)), dim3(256), 0, st, bits, nbmw, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_tile_trace(const ExpandArgs& e, uint32_t* cand_bits, int64_t* ncand, hipStream_t st) {
     hipError_t err = launch_tile_expand(e, st);
     if (err != hipSuccess) return err;

@@ -29,7 +29,7 @@ EXPORTED = ["gf_build_forest", "gf_build_forest_ex", "gf_free_forest", "gf_fores
             "gf_query_multi", "gf_multi_stats", "gf_query_trace", "gf_query_trace_ex",
             "gf_query_noalloc",
             "gf_fp8_tables", "gf_hbm_probe",
-            "gf_last_query_timing", "gf_last_error", "gf_version"]
+            "gf_last_query_timing", "gf_last_error", "gf_version", "gf_device_bytes"]
 MULTI_AUTOTUNE, MULTI_EAGER = 1, 2
 
 
@@ -77,9 +77,11 @@ def load():
     lib.gf_hbm_probe.argtypes = [P, i64, i32, P, P]
     lib.gf_last_query_timing.argtypes = [P, i32, P, P]
     lib.gf_last_error.restype = ctypes.c_char_p
+    lib.gf_device_bytes.restype = ctypes.c_int64
+    lib.gf_device_bytes.argtypes = []
     lib.gf_version.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("gf_last_error", "gf_version"):
+        if name not in ("gf_last_error", "gf_version", "gf_device_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -133,3 +133,16 @@ def test_build_refuses_a_near_tie_in_D_before_hip(lib):
     assert lib.gf_build_forest(p, 500, 6, 2, 3, 8, 1, 0, None, ctypes.byref(out)) == geraf.GF_EINVAL
     assert b"near-tie" in lib.gf_last_error()
     assert not out.value
+
+
+def test_device_memory_cap_refuses_a_build_before_hip(lib, monkeypatch):
+    """GF_MAX_DEVICE_BYTES below the FP32 rows: GF_ENOMEM with no HIP call
+    (this runs without a GPU)."""
+    X = np.zeros((100, 8), np.float32)
+    out = ctypes.c_void_p()
+    monkeypatch.setenv("GF_MAX_DEVICE_BYTES", "1000")
+    st = lib.gf_build_forest(X.ctypes.data_as(ctypes.c_void_p), 100, 8, 2, 2, 4, 0, 0, None,
+                             ctypes.byref(out))
+    assert st == geraf.GF_ENOMEM
+    assert b"GF_MAX_DEVICE_BYTES" in lib.gf_last_error()
+    assert lib.gf_device_bytes() == 0

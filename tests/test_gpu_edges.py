@@ -146,3 +146,95 @@ def test_more_queries_than_one_batch(form, path, monkeypatch):
             assert abs(dd_h[i][r] - true_d) <= 1e-5 * true_d
         hits += len(set(got.tolist()) & set(ref["ids"][j].tolist()))
     assert hits / ref["ids"].size >= 0.95
+
+
+def test_device_memory_cap_enomem_and_recovery(monkeypatch):
+    """Under GF_MAX_DEVICE_BYTES a query whose workspace would exceed the cap
+    fails with GF_ENOMEM and leaves the forest usable; a build refused part
+    way releases what it had allocated."""
+    rng = np.random.default_rng(31)
+    X = rng.standard_normal((4000, 32)).astype(np.float32)
+    Q = rng.standard_normal((3000, 32)).astype(np.float32)
+    base = geraf.load().gf_device_bytes()
+    F = geraf.build_forest(X, 4, 5, 8, 1)
+    held = geraf.load().gf_device_bytes()
+    assert held > base
+    ids = torch.empty((3000, 5), dtype=torch.int32, device="cuda:0")
+    dd = torch.empty((3000, 5), dtype=torch.float32, device="cuda:0")
+    monkeypatch.setenv("GF_MAX_DEVICE_BYTES", str(held + 4096))
+    with pytest.raises(geraf.GerafError) as e:
+        geraf.query(F, torch.from_numpy(Q).to("cuda:0"), 5, 64, ids, dd)
+    assert e.value.status == geraf.GF_ENOMEM
+    # a build whose FP32 rows (4000 x 32 floats) fit but whose trees do not
+    monkeypatch.setenv("GF_MAX_DEVICE_BYTES", str(held + 4000 * 32 * 4 + 1000))
+    with pytest.raises(geraf.GerafError) as e:
+        geraf.build_forest(X, 4, 5, 8, 1)
+    assert e.value.status == geraf.GF_ENOMEM
+    assert geraf.load().gf_device_bytes() == held
+    monkeypatch.delenv("GF_MAX_DEVICE_BYTES")
+    geraf.query(F, torch.from_numpy(Q).to("cuda:0"), 5, 64, ids, dd)
+    torch.cuda.synchronize()
+    assert (ids.cpu().numpy() >= 0).all()
+    F.free()
+    assert geraf.load().gf_device_bytes() == base
+
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def test_ids_beyond_one_workgroup_bitmap(monkeypatch):
+    """n = 1.5M (47k bitmap words, above the ~37k one scan workgroup's LDS
+    holds): the row scan cuts every query's id range into slices, traces
+    included.  Opened leaves and candidate sets bit-exact, FP32 neighbours
+    by the acceptance rule; the BF16 form on both paths (the tile path and
+    the sliced row scan) returns candidates with exact
+    FP32 distances.  GF_SCAN_PATH forces each path."""
+    rng = np.random.default_rng(41)
+    n, d = 1_500_000, 16
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Q = (X[rng.integers(0, n, 24)] + 0.1 * rng.standard_normal((24, d))).astype(np.float32)
+    m, t, p, seed = 4, 6, 32, 5
+    Fg = geraf.build_forest(X, m, t, p, seed, forms=("bf16",))
+    Fo = oracle.build_forest(X, m, t, p, seed)
+    assert_tree_arrays_equal(Fg.export_tree(), Fo)
+    k = 10
+    for c in (40, 600):
+        ref = oracle.search(Fo, X, Q, k, c, candidates=True)
+        nq = len(Q)
+        lb = np.zeros((nq, Fg.m, Fg.leaf_words), np.uint32)
+        cb = np.zeros((nq, (n + 31) // 32), np.uint32)
+        nc = np.zeros(nq, np.int64)
+        geraf.query_trace(Fg, Q, c, leaf_bits=lb, cand_bits=cb, ncand=nc)
+        for i in range(nq):
+            assert leaf_set_from_bits(lb[i]) == set(ref["opened"][i].tolist()), f"c={c} query {i}"
+            assert np.array_equal(ids_from_bits(cb[i], n), ref["cand"][i]), f"c={c} query {i}"
+        assert np.array_equal(nc, ref["ncand"])
+        # counts alone (a sliced trace sums them from the bitmap rows)
+        nc2 = np.zeros(nq, np.int64)
+        geraf.query_trace(Fg, Q, c, ncand=nc2)
+        assert np.array_equal(nc2, ref["ncand"])
+        ids = torch.empty((nq, k), dtype=torch.int32, device="cuda:0")
+        dd = torch.empty((nq, k), dtype=torch.float32, device="cuda:0")
+        geraf.query(Fg, dev(Q), k, c, ids, dd)
+        torch.cuda.synchronize()
+        check_knn(ids.cpu().numpy(), dd.cpu().numpy(), ref["ids"], ref["dists"], X=X, Q=Q,
+                  cand=ref["cand"])
+        for path in ("tile", "rows"):
+            nb = 16
+            monkeypatch.setenv("GF_SCAN_PATH", path)
+            ib = torch.empty((nb, k), dtype=torch.int32, device="cuda:0")
+            db = torch.empty((nb, k), dtype=torch.float32, device="cuda:0")
+            geraf.query(Fg, dev(Q[:nb]), k, c, ib, db, form="bf16")
+            torch.cuda.synchronize()
+            monkeypatch.delenv("GF_SCAN_PATH")
+            assert geraf.last_query_timing()["path"] == path
+            ib, db = ib.cpu().numpy(), db.cpu().numpy()
+            for i in range(nb):
+                got = ib[i][ib[i] >= 0]
+                assert np.isin(got, ref["cand"][i]).all()
+                for r, gid in enumerate(got.tolist()):
+                    diff = X[gid].astype(np.float64) - Q[i].astype(np.float64)
+                    assert abs(db[i][r] - float(diff @ diff)) <= 1e-5 * float(diff @ diff)
+    Fg.free()
