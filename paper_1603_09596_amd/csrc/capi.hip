@@ -319,7 +319,8 @@ WsLayout ws_layout(const gf_forest* F, int nb, int k, int form, bool tile, int64
         const TilePlan tp = tile_plan(F, nb, form, checks_max);
         L.oopen = c.take<uint32_t>(size_t(tp.nchunk) * F->host.m * (size_t{1} << F->host.H) * tp.cw);
         L.ovis = c.take<uint32_t>(size_t(tp.nchunk) * F->host.n * tp.cw);
-        L.othr = c.take<uint32_t>(nb);
+        // per query the shared bound and the splits' rank scores
+        L.othr = c.take<uint32_t>(size_t(nb) * gf::kBoundWords);
         const size_t lists = form == gf::kFormFP8 ? 1 : size_t(tp.nsplit);
         L.ops = c.take<float>(size_t(nb) * lists * gf::kTileList);
         L.opi = c.take<int>(size_t(nb) * lists * gf::kTileList);
@@ -615,11 +616,16 @@ gf_status launch_tile(gf_forest* F, const QueryJob& J, int nb, const Workspace& 
     ta.nq = nb; ta.n = h.n; ta.ld16 = F->ld16; ta.cw = tp.cw; ta.Q16 = w.Q16; ta.X16 = F->X16;
     ta.norm16 = F->norm16; ta.visT = w.visT; ta.gthr = w.gthr; ta.cap = J.kk; ta.nsplit = tp.nsplit;
     ta.split_pts = tp.split_pts; ta.part_s = w.part_s; ta.part_i = w.part_i;
+    // rank scores: each of 2 or 3 splits publishes its ceil(kk / nsplit)-th best
+    ta.nrb = (tp.nsplit >= 2 && tp.nsplit < gf::kBoundWords) ? tp.nsplit : 0;
+    ta.rpos = ta.nrb ? J.kk - (J.kk + tp.nsplit - 1) / tp.nsplit : 0;
+    gf::ExpandArgs eb = ea;
+    eb.nrb = ta.nrb;
     gf::MergeArgs ma{};
     ma.nq = nb; ma.k = J.k; ma.kk = J.kk; ma.d = h.d; ma.nsplit = tp.nsplit; ma.rerank = true;
     ma.part_s = w.part_s; ma.part_i = w.part_i; ma.Q = w.Qp; ma.ldq = F->ld32;
     ma.X32 = F->X32; ma.ld32 = F->ld32; ma.ids = ca.ids; ma.dists = ca.dists;
-    GF_HIP(gf::launch_tile_path(ea, ta, ma, st, ev));
+    GF_HIP(gf::launch_tile_path(eb, ta, ma, st, ev));
     return GF_OK;
 }
 

@@ -141,6 +141,7 @@ bool scan_supported(int64_t n, int form, int64_t ld8);
 // ------------------------------------------------------- tile (MFMA) path
 
 constexpr int kTileList = 48;   // best scores kept per (query, point split)
+constexpr int kBoundWords = 4;   // per query: the shared bound and up to 3 splits' rank scores
 
 // Candidate sets in point-major form for the tile path.  Queries are grouped
 // in chunks of 32 cw (cw words of query bits per row, cw a power of two in
@@ -154,7 +155,10 @@ struct ExpandArgs {
     const uint32_t* order;      // [n] point ids in tree 0's leaf order (the expansion's order)
     uint32_t* openT;            // [nchunk][m 2^H][cw] queries that opened each leaf
     uint32_t* visT;             // [nchunk][n][cw] queries having each point as candidate
-    uint32_t* gthr;             // [nq] set to the bits of +inf here
+    uint32_t* gthr;             // [nq][kBoundWords]: word 0 set to the bits of +inf
+                                // here, words 1..nrb to 0xFFFFFFFF (no rank score
+                                // yet), the rest to 0
+    int nrb;                    // the tile kernel's rank-score splits (0: none)
 };
 
 struct TileArgs {
@@ -165,10 +169,15 @@ struct TileArgs {
     const uint16_t* X16;        // [n][ld16]
     const float* norm16;        // [n]
     const uint32_t* visT;       // [nchunk][n][cw]
-    uint32_t* gthr;             // [nq] order-preserving bits of an upper bound on
-                                // each query's cap-th best score
+    // [nq][kBoundWords]: word 0 holds the order-preserving bits of an upper
+    // bound on the query's cap-th best score; words 1..nrb the splits' rank
+    // scores (2 <= nsplit <= kBoundWords - 1 gives nrb = nsplit, else 0):
+    // split s's rpub-th best, rpub = ceil(cap / nsplit), so that the largest
+    // of the nrb is a bound as well, and is published to word 0.
+    uint32_t* gthr;
     int cap;                    // list capacity per (query, split): the merge's kk, <= kTileList
     int nsplit;
+    int nrb, rpos;              // rpos = cap - rpub: the list position of rank rpub - 1
     int64_t split_pts;          // points per split, multiple of 64, split_pts * ld16 * 2 < 2^31
     float* part_s;              // [nq][nsplit][kTileList]
     int* part_i;

@@ -54,30 +54,28 @@ constexpr int kSlots = 3;             // list entries per lane and query (x 16 l
 constexpr int kExpandThreads = 1024;
 constexpr int kXcds = 8;              // XCDs of an MI355X (32 CUs each)
 
-// One DPP step of a 16-lane reduction (a DPP row is a quarter-wave).
-template <int CTRL>
-__device__ __forceinline__ void quarter_max_step(float& s, int& i) {
-    const float os = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), CTRL, 0xF, 0xF, false));
-    const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
-    if (entry_before(s, i, os, oi)) { s = os; i = oi; }
+// DPP moves within a quarter-wave (a DPP row): lane c takes lane c + 1
+// (c = 15 takes lane 0), and every lane takes lane 0.
+__device__ __forceinline__ int row_next(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x12F, 0xF, 0xF, false);   // row_ror:15
 }
-
-// Lexicographic maximum of (s, i) over the 16 lanes of a quarter-wave:
-// pairs, quads, halves of the row, whole row.
-__device__ __forceinline__ void quarter_max(float& s, int& i) {
-    quarter_max_step<0xB1>(s, i);    // quad_perm [1, 0, 3, 2]
-    quarter_max_step<0x4E>(s, i);    // quad_perm [2, 3, 0, 1]
-    quarter_max_step<0x141>(s, i);   // row_half_mirror
-    quarter_max_step<0x140>(s, i);   // row_mirror
+__device__ __forceinline__ float row_next(float v) { return __int_as_float(row_next(__float_as_int(v))); }
+__device__ __forceinline__ int row_first(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x150, 0xF, 0xF, false);   // row_newbcast:0
 }
+__device__ __forceinline__ float row_first(float v) { return __int_as_float(row_first(__float_as_int(v))); }
 
 // Offer every lane's (sc, id) with cand set to the list of its quarter-wave.
-// The 16 lanes 16u..16u+15 share one query's list of 48 slots (lane c
-// holds entries 3c..3c+2 in registers, unsorted) and keep its current worst
-// entry (ts, ti).  The four quarters insert in parallel; a candidate
-// replaces the worst entry when it precedes it.
+// The 16 lanes 16u..16u+15 share one query's list, kept in order across the
+// lanes: position p = 16 j + c (slot j of lane c) holds the entry of rank
+// cap - 1 - p, so position 0 is the worst and position cap - 1 the best;
+// positions from cap on hold (-inf, -1), which precede every score and never
+// move.  Each round the four quarters take their lowest pending candidate;
+// where it precedes the worst entry (position 0, lane 0 of the quarter), the
+// positions below its place take their successor's entry (the worst drops
+// out) and its place takes the candidate, all in registers.
 __device__ __forceinline__ void quarter_offer(bool cand, float sc, int id, float (&vs)[kSlots],
-                                              int (&vi)[kSlots], float& ts, int& ti) {
+                                              int (&vi)[kSlots]) {
     const int lane = threadIdx.x & (kWave - 1);
     const int quarter = lane >> 4, col = lane & 15;
     uint64_t m = __ballot(cand);
@@ -86,32 +84,26 @@ __device__ __forceinline__ void quarter_offer(bool cand, float sc, int id, float
         const int src = 16 * quarter + (qm ? __builtin_ctz(qm) : 0);
         const float cs = __shfl(sc, src);
         const int ci = __shfl(id, src);
-        const bool ins = qm != 0 && entry_before(cs, ci, ts, ti);
-        int slot = -1;
+        const bool go = qm != 0 && entry_before(cs, ci, row_first(vs[0]), row_first(vi[0]));
+        // the entry one position up: the next lane's, or for lane 15 lane 0's
+        // of the next slot; past the last slot the (-inf, -1) end mark
+        float ns[kSlots];
+        int ni[kSlots];
 #pragma unroll
-        for (int j = 0; j < kSlots; ++j)
-            if (vs[j] == ts && vi[j] == ti) slot = j;
-        const uint64_t hb = __ballot(ins && slot >= 0);
-        const uint32_t hq = uint32_t(hb >> (16 * quarter)) & 0xFFFFu;
-        if (ins && hq && col == __builtin_ctz(hq)) {
-#pragma unroll
-            for (int j = 0; j < kSlots; ++j)
-                if (j == slot) { vs[j] = cs; vi[j] = ci; }
+        for (int j = 0; j < kSlots; ++j) {
+            ns[j] = row_next(vs[j]);
+            ni[j] = row_next(vi[j]);
         }
-        float ws = vs[0];
-        int wi = vi[0];
 #pragma unroll
-        for (int j = 1; j < kSlots; ++j)
-            if (entry_before(ws, wi, vs[j], vi[j])) { ws = vs[j]; wi = vi[j]; }
-        quarter_max(ws, wi);
-        if (ins) { ts = ws; ti = wi; }
-        uint64_t low = 0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint64_t mq = (m >> (16 * u)) & 0xFFFFull;
-            low |= (mq & (~mq + 1)) << (16 * u);
+        for (int j = 0; j < kSlots; ++j) {
+            const float us = col < 15 ? ns[j] : (j + 1 < kSlots ? ns[j + 1] : -__builtin_inff());
+            const int ui = col < 15 ? ni[j] : (j + 1 < kSlots ? ni[j + 1] : -1);
+            const bool keep = !go || entry_before(vs[j], vi[j], cs, ci);
+            const bool place = entry_before(us, ui, cs, ci);
+            vs[j] = keep ? vs[j] : (place ? cs : us);
+            vi[j] = keep ? vi[j] : (place ? ci : ui);
         }
-        m &= ~low;
+        m &= ~__ballot(qm != 0 && lane == src);   // each quarter's candidate is done
     }
 }
 
@@ -128,9 +120,10 @@ constexpr int kRowsPerInst = kWave / kUnits;           // rows per 1 KB wave ins
 constexpr int kDmaPerWave = kStageBytes / 1024 / kTWaves;   // 4
 static_assert(kRowsPerInst * kUnits == kWave && kDmaPerWave * kTWaves * 1024 == kStageBytes, "stage shape");
 // epilogue operands per tile (dwords): 4 candidate words per point, the
-// points' norms, the block's 128 shared thresholds
+// points' norms, the block's 128 rows of shared bounds (kBoundWords each)
 constexpr int kEpiVis = 0, kEpiNorm = 4 * kTP, kEpiThr = 5 * kTP;
-constexpr int kEpi = 5 * kTP + kTQ;
+constexpr int kEpi = 5 * kTP + kBoundWords * kTQ;
+static_assert(kBoundWords == 4, "one 16-byte load per query's bound row");
 
 // Order-preserving map of float scores to uint32 (a < b <=> key(a) < key(b)).
 __device__ __forceinline__ uint32_t score_key(float f) {
@@ -172,10 +165,14 @@ __device__ __forceinline__ void dma_4(const void* g, uint32_t lds) {
     asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off"
                  :: "v"(g), "{m0}"(__builtin_amdgcn_readfirstlane(lds)) : "memory");
 }
-// Device-scope variant (sc1: served by L2, not a CU cache) for values that
+// Device-scope variants (sc1: served by L2, not a CU cache) for values that
 // other workgroups update with atomics during the kernel.
 __device__ __forceinline__ void dma_4_dev(const void* g, uint32_t lds) {
     asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off sc1"
+                 :: "v"(g), "{m0}"(__builtin_amdgcn_readfirstlane(lds)) : "memory");
+}
+__device__ __forceinline__ void dma_16_dev(const void* g, uint32_t lds) {
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off sc1"
                  :: "v"(g), "{m0}"(__builtin_amdgcn_readfirstlane(lds)) : "memory");
 }
 
@@ -243,18 +240,17 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     // the A operands are complete before any direct load is issued, so the
     // compiler has no pending load of its own to wait for inside the loop
     __builtin_amdgcn_s_waitcnt(kWaitVm(0));
-    // the lists of this lane's four queries: kSlots entries each, in registers.
-    // Entries past the capacity hold (-inf, -1), which precede every score,
-    // so they are never the worst entry: a list then keeps its cap best.
-    float ts[4], ls[4][kSlots];
-    int ti[4], li[4][kSlots];
+    // the lists of this lane's four queries: kSlots positions each (position
+    // 16 j + col in slot j), in registers, ordered from the worst entry at
+    // position 0.  Positions from the capacity on hold (-inf, -1), which
+    // precede every score, so a list keeps its cap best.
+    float ls[4][kSlots];
+    int li[4][kSlots];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        ts[i] = __builtin_inff();
-        ti[i] = 0x7FFFFFFF;
 #pragma unroll
         for (int j = 0; j < kSlots; ++j) {
-            const bool pad = col * kSlots + j >= a.cap;
+            const bool pad = 16 * j + col >= a.cap;
             ls[i][j] = pad ? -__builtin_inff() : __builtin_inff();
             li[i][j] = pad ? -1 : 0x7FFFFFFF;
         }
@@ -316,7 +312,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         }
     };
     // wave 0 loads the tile's candidate words, wave 1 its norms, waves 2 and
-    // 3 the block's thresholds
+    // 3 the block's bound rows
     auto issue_epi = [&](int t) {
         const int xl = t * kTP + lane;
         const int xc = xl < npts ? xl : 0;
@@ -326,7 +322,8 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             dma_4(a.norm16 + pb + xc, epi0 + 4u * kEpiNorm);
         } else if (wave < 4) {
             const int qq = qblk * kTQ + (wave - 2) * kWave + lane;
-            dma_4_dev(a.gthr + (qq < a.nq ? qq : 0), epi0 + 4u * (kEpiThr + (wave - 2) * kWave));
+            dma_16_dev(a.gthr + kBoundWords * (qq < a.nq ? qq : 0),
+                       epi0 + 4u * (kEpiThr + kBoundWords * (wave - 2) * kWave));
         }
     };
     set_rows();
@@ -439,7 +436,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         bool any = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            lim[i] = fminf(ts[i], key_score(epi[kEpiThr + q0 - qblk * kTQ + 4 * quarter + i]));
+            lim[i] = fminf(row_first(ls[i][0]), key_score(epi[kEpiThr + kBoundWords * (q0 - qblk * kTQ + 4 * quarter + i)]));
             bm[i] = __builtin_inff();
 #pragma unroll
             for (int b = 0; b < 4; ++b)
@@ -449,6 +446,11 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         // Only queries with a candidate at or below their limit in this tile
         // go through the (rare) insertions, one score at a time.
         if (__ballot(any)) {
+            // the lane's first query, made opaque so that the addresses and
+            // tests derived from it are formed here when needed rather than
+            // held in registers across the whole loop
+            int qme = q0 + 4 * quarter;
+            asm volatile("" : "+v"(qme));
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (!__ballot(bm[i] <= lim[i])) continue;
@@ -456,13 +458,35 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
                 for (int b = 0; b < 4; ++b) {
                     const int x = int(pb) + t * kTP + 16 * b + col;
                     const bool cand = ((word[b] >> i) & 1u) && sum[b][i] <= lim[i];
-                    quarter_offer(cand, sum[b][i], x, ls[i], li[i], ts[i], ti[i]);
-                    lim[i] = fminf(lim[i], ts[i]);
+                    quarter_offer(cand, sum[b][i], x, ls[i], li[i]);
+                    lim[i] = fminf(lim[i], row_first(ls[i][0]));
                 }
-                // publish a full list's worst score as a bound for the other splits
-                const int q = q0 + 4 * quarter + i;
-                const float g = key_score(epi[kEpiThr + q0 - qblk * kTQ + 4 * quarter + i]);
-                if (col == 0 && q < a.nq && ts[i] < g) atomicMin(a.gthr + q, score_key(ts[i]));
+                // publish a full list's worst score as a bound for the other
+                // splits, and the score of its rank rpub - 1
+                const int q = qme + i;
+                uint32_t* br = epi + kEpiThr + kBoundWords * (q - qblk * kTQ);   // its bound row
+                uint32_t* gr = a.gthr + int64_t(kBoundWords) * q;
+                if (col == 0 && q < a.nq && ls[i][0] < key_score(br[0])) atomicMin(gr, score_key(ls[i][0]));
+                if (a.nrb) {
+                    // Every split holds rpub entries at or below its published
+                    // score, so the largest of the nrb scores has nrb rpub >= cap
+                    // entries at or below it: a bound on the cap-th best too.
+                    // The other splits' scores come from this tile's copy; an
+                    // older (larger) score only loosens the bound.
+                    // (the lane holding position rpos publishes it)
+                    const int rj = a.rpos >> 4;
+                    const float rv = rj == 0 ? ls[i][0] : (rj == 1 ? ls[i][1] : ls[i][2]);
+                    const uint32_t rk = score_key(rv);
+                    if (col == (a.rpos & 15) && q < a.nq && rv < __builtin_inff() && rk < br[1 + split]) {
+                        atomicMin(gr + 1 + split, rk);
+                        // this tile's copy of the row takes the new score (only
+                        // this lane reads the rank words of this query), and
+                        // words past nrb hold 0
+                        br[1 + split] = rk;
+                        const uint32_t bk = max(max(br[1], br[2]), br[3]);
+                        if (bk < br[0]) atomicMin(gr, bk);
+                    }
+                }
             }
         }
     }
@@ -513,7 +537,11 @@ __global__ __launch_bounds__(1024) void k_open_transpose(ExpandArgs a) {
 #pragma unroll
     for (int u = 0; u < kTransposeWords; ++u)
         bits[u] = (q < a.nq && f0 + u < words) ? a.leafbits[(f0 + u) * a.nq + q] : 0u;
-    if (f0 == 0 && q < a.nq) a.gthr[q] = 0xFF800000u;   // shared bound +inf
+    if (f0 == 0 && q < a.nq) {
+        // shared bound +inf; no rank scores yet (words past nrb: 0, no split)
+        a.gthr[int64_t(kBoundWords) * q] = 0xFF800000u;
+        for (int u = 1; u < kBoundWords; ++u) a.gthr[int64_t(kBoundWords) * q + u] = u <= a.nrb ? 0xFFFFFFFFu : 0u;
+    }
     constexpr uint32_t kLow[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
 #pragma unroll
     for (int u = 0; u < kTransposeWords; ++u) {

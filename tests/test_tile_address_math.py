@@ -5,14 +5,15 @@ epilogue operands into LDS with direct loads whose addresses it computes
 itself: per stage, instruction j of wave w has lane l read 16 bytes at byte
 offset trow[j] + koff of its split's rows and write them at LDS byte
 xs0 + buf * 32 KiB + (w + 8 j) * 1 KiB + 16 l; per tile, waves 0..3 load
-the candidate words, the norms and the block's shared bounds into the
+the candidate words, the norms and the block's rows of shared bounds (four
+words per query: the bound and up to three splits' rank scores) into the
 epilogue area, and the two waves of each pair swap partial sums through a
 32 KiB exchange area.  This test recomputes those offsets with the kernel's
 formulas for every configuration launch_tile_path admits (the row stride,
 the template k depth, ragged point counts and splits, query chunkings) and
 asserts that every global access lies inside its buffer and every LDS target
-inside the kernel's static allocation (3 x 32 KiB stages + 448-word
-epilogue area + 32 KiB exchange = 129.75 KiB).  No GPU."""
+inside the kernel's static allocation (3 x 32 KiB stages + 832-word
+epilogue area + 32 KiB exchange = 131.25 KiB).  No GPU."""
 import numpy as np
 import pytest
 
@@ -21,8 +22,9 @@ KSTAGE = KTP * KKS * 2                      # bytes per stage
 KUNITS = KKS // 8                           # 16-byte units per staged row
 KROWS_PER_INST = KWAVE // KUNITS            # rows per 1 KiB wave instruction
 KDMA_PER_WAVE = KSTAGE // 1024 // KTWAVES   # 4
+KBOUND_WORDS = 4                            # per query: shared bound + 3 rank scores
 KEPI_VIS, KEPI_NORM, KEPI_THR = 0, 4 * KTP, 5 * KTP
-KEPI_WORDS = 5 * KTP + KTQ
+KEPI_WORDS = 5 * KTP + KBOUND_WORDS * KTQ
 KXCH_BYTES = KTWAVES * 4 * KWAVE * 16      # f4 partial sums [wave][block][lane]
 LDS_BYTES = KNBUF * KSTAGE + 4 * KEPI_WORDS + KXCH_BYTES
 KSTEPS_TEMPLATES = (4, 8, 12, 16, 20, 24, 28, 30, 32)
@@ -93,8 +95,9 @@ def check_stage_loads(n, ld16, split_pts):
 
 
 def check_epilogue_loads(n, nq, cw, split_pts):
-    """Candidate words (16 B per lane), norms and shared bounds (4 B per
-    lane) of every tile of every (query block, split)."""
+    """Candidate words (16 B per lane), norms (4 B per lane) and bound rows
+    (16 B per lane) of every tile of every (query block, split); the bound
+    rows are [nq][4] words."""
     nqw = (nq + 31) // 32
     nchunk = (nqw + cw - 1) // cw
     vis_words = nchunk * n * cw
@@ -106,10 +109,11 @@ def check_epilogue_loads(n, nq, cw, split_pts):
         assert wo + 4 <= cw
         for w in (2, 3):
             qq = qblk * KTQ + (w - 2) * KWAVE + lane
-            g = np.where(qq < nq, qq, 0)
-            assert g.max() < nq
-            lds = 4 * (KEPI_THR + (w - 2) * KWAVE) + 4 * lane
-            assert (lds + 4).max() <= 4 * KEPI_WORDS
+            g = KBOUND_WORDS * np.where(qq < nq, qq, 0)      # words from gthr's base
+            assert g.min() >= 0 and (g + KBOUND_WORDS).max() <= KBOUND_WORDS * nq
+            assert (g % 4 == 0).all()                        # 16-byte aligned
+            lds = 4 * (KEPI_THR + KBOUND_WORDS * (w - 2) * KWAVE) + 16 * lane
+            assert lds.min() >= 4 * KEPI_THR and (lds + 16).max() <= 4 * KEPI_WORDS
         for split in sorted({0, 1, nsplit - 2, nsplit - 1} & set(range(nsplit))):
             pb = split * split_pts
             npts = split_pts if pb + split_pts < n else n - pb
@@ -125,8 +129,8 @@ def check_epilogue_loads(n, nq, cw, split_pts):
                 assert (4 * KEPI_NORM + 4 * lane + 4).max() <= 4 * KEPI_THR
 
 
-def test_static_lds_allocation_is_129_75_kib():
-    assert LDS_BYTES == 3 * 32768 + 1792 + 32768
+def test_static_lds_allocation_is_131_25_kib():
+    assert LDS_BYTES == 3 * 32768 + 3328 + 32768
     assert LDS_BYTES <= 160 * 1024
 
 
