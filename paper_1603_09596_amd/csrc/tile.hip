@@ -54,56 +54,73 @@ constexpr int kSlots = 3;             // list entries per lane and query (x 16 l
 constexpr int kExpandThreads = 1024;
 constexpr int kXcds = 8;              // XCDs of an MI355X (32 CUs each)
 
+// Order-preserving map of float scores to uint32 (a < b <=> key(a) < key(b)).
+__device__ __forceinline__ uint32_t score_key(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key_score(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// List entries as 64-bit keys: the score's key above the id with its sign bit
+// flipped, so that one unsigned comparison is the (score, id) order.  Scores
+// are finite and never -0 (a score is a norm minus twice a product, and x - x
+// rounds to +0), so the key order is the order entry_before uses.  Key 0
+// precedes every entry (the end mark) and kEmpty follows every entry.
+constexpr uint64_t kEmpty = ~uint64_t{0};
+__device__ __forceinline__ uint64_t entry_key(float s, int id) {
+    return (uint64_t(score_key(s)) << 32) | (uint32_t(id) ^ 0x80000000u);
+}
+__device__ __forceinline__ float entry_score(uint64_t k) { return key_score(uint32_t(k >> 32)); }
+__device__ __forceinline__ int entry_id(uint64_t k) { return int(uint32_t(k) ^ 0x80000000u); }
+
 // DPP moves within a quarter-wave (a DPP row): lane c takes lane c + 1
 // (c = 15 takes lane 0), and every lane takes lane 0.
-__device__ __forceinline__ int row_next(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x12F, 0xF, 0xF, false);   // row_ror:15
+__device__ __forceinline__ uint32_t row_next(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x12F, 0xF, 0xF, false));   // row_ror:15
 }
-__device__ __forceinline__ float row_next(float v) { return __int_as_float(row_next(__float_as_int(v))); }
-__device__ __forceinline__ int row_first(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x150, 0xF, 0xF, false);   // row_newbcast:0
+__device__ __forceinline__ uint32_t row_first(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x150, 0xF, 0xF, false));   // row_newbcast:0
 }
-__device__ __forceinline__ float row_first(float v) { return __int_as_float(row_first(__float_as_int(v))); }
+__device__ __forceinline__ uint64_t row_next(uint64_t v) {
+    return (uint64_t(row_next(uint32_t(v >> 32))) << 32) | row_next(uint32_t(v));
+}
+__device__ __forceinline__ uint64_t row_first(uint64_t v) {
+    return (uint64_t(row_first(uint32_t(v >> 32))) << 32) | row_first(uint32_t(v));
+}
 
-// Offer every lane's (sc, id) with cand set to the list of its quarter-wave.
+// Offer every lane's entry key with cand set to the list of its quarter-wave.
 // The 16 lanes 16u..16u+15 share one query's list, kept in order across the
 // lanes: position p = 16 j + c (slot j of lane c) holds the entry of rank
 // cap - 1 - p, so position 0 is the worst and position cap - 1 the best;
-// positions from cap on hold (-inf, -1), which precede every score and never
-// move.  Each round the four quarters take their lowest pending candidate;
+// positions from cap on hold key 0, which precedes every entry and never
+// moves.  Each round the four quarters take their lowest pending candidate;
 // where it precedes the worst entry (position 0, lane 0 of the quarter), the
 // positions below its place take their successor's entry (the worst drops
 // out) and its place takes the candidate, all in registers.
-__device__ __forceinline__ void quarter_offer(bool cand, float sc, int id, float (&vs)[kSlots],
-                                              int (&vi)[kSlots]) {
+__device__ __forceinline__ void quarter_offer(bool cand, uint64_t key, uint64_t (&v)[kSlots]) {
     const int lane = threadIdx.x & (kWave - 1);
     const int quarter = lane >> 4, col = lane & 15;
     uint64_t m = __ballot(cand);
     while (m) {
         const uint32_t qm = uint32_t(m >> (16 * quarter)) & 0xFFFFu;
         const int src = 16 * quarter + (qm ? __builtin_ctz(qm) : 0);
-        const float cs = __shfl(sc, src);
-        const int ci = __shfl(id, src);
-        const bool go = qm != 0 && entry_before(cs, ci, row_first(vs[0]), row_first(vi[0]));
+        const uint64_t c = (uint64_t(uint32_t(__shfl(int(key >> 32), src))) << 32) |
+                           uint32_t(__shfl(int(uint32_t(key)), src));
+        const bool go = (qm != 0) & (c < row_first(v[0]));
         // the entry one position up: the next lane's, or for lane 15 lane 0's
-        // of the next slot; past the last slot the (-inf, -1) end mark
-        float ns[kSlots];
-        int ni[kSlots];
+        // of the next slot; past the last slot the end mark
+        uint64_t n[kSlots];
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) n[j] = row_next(v[j]);
 #pragma unroll
         for (int j = 0; j < kSlots; ++j) {
-            ns[j] = row_next(vs[j]);
-            ni[j] = row_next(vi[j]);
+            const uint64_t u = col < 15 ? n[j] : (j + 1 < kSlots ? n[j + 1] : uint64_t{0});
+            const bool keep = (!go) | (v[j] < c);
+            v[j] = keep ? v[j] : (u < c ? c : u);
         }
-#pragma unroll
-        for (int j = 0; j < kSlots; ++j) {
-            const float us = col < 15 ? ns[j] : (j + 1 < kSlots ? ns[j + 1] : -__builtin_inff());
-            const int ui = col < 15 ? ni[j] : (j + 1 < kSlots ? ni[j + 1] : -1);
-            const bool keep = !go || entry_before(vs[j], vi[j], cs, ci);
-            const bool place = entry_before(us, ui, cs, ci);
-            vs[j] = keep ? vs[j] : (place ? cs : us);
-            vi[j] = keep ? vi[j] : (place ? ci : ui);
-        }
-        m &= ~__ballot(qm != 0 && lane == src);   // each quarter's candidate is done
+        m &= ~__ballot((qm != 0) & (lane == src));   // each quarter's candidate is done
     }
 }
 
@@ -124,15 +141,6 @@ static_assert(kRowsPerInst * kUnits == kWave && kDmaPerWave * kTWaves * 1024 == 
 constexpr int kEpiVis = 0, kEpiNorm = 4 * kTP, kEpiThr = 5 * kTP;
 constexpr int kEpi = 5 * kTP + kBoundWords * kTQ;
 static_assert(kBoundWords == 4, "one 16-byte load per query's bound row");
-
-// Order-preserving map of float scores to uint32 (a < b <=> key(a) < key(b)).
-__device__ __forceinline__ uint32_t score_key(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float key_score(uint32_t k) {
-    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
-}
 
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
@@ -242,19 +250,13 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     __builtin_amdgcn_s_waitcnt(kWaitVm(0));
     // the lists of this lane's four queries: kSlots positions each (position
     // 16 j + col in slot j), in registers, ordered from the worst entry at
-    // position 0.  Positions from the capacity on hold (-inf, -1), which
-    // precede every score, so a list keeps its cap best.
-    float ls[4][kSlots];
-    int li[4][kSlots];
+    // position 0.  Positions from the capacity on hold the end mark 0, which
+    // precedes every entry, so a list keeps its cap best.
+    uint64_t lk[4][kSlots];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < kSlots; ++j) {
-            const bool pad = 16 * j + col >= a.cap;
-            ls[i][j] = pad ? -__builtin_inff() : __builtin_inff();
-            li[i][j] = pad ? -1 : 0x7FFFFFFF;
-        }
-    }
+        for (int j = 0; j < kSlots; ++j) lk[i][j] = 16 * j + col >= a.cap ? uint64_t{0} : kEmpty;
 
     const int64_t pb = int64_t(split) * a.split_pts;
     const int npts = int((pb + a.split_pts < a.n) ? a.split_pts : a.n - pb);
@@ -436,7 +438,10 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
         bool any = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            lim[i] = fminf(row_first(ls[i][0]), key_score(epi[kEpiThr + kBoundWords * (q0 - qblk * kTQ + 4 * quarter + i)]));
+            // the list's worst score (NaN, ignored, while the list is not full)
+            // and the shared bound
+            lim[i] = fminf(key_score(row_first(uint32_t(lk[i][0] >> 32))),
+                           key_score(epi[kEpiThr + kBoundWords * (q0 - qblk * kTQ + 4 * quarter + i)]));
             bm[i] = __builtin_inff();
 #pragma unroll
             for (int b = 0; b < 4; ++b)
@@ -458,15 +463,16 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
                 for (int b = 0; b < 4; ++b) {
                     const int x = int(pb) + t * kTP + 16 * b + col;
                     const bool cand = ((word[b] >> i) & 1u) && sum[b][i] <= lim[i];
-                    quarter_offer(cand, sum[b][i], x, ls[i], li[i]);
-                    lim[i] = fminf(lim[i], row_first(ls[i][0]));
+                    quarter_offer(cand, entry_key(sum[b][i], x), lk[i]);
+                    lim[i] = fminf(lim[i], key_score(row_first(uint32_t(lk[i][0] >> 32))));
                 }
                 // publish a full list's worst score as a bound for the other
                 // splits, and the score of its rank rpub - 1
                 const int q = qme + i;
                 uint32_t* br = epi + kEpiThr + kBoundWords * (q - qblk * kTQ);   // its bound row
                 uint32_t* gr = a.gthr + int64_t(kBoundWords) * q;
-                if (col == 0 && q < a.nq && ls[i][0] < key_score(br[0])) atomicMin(gr, score_key(ls[i][0]));
+                const uint32_t wk = uint32_t(lk[i][0] >> 32);   // lane 0: the worst score's key
+                if (col == 0 && q < a.nq && wk < br[0]) atomicMin(gr, wk);
                 if (a.nrb) {
                     // Every split holds rpub entries at or below its published
                     // score, so the largest of the nrb scores has nrb rpub >= cap
@@ -475,9 +481,8 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
                     // older (larger) score only loosens the bound.
                     // (the lane holding position rpos publishes it)
                     const int rj = a.rpos >> 4;
-                    const float rv = rj == 0 ? ls[i][0] : (rj == 1 ? ls[i][1] : ls[i][2]);
-                    const uint32_t rk = score_key(rv);
-                    if (col == (a.rpos & 15) && q < a.nq && rv < __builtin_inff() && rk < br[1 + split]) {
+                    const uint32_t rk = uint32_t((rj == 0 ? lk[i][0] : (rj == 1 ? lk[i][1] : lk[i][2])) >> 32);
+                    if (col == (a.rpos & 15) && q < a.nq && rk < br[1 + split]) {
                         atomicMin(gr + 1 + split, rk);
                         // this tile's copy of the row takes the new score (only
                         // this lane reads the rank words of this query), and
@@ -499,9 +504,10 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             const int64_t base = (int64_t(q) * a.nsplit + split) * kTileList;
 #pragma unroll
             for (int j = 0; j < kSlots; ++j) {
-                const bool pad = li[i][j] < 0;
-                a.part_s[base + col * kSlots + j] = pad ? __builtin_inff() : ls[i][j];
-                a.part_i[base + col * kSlots + j] = pad ? 0x7FFFFFFF : li[i][j];
+                const uint64_t e = lk[i][j];
+                const bool pad = e == 0 || e == kEmpty;
+                a.part_s[base + col * kSlots + j] = pad ? __builtin_inff() : entry_score(e);
+                a.part_i[base + col * kSlots + j] = pad ? 0x7FFFFFFF : entry_id(e);
             }
         }
     }
