@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     // positions unit ^ (r & 15), so the contiguous 1 KB writes of the direct
     // loads and the 16-row B-operand reads are both free of bank conflicts.
     __shared__ __attribute__((aligned(1024))) uint16_t xs[kNBuf * kStageBytes / 2];
-    __shared__ __attribute__((aligned(1024))) uint32_t epi[kEpi];
+    __shared__ __attribute__((aligned(1024))) uint32_t epi[2][kEpi];
     // partial sums handed to the other wave of the pair: [wave][block][lane]
     __shared__ __attribute__((aligned(16))) f4 xch[kTWaves * 4 * kWave];
     const int lane = threadIdx.x & (kWave - 1);
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     const int64_t pb = int64_t(split) * a.split_pts;
     const int npts = int((pb + a.split_pts < a.n) ? a.split_pts : a.n - pb);
     const int ntile = (npts + kTP - 1) / kTP;
-    const uint32_t xs0 = lds_offset(xs), epi0 = lds_offset(epi);
+    const uint32_t xs0 = lds_offset(xs), epib = lds_offset(epi);
     const void* xbase = uniform_ptr(a.X16 + pb * a.ld16);
     const uint32_t rowbytes = uint32_t(a.ld16) * 2u;
     // this block's 128 queries: words wo .. wo + 3 of query chunk qc
@@ -316,6 +316,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     // wave 0 loads the tile's candidate words, wave 1 its norms, waves 2 and
     // 3 the block's bound rows
     auto issue_epi = [&](int t) {
+        const uint32_t epi0 = epib + 4u * kEpi * uint32_t(t & 1);   // this tile's buffer
         const int xl = t * kTP + lane;
         const int xc = xl < npts ? xl : 0;
         if (wave == 0) {
@@ -336,7 +337,12 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
     f4* const xout = xch + wave * 4 * kWave + lane;
     const int xdelta = half ? -4 * 4 * kWave : 4 * 4 * kWave;   // to the partner's slot
     int buf = 0, left = ntile * NC;                  // stages not yet consumed
-    for (int t = 0; t < ntile; ++t) {
+    // The epilogue of tile t runs after the first barrier of tile t + 1 (an
+    // extra pass t = ntile has only that barrier and the last epilogue): the
+    // partial-sum swap needs no barrier of its own, and the epilogue operands
+    // alternate between two LDS buffers.
+    f4 sum[4];
+    for (int t = 0; t <= ntile; ++t) {
         f4 acc[2][4];
 #pragma unroll
         for (int g = 0; g < 2; ++g)
@@ -350,13 +356,101 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             // many stages' worth completes the current stage for this wave,
             // and the barrier then covers every wave (and frees the previous
             // stage's buffer for reuse).
-            static_assert(kNBuf == 3 || kNBuf == 4, "wait immediates for one or two stages ahead");
+            // At a tile's first barrier the swap's LDS writes must be done as
+            // well, and the previous tile's epilogue loads: with more than one
+            // stage per tile a later stage's loads were issued after them, so
+            // the wait covers them; with one stage per tile wait for all.
+            static_assert(kNBuf == 3, "wait immediates for two stages ahead");
             asm volatile("" ::: "memory");
-            if (kNBuf == 4 && left > 2) __builtin_amdgcn_s_waitcnt(kWaitVm(2 * kDmaPerWave));
+            if (c == 0 && (NC == 1 || left < 2)) __builtin_amdgcn_s_waitcnt(kWaitVmLds(0));
+            else if (c == 0) __builtin_amdgcn_s_waitcnt(kWaitVmLds(kDmaPerWave));
             else if (left >= 2) __builtin_amdgcn_s_waitcnt(kWaitVm(kDmaPerWave));
             else __builtin_amdgcn_s_waitcnt(kWaitVm(0));
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
+            if (c == 0 && t > 0) {
+                const int tp = t - 1;                          // the tile this epilogue finishes
+                uint32_t* const E = epi[tp & 1];               // its operands' buffer
+#pragma unroll
+                for (int b = 0; b < 4; ++b) sum[b] += xout[xdelta + b * kWave];
+                // epilogue: C[row 4 quarter + i][col] of block b = q(row) . x(16 b + col).
+                // A point enters a query's list only if it is a candidate of the
+                // query and its score is at most both the list's worst and the
+                // shared bound (an upper bound on the query's cap-th best over
+                // all splits, so nothing it excludes can be in the final lists); the
+                // insertion re-checks the exact (score, id) order.
+                uint32_t word[4];
+        #pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int xl = tp * kTP + 16 * b + col;
+                    const uint32_t w = E[kEpiVis + (16 * b + col) * 4 + wv] >> bit0;
+                    word[b] = xl < npts ? w : 0u;
+                    const float nx = __uint_as_float(E[kEpiNorm + 16 * b + col]);
+        #pragma unroll
+                    for (int i = 0; i < 4; ++i) sum[b][i] = nx - 2.0f * sum[b][i];   // scores
+                }
+                float lim[4], bm[4];
+                bool any = false;
+        #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    // the list's worst score (NaN, ignored, while the list is not full)
+                    // and the shared bound
+                    lim[i] = fminf(key_score(row_first(uint32_t(lk[i][0] >> 32))),
+                                   key_score(E[kEpiThr + kBoundWords * (q0 - qblk * kTQ + 4 * quarter + i)]));
+                    bm[i] = __builtin_inff();
+        #pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        bm[i] = (((word[b] >> i) & 1u) && sum[b][i] < bm[i]) ? sum[b][i] : bm[i];
+                    any = any || bm[i] <= lim[i];
+                }
+                // Only queries with a candidate at or below their limit in this tile
+                // go through the (rare) insertions, one score at a time.
+                if (__ballot(any)) {
+                    // the lane's first query, made opaque so that the addresses and
+                    // tests derived from it are formed here when needed rather than
+                    // held in registers across the whole loop
+                    int qme = q0 + 4 * quarter;
+                    asm volatile("" : "+v"(qme));
+        #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (!__ballot(bm[i] <= lim[i])) continue;
+        #pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int x = int(pb) + tp * kTP + 16 * b + col;
+                            const bool cand = ((word[b] >> i) & 1u) && sum[b][i] <= lim[i];
+                            quarter_offer(cand, entry_key(sum[b][i], x), lk[i]);
+                            lim[i] = fminf(lim[i], key_score(row_first(uint32_t(lk[i][0] >> 32))));
+                        }
+                        // publish a full list's worst score as a bound for the other
+                        // splits, and the score of its rank rpub - 1
+                        const int q = qme + i;
+                        uint32_t* br = E + kEpiThr + kBoundWords * (q - qblk * kTQ);   // its bound row
+                        uint32_t* gr = a.gthr + int64_t(kBoundWords) * q;
+                        const uint32_t wk = uint32_t(lk[i][0] >> 32);   // lane 0: the worst score's key
+                        if (col == 0 && q < a.nq && wk < br[0]) atomicMin(gr, wk);
+                        if (a.nrb) {
+                            // Every split holds rpub entries at or below its published
+                            // score, so the largest of the nrb scores has nrb rpub >= cap
+                            // entries at or below it: a bound on the cap-th best too.
+                            // The other splits' scores come from this tile's copy; an
+                            // older (larger) score only loosens the bound.
+                            // (the lane holding position rpos publishes it)
+                            const int rj = a.rpos >> 4;
+                            const uint32_t rk = uint32_t((rj == 0 ? lk[i][0] : (rj == 1 ? lk[i][1] : lk[i][2])) >> 32);
+                            if (col == (a.rpos & 15) && q < a.nq && rk < br[1 + split]) {
+                                atomicMin(gr + 1 + split, rk);
+                                // this tile's copy of the row takes the new score (only
+                                // this lane reads the rank words of this query), and
+                                // words past nrb hold 0
+                                br[1 + split] = rk;
+                                const uint32_t bk = max(max(br[1], br[2]), br[3]);
+                                if (bk < br[0]) atomicMin(gr, bk);
+                            }
+                        }
+                    }
+                }
+            }
+            if (t == ntile) break;
             const uint16_t* xb = xs + buf * (kStageBytes / 2);
             // B fragments run one k step ahead of the MFMAs that use them:
             // block b's next fragment is read as soon as both query groups'
@@ -393,106 +487,21 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
             buf = (buf + 1 == kNBuf) ? 0 : buf + 1;
             --left;
         }
-        // The epilogue loads went out in this tile's first stage, right after
-        // the loads of the stage kNBuf - 1 ahead.  With NC > kNBuf stages per
-        // tile the wait before the last stage's barrier (for that stage's
-        // loads, issued later) already covered them in every wave.  Shorter
-        // tiles wait for everything before the barrier of the swap below.
-        static_assert(kNBuf == 3, "the epilogue-load argument counts three buffers");
+        if (t == ntile) break;
         // Swap: this wave hands its partial sums of the other group to its
-        // partner and adds the partner's partial sums of its own group, so
+        // partner, which adds them after the next tile's first barrier, so
         // each score is (even k steps) + (odd k steps) in FP32 whichever wave
         // finishes it.  The partner reads this wave's slot before it reaches
-        // the next tile's first barrier, and this wave writes it again only
-        // after that barrier.
-        f4 sum[4];
+        // the following barrier, and this wave writes it again only after
+        // that barrier (with one stage per tile, after an extra barrier).
+        if constexpr (NC == 1) {
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+        }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             xout[b * kWave] = acc[1][b];
             sum[b] = acc[0][b];
-        }
-        asm volatile("" ::: "memory");
-        if (NC <= kNBuf) __builtin_amdgcn_s_waitcnt(kWaitVmLds(0));
-        else __builtin_amdgcn_s_waitcnt(kWaitVmLds(63));
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int b = 0; b < 4; ++b) sum[b] += xout[xdelta + b * kWave];
-        // epilogue: C[row 4 quarter + i][col] of block b = q(row) . x(16 b + col).
-        // A point enters a query's list only if it is a candidate of the
-        // query and its score is at most both the list's worst and the
-        // shared bound (an upper bound on the query's cap-th best over
-        // all splits, so nothing it excludes can be in the final lists); the
-        // insertion re-checks the exact (score, id) order.
-        uint32_t word[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int xl = t * kTP + 16 * b + col;
-            const uint32_t w = epi[kEpiVis + (16 * b + col) * 4 + wv] >> bit0;
-            word[b] = xl < npts ? w : 0u;
-            const float nx = __uint_as_float(epi[kEpiNorm + 16 * b + col]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) sum[b][i] = nx - 2.0f * sum[b][i];   // scores
-        }
-        float lim[4], bm[4];
-        bool any = false;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            // the list's worst score (NaN, ignored, while the list is not full)
-            // and the shared bound
-            lim[i] = fminf(key_score(row_first(uint32_t(lk[i][0] >> 32))),
-                           key_score(epi[kEpiThr + kBoundWords * (q0 - qblk * kTQ + 4 * quarter + i)]));
-            bm[i] = __builtin_inff();
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                bm[i] = (((word[b] >> i) & 1u) && sum[b][i] < bm[i]) ? sum[b][i] : bm[i];
-            any = any || bm[i] <= lim[i];
-        }
-        // Only queries with a candidate at or below their limit in this tile
-        // go through the (rare) insertions, one score at a time.
-        if (__ballot(any)) {
-            // the lane's first query, made opaque so that the addresses and
-            // tests derived from it are formed here when needed rather than
-            // held in registers across the whole loop
-            int qme = q0 + 4 * quarter;
-            asm volatile("" : "+v"(qme));
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (!__ballot(bm[i] <= lim[i])) continue;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int x = int(pb) + t * kTP + 16 * b + col;
-                    const bool cand = ((word[b] >> i) & 1u) && sum[b][i] <= lim[i];
-                    quarter_offer(cand, entry_key(sum[b][i], x), lk[i]);
-                    lim[i] = fminf(lim[i], key_score(row_first(uint32_t(lk[i][0] >> 32))));
-                }
-                // publish a full list's worst score as a bound for the other
-                // splits, and the score of its rank rpub - 1
-                const int q = qme + i;
-                uint32_t* br = epi + kEpiThr + kBoundWords * (q - qblk * kTQ);   // its bound row
-                uint32_t* gr = a.gthr + int64_t(kBoundWords) * q;
-                const uint32_t wk = uint32_t(lk[i][0] >> 32);   // lane 0: the worst score's key
-                if (col == 0 && q < a.nq && wk < br[0]) atomicMin(gr, wk);
-                if (a.nrb) {
-                    // Every split holds rpub entries at or below its published
-                    // score, so the largest of the nrb scores has nrb rpub >= cap
-                    // entries at or below it: a bound on the cap-th best too.
-                    // The other splits' scores come from this tile's copy; an
-                    // older (larger) score only loosens the bound.
-                    // (the lane holding position rpos publishes it)
-                    const int rj = a.rpos >> 4;
-                    const uint32_t rk = uint32_t((rj == 0 ? lk[i][0] : (rj == 1 ? lk[i][1] : lk[i][2])) >> 32);
-                    if (col == (a.rpos & 15) && q < a.nq && rk < br[1 + split]) {
-                        atomicMin(gr + 1 + split, rk);
-                        // this tile's copy of the row takes the new score (only
-                        // this lane reads the rank words of this query), and
-                        // words past nrb hold 0
-                        br[1 + split] = rk;
-                        const uint32_t bk = max(max(br[1], br[2]), br[3]);
-                        if (bk < br[0]) atomicMin(gr, bk);
-                    }
-                }
-            }
         }
     }
     __builtin_amdgcn_s_waitcnt(kWaitVm(0));

@@ -12,8 +12,9 @@ epilogue area, and the two waves of each pair swap partial sums through a
 formulas for every configuration launch_tile_path admits (the row stride,
 the template k depth, ragged point counts and splits, query chunkings) and
 asserts that every global access lies inside its buffer and every LDS target
-inside the kernel's static allocation (3 x 32 KiB stages + 832-word
-epilogue area + 32 KiB exchange = 131.25 KiB).  No GPU."""
+inside the kernel's static allocation (3 x 32 KiB stages + two 832-word
+epilogue areas, used by alternate tiles, + 32 KiB exchange = 134.5 KiB).
+No GPU."""
 import numpy as np
 import pytest
 
@@ -26,7 +27,8 @@ KBOUND_WORDS = 4                            # per query: shared bound + 3 rank s
 KEPI_VIS, KEPI_NORM, KEPI_THR = 0, 4 * KTP, 5 * KTP
 KEPI_WORDS = 5 * KTP + KBOUND_WORDS * KTQ
 KXCH_BYTES = KTWAVES * 4 * KWAVE * 16      # f4 partial sums [wave][block][lane]
-LDS_BYTES = KNBUF * KSTAGE + 4 * KEPI_WORDS + KXCH_BYTES
+KEPI_BUFS = 2                               # tile t's operands go to area t & 1
+LDS_BYTES = KNBUF * KSTAGE + KEPI_BUFS * 4 * KEPI_WORDS + KXCH_BYTES
 KSTEPS_TEMPLATES = (4, 8, 12, 16, 20, 24, 28, 30, 32)
 
 
@@ -112,8 +114,10 @@ def check_epilogue_loads(n, nq, cw, split_pts):
             g = KBOUND_WORDS * np.where(qq < nq, qq, 0)      # words from gthr's base
             assert g.min() >= 0 and (g + KBOUND_WORDS).max() <= KBOUND_WORDS * nq
             assert (g % 4 == 0).all()                        # 16-byte aligned
-            lds = 4 * (KEPI_THR + KBOUND_WORDS * (w - 2) * KWAVE) + 16 * lane
-            assert lds.min() >= 4 * KEPI_THR and (lds + 16).max() <= 4 * KEPI_WORDS
+            for u in range(KEPI_BUFS):
+                lds = 4 * KEPI_WORDS * u + 4 * (KEPI_THR + KBOUND_WORDS * (w - 2) * KWAVE) + 16 * lane
+                assert lds.min() >= 4 * KEPI_WORDS * u + 4 * KEPI_THR
+                assert (lds + 16).max() <= 4 * KEPI_WORDS * (u + 1)
         for split in sorted({0, 1, nsplit - 2, nsplit - 1} & set(range(nsplit))):
             pb = split * split_pts
             npts = split_pts if pb + split_pts < n else n - pb
@@ -123,14 +127,16 @@ def check_epilogue_loads(n, nq, cw, split_pts):
                 xc = np.where(xl < npts, xl, 0)
                 vis = (qc * n + pb + xc) * cw + wo          # words from visT's base
                 assert vis.min() >= 0 and (vis + 4).max() <= vis_words
-                assert (4 * KEPI_VIS + 16 * lane + 16).max() <= 4 * KEPI_NORM
+                e0 = 4 * KEPI_WORDS * (t & 1)              # this tile's area
+                assert (e0 + 4 * KEPI_VIS + 16 * lane + 16).max() <= e0 + 4 * KEPI_NORM
                 nrm = pb + xc
                 assert nrm.max() < n
-                assert (4 * KEPI_NORM + 4 * lane + 4).max() <= 4 * KEPI_THR
+                assert (e0 + 4 * KEPI_NORM + 4 * lane + 4).max() <= e0 + 4 * KEPI_THR
+                assert e0 + 4 * KEPI_WORDS <= KEPI_BUFS * 4 * KEPI_WORDS
 
 
-def test_static_lds_allocation_is_131_25_kib():
-    assert LDS_BYTES == 3 * 32768 + 3328 + 32768
+def test_static_lds_allocation_is_134_5_kib():
+    assert LDS_BYTES == 3 * 32768 + 2 * 3328 + 32768
     assert LDS_BYTES <= 160 * 1024
 
 
