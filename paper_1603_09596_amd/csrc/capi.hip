@@ -243,9 +243,10 @@ int device_cus() {
 TilePlan tile_plan(const gf_forest* F, int nb, int form = gf::kFormBF16, int64_t checks_max = 0) {
     TilePlan p;
     if (form == gf::kFormFP8) {
-        // one workgroup per CU at a time, each a 128-query block and a split
-        // of the tiles: the split count with the least time in whole rounds
-        const int64_t qblocks = (nb + 127) / 128;
+        // one workgroup per CU at a time, each a block of kTile8Queries
+        // queries and a split of the tiles: the split count with the least
+        // time in whole rounds
+        const int64_t qblocks = (nb + gf::kTile8Queries - 1) / gf::kTile8Queries;
         const int64_t tiles = gf::tile8_ntiles(F->host.n);
         const int64_t cus = device_cus();
         int64_t ns = 1;

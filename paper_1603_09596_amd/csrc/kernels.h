@@ -199,6 +199,7 @@ struct MergeArgs {
 // FP8 tile path (wide rows): dense FP8 MFMA scores of 128-query blocks
 // against 128-point tiles, kept only for each query's candidates, written
 // compactly per query, then the kk best per query.
+constexpr int kTile8Queries = 256;   // queries per FP8 tile workgroup
 struct Tile8Args {
     int nq;
     int64_t n, ld8;             // ld8: a multiple of 16

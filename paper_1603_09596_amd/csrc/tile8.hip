@@ -36,11 +36,10 @@ namespace gf {
 namespace {
 
 constexpr int kW = 64;                 // wavefront
-constexpr int kQB = 128;               // queries per workgroup
+constexpr int kQB = kTile8Queries;     // queries per workgroup
 constexpr int kTP8 = 128;              // points per tile
 constexpr int kKS8 = 128;              // k bytes per stage (one MFMA depth)
-constexpr int kT8Threads = 256;        // 4 waves, each a 64 x 64 block
-constexpr int kStage8 = kQB * kKS8;    // bytes of one operand stage (16 KB)
+constexpr int kT8Threads = 512;        // 8 waves, each a 64 x 64 block
 constexpr int kXcd8 = 8;               // XCDs of an MI355X
 
 typedef int v8i __attribute__((ext_vector_type(8)));
@@ -110,18 +109,54 @@ __global__ __launch_bounds__(256) void k_cand_prefix(const uint64_t* __restrict_
     }
 }
 
-// The score kernel.  Workgroups are dispatched to the XCDs round-robin
-// (workgroup i to XCD i % 8); each XCD takes a consecutive run of the
-// split-major (split, query block) list, so the query blocks of one split
+// Direct global -> LDS loads (global_load_lds_dwordx4): every lane reads 16
+// bytes at base + voff and the wave writes them contiguously at LDS address
+// m0 + 16 lane.  Issued from inline assembly so that the compiler does not
+// wait for them before unrelated LDS reads; the kernel waits itself
+// (s_waitcnt vmcnt) before the barrier that publishes a stage.
+__device__ __forceinline__ void dma8_16s(const void* base, uint32_t voff, uint32_t lds) {
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+                 :: "v"(voff), "s"(base), "{m0}"(__builtin_amdgcn_readfirstlane(lds)) : "memory");
+}
+__device__ __forceinline__ const void* uniform8(const void* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    return reinterpret_cast<const void*>((uint64_t(hi) << 32) | lo);
+}
+// s_waitcnt immediates (gfx9 encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] at 15:14)
+constexpr int kWait8(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
+typedef __attribute__((address_space(3))) uint32_t lds8_u32;
+__device__ __forceinline__ uint32_t lds8_offset(const void* p) {
+    return uint32_t(uintptr_t((const lds8_u32*)p));
+}
+
+constexpr int kNBuf8 = 3;                          // stage buffers (two stages in flight)
+constexpr int kStageA8 = kQB * kKS8;               // 32 KB of query rows per stage
+constexpr int kStageB8 = kTP8 * kKS8;              // 16 KB of point rows per stage
+constexpr int kDmaA8 = kStageA8 / 1024 / (kT8Threads / kW);   // 1 KB loads per wave and stage: 4
+constexpr int kDmaB8 = kStageB8 / 1024 / (kT8Threads / kW);   // 2
+static_assert(kDmaA8 * 1024 * (kT8Threads / kW) == kStageA8 && kDmaB8 * 1024 * (kT8Threads / kW) == kStageB8,
+              "stage shape");
+
+// The score kernel: grid (query blocks of 256, point splits), 8 waves; wave
+// w computes queries 64 (w >> 1) .. + 64 against points 64 (w & 1) .. + 64
+// of each 128-point tile with v_mfma_scale_f32_16x16x128_f8f6f4 (neutral
+// scales, FP32 accumulation), 4 x 4 fragments.  Both operands stream through
+// LDS in 128-byte k stages by direct loads, three buffers, two stages in
+// flight across tile boundaries.  Workgroups are dispatched to the XCDs
+// round-robin (workgroup i to XCD i % 8); each XCD takes a consecutive run of
+// the split-major (split, query block) list, so the query blocks of one split
 // run on one XCD and share its L2 for the split's rows.
 //
 // LDS per operand stage: row r (a query or a point) holds its 128 k bytes as
-// eight 16-byte units, unit u at position u ^ (r & 7): the 16-byte stores
-// of a row's eight threads and the MFMA operand reads of eight consecutive
-// rows both spread over all banks.
+// eight 16-byte units, unit u at position u ^ (r & 7): each direct load
+// writes 8 whole rows, and the MFMA operand reads of 16 consecutive rows
+// spread over all banks.  k bytes past the row (ld8 is a multiple of 16, not
+// of 128) are loaded from a valid address and zeroed in the fragments.
 __global__ __launch_bounds__(kT8Threads) void k_tile_fp8(Tile8Args a) {
-    __shared__ __attribute__((aligned(1024))) uint8_t sA[2][kStage8];
-    __shared__ __attribute__((aligned(1024))) uint8_t sB[2][kStage8];
+    __shared__ __attribute__((aligned(1024))) uint8_t sA[kNBuf8][kStageA8];
+    __shared__ __attribute__((aligned(1024))) uint8_t sB[kNBuf8][kStageB8];
     __shared__ uint64_t sMask[kQB][2];
     __shared__ uint32_t sOff[kQB];
     __shared__ float sQs[kQB];
@@ -143,65 +178,95 @@ __global__ __launch_bounds__(kT8Threads) void k_tile_fp8(Tile8Args a) {
     const int nk = int((a.ld8 + kKS8 - 1) / kKS8);
     if (tid < kQB) sQs[tid] = (q0 + tid < a.nq) ? a.qscale[q0 + tid] : 0.0f;
 
-    // staging: thread tid moves unit u = tid & 7 of rows r0 + 32 j, j < 4,
-    // of both operands
-    const int su = tid & 7, sr0 = tid >> 3;
-    // MFMA operands: wave = (query half, point half); lane l reads row
-    // (l & 15) of each 16-row fragment, k bytes 32 (l >> 4) .. + 32
+    // MFMA operands: lane l reads row (l & 15) of each 16-row fragment, k
+    // bytes 32 (l >> 4) .. + 32 (units 2 fg and 2 fg + 1)
     const int qh = wave >> 1, ph = wave & 1;
     const int fr = lane & 15, fg = lane >> 4;
+    // Direct loads: instruction j of wave w writes rows 8 (w + 8 j) .. + 8 of
+    // a stage; lane l the unit at position l % 8 of row 8 (w + 8 j) + l / 8,
+    // which holds k unit (l % 8) ^ (row & 7).  Row r's low 3 bits are
+    // (l / 8) & 7 for every instruction, so a lane loads the same unit of
+    // each of its rows.  Rows past the queries or points are clamped to row
+    // 0 of the block or tile; their scores are never kept.
+    const int drow = lane >> 3;                       // row within the 8 of an instruction
+    const uint32_t du = uint32_t((lane & 7) ^ drow);  // k unit this lane loads
+    const uint32_t sA0 = lds8_offset(sA), sB0 = lds8_offset(sB);
+    const void* qbase = uniform8(a.Q8 + int64_t(q0) * a.ld8);
+    uint32_t qoff[kDmaA8];
+#pragma unroll
+    for (int j = 0; j < kDmaA8; ++j) {
+        const int r = 8 * (wave + 8 * j) + drow;
+        qoff[j] = uint32_t(q0 + r < a.nq ? r : 0) * uint32_t(a.ld8);
+    }
+    // issue cursor: the next stage to load is stage ic of tile it, into ibuf
+    int it = t_begin, ic = 0, ibuf = 0;
+    const int nstages = (t_end - t_begin) * nk;
+    auto issue_next = [&]() {
+        const uint32_t k = uint32_t(ic * kKS8) + 16u * du;
+        const uint32_t koff = k < uint32_t(a.ld8) ? k : 0u;
+#pragma unroll
+        for (int j = 0; j < kDmaA8; ++j)
+            dma8_16s(qbase, qoff[j] + koff, sA0 + uint32_t(ibuf * kStageA8 + (wave + 8 * j) * 1024));
+        const int64_t x0 = int64_t(it) * kTP8;
+        const void* xbase = uniform8(a.X8 + x0 * a.ld8);
+#pragma unroll
+        for (int j = 0; j < kDmaB8; ++j) {
+            const int r = 8 * (wave + 8 * j) + drow;
+            const uint32_t xo = uint32_t(x0 + r < a.n ? r : 0) * uint32_t(a.ld8);
+            dma8_16s(xbase, xo + koff, sB0 + uint32_t(ibuf * kStageB8 + (wave + 8 * j) * 1024));
+        }
+        ibuf = (ibuf + 1 == kNBuf8) ? 0 : ibuf + 1;
+        if (++ic == nk) {
+            ic = 0;
+            ++it;
+        }
+    };
+    int issued = 0;
+    for (; issued < kNBuf8 - 1 && issued < nstages; ++issued) issue_next();
 
+    int buf = 0, consumed = 0;
     for (int T = t_begin; T < t_end; ++T) {
         const int64_t x0 = int64_t(T) * kTP8;
-        uint4 ra[4], rb[4];
-        auto load_stage = [&](int kc) {
-            const int64_t kb = int64_t(kc) * kKS8 + 16 * su;
-            const bool kin = kb < a.ld8;   // ld8 is a multiple of 16: whole units in or out
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = sr0 + 32 * j;
-                const int q = q0 + r;
-                const int64_t x = x0 + r;
-                ra[j] = (kin && q < a.nq) ? *reinterpret_cast<const uint4*>(a.Q8 + int64_t(q) * a.ld8 + kb)
-                                          : make_uint4(0, 0, 0, 0);
-                rb[j] = (kin && x < a.n) ? *reinterpret_cast<const uint4*>(a.X8 + x * a.ld8 + kb)
-                                         : make_uint4(0, 0, 0, 0);
-            }
-        };
-        auto store_stage = [&](int buf) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = sr0 + 32 * j;
-                const int off = r * kKS8 + ((su ^ (r & 7)) << 4);
-                *reinterpret_cast<uint4*>(&sA[buf][off]) = ra[j];
-                *reinterpret_cast<uint4*>(&sB[buf][off]) = rb[j];
-            }
-        };
         f4v acc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
-        load_stage(0);
-        __syncthreads();   // the previous tile's epilogue is done with its LDS operands
-        store_stage(0);
-        __syncthreads();
         for (int kc = 0; kc < nk; ++kc) {
-            const int buf = kc & 1;
-            if (kc + 1 < nk) load_stage(kc + 1);   // in flight during the MFMAs
+            // Loads complete in issue order: after this stage's loads at
+            // most one later stage's were issued, so waiting down to one
+            // stage's worth completes this stage for this wave, and the
+            // barrier then covers every wave and frees the buffer of the
+            // stage before for reuse.
+            asm volatile("" ::: "memory");
+            if (issued - consumed >= 2) __builtin_amdgcn_s_waitcnt(kWait8(kDmaA8 + kDmaB8));
+            else __builtin_amdgcn_s_waitcnt(kWait8(0));
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (issued < nstages) {
+                issue_next();
+                ++issued;
+            }
+            const uint8_t* A = sA[buf];
+            const uint8_t* B = sB[buf];
+            // fragments: 32 k bytes of the lane's row; bytes past the row are zero
+            const bool lo_in = kc * kKS8 + 32 * fg < a.ld8;
+            const bool hi_in = kc * kKS8 + 32 * fg + 16 < a.ld8;
             v8i fa[4], fb[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = 64 * qh + 16 * i + fr;
-                const uint4 lo = *reinterpret_cast<const uint4*>(&sA[buf][r * kKS8 + (((2 * fg) ^ (r & 7)) << 4)]);
-                const uint4 hi = *reinterpret_cast<const uint4*>(&sA[buf][r * kKS8 + (((2 * fg + 1) ^ (r & 7)) << 4)]);
+                uint4 lo = *reinterpret_cast<const uint4*>(&A[r * kKS8 + (((2 * fg) ^ (r & 7)) << 4)]);
+                uint4 hi = *reinterpret_cast<const uint4*>(&A[r * kKS8 + (((2 * fg + 1) ^ (r & 7)) << 4)]);
+                if (!lo_in) lo = make_uint4(0, 0, 0, 0);
+                if (!hi_in) hi = make_uint4(0, 0, 0, 0);
                 fa[i] = v8i{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int r = 64 * ph + 16 * j + fr;
-                const uint4 lo = *reinterpret_cast<const uint4*>(&sB[buf][r * kKS8 + (((2 * fg) ^ (r & 7)) << 4)]);
-                const uint4 hi = *reinterpret_cast<const uint4*>(&sB[buf][r * kKS8 + (((2 * fg + 1) ^ (r & 7)) << 4)]);
+                const uint4 lo = *reinterpret_cast<const uint4*>(&B[r * kKS8 + (((2 * fg) ^ (r & 7)) << 4)]);
+                const uint4 hi = *reinterpret_cast<const uint4*>(&B[r * kKS8 + (((2 * fg + 1) ^ (r & 7)) << 4)]);
                 fb[j] = v8i{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
             }
 #pragma unroll
@@ -210,11 +275,12 @@ __global__ __launch_bounds__(kT8Threads) void k_tile_fp8(Tile8Args a) {
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[i], fb[j], acc[i][j],
                                                                                 0, 0, 0, 127, 0, 127);
-            if (kc + 1 < nk) store_stage(buf ^ 1);   // that buffer was released by the last barrier
-            __syncthreads();
+            buf = (buf + 1 == kNBuf8) ? 0 : buf + 1;
+            ++consumed;
         }
         // epilogue operands of this tile: the block's masks and offsets, the
-        // points' norms and scales
+        // points' norms and scales.  The previous tile's epilogue finished
+        // reading them before this tile's first stage barrier.
         if (tid < kQB) {
             const int q = q0 + tid;
             if (q < a.nq) {
@@ -227,14 +293,14 @@ __global__ __launch_bounds__(kT8Threads) void k_tile_fp8(Tile8Args a) {
                 sMask[tid][1] = 0;
                 sOff[tid] = 0;
             }
-        } else {
+        } else if (tid < kQB + kTP8) {
             const int xl = tid - kQB;
             const int64_t x = x0 + xl;
             sXn[xl] = x < a.n ? a.norm8[x] : 0.0f;
             sXs[xl] = x < a.n ? a.scale8[x] : 0.0f;
         }
         __syncthreads();
-        // C[row 4 fg + i][col fr] of fragment (i, j): query 64 qh + 16 ii + 4 fg + e,
+        // C[row 4 fg + e][col fr] of fragment (ii, j): query 64 qh + 16 ii + 4 fg + e,
         // point 64 ph + 16 j + fr of the tile
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii)
@@ -256,7 +322,10 @@ __global__ __launch_bounds__(kT8Threads) void k_tile_fp8(Tile8Args a) {
                     }
                 }
             }
+        // the next tile's epilogue overwrites these operands only after the
+        // barriers of its k stages (at least one)
     }
+    __builtin_amdgcn_s_waitcnt(kWait8(0));
 }
 
 // The kk best (score, id) of each query among its candidates: a radix select
