@@ -273,6 +273,9 @@ TilePlan tile_plan(const gf_forest* F, int nb, int form = gf::kFormBF16, int64_t
         const double cost = rounds / double(s) + 0.002 * double(s);
         if (cost < best) { best = cost; ns = s; }
     }
+    // GF_TILE_SPLITS=s forces the split count (tests: the result does not depend on it)
+    const char* senv = std::getenv("GF_TILE_SPLITS");
+    if (senv && std::atoi(senv) > 0) ns = std::min<int64_t>(tiles, std::atoi(senv));
     if ((tiles + ns - 1) / ns > max_tiles) ns = (tiles + max_tiles - 1) / max_tiles;
     p.split_pts = ((tiles + ns - 1) / ns) * 64;
     p.nsplit = int((F->host.n + p.split_pts - 1) / p.split_pts);

@@ -490,3 +490,30 @@ def test_sliced_row_scan_equals_one_workgroup_per_query(name, form, k, c, monkey
         out.append((ids, dd))
     for ids, dd in out[1:]:
         assert np.array_equal(ids, out[0][0]) and np.array_equal(dd, out[0][1])
+
+
+@pytest.mark.parametrize("k", [1, 5, 10, 12])
+def test_tile_path_bf16_independent_of_split_count(k, monkeypatch):
+    """The BF16 tile path's lists are exact: the kk best scores of each
+    query over its candidates do not depend on how the points are split
+    among workgroups (one split: no shared bound; two or three: the rank
+    bound as well; four: the worst-entry bound alone), so the neighbours and
+    distances are bit-identical for every split count, at every list
+    capacity kk = 4 k (k = 12 fills all 48 positions)."""
+    X, Q, Fg, Fo, _ = forests("desc-60k-960", forms=("bf16",))
+    monkeypatch.setenv("GF_SCAN_PATH", "tile")
+    out = []
+    for ns in (1, 2, 3, 4):
+        monkeypatch.setenv("GF_TILE_SPLITS", str(ns))
+        ids = np.zeros((len(Q), k), np.int32)
+        dd = np.zeros((len(Q), k), np.float32)
+        geraf.query(Fg, Q, k, 4096, ids, dd, form="bf16")
+        assert geraf.last_query_timing()["path"] == "tile"
+        out.append((ids, dd))
+    for ns, (ids, dd) in zip((2, 3, 4), out[1:]):
+        assert np.array_equal(ids, out[0][0]), f"{ns} splits"
+        assert np.array_equal(dd.view(np.uint32), out[0][1].view(np.uint32)), f"{ns} splits"
+    ref = oracle.search(Fo, X, Q, k, 4096, trace=False, candidates=True)
+    for i in range(len(Q)):
+        got = out[0][0][i][out[0][0][i] >= 0]
+        assert np.isin(got, ref["cand"][i]).all()
