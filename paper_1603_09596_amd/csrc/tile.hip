@@ -51,6 +51,11 @@ constexpr int kTThreads = kTWaves * kWave;
 constexpr int kTQ = kTWaves * 16;     // queries per workgroup (32 per wave pair)
 constexpr int kTP = 64;               // points per tile
 constexpr int kSlots = 3;             // list entries per lane and query (x 16 lanes)
+// Tiles between publications of the shared bounds: the atomics are
+// vector-memory operations, so the next stage's wait for its loads also
+// waits for them, and publishing after every tile's inserts cost more than
+// the pruning it bought.
+constexpr int kPublishTiles = 16;
 constexpr int kExpandThreads = 1024;
 constexpr int kXcds = 8;              // XCDs of an MI355X (32 CUs each)
 
@@ -380,25 +385,25 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
                 // all splits, so nothing it excludes can be in the final lists); the
                 // insertion re-checks the exact (score, id) order.
                 uint32_t word[4];
-        #pragma unroll
+#pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const int xl = tp * kTP + 16 * b + col;
                     const uint32_t w = E[kEpiVis + (16 * b + col) * 4 + wv] >> bit0;
                     word[b] = xl < npts ? w : 0u;
                     const float nx = __uint_as_float(E[kEpiNorm + 16 * b + col]);
-        #pragma unroll
+#pragma unroll
                     for (int i = 0; i < 4; ++i) sum[b][i] = nx - 2.0f * sum[b][i];   // scores
                 }
                 float lim[4], bm[4];
                 bool any = false;
-        #pragma unroll
+#pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     // the list's worst score (NaN, ignored, while the list is not full)
                     // and the shared bound
                     lim[i] = fminf(key_score(row_first(uint32_t(lk[i][0] >> 32))),
                                    key_score(E[kEpiThr + kBoundWords * (q0 - qblk * kTQ + 4 * quarter + i)]));
                     bm[i] = __builtin_inff();
-        #pragma unroll
+#pragma unroll
                     for (int b = 0; b < 4; ++b)
                         bm[i] = (((word[b] >> i) & 1u) && sum[b][i] < bm[i]) ? sum[b][i] : bm[i];
                     any = any || bm[i] <= lim[i];
@@ -411,24 +416,34 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
                     // held in registers across the whole loop
                     int qme = q0 + 4 * quarter;
                     asm volatile("" : "+v"(qme));
-        #pragma unroll
+#pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         if (!__ballot(bm[i] <= lim[i])) continue;
-        #pragma unroll
+#pragma unroll
                         for (int b = 0; b < 4; ++b) {
                             const int x = int(pb) + tp * kTP + 16 * b + col;
                             const bool cand = ((word[b] >> i) & 1u) && sum[b][i] <= lim[i];
                             quarter_offer(cand, entry_key(sum[b][i], x), lk[i]);
                             lim[i] = fminf(lim[i], key_score(row_first(uint32_t(lk[i][0] >> 32))));
                         }
-                        // publish a full list's worst score as a bound for the other
-                        // splits, and the score of its rank rpub - 1
+                    }
+                }
+                // Every kPublishTiles tiles (and at the last), publish each
+                // query's bounds for the other splits: a full list's worst
+                // score, and the score of its rank rpub - 1.  Global atomics
+                // are counted with the stage loads by the next stage's wait,
+                // so they go out in batches rather than after every insert.
+                if ((tp % kPublishTiles) == kPublishTiles - 1 || tp == ntile - 1) {
+                    int qme = q0 + 4 * quarter;
+                    asm volatile("" : "+v"(qme));
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
                         const int q = qme + i;
                         uint32_t* br = E + kEpiThr + kBoundWords * (q - qblk * kTQ);   // its bound row
                         uint32_t* gr = a.gthr + int64_t(kBoundWords) * q;
                         const uint32_t wk = uint32_t(lk[i][0] >> 32);   // lane 0: the worst score's key
                         if (col == 0 && q < a.nq && wk < br[0]) atomicMin(gr, wk);
-                        if (a.nrb) {
+                        if (split < a.nrb) {
                             // Every split holds rpub entries at or below its published
                             // score, so the largest of the nrb scores has nrb rpub >= cap
                             // entries at or below it: a bound on the cap-th best too.
