@@ -257,7 +257,9 @@ TilePlan tile_plan(const gf_forest* F, int nb, int form = gf::kFormBF16, int64_t
             if (cost < best) { best = cost; ns = s; }
         }
         p.ntiles8 = int(tiles);
-        p.split_tiles8 = int((tiles + ns - 1) / ns);
+        // the score kernel takes the 128-point tiles in pairs: splits of an
+        // even number of tiles (the last may be odd)
+        p.split_tiles8 = int(((tiles + ns - 1) / ns + 1) / 2 * 2);
         p.nsplit8 = int((tiles + p.split_tiles8 - 1) / p.split_tiles8);
         p.cap8 = std::max<int64_t>(1, std::min<int64_t>(F->host.n, std::max<int64_t>(1, checks_max) *
                                                                          int64_t(std::max(1, F->maxleaf))));

@@ -38,7 +38,6 @@ namespace {
 constexpr int kW = 64;                 // wavefront
 constexpr int kQB = kTile8Queries;     // queries per workgroup
 constexpr int kTP8 = 128;              // points per tile
-constexpr int kKS8 = 128;              // k bytes per stage (one MFMA depth)
 constexpr int kT8Threads = 512;        // 8 waves, each a 64 x 64 block
 constexpr int kXcd8 = 8;               // XCDs of an MI355X
 
@@ -131,36 +130,45 @@ __device__ __forceinline__ uint32_t lds8_offset(const void* p) {
     return uint32_t(uintptr_t((const lds8_u32*)p));
 }
 
-constexpr int kNBuf8 = 3;                          // stage buffers (two stages in flight)
-constexpr int kStageA8 = kQB * kKS8;               // 32 KB of query rows per stage
-constexpr int kStageB8 = kTP8 * kKS8;              // 16 KB of point rows per stage
-constexpr int kDmaA8 = kStageA8 / 1024 / (kT8Threads / kW);   // 1 KB loads per wave and stage: 4
+constexpr int kNBuf8 = 4;                          // stage buffers (three stages in flight)
+constexpr int kKS = 64;                            // k bytes per stage (one 32x32x64 MFMA depth)
+constexpr int kTW8 = 2 * kTP8;                     // points per workgroup tile: two mask tiles
+constexpr int kStageA8 = kQB * kKS;                // 16 KB of query rows per stage
+constexpr int kStageB8 = kTW8 * kKS;               // 16 KB of point rows per stage
+constexpr int kDmaA8 = kStageA8 / 1024 / (kT8Threads / kW);   // 1 KB loads per wave and stage: 2
 constexpr int kDmaB8 = kStageB8 / 1024 / (kT8Threads / kW);   // 2
+constexpr int kDma8 = kDmaA8 + kDmaB8;
 static_assert(kDmaA8 * 1024 * (kT8Threads / kW) == kStageA8 && kDmaB8 * 1024 * (kT8Threads / kW) == kStageB8,
               "stage shape");
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Byte offset in a stage of 16-byte unit u (0..3) of row r: rows are paired
+// into 128-byte lines, row r in line r >> 1 at unit positions u + 4 (r & 1),
+// XOR (r >> 1) & 7.  A direct load's lane l % 8 takes position l % 8 of line
+// l / 8, and the operand reads of 8 consecutive rows (one unit each) fall on
+// 8 different 16-byte bank groups.
+__device__ __forceinline__ int unit_off8(int r, int u) {
+    return (r >> 1) * 128 + (((u + 4 * (r & 1)) ^ ((r >> 1) & 7)) << 4);
+}
 
 // The score kernel: grid (query blocks of 256, point splits), 8 waves; wave
-// w computes queries 64 (w >> 1) .. + 64 against points 64 (w & 1) .. + 64
-// of each 128-point tile with v_mfma_scale_f32_16x16x128_f8f6f4 (neutral
-// scales, FP32 accumulation), 4 x 4 fragments.  Both operands stream through
-// LDS in 128-byte k stages by direct loads, three buffers, two stages in
-// flight across tile boundaries.  Workgroups are dispatched to the XCDs
-// round-robin (workgroup i to XCD i % 8); each XCD takes a consecutive run of
-// the split-major (split, query block) list, so the query blocks of one split
-// run on one XCD and share its L2 for the split's rows.
-//
-// LDS per operand stage: row r (a query or a point) holds its 128 k bytes as
-// eight 16-byte units, unit u at position u ^ (r & 7): each direct load
-// writes 8 whole rows, and the MFMA operand reads of 16 consecutive rows
-// spread over all banks.  k bytes past the row (ld8 is a multiple of 16, not
-// of 128) are loaded from a valid address and zeroed in the fragments.
+// w computes queries 64 (w >> 1) .. + 64 against points 128 (w & 1) .. + 128
+// of each 256-point tile (two 128-point mask tiles) with
+// v_mfma_scale_f32_32x32x64_f8f6f4 (neutral scales, FP32 accumulation), 2 x 4
+// blocks of 32 x 32.  Both operands stream through LDS in 64-byte k stages by
+// direct loads, four buffers, three stages in flight across tile boundaries.
+// Workgroups are dispatched to the XCDs round-robin (workgroup i to XCD
+// i % 8); each XCD takes a consecutive run of the split-major (split, query
+// block) list, so the query blocks of one split run on one XCD and share its
+// L2 for the split's rows.  k bytes past the row (ld8 is a multiple of 16,
+// not of 64) are loaded from a valid address and zeroed in the fragments.
 __global__ __launch_bounds__(kT8Threads) void k_tile_fp8(Tile8Args a) {
     __shared__ __attribute__((aligned(1024))) uint8_t sA[kNBuf8][kStageA8];
     __shared__ __attribute__((aligned(1024))) uint8_t sB[kNBuf8][kStageB8];
-    __shared__ uint64_t sMask[kQB][2];
-    __shared__ uint32_t sOff[kQB];
+    __shared__ uint64_t sMask[kQB][2][2];
+    __shared__ uint32_t sOff[kQB][2];
     __shared__ float sQs[kQB];
-    __shared__ float sXn[kTP8], sXs[kTP8];
+    __shared__ float sXn[kTW8], sXs[kTW8];
     const int tid = threadIdx.x, lane = tid & (kW - 1), wave = tid / kW;
     int qblk, split;
     {
@@ -173,73 +181,76 @@ __global__ __launch_bounds__(kT8Threads) void k_tile_fp8(Tile8Args a) {
         qblk = L - split * nqb;
     }
     const int q0 = qblk * kQB;
-    const int t_begin = split * a.split_tiles;
+    const int t_begin = split * a.split_tiles;            // even: tiles are taken in pairs
     const int t_end = min(a.ntiles, t_begin + a.split_tiles);
-    const int nk = int((a.ld8 + kKS8 - 1) / kKS8);
+    const int npair = (t_end - t_begin + 1) / 2;
+    const int nk = int((a.ld8 + kKS - 1) / kKS);
     if (tid < kQB) sQs[tid] = (q0 + tid < a.nq) ? a.qscale[q0 + tid] : 0.0f;
 
-    // MFMA operands: lane l reads row (l & 15) of each 16-row fragment, k
-    // bytes 32 (l >> 4) .. + 32 (units 2 fg and 2 fg + 1)
-    const int qh = wave >> 1, ph = wave & 1;
-    const int fr = lane & 15, fg = lane >> 4;
-    // Direct loads: instruction j of wave w writes rows 8 (w + 8 j) .. + 8 of
-    // a stage; lane l the unit at position l % 8 of row 8 (w + 8 j) + l / 8,
-    // which holds k unit (l % 8) ^ (row & 7).  Row r's low 3 bits are
-    // (l / 8) & 7 for every instruction, so a lane loads the same unit of
-    // each of its rows.  Rows past the queries or points are clamped to row
-    // 0 of the block or tile; their scores are never kept.
-    const int drow = lane >> 3;                       // row within the 8 of an instruction
-    const uint32_t du = uint32_t((lane & 7) ^ drow);  // k unit this lane loads
+    // MFMA operands: lane l reads row (l & 31) of each 32-row fragment, k
+    // bytes 32 (l >> 5) .. + 32 of the stage (units 2 kg and 2 kg + 1)
+    const int qq = wave >> 1, ph = wave & 1;
+    const int fr = lane & 31, kg = lane >> 5;
+    // Direct loads: instruction j of wave w writes lines 8 (w + 8 j) .. + 8
+    // (rows 16 (w + 8 j) .. + 16) of a stage; lane l position l % 8 of line
+    // 8 (w + 8 j) + l / 8, which holds row 2 line + s / 4, unit s % 4, with
+    // s = (l % 8) ^ (line & 7).  Rows past the queries or points are clamped
+    // to the block's or tile's first row; their scores are never kept.
+    const int dline = lane >> 3;                          // line within the 8 of an instruction
+    const int ds = (lane & 7) ^ dline;                    // (line & 7) == dline for every instruction
+    const int drow = 2 * dline + (ds >> 2), du = ds & 3;  // row within the 16, unit
     const uint32_t sA0 = lds8_offset(sA), sB0 = lds8_offset(sB);
     const void* qbase = uniform8(a.Q8 + int64_t(q0) * a.ld8);
     uint32_t qoff[kDmaA8];
 #pragma unroll
     for (int j = 0; j < kDmaA8; ++j) {
-        const int r = 8 * (wave + 8 * j) + drow;
+        const int r = 16 * (wave + 8 * j) + drow;
         qoff[j] = uint32_t(q0 + r < a.nq ? r : 0) * uint32_t(a.ld8);
     }
-    // issue cursor: the next stage to load is stage ic of tile it, into ibuf
-    int it = t_begin, ic = 0, ibuf = 0;
-    const int nstages = (t_end - t_begin) * nk;
+    // issue cursor: the next stage to load is stage ic of tile pair ip, into ibuf
+    int ip = 0, ic = 0, ibuf = 0;
+    const int nstages = npair * nk;
     auto issue_next = [&]() {
-        const uint32_t k = uint32_t(ic * kKS8) + 16u * du;
+        const uint32_t k = uint32_t(ic * kKS) + 16u * uint32_t(du);
         const uint32_t koff = k < uint32_t(a.ld8) ? k : 0u;
 #pragma unroll
         for (int j = 0; j < kDmaA8; ++j)
             dma8_16s(qbase, qoff[j] + koff, sA0 + uint32_t(ibuf * kStageA8 + (wave + 8 * j) * 1024));
-        const int64_t x0 = int64_t(it) * kTP8;
+        const int64_t x0 = int64_t(t_begin + 2 * ip) * kTP8;
         const void* xbase = uniform8(a.X8 + x0 * a.ld8);
 #pragma unroll
         for (int j = 0; j < kDmaB8; ++j) {
-            const int r = 8 * (wave + 8 * j) + drow;
+            const int r = 16 * (wave + 8 * j) + drow;
             const uint32_t xo = uint32_t(x0 + r < a.n ? r : 0) * uint32_t(a.ld8);
             dma8_16s(xbase, xo + koff, sB0 + uint32_t(ibuf * kStageB8 + (wave + 8 * j) * 1024));
         }
         ibuf = (ibuf + 1 == kNBuf8) ? 0 : ibuf + 1;
         if (++ic == nk) {
             ic = 0;
-            ++it;
+            ++ip;
         }
     };
     int issued = 0;
     for (; issued < kNBuf8 - 1 && issued < nstages; ++issued) issue_next();
 
     int buf = 0, consumed = 0;
-    for (int T = t_begin; T < t_end; ++T) {
+    for (int P = 0; P < npair; ++P) {
+        const int T = t_begin + 2 * P;
         const int64_t x0 = int64_t(T) * kTP8;
-        f4v acc[4][4];
+        v16f acc[2][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int j = 0; j < 4; ++j) acc[i][j] = v16f{};
         for (int kc = 0; kc < nk; ++kc) {
-            // Loads complete in issue order: after this stage's loads at
-            // most one later stage's were issued, so waiting down to one
-            // stage's worth completes this stage for this wave, and the
-            // barrier then covers every wave and frees the buffer of the
-            // stage before for reuse.
+            // Loads complete in issue order: waiting down to the stages issued
+            // after this one completes this stage for this wave, and the
+            // barrier then covers every wave and frees the buffer of the stage
+            // before for reuse.
             asm volatile("" ::: "memory");
-            if (issued - consumed >= 2) __builtin_amdgcn_s_waitcnt(kWait8(kDmaA8 + kDmaB8));
+            const int ahead = issued - consumed - 1;
+            if (ahead >= 2) __builtin_amdgcn_s_waitcnt(kWait8(2 * kDma8));
+            else if (ahead == 1) __builtin_amdgcn_s_waitcnt(kWait8(kDma8));
             else __builtin_amdgcn_s_waitcnt(kWait8(0));
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
@@ -250,80 +261,85 @@ __global__ __launch_bounds__(kT8Threads) void k_tile_fp8(Tile8Args a) {
             const uint8_t* A = sA[buf];
             const uint8_t* B = sB[buf];
             // fragments: 32 k bytes of the lane's row; bytes past the row are zero
-            const bool lo_in = kc * kKS8 + 32 * fg < a.ld8;
-            const bool hi_in = kc * kKS8 + 32 * fg + 16 < a.ld8;
-            v8i fa[4], fb[4];
+            const bool lo_in = kc * kKS + 32 * kg < a.ld8;
+            const bool hi_in = kc * kKS + 32 * kg + 16 < a.ld8;
+            v8i fa[2], fb[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = 64 * qh + 16 * i + fr;
-                uint4 lo = *reinterpret_cast<const uint4*>(&A[r * kKS8 + (((2 * fg) ^ (r & 7)) << 4)]);
-                uint4 hi = *reinterpret_cast<const uint4*>(&A[r * kKS8 + (((2 * fg + 1) ^ (r & 7)) << 4)]);
+            for (int i = 0; i < 2; ++i) {
+                const int r = 64 * qq + 32 * i + fr;
+                uint4 lo = *reinterpret_cast<const uint4*>(&A[unit_off8(r, 2 * kg)]);
+                uint4 hi = *reinterpret_cast<const uint4*>(&A[unit_off8(r, 2 * kg + 1)]);
                 if (!lo_in) lo = make_uint4(0, 0, 0, 0);
                 if (!hi_in) hi = make_uint4(0, 0, 0, 0);
                 fa[i] = v8i{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int r = 64 * ph + 16 * j + fr;
-                const uint4 lo = *reinterpret_cast<const uint4*>(&B[r * kKS8 + (((2 * fg) ^ (r & 7)) << 4)]);
-                const uint4 hi = *reinterpret_cast<const uint4*>(&B[r * kKS8 + (((2 * fg + 1) ^ (r & 7)) << 4)]);
+                const int r = 128 * ph + 32 * j + fr;
+                const uint4 lo = *reinterpret_cast<const uint4*>(&B[unit_off8(r, 2 * kg)]);
+                const uint4 hi = *reinterpret_cast<const uint4*>(&B[unit_off8(r, 2 * kg + 1)]);
                 fb[j] = v8i{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[i], fb[j], acc[i][j],
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j],
                                                                                 0, 0, 0, 127, 0, 127);
             buf = (buf + 1 == kNBuf8) ? 0 : buf + 1;
             ++consumed;
         }
-        // epilogue operands of this tile: the block's masks and offsets, the
-        // points' norms and scales.  The previous tile's epilogue finished
-        // reading them before this tile's first stage barrier.
+        // epilogue operands of this tile pair: the block's masks and offsets
+        // of both mask tiles, the points' norms and scales.  The previous
+        // pair's epilogue finished reading them before this pair's first
+        // stage barrier.
         if (tid < kQB) {
             const int q = q0 + tid;
-            if (q < a.nq) {
-                const int64_t mi = (int64_t(q) * a.ntiles + T) * 2;
-                sMask[tid][0] = a.masks[mi];
-                sMask[tid][1] = a.masks[mi + 1];
-                sOff[tid] = a.offs[int64_t(q) * a.ntiles + T];
-            } else {
-                sMask[tid][0] = 0;
-                sMask[tid][1] = 0;
-                sOff[tid] = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bool in = q < a.nq && T + h < t_end;
+                const int64_t mi = (int64_t(q) * a.ntiles + T + h) * 2;
+                sMask[tid][h][0] = in ? a.masks[mi] : 0;
+                sMask[tid][h][1] = in ? a.masks[mi + 1] : 0;
+                sOff[tid][h] = in ? a.offs[int64_t(q) * a.ntiles + T + h] : 0;
             }
-        } else if (tid < kQB + kTP8) {
-            const int xl = tid - kQB;
+        } else {
+            const int xl = tid - kQB;                      // 256 threads for the 256 points
             const int64_t x = x0 + xl;
-            sXn[xl] = x < a.n ? a.norm8[x] : 0.0f;
-            sXs[xl] = x < a.n ? a.scale8[x] : 0.0f;
+            const bool in = x < a.n && T + (xl >> 7) < t_end;
+            sXn[xl] = in ? a.norm8[x] : 0.0f;
+            sXs[xl] = in ? a.scale8[x] : 0.0f;
         }
         __syncthreads();
-        // C[row 4 fg + e][col fr] of fragment (ii, j): query 64 qh + 16 ii + 4 fg + e,
-        // point 64 ph + 16 j + fr of the tile
+        // C[row][col] of block (i, j): lane l holds column l % 32 and, in
+        // element e, row 8 (e / 4) + 4 (l / 32) + e % 4: query
+        // 64 qq + 32 i + row, point 128 ph + 32 j + l % 32 of the pair.  The
+        // lane's first row is made opaque, so that the addresses derived from
+        // it are formed here rather than held in registers across the loop.
+        int qrow = 64 * qq + 4 * kg;
+        asm volatile("" : "+v"(qrow));
 #pragma unroll
-        for (int ii = 0; ii < 4; ++ii)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int ql = 64 * qh + 16 * ii + 4 * fg + e;
-                const uint64_t m0 = sMask[ql][0], m1 = sMask[ql][1];
+            for (int e = 0; e < 16; ++e) {
+                const int ql = qrow + 32 * i + 8 * (e >> 2) + (e & 3);
+                const int h = ph;                           // the wave's points lie in mask tile ph
+                const uint64_t m0 = sMask[ql][h][0], m1 = sMask[ql][h][1];
                 if (!(m0 | m1)) continue;
-                const int64_t slot0 = int64_t(q0 + ql) * a.cap + sOff[ql];
+                const int64_t slot0 = int64_t(q0 + ql) * a.cap + sOff[ql][h];
                 const float qs2 = 2.0f * sQs[ql];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int xl = 64 * ph + 16 * j + fr;
-                    const bool cand = ((xl < 64 ? (m0 >> xl) : (m1 >> (xl - 64))) & 1u) != 0;
+                    const int xt = 32 * j + fr;             // point within mask tile h
+                    const bool cand = ((xt < 64 ? (m0 >> xt) : (m1 >> (xt - 64))) & 1u) != 0;
                     if (cand) {
-                        const int64_t slot = slot0 + popc128_below(m0, m1, xl);
-                        a.out_s[slot] = sXn[xl] - qs2 * sXs[xl] * acc[ii][j][e];
+                        const int xl = kTP8 * h + xt;
+                        const int64_t slot = slot0 + popc128_below(m0, m1, xt);
+                        a.out_s[slot] = sXn[xl] - qs2 * sXs[xl] * acc[i][j][e];
                         a.out_i[slot] = int(x0 + xl);
                     }
                 }
             }
-        // the next tile's epilogue overwrites these operands only after the
-        // barriers of its k stages (at least one)
     }
     __builtin_amdgcn_s_waitcnt(kWait8(0));
 }
@@ -396,8 +412,8 @@ __global__ __launch_bounds__(256) void k_topk_select(const float* __restrict__ o
 int tile8_ntiles(int64_t n) { return int((n + kTP8 - 1) / kTP8); }
 
 hipError_t launch_tile8(const Tile8Args& t, int nqw, hipStream_t st, hipEvent_t* ev) {
-    if (t.cw < 4 || t.cw > 32 || t.ld8 % 16 || t.ntiles != tile8_ntiles(t.n) || t.split_tiles < 1 ||
-        t.nsplit * t.split_tiles < t.ntiles)
+    if (t.cw < 4 || t.cw > 32 || t.ld8 % 16 || t.ntiles != tile8_ntiles(t.n) || t.split_tiles < 2 ||
+        t.split_tiles % 2 || t.nsplit * t.split_tiles < t.ntiles)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_cand_masks, dim3(unsigned(t.ntiles), unsigned(nqw)), dim3(128), 0, st,
                        t.visT, t.nq, t.n, t.cw, t.ntiles, t.masks);
