@@ -25,10 +25,14 @@
 //                    stream into three LDS buffers with direct global->LDS
 //                    loads (two stages in flight) as B operands.  After a tile
 //                    the two waves swap half their partial sums through LDS,
-//                    and each finishes 16 queries: the epilogue masks by the
-//                    candidate bits and keeps, per query and split, the `cap`
-//                    best (score, id) pairs in registers, three on each of the
-//                    16 lanes that hold that query's row of the MFMA result.
+//                    and each finishes 16 queries after the next tile's first
+//                    barrier: the epilogue masks by the candidate bits and
+//                    keeps, per query and split, the `cap` best (score, id)
+//                    pairs in registers, ordered across the 16 lanes that
+//                    hold that query's row of the MFMA result (three each).
+//                    The splits of a query block share bounds on its cap-th
+//                    best score (a full list's worst, and each split's
+//                    ceil(cap / nsplit)-th best) that let them skip points.
 //   k_merge_rerank   one workgroup per query: best `kk` over the splits, then
 //                    FP32 compensated re-rank and FP64 tie re-check.
 #include <hip/hip_runtime.h>
