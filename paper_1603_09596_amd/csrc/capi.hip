@@ -207,6 +207,7 @@ struct Workspace {
     uint32_t* openT; uint32_t* visT; uint32_t* gthr; float* part_s; int* part_i;   // tile paths only
     uint64_t* masks8; uint32_t* offs8; uint32_t* total8; float* out_s8; int* out_i8;   // FP8 tile path
     float* qt;   // [m][nb][t] reflected query coordinates (isometry variant only)
+    uint32_t* gbits;   // [nb][ceil(n/32)] candidate bitmap of a small sliced row scan
 };
 
 // Split of the points for the tile path: enough (query block, split)
@@ -294,6 +295,7 @@ struct WsLayout {
     size_t ock = 0, occ = 0, olb = 0, ofl = 0, oql = 0, oids = 0, odst = 0, oqt = 0;
     size_t oopen = 0, ovis = 0, othr = 0, ops = 0, opi = 0;
     size_t omask = 0, ooff = 0, otot = 0, oos = 0, ooi = 0;
+    size_t ogb = 0;
     size_t need = 0;   // bytes
 };
 
@@ -309,7 +311,7 @@ WsLayout ws_layout(const gf_forest* F, int nb, int k, int form, bool tile, int64
     L.oqn = c.take<float>(nb);
     L.ocpq = c.take<int32_t>(nb);
     L.ost = c.take<gf::SelState>(nb);
-    const int nslice = F->host.m * gf::select_slices_per_tree(F->host.H);
+    const int nslice = F->host.m * gf::select_slices_per_tree(F->host.H, F->host.m, nb);
     L.ohist = c.take<uint32_t>(size_t(nb) * nslice * 128);
     L.onc = c.take<uint32_t>(size_t(nb) * nslice);
     const int64_t ccap = gf::collect_capacity(F->host.H);
@@ -338,9 +340,11 @@ WsLayout ws_layout(const gf_forest* F, int nb, int k, int form, bool tile, int64
             L.ooi = c.take<int>(size_t(nb) * tp.cap8);
         }
     } else if (scan_nslice > 1) {
-        // the sliced row scan's per-slice lists
+        // the sliced row scan's per-slice lists, and for a small batch the
+        // candidate bitmap every slice reads its words of
         L.ops = c.take<float>(size_t(nb) * scan_nslice * gf::kTileList);
         L.opi = c.take<int>(size_t(nb) * scan_nslice * gf::kTileList);
+        if (nb <= gf::kMarkMaxQueries) L.ogb = c.take<uint32_t>(size_t(nb) * ((F->host.n + 31) / 32));
     }
     L.need = c.off + 256;
     return L;
@@ -375,6 +379,7 @@ void ws_bind(const gf_forest* F, const WsLayout& L, char* b, int form, bool tile
     w.total8 = t8 ? reinterpret_cast<uint32_t*>(b + L.otot) : nullptr;
     w.out_s8 = t8 ? reinterpret_cast<float*>(b + L.oos) : nullptr;
     w.out_i8 = t8 ? reinterpret_cast<int*>(b + L.ooi) : nullptr;
+    w.gbits = L.ogb ? reinterpret_cast<uint32_t*>(b + L.ogb) : nullptr;
 }
 
 gf_status get_workspace(gf_forest* F, int nb, int k, int form, bool tile, Workspace& w,
@@ -512,7 +517,7 @@ gf::SelectArgs make_select_args(const gf_forest* F, int nb, const Workspace& w, 
     sa.n_internal = (int64_t{1} << h.H) - 1; sa.W = int(W); sa.nodes = F->nodes; sa.D = F->D;
     sa.drange = F->drange;
     sa.leaves = h.real_leaves;
-    sa.nslice = h.m * gf::select_slices_per_tree(h.H);
+    sa.nslice = h.m * gf::select_slices_per_tree(h.H, h.m, nb);
     sa.state = w.state; sa.hist = w.hist; sa.coff = w.coff; sa.ckey = w.ckey;
     sa.ccap = gf::collect_capacity(h.H);
     sa.ccode = w.ccode; sa.leafbits = w.leafbits; sa.qlist = w.qlist; sa.nlist = 0;
@@ -555,7 +560,7 @@ gf_status launch_selection(const gf_forest* F, const QueryJob& J, int nb, const 
         gf::SelectArgs sw = sa;
         if (sparse) sw.nlist = int(more[1]);
         GF_HIP(gf::launch_select_walk(sw, phase, false, st, sparse ? 16 : 1));
-        hipLaunchKernelGGL(gf::k_select_pick, dim3(nb), dim3(128), 0, st, sa, phase, w.flags + 1);
+        hipLaunchKernelGGL(gf::k_select_pick, dim3(nb), dim3(gf::kPickThreads), 0, st, sa, phase, w.flags + 1);
         GF_HIP(hipGetLastError());
         if (early_exit && phase != gf::kPhSample) {
             GF_HIP(hipMemcpyAsync(more, w.flags + 1, 8, hipMemcpyDeviceToHost, st));
@@ -650,6 +655,10 @@ gf_status launch_rows(const gf_forest* F, const QueryJob& J, int nb, const Works
         ncand = ca.ncand;
         ca.ncand = nullptr;
         if (ncand && !ca.cand_bits) return fail(GF_EINTERNAL, "sliced trace without a bitmap");
+        if (w.gbits) {
+            GF_HIP(gf::launch_mark_candidates(ca, w.gbits, st));
+            ca.gbits = w.gbits;
+        }
     }
     GF_HIP(gf::launch_scan(ca, J.form, st));
     if (ncand) GF_HIP(gf::launch_count_bits(ca.cand_bits, nb, (F->host.n + 31) / 32, ncand, st));

@@ -75,9 +75,12 @@ __global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, in
 // Also clears flags[0..1] (the radix-pass flags of k_select_pick).
 __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps,
                               uint32_t* flags);
-// flags[0]: set when some query goes on to a radix pass; flags[1]: how many
+// flags[0]: set when some query goes on to a radix pass; flags[1]: how many.
+// One workgroup of kPickThreads per query.
+constexpr int kPickThreads = 512;
 __global__ void k_select_pick(SelectArgs a, int phase, uint32_t* flags);
-int select_slices_per_tree(int H);
+// leaf ranges per tree of the counting and collect walks (nslice = m times it)
+int select_slices_per_tree(int H, int m, int nq);
 __global__ void k_select_finish(SelectArgs a);
 // phase: kPhSample / kPhWindow / kPhRadix for a counting walk (ignored with
 // collect).  zfine > 1 splits each slice of a radix walk over zfine
@@ -122,6 +125,10 @@ struct ScanArgs {
     int64_t slice_words;
     float* part_s;
     int* part_i;
+    // [nq][ceil(n/32)] candidate bitmap built beforehand by
+    // launch_mark_candidates (small sliced batches), or null: each slice
+    // then expands the opened leaves itself
+    const uint32_t* gbits;
 };
 
 // Scan kernel launch: one workgroup per query.  Returns hipErrorInvalidValue
@@ -133,6 +140,11 @@ size_t scan_lds_bytes_words(int64_t words, int form, int64_t ld8);
 // when not even one step fits (FP8 rows too wide to stage the query).  Id
 // ranges above it are cut into slices of at most this many words.
 int64_t scan_max_slice_words(int form, int64_t ld8);
+// Candidate bitmap of each query, [nq][ceil(n/32)], from the opened leaves
+// (cleared first), for the sliced scan of a small batch: one pass over the
+// opened leaves instead of one per slice.
+constexpr int kMarkMaxQueries = 64;
+hipError_t launch_mark_candidates(const ScanArgs& a, uint32_t* gbits, hipStream_t st);
 // Number of set bits of each query's row of an [nq][nbmw] bitmap.
 hipError_t launch_count_bits(const uint32_t* bits, int nq, int64_t nbmw, int64_t* count, hipStream_t st);
 size_t scan_lds_bytes(int64_t n, int form, int64_t ld8);

@@ -20,6 +20,7 @@
 //      (FP64 distance, id).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -149,11 +150,17 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     float* rr_d = reinterpret_cast<float*>(mg_i + kWaves * kWave);       // [64]
     float* q8f = rr_d + kWave;          // [ld8] decoded FP8 query, or the staged FP32 / BF16 query
 
-    // 1. visited bitmap <- union of the opened leaves
-    for (int64_t i = threadIdx.x; i < nbmw_pad; i += kThreads) bm[i] = 0u;
-    __syncthreads();
-    expand_opened_leaves(bm, a.leafbits, q, a.nq, a.m, a.W, a.H, a.permp, a.pp, threadIdx.x,
-                         kThreads, w_lo, w_lo + nbmw);
+    // 1. visited bitmap <- union of the opened leaves (this slice's words of
+    // the query's bitmap, when one was built beforehand)
+    if (a.gbits) {
+        const uint32_t* g = a.gbits + int64_t(q) * nbmw_all + w_lo;
+        for (int64_t i = threadIdx.x; i < nbmw_pad; i += kThreads) bm[i] = i < nbmw ? g[i] : 0u;
+    } else {
+        for (int64_t i = threadIdx.x; i < nbmw_pad; i += kThreads) bm[i] = 0u;
+        __syncthreads();
+        expand_opened_leaves(bm, a.leafbits, q, a.nq, a.m, a.W, a.H, a.permp, a.pp, threadIdx.x,
+                             kThreads, w_lo, w_lo + nbmw);
+    }
     __syncthreads();
     if (a.cand_bits) {
         // this slice's words of the query's row of the candidate bitmap
@@ -433,6 +440,51 @@ int64_t scan_max_slice_words(int form, int64_t ld8) {
     const size_t fixed = scan_lds_bytes_words(0, form, ld8);
     if (fixed + size_t(kListWords) * 4 > 160 * 1024) return 0;
     return int64_t((160 * 1024 - fixed) / 4) / kListWords * kListWords;
+}
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* p, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+        p[i] = 0u;
+}
+
+// One thread per leaf of the forest (x) and query (y): an opened leaf's point
+// ids go into the query's row of the bitmap.
+__global__ __launch_bounds__(256) void k_mark_candidates(ScanArgs a, uint32_t* gbits) {
+    const int q = int(blockIdx.y);
+    const int64_t leaf = int64_t(blockIdx.x) * 256 + threadIdx.x;   // word leaf / 32, bit leaf % 32
+    const int64_t f = leaf >> 5;
+    if (f >= int64_t(a.m) * a.W) return;
+    if (!((a.leafbits[f * a.nq + q] >> (leaf & 31)) & 1u)) return;
+    const int64_t nleaf = int64_t(1) << a.H;
+    const int64_t tree = f / a.W, lt = (f % a.W) * 32 + (leaf & 31);
+    if (lt >= nleaf) return;
+    const uint4* row = reinterpret_cast<const uint4*>(a.permp + (tree * nleaf + lt) * a.pp);
+    uint32_t* g = gbits + int64_t(q) * ((a.n + 31) / 32);
+    for (int c = 0; c < a.pp / 4; ++c) {
+        const uint4 v = row[c];
+        const uint32_t ids[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (ids[e] != 0xFFFFFFFFu) atomicOr(&g[ids[e] >> 5], 1u << (ids[e] & 31u));
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mark_candidates(const ScanArgs& a, uint32_t* gbits, hipStream_t st) {
+    if (a.nq <= 0) return hipSuccess;
+    if (a.nq > kMarkMaxQueries || a.pp % 4) return hipErrorInvalidValue;
+    const int64_t words = int64_t(a.nq) * ((a.n + 31) / 32);
+    const int64_t zb = std::min<int64_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_words, dim3(unsigned(zb)), dim3(256), 0, st, gbits, words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t leaves = int64_t(a.m) * a.W * 32;
+    hipLaunchKernelGGL(k_mark_candidates, dim3(unsigned((leaves + 255) / 256), unsigned(a.nq)), dim3(256), 0,
+                       st, a, gbits);
+    return hipGetLastError();
 }
 
 hipError_t launch_scan(const ScanArgs& a, int form, hipStream_t st) {

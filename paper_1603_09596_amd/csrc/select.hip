@@ -191,6 +191,7 @@ __device__ __forceinline__ void stage_query_dims(const SelectArgs& a, int q, uin
 // counters), each keeping its own path state.
 constexpr int kSelWaves = 4;
 constexpr int kSelThreads = kSelWaves * kWave;
+constexpr int kSelMinGroups = 1024;
 
 __device__ __forceinline__ void wave_chunks(uint32_t nchunks, uint32_t& cb, uint32_t& ce) {
     const uint32_t per = (nchunks + gridDim.z - 1) / gridDim.z;
@@ -604,12 +605,11 @@ __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, 
 //   window: fix the 1/128-octave bin of the B-th key if it is inside the
 //           window, else start radix passes from the top of the key;
 //   radix:  fix the digit holding the B-th key.
-// A query whose bin holds at most kCollectCap leaves is ready, and the
-// offsets at which each slice will write its share of the bin are set.
-// Returns whether the query's next walk is a radix pass; such queries set
+// A query whose bin holds at most kCollectCap leaves is ready (ready_bin is
+// set to the bin).  Returns whether the query's next walk is a radix pass; such queries set
 // flags[0] and are listed in qlist at positions counted in flags[1].
 __device__ bool pick_one(const SelectArgs& a, int phase, SelState s, const uint32_t* tot,
-                         const uint32_t* h, uint32_t* flags) {
+                         uint32_t* flags, int& ready_bin) {
     const int q = blockIdx.x;
     const uint32_t ns = uint32_t(sample_trees(a.m));
     // the sample covers ns of the m trees: aim at the same share of its leaves
@@ -655,11 +655,7 @@ __device__ bool pick_one(const SelectArgs& a, int phase, SelState s, const uint3
         s.bincount = tot[dgt];
         if (s.bincount <= uint32_t(kCollectCap) || s.cs == 0u) {
             s.status = kSelReady;
-            uint32_t off = 0;
-            for (int sl = 0; sl < a.nslice; ++sl) {
-                a.coff[int64_t(q) * a.nslice + sl] = off;
-                off += h[int64_t(sl) * kBins + dgt];
-            }
+            ready_bin = dgt;
         } else {
             radix = true;
         }
@@ -676,28 +672,63 @@ __device__ bool pick_one(const SelectArgs& a, int phase, SelState s, const uint3
 }
 
 // After a counting walk: for the queries it served, sum each bin over the
-// slices (one workgroup of 128 threads per query, thread b takes bin b) and
-// move the query on (pick_one).
-__global__ __launch_bounds__(kBins) void k_select_pick(SelectArgs a, int phase, uint32_t* flags) {
+// slices (one workgroup per query, kPickParts threads per bin, each taking
+// every kPickParts-th slice) and move the query on (pick_one).  A query that
+// is ready gets the offsets at which each slice writes its share of the bin:
+// an exclusive prefix sum over the slices (in wave 0).
+constexpr int kPickParts = 4;
+static_assert(kPickThreads == kPickParts * kBins, "kPickParts threads per bin");
+__global__ __launch_bounds__(kPickThreads) void k_select_pick(SelectArgs a, int phase, uint32_t* flags) {
+    __shared__ uint32_t part[kPickParts][kBins];
     __shared__ uint32_t tot[kBins];
-    __shared__ uint32_t again;
+    __shared__ int again, rbin;
     const int q = blockIdx.x;
     const SelState s = a.state[q];
     if (s.status != kSelSearching || s.phase != uint32_t(phase)) return;
     uint32_t* h = a.hist + int64_t(q) * a.nslice * kBins;
+    const int b = int(threadIdx.x) % kBins, pp = int(threadIdx.x) / kBins;
     // the sample walk writes the first ns * (nslice / ns) slices
     const int ns = sample_trees(a.m);
     const int nsl = (phase == kPhSample) ? ns * (a.nslice / ns) : a.nslice;
     uint32_t sum = 0;
-    for (int sl = 0; sl < nsl; ++sl) sum += h[int64_t(sl) * kBins + threadIdx.x];
-    tot[threadIdx.x] = sum;
+    for (int sl = pp; sl < nsl; sl += kPickParts) sum += h[int64_t(sl) * kBins + b];
+    part[pp][b] = sum;
     __syncthreads();
-    if (threadIdx.x == 0) again = pick_one(a, phase, s, tot, h, flags) ? 1u : 0u;
+    if (pp == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int i = 0; i < kPickParts; ++i) t += part[i][b];
+        tot[b] = t;
+    }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        int rb = -1;
+        again = pick_one(a, phase, s, tot, flags, rb) ? 1 : 0;
+        rbin = rb;
+    }
+    __syncthreads();
+    if (rbin >= 0 && threadIdx.x < kWave) {
+        // lane l of wave 0 takes a run of consecutive slices
+        const int lane = int(threadIdx.x);
+        const int per = (a.nslice + kWave - 1) / kWave;
+        const int s0 = min(a.nslice, lane * per), s1 = min(a.nslice, s0 + per);
+        uint32_t loc = 0;
+        for (int sl = s0; sl < s1; ++sl) loc += h[int64_t(sl) * kBins + rbin];
+        uint32_t inc = loc;   // inclusive scan of the runs over the lanes
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t v = __shfl_up(inc, o);
+            if (lane >= o) inc += v;
+        }
+        uint32_t off = inc - loc;
+        for (int sl = s0; sl < s1; ++sl) {
+            a.coff[int64_t(q) * a.nslice + sl] = off;
+            off += h[int64_t(sl) * kBins + rbin];
+        }
+    }
     // a query that goes on to a radix pass gets cleared rows (that pass may
-    // add into them); thread b clears bin b, which only it has read
+    // add into them); each thread clears the slices of bin b it has read
     if (again)
-        for (int sl = 0; sl < a.nslice; ++sl) h[int64_t(sl) * kBins + threadIdx.x] = 0u;
+        for (int sl = pp; sl < a.nslice; sl += kPickParts) h[int64_t(sl) * kBins + b] = 0u;
 }
 
 // Resolve the bin: exactly (B - below) of the collected leaves are taken
@@ -999,10 +1030,15 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
 }
 
 // Each tree is walked in ranges of at most 2^15 leaves (one workgroup per
-// range), so that the packed 16-bit histogram counters cannot overflow.
-int select_slices_per_tree(int H) {
+// range), so that the packed 16-bit histogram counters cannot overflow.  For
+// small batches the ranges are cut finer, down to 2^10 leaves (8 chunks of 32
+// per wave), until a walk has kSelMinGroups workgroups: a single query
+// otherwise walks each tree on one CU.
+int select_slices_per_tree(int H, int m, int nq) {
     int z = 1;
     while ((int64_t{1} << H) / z > 32768) z <<= 1;
+    const int64_t groups = int64_t((nq + kWave - 1) / kWave) * m;
+    while (groups * z < kSelMinGroups && (int64_t{1} << H) / z > 1024) z <<= 1;
     return z;
 }
 
@@ -1017,7 +1053,7 @@ hipError_t launch_select_walk(const SelectArgs& a, int phase, bool collect, hipS
                size_t(kSelWaves) * (entry ? 2 : 1) * (U + 1) * kWave * 4;
     };
     if (lds_of(true) > 160 * 1024) return hipErrorInvalidValue;
-    const int zsplit = select_slices_per_tree(a.H);
+    const int zsplit = select_slices_per_tree(a.H, a.m, a.nq);
     if (a.nslice != a.m * zsplit) return hipErrorInvalidValue;
     // the sample walk covers the first sample_trees(m) trees, in as many
     // slices as a full walk has
