@@ -691,6 +691,7 @@ __global__ __launch_bounds__(kPickThreads) void k_select_pick(SelectArgs a, int 
     const int ns = sample_trees(a.m);
     const int nsl = (phase == kPhSample) ? ns * (a.nslice / ns) : a.nslice;
     uint32_t sum = 0;
+#pragma unroll 8
     for (int sl = pp; sl < nsl; sl += kPickParts) sum += h[int64_t(sl) * kBins + b];
     part[pp][b] = sum;
     __syncthreads();
@@ -713,6 +714,7 @@ __global__ __launch_bounds__(kPickThreads) void k_select_pick(SelectArgs a, int 
         const int per = (a.nslice + kWave - 1) / kWave;
         const int s0 = min(a.nslice, lane * per), s1 = min(a.nslice, s0 + per);
         uint32_t loc = 0;
+#pragma unroll 8
         for (int sl = s0; sl < s1; ++sl) loc += h[int64_t(sl) * kBins + rbin];
         uint32_t inc = loc;   // inclusive scan of the runs over the lanes
         for (int o = 1; o < kWave; o <<= 1) {

@@ -672,8 +672,14 @@ __global__ __launch_bounds__(kMergeMax) void k_merge_rerank(MergeArgs a) {
             L.d = lane < a.kk ? md[lane] : __builtin_inff();
             L.id = lane < a.kk ? mi[lane] : 0x7FFFFFFF;
         }
-    } else if (wave == 0) {
-        for (int64_t e0 = 0; e0 < tot; e0 += kWave) {
+    } else {
+        // each wave keeps the kk best of every blockDim.x / kWave-th run of
+        // kWave entries; then the waves' lists (at most kMergeMax entries)
+        // are ranked at once as above
+        __shared__ float es[kMergeMax];
+        __shared__ int ei[kMergeMax];
+        const int nw = int(blockDim.x) / kWave;
+        for (int64_t e0 = int64_t(wave) * kWave; e0 < tot; e0 += int64_t(nw) * kWave) {
             const int64_t e = e0 + lane;
             const float s = e < tot ? ps[e] : __builtin_inff();
             const int id = e < tot ? pi[e] : 0x7FFFFFFF;
@@ -686,9 +692,23 @@ __global__ __launch_bounds__(kMergeMax) void k_merge_rerank(MergeArgs a) {
                 L.offer(__shfl(s, src), __shfl(id, src), a.kk);
             }
         }
-        if (lane < a.kk) {
-            md[lane] = L.d;
-            mi[lane] = L.id;
+        const int t = int(threadIdx.x);
+        const float sv = lane < a.kk ? L.d : __builtin_inff();
+        const int iv = lane < a.kk ? L.id : 0x7FFFFFFF;
+        es[t] = sv;
+        ei[t] = iv;
+        if (t < kWave) { md[t] = __builtin_inff(); mi[t] = 0x7FFFFFFF; }
+        __syncthreads();
+        if (sv < __builtin_inff()) {
+            int rank = 0;
+            for (int f = 0; f < int(blockDim.x); ++f)
+                if (es[f] < __builtin_inff() && entry_before(es[f], ei[f], sv, iv)) ++rank;
+            if (rank < a.kk) { md[rank] = sv; mi[rank] = iv; }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            L.d = lane < a.kk ? md[lane] : __builtin_inff();
+            L.id = lane < a.kk ? mi[lane] : 0x7FFFFFFF;
         }
     }
     __syncthreads();
