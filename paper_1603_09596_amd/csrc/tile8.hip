@@ -3,9 +3,9 @@
 //
 // At d = 10,000 a query's candidates (Sec. 2.3) are a few percent of the
 // points, yet gathering them row by row reads 10 KB per candidate from HBM,
-// while the dense product of a 128-query block with a 128-point tile costs
-// 0.3 GFLOP on the FP8 matrix cores (5 PFLOP/s): scoring every pair of a
-// block is cheaper than gathering the pairs that count.  The forest then
+// while the dense product of a 256-query block with a 256-point tile pair
+// costs 1.3 GFLOP on the FP8 matrix cores (5 PFLOP/s): scoring every pair of
+// a block is cheaper than gathering the pairs that count.  The forest then
 // decides which scores are kept, through the per-point candidate words of
 // the tile path's expansion, and only those are written out, compacted:
 //
@@ -14,13 +14,15 @@
 //                  per-point words of query bits (ballots over the points);
 //   k_cand_prefix  per query: the exclusive prefix count of its candidates
 //                  over the tiles, so that every candidate has its own slot;
-//   k_tile_fp8     grid (query blocks of 128, point splits): A (queries) and
-//                  B (points) stream through LDS in 128-byte k stages, both
-//                  double-buffered; each wave computes a 64 x 64 block with
-//                  v_mfma_scale_f32_16x16x128_f8f6f4 (neutral scales, FP32
-//                  accumulation); the epilogue forms ||x||^2 - 2 s_q s_x q.x
-//                  for the candidates only and writes (score, id) to the
-//                  query's slots;
+//   k_tile_fp8     grid (query blocks of 256, point splits of an even number
+//                  of tiles): A (queries) and B (points) stream through LDS
+//                  by direct loads in 64-byte k stages, four buffers with
+//                  three in flight; each wave computes 64 queries x 128
+//                  points of the 256 x 256 block as 2 x 4 blocks of 32 x 32
+//                  with v_mfma_scale_f32_32x32x64_f8f6f4 (neutral scales,
+//                  FP32 accumulation); the epilogue forms
+//                  ||x||^2 - 2 s_q s_x q.x for the candidates only and writes
+//                  (score, id) to the query's slots;
 //   k_topk_select  per query: a radix select over the (score, id) keys of its
 //                  candidates keeps the kk best, handed to the tile path's
 //                  merge, FP32 compensated re-rank and FP64 tie re-check.
@@ -38,7 +40,7 @@ namespace {
 constexpr int kW = 64;                 // wavefront
 constexpr int kQB = kTile8Queries;     // queries per workgroup
 constexpr int kTP8 = 128;              // points per tile
-constexpr int kT8Threads = 512;        // 8 waves, each a 64 x 64 block
+constexpr int kT8Threads = 512;        // 8 waves, each 64 queries x 128 points
 constexpr int kXcd8 = 8;               // XCDs of an MI355X
 
 typedef int v8i __attribute__((ext_vector_type(8)));
