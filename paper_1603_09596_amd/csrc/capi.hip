@@ -560,7 +560,8 @@ gf_status launch_selection(const gf_forest* F, const QueryJob& J, int nb, const 
         gf::SelectArgs sw = sa;
         if (sparse) sw.nlist = int(more[1]);
         GF_HIP(gf::launch_select_walk(sw, phase, false, st, sparse ? 16 : 1));
-        hipLaunchKernelGGL(gf::k_select_pick, dim3(nb), dim3(gf::kPickThreads), 0, st, sa, phase, w.flags + 1);
+        hipLaunchKernelGGL(gf::k_select_pick, dim3(nb), dim3(gf::pick_threads(sa.nslice)), 0, st, sa, phase,
+                           w.flags + 1);
         GF_HIP(hipGetLastError());
         if (early_exit && phase != gf::kPhSample) {
             GF_HIP(hipMemcpyAsync(more, w.flags + 1, 8, hipMemcpyDeviceToHost, st));

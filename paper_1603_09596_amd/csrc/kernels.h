@@ -76,8 +76,9 @@ __global__ void k_reflect_queries(const float* Q, int64_t ldq, int nq, int d, in
 __global__ void k_select_init(SelectArgs a, int32_t checks, const int32_t* cpq, double eps,
                               uint32_t* flags);
 // flags[0]: set when some query goes on to a radix pass; flags[1]: how many.
-// One workgroup of kPickThreads per query.
+// One workgroup per query: pick_threads(nslice) threads, at most kPickThreads.
 constexpr int kPickThreads = 512;
+inline int pick_threads(int nslice) { return nslice > 64 ? kPickThreads : 128; }
 __global__ void k_select_pick(SelectArgs a, int phase, uint32_t* flags);
 // leaf ranges per tree of the counting and collect walks (nslice = m times it)
 int select_slices_per_tree(int H, int m, int nq);

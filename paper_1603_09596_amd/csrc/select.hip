@@ -672,8 +672,9 @@ __device__ bool pick_one(const SelectArgs& a, int phase, SelState s, const uint3
 }
 
 // After a counting walk: for the queries it served, sum each bin over the
-// slices (one workgroup per query, kPickParts threads per bin, each taking
-// every kPickParts-th slice) and move the query on (pick_one).  A query that
+// slices (one workgroup per query, blockDim.x / kBins threads per bin, at
+// most kPickParts, each taking every blockDim.x / kBins-th slice) and move
+// the query on (pick_one).  A query that
 // is ready gets the offsets at which each slice writes its share of the bin:
 // an exclusive prefix sum over the slices (in wave 0).
 constexpr int kPickParts = 4;
@@ -687,18 +688,18 @@ __global__ __launch_bounds__(kPickThreads) void k_select_pick(SelectArgs a, int 
     if (s.status != kSelSearching || s.phase != uint32_t(phase)) return;
     uint32_t* h = a.hist + int64_t(q) * a.nslice * kBins;
     const int b = int(threadIdx.x) % kBins, pp = int(threadIdx.x) / kBins;
+    const int parts = int(blockDim.x) / kBins;
     // the sample walk writes the first ns * (nslice / ns) slices
     const int ns = sample_trees(a.m);
     const int nsl = (phase == kPhSample) ? ns * (a.nslice / ns) : a.nslice;
     uint32_t sum = 0;
 #pragma unroll 8
-    for (int sl = pp; sl < nsl; sl += kPickParts) sum += h[int64_t(sl) * kBins + b];
+    for (int sl = pp; sl < nsl; sl += parts) sum += h[int64_t(sl) * kBins + b];
     part[pp][b] = sum;
     __syncthreads();
     if (pp == 0) {
         uint32_t t = 0;
-#pragma unroll
-        for (int i = 0; i < kPickParts; ++i) t += part[i][b];
+        for (int i = 0; i < parts; ++i) t += part[i][b];
         tot[b] = t;
     }
     __syncthreads();
@@ -730,7 +731,7 @@ __global__ __launch_bounds__(kPickThreads) void k_select_pick(SelectArgs a, int 
     // a query that goes on to a radix pass gets cleared rows (that pass may
     // add into them); each thread clears the slices of bin b it has read
     if (again)
-        for (int sl = pp; sl < a.nslice; sl += kPickParts) h[int64_t(sl) * kBins + b] = 0u;
+        for (int sl = pp; sl < a.nslice; sl += parts) h[int64_t(sl) * kBins + b] = 0u;
 }
 
 // Resolve the bin: exactly (B - below) of the collected leaves are taken
