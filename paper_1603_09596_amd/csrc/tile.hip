@@ -481,6 +481,9 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
                     v[b] = *reinterpret_cast<const uint4*>(xb + ldsel(0) + 16 * kKS * b);
             // keep the scheduler from sinking the reads down to their uses
             __builtin_amdgcn_sched_barrier(0);
+            // A wave issuing its stage's MFMAs takes issue priority over its
+            // SIMD partner while that one is in its epilogue or list inserts.
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int s = 0; s < kHalf; ++s) {
                 const int J = c * kHalf + s;
@@ -503,6 +506,7 @@ __global__ __launch_bounds__(kTThreads) void k_tile_bf16(TileArgs a) {
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
+            __builtin_amdgcn_s_setprio(0);
             buf = (buf + 1 == kNBuf) ? 0 : buf + 1;
             --left;
         }
