@@ -168,6 +168,25 @@ def test_opened_leaves_and_candidates_bit_exact(name, k, c, eps):
     assert np.array_equal(nc, ref["ncand"])
 
 
+@pytest.mark.parametrize("name,c", [("quant-h16", 20_000), ("deep-h17", 60_000), ("scales", 200)])
+def test_opened_leaves_independent_of_batch_size(name, c):
+    """Small batches walk each tree in finer leaf ranges (more workgroups per
+    tree, more histogram slices per query): a query's opened leaves and
+    candidates must be the oracle's whatever batch it comes in."""
+    X, Q, Fg, Fo, _ = forests(name)
+    ref = oracle.search(Fo, X, Q[:6], 5, c, candidates=True)
+    for lo, hi in ((0, 1), (1, 3), (0, 6)):
+        nq = hi - lo
+        lb_d = dev(np.zeros((nq, Fg.m, Fg.leaf_words), np.uint32))
+        cb_d = dev(np.zeros((nq, (Fg.n + 31) // 32), np.uint32))
+        geraf.query_trace(Fg, dev(Q[lo:hi]), c, leaf_bits=lb_d, cand_bits=cb_d)
+        torch.cuda.synchronize()
+        lb, cb = lb_d.cpu().numpy(), cb_d.cpu().numpy()
+        for i in range(nq):
+            assert leaf_set_from_bits(lb[i]) == set(ref["opened"][lo + i].tolist()), f"batch {lo}:{hi} query {i}"
+            assert np.array_equal(ids_from_bits(cb[i], Fg.n), ref["cand"][lo + i]), f"batch {lo}:{hi} query {i}"
+
+
 @pytest.mark.parametrize("name,c", [("desc-60k-960", 4096), ("gauss-10k-128", 700),
                                     ("sphere-20k-1000", 1024), ("ragged-3001-77", 300),
                                     ("quantised", 37), ("scales", 200), ("quant-h16", 20_000)])
@@ -490,6 +509,24 @@ def test_sliced_row_scan_equals_one_workgroup_per_query(name, form, k, c, monkey
         out.append((ids, dd))
     for ids, dd in out[1:]:
         assert np.array_equal(ids, out[0][0]) and np.array_equal(dd, out[0][1])
+
+
+def test_row_scan_bitmap_prepass_boundary(monkeypatch):
+    """Sliced row scans of batches of up to 64 queries read a candidate bitmap
+    built once per query; larger batches expand the opened leaves in every
+    slice.  The first 64 queries' results agree bit for bit across that
+    boundary, and a single query's with both."""
+    X, Q, Fg, Fo, _ = forests("desc-60k-960", forms=("bf16",))
+    monkeypatch.setenv("GF_SCAN_PATH", "rows")
+    monkeypatch.delenv("GF_SCAN_SLICES", raising=False)
+    res = {}
+    for nq in (1, 64, 65):
+        ids = np.zeros((nq, 10), np.int32)
+        dd = np.zeros((nq, 10), np.float32)
+        geraf.query(Fg, Q[:nq], 10, 4096, ids, dd, form="bf16")
+        res[nq] = (ids, dd)
+    assert np.array_equal(res[64][0], res[65][0][:64]) and np.array_equal(res[64][1], res[65][1][:64])
+    assert np.array_equal(res[1][0], res[65][0][:1]) and np.array_equal(res[1][1], res[65][1][:1])
 
 
 @pytest.mark.parametrize("k", [1, 5, 10, 12])
