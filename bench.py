@@ -243,7 +243,9 @@ def pmc_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc
     summary of `workload` (profiles/pmc_<workload>.txt or
     profiles/pmc_<workload>_<part>.txt), or None when none records that
-    kernel, or the one that does was taken on a different source of it."""
+    kernel, or the one that does was taken on a different source of it (the
+    kernel's source_file and, where recorded, the launch_file that chooses
+    its launch shape)."""
     import glob
     paths = sorted(glob.glob(os.path.join(ROOT, "profiles", f"pmc_{glob.escape(workload)}*.txt")))
     for path in paths:
@@ -255,9 +257,13 @@ def pmc_traffic(kernel, workload):
         src = vals.get("source_file")
         if vals.get("kernel") != kernel or not src:
             continue
-        cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
-        if vals.get("source_sha256") != cur:
-            return None
+        for fkey, hkey in (("source_file", "source_sha256"), ("launch_file", "launch_sha256")):
+            f = vals.get(fkey)
+            if f is None:
+                continue
+            cur = hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest()
+            if vals.get(hkey) != cur:
+                return None
         try:
             return float(vals["hbm_bytes_per_dispatch"])
         except (KeyError, ValueError):

@@ -224,10 +224,25 @@ struct TilePlan {
     int64_t cap8 = 0;
 };
 
-// The tile kernel runs one workgroup per CU at a time, so the batch takes
-// ceil(qblocks * ns / CUs) rounds of 1/ns of the work each; among split
-// counts the one with the least such time wins, with a small charge per
-// split for its list (every split fills and merges its own per-query list).
+// The tile kernels run one workgroup per CU at a time, so the batch takes
+// ceil(qblocks * ns / CUs) rounds of 1/ns of the work each, plus a fixed
+// cost per round (start-up, list fill and write-out: about 0.4% of one
+// workgroup's pass over all the points, measured at 10^6 x 960).  Among the
+// split counts within 2% of the least such time the smallest wins: every
+// split fills and merges its own per-query list, and with 2 or 3 splits the
+// splits also share a rank bound.
+int64_t pick_splits(int64_t qblocks, int64_t max_splits, int64_t cus) {
+    auto cost = [&](int64_t s) {
+        const double rounds = double((qblocks * s + cus - 1) / cus);
+        return rounds * (1.0 / double(s) + 0.004);
+    };
+    double best = 1e300;
+    for (int64_t s = 1; s <= max_splits; ++s) best = std::min(best, cost(s));
+    for (int64_t s = 1; s <= max_splits; ++s)
+        if (cost(s) <= 1.02 * best) return s;
+    return 1;
+}
+
 int device_cus() {
     static int cus = 0;
     if (cus == 0) {
@@ -249,14 +264,7 @@ TilePlan tile_plan(const gf_forest* F, int nb, int form = gf::kFormBF16, int64_t
         // time in whole rounds
         const int64_t qblocks = (nb + gf::kTile8Queries - 1) / gf::kTile8Queries;
         const int64_t tiles = gf::tile8_ntiles(F->host.n);
-        const int64_t cus = device_cus();
-        int64_t ns = 1;
-        double best = 1e300;
-        for (int64_t s = 1; s <= std::min<int64_t>(tiles, 512); ++s) {
-            const double rounds = double((qblocks * s + cus - 1) / cus);
-            const double cost = rounds / double(s) + 0.002 * double(s);
-            if (cost < best) { best = cost; ns = s; }
-        }
+        const int64_t ns = pick_splits(qblocks, std::min<int64_t>((tiles + 1) / 2, 512), device_cus());
         p.ntiles8 = int(tiles);
         // the score kernel takes the 128-point tiles in pairs: splits of an
         // even number of tiles (the last may be odd)
@@ -268,14 +276,7 @@ TilePlan tile_plan(const gf_forest* F, int nb, int form = gf::kFormBF16, int64_t
     const int64_t qblocks = (nb + 127) / 128;
     const int64_t tiles = (F->host.n + 63) / 64;
     const int64_t max_tiles = ((int64_t{1} << 31) - 1) / (int64_t(F->ld16) * 2 * 64);
-    const int64_t cus = device_cus();
-    int64_t ns = 1;
-    double best = 1e300;
-    for (int64_t s = 1; s <= std::min<int64_t>(tiles, 256); ++s) {
-        const double rounds = double((qblocks * s + cus - 1) / cus);
-        const double cost = rounds / double(s) + 0.002 * double(s);
-        if (cost < best) { best = cost; ns = s; }
-    }
+    int64_t ns = pick_splits(qblocks, std::min<int64_t>(tiles, 256), device_cus());
     // GF_TILE_SPLITS=s forces the split count (tests: the result does not depend on it)
     const char* senv = std::getenv("GF_TILE_SPLITS");
     if (senv && std::atoi(senv) > 0) ns = std::min<int64_t>(tiles, std::atoi(senv));
@@ -455,10 +456,11 @@ bool use_tile_path(const gf_forest* F, const QueryJob& J, int nb) {
     const char* env = std::getenv("GF_SCAN_PATH");
     if (env && std::strcmp(env, "rows") == 0) return false;
     if (env && std::strcmp(env, "tile") == 0) return true;
-    // batch sizes from which the tile path measured faster (1M x 960 BF16:
-    // 5.4 vs 7.0 ms at 16 queries; 200k x 10,000 FP8: 12.1 vs 26.6 ms at 1,024
-    // queries, 11.4 vs 4.7 ms at 128)
-    if (nb < (J.form == gf::kFormFP8 ? 512 : 16)) return false;
+    // batch sizes from which the tile path measured faster, with the splits
+    // of pick_splits (1M x 960 BF16: 1.19 vs 1.42 ms at 2 queries, 0.86 vs
+    // 0.79 at 1; 200k x 10,000 FP8: 1.72 vs 1.78 ms at 32 queries, 1.52 vs
+    // 1.02 at 8)
+    if (nb < (J.form == gf::kFormFP8 ? 32 : 2)) return false;
     const double leaf_pts = double(F->host.n) * F->host.m / double(F->host.real_leaves);
     const double cand_est = J.checks_mean * leaf_pts * 0.5;
     return cand_est * (J.form == gf::kFormFP8 ? 192.0 : 256.0) >= double(F->host.n);

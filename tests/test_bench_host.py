@@ -73,6 +73,24 @@ def test_pmc_traffic_reads_the_record_of_the_named_kernel():
     assert bench.pmc_traffic("no_such_kernel", "desc-1m-960") is None
 
 
+def test_pmc_traffic_is_null_once_kernel_or_launch_source_changes(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "k.hip").write_text("kernel v1")
+    (tmp_path / "l.hip").write_text("launch v1")
+    import hashlib
+    h = lambda t: hashlib.sha256(t.encode()).hexdigest()
+    rec = ("kernel: k_x\nsource_file: k.hip\nsource_sha256: %s\n"
+           "launch_file: l.hip\nlaunch_sha256: %s\nhbm_bytes_per_dispatch: 5000000000\n")
+    (tmp_path / "profiles" / "pmc_w.txt").write_text(rec % (h("kernel v1"), h("launch v1")))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.pmc_traffic("k_x", "w") == 5e9
+    (tmp_path / "l.hip").write_text("launch v2")
+    assert bench.pmc_traffic("k_x", "w") is None
+    (tmp_path / "l.hip").write_text("launch v1")
+    (tmp_path / "k.hip").write_text("kernel v2")
+    assert bench.pmc_traffic("k_x", "w") is None
+
+
 def test_vs_oracle_recall_and_distance_errors():
     import numpy as np
     X = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 2.0], [3.0, 0.0]], np.float32)
