@@ -173,11 +173,11 @@ gf_status gf_export_tree(const gf_forest *F, int32_t *D, int32_t *split_dim,
  * Two execution paths give the same candidate sets: the row path gathers
  * each query's candidate rows (for small batches each query's id range is
  * cut into slices, one workgroup each; GF_SCAN_SLICES=<count> forces a
- * count, for testing); the tile paths score 128-query blocks against all
- * points on MFMA and keep only those of each query's candidates: BF16 (d <=
- * 1024, batches of >= 16 queries whose candidates exceed ~1/256 of the
- * points) and FP8 (any d, batches of >= 512 queries whose candidates exceed
- * ~1/192 of the points).  The environment variable GF_SCAN_PATH (= rows |
+ * count, for testing); the tile paths score blocks of queries (128 BF16, 256
+ * FP8) against all points on MFMA and keep only those of each query's
+ * candidates: BF16 (d <= 1024, batches of >= 2 queries whose candidates
+ * exceed ~1/256 of the points) and FP8 (any d, batches of >= 32 queries whose
+ * candidates exceed ~1/192 of the points).  The environment variable GF_SCAN_PATH (= rows |
  * tile) overrides the choice where a tile path is available.
  * Rows wider than 4,096 FP32 (8,192 BF16) elements are streamed against a
  * copy of the query in LDS where it fits beside the visited bitmap;
