@@ -571,7 +571,7 @@ gf_status launch_selection(const gf_forest* F, const QueryJob& J, int nb, const 
         }
     }
     GF_HIP(gf::launch_select_walk(sa, 0, true, st));
-    hipLaunchKernelGGL(gf::k_select_finish, dim3(nb), dim3(256), 0, st, sa);
+    hipLaunchKernelGGL(gf::k_select_finish, dim3(nb), dim3(gf::finish_threads(nb)), 0, st, sa);
     GF_HIP(hipGetLastError());
     return GF_OK;
 }

@@ -511,7 +511,9 @@ __device__ __forceinline__ void pick_bin(const uint32_t* hist, uint32_t cur, int
         const uint32_t y = __shfl_up(incl, o);
         if (lane >= o) incl += y;
     }
-    if (lane == kWave - 1) wsum[wv] = incl;
+    // the bins lie in the first four waves (the later ones of a wider
+    // workgroup hold none)
+    if (lane == kWave - 1 && wv < 4) wsum[wv] = incl;
     __syncthreads();
     uint32_t base = 0, total = 0;
     for (int k = 0; k < 4; ++k) {
@@ -764,7 +766,7 @@ __device__ void select56(uint32_t cnt, uint32_t need, Get get, uint32_t* hist, u
     left = need;
     ties = 0;
     for (int shift = 48; shift >= 0; shift -= 8) {
-        hist[threadIdx.x] = 0;
+        if (threadIdx.x < 256) hist[threadIdx.x] = 0;
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
             uint64_t v;
@@ -786,7 +788,7 @@ __device__ void select56(uint32_t cnt, uint32_t need, Get get, uint32_t* hist, u
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
+__global__ __launch_bounds__(kFinishThreadsMax) void k_select_finish(SelectArgs a) {
     __shared__ uint32_t hist[256];
     __shared__ uint32_t pub[3];
     __shared__ uint32_t wsum[4];
@@ -861,7 +863,7 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
         if (need < cnt) {
             for (int pass = 0; pass < 8; ++pass) {
                 const int shift = 56 - 8 * pass;
-                hist[threadIdx.x] = 0;
+                if (threadIdx.x < 256) hist[threadIdx.x] = 0;
                 __syncthreads();
                 const uint64_t prefix = sh_prefix;
                 for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
@@ -931,7 +933,7 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
     uint32_t cur = uint32_t(s.prefix), left = need, ties = cnt;
     for (int r = int(s.cs) - 32; r > 0;) {
         const int w = r < 8 ? r : 8, sh = r - w;
-        hist[threadIdx.x] = 0;
+        if (threadIdx.x < 256) hist[threadIdx.x] = 0;
         __syncthreads();
         for (uint32_t i0 = threadIdx.x; i0 < cnt; i0 += kFinishUnroll * bstep) {
             uint32_t ev[kFinishUnroll];
@@ -985,7 +987,7 @@ __global__ __launch_bounds__(256) void k_select_finish(SelectArgs a) {
     uint32_t tcur = 0, tties = 0;
     for (int r = 32; r > 0;) {
         const int sh = r - 8;
-        hist[threadIdx.x] = 0;
+        if (threadIdx.x < 256) hist[threadIdx.x] = 0;
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
             if (effs[i] != estar) continue;
