@@ -185,11 +185,12 @@ __device__ __forceinline__ void stage_query_dims(const SelectArgs& a, int q, uin
     }
 }
 
-// The four waves of a walk workgroup serve the same 64 queries (lane =
-// query) and split the slice's chunks into four consecutive ranges; they
+// The eight waves of a walk workgroup serve the same 64 queries (lane =
+// query) and split the slice's chunks into eight consecutive ranges; they
 // share the staged query coordinates and the histogram (or the collect
-// counters), each keeping its own path state.
-constexpr int kSelWaves = 4;
+// counters), each keeping its own path state.  (Measured at 10,000 queries:
+// selection 5.26 ms with four waves, 4.89 with eight, 5.67 with sixteen.)
+constexpr int kSelWaves = 8;
 constexpr int kSelThreads = kSelWaves * kWave;
 constexpr int kSelMinGroups = 1024;
 
