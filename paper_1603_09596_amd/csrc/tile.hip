@@ -617,8 +617,17 @@ __global__ __launch_bounds__(256) void k_expand_points(ExpandArgs a) {
     const int chunk = blockIdx.y;
     const int64_t rows = int64_t(a.m) << a.H;
     const uint32_t* op = a.openT + int64_t(chunk) * rows * a.cw + w;
+    // Workgroups go to the XCDs round-robin; each XCD takes a consecutive run
+    // of point groups instead, so that neighbouring groups (points of nearby
+    // leaves, which share leaves in the other trees too) meet in one L2.
+    int64_t gblk;
+    {
+        const int64_t total = gridDim.x, i = blockIdx.x, x = i % kXcds, j = i / kXcds;
+        const int64_t base = total / kXcds, rem = total % kXcds;
+        gblk = (x < rem) ? x * (base + 1) + j : rem * (base + 1) + (x - rem) * base + j;
+    }
     for (int rep = 0; rep < kExpandRepeat; ++rep) {
-        const int64_t i = (int64_t(blockIdx.x) * kExpandRepeat + rep) * per + threadIdx.x / a.cw;
+        const int64_t i = (gblk * kExpandRepeat + rep) * per + threadIdx.x / a.cw;
         if (i >= a.n) return;
         const int64_t x = a.order[i];
         const uint32_t* lf = a.leafof + x * a.m;
