@@ -194,9 +194,24 @@ constexpr int kSelWaves = 8;
 constexpr int kSelThreads = kSelWaves * kWave;
 constexpr int kSelMinGroups = 1024;
 
-__device__ __forceinline__ void wave_chunks(uint32_t nchunks, uint32_t& cb, uint32_t& ce) {
+// Workgroups go to the XCDs round-robin; each XCD takes a consecutive run of
+// (tree, slice, query group) in that order instead, so that the node rows of
+// about m / 8 trees stay in its L2.
+__device__ __forceinline__ void walk_ids(uint32_t& qb, uint32_t& tree, uint32_t& z) {
+    const uint32_t nx = gridDim.x, ny = gridDim.y, nz = gridDim.z;
+    const uint32_t total = nx * ny * nz;
+    const uint32_t i = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+    const uint32_t x = i % 8u, j = i / 8u, base = total / 8u, rem = total % 8u;
+    const uint32_t L = (x < rem) ? x * (base + 1u) + j : rem * (base + 1u) + (x - rem) * base + j;
+    qb = L % nx;
+    const uint32_t r = L / nx;
+    z = r % nz;
+    tree = r / nz;
+}
+
+__device__ __forceinline__ void wave_chunks(uint32_t nchunks, uint32_t zi, uint32_t& cb, uint32_t& ce) {
     const uint32_t per = (nchunks + gridDim.z - 1) / gridDim.z;
-    const uint32_t zb = blockIdx.z * per;
+    const uint32_t zb = zi * per;
     const uint32_t ze = min(nchunks, zb + per);
     const uint32_t wper = (ze > zb) ? (ze - zb + kSelWaves - 1) / kSelWaves : 0u;
     const uint32_t w = threadIdx.x / kWave;
@@ -223,9 +238,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
     int32_t* pe = reinterpret_cast<int32_t*>(hist + (kBins / 2) * kWave) + wave * kPath * (U + 1) * kWave;
     uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (U + 1) * kWave);   // [U+1][64] per wave
     // a compact radix walk serves the listed queries only
-    const int slot = int(blockIdx.x) * kWave + lane;
+    uint32_t wqb, tree, wz;
+    walk_ids(wqb, tree, wz);
+    const int slot = int(wqb) * kWave + lane;
     const int q = (PHASE == kPhRadix && a.nlist > 0) ? (slot < a.nlist ? int(a.qlist[slot]) : a.nq) : slot;
-    const uint32_t tree = blockIdx.y;
     const SelState st = (q < a.nq) ? a.state[q] : SelState{};
     const bool active = (q < a.nq) && st.status == kSelSearching && st.phase == uint32_t(PHASE);
     if (!__any(active)) return;   // the same for every wave of the workgroup
@@ -233,7 +249,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
     for (int b = wave; b < kBins / 2; b += kSelWaves) hist[b * kWave + lane] = 0u;
     __syncthreads();
     uint32_t cb, ce;
-    wave_chunks(1u << U, cb, ce);
+    wave_chunks(1u << U, wz, cb, ce);
     const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
     auto count = [&](uint32_t dgt) {
         atomicAdd(&hist[(dgt >> 1) * kWave + lane], (dgt & 1u) ? 65536u : 1u);
@@ -300,7 +316,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_hist(SelectArgs a) {
     // sent the query here has cleared.
     const int zsplit = a.nslice / a.m;
     const int zf = (PHASE == kPhRadix) ? int(gridDim.z) / zsplit : 1;
-    const int slice = int(tree) * (int(gridDim.z) / zf) + int(blockIdx.z) / zf;
+    const int slice = int(tree) * (int(gridDim.z) / zf) + int(wz) / zf;
     uint32_t* gh = a.hist + (int64_t(q) * a.nslice + slice) * kBins;
     if (PHASE == kPhWindow) {
         for (int b = wave; b < kBins; b += kSelWaves) gh[b] = b < kWinBins ? hist[b * kWave + lane] : 0u;
@@ -343,8 +359,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
     constexpr int kPath = FULL ? 2 : 1;
     int32_t* pe = reinterpret_cast<int32_t*>(cnt + kWave) + wave * kPath * (U + 1) * kWave;
     uint32_t* pn = reinterpret_cast<uint32_t*>(pe + (U + 1) * kWave);
-    const int q = blockIdx.x * kWave + lane;
-    const uint32_t tree = blockIdx.y;
+    uint32_t wqb, tree, wz;
+    walk_ids(wqb, tree, wz);
+    const int q = int(wqb) * kWave + lane;
     const bool valid = q < a.nq;
     const SelState st = valid ? a.state[q] : SelState{};
     const bool all = valid && st.status == kSelAll;
@@ -353,14 +370,14 @@ __global__ __launch_bounds__(kSelThreads) void k_select_collect(SelectArgs a) {
     if (__any(full) != FULL) return;   // the same for every wave of the workgroup
     // this slice's share of the bin starts at coff[q][slice]; the waves take
     // slots from a shared counter (the order of the collected keys is free)
-    const int slice = int(tree) * int(gridDim.z) + int(blockIdx.z);
+    const int slice = int(tree) * int(gridDim.z) + int(wz);
     if (wave == 0) {
         stage_query_dims(a, q, tree, qd);
         cnt[lane] = ready ? a.coff[int64_t(q) * a.nslice + slice] : 0u;
     }
     __syncthreads();
     uint32_t cb, ce;
-    wave_chunks(1u << U, cb, ce);
+    wave_chunks(1u << U, wz, cb, ce);
     const uint2* nodes = a.nodes + int64_t(tree) * a.n_internal;
     uint64_t* keys = a.ckey + int64_t(q) * a.ccap;
     uint32_t* effs = reinterpret_cast<uint32_t*>(keys);
